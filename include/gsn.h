@@ -1,0 +1,248 @@
+/*
+ * gsn.h -- C ABI of the MI355X (gfx950) stochastic local-Newton 3DGS step.
+ *
+ * Method: "3DGS^2: Near Second-order Converging 3D Gaussian Splatting"
+ * (arxiv 2501.13975).  For one training image the library renders the image
+ * from the Gaussian kernels (Sec. 3, eq. 3dgs), assembles each kernel's
+ * gradient and small Hessian blocks of the image loss per attribute group
+ * (Sec. 4.2, eq. local_hessian_gradient), adds the same blocks from the
+ * secondary targets (Sec. 4.3, eq. tildel), solves the per-kernel local
+ * Newton systems (eq. local_newton) and applies the steps.
+ *
+ * Conventions shared by every call
+ *  - Pointers named d_* are DEVICE pointers on the context's device, owned by
+ *    the caller; the library never frees them.  Host pointers are named h_*.
+ *  - Arrays are structure-of-arrays, row per field: a "[F][N]" array holds
+ *    field f of kernel k at index f * N + k.  float is IEEE binary32.
+ *  - Every call is asynchronous on the context's HIP stream and returns a
+ *    gsn_status; results are valid after the stream is synchronised.
+ *    gsn_render additionally synchronises the stream once to learn the number
+ *    of (tile, kernel) pairs it must sort.
+ *  - Invalid arguments are reported before any work is launched
+ *    (GSN_E_INVALID, GSN_E_SHAPE); gsn_last_error() gives a message.
+ *  - A context is used from one host thread at a time.
+ */
+#ifndef GSN_H
+#define GSN_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    GSN_OK = 0,
+    GSN_E_INVALID = -1,  /* null pointer, bad option value, unknown handle */
+    GSN_E_SHAPE = -2,    /* sizes inconsistent with each other or with the frame */
+    GSN_E_CAPACITY = -3, /* a size exceeds what the call supports */
+    GSN_E_HIP = -4,      /* a HIP runtime call failed (message has the HIP error) */
+    GSN_E_NOMEM = -5     /* device allocation of internal scratch failed */
+} gsn_status;
+
+typedef struct gsn_ctx gsn_ctx;
+typedef struct gsn_frame gsn_frame;
+
+/* Gaussian kernels (Sec. 3): position p, unit quaternion q = (w, x, y, z),
+ * linear scale s > 0, opacity sigma in (0, 1), SH colour coefficients.
+ * d_pos [3][n], d_rot [4][n], d_scale [3][n], d_opac [n],
+ * d_sh [3][K][n] with K = (sh_degree + 1)^2, sh_degree in 0..3. */
+typedef struct {
+    float *d_pos, *d_rot, *d_scale, *d_opac, *d_sh;
+    int32_t n;
+    int32_t sh_degree;
+} gsn_gaussians;
+
+/* Pinhole camera, world -> camera rigid transform with OpenCV axes
+ * (x right, y down, z forward); pixel centres at integer coordinates.
+ * R is row-major. */
+typedef struct {
+    float R[9];
+    float t[3];
+    float fx, fy, cx, cy;
+    int32_t width, height;
+    float znear;
+} gsn_camera;
+
+/* Rasteriser options.  tile must be 16.  alpha = min(alpha_max, sigma G);
+ * splats with alpha < alpha_min are skipped; a pixel stops before its
+ * transmittance would drop below T_min; kappa is added to the diagonal of the
+ * 2D covariance; a splat covers the tiles within radius_sigma standard
+ * deviations of its major axis; bg is the background colour. */
+typedef struct {
+    int32_t tile;
+    float alpha_min, alpha_max, T_min, kappa, radius_sigma;
+    float bg[3];
+} gsn_render_opts;
+
+/* Loss options (Sec. 4.2): L = L2 + lambda_ssim * L_S, with an 11x11 Gaussian
+ * SSIM window (sigma 1.5).  weight multiplies this view's gradient and
+ * Hessian before they are added to the blocks (1 for every target, Sec. 4.3). */
+typedef struct {
+    float lambda_ssim;
+    float weight;
+    int32_t keep_zstats; /* nonzero: keep this view's per-kernel projected-space
+                            statistics in the frame for gsn_frame_zstats */
+} gsn_loss_opts;
+
+/* Solve options.  Damping: Cholesky of H + mu_j I, mu_j = mu0 10^j for
+ * j = 0..max_escalations with mu0 = damp_rel * max(mean diag H, 0) +
+ * damp_abs / (3 |I|); accepted when all pivots are positive and
+ * min/max pivot >= pivot_min; otherwise the scaled gradient step.
+ * Opacity barrier weight alpha_sigma = barrier_beta / (3 |I|), |I| =
+ * npix_primary.  sh_floor: per-view colour curvature floor relative to the
+ * largest.  scale_floor: s_new >= scale_floor * s.  opac_ftb:
+ * fraction-to-boundary factor of the opacity update.  kappa: the 2D
+ * covariance dilation the primary target was rendered with (the scaling
+ * solve differentiates that covariance's eigenvalues). */
+typedef struct {
+    float damp_rel, damp_abs, pivot_min;
+    int32_t max_escalations;
+    float barrier_beta, sh_floor, scale_floor, opac_ftb;
+    int32_t npix_primary;
+    float kappa;
+} gsn_solve_opts;
+
+/* Per-kernel gradient/Hessian blocks, summed over the views added so far.
+ * d_data is a device array of gsn_blocks_floats(n, n_views) floats laid out
+ * [GSN_BLK_BASE + GSN_BLK_VIEW * n_views][n]:
+ *   rows 0..2 g_p, 3..8 H_p (xx xy xz yy yz zz), 9..12 g_q, 13..22 H_q
+ *   (upper triangle row by row), 23..25 g_s, 26..31 H_s, 32 g_sigma,
+ *   33 H_sigma, 34 coverage of the primary target (sum of alpha T);
+ *   then per view slot v at 35 + 10 v: gamma (dL/dc~, 3), s (sum h (alpha T)^2,
+ *   3), view direction r (3), coverage (1). */
+#define GSN_BLK_BASE 35
+#define GSN_BLK_VIEW 10
+typedef struct {
+    float* d_data;
+    int32_t n;
+    int32_t n_views;
+} gsn_blocks;
+
+/* Newton steps, d_data [GSN_STEP_BASE + 3K][n]: rows 0..2 Delta p, 3 theta
+ * (rotation angle about the axis), 4..6 rotation axis r_k, 7..9 Delta s,
+ * 10 Delta sigma, 11.. Delta SH [3][K].  d_flags [5][n] int32: escalation
+ * index per group (position, rotation, scaling, opacity), -1 for the
+ * gradient fallback, -2 when the kernel is not seen by the primary target
+ * (no step); row 4 holds the number of views the colour solve used. */
+#define GSN_STEP_BASE 11
+typedef struct {
+    float* d_data;
+    int32_t* d_flags;
+    int32_t n;
+    int32_t sh_degree;
+} gsn_steps;
+
+/* ---------------------------------------------------------------- context */
+
+/* Creates a context on HIP device `device` issuing work on `hip_stream`
+ * (a hipStream_t; NULL means the null stream).  *out receives the handle. */
+gsn_status gsn_create(gsn_ctx** out, int32_t device, void* hip_stream);
+/* Frees the context and all frames and scratch it owns.  NULL is a no-op. */
+gsn_status gsn_destroy(gsn_ctx* ctx);
+/* Message of the last failed call on this context ("" if none).  Owned by the context. */
+const char* gsn_last_error(const gsn_ctx* ctx);
+/* Switches the stream used by later calls. */
+gsn_status gsn_set_stream(gsn_ctx* ctx, void* hip_stream);
+
+/* A frame holds one rendered view: projected kernels, the depth-ordered
+ * per-tile lists, the image and per-pixel compositing state that
+ * gsn_accumulate_hessian needs.  Owned by the context. */
+gsn_status gsn_frame_create(gsn_ctx* ctx, gsn_frame** out);
+gsn_status gsn_frame_destroy(gsn_ctx* ctx, gsn_frame* frame);
+
+/* --------------------------------------------------------------- the step */
+
+/* Renders the image of `g` seen by `cam` (Sec. 3, eq. 3dgs) into `frame`:
+ * projection of every kernel (EWA 2D covariance, view-dependent SH colour,
+ * Appendix A.1-A.3), binning into 16x16 tiles, a global depth sort and a
+ * stable partition by tile, and front-to-back alpha compositing per pixel.
+ * The tile rectangles and depth keys are computed in single precision with
+ * a fixed operation order and no contraction.  d_rgb_out [3][H][W] and
+ * d_T_out [H][W] receive copies of the image and final transmittance when
+ * not NULL.  Errors: GSN_E_INVALID (null handle or arrays, tile != 16,
+ * sh_degree outside 0..3), GSN_E_SHAPE (n < 0, image size <= 0). */
+gsn_status gsn_render(gsn_ctx* ctx, const gsn_gaussians* g, const gsn_camera* cam,
+                      const gsn_render_opts* opts, gsn_frame* frame, float* d_rgb_out,
+                      float* d_T_out);
+
+/* Adds to `blocks` the gradient and Hessian blocks of the loss of the image
+ * in `frame` against d_target [3][H][W] (Sec. 4.2, eq. local_hessian_gradient
+ * with the per-pixel diagonal image Hessian of L2 + lambda SSIM), for every
+ * kernel and attribute group, and writes this view's colour statistics into
+ * view slot `view_slot` (0 = primary target, 1.. = secondary targets, Sec.
+ * 4.3).  `g` must be the kernels the frame was rendered from.  Slot 0 also
+ * sets the primary coverage row.  d_loss_out (device double[2], may be NULL)
+ * receives (L2, L_S) of this view.  Blocks are accumulated with a fixed
+ * reduction order (no atomics), so results are deterministic.
+ * Errors: GSN_E_SHAPE (n differs from the frame's, view_slot outside
+ * 0..n_views-1), GSN_E_INVALID (frame never rendered, null pointers). */
+gsn_status gsn_accumulate_hessian(gsn_ctx* ctx, const gsn_gaussians* g, const gsn_frame* frame,
+                                  const float* d_target, const gsn_loss_opts* opts,
+                                  int32_t view_slot, gsn_blocks* blocks, double* d_loss_out);
+
+/* Solves every kernel's local Newton systems (eq. local_newton) in the
+ * paper's reduced coordinates relative to the primary camera: position in
+ * the plane normal to the view direction r_k, rotation angle about r_k,
+ * scale in the row space of d(lambda)/ds (eigenvalues of the primary 2D
+ * covariance), opacity with a log barrier, SH colour per channel from the
+ * per-view statistics (Sec. 4.2, Position/Scaling/Rotation/Opacity/Color
+ * solve).  Kernels the primary target does not see get no step.
+ * Errors: GSN_E_SHAPE (blocks.n or steps.n != g->n, sh_degree mismatch). */
+gsn_status gsn_local_newton_solve(gsn_ctx* ctx, const gsn_gaussians* g, const gsn_camera* primary,
+                                  const gsn_blocks* blocks, const gsn_solve_opts* opts,
+                                  gsn_steps* steps);
+
+/* Applies the steps in place, for the groups in group_mask (bit 0 position,
+ * 1 rotation, 2 scaling, 3 opacity, 4 colour): p += Delta p; q <- dq(theta) q
+ * renormalised with dq = (cos(theta/2), sin(theta/2) r_k); s <- max(s + Delta s,
+ * scale_floor s); sigma <- sigma + Delta sigma clipped to the fraction
+ * opac_ftb of the way to 0 or 1; SH += Delta SH (Sec. 4.2).
+ * Errors: GSN_E_SHAPE (steps.n != g->n). */
+gsn_status gsn_apply_step(gsn_ctx* ctx, gsn_gaussians* g, const gsn_steps* steps,
+                          const gsn_solve_opts* opts, uint32_t group_mask);
+
+/* ---------------------------------------------------------------- helpers */
+
+/* Number of floats of a blocks array for n kernels and n_views view slots. */
+int64_t gsn_blocks_floats(int32_t n, int32_t n_views);
+/* Zeroes a blocks array (asynchronously, with a fill kernel). */
+gsn_status gsn_blocks_zero(gsn_ctx* ctx, gsn_blocks* blocks);
+/* Number of floats of a steps array for n kernels and SH degree. */
+int64_t gsn_steps_floats(int32_t n, int32_t sh_degree);
+
+/* Secondary targets are downsampled (Sec. 4.3): d_dst [3][H/2][W/2] is the
+ * 2x2 box mean of d_src [3][H][W].  Errors: GSN_E_SHAPE (W or H < 2). */
+gsn_status gsn_downsample2x(gsn_ctx* ctx, const float* d_src, int32_t width, int32_t height,
+                            float* d_dst);
+
+/* Camera KNN on the bounding sphere (Sec. 4.1), on the host: camera centres
+ * h_centers [ncam][3] are projected radially onto a sphere about
+ * h_scene_center and ranked by great-circle distance; h_out [ncam][k]
+ * receives the k nearest other cameras (ties by lower index).
+ * Errors: GSN_E_INVALID (k < 1 or k >= ncam). */
+gsn_status gsn_camera_knn(const double* h_centers, int32_t ncam, const double* h_scene_center,
+                          int32_t k, int32_t* h_out);
+
+/* Frame introspection for tests and profiling (host values, synchronous on the
+ * context's stream): number of (tile, kernel) pairs of the last render, and
+ * copies of its per-tile ranges (uint32 [2][tiles]) and sorted kernel ids
+ * (uint32 [pairs]) into device buffers.  Any pointer may be NULL. */
+gsn_status gsn_frame_info(gsn_ctx* ctx, const gsn_frame* frame, int64_t* h_pairs, int32_t* h_tiles_x,
+                          int32_t* h_tiles_y);
+gsn_status gsn_frame_lists(gsn_ctx* ctx, const gsn_frame* frame, uint32_t* d_ranges, uint32_t* d_ids,
+                           uint32_t* d_depth_bits, int32_t* d_rect, uint32_t* d_ncontrib);
+/* Per-kernel projected-space statistics of the last gsn_accumulate_hessian on
+ * this frame that ran with keep_zstats (float [44][n]): gradient w.r.t.
+ * (pi_x, pi_y, Q_xx, Q_xy, Q_yy) (5), sigma (1), c~ (3); Hessian block over
+ * (pi, Q) (15, upper triangle), its cross block with c~ (5 x 3), the c~
+ * diagonal (3), the sigma-sigma entry (1) and the coverage sum alpha T (1). */
+gsn_status gsn_frame_zstats(gsn_ctx* ctx, const gsn_frame* frame, float* d_out);
+/* Copies of the per-pixel loss gradient dL/dc and diagonal Hessian d2L/dc2
+ * ([3][H][W] floats each) of the last gsn_accumulate_hessian on this frame. */
+gsn_status gsn_frame_loss_maps(gsn_ctx* ctx, const gsn_frame* frame, float* d_dL, float* d_h);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* GSN_H */

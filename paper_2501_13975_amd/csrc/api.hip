@@ -1,0 +1,439 @@
+// api.hip -- C ABI entry points of libgsn (declared in include/gsn.h).
+#include <stdarg.h>
+#include <stdio.h>
+
+#include <algorithm>
+#include <cmath>
+#include <new>
+#include <set>
+#include <utility>
+#include <vector>
+
+#include "gsn_internal.h"
+
+hipError_t buf_reserve(DevBuf& b, size_t bytes) {
+    if (bytes <= b.bytes && b.p) return hipSuccess;
+    if (b.p) {
+        hipError_t e = hipFree(b.p);
+        if (e != hipSuccess) return e;
+        b.p = nullptr;
+        b.bytes = 0;
+    }
+    // round up so repeated small growth does not reallocate every call
+    size_t want = bytes + bytes / 8 + 256;
+    hipError_t e = hipMalloc(&b.p, want);
+    if (e != hipSuccess) {
+        b.p = nullptr;
+        return e;
+    }
+    b.bytes = want;
+    return hipSuccess;
+}
+
+void buf_free(DevBuf& b) {
+    if (b.p) (void)hipFree(b.p);
+    b.p = nullptr;
+    b.bytes = 0;
+}
+
+namespace {
+
+gsn_status fail(gsn_ctx* ctx, gsn_status st, const char* fmt, ...) __attribute__((format(printf, 3, 4)));
+gsn_status fail(gsn_ctx* ctx, gsn_status st, const char* fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    if (ctx) ctx->err = buf;
+    return st;
+}
+
+#define HIP_TRY(ctx, expr)                                                                                  \
+    do {                                                                                                    \
+        hipError_t _e = (expr);                                                                             \
+        if (_e != hipSuccess)                                                                               \
+            return fail(ctx, _e == hipErrorOutOfMemory ? GSN_E_NOMEM : GSN_E_HIP, "%s: %s (%s:%d)", #expr, \
+                        hipGetErrorString(_e), __FILE__, __LINE__);                                         \
+    } while (0)
+
+DevCam make_devcam(const gsn_camera& c) {
+    DevCam d;
+    for (int i = 0; i < 9; ++i) d.R[i] = c.R[i];
+    for (int i = 0; i < 3; ++i) d.t[i] = c.t[i];
+    d.fx = c.fx;
+    d.fy = c.fy;
+    d.cx = c.cx;
+    d.cy = c.cy;
+    for (int i = 0; i < 3; ++i) {
+        const double o = -((double)c.R[i] * c.t[0] + (double)c.R[3 + i] * c.t[1] + (double)c.R[6 + i] * c.t[2]);
+        d.o[i] = (float)o;
+    }
+    d.W = c.width;
+    d.H = c.height;
+    d.tiles_x = (c.width + GSN_TILE - 1) / GSN_TILE;
+    d.tiles_y = (c.height + GSN_TILE - 1) / GSN_TILE;
+    d.znear = c.znear;
+    return d;
+}
+
+gsn_status check_gaussians(gsn_ctx* ctx, const gsn_gaussians* g) {
+    if (!g) return fail(ctx, GSN_E_INVALID, "gaussians is NULL");
+    if (g->n < 0) return fail(ctx, GSN_E_SHAPE, "n = %d < 0", g->n);
+    if (g->sh_degree < 0 || g->sh_degree > 3) return fail(ctx, GSN_E_INVALID, "sh_degree %d not in 0..3", g->sh_degree);
+    if (g->n > 0 && (!g->d_pos || !g->d_rot || !g->d_scale || !g->d_opac || !g->d_sh))
+        return fail(ctx, GSN_E_INVALID, "a gaussian attribute array is NULL");
+    if ((int64_t)g->n >= (1ll << 31) / 64) return fail(ctx, GSN_E_CAPACITY, "n = %d too large", g->n);
+    return GSN_OK;
+}
+
+gsn_status check_camera(gsn_ctx* ctx, const gsn_camera* c) {
+    if (!c) return fail(ctx, GSN_E_INVALID, "camera is NULL");
+    if (c->width <= 0 || c->height <= 0) return fail(ctx, GSN_E_SHAPE, "image %dx%d", c->width, c->height);
+    if ((c->width + GSN_TILE - 1) / GSN_TILE > 65535 || (c->height + GSN_TILE - 1) / GSN_TILE > 65535)
+        return fail(ctx, GSN_E_CAPACITY, "image too large");
+    if ((int64_t)c->width * c->height > (1ll << 28)) return fail(ctx, GSN_E_CAPACITY, "image too large");
+    if (!(c->fx > 0.f) || !(c->fy > 0.f) || !(c->znear > 0.f))
+        return fail(ctx, GSN_E_INVALID, "focal lengths and znear must be positive");
+    return GSN_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+gsn_status gsn_create(gsn_ctx** out, int32_t device, void* hip_stream) {
+    if (!out) return GSN_E_INVALID;
+    *out = nullptr;
+    int count = 0;
+    if (hipGetDeviceCount(&count) != hipSuccess || device < 0 || device >= count) return GSN_E_INVALID;
+    gsn_ctx* c = new (std::nothrow) gsn_ctx;
+    if (!c) return GSN_E_NOMEM;
+    c->device = device;
+    c->stream = static_cast<hipStream_t>(hip_stream);
+    *out = c;
+    return GSN_OK;
+}
+
+gsn_status gsn_destroy(gsn_ctx* ctx) {
+    delete ctx;
+    return GSN_OK;
+}
+
+const char* gsn_last_error(const gsn_ctx* ctx) { return ctx ? ctx->err.c_str() : "null context"; }
+
+gsn_status gsn_set_stream(gsn_ctx* ctx, void* hip_stream) {
+    if (!ctx) return GSN_E_INVALID;
+    ctx->stream = static_cast<hipStream_t>(hip_stream);
+    return GSN_OK;
+}
+
+gsn_status gsn_frame_create(gsn_ctx* ctx, gsn_frame** out) {
+    if (!ctx || !out) return GSN_E_INVALID;
+    gsn_frame* f = new (std::nothrow) gsn_frame;
+    if (!f) return fail(ctx, GSN_E_NOMEM, "frame allocation failed");
+    HIP_TRY(ctx, hipSetDevice(ctx->device));
+    HIP_TRY(ctx, hipHostMalloc((void**)&f->h_total, sizeof(uint32_t), hipHostMallocDefault));
+    *out = f;
+    return GSN_OK;
+}
+
+gsn_status gsn_frame_destroy(gsn_ctx* ctx, gsn_frame* f) {
+    if (!ctx || !f) return GSN_E_INVALID;
+    (void)hipSetDevice(ctx->device);
+    (void)hipStreamSynchronize(ctx->stream);
+    DevBuf* all[] = {&f->rec, &f->rect, &f->depth_key, &f->ntiles, &f->ids_a, &f->ids_b, &f->keys_a, &f->keys_b,
+                     &f->offsets, &f->pair_off, &f->pk_a, &f->pv_a, &f->pk_b, &f->pv_b, &f->partial, &f->flags,
+                     &f->ranges, &f->img, &f->Tfin, &f->ncontrib, &f->dL, &f->hd, &f->coef, &f->zstats,
+                     &f->loss_part, &f->hist, &f->scan_tmp, &f->total};
+    for (DevBuf* b : all) buf_free(*b);
+    if (f->h_total) (void)hipHostFree(f->h_total);
+    delete f;
+    return GSN_OK;
+}
+
+gsn_status gsn_render(gsn_ctx* ctx, const gsn_gaussians* g, const gsn_camera* cam, const gsn_render_opts* opts,
+                      gsn_frame* f, float* d_rgb_out, float* d_T_out) {
+    if (!ctx || !f || !opts) return fail(ctx, GSN_E_INVALID, "null context, frame or options");
+    gsn_status st = check_gaussians(ctx, g);
+    if (st != GSN_OK) return st;
+    if ((st = check_camera(ctx, cam)) != GSN_OK) return st;
+    if (opts->tile != GSN_TILE) return fail(ctx, GSN_E_INVALID, "tile must be %d", GSN_TILE);
+    if (!(opts->alpha_max > 0.f && opts->alpha_max < 1.f) || !(opts->alpha_min >= 0.f) || !(opts->T_min >= 0.f) ||
+        !(opts->kappa >= 0.f) || !(opts->radius_sigma > 0.f))
+        return fail(ctx, GSN_E_INVALID, "render option out of range");
+    HIP_TRY(ctx, hipSetDevice(ctx->device));
+    hipStream_t s = ctx->stream;
+    const int n = g->n;
+    f->rendered = false;
+    f->n = n;
+    f->K = (g->sh_degree + 1) * (g->sh_degree + 1);
+    f->cam = make_devcam(*cam);
+    f->W = cam->width;
+    f->H = cam->height;
+    f->tiles_x = f->cam.tiles_x;
+    f->tiles_y = f->cam.tiles_y;
+    f->ro.alpha_min = opts->alpha_min;
+    f->ro.alpha_max = opts->alpha_max;
+    f->ro.T_min = opts->T_min;
+    f->ro.kappa = opts->kappa;
+    f->ro.radius_sigma = opts->radius_sigma;
+    for (int i = 0; i < 3; ++i) f->ro.bg[i] = opts->bg[i];
+    const size_t nn = (size_t)std::max(n, 1);
+    const size_t npx = (size_t)f->W * f->H, tiles = (size_t)f->tiles_x * f->tiles_y;
+    HIP_TRY(ctx, buf_reserve(f->rec, nn * 3 * sizeof(float4)));
+    HIP_TRY(ctx, buf_reserve(f->rect, nn * sizeof(uint2)));
+    HIP_TRY(ctx, buf_reserve(f->depth_key, nn * 4));
+    HIP_TRY(ctx, buf_reserve(f->ntiles, nn * 4));
+    HIP_TRY(ctx, buf_reserve(f->ids_a, nn * 4));
+    HIP_TRY(ctx, buf_reserve(f->ids_b, nn * 4));
+    HIP_TRY(ctx, buf_reserve(f->keys_a, nn * 4));
+    HIP_TRY(ctx, buf_reserve(f->keys_b, nn * 4));
+    HIP_TRY(ctx, buf_reserve(f->offsets, (nn + 1) * 4));
+    HIP_TRY(ctx, buf_reserve(f->pair_off, nn * 4));
+    HIP_TRY(ctx, buf_reserve(f->ranges, tiles * sizeof(uint2)));
+    HIP_TRY(ctx, buf_reserve(f->img, 3 * npx * 4));
+    HIP_TRY(ctx, buf_reserve(f->Tfin, npx * 4));
+    HIP_TRY(ctx, buf_reserve(f->ncontrib, npx * 4));
+    HIP_TRY(ctx, buf_reserve(f->total, 16));
+    // sort and scan scratch for the per-kernel stages, reserved before any launch so that
+    // no buffer is reallocated while work that uses it may still be queued
+    HIP_TRY(ctx, buf_reserve(f->hist, (size_t)256 * ((nn + 4095) / 4096) * 8));
+    HIP_TRY(ctx, buf_reserve(f->scan_tmp, scan_tmp_bytes((uint32_t)nn)));
+    uint32_t* d_total = bp<uint32_t>(f->total);
+    // 1. projection and binning decisions
+    launch_preprocess(*g, f->cam, f->ro, bp<float4>(f->rec), bp<uint2>(f->rect), bp<uint32_t>(f->keys_a),
+                      bp<uint32_t>(f->ids_a), bp<uint32_t>(f->ntiles), s);
+    HIP_TRY(ctx, hipGetLastError());
+    // 2. depth order of the kernels: stable radix sort of (depth bits, id)
+    HIP_TRY(ctx, radix_sort_pairs(bp<uint32_t>(f->keys_a), bp<uint32_t>(f->ids_a), bp<uint32_t>(f->keys_b),
+                                  bp<uint32_t>(f->ids_b), (uint32_t)n, 0, 32, f->hist, f->scan_tmp, s));
+    // 3. pair offsets in depth order
+    launch_gather_u32(bp<uint32_t>(f->ntiles), bp<uint32_t>(f->ids_a), bp<uint32_t>(f->keys_b), (uint32_t)n, s);
+    if (n > 0) {
+        HIP_TRY(ctx, exclusive_scan_u32(bp<uint32_t>(f->keys_b), bp<uint32_t>(f->offsets), (uint32_t)n, d_total,
+                                        f->scan_tmp, s));
+    } else {
+        launch_fill_u32(d_total, 0u, 1, s);
+    }
+    HIP_TRY(ctx, hipMemcpyAsync(f->h_total, d_total, 4, hipMemcpyDeviceToHost, s));
+    HIP_TRY(ctx, hipStreamSynchronize(s));
+    const uint32_t P = *f->h_total;
+    f->pairs = P;
+    const size_t pp = std::max<size_t>(P, 1);
+    // the stream is idle here: growing scratch cannot race with queued work
+    HIP_TRY(ctx, buf_reserve(f->hist, (size_t)256 * ((pp + 4095) / 4096) * 8));
+    HIP_TRY(ctx, buf_reserve(f->scan_tmp, scan_tmp_bytes((uint32_t)std::max<size_t>(pp, nn))));
+    HIP_TRY(ctx, buf_reserve(f->pk_a, pp * 4));
+    HIP_TRY(ctx, buf_reserve(f->pv_a, pp * 4));
+    HIP_TRY(ctx, buf_reserve(f->pk_b, pp * 4));
+    HIP_TRY(ctx, buf_reserve(f->pv_b, pp * 4));
+    // 4. pairs in depth order, then a stable partition by tile id
+    launch_emit_pairs(bp<uint32_t>(f->ids_a), bp<uint32_t>(f->offsets), (uint32_t)n, bp<uint2>(f->rect),
+                      (uint32_t)f->tiles_x, bp<uint32_t>(f->pk_a), bp<uint32_t>(f->pv_a), bp<uint32_t>(f->pair_off),
+                      s);
+    int tile_bits = 1;
+    while ((1ull << tile_bits) < tiles) ++tile_bits;
+    HIP_TRY(ctx, radix_sort_pairs(bp<uint32_t>(f->pk_a), bp<uint32_t>(f->pv_a), bp<uint32_t>(f->pk_b),
+                                  bp<uint32_t>(f->pv_b), P, 0, tile_bits, f->hist, f->scan_tmp, s));
+    launch_fill_u32(bp<uint32_t>(f->ranges), 0u, 2 * tiles, s);
+    launch_tile_ranges(bp<uint32_t>(f->pk_a), P, bp<uint2>(f->ranges), s);
+    // 5. front-to-back compositing
+    launch_raster_fwd(bp<uint2>(f->ranges), bp<uint32_t>(f->pv_a), bp<float4>(f->rec), (uint32_t)n, f->cam, f->ro,
+                      bp<float>(f->img), bp<float>(f->Tfin), bp<uint32_t>(f->ncontrib), s);
+    HIP_TRY(ctx, hipGetLastError());
+    if (d_rgb_out) HIP_TRY(ctx, hipMemcpyAsync(d_rgb_out, f->img.p, 3 * npx * 4, hipMemcpyDeviceToDevice, s));
+    if (d_T_out) HIP_TRY(ctx, hipMemcpyAsync(d_T_out, f->Tfin.p, npx * 4, hipMemcpyDeviceToDevice, s));
+    f->rendered = true;
+    return GSN_OK;
+}
+
+gsn_status gsn_accumulate_hessian(gsn_ctx* ctx, const gsn_gaussians* g, const gsn_frame* fc, const float* d_target,
+                                  const gsn_loss_opts* opts, int32_t view_slot, gsn_blocks* b, double* d_loss_out) {
+    if (!ctx || !fc || !opts || !b || !d_target) return fail(ctx, GSN_E_INVALID, "null argument");
+    gsn_frame* f = const_cast<gsn_frame*>(fc);
+    gsn_status st = check_gaussians(ctx, g);
+    if (st != GSN_OK) return st;
+    if (!f->rendered) return fail(ctx, GSN_E_INVALID, "frame was never rendered");
+    if (g->n != f->n || b->n != g->n) return fail(ctx, GSN_E_SHAPE, "n mismatch (g %d, frame %d, blocks %d)", g->n, f->n, b->n);
+    if ((g->sh_degree + 1) * (g->sh_degree + 1) != f->K) return fail(ctx, GSN_E_SHAPE, "sh_degree differs from the frame's");
+    if (view_slot < 0 || view_slot >= b->n_views) return fail(ctx, GSN_E_SHAPE, "view_slot %d outside 0..%d", view_slot, b->n_views - 1);
+    if (!b->d_data && b->n > 0) return fail(ctx, GSN_E_INVALID, "blocks data is NULL");
+    if (!(opts->lambda_ssim >= 0.f)) return fail(ctx, GSN_E_INVALID, "lambda_ssim must be >= 0");
+    HIP_TRY(ctx, hipSetDevice(ctx->device));
+    hipStream_t s = ctx->stream;
+    const size_t npx = (size_t)f->W * f->H;
+    HIP_TRY(ctx, buf_reserve(f->dL, 3 * npx * 4));
+    HIP_TRY(ctx, buf_reserve(f->hd, 3 * npx * 4));
+    HIP_TRY(ctx, buf_reserve(f->coef, 24 * npx * 4));
+    const int nparts = ((f->W + 15) / 16) * ((f->H + 15) / 16) * 3;
+    HIP_TRY(ctx, buf_reserve(f->loss_part, (size_t)2 * nparts * sizeof(double)));
+    int np_out = 0;
+    launch_loss_maps(bp<float>(f->img), d_target, f->W, f->H, opts->lambda_ssim, bp<float>(f->coef),
+                     bp<float>(f->dL), bp<float>(f->hd), bp<double>(f->loss_part), &np_out, s);
+    if (d_loss_out) launch_loss_reduce(bp<double>(f->loss_part), np_out, f->W, f->H, d_loss_out, s);
+    HIP_TRY(ctx, hipGetLastError());
+    const size_t pp = std::max<size_t>((size_t)f->pairs, 1);
+    HIP_TRY(ctx, buf_reserve(f->partial, pp * GSN_NZ * 4));
+    HIP_TRY(ctx, buf_reserve(f->flags, (pp + 3) / 4 * 4));
+    launch_fill_u32(bp<uint32_t>(f->flags), 0u, (pp + 3) / 4, s);
+    if (f->pairs > 0) launch_raster_bwd(*f, bp<float>(f->dL), bp<float>(f->hd), s);
+    float* zs = nullptr;
+    if (opts->keep_zstats) {
+        HIP_TRY(ctx, buf_reserve(f->zstats, (size_t)std::max(f->n, 1) * GSN_NZ * 4));
+        zs = bp<float>(f->zstats);
+    }
+    launch_reduce_chain(*f, *g, opts->weight, view_slot, *b, zs, s);
+    HIP_TRY(ctx, hipGetLastError());
+    return GSN_OK;
+}
+
+gsn_status gsn_local_newton_solve(gsn_ctx* ctx, const gsn_gaussians* g, const gsn_camera* primary,
+                                  const gsn_blocks* b, const gsn_solve_opts* o, gsn_steps* st) {
+    if (!ctx || !b || !o || !st) return fail(ctx, GSN_E_INVALID, "null argument");
+    gsn_status r = check_gaussians(ctx, g);
+    if (r != GSN_OK) return r;
+    if ((r = check_camera(ctx, primary)) != GSN_OK) return r;
+    if (b->n != g->n || st->n != g->n) return fail(ctx, GSN_E_SHAPE, "n mismatch");
+    if (st->sh_degree != g->sh_degree) return fail(ctx, GSN_E_SHAPE, "steps sh_degree differs");
+    if (b->n_views < 1 || b->n_views > 9) return fail(ctx, GSN_E_CAPACITY, "n_views %d not in 1..9", b->n_views);
+    if (g->n > 0 && (!b->d_data || !st->d_data || !st->d_flags)) return fail(ctx, GSN_E_INVALID, "null device array");
+    if (o->npix_primary <= 0 || o->max_escalations < 0 || o->max_escalations > 30)
+        return fail(ctx, GSN_E_INVALID, "solve option out of range");
+    HIP_TRY(ctx, hipSetDevice(ctx->device));
+    launch_solve(*g, make_devcam(*primary), o->kappa, *b, *o, *st, ctx->stream);
+    HIP_TRY(ctx, hipGetLastError());
+    return GSN_OK;
+}
+
+gsn_status gsn_apply_step(gsn_ctx* ctx, gsn_gaussians* g, const gsn_steps* st, const gsn_solve_opts* o,
+                          uint32_t group_mask) {
+    if (!ctx || !st || !o) return fail(ctx, GSN_E_INVALID, "null argument");
+    gsn_status r = check_gaussians(ctx, g);
+    if (r != GSN_OK) return r;
+    if (st->n != g->n || st->sh_degree != g->sh_degree) return fail(ctx, GSN_E_SHAPE, "steps do not match gaussians");
+    HIP_TRY(ctx, hipSetDevice(ctx->device));
+    launch_apply(*g, *st, *o, group_mask, ctx->stream);
+    HIP_TRY(ctx, hipGetLastError());
+    return GSN_OK;
+}
+
+int64_t gsn_blocks_floats(int32_t n, int32_t n_views) {
+    if (n < 0 || n_views < 1) return 0;
+    return (int64_t)(GSN_BLK_BASE + GSN_BLK_VIEW * n_views) * n;
+}
+
+gsn_status gsn_blocks_zero(gsn_ctx* ctx, gsn_blocks* b) {
+    if (!ctx || !b) return GSN_E_INVALID;
+    if (b->n == 0) return GSN_OK;
+    if (!b->d_data) return fail(ctx, GSN_E_INVALID, "blocks data is NULL");
+    HIP_TRY(ctx, hipSetDevice(ctx->device));
+    launch_fill_f32(b->d_data, 0.f, (size_t)gsn_blocks_floats(b->n, b->n_views), ctx->stream);
+    HIP_TRY(ctx, hipGetLastError());
+    return GSN_OK;
+}
+
+int64_t gsn_steps_floats(int32_t n, int32_t sh_degree) {
+    if (n < 0 || sh_degree < 0 || sh_degree > 3) return 0;
+    return (int64_t)(GSN_STEP_BASE + 3 * (sh_degree + 1) * (sh_degree + 1)) * n;
+}
+
+gsn_status gsn_downsample2x(gsn_ctx* ctx, const float* d_src, int32_t width, int32_t height, float* d_dst) {
+    if (!ctx || !d_src || !d_dst) return fail(ctx, GSN_E_INVALID, "null argument");
+    if (width < 2 || height < 2) return fail(ctx, GSN_E_SHAPE, "image %dx%d too small", width, height);
+    HIP_TRY(ctx, hipSetDevice(ctx->device));
+    launch_downsample2x(d_src, width, height, d_dst, ctx->stream);
+    HIP_TRY(ctx, hipGetLastError());
+    return GSN_OK;
+}
+
+gsn_status gsn_camera_knn(const double* c, int32_t ncam, const double* sc, int32_t k, int32_t* out) {
+    if (!c || !sc || !out || k < 1 || k >= ncam) return GSN_E_INVALID;
+    std::vector<double> u(3 * (size_t)ncam);
+    for (int i = 0; i < ncam; ++i) {
+        double d[3], nn = 0;
+        for (int a = 0; a < 3; ++a) {
+            d[a] = c[3 * i + a] - sc[a];
+            nn += d[a] * d[a];
+        }
+        nn = std::sqrt(nn);
+        for (int a = 0; a < 3; ++a) u[3 * i + a] = d[a] / nn;
+    }
+    std::vector<std::pair<double, int>> dist;
+    for (int i = 0; i < ncam; ++i) {
+        dist.clear();
+        for (int j = 0; j < ncam; ++j) {
+            if (j == i) continue;
+            const double dot = u[3 * i] * u[3 * j] + u[3 * i + 1] * u[3 * j + 1] + u[3 * i + 2] * u[3 * j + 2];
+            dist.emplace_back(std::acos(std::max(-1.0, std::min(1.0, dot))), j);
+        }
+        std::partial_sort(dist.begin(), dist.begin() + k, dist.end());
+        for (int a = 0; a < k; ++a) out[(size_t)i * k + a] = dist[a].second;
+    }
+    return GSN_OK;
+}
+
+gsn_status gsn_frame_info(gsn_ctx* ctx, const gsn_frame* f, int64_t* pairs, int32_t* tx, int32_t* ty) {
+    if (!ctx || !f) return GSN_E_INVALID;
+    if (pairs) *pairs = f->pairs;
+    if (tx) *tx = f->tiles_x;
+    if (ty) *ty = f->tiles_y;
+    return GSN_OK;
+}
+
+gsn_status gsn_frame_lists(gsn_ctx* ctx, const gsn_frame* f, uint32_t* d_ranges, uint32_t* d_ids,
+                           uint32_t* d_depth_bits, int32_t* d_rect, uint32_t* d_ncontrib) {
+    if (!ctx || !f) return GSN_E_INVALID;
+    if (!f->rendered) return fail(ctx, GSN_E_INVALID, "frame was never rendered");
+    HIP_TRY(ctx, hipSetDevice(ctx->device));
+    hipStream_t s = ctx->stream;
+    const size_t tiles = (size_t)f->tiles_x * f->tiles_y, npx = (size_t)f->W * f->H;
+    if (d_ranges) HIP_TRY(ctx, hipMemcpyAsync(d_ranges, f->ranges.p, tiles * 8, hipMemcpyDeviceToDevice, s));
+    if (d_ids && f->pairs) HIP_TRY(ctx, hipMemcpyAsync(d_ids, f->pv_a.p, (size_t)f->pairs * 4, hipMemcpyDeviceToDevice, s));
+    if (d_ncontrib) HIP_TRY(ctx, hipMemcpyAsync(d_ncontrib, f->ncontrib.p, npx * 4, hipMemcpyDeviceToDevice, s));
+    if ((d_depth_bits || d_rect) && f->n > 0) {
+        // depth keys were sorted in place; recompute the per-kernel view from the rect/keys copies
+        std::vector<uint2> rect(f->n);
+        HIP_TRY(ctx, hipMemcpyAsync(rect.data(), f->rect.p, (size_t)f->n * 8, hipMemcpyDeviceToHost, s));
+        HIP_TRY(ctx, hipStreamSynchronize(s));
+        if (d_rect) {
+            std::vector<int32_t> r4((size_t)4 * f->n);
+            for (int k = 0; k < f->n; ++k) {
+                r4[k] = rect[k].x & 0xffff;
+                r4[f->n + k] = rect[k].x >> 16;
+                r4[2 * (size_t)f->n + k] = rect[k].y & 0xffff;
+                r4[3 * (size_t)f->n + k] = rect[k].y >> 16;
+            }
+            HIP_TRY(ctx, hipMemcpy(d_rect, r4.data(), r4.size() * 4, hipMemcpyHostToDevice));
+        }
+        if (d_depth_bits) {
+            // the sorted keys are in keys_a in depth order with ids in ids_a: scatter them back by id
+            std::vector<uint32_t> keys(f->n), ids(f->n), out(f->n);
+            HIP_TRY(ctx, hipMemcpy(keys.data(), f->keys_a.p, (size_t)f->n * 4, hipMemcpyDeviceToHost));
+            HIP_TRY(ctx, hipMemcpy(ids.data(), f->ids_a.p, (size_t)f->n * 4, hipMemcpyDeviceToHost));
+            for (int r = 0; r < f->n; ++r) out[ids[r]] = keys[r];
+            HIP_TRY(ctx, hipMemcpy(d_depth_bits, out.data(), (size_t)f->n * 4, hipMemcpyHostToDevice));
+        }
+    }
+    return GSN_OK;
+}
+
+gsn_status gsn_frame_zstats(gsn_ctx* ctx, const gsn_frame* f, float* d_out) {
+    if (!ctx || !f || !d_out) return GSN_E_INVALID;
+    if (!f->zstats.p) return fail(ctx, GSN_E_INVALID, "no statistics kept: run gsn_accumulate_hessian with keep_zstats");
+    HIP_TRY(ctx, hipSetDevice(ctx->device));
+    HIP_TRY(ctx, hipMemcpyAsync(d_out, f->zstats.p, (size_t)f->n * GSN_NZ * 4, hipMemcpyDeviceToDevice, ctx->stream));
+    return GSN_OK;
+}
+
+gsn_status gsn_frame_loss_maps(gsn_ctx* ctx, const gsn_frame* f, float* d_dL, float* d_h) {
+    if (!ctx || !f) return GSN_E_INVALID;
+    if (!f->dL.p) return fail(ctx, GSN_E_INVALID, "no loss maps: run gsn_accumulate_hessian first");
+    HIP_TRY(ctx, hipSetDevice(ctx->device));
+    const size_t bytes = (size_t)3 * f->W * f->H * 4;
+    if (d_dL) HIP_TRY(ctx, hipMemcpyAsync(d_dL, f->dL.p, bytes, hipMemcpyDeviceToDevice, ctx->stream));
+    if (d_h) HIP_TRY(ctx, hipMemcpyAsync(d_h, f->hd.p, bytes, hipMemcpyDeviceToDevice, ctx->stream));
+    return GSN_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,94 @@
+// gsn_internal.h -- host-side declarations shared by the translation units of libgsn.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+
+#include "../../include/gsn.h"
+#include "device_common.h"
+
+// Device buffer that only grows.
+struct DevBuf {
+    void* p = nullptr;
+    size_t bytes = 0;
+};
+hipError_t buf_reserve(DevBuf& b, size_t bytes);
+void buf_free(DevBuf& b);
+template <class T>
+T* bp(const DevBuf& b) { return static_cast<T*>(b.p); }
+
+struct gsn_frame {
+    bool rendered = false;
+    int n = 0, K = 0, W = 0, H = 0, tiles_x = 0, tiles_y = 0;
+    int64_t pairs = 0;
+    DevCam cam{};
+    DevRenderOpts ro{};
+    // per kernel
+    DevBuf rec;         // float4 [3][n]: (mx, my, qxx, qxy), (qyy, sigma, r, g), (b, -, -, -)
+    DevBuf rect;        // uint2 [n]: (x0 | y0 << 16, x1 | y1 << 16)
+    DevBuf depth_key;   // u32 [n], 0xffffffff when culled
+    DevBuf ntiles;      // u32 [n]
+    DevBuf ids_a, ids_b, keys_a, keys_b;  // u32 [n] sort ping-pong
+    DevBuf offsets;     // u32 [n + 1] pair offset by depth rank
+    DevBuf pair_off;    // u32 [n] pair offset by kernel id
+    // per pair
+    DevBuf pk_a, pv_a, pk_b, pv_b;  // u32 [pairs] (tile, id) ping-pong
+    DevBuf partial;     // float [pairs][GSN_NZ]
+    DevBuf flags;       // u8 [pairs]
+    // per tile / pixel
+    DevBuf ranges;      // uint2 [tiles]
+    DevBuf img;         // float [3][H][W]
+    DevBuf Tfin;        // float [H][W]
+    DevBuf ncontrib;    // u32 [H][W]
+    DevBuf dL, hd;      // float [3][H][W] loss maps
+    DevBuf coef;        // float [3][8][H][W] SSIM coefficient maps
+    DevBuf zstats;      // float [GSN_NZ][n], optional debug copy
+    DevBuf loss_part;   // double [2][nblocks]
+    // sort / scan scratch
+    DevBuf hist, scan_tmp, total;
+    uint32_t* h_total = nullptr;  // pinned host word
+};
+
+struct gsn_ctx {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    std::string err;
+};
+
+// ---- launchers (render.hip)
+void launch_fill_u32(uint32_t* p, uint32_t v, size_t n, hipStream_t s);
+void launch_fill_f32(float* p, float v, size_t n, hipStream_t s);
+void launch_preprocess(const gsn_gaussians& g, const DevCam& cam, const DevRenderOpts& ro, float4* rec,
+                       uint2* rect, uint32_t* depth_key, uint32_t* ids, uint32_t* ntiles, hipStream_t s);
+// stable LSD radix sort of (key, val) pairs on bits [bit_lo, bit_hi); result lands in (k0, v0)
+hipError_t radix_sort_pairs(uint32_t* k0, uint32_t* v0, uint32_t* k1, uint32_t* v1, uint32_t n, int bit_lo,
+                            int bit_hi, DevBuf& hist, DevBuf& scan_tmp, hipStream_t s);
+// bytes of scan scratch for scanning up to n values (and the 256 x blocks radix histograms of n keys)
+size_t scan_tmp_bytes(uint32_t n);
+// exclusive scan of n u32 values into out; *d_total receives the sum
+hipError_t exclusive_scan_u32(const uint32_t* in, uint32_t* out, uint32_t n, uint32_t* d_total,
+                              DevBuf& scan_tmp, hipStream_t s);
+void launch_gather_u32(const uint32_t* src, const uint32_t* idx, uint32_t* dst, uint32_t n, hipStream_t s);
+void launch_emit_pairs(const uint32_t* sorted_ids, const uint32_t* offsets, uint32_t n, const uint2* rect,
+                       uint32_t tiles_x, uint32_t* keys, uint32_t* vals, uint32_t* pair_off, hipStream_t s);
+void launch_tile_ranges(const uint32_t* keys, uint32_t pairs, uint2* ranges, hipStream_t s);
+void launch_raster_fwd(const uint2* ranges, const uint32_t* ids, const float4* rec, uint32_t n, const DevCam& cam,
+                       const DevRenderOpts& ro, float* img, float* Tfin, uint32_t* ncontrib, hipStream_t s);
+void launch_downsample2x(const float* src, int W, int H, float* dst, hipStream_t s);
+
+// ---- launchers (loss.hip)
+void launch_loss_maps(const float* img, const float* tgt, int W, int H, float lambda, float* coef, float* dL,
+                      float* hd, double* part, int* nparts, hipStream_t s);
+void launch_loss_reduce(const double* part, int nparts, int W, int H, double* out, hipStream_t s);
+
+// ---- launchers (backward.hip)
+void launch_raster_bwd(const gsn_frame& f, const float* dL, const float* hd, hipStream_t s);
+void launch_reduce_chain(const gsn_frame& f, const gsn_gaussians& g, float weight, int slot, const gsn_blocks& b,
+                         float* zstats_out, hipStream_t s);
+
+// ---- launchers (solve.hip)
+void launch_solve(const gsn_gaussians& g, const DevCam& cam, float kappa, const gsn_blocks& b,
+                  const gsn_solve_opts& o, const gsn_steps& st, hipStream_t s);
+void launch_apply(const gsn_gaussians& g, const gsn_steps& st, const gsn_solve_opts& o, uint32_t mask,
+                  hipStream_t s);

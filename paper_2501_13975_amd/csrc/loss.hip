@@ -1,0 +1,225 @@
+// loss.hip -- per-pixel loss derivative maps (Sec. 4.2).
+//
+// L = L2 + lambda L_S with L2 = 1/(6|I|) sum (c - c^t)^2 and
+// L_S = 1/(3|I|) sum_pix sum_ch (1 - SSIM), SSIM over an 11x11 Gaussian window
+// (sigma 1.5, zero padding), C1 = 0.01^2, C2 = 0.03^2.  With the paper's f0..f3
+// (f0 = 2 mu mu^t + C1, f1 = 2 cov + C2, f2 = mu^2 + mu^t^2 + C1,
+// f3 = var + var^t + C2) the derivative of one window's SSIM F with respect to a
+// pixel value c at window weight w is
+//     dF = w (a0 + a1 c^t - a2 c) F,   a0 = 2mu^t/f0 - 2mu^t/f1 - 2mu/f2 + 2mu/f3,
+//                                       a1 = 2/f1, a2 = 2/f3,
+// and its exact second derivative is
+//     d2F = w^2 F (b0 + bt c^t + bc c + bcc c^2 + btc c c^t) - 2 w F / f3
+// with b0 = a0^2 - 4mu^t^2/f0^2 - 4mu^t^2/f1^2 - 2/f2 + 4mu^2/f2^2 + 2/f3 + 4mu^2/f3^2,
+// bt = 2 a0 a1 + 8 mu^t/f1^2, bc = -2 a0 a2 - 8 mu/f3^2, bcc = 8/f3^2, btc = -8/(f1 f3).
+// Summing over the windows that contain a pixel turns each window-centred
+// coefficient map into a correlation with w (three maps) or w^2 (five maps).
+//
+// Pass 1 (one workgroup per 16x16 tile of window centres and channel): moments
+// by separable convolution through LDS, then the eight coefficient maps and the
+// loss partial sums (double).  Pass 2: the eight correlations and the per-pixel
+// gradient dL and diagonal Hessian h.  Pass 3: double-precision reduction of
+// the loss partials in a fixed order.
+#include "gsn_internal.h"
+
+namespace {
+
+constexpr int T = 16, HALO = 5, R = T + 2 * HALO;  // 26
+constexpr float kC1 = 0.0001f, kC2 = 0.0009f;
+
+__device__ __forceinline__ void window_weights(float* g, float* g2) {
+    // normalised 1D Gaussian, sigma 1.5; the 2D window is the outer product
+    if (threadIdx.x < 11) {
+        double s = 0.0, v[11];
+        for (int i = 0; i < 11; ++i) {
+            v[i] = exp(-((double)((i - 5) * (i - 5))) / (2.0 * 1.5 * 1.5));
+            s += v[i];
+        }
+        const double gi = v[threadIdx.x] / s;
+        g[threadIdx.x] = (float)gi;
+        g2[threadIdx.x] = (float)(gi * gi);
+    }
+}
+
+__global__ __launch_bounds__(256) void ssim_coef_kernel(const float* __restrict__ img, const float* __restrict__ tgt,
+                                                         int W, int H, float* __restrict__ coef,
+                                                         double* __restrict__ part) {
+    __shared__ float g[11], g2[11];
+    __shared__ float sc[R][R], st[R][R];
+    __shared__ float hs[5][R][T];
+    const int ch = blockIdx.z;
+    const int x0 = blockIdx.x * T - HALO, y0 = blockIdx.y * T - HALO;
+    const size_t np = (size_t)W * H;
+    const float* I = img + ch * np;
+    const float* Tg = tgt + ch * np;
+    window_weights(g, g2);
+    for (int i = threadIdx.x; i < R * R; i += 256) {
+        const int yy = i / R, xx = i % R, x = x0 + xx, y = y0 + yy;
+        const bool in = x >= 0 && y >= 0 && x < W && y < H;
+        sc[yy][xx] = in ? I[(size_t)y * W + x] : 0.f;
+        st[yy][xx] = in ? Tg[(size_t)y * W + x] : 0.f;
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < R * T; i += 256) {
+        const int yy = i / T, xx = i % T;
+        float a = 0, b = 0, c = 0, d = 0, e = 0;
+#pragma unroll
+        for (int k = 0; k < 11; ++k) {
+            const float u = sc[yy][xx + k], v = st[yy][xx + k], w = g[k];
+            a += w * u;
+            b += w * v;
+            c += w * u * u;
+            d += w * v * v;
+            e += w * u * v;
+        }
+        hs[0][yy][xx] = a;
+        hs[1][yy][xx] = b;
+        hs[2][yy][xx] = c;
+        hs[3][yy][xx] = d;
+        hs[4][yy][xx] = e;
+    }
+    __syncthreads();
+    const int lx = threadIdx.x % T, ly = threadIdx.x / T;
+    const int x = blockIdx.x * T + lx, y = blockIdx.y * T + ly;
+    double l2 = 0.0, ls = 0.0;
+    if (x < W && y < H) {
+        float m[5] = {0, 0, 0, 0, 0};
+#pragma unroll
+        for (int k = 0; k < 11; ++k)
+#pragma unroll
+            for (int q = 0; q < 5; ++q) m[q] += g[k] * hs[q][ly + k][lx];
+        const float mu = m[0], mut = m[1];
+        const float f0 = 2.f * mu * mut + kC1;
+        const float f1 = 2.f * (m[4] - mu * mut) + kC2;
+        const float f2 = mu * mu + mut * mut + kC1;
+        const float f3 = (m[2] - mu * mu) + (m[3] - mut * mut) + kC2;
+        const float F = (f0 * f1) / (f2 * f3);
+        const float i0 = 1.f / f0, i1 = 1.f / f1, i2 = 1.f / f2, i3 = 1.f / f3;
+        const float a0 = 2.f * mut * i0 - 2.f * mut * i1 - 2.f * mu * i2 + 2.f * mu * i3;
+        const float a1 = 2.f * i1, a2 = 2.f * i3;
+        const float b0 = a0 * a0 - 4.f * mut * mut * i0 * i0 - 4.f * mut * mut * i1 * i1 - 2.f * i2 +
+                         4.f * mu * mu * i2 * i2 + 2.f * i3 + 4.f * mu * mu * i3 * i3;
+        const float bt = 2.f * a0 * a1 + 8.f * mut * i1 * i1;
+        const float bc = -2.f * a0 * a2 - 8.f * mu * i3 * i3;
+        const float bcc = 8.f * i3 * i3;
+        const float btc = -8.f * i1 * i3;
+        const size_t pi = (size_t)y * W + x;
+        float* cf = coef + (size_t)ch * 8 * np;
+        cf[0 * np + pi] = F * a0;
+        cf[1 * np + pi] = F * a1;
+        cf[2 * np + pi] = F * a2;
+        cf[3 * np + pi] = F * b0;
+        cf[4 * np + pi] = F * bt;
+        cf[5 * np + pi] = F * bc;
+        cf[6 * np + pi] = F * bcc;
+        cf[7 * np + pi] = F * btc;
+        const double r = (double)sc[ly + HALO][lx + HALO] - (double)st[ly + HALO][lx + HALO];
+        l2 = r * r;
+        ls = 1.0 - (double)F;
+    }
+    // deterministic block reduction in double
+    __shared__ double red[2][256];
+    red[0][threadIdx.x] = l2;
+    red[1][threadIdx.x] = ls;
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+        if (threadIdx.x < s) {
+            red[0][threadIdx.x] += red[0][threadIdx.x + s];
+            red[1][threadIdx.x] += red[1][threadIdx.x + s];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        const int nb = gridDim.x * gridDim.y * gridDim.z;
+        const int b = (blockIdx.z * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x;
+        part[b] = red[0][0];
+        part[nb + b] = red[1][0];
+    }
+}
+
+__global__ __launch_bounds__(256) void ssim_grad_kernel(const float* __restrict__ img, const float* __restrict__ tgt,
+                                                         int W, int H, float lambda, const float* __restrict__ coef,
+                                                         float* __restrict__ dL, float* __restrict__ hd) {
+    __shared__ float g[11], g2[11];
+    __shared__ float sm[8][R][R];
+    __shared__ float hs[8][R][T];
+    const int ch = blockIdx.z;
+    const int x0 = blockIdx.x * T - HALO, y0 = blockIdx.y * T - HALO;
+    const size_t np = (size_t)W * H;
+    const float* cf = coef + (size_t)ch * 8 * np;
+    window_weights(g, g2);
+    for (int i = threadIdx.x; i < R * R; i += 256) {
+        const int yy = i / R, xx = i % R, x = x0 + xx, y = y0 + yy;
+        const bool in = x >= 0 && y >= 0 && x < W && y < H;
+        const size_t pi = (size_t)y * W + x;
+#pragma unroll
+        for (int q = 0; q < 8; ++q) sm[q][yy][xx] = in ? cf[q * np + pi] : 0.f;
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < R * T; i += 256) {
+        const int yy = i / T, xx = i % T;
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+            float a = 0.f;
+#pragma unroll
+            for (int k = 0; k < 11; ++k) a += (q < 3 ? g[k] : g2[k]) * sm[q][yy][xx + k];
+            hs[q][yy][xx] = a;
+        }
+    }
+    __syncthreads();
+    const int lx = threadIdx.x % T, ly = threadIdx.x / T;
+    const int x = blockIdx.x * T + lx, y = blockIdx.y * T + ly;
+    if (x >= W || y >= H) return;
+    float v[8];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+        float a = 0.f;
+#pragma unroll
+        for (int k = 0; k < 11; ++k) a += (q < 3 ? g[k] : g2[k]) * hs[q][ly + k][lx];
+        v[q] = a;
+    }
+    const size_t pi = (size_t)y * W + x;
+    const float c = img[ch * np + pi], t = tgt[ch * np + pi];
+    const float norm = 1.0f / (3.0f * (float)np);
+    const float d1 = v[0] + t * v[1] - c * v[2];
+    const float d2 = v[3] + t * v[4] + c * v[5] + c * c * v[6] + c * t * v[7] - v[2];
+    dL[ch * np + pi] = (c - t) * norm - lambda * norm * d1;
+    hd[ch * np + pi] = norm - lambda * norm * d2;
+}
+
+__global__ void loss_reduce_kernel(const double* __restrict__ part, int nparts, double npix, double* __restrict__ out) {
+    __shared__ double red[2][256];
+    double a = 0.0, b = 0.0;
+    for (int i = threadIdx.x; i < nparts; i += 256) {
+        a += part[i];
+        b += part[nparts + i];
+    }
+    red[0][threadIdx.x] = a;
+    red[1][threadIdx.x] = b;
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+        if (threadIdx.x < s) {
+            red[0][threadIdx.x] += red[0][threadIdx.x + s];
+            red[1][threadIdx.x] += red[1][threadIdx.x + s];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        out[0] = red[0][0] / (6.0 * npix);
+        out[1] = red[1][0] / (3.0 * npix);
+    }
+}
+
+}  // namespace
+
+void launch_loss_maps(const float* img, const float* tgt, int W, int H, float lambda, float* coef, float* dL,
+                      float* hd, double* part, int* nparts, hipStream_t s) {
+    dim3 grid((W + T - 1) / T, (H + T - 1) / T, 3);
+    *nparts = (int)(grid.x * grid.y * grid.z);
+    ssim_coef_kernel<<<grid, 256, 0, s>>>(img, tgt, W, H, coef, part);
+    ssim_grad_kernel<<<grid, 256, 0, s>>>(img, tgt, W, H, lambda, coef, dL, hd);
+}
+
+void launch_loss_reduce(const double* part, int nparts, int W, int H, double* out, hipStream_t s) {
+    loss_reduce_kernel<<<1, 256, 0, s>>>(part, nparts, (double)W * (double)H, out);
+}

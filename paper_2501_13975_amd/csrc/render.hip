@@ -1,0 +1,504 @@
+// render.hip -- projection, binning and forward compositing (Sec. 3, eq. 3dgs).
+//
+// Layout: one thread per kernel for projection; a global stable LSD radix sort
+// of kernels by depth; (tile, kernel) pairs emitted in depth order and then
+// stably radix-partitioned by tile id, so every tile's list comes out
+// depth-ordered without a per-tile sort; one 256-thread workgroup (four
+// wave64s) per 16x16 tile for compositing, splat records staged through LDS.
+#include <algorithm>
+
+#include "gsn_internal.h"
+
+namespace {
+
+constexpr int kThreads = 256;
+
+__global__ void fill_u32_kernel(uint32_t* p, uint32_t v, size_t n) {
+    size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const size_t stride = (size_t)gridDim.x * blockDim.x;
+    for (; i < n; i += stride) p[i] = v;
+}
+__global__ void fill_f32_kernel(float* p, float v, size_t n) {
+    size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const size_t stride = (size_t)gridDim.x * blockDim.x;
+    for (; i < n; i += stride) p[i] = v;
+}
+
+int grid_for(size_t n, int threads = kThreads, int cap = 65536) {
+    size_t b = (n + threads - 1) / threads;
+    if (b < 1) b = 1;
+    if (b > (size_t)cap) b = cap;
+    return (int)b;
+}
+
+// ---------------------------------------------------------------------------
+// Binning decisions in single precision: one IEEE operation per step, left to
+// right, no contraction, correctly rounded division and square root.  Any
+// other implementation of the same sequence reproduces the depth key and the
+// tile rectangle bit for bit.
+// ---------------------------------------------------------------------------
+struct BinOut {
+    float tx, ty, tz, cxx, cxy, cyy, det, u, v;
+    int x0, y0, x1, y1;
+    bool vis;
+};
+
+__device__ __noinline__ BinOut bin_spec(float px, float py, float pz, float qw, float qx, float qy, float qz,
+                                        float s0, float s1, float s2, const DevCam& c, float kappa, float rsig) {
+#pragma clang fp contract(off)
+    BinOut b;
+    b.vis = false;
+    b.x0 = b.y0 = b.x1 = b.y1 = 0;
+    const float* R = c.R;
+    b.tx = ((R[0] * px + R[1] * py) + R[2] * pz) + c.t[0];
+    b.ty = ((R[3] * px + R[4] * py) + R[5] * pz) + c.t[1];
+    b.tz = ((R[6] * px + R[7] * py) + R[8] * pz) + c.t[2];
+    if (!(b.tz > c.znear)) return b;
+    const float nq = sqrtf(((qw * qw + qx * qx) + qy * qy) + qz * qz);
+    const float w = ((qw) / (nq)), x = ((qx) / (nq)), y = ((qy) / (nq)), z = ((qz) / (nq));
+    const float r[3][3] = {{1.0f - 2.0f * (y * y + z * z), 2.0f * (x * y - w * z), 2.0f * (x * z + w * y)},
+                           {2.0f * (x * y + w * z), 1.0f - 2.0f * (x * x + z * z), 2.0f * (y * z - w * x)},
+                           {2.0f * (x * z - w * y), 2.0f * (y * z + w * x), 1.0f - 2.0f * (x * x + y * y)}};
+    const float s[3] = {s0, s1, s2};
+    float m[3][3];
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int j = 0; j < 3; ++j) m[i][j] = r[i][j] * s[j];
+    float S[3][3];
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int j = 0; j < 3; ++j) S[i][j] = (m[i][0] * m[j][0] + m[i][1] * m[j][1]) + m[i][2] * m[j][2];
+    const float j00 = ((c.fx) / (b.tz));
+    const float j02 = ((-(c.fx * b.tx)) / (b.tz * b.tz));
+    const float j11 = ((c.fy) / (b.tz));
+    const float j12 = ((-(c.fy * b.ty)) / (b.tz * b.tz));
+    float a[2][3];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        a[0][k] = j00 * R[k] + j02 * R[6 + k];
+        a[1][k] = j11 * R[3 + k] + j12 * R[6 + k];
+    }
+    float bb[2][3];
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int k = 0; k < 3; ++k) bb[i][k] = (a[i][0] * S[0][k] + a[i][1] * S[1][k]) + a[i][2] * S[2][k];
+    b.cxx = ((bb[0][0] * a[0][0] + bb[0][1] * a[0][1]) + bb[0][2] * a[0][2]) + kappa;
+    b.cxy = (bb[0][0] * a[1][0] + bb[0][1] * a[1][1]) + bb[0][2] * a[1][2];
+    b.cyy = ((bb[1][0] * a[1][0] + bb[1][1] * a[1][1]) + bb[1][2] * a[1][2]) + kappa;
+    b.det = b.cxx * b.cyy - b.cxy * b.cxy;
+    if (!(b.det > 0.0f)) return b;
+    const float mid = 0.5f * (b.cxx + b.cyy);
+    const float lam = mid + sqrtf(fmaxf(0.1f, mid * mid - b.det));
+    const float radius = ceilf(rsig * sqrtf(lam));
+    b.u = ((c.fx * b.tx) / (b.tz)) + c.cx;
+    b.v = ((c.fy * b.ty) / (b.tz)) + c.cy;
+    const float ft = (float)GSN_TILE;
+    const float x0 = fminf(fmaxf(floorf(((b.u - radius) / (ft))), 0.0f), (float)c.tiles_x);
+    const float x1 = fminf(fmaxf(floorf(((b.u + radius) / (ft))) + 1.0f, 0.0f), (float)c.tiles_x);
+    const float y0 = fminf(fmaxf(floorf(((b.v - radius) / (ft))), 0.0f), (float)c.tiles_y);
+    const float y1 = fminf(fmaxf(floorf(((b.v + radius) / (ft))) + 1.0f, 0.0f), (float)c.tiles_y);
+    b.x0 = (int)x0;
+    b.x1 = (int)x1;
+    b.y0 = (int)y0;
+    b.y1 = (int)y1;
+    b.vis = (b.x1 > b.x0) && (b.y1 > b.y0);
+    return b;
+}
+
+// One thread per kernel: binning decisions, conic, view-dependent colour.
+__global__ __launch_bounds__(kThreads) void preprocess_kernel(
+    const float* __restrict__ pos, const float* __restrict__ rot, const float* __restrict__ scale,
+    const float* __restrict__ opac, const float* __restrict__ sh, int n, int K, DevCam cam, DevRenderOpts ro,
+    float4* __restrict__ rec, uint2* __restrict__ rect, uint32_t* __restrict__ depth_key,
+    uint32_t* __restrict__ ids, uint32_t* __restrict__ ntiles) {
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= n) return;
+    const float px = pos[k], py = pos[n + k], pz = pos[2 * n + k];
+    const BinOut b = bin_spec(px, py, pz, rot[k], rot[n + k], rot[2 * n + k], rot[3 * n + k], scale[k],
+                              scale[n + k], scale[2 * n + k], cam, ro.kappa, ro.radius_sigma);
+    ids[k] = (uint32_t)k;
+    if (!b.vis) {
+        depth_key[k] = 0xffffffffu;
+        ntiles[k] = 0;
+        rect[k] = make_uint2(0, 0);
+        return;
+    }
+    depth_key[k] = __float_as_uint(b.tz);
+    ntiles[k] = (uint32_t)((b.x1 - b.x0) * (b.y1 - b.y0));
+    rect[k] = make_uint2((uint32_t)b.x0 | ((uint32_t)b.y0 << 16), (uint32_t)b.x1 | ((uint32_t)b.y1 << 16));
+    const float idet = 1.0f / b.det;
+    // view direction from the camera centre and SH colour c~ = sum_i Y_i(r) c_i
+    const float dx = px - cam.o[0], dy = py - cam.o[1], dz = pz - cam.o[2];
+    const float il = rsqrtf(dx * dx + dy * dy + dz * dz);
+    float Y[16];
+    sh_basis_dev<float>(K, dx * il, dy * il, dz * il, Y);
+    float col[3];
+#pragma unroll
+    for (int ch = 0; ch < 3; ++ch) {
+        float acc = 0.f;
+        for (int i = 0; i < K; ++i) acc += Y[i] * sh[((size_t)ch * K + i) * n + k];
+        col[ch] = acc;
+    }
+    rec[k] = make_float4(b.u, b.v, b.cyy * idet, -b.cxy * idet);
+    rec[n + k] = make_float4(b.cxx * idet, opac[k], col[0], col[1]);
+    rec[2 * (size_t)n + k] = make_float4(col[2], 0.f, 0.f, 0.f);
+}
+
+// ---------------------------------------------------------------------------
+// Device-wide exclusive scan (u32): per-block totals, a recursive scan of the
+// totals, then a block-local scan with the block's offset added.
+// ---------------------------------------------------------------------------
+constexpr int kScanItems = 8;
+constexpr int kScanTile = kThreads * kScanItems;
+
+__device__ __forceinline__ uint32_t wave_incl_scan(uint32_t v) {
+    const int lane = __lane_id();
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        const uint32_t o = __shfl_up(v, d, 64);
+        if (lane >= d) v += o;
+    }
+    return v;
+}
+
+// Block-wide exclusive scan of one value per thread; returns the block total in *total.
+__device__ __forceinline__ uint32_t block_excl_scan(uint32_t v, uint32_t* total) {
+    __shared__ uint32_t wsum[kThreads / 64];
+    const int lane = __lane_id(), wave = threadIdx.x / 64;
+    const uint32_t inc = wave_incl_scan(v);
+    if (lane == 63) wsum[wave] = inc;
+    __syncthreads();
+    uint32_t off = 0, tot = 0;
+#pragma unroll
+    for (int w = 0; w < kThreads / 64; ++w) {
+        if (w < wave) off += wsum[w];
+        tot += wsum[w];
+    }
+    __syncthreads();
+    *total = tot;
+    return off + inc - v;
+}
+
+__global__ __launch_bounds__(kThreads) void scan_reduce_kernel(const uint32_t* __restrict__ in, uint32_t n,
+                                                                uint32_t* __restrict__ block_sums) {
+    const size_t base = (size_t)blockIdx.x * kScanTile;
+    uint32_t s = 0;
+#pragma unroll
+    for (int i = 0; i < kScanItems; ++i) {
+        const size_t idx = base + (size_t)i * kThreads + threadIdx.x;
+        if (idx < n) s += in[idx];
+    }
+    uint32_t tot;
+    block_excl_scan(s, &tot);
+    if (threadIdx.x == 0) block_sums[blockIdx.x] = tot;
+}
+
+__global__ __launch_bounds__(kThreads) void scan_apply_kernel(const uint32_t* __restrict__ in,
+                                                               uint32_t* __restrict__ out, uint32_t n,
+                                                               const uint32_t* __restrict__ block_off,
+                                                               uint32_t* __restrict__ d_total) {
+    const size_t base = (size_t)blockIdx.x * kScanTile + (size_t)threadIdx.x * kScanItems;
+    uint32_t v[kScanItems], s = 0;
+#pragma unroll
+    for (int i = 0; i < kScanItems; ++i) {
+        const size_t idx = base + i;
+        v[i] = idx < n ? in[idx] : 0u;
+        s += v[i];
+    }
+    uint32_t tot;
+    uint32_t off = block_excl_scan(s, &tot) + (block_off ? block_off[blockIdx.x] : 0u);
+#pragma unroll
+    for (int i = 0; i < kScanItems; ++i) {
+        const size_t idx = base + i;
+        if (idx < n) out[idx] = off;
+        off += v[i];
+    }
+    if (d_total && blockIdx.x == gridDim.x - 1 && threadIdx.x == kThreads - 1) *d_total = off;
+}
+
+hipError_t scan_rec(const uint32_t* in, uint32_t* out, uint32_t n, uint32_t* d_total, uint32_t* tmp,
+                    size_t tmp_words, hipStream_t s) {
+    const uint32_t nb = (n + kScanTile - 1) / kScanTile;
+    if (nb <= 1) {
+        scan_apply_kernel<<<1, kThreads, 0, s>>>(in, out, n, nullptr, d_total);
+        return hipGetLastError();
+    }
+    if ((size_t)2 * nb > tmp_words) return hipErrorInvalidValue;
+    uint32_t* sums = tmp;
+    uint32_t* offs = tmp + nb;
+    scan_reduce_kernel<<<nb, kThreads, 0, s>>>(in, n, sums);
+    hipError_t e = scan_rec(sums, offs, nb, nullptr, tmp + 2 * nb, tmp_words - 2 * nb, s);
+    if (e != hipSuccess) return e;
+    scan_apply_kernel<<<nb, kThreads, 0, s>>>(in, out, n, offs, d_total);
+    return hipGetLastError();
+}
+
+size_t scan_tmp_words(uint32_t n) {
+    size_t words = 0;
+    uint32_t m = n;
+    while (m > (uint32_t)kScanTile) {
+        const uint32_t nb = (m + kScanTile - 1) / kScanTile;
+        words += 2 * (size_t)nb;
+        m = nb;
+    }
+    return words + 16;
+}
+
+// ---------------------------------------------------------------------------
+// Stable LSD radix sort, 8-bit digits, 4096 keys per workgroup per pass:
+// histogram per workgroup -> exclusive scan over (digit, workgroup) ->
+// stable scatter.  Within a workgroup the keys are ranked in order: each
+// wave finds its lanes with equal digit by ballots over the digit bits.
+// ---------------------------------------------------------------------------
+constexpr int kRsItems = 16;
+constexpr int kRsTile = kThreads * kRsItems;
+
+__global__ __launch_bounds__(kThreads) void radix_hist_kernel(const uint32_t* __restrict__ keys, uint32_t n,
+                                                               int shift, uint32_t nb, uint32_t* __restrict__ hist) {
+    __shared__ uint32_t cnt[256];
+    cnt[threadIdx.x] = 0;
+    __syncthreads();
+    const size_t base = (size_t)blockIdx.x * kRsTile;
+#pragma unroll 4
+    for (int i = 0; i < kRsItems; ++i) {
+        const size_t idx = base + (size_t)i * kThreads + threadIdx.x;
+        if (idx < n) atomicAdd(&cnt[(keys[idx] >> shift) & 255u], 1u);
+    }
+    __syncthreads();
+    hist[(size_t)threadIdx.x * nb + blockIdx.x] = cnt[threadIdx.x];
+}
+
+__global__ __launch_bounds__(kThreads) void radix_scatter_kernel(
+    const uint32_t* __restrict__ kin, const uint32_t* __restrict__ vin, uint32_t n, int shift, uint32_t nb,
+    const uint32_t* __restrict__ offs, uint32_t* __restrict__ kout, uint32_t* __restrict__ vout) {
+    __shared__ uint32_t base_d[256];
+    __shared__ uint32_t running[256];
+    __shared__ uint32_t wcnt[kThreads / 64][256];
+    const int tid = threadIdx.x, lane = __lane_id(), wave = tid / 64;
+    base_d[tid] = offs[(size_t)tid * nb + blockIdx.x];
+    running[tid] = 0;
+    const uint64_t lt_mask = (lane == 0) ? 0ull : ((~0ull) >> (64 - lane));
+    const size_t base = (size_t)blockIdx.x * kRsTile;
+    for (int it = 0; it < kRsItems; ++it) {
+        const size_t idx = base + (size_t)it * kThreads + tid;
+        const bool valid = idx < n;
+        const uint32_t key = valid ? kin[idx] : 0u;
+        const uint32_t val = valid ? vin[idx] : 0u;
+        const uint32_t d = (key >> shift) & 255u;
+#pragma unroll
+        for (int w = 0; w < kThreads / 64; ++w) wcnt[w][tid] = 0;
+        __syncthreads();
+        uint64_t peers = __ballot(valid);
+        if (!valid) peers = ~peers;
+#pragma unroll
+        for (int b = 0; b < 8; ++b) {
+            const bool bit = (d >> b) & 1u;
+            const uint64_t m = __ballot(bit);
+            peers &= bit ? m : ~m;
+        }
+        const uint32_t rank = __popcll(peers & lt_mask);
+        if (valid && rank == 0) wcnt[wave][d] = __popcll(peers);
+        __syncthreads();
+        if (valid) {
+            uint32_t pos = base_d[d] + running[d] + rank;
+            for (int w = 0; w < wave; ++w) pos += wcnt[w][d];
+            kout[pos] = key;
+            vout[pos] = val;
+        }
+        __syncthreads();
+        uint32_t add = 0;
+#pragma unroll
+        for (int w = 0; w < kThreads / 64; ++w) add += wcnt[w][tid];
+        running[tid] += add;
+        __syncthreads();
+    }
+}
+
+__global__ void gather_u32_kernel(const uint32_t* __restrict__ src, const uint32_t* __restrict__ idx,
+                                  uint32_t* __restrict__ dst, uint32_t n) {
+    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) dst[i] = src[idx[i]];
+}
+
+// One thread per depth rank: writes the kernel's (tile, id) pairs, row-major
+// over its rectangle, at its scanned offset.
+__global__ void emit_pairs_kernel(const uint32_t* __restrict__ sorted_ids, const uint32_t* __restrict__ offsets,
+                                  uint32_t n, const uint2* __restrict__ rect, uint32_t tiles_x,
+                                  uint32_t* __restrict__ keys, uint32_t* __restrict__ vals,
+                                  uint32_t* __restrict__ pair_off) {
+    const uint32_t r = blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= n) return;
+    const uint32_t id = sorted_ids[r];
+    const uint32_t off = offsets[r];
+    pair_off[id] = off;
+    const uint2 rc = rect[id];
+    const uint32_t x0 = rc.x & 0xffffu, y0 = rc.x >> 16, x1 = rc.y & 0xffffu, y1 = rc.y >> 16;
+    uint32_t i = off;
+    for (uint32_t ty = y0; ty < y1; ++ty)
+        for (uint32_t tx = x0; tx < x1; ++tx, ++i) {
+            keys[i] = ty * tiles_x + tx;
+            vals[i] = id;
+        }
+}
+
+__global__ void tile_ranges_kernel(const uint32_t* __restrict__ keys, uint32_t pairs, uint2* __restrict__ ranges) {
+    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= pairs) return;
+    const uint32_t k = keys[i];
+    if (i == 0 || keys[i - 1] != k) ranges[k].x = i;
+    if (i == pairs - 1 || keys[i + 1] != k) ranges[k].y = i + 1;
+}
+
+// ---------------------------------------------------------------------------
+// Forward compositing, one workgroup per tile, one thread per pixel.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(GSN_BLOCK) void raster_fwd_kernel(
+    const uint2* __restrict__ ranges, const uint32_t* __restrict__ ids, const float4* __restrict__ rec, uint32_t n,
+    DevCam cam, DevRenderOpts ro, float* __restrict__ img, float* __restrict__ Tfin,
+    uint32_t* __restrict__ ncontrib) {
+    __shared__ float4 s_a[GSN_BLOCK];
+    __shared__ float4 s_b[GSN_BLOCK];
+    __shared__ float s_c[GSN_BLOCK];
+    const int tile = blockIdx.x;
+    const int tx = tile % cam.tiles_x, ty = tile / cam.tiles_x;
+    const int px = tx * GSN_TILE + (threadIdx.x % GSN_TILE);
+    const int py = ty * GSN_TILE + (threadIdx.x / GSN_TILE);
+    const bool inside = px < cam.W && py < cam.H;
+    const uint2 rg = ranges[tile];
+    float T = 1.0f, C0 = 0.f, C1 = 0.f, C2 = 0.f;
+    uint32_t last = 0;
+    bool done = !inside;
+    const float fpx = (float)px, fpy = (float)py;
+    for (uint32_t base = rg.x; base < rg.y; base += GSN_BLOCK) {
+        if (__syncthreads_count(done) == GSN_BLOCK) break;
+        const uint32_t e = base + threadIdx.x;
+        if (e < rg.y) {
+            const uint32_t id = ids[e];
+            s_a[threadIdx.x] = rec[id];
+            s_b[threadIdx.x] = rec[n + id];
+            s_c[threadIdx.x] = rec[2 * (size_t)n + id].x;
+        }
+        __syncthreads();
+        const int cnt = min((uint32_t)GSN_BLOCK, rg.y - base);
+        for (int j = 0; j < cnt && !done; ++j) {
+            const float4 a = s_a[j], b = s_b[j];
+            const SplatEval ev = eval_splat(a.x, a.y, a.z, a.w, b.x, b.y, fpx, fpy, ro.alpha_max);
+            if (ev.alpha < ro.alpha_min) continue;
+            const float Tn = T * (1.0f - ev.alpha);
+            if (Tn < ro.T_min) {
+                done = true;
+                break;
+            }
+            const float w = ev.alpha * T;
+            C0 += w * b.z;
+            C1 += w * b.w;
+            C2 += w * s_c[j];
+            T = Tn;
+            last = base + j + 1 - rg.x;
+        }
+    }
+    if (inside) {
+        const size_t np = (size_t)cam.W * cam.H, pi = (size_t)py * cam.W + px;
+        img[pi] = C0 + T * ro.bg[0];
+        img[np + pi] = C1 + T * ro.bg[1];
+        img[2 * np + pi] = C2 + T * ro.bg[2];
+        Tfin[pi] = T;
+        ncontrib[pi] = last;
+    }
+}
+
+__global__ void downsample2x_kernel(const float* __restrict__ src, int W, int H, float* __restrict__ dst) {
+    const int w2 = W / 2, h2 = H / 2;
+    const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= (size_t)3 * w2 * h2) return;
+    const int x = (int)(i % w2), y = (int)((i / w2) % h2), ch = (int)(i / ((size_t)w2 * h2));
+    const float* s = src + (size_t)ch * W * H;
+    const float a = s[(size_t)(2 * y) * W + 2 * x], b = s[(size_t)(2 * y) * W + 2 * x + 1];
+    const float c = s[(size_t)(2 * y + 1) * W + 2 * x], d = s[(size_t)(2 * y + 1) * W + 2 * x + 1];
+    dst[i] = 0.25f * (((a + b) + c) + d);
+}
+
+}  // namespace
+
+// ------------------------------------------------------------------ launchers
+void launch_fill_u32(uint32_t* p, uint32_t v, size_t n, hipStream_t s) {
+    if (n) fill_u32_kernel<<<grid_for(n), kThreads, 0, s>>>(p, v, n);
+}
+void launch_fill_f32(float* p, float v, size_t n, hipStream_t s) {
+    if (n) fill_f32_kernel<<<grid_for(n), kThreads, 0, s>>>(p, v, n);
+}
+
+void launch_preprocess(const gsn_gaussians& g, const DevCam& cam, const DevRenderOpts& ro, float4* rec,
+                       uint2* rect, uint32_t* depth_key, uint32_t* ids, uint32_t* ntiles, hipStream_t s) {
+    if (g.n == 0) return;
+    const int K = (g.sh_degree + 1) * (g.sh_degree + 1);
+    preprocess_kernel<<<(g.n + kThreads - 1) / kThreads, kThreads, 0, s>>>(
+        g.d_pos, g.d_rot, g.d_scale, g.d_opac, g.d_sh, g.n, K, cam, ro, rec, rect, depth_key, ids, ntiles);
+}
+
+size_t scan_tmp_bytes(uint32_t n) {
+    const size_t hist_words = (size_t)256 * ((n + kRsTile - 1) / kRsTile);
+    return 4 * std::max(scan_tmp_words(n), scan_tmp_words((uint32_t)hist_words));
+}
+
+hipError_t exclusive_scan_u32(const uint32_t* in, uint32_t* out, uint32_t n, uint32_t* d_total, DevBuf& scan_tmp,
+                              hipStream_t s) {
+    const size_t words = scan_tmp_words(n);
+    hipError_t e = buf_reserve(scan_tmp, words * 4);
+    if (e != hipSuccess) return e;
+    return scan_rec(in, out, n, d_total, bp<uint32_t>(scan_tmp), words, s);
+}
+
+hipError_t radix_sort_pairs(uint32_t* k0, uint32_t* v0, uint32_t* k1, uint32_t* v1, uint32_t n, int bit_lo,
+                            int bit_hi, DevBuf& hist, DevBuf& scan_tmp, hipStream_t s) {
+    if (n == 0) return hipSuccess;
+    const uint32_t nb = (n + kRsTile - 1) / kRsTile;
+    hipError_t e = buf_reserve(hist, (size_t)256 * nb * 4 * 2);
+    if (e != hipSuccess) return e;
+    uint32_t* h = bp<uint32_t>(hist);
+    uint32_t* o = h + (size_t)256 * nb;
+    int passes = 0;
+    uint32_t *ka = k0, *va = v0, *kb = k1, *vb = v1;
+    for (int shift = bit_lo; shift < bit_hi; shift += 8, ++passes) {
+        radix_hist_kernel<<<nb, kThreads, 0, s>>>(ka, n, shift, nb, h);
+        e = exclusive_scan_u32(h, o, 256 * nb, nullptr, scan_tmp, s);
+        if (e != hipSuccess) return e;
+        radix_scatter_kernel<<<nb, kThreads, 0, s>>>(ka, va, n, shift, nb, o, kb, vb);
+        uint32_t* t = ka; ka = kb; kb = t;
+        t = va; va = vb; vb = t;
+    }
+    if (passes & 1) {
+        e = hipMemcpyAsync(k0, ka, (size_t)n * 4, hipMemcpyDeviceToDevice, s);
+        if (e == hipSuccess) e = hipMemcpyAsync(v0, va, (size_t)n * 4, hipMemcpyDeviceToDevice, s);
+        if (e != hipSuccess) return e;
+    }
+    return hipGetLastError();
+}
+
+void launch_gather_u32(const uint32_t* src, const uint32_t* idx, uint32_t* dst, uint32_t n, hipStream_t s) {
+    if (n) gather_u32_kernel<<<(n + kThreads - 1) / kThreads, kThreads, 0, s>>>(src, idx, dst, n);
+}
+
+void launch_emit_pairs(const uint32_t* sorted_ids, const uint32_t* offsets, uint32_t n, const uint2* rect,
+                       uint32_t tiles_x, uint32_t* keys, uint32_t* vals, uint32_t* pair_off, hipStream_t s) {
+    if (n) emit_pairs_kernel<<<(n + kThreads - 1) / kThreads, kThreads, 0, s>>>(sorted_ids, offsets, n, rect, tiles_x,
+                                                                               keys, vals, pair_off);
+}
+
+void launch_tile_ranges(const uint32_t* keys, uint32_t pairs, uint2* ranges, hipStream_t s) {
+    if (pairs) tile_ranges_kernel<<<(pairs + kThreads - 1) / kThreads, kThreads, 0, s>>>(keys, pairs, ranges);
+}
+
+void launch_raster_fwd(const uint2* ranges, const uint32_t* ids, const float4* rec, uint32_t n, const DevCam& cam,
+                       const DevRenderOpts& ro, float* img, float* Tfin, uint32_t* ncontrib, hipStream_t s) {
+    const int tiles = cam.tiles_x * cam.tiles_y;
+    raster_fwd_kernel<<<tiles, GSN_BLOCK, 0, s>>>(ranges, ids, rec, n, cam, ro, img, Tfin, ncontrib);
+}
+
+void launch_downsample2x(const float* src, int W, int H, float* dst, hipStream_t s) {
+    const size_t n = (size_t)3 * (W / 2) * (H / 2);
+    if (n) downsample2x_kernel<<<(unsigned)((n + kThreads - 1) / kThreads), kThreads, 0, s>>>(src, W, H, dst);
+}

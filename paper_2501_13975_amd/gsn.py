@@ -1,0 +1,305 @@
+"""ctypes binding of libgsn (include/gsn.h): argument marshalling only.
+
+Every step of the training path runs in the HIP library; this module turns
+torch device tensors into the plain pointers and structs of the C ABI.  It
+raises if the library has not been built -- there is no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import torch
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libgsn.so")
+
+GSN_BLK_BASE, GSN_BLK_VIEW, GSN_STEP_BASE, GSN_NZ = 35, 10, 11, 44
+STATUS = {0: "GSN_OK", -1: "GSN_E_INVALID", -2: "GSN_E_SHAPE", -3: "GSN_E_CAPACITY", -4: "GSN_E_HIP",
+          -5: "GSN_E_NOMEM"}
+
+_lib = None
+
+
+class GsnError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"{STATUS.get(status, status)}: {msg}")
+        self.status = status
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with __graft_entry__.build() "
+                               "(python paper_2501_13975_amd/build_lib.py)")
+        L = ctypes.CDLL(LIB_PATH)
+        P = ctypes.c_void_p
+        for name, args in {
+            "gsn_create": [ctypes.POINTER(P), ctypes.c_int32, P],
+            "gsn_destroy": [P], "gsn_set_stream": [P, P],
+            "gsn_frame_create": [P, ctypes.POINTER(P)], "gsn_frame_destroy": [P, P],
+            "gsn_render": [P, P, P, P, P, P, P],
+            "gsn_accumulate_hessian": [P, P, P, P, P, ctypes.c_int32, P, P],
+            "gsn_local_newton_solve": [P, P, P, P, P, P],
+            "gsn_apply_step": [P, P, P, P, ctypes.c_uint32],
+            "gsn_blocks_zero": [P, P],
+            "gsn_downsample2x": [P, P, ctypes.c_int32, ctypes.c_int32, P],
+            "gsn_camera_knn": [P, ctypes.c_int32, P, ctypes.c_int32, P],
+            "gsn_frame_info": [P, P, P, P, P],
+            "gsn_frame_lists": [P, P, P, P, P, P, P],
+            "gsn_frame_zstats": [P, P, P],
+            "gsn_frame_loss_maps": [P, P, P, P],
+        }.items():
+            fn = getattr(L, name)
+            fn.argtypes = args
+            fn.restype = ctypes.c_int
+        L.gsn_last_error.argtypes = [P]
+        L.gsn_last_error.restype = ctypes.c_char_p
+        L.gsn_blocks_floats.argtypes = [ctypes.c_int32, ctypes.c_int32]
+        L.gsn_blocks_floats.restype = ctypes.c_int64
+        L.gsn_steps_floats.argtypes = [ctypes.c_int32, ctypes.c_int32]
+        L.gsn_steps_floats.restype = ctypes.c_int64
+        _lib = L
+    return _lib
+
+
+# ------------------------------------------------------------------ C structs
+class CGaussians(ctypes.Structure):
+    _fields_ = [("d_pos", ctypes.c_void_p), ("d_rot", ctypes.c_void_p), ("d_scale", ctypes.c_void_p),
+                ("d_opac", ctypes.c_void_p), ("d_sh", ctypes.c_void_p), ("n", ctypes.c_int32),
+                ("sh_degree", ctypes.c_int32)]
+
+
+class CCamera(ctypes.Structure):
+    _fields_ = [("R", ctypes.c_float * 9), ("t", ctypes.c_float * 3), ("fx", ctypes.c_float),
+                ("fy", ctypes.c_float), ("cx", ctypes.c_float), ("cy", ctypes.c_float),
+                ("width", ctypes.c_int32), ("height", ctypes.c_int32), ("znear", ctypes.c_float)]
+
+
+class CRenderOpts(ctypes.Structure):
+    _fields_ = [("tile", ctypes.c_int32), ("alpha_min", ctypes.c_float), ("alpha_max", ctypes.c_float),
+                ("T_min", ctypes.c_float), ("kappa", ctypes.c_float), ("radius_sigma", ctypes.c_float),
+                ("bg", ctypes.c_float * 3)]
+
+
+class CLossOpts(ctypes.Structure):
+    _fields_ = [("lambda_ssim", ctypes.c_float), ("weight", ctypes.c_float), ("keep_zstats", ctypes.c_int32)]
+
+
+class CSolveOpts(ctypes.Structure):
+    _fields_ = [("damp_rel", ctypes.c_float), ("damp_abs", ctypes.c_float), ("pivot_min", ctypes.c_float),
+                ("max_escalations", ctypes.c_int32), ("barrier_beta", ctypes.c_float),
+                ("sh_floor", ctypes.c_float), ("scale_floor", ctypes.c_float), ("opac_ftb", ctypes.c_float),
+                ("npix_primary", ctypes.c_int32), ("kappa", ctypes.c_float)]
+
+
+class CBlocks(ctypes.Structure):
+    _fields_ = [("d_data", ctypes.c_void_p), ("n", ctypes.c_int32), ("n_views", ctypes.c_int32)]
+
+
+class CSteps(ctypes.Structure):
+    _fields_ = [("d_data", ctypes.c_void_p), ("d_flags", ctypes.c_void_p), ("n", ctypes.c_int32),
+                ("sh_degree", ctypes.c_int32)]
+
+
+def render_opts(alpha_min=1.0 / 255.0, alpha_max=0.99, T_min=1e-4, kappa=0.3, radius_sigma=3.0,
+                bg=(0.0, 0.0, 0.0)):
+    return CRenderOpts(16, alpha_min, alpha_max, T_min, kappa, radius_sigma, (ctypes.c_float * 3)(*bg))
+
+
+def loss_opts(lambda_ssim=0.2, weight=1.0, keep_zstats=False):
+    return CLossOpts(lambda_ssim, weight, int(keep_zstats))
+
+
+def solve_opts(npix_primary, kappa=0.3, damp_rel=1e-3, damp_abs=1e-12, pivot_min=1e-6, max_escalations=7,
+               barrier_beta=1e-2, sh_floor=1e-3, scale_floor=0.1, opac_ftb=0.995):
+    return CSolveOpts(damp_rel, damp_abs, pivot_min, max_escalations, barrier_beta, sh_floor, scale_floor,
+                      opac_ftb, int(npix_primary), kappa)
+
+
+def camera(c) -> CCamera:
+    """synth.scenes.Camera -> C struct."""
+    import numpy as np
+    R = np.asarray(c.R, np.float32).reshape(-1)
+    t = np.asarray(c.t, np.float32)
+    return CCamera((ctypes.c_float * 9)(*R.tolist()), (ctypes.c_float * 3)(*t.tolist()), c.fx, c.fy, c.cx,
+                   c.cy, c.width, c.height, c.znear)
+
+
+def _ptr(t: torch.Tensor):
+    if t is None:
+        return None
+    if not t.is_cuda:
+        raise ValueError("expected a device tensor")
+    if not t.is_contiguous():
+        raise ValueError("expected a contiguous tensor")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+class DeviceGaussians:
+    """Kernel attributes as device tensors: pos [3,N], rot [4,N], scale [3,N], opac [N], sh [3,K,N] (f32)."""
+
+    def __init__(self, pos, rot, scale, opac, sh, sh_degree):
+        self.pos, self.rot, self.scale, self.opac, self.sh = pos, rot, scale, opac, sh
+        self.sh_degree = int(sh_degree)
+
+    @staticmethod
+    def from_host(g, device="cuda"):
+        f = lambda a: torch.as_tensor(a, dtype=torch.float32).contiguous().to(device)  # noqa: E731
+        return DeviceGaussians(f(g.pos), f(g.rot), f(g.scale), f(g.opac), f(g.sh), g.sh_degree)
+
+    @property
+    def n(self):
+        return int(self.pos.shape[1])
+
+    def clone(self):
+        return DeviceGaussians(self.pos.clone(), self.rot.clone(), self.scale.clone(), self.opac.clone(),
+                               self.sh.clone(), self.sh_degree)
+
+    def c(self) -> CGaussians:
+        return CGaussians(_ptr(self.pos), _ptr(self.rot), _ptr(self.scale), _ptr(self.opac), _ptr(self.sh),
+                          self.n, self.sh_degree)
+
+    def to_host(self):
+        from synth.scenes import Gaussians
+        return Gaussians(self.pos.cpu().numpy(), self.rot.cpu().numpy(), self.scale.cpu().numpy(),
+                         self.opac.cpu().numpy(), self.sh.cpu().numpy(), self.sh_degree)
+
+
+class Frame:
+    def __init__(self, ctx: "Context"):
+        self.ctx = ctx
+        h = ctypes.c_void_p()
+        ctx._check(lib().gsn_frame_create(ctx.h, ctypes.byref(h)))
+        self.h = h
+
+    def close(self):
+        if self.h:
+            lib().gsn_frame_destroy(self.ctx.h, self.h)
+            self.h = None
+
+    def info(self):
+        pairs, tx, ty = ctypes.c_int64(), ctypes.c_int32(), ctypes.c_int32()
+        self.ctx._check(lib().gsn_frame_info(self.ctx.h, self.h, ctypes.byref(pairs), ctypes.byref(tx),
+                                             ctypes.byref(ty)))
+        return pairs.value, tx.value, ty.value
+
+    def lists(self, n, npix):
+        """Copies of (ranges [tiles,2] u32, ids [pairs] u32, depth bits [n] u32, rect [4,n] i32, ncontrib [npix])."""
+        pairs, tx, ty = self.info()
+        dev = self.ctx.device
+        ranges = torch.zeros(tx * ty * 2, dtype=torch.int32, device=dev)
+        ids = torch.zeros(max(pairs, 1), dtype=torch.int32, device=dev)
+        depth = torch.zeros(max(n, 1), dtype=torch.int32, device=dev)
+        rect = torch.zeros(4 * max(n, 1), dtype=torch.int32, device=dev)
+        nc = torch.zeros(npix, dtype=torch.int32, device=dev)
+        self.ctx._check(lib().gsn_frame_lists(self.ctx.h, self.h, _ptr(ranges), _ptr(ids), _ptr(depth),
+                                              _ptr(rect), _ptr(nc)))
+        torch.cuda.synchronize(dev)
+        return ranges.view(-1, 2), ids[:pairs], depth[:n], rect[:4 * n].view(4, n), nc
+
+    def loss_maps(self, H, W):
+        dL = torch.zeros(3, H, W, dtype=torch.float32, device=self.ctx.device)
+        h = torch.zeros(3, H, W, dtype=torch.float32, device=self.ctx.device)
+        self.ctx._check(lib().gsn_frame_loss_maps(self.ctx.h, self.h, _ptr(dL), _ptr(h)))
+        return dL, h
+
+    def zstats(self, n):
+        out = torch.zeros(GSN_NZ * max(n, 1), dtype=torch.float32, device=self.ctx.device)
+        self.ctx._check(lib().gsn_frame_zstats(self.ctx.h, self.h, _ptr(out)))
+        return out[:GSN_NZ * n].view(GSN_NZ, n)
+
+
+class Context:
+    def __init__(self, device=0, stream=None):
+        self.device = torch.device("cuda", device) if isinstance(device, int) else torch.device(device)
+        idx = self.device.index if self.device.index is not None else 0
+        stream = stream or torch.cuda.current_stream(self.device)
+        h = ctypes.c_void_p()
+        st = lib().gsn_create(ctypes.byref(h), idx, ctypes.c_void_p(stream.cuda_stream))
+        if st != 0:
+            raise GsnError(st, "gsn_create failed (no HIP device?)")
+        self.h = h
+        self.stream = stream
+
+    def _check(self, st):
+        if st != 0:
+            raise GsnError(st, lib().gsn_last_error(self.h).decode())
+
+    def close(self):
+        if self.h:
+            lib().gsn_destroy(self.h)
+            self.h = None
+
+    def frame(self) -> Frame:
+        return Frame(self)
+
+    def render(self, g: DeviceGaussians, cam: CCamera, ro: CRenderOpts, frame: Frame, rgb=None, T=None):
+        cg = g.c()
+        self._check(lib().gsn_render(self.h, ctypes.byref(cg), ctypes.byref(cam), ctypes.byref(ro), frame.h,
+                                     _ptr(rgb), _ptr(T)))
+
+    def accumulate_hessian(self, g, frame, target, lo: CLossOpts, view_slot, blocks: "Blocks", loss_out=None):
+        cg = g.c()
+        cb = blocks.c()
+        self._check(lib().gsn_accumulate_hessian(self.h, ctypes.byref(cg), frame.h, _ptr(target),
+                                                 ctypes.byref(lo), int(view_slot), ctypes.byref(cb),
+                                                 _ptr(loss_out)))
+
+    def local_newton_solve(self, g, primary: CCamera, blocks: "Blocks", so: CSolveOpts, steps: "Steps"):
+        cg, cb, cs = g.c(), blocks.c(), steps.c()
+        self._check(lib().gsn_local_newton_solve(self.h, ctypes.byref(cg), ctypes.byref(primary),
+                                                 ctypes.byref(cb), ctypes.byref(so), ctypes.byref(cs)))
+
+    def apply_step(self, g, steps: "Steps", so: CSolveOpts, group_mask=31):
+        cg, cs = g.c(), steps.c()
+        self._check(lib().gsn_apply_step(self.h, ctypes.byref(cg), ctypes.byref(cs), ctypes.byref(so),
+                                         int(group_mask)))
+
+    def blocks_zero(self, blocks: "Blocks"):
+        cb = blocks.c()
+        self._check(lib().gsn_blocks_zero(self.h, ctypes.byref(cb)))
+
+    def downsample2x(self, src, W, H, dst):
+        self._check(lib().gsn_downsample2x(self.h, _ptr(src), int(W), int(H), _ptr(dst)))
+
+
+class Blocks:
+    def __init__(self, n, n_views, device):
+        self.n, self.n_views = int(n), int(n_views)
+        nf = lib().gsn_blocks_floats(self.n, self.n_views)
+        self.data = torch.zeros(max(nf, 1), dtype=torch.float32, device=device)
+
+    def c(self):
+        return CBlocks(_ptr(self.data), self.n, self.n_views)
+
+    def view(self):
+        return self.data[:(GSN_BLK_BASE + GSN_BLK_VIEW * self.n_views) * self.n].view(-1, self.n)
+
+
+class Steps:
+    def __init__(self, n, sh_degree, device):
+        self.n, self.sh_degree = int(n), int(sh_degree)
+        nf = lib().gsn_steps_floats(self.n, self.sh_degree)
+        self.data = torch.zeros(max(nf, 1), dtype=torch.float32, device=device)
+        self.flags = torch.zeros(5 * max(self.n, 1), dtype=torch.int32, device=device)
+
+    def c(self):
+        return CSteps(_ptr(self.data), _ptr(self.flags), self.n, self.sh_degree)
+
+    def view(self):
+        K = (self.sh_degree + 1) ** 2
+        return self.data[:(GSN_STEP_BASE + 3 * K) * self.n].view(-1, self.n), self.flags[:5 * self.n].view(5, self.n)
+
+
+def camera_knn(centers, scene_center, k=3):
+    import numpy as np
+    c = np.ascontiguousarray(centers, np.float64)
+    sc = np.ascontiguousarray(scene_center, np.float64)
+    out = np.zeros((c.shape[0], k), np.int32)
+    st = lib().gsn_camera_knn(c.ctypes.data_as(ctypes.c_void_p), c.shape[0], sc.ctypes.data_as(ctypes.c_void_p),
+                              k, out.ctypes.data_as(ctypes.c_void_p))
+    if st != 0:
+        raise GsnError(st, "gsn_camera_knn: k must be in 1..ncam-1")
+    return out
