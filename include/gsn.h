@@ -86,9 +86,13 @@ typedef struct {
 } gsn_loss_opts;
 
 /* Solve options.  Damping: Cholesky of H + mu_j I, mu_j = mu0 10^j for
- * j = 0..max_escalations with mu0 = damp_rel * max(mean diag H, 0) +
- * damp_abs / (3 |I|); accepted when all pivots are positive and
- * min/max pivot >= pivot_min; otherwise the scaled gradient step.
+ * j = 0..max_escalations with mu0 = damp_rel * |H|_F / sqrt(n) +
+ * damp_abs / (3 |I|); accepted when every pivot exceeds
+ * pivot_min (|H|_F / sqrt(n) + mu_j) and min/max pivot >= pivot_min;
+ * otherwise the scaled gradient step.  Steps are
+ * then clamped to trust radii: |Delta p| <= trust_pos * max(s),
+ * |theta| <= trust_rot, |Delta s| <= trust_scale * |s|.  The small systems are
+ * solved in double precision.
  * Opacity barrier weight alpha_sigma = barrier_beta / (3 |I|), |I| =
  * npix_primary.  sh_floor: per-view colour curvature floor relative to the
  * largest.  scale_floor: s_new >= scale_floor * s.  opac_ftb:
@@ -101,17 +105,20 @@ typedef struct {
     float barrier_beta, sh_floor, scale_floor, opac_ftb;
     int32_t npix_primary;
     float kappa;
+    float trust_pos, trust_rot, trust_scale;
 } gsn_solve_opts;
 
 /* Per-kernel gradient/Hessian blocks, summed over the views added so far.
  * d_data is a device array of gsn_blocks_floats(n, n_views) floats laid out
  * [GSN_BLK_BASE + GSN_BLK_VIEW * n_views][n]:
- *   rows 0..2 g_p, 3..8 H_p (xx xy xz yy yz zz), 9..12 g_q, 13..22 H_q
- *   (upper triangle row by row), 23..25 g_s, 26..31 H_s, 32 g_sigma,
- *   33 H_sigma, 34 coverage of the primary target (sum of alpha T);
- *   then per view slot v at 35 + 10 v: gamma (dL/dc~, 3), s (sum h (alpha T)^2,
- *   3), view direction r (3), coverage (1). */
-#define GSN_BLK_BASE 35
+ *   rows 0..2 g_p, 3..8 H_p (xx xy xz yy yz zz); rows 9..11 g_omega and 12..17
+ *   H_omega for the rotation, parametrised by the left rotation vector omega
+ *   (q <- exp(omega/2) q, so the paper's rotation angle about r_k is omega =
+ *   theta r_k); 18..20 g_s, 21..26 H_s; 27 g_sigma, 28 H_sigma; 29 coverage of
+ *   the primary target (sum of alpha T); then per view slot v at 30 + 10 v:
+ *   gamma (dL/dc~, 3), s (sum h (alpha T)^2, 3), view direction r (3),
+ *   coverage (1). */
+#define GSN_BLK_BASE 30
 #define GSN_BLK_VIEW 10
 typedef struct {
     float* d_data;
@@ -233,11 +240,19 @@ gsn_status gsn_frame_info(gsn_ctx* ctx, const gsn_frame* frame, int64_t* h_pairs
 gsn_status gsn_frame_lists(gsn_ctx* ctx, const gsn_frame* frame, uint32_t* d_ranges, uint32_t* d_ids,
                            uint32_t* d_depth_bits, int32_t* d_rect, uint32_t* d_ncontrib);
 /* Per-kernel projected-space statistics of the last gsn_accumulate_hessian on
- * this frame that ran with keep_zstats (float [44][n]): gradient w.r.t.
- * (pi_x, pi_y, Q_xx, Q_xy, Q_yy) (5), sigma (1), c~ (3); Hessian block over
- * (pi, Q) (15, upper triangle), its cross block with c~ (5 x 3), the c~
- * diagonal (3), the sigma-sigma entry (1) and the coverage sum alpha T (1). */
+ * this frame that ran with keep_zstats (float [44][n]), in each kernel's
+ * principal frame (pi' = V^T pi, Q' = V^T Q V, V from gsn_frame_records):
+ * gradient w.r.t. (pi'_1, pi'_2, Q'_11, Q'_12, Q'_22) (5), sigma (1), c~ (3);
+ * Hessian block over (pi', Q') (15, upper triangle), its cross block with c~
+ * (5 x 3), the c~ diagonal (3), the sigma-sigma entry (1) and the coverage
+ * sum alpha T (1). */
 gsn_status gsn_frame_zstats(gsn_ctx* ctx, const gsn_frame* frame, float* d_out);
+/* Copy of the projected kernels of the last render (float [12][n]): image
+ * position (2), conic in the principal frame q1 = 1/lambda1, q2 = 1/lambda2 (2),
+ * principal axis (cos, sin) (2), opacity (1), view-dependent colour (3), 0, 0.
+ * The per-kernel statistics of gsn_frame_zstats are expressed in this
+ * principal frame. */
+gsn_status gsn_frame_records(gsn_ctx* ctx, const gsn_frame* frame, float* d_out);
 /* Copies of the per-pixel loss gradient dL/dc and diagonal Hessian d2L/dc2
  * ([3][H][W] floats each) of the last gsn_accumulate_hessian on this frame. */
 gsn_status gsn_frame_loss_maps(gsn_ctx* ctx, const gsn_frame* frame, float* d_dL, float* d_h);

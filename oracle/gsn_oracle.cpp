@@ -57,6 +57,9 @@ enum Opt {
     O_SCALE_FLOOR,   // s_new >= scale_floor * s
     O_OPAC_FTB,      // fraction-to-boundary factor for the opacity update
     O_NPIX_PRIMARY,  // |I| of the primary target (barrier and damping scales)
+    O_TRUST_POS,     // |Delta p| <= trust_pos * max_a s_a
+    O_TRUST_ROT,     // |theta| <= trust_rot (radians)
+    O_TRUST_SCALE,   // |Delta s| <= trust_scale * |s|
     O_COUNT
 };
 
@@ -671,14 +674,16 @@ extern "C" {
 
 // Number of doubles per kernel written by orc_blocks.
 enum {
-    B_GP = 0, B_HP = 3, B_GQ = 12, B_HQ = 16, B_GS = 32, B_HS = 35, B_GO = 44, B_HO = 45,
-    B_W = 46, B_GAM = 47, B_SC = 50, B_R = 53, B_COUNT = 56
+    B_GP = 0, B_HP = 3, B_GW = 12, B_HW = 15, B_GS = 24, B_HS = 27, B_GO = 36, B_HO = 37,
+    B_W = 38, B_GAM = 39, B_SC = 42, B_R = 45, B_COUNT = 48
 };
 int orc_block_count() { return B_COUNT; }
 
 // Per-kernel gradient and Hessian blocks of one view's loss for the kernels
 // in sel (eq. local_hessian_gradient), with respect to position p (3x3),
-// quaternion q (4x4, through q/|q|), scale s (3x3) and opacity sigma (1x1),
+// the left rotation vector omega of the orientation (3x3; q(omega) =
+// exp(omega/2) q, so the paper's rotation by theta about r_k is omega = theta r_k),
+// scale s (3x3) and opacity sigma (1x1),
 // plus the colour statistics that determine the SH blocks: per channel
 // gamma = dL/dc~ and s = sum_pix h (alpha T)^2 (so that the SH gradient is
 // gamma Y(r) and the SH Hessian s Y(r) Y(r)^T, colour being linear in the
@@ -714,10 +719,19 @@ int orc_blocks(int n, int K, const double* pos, const double* rot, const double*
         for (int a = 0; a < 3; ++a) { pj[a] = Jet<3>::var(p[a], a); pq[a] = Jet<3>(q[a]); ps[a] = Jet<3>(s[a]); }
         pq[3] = Jet<3>(q[3]);
         const Proj<Jet<3>> PP = project<Jet<3>>(pj, pq, ps, shk, K, c, kappa);
-        Jet<4> qp[3], qq[4], qs[3];
-        for (int a = 0; a < 3; ++a) { qp[a] = Jet<4>(p[a]); qs[a] = Jet<4>(s[a]); }
-        for (int a = 0; a < 4; ++a) qq[a] = Jet<4>::var(q[a], a);
-        const Proj<Jet<4>> PQ = project<Jet<4>>(qp, qq, qs, shk, K, c, kappa);
+        // q(omega) = exp(omega/2) q with exp(omega/2) = (1 - |omega|^2/8, omega/2) to second order
+        Jet<3> wp[3], wq[4], ws[3];
+        {
+            const Jet<3> w0 = Jet<3>::var(0.0, 0), w1 = Jet<3>::var(0.0, 1), w2 = Jet<3>::var(0.0, 2);
+            const Jet<3> e0 = 1.0 - (w0 * w0 + w1 * w1 + w2 * w2) / 8.0;
+            const Jet<3> e1 = 0.5 * w0, e2 = 0.5 * w1, e3 = 0.5 * w2;
+            wq[0] = e0 * q[0] - e1 * q[1] - e2 * q[2] - e3 * q[3];
+            wq[1] = e0 * q[1] + e1 * q[0] + e2 * q[3] - e3 * q[2];
+            wq[2] = e0 * q[2] + e2 * q[0] + e3 * q[1] - e1 * q[3];
+            wq[3] = e0 * q[3] + e3 * q[0] + e1 * q[2] - e2 * q[1];
+        }
+        for (int a = 0; a < 3; ++a) { wp[a] = Jet<3>(p[a]); ws[a] = Jet<3>(s[a]); }
+        const Proj<Jet<3>> PW = project<Jet<3>>(wp, wq, ws, shk, K, c, kappa);
         Jet<3> sp[3], sq[4], ss[3];
         for (int a = 0; a < 3; ++a) { sp[a] = Jet<3>(p[a]); ss[a] = Jet<3>::var(s[a], a); }
         for (int a = 0; a < 4; ++a) sq[a] = Jet<3>(q[a]);
@@ -727,7 +741,6 @@ int orc_blocks(int n, int K, const double* pos, const double* rot, const double*
         to_jets<1>(PV, opi, oQ, oct);
         const Jet<1> osig = Jet<1>::var(sigv, 0);
         const Jet<3> sig3(sigv);
-        const Jet<4> sig4(sigv);
         // view direction
         double d[3], dn = 0;
         for (int a = 0; a < 3; ++a) { d[a] = p[a] - c.o[a]; dn += d[a] * d[a]; }
@@ -737,7 +750,7 @@ int orc_blocks(int n, int K, const double* pos, const double* rot, const double*
                           [&](double x, double y, double T, const double* A, double alpha, bool clamped,
                               const double* dl, const double* hh) {
                               pixel_accum<3>(PP.pi, PP.Q, sig3, PP.ct, x, y, T, A, clamped, amax, dl, hh, B + B_GP, B + B_HP);
-                              pixel_accum<4>(PQ.pi, PQ.Q, sig4, PQ.ct, x, y, T, A, clamped, amax, dl, hh, B + B_GQ, B + B_HQ);
+                              pixel_accum<3>(PW.pi, PW.Q, sig3, PW.ct, x, y, T, A, clamped, amax, dl, hh, B + B_GW, B + B_HW);
                               pixel_accum<3>(PS.pi, PS.Q, sig3, PS.ct, x, y, T, A, clamped, amax, dl, hh, B + B_GS, B + B_HS);
                               pixel_accum<1>(opi, oQ, osig, oct, x, y, T, A, clamped, amax, dl, hh, B + B_GO, B + B_HO);
                               // colour: dc_ch/dc~_ch = alpha T, and c is linear in c~
@@ -793,13 +806,17 @@ int orc_zstats(int n, int K, const double* pos, const double* rot, const double*
 // ---------------------------------------------------------------------------
 // Local Newton solves in the paper's reduced coordinates (Sec. 4.2), with the
 // damping rule this implementation adopts where the paper specifies none:
-// Cholesky of H + mu_j I, mu_j = mu0 10^j (j = 0..max_esc), accepted when every
-// pivot is positive and min/max pivot >= pivot_min; if every attempt fails the
-// step is the scaled gradient -g / (mean |H_ii| + mu_max).
+// Cholesky of H + mu_j I, mu_j = mu0 10^j (j = 0..max_esc), mu0 = damp_rel |H|_F /
+// sqrt(n) + damp_abs / (3 |I|), accepted when every pivot exceeds pivot_min
+// (|H|_F / sqrt(n) + mu_j) and min/max pivot >= pivot_min; if every attempt fails the step is the scaled
+// gradient -g / (|H|_F / sqrt(n) + mu_max).  The step is then clamped to the
+// group's trust radius.
 // ---------------------------------------------------------------------------
 namespace {
 
-bool cholesky_solve(int n, const double* A, const double* b, double pivot_min, double* x) {
+// Cholesky solve of A x = b; fails unless every pivot exceeds `floor` and
+// min/max pivot >= pivot_min.
+bool cholesky_solve(int n, const double* A, const double* b, double pivot_min, double* x, double floor = 0.0) {
     double L[16 * 16];
     double dmin = std::numeric_limits<double>::infinity(), dmax = 0.0;
     for (int i = 0; i < n; ++i) {
@@ -807,7 +824,7 @@ bool cholesky_solve(int n, const double* A, const double* b, double pivot_min, d
             double s = A[i * n + j];
             for (int k = 0; k < j; ++k) s -= L[i * n + k] * L[j * n + k];
             if (i == j) {
-                if (!(s > 0.0)) return false;
+                if (!(s > floor)) return false;
                 dmin = std::min(dmin, s);
                 dmax = std::max(dmax, s);
                 L[i * n + i] = std::sqrt(s);
@@ -832,17 +849,16 @@ bool cholesky_solve(int n, const double* A, const double* b, double pivot_min, d
 }
 
 // Solves (H + mu I) x = -g by the damping rule; returns the escalation index j
-// that succeeded, or -1 for the scaled-gradient fallback.
-int damped_solve(int n, const double* H, const double* g, const double* o, double* x) {
+// that succeeded, or -1 for the scaled-gradient fallback.  *cond receives the
+// 2-norm condition number of the matrix that was solved (1 for the fallback).
+int damped_solve(int n, const double* H, const double* g, const double* o, double* x, double* cond) {
     const double abs_scale = 1.0 / (3.0 * o[O_NPIX_PRIMARY]);
-    double md = 0.0, ma = 0.0;
-    for (int i = 0; i < n; ++i) {
-        md += H[i * n + i];
-        ma += std::fabs(H[i * n + i]);
-    }
-    md /= n;
-    ma /= n;
-    const double mu0 = o[O_DAMP_REL] * std::max(md, 0.0) + o[O_DAMP_ABS] * abs_scale;
+    // scale of H: Frobenius norm / sqrt(n) (invariant to the choice of reduced basis,
+    // positive for indefinite H)
+    double ma = 0.0;
+    for (int i = 0; i < n * n; ++i) ma += H[i] * H[i];
+    ma = std::sqrt(ma / n);
+    const double mu0 = o[O_DAMP_REL] * ma + o[O_DAMP_ABS] * abs_scale;
     const int jmax = (int)o[O_MAX_ESC];
     double A[16 * 16], b[16];
     for (int i = 0; i < n; ++i) b[i] = -g[i];
@@ -850,12 +866,31 @@ int damped_solve(int n, const double* H, const double* g, const double* o, doubl
     for (int j = 0; j <= jmax; ++j) {
         for (int i = 0; i < n * n; ++i) A[i] = H[i];
         for (int i = 0; i < n; ++i) A[i * n + i] += mu;
-        if (cholesky_solve(n, A, b, o[O_PIVOT_MIN], x)) return j;
+        // a pivot must also exceed pivot_min times the size of H + mu I, so that an
+        // indefinite H shifted to (nearly) singular is not accepted
+        if (cholesky_solve(n, A, b, o[O_PIVOT_MIN], x, o[O_PIVOT_MIN] * (ma + mu))) {
+            *cond = 1.0;
+            if (n == 2) {
+                const double mid = 0.5 * (A[0] + A[3]), rad = std::sqrt(0.25 * (A[0] - A[3]) * (A[0] - A[3]) + A[1] * A[1]);
+                *cond = (mid + rad) / (mid - rad);
+            }
+            return j;
+        }
         if (j < jmax) mu *= 10.0;
     }
     const double den = ma + mu;
     for (int i = 0; i < n; ++i) x[i] = -g[i] / den;
+    *cond = 1.0;
     return -1;
+}
+
+// Radial trust-region clamp: scales x so that |x| <= radius.
+void clamp_norm(int n, double* x, double radius) {
+    double nn = 0.0;
+    for (int i = 0; i < n; ++i) nn += x[i] * x[i];
+    nn = std::sqrt(nn);
+    if (nn > radius && nn > 0.0)
+        for (int i = 0; i < n; ++i) x[i] *= radius / nn;
 }
 
 void quat_mul(const double a[4], const double b[4], double r[4]) {
@@ -870,16 +905,19 @@ void quat_mul(const double a[4], const double b[4], double r[4]) {
 extern "C" {
 
 // Summed-block layout consumed by orc_solve: per kernel
-//   g_p 3 | H_p 9 | g_q 4 | H_q 16 | g_s 3 | H_s 9 | g_sig | H_sig | w_primary   (47)
+//   g_p 3 | H_p 9 | g_omega 3 | H_omega 9 | g_s 3 | H_s 9 | g_sig | H_sig | w_primary   (39)
 // followed by V view records (gamma 3 | s 3 | r 3 | w 1).
 // Step layout: dpos 3 | dtheta | axis 3 | dscale 3 | dopac | dsh [3][K]   (11 + 3K)
 // Decisions [n][5]: escalation index for (position, rotation, scale, opacity),
 // -1 = gradient fallback, -2 = kernel not visible in the primary (no step);
 // the fifth entry is the number of views used by the colour solve.
-enum { S_COUNT_BASE = 47, S_VIEW = 10, ST_DPOS = 0, ST_DTH = 3, ST_AXIS = 4, ST_DS = 7, ST_DO = 10, ST_DSH = 11 };
+// cond [n][4] (may be NULL): condition number of each group's solved matrix.
+// Every step is then clamped to its group's trust radius.
+enum { S_COUNT_BASE = 39, S_VIEW = 10, ST_DPOS = 0, ST_DTH = 3, ST_AXIS = 4, ST_DS = 7, ST_DO = 10, ST_DSH = 11 };
 
 int orc_solve(int n, int K, const double* pos, const double* rot, const double* scale, const double* opac,
-              const double* cam, const double* o, int V, const double* blocks, double* steps, int32_t* dec) {
+              const double* cam, const double* o, int V, const double* blocks, double* steps, int32_t* dec,
+              double* cond) {
     const Cam c = load_cam(cam);
     const int NB = S_COUNT_BASE + V * S_VIEW, NS = 11 + 3 * K;
     const double kappa = o[O_SMOOTH] != 0.0 ? 0.0 : o[O_KAPPA];
@@ -889,9 +927,12 @@ int orc_solve(int n, int K, const double* pos, const double* rot, const double* 
         const double* B = blocks + (size_t)k * NB;
         double* st = steps + (size_t)k * NS;
         int32_t* dk = dec + (size_t)k * 5;
+        double cnd[4] = {1.0, 1.0, 1.0, 1.0};
         std::fill(st, st + NS, 0.0);
         for (int i = 0; i < 5; ++i) dk[i] = -2;
-        if (!(B[46] > 0.0)) continue;  // only kernels the primary target sees are trained
+        if (cond)
+            for (int i = 0; i < 4; ++i) cond[(size_t)k * 4 + i] = 1.0;
+        if (!(B[38] > 0.0)) continue;  // only kernels the primary target sees are trained
         double p[3], q[4], s[3];
         for (int a = 0; a < 3; ++a) p[a] = pos[(size_t)a * n + k];
         for (int a = 0; a < 4; ++a) q[a] = rot[(size_t)a * n + k];
@@ -927,23 +968,21 @@ int orc_solve(int n, int K, const double* pos, const double* rot, const double* 
                     H2[i * 2 + j] = acc;
                 }
             }
-            dk[0] = damped_solve(2, H2, g2, o, dv);
+            dk[0] = damped_solve(2, H2, g2, o, dv, &cnd[0]);
+            clamp_norm(2, dv, o[O_TRUST_POS] * std::max(s[0], std::max(s[1], s[2])));
             for (int a = 0; a < 3; ++a) st[ST_DPOS + a] = ux[a] * dv[0] + uy[a] * dv[1];
         }
-        // Rotation: q(theta) = dq(theta) * q with dq = [cos(theta/2), sin(theta/2) r].
+        // Rotation: q(theta) = dq(theta) * q with dq = [cos(theta/2), sin(theta/2) r], the left
+        // rotation by omega = theta r: g_theta = r . g_omega, H_theta = r^T H_omega r.
         {
-            const double rq[4] = {0.0, 0.5 * r[0], 0.5 * r[1], 0.5 * r[2]};
-            double t[4];
-            quat_mul(rq, q, t);  // dq/dtheta at 0; d2q/dtheta2 at 0 is -q/4
-            double gt = 0.0, Ht = 0.0, gq_q = 0.0;
-            for (int a = 0; a < 4; ++a) {
-                gt += B[12 + a] * t[a];
-                gq_q += B[12 + a] * q[a];
-                for (int b = 0; b < 4; ++b) Ht += t[a] * B[16 + a * 4 + b] * t[b];
+            double gt = 0.0, Ht = 0.0;
+            for (int a = 0; a < 3; ++a) {
+                gt += r[a] * B[12 + a];
+                for (int b = 0; b < 3; ++b) Ht += r[a] * B[15 + a * 3 + b] * r[b];
             }
-            Ht += -0.25 * gq_q;
             double th;
-            dk[1] = damped_solve(1, &Ht, &gt, o, &th);
+            dk[1] = damped_solve(1, &Ht, &gt, o, &th, &cnd[1]);
+            clamp_norm(1, &th, o[O_TRUST_ROT]);
             st[ST_DTH] = th;
         }
         // Scaling: Newton restricted to the row space of T = d lambda / d s, where
@@ -979,36 +1018,45 @@ int orc_solve(int n, int K, const double* pos, const double* rot, const double* 
                                          {2 * (x * y + w * z), 1 - 2 * (x * x + z * z), 2 * (y * z - w * x)},
                                          {2 * (x * z - w * y), 2 * (y * z + w * x), 1 - 2 * (x * x + y * y)}};
                 const double* vv[2] = {v1, v2};  // rows: lambda_min, lambda_max
-                for (int i = 0; i < 2; ++i)
+                for (int i = 0; i < 2; ++i) {
                     for (int a = 0; a < 3; ++a) {
                         double e = 0.0;  // v_i^T M R e_a
                         for (int b = 0; b < 2; ++b)
                             for (int kk = 0; kk < 3; ++kk) e += vv[i][b] * M[b][kk] * Rq[kk][a];
                         T2[i][a] = 2.0 * s[a] * e * e;
                     }
+                    // only the row space of T matters; unit rows keep the reduced system well scaled
+                    const double tn = std::sqrt(T2[i][0] * T2[i][0] + T2[i][1] * T2[i][1] + T2[i][2] * T2[i][2]);
+                    if (tn > 0.0)
+                        for (int a = 0; a < 3; ++a) T2[i][a] /= tn;
+                }
             }
             double H2[4], g2[2], av[2];
             for (int i = 0; i < 2; ++i) {
                 g2[i] = 0.0;
-                for (int a = 0; a < 3; ++a) g2[i] += T2[i][a] * B[32 + a];
+                for (int a = 0; a < 3; ++a) g2[i] += T2[i][a] * B[24 + a];
                 for (int j = 0; j < 2; ++j) {
                     double acc = 0.0;
                     for (int a = 0; a < 3; ++a)
-                        for (int b = 0; b < 3; ++b) acc += T2[i][a] * B[35 + a * 3 + b] * T2[j][b];
+                        for (int b = 0; b < 3; ++b) acc += T2[i][a] * B[27 + a * 3 + b] * T2[j][b];
                     H2[i * 2 + j] = acc;
                 }
             }
-            dk[2] = damped_solve(2, H2, g2, o, av);
-            for (int a = 0; a < 3; ++a) st[ST_DS + a] = T2[0][a] * av[0] + T2[1][a] * av[1];
+            dk[2] = damped_solve(2, H2, g2, o, av, &cnd[2]);
+            // the rows of T are unit but not orthogonal, so the clamp acts on Delta s itself
+            double dsv[3];
+            for (int a = 0; a < 3; ++a) dsv[a] = T2[0][a] * av[0] + T2[1][a] * av[1];
+            clamp_norm(3, dsv, o[O_TRUST_SCALE] * std::sqrt(s[0] * s[0] + s[1] * s[1] + s[2] * s[2]));
+            for (int a = 0; a < 3; ++a) st[ST_DS + a] = dsv[a];
         }
         // Opacity with the log barrier -alpha_s [ln sigma + ln(1 - sigma)].
         {
             const double as = o[O_BARRIER_BETA] * abs_scale;
             const double gB = as * (1.0 / (1.0 - sig) - 1.0 / sig);
             const double hB = as * (1.0 / (sig * sig) + 1.0 / ((1.0 - sig) * (1.0 - sig)));
-            const double H1 = B[45] + hB, g1 = B[44] + gB;
+            const double H1 = B[37] + hB, g1 = B[36] + gB;
             double ds;
-            dk[3] = damped_solve(1, &H1, &g1, o, &ds);
+            dk[3] = damped_solve(1, &H1, &g1, o, &ds, &cnd[3]);
             st[ST_DO] = ds;
         }
         // Colour: per channel, G = sum_v s~_v b_v b_v^T, g = sum_v gamma_v b_v, b_v = Y(r_v).
@@ -1046,6 +1094,8 @@ int orc_solve(int n, int K, const double* pos, const double* rot, const double* 
                     for (int i = 0; i < K; ++i) st[ST_DSH + ch * K + i] = x[i];
             }
         }
+        if (cond)
+            for (int i = 0; i < 4; ++i) cond[(size_t)k * 4 + i] = cnd[i];
     }
     return 0;
 }

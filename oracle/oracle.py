@@ -25,13 +25,15 @@ LIB = os.path.join(HERE, "liboracle.so")
 
 O_NAMES = ["tile", "alpha_min", "alpha_max", "T_min", "kappa", "radius_sigma", "smooth",
            "bg_r", "bg_g", "bg_b", "lambda_ssim", "barrier_beta", "damp_rel", "damp_abs",
-           "pivot_min", "max_esc", "sh_floor", "scale_floor", "opac_ftb", "npix_primary"]
+           "pivot_min", "max_esc", "sh_floor", "scale_floor", "opac_ftb", "npix_primary", "trust_pos",
+           "trust_rot", "trust_scale"]
 DEFAULTS = dict(tile=16, alpha_min=1.0 / 255.0, alpha_max=0.99, T_min=1e-4, kappa=0.3,
                 radius_sigma=3.0, smooth=0, bg_r=0.0, bg_g=0.0, bg_b=0.0, lambda_ssim=0.2,
-                barrier_beta=1e-2, damp_rel=1e-3, damp_abs=1e-12, pivot_min=1e-6, max_esc=7,
-                sh_floor=1e-3, scale_floor=0.1, opac_ftb=0.995, npix_primary=1.0)
-B_COUNT = 56
-NB_BASE, NB_VIEW = 47, 10
+                barrier_beta=1e-2, damp_rel=1e-3, damp_abs=1e-12, pivot_min=1e-3, max_esc=7,
+                sh_floor=1e-3, scale_floor=0.1, opac_ftb=0.995, npix_primary=1.0, trust_pos=2.0,
+                trust_rot=0.5, trust_scale=0.5)
+B_COUNT = 48
+NB_BASE, NB_VIEW = 39, 10
 
 
 def build(force: bool = False) -> str:
@@ -222,7 +224,7 @@ def zstats(g, fr: Frame, dL, hd, sel=None):
 
 
 def sum_blocks(per_view):
-    """Combine per-view blocks [V] of [n][56] into the solve layout [n][47 + 10 V].
+    """Combine per-view blocks [V] of [n][48] into the solve layout [n][39 + 10 V].
 
     Position, rotation, scaling and opacity blocks are summed over the views
     (weight 1, Sec. 4.3); the colour statistics stay per view; the coverage
@@ -231,26 +233,29 @@ def sum_blocks(per_view):
     n = per_view[0].shape[0]
     out = np.zeros((n, NB_BASE + NB_VIEW * V))
     for b in per_view:
-        out[:, :46] += b[:, :46]
-    out[:, 46] = per_view[0][:, 46]
+        out[:, :38] += b[:, :38]
+    out[:, 38] = per_view[0][:, 38]
     for v, b in enumerate(per_view):
         base = NB_BASE + NB_VIEW * v
-        out[:, base:base + 3] = b[:, 47:50]
-        out[:, base + 3:base + 6] = b[:, 50:53]
-        out[:, base + 6:base + 9] = b[:, 53:56]
-        out[:, base + 9] = b[:, 46]
+        out[:, base:base + 3] = b[:, 39:42]
+        out[:, base + 3:base + 6] = b[:, 42:45]
+        out[:, base + 6:base + 9] = b[:, 45:48]
+        out[:, base + 9] = b[:, 38]
     return out
 
 
-def solve(g, cam, o, summed, V):
+def solve(g, cam, o, summed, V, with_cond=False):
+    """Reduced-coordinate damped solves; returns steps [n][11 + 3K], decisions [n][5] (and
+    the condition number [n][4] of each group's solved matrix when with_cond)."""
     g64 = G64.of(g)
     K = g64.K
     steps = np.zeros((g64.n, 11 + 3 * K))
     dec = np.zeros((g64.n, 5), np.int32)
+    cond = np.zeros((g64.n, 4))
     lib().orc_solve(ctypes.c_int(g64.n), ctypes.c_int(K), _p(g64.pos), _p(g64.rot), _p(g64.scale),
                     _p(g64.opac), _p(cam_vec(cam)), _p(o), ctypes.c_int(V),
-                    _p(np.ascontiguousarray(summed)), _p(steps), _p(dec))
-    return steps, dec
+                    _p(np.ascontiguousarray(summed)), _p(steps), _p(dec), _p(cond))
+    return (steps, dec, cond) if with_cond else (steps, dec)
 
 
 def apply(g, steps, dec, o, mask=31) -> G64:
@@ -312,9 +317,9 @@ def sweep(g, cams, targets, t, knn_table=None, o=None, mask=31):
         losses.append(parts)
         frames.append(fr)
     summed = sum_blocks(per_view)
-    steps, dec = solve(g64, cam, o, summed, len(views))
+    steps, dec, cond = solve(g64, cam, o, summed, len(views), with_cond=True)
     new = apply(g64, steps, dec, o, mask)
-    return dict(new=new, steps=steps, dec=dec, summed=summed, per_view=per_view,
+    return dict(new=new, steps=steps, dec=dec, cond=cond, summed=summed, per_view=per_view,
                 losses=losses, frames=frames, opts=o)
 
 

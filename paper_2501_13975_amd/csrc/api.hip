@@ -144,7 +144,7 @@ gsn_status gsn_frame_destroy(gsn_ctx* ctx, gsn_frame* f) {
     (void)hipStreamSynchronize(ctx->stream);
     DevBuf* all[] = {&f->rec, &f->rect, &f->depth_key, &f->ntiles, &f->ids_a, &f->ids_b, &f->keys_a, &f->keys_b,
                      &f->offsets, &f->pair_off, &f->pk_a, &f->pv_a, &f->pk_b, &f->pv_b, &f->partial, &f->flags,
-                     &f->ranges, &f->img, &f->Tfin, &f->ncontrib, &f->dL, &f->hd, &f->coef, &f->zstats,
+                     &f->ranges, &f->img, &f->img64, &f->Tfin, &f->ncontrib, &f->dL, &f->hd, &f->coef, &f->zstats,
                      &f->loss_part, &f->hist, &f->scan_tmp, &f->total};
     for (DevBuf* b : all) buf_free(*b);
     if (f->h_total) (void)hipHostFree(f->h_total);
@@ -193,6 +193,7 @@ gsn_status gsn_render(gsn_ctx* ctx, const gsn_gaussians* g, const gsn_camera* ca
     HIP_TRY(ctx, buf_reserve(f->pair_off, nn * 4));
     HIP_TRY(ctx, buf_reserve(f->ranges, tiles * sizeof(uint2)));
     HIP_TRY(ctx, buf_reserve(f->img, 3 * npx * 4));
+    HIP_TRY(ctx, buf_reserve(f->img64, 3 * npx * 8));
     HIP_TRY(ctx, buf_reserve(f->Tfin, npx * 4));
     HIP_TRY(ctx, buf_reserve(f->ncontrib, npx * 4));
     HIP_TRY(ctx, buf_reserve(f->total, 16));
@@ -240,7 +241,7 @@ gsn_status gsn_render(gsn_ctx* ctx, const gsn_gaussians* g, const gsn_camera* ca
     launch_tile_ranges(bp<uint32_t>(f->pk_a), P, bp<uint2>(f->ranges), s);
     // 5. front-to-back compositing
     launch_raster_fwd(bp<uint2>(f->ranges), bp<uint32_t>(f->pv_a), bp<float4>(f->rec), (uint32_t)n, f->cam, f->ro,
-                      bp<float>(f->img), bp<float>(f->Tfin), bp<uint32_t>(f->ncontrib), s);
+                      bp<float>(f->img), bp<double>(f->img64), bp<float>(f->Tfin), bp<uint32_t>(f->ncontrib), s);
     HIP_TRY(ctx, hipGetLastError());
     if (d_rgb_out) HIP_TRY(ctx, hipMemcpyAsync(d_rgb_out, f->img.p, 3 * npx * 4, hipMemcpyDeviceToDevice, s));
     if (d_T_out) HIP_TRY(ctx, hipMemcpyAsync(d_T_out, f->Tfin.p, npx * 4, hipMemcpyDeviceToDevice, s));
@@ -265,11 +266,11 @@ gsn_status gsn_accumulate_hessian(gsn_ctx* ctx, const gsn_gaussians* g, const gs
     const size_t npx = (size_t)f->W * f->H;
     HIP_TRY(ctx, buf_reserve(f->dL, 3 * npx * 4));
     HIP_TRY(ctx, buf_reserve(f->hd, 3 * npx * 4));
-    HIP_TRY(ctx, buf_reserve(f->coef, 24 * npx * 4));
+    HIP_TRY(ctx, buf_reserve(f->coef, 24 * npx * 8));
     const int nparts = ((f->W + 15) / 16) * ((f->H + 15) / 16) * 3;
     HIP_TRY(ctx, buf_reserve(f->loss_part, (size_t)2 * nparts * sizeof(double)));
     int np_out = 0;
-    launch_loss_maps(bp<float>(f->img), d_target, f->W, f->H, opts->lambda_ssim, bp<float>(f->coef),
+    launch_loss_maps(bp<float>(f->img), d_target, f->W, f->H, opts->lambda_ssim, bp<double>(f->coef),
                      bp<float>(f->dL), bp<float>(f->hd), bp<double>(f->loss_part), &np_out, s);
     if (d_loss_out) launch_loss_reduce(bp<double>(f->loss_part), np_out, f->W, f->H, d_loss_out, s);
     HIP_TRY(ctx, hipGetLastError());
@@ -423,6 +424,14 @@ gsn_status gsn_frame_zstats(gsn_ctx* ctx, const gsn_frame* f, float* d_out) {
     if (!f->zstats.p) return fail(ctx, GSN_E_INVALID, "no statistics kept: run gsn_accumulate_hessian with keep_zstats");
     HIP_TRY(ctx, hipSetDevice(ctx->device));
     HIP_TRY(ctx, hipMemcpyAsync(d_out, f->zstats.p, (size_t)f->n * GSN_NZ * 4, hipMemcpyDeviceToDevice, ctx->stream));
+    return GSN_OK;
+}
+
+gsn_status gsn_frame_records(gsn_ctx* ctx, const gsn_frame* f, float* d_out) {
+    if (!ctx || !f || !d_out) return GSN_E_INVALID;
+    if (!f->rendered) return fail(ctx, GSN_E_INVALID, "frame was never rendered");
+    HIP_TRY(ctx, hipSetDevice(ctx->device));
+    HIP_TRY(ctx, hipMemcpyAsync(d_out, f->rec.p, (size_t)f->n * 48, hipMemcpyDeviceToDevice, ctx->stream));
     return GSN_OK;
 }
 

@@ -1,0 +1,243 @@
+// chain.h -- chain rule from projected-space statistics to attribute blocks.
+// Host-and-device code: the same functions run in the reduce_chain kernel and in
+// host-side precision studies.
+//
+// Per attribute group y, H_y = J^T H_z J + sum_i (g_z)_i d2 z_i/dy2 with J = dz/dy
+// (eq. local_hessian_gradient applied to the projected quantities z), using
+// second-order jets for z(y).  Sigma = A A^T + kappa I with A = J_persp W R S
+// (Appendix A.3).  Position runs in single precision; scale and rotation run in
+// double precision, because the inverse Q = Sigma^{-1} of thin splats amplifies
+// rounding by the squared condition number of Sigma.
+#pragma once
+#include "device_common.h"
+
+struct KParams {
+    float p[3], q[4], s[3];
+    float fc, fs;  // principal frame of the splat in this view: e1 = (fc, fs), e2 = (-fs, fc)
+};
+
+// Rows of M rotated into the principal frame: M' = V^T M.
+template <class TT>
+GSN_HD inline void to_frame(TT M[2][3], float fc, float fs) {
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        const TT m0 = M[0][k], m1 = M[1][k];
+        M[0][k] = fc * m0 + fs * m1;
+        M[1][k] = fc * m1 - fs * m0;
+    }
+}
+
+// M = J_persp W: Jacobian of the perspective map at t = W p + t_c times the camera rotation.
+template <class TT>
+GSN_HD inline void persp_M(const TT t[3], const DevCam& c, TT M[2][3], TT& iz) {
+    iz = jrecip(t[2]);
+    const TT J00 = c.fx * iz, J11 = c.fy * iz;
+    const TT J02 = -(c.fx * t[0]) * iz * iz, J12 = -(c.fy * t[1]) * iz * iz;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        M[0][k] = J00 * c.R[k] + J02 * c.R[6 + k];
+        M[1][k] = J11 * c.R[3 + k] + J12 * c.R[6 + k];
+    }
+}
+
+// Rotation matrix of the unit quaternion q/|q| = (w, x, y, z).
+template <class T>
+GSN_HD inline void quat_rot(const float q[4], T Rq[3][3]) {
+    const T qn = sqrt((T)q[0] * q[0] + (T)q[1] * q[1] + (T)q[2] * q[2] + (T)q[3] * q[3]);
+    const T w = q[0] / qn, x = q[1] / qn, y = q[2] / qn, z = q[3] / qn;
+    Rq[0][0] = T(1) - T(2) * (y * y + z * z);
+    Rq[0][1] = T(2) * (x * y - w * z);
+    Rq[0][2] = T(2) * (x * z + w * y);
+    Rq[1][0] = T(2) * (x * y + w * z);
+    Rq[1][1] = T(1) - T(2) * (x * x + z * z);
+    Rq[1][2] = T(2) * (y * z - w * x);
+    Rq[2][0] = T(2) * (x * z - w * y);
+    Rq[2][1] = T(2) * (y * z + w * x);
+    Rq[2][2] = T(1) - T(2) * (x * x + y * y);
+}
+
+// Q = Sigma^{-1} from A (2x3): Sigma = A A^T + kappa I.  The determinant is taken
+// in the Cauchy-Binet form det(A A^T) = sum of squared 2x2 minors of A, plus
+// kappa tr(A A^T) + kappa^2: a sum of non-negative terms, free of the
+// cancellation of Sigma_xx Sigma_yy - Sigma_xy^2 for elongated splats.
+template <class TT, class K>
+GSN_HD inline void conic_from_A(const TT A[2][3], K kappa, TT Q[3]) {
+    const TT sxx0 = A[0][0] * A[0][0] + A[0][1] * A[0][1] + A[0][2] * A[0][2];
+    const TT syy0 = A[1][0] * A[1][0] + A[1][1] * A[1][1] + A[1][2] * A[1][2];
+    const TT sxy = A[0][0] * A[1][0] + A[0][1] * A[1][1] + A[0][2] * A[1][2];
+    const TT m01 = A[0][0] * A[1][1] - A[0][1] * A[1][0];
+    const TT m02 = A[0][0] * A[1][2] - A[0][2] * A[1][0];
+    const TT m12 = A[0][1] * A[1][2] - A[0][2] * A[1][1];
+    const TT det = m01 * m01 + m02 * m02 + m12 * m12 + kappa * (sxx0 + syy0) + kappa * kappa;
+    const TT sxx = sxx0 + kappa, syy = syy0 + kappa;
+    const TT idet = jrecip(det);
+    Q[0] = syy * idet;
+    Q[1] = -(sxy * idet);
+    Q[2] = sxx * idet;
+}
+
+// g_a = sum_i gz_i dz_i/dy_a;  H_ab = sum_ij Hz_ij dz_i/dy_a dz_j/dy_b + sum_i gz_i d2z_i/dy_a dy_b (packed).
+template <int N, int NZ, class T>
+GSN_HD inline void chain_accumulate(const FJet<N, T>* zj, const T* gz, const T Hz[NZ][NZ], T* g, T* H) {
+#pragma unroll
+    for (int a = 0; a < N; ++a) {
+        T acc = T(0);
+#pragma unroll
+        for (int i = 0; i < NZ; ++i) acc += gz[i] * zj[i].g[a];
+        g[a] = acc;
+    }
+    T t[NZ][N];
+#pragma unroll
+    for (int i = 0; i < NZ; ++i)
+#pragma unroll
+        for (int b = 0; b < N; ++b) {
+            T acc = T(0);
+#pragma unroll
+            for (int j = 0; j < NZ; ++j) acc += Hz[i][j] * zj[j].g[b];
+            t[i][b] = acc;
+        }
+    int idx = 0;
+#pragma unroll
+    for (int a = 0; a < N; ++a)
+#pragma unroll
+        for (int b = a; b < N; ++b, ++idx) {
+            T acc = T(0);
+#pragma unroll
+            for (int i = 0; i < NZ; ++i) acc += zj[i].g[a] * t[i][b] + gz[i] * zj[i].h[idx];
+            H[idx] = acc;
+        }
+}
+
+// Position: z = (pi', Q', c~) as functions of p (pi through the projection, Q through the
+// perspective Jacobian, c~ through the view direction of the SH colour), in the
+// splat's principal frame (pi' = V^T pi, Q' = (V^T M R S)(V^T M R S)^T + kappa I inverted).
+GSN_HD inline void chain_position(const KParams& kp, const float* shk, int K, const DevCam& c, float kappa,
+                                  const float* z, float* g, float* H) {
+    typedef FJet<3> J;
+    J p[3] = {J::var(kp.p[0], 0), J::var(kp.p[1], 1), J::var(kp.p[2], 2)};
+    J t[3];
+#pragma unroll
+    for (int i = 0; i < 3; ++i) t[i] = c.R[3 * i] * p[0] + c.R[3 * i + 1] * p[1] + c.R[3 * i + 2] * p[2] + c.t[i];
+    J M[2][3], iz;
+    persp_M(t, c, M, iz);
+    to_frame(M, kp.fc, kp.fs);
+    float Rq[3][3];
+    quat_rot<float>(kp.q, Rq);
+    J A[2][3];
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int a = 0; a < 3; ++a)
+            A[i][a] = (M[i][0] * Rq[0][a] + M[i][1] * Rq[1][a] + M[i][2] * Rq[2][a]) * kp.s[a];
+    J zj[8];
+    conic_from_A(A, kappa, zj + 2);
+    {
+        const J px = c.fx * t[0] * iz, py = c.fy * t[1] * iz;  // pi up to a constant offset
+        zj[0] = kp.fc * px + kp.fs * py;
+        zj[1] = kp.fc * py - kp.fs * px;
+    }
+    {
+        const J d0 = p[0] - c.o[0], d1 = p[1] - c.o[1], d2 = p[2] - c.o[2];
+        const J il = jrecip(jsqrt(d0 * d0 + d1 * d1 + d2 * d2));
+        J Y[16];
+        sh_basis_dev<J>(K, d0 * il, d1 * il, d2 * il, Y);
+#pragma unroll
+        for (int ch = 0; ch < 3; ++ch) {
+            J acc(0.f);
+            for (int i = 0; i < K; ++i) acc = acc + shk[ch * K + i] * Y[i];
+            zj[5 + ch] = acc;
+        }
+    }
+    // H_z over (pi_x, pi_y, Q_xx, Q_xy, Q_yy, c~_R, c~_G, c~_B)
+    float Hz[8][8];
+    int idx = 9;
+#pragma unroll
+    for (int i = 0; i < 5; ++i)
+#pragma unroll
+        for (int j = i; j < 5; ++j, ++idx) Hz[i][j] = Hz[j][i] = z[idx];
+#pragma unroll
+    for (int i = 0; i < 5; ++i)
+#pragma unroll
+        for (int ch = 0; ch < 3; ++ch) Hz[i][5 + ch] = Hz[5 + ch][i] = z[24 + i * 3 + ch];
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+#pragma unroll
+        for (int b = 0; b < 3; ++b) Hz[5 + a][5 + b] = a == b ? z[39 + a] : 0.f;
+    const float gz[8] = {z[0], z[1], z[2], z[3], z[4], z[6], z[7], z[8]};
+    chain_accumulate<3, 8, float>(zj, gz, Hz, g, H);
+}
+
+// Statistics of Q' = (Q'_11, Q'_12, Q'_22) in double: entries 2..4 of the (pi', Q') block.
+GSN_HD inline void q_stats(const float* z, double gz[3], double Hz[3][3]) {
+    const int pk[3][3] = {{9 + 9, 9 + 10, 9 + 11}, {9 + 10, 9 + 12, 9 + 13}, {9 + 11, 9 + 13, 9 + 14}};
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+        gz[i] = z[2 + i];
+#pragma unroll
+        for (int j = 0; j < 3; ++j) Hz[i][j] = z[pk[i][j]];
+    }
+}
+
+// Scale: A = M R diag(s) is linear in s.
+GSN_HD inline void chain_scale(const KParams& kp, const DevCam& c, float kappa, const float* z, double* g, double* H) {
+    typedef FJet<3, double> J;
+    double tf[3];
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+        tf[i] = (double)c.R[3 * i] * kp.p[0] + (double)c.R[3 * i + 1] * kp.p[1] + (double)c.R[3 * i + 2] * kp.p[2] +
+                c.t[i];
+    double M[2][3], iz;
+    persp_M<double>(tf, c, M, iz);
+    to_frame(M, kp.fc, kp.fs);
+    double Rq[3][3];
+    quat_rot<double>(kp.q, Rq);
+    J A[2][3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        const J sv = J::var((double)kp.s[a], a);
+#pragma unroll
+        for (int i = 0; i < 2; ++i) A[i][a] = (M[i][0] * Rq[0][a] + M[i][1] * Rq[1][a] + M[i][2] * Rq[2][a]) * sv;
+    }
+    J Q[3];
+    conic_from_A(A, (double)kappa, Q);
+    double gz[3], Hz[3][3];
+    q_stats(z, gz, Hz);
+    chain_accumulate<3, 3, double>(Q, gz, Hz, g, H);
+}
+
+// Rotation in the tangent space of left rotations: R(omega) = exp([omega]_x) R0, i.e.
+// q(omega) = exp(omega/2) * q0.  To second order at omega = 0,
+// A(omega) = M (B0 + omega x B0 + (1/2) omega x (omega x B0)) with B0 = R0 diag(s).
+GSN_HD inline void chain_rotation(const KParams& kp, const DevCam& c, float kappa, const float* z, double* g,
+                                  double* H) {
+    typedef FJet<3, double> J;
+    double tf[3];
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+        tf[i] = (double)c.R[3 * i] * kp.p[0] + (double)c.R[3 * i + 1] * kp.p[1] + (double)c.R[3 * i + 2] * kp.p[2] +
+                c.t[i];
+    double M[2][3], iz;
+    persp_M<double>(tf, c, M, iz);
+    to_frame(M, kp.fc, kp.fs);
+    double Rq[3][3];
+    quat_rot<double>(kp.q, Rq);
+    const J w[3] = {J::var(0.0, 0), J::var(0.0, 1), J::var(0.0, 2)};
+    J A[2][3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        const double b[3] = {Rq[0][a] * kp.s[a], Rq[1][a] * kp.s[a], Rq[2][a] * kp.s[a]};
+        // c1 = w x b (linear), c2 = w x c1 (quadratic)
+        const J c1[3] = {w[1] * b[2] - w[2] * b[1], w[2] * b[0] - w[0] * b[2], w[0] * b[1] - w[1] * b[0]};
+        const J c2[3] = {w[1] * c1[2] - w[2] * c1[1], w[2] * c1[0] - w[0] * c1[2], w[0] * c1[1] - w[1] * c1[0]};
+        J col[3];
+#pragma unroll
+        for (int k = 0; k < 3; ++k) col[k] = (c1[k] + 0.5 * c2[k]) + b[k];
+#pragma unroll
+        for (int i = 0; i < 2; ++i) A[i][a] = M[i][0] * col[0] + M[i][1] * col[1] + M[i][2] * col[2];
+    }
+    J Q[3];
+    conic_from_A(A, (double)kappa, Q);
+    double gz[3], Hz[3][3];
+    q_stats(z, gz, Hz);
+    chain_accumulate<3, 3, double>(Q, gz, Hz, g, H);
+}

@@ -3,6 +3,10 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#ifndef GSN_HD
+#define GSN_HD __host__ __device__
+#endif
+
 #define GSN_TILE 16
 #define GSN_BLOCK 256          // threads per tile workgroup (16 x 16 pixels, four wave64s)
 #define GSN_NZ 44              // per-kernel projected-space statistics, see backward.hip
@@ -23,26 +27,68 @@ struct DevRenderOpts {
 };
 
 // ----------------------------------------------------------------------------
-// Alpha of one splat at one pixel: alpha = min(alpha_max, sigma exp(-d^T Q d / 2)).
-// Forward and backward passes call this same function so that their skip and
-// stop decisions agree exactly.
+// Splat records are kept in each splat's principal-axis frame: the eigenvectors
+// of its 2D covariance, e1 = (c, s) and e2 = (-s, c), with eigenvalues
+// lambda1 >= lambda2, so that the conic is Q' = diag(q1, q2), q_i = 1/lambda_i.
+// Record (three float4 per kernel):
+//   (mx, my, q1, q2), (c, s, sigma, colour_R), (colour_G, colour_B, -, -).
+// Working in this frame keeps the per-pixel derivative terms of thin splats
+// well conditioned (in the image frame their conic derivatives are nearly
+// collinear and rounding destroys the minor directions).
+//
+// Alpha of one splat at one pixel: alpha = min(alpha_max, sigma exp(-d'^T Q' d' / 2)),
+// d' = V^T (m - x).  Forward and backward passes call this same function so
+// that their skip and stop decisions agree exactly.
 // ----------------------------------------------------------------------------
 struct SplatEval {
-    float G, alpha, dx, dy;
+    float G, alpha, d1, d2;  // d1, d2: offset from the pixel in the principal frame
     bool clamped;
 };
 
-__device__ __forceinline__ SplatEval eval_splat(float mx, float my, float qxx, float qxy, float qyy,
+__device__ __forceinline__ SplatEval eval_splat(float mx, float my, float q1, float q2, float c, float s,
                                                 float sig, float px, float py, float amax) {
     SplatEval e;
-    e.dx = mx - px;
-    e.dy = my - py;
-    const float power = -0.5f * (qxx * e.dx * e.dx + qyy * e.dy * e.dy) - qxy * e.dx * e.dy;
+    const float dx = mx - px, dy = my - py;
+    e.d1 = c * dx + s * dy;
+    e.d2 = c * dy - s * dx;
+    const float power = -0.5f * (q1 * e.d1 * e.d1 + q2 * e.d2 * e.d2);
     e.G = __expf(power);
     const float a = sig * e.G;
     e.clamped = a > amax;
     e.alpha = e.clamped ? amax : a;
     return e;
+}
+
+// Principal frame of Sigma = A A^T + kappa I (A = J W R S, 2x3): eigenvalues from the
+// trace and the Cauchy-Binet determinant (sum of squared 2x2 minors), the minor one as
+// det / lambda1 so that neither cancels.
+template <class T>
+GSN_HD inline void principal_frame(const T A[2][3], T kappa, T& l1, T& l2, T& c, T& s) {
+    const T sxx = A[0][0] * A[0][0] + A[0][1] * A[0][1] + A[0][2] * A[0][2] + kappa;
+    const T syy = A[1][0] * A[1][0] + A[1][1] * A[1][1] + A[1][2] * A[1][2] + kappa;
+    const T sxy = A[0][0] * A[1][0] + A[0][1] * A[1][1] + A[0][2] * A[1][2];
+    const T m01 = A[0][0] * A[1][1] - A[0][1] * A[1][0];
+    const T m02 = A[0][0] * A[1][2] - A[0][2] * A[1][0];
+    const T m12 = A[0][1] * A[1][2] - A[0][2] * A[1][1];
+    const T det = m01 * m01 + m02 * m02 + m12 * m12 + kappa * (sxx + syy - kappa);
+    const T half = T(0.5) * (sxx - syy);
+    const T rad = sqrt(half * half + sxy * sxy);
+    l1 = T(0.5) * (sxx + syy) + rad;
+    l2 = det / l1;
+    // eigenvector of l1: the better conditioned of (l1 - syy, sxy) and (sxy, l1 - sxx)
+    T vx = l1 - syy, vy = sxy;
+    if (fabs(sxy) + fabs(l1 - sxx) > fabs(vx) + fabs(vy)) {
+        vx = sxy;
+        vy = l1 - sxx;
+    }
+    const T vn = sqrt(vx * vx + vy * vy);
+    if (vn > T(0)) {
+        c = vx / vn;
+        s = vy / vn;
+    } else {
+        c = T(1);
+        s = T(0);
+    }
 }
 
 // ----------------------------------------------------------------------------
@@ -61,7 +107,7 @@ __device__ __forceinline__ SplatEval eval_splat(float mx, float my, float qxx, f
 #define SH_C3E 1.44530572132027737f
 
 template <class T>
-__device__ __forceinline__ void sh_basis_dev(int K, const T& x, const T& y, const T& z, T* Y) {
+GSN_HD inline void sh_basis_dev(int K, const T& x, const T& y, const T& z, T* Y) {
     Y[0] = T(SH_C0);
     if (K <= 1) return;
     Y[1] = -SH_C1 * y;
@@ -85,69 +131,69 @@ __device__ __forceinline__ void sh_basis_dev(int K, const T& x, const T& y, cons
 }
 
 // ----------------------------------------------------------------------------
-// Second-order forward-mode jets in single precision: value, gradient and the
-// packed upper triangle of the Hessian with respect to N variables.  Used by
-// the per-kernel chain rule (projected quantities as functions of position,
-// rotation or scale).
+// Second-order forward-mode jets: value, gradient and the packed upper triangle
+// of the Hessian with respect to N variables, in single or double precision.
+// Used by the per-kernel chain rule (projected quantities as functions of
+// position, rotation or scale).
 // ----------------------------------------------------------------------------
-template <int N>
+template <int N, class T = float>
 struct FJet {
     static constexpr int NH = N * (N + 1) / 2;
-    float v;
-    float g[N];
-    float h[NH];
-    __device__ FJet() : v(0.f) {
+    T v;
+    T g[N];
+    T h[NH];
+    GSN_HD FJet() : v(T(0)) {
 #pragma unroll
-        for (int i = 0; i < N; ++i) g[i] = 0.f;
+        for (int i = 0; i < N; ++i) g[i] = T(0);
 #pragma unroll
-        for (int i = 0; i < NH; ++i) h[i] = 0.f;
+        for (int i = 0; i < NH; ++i) h[i] = T(0);
     }
-    __device__ FJet(float c) : v(c) {  // NOLINT
+    GSN_HD FJet(T c) : v(c) {  // NOLINT
 #pragma unroll
-        for (int i = 0; i < N; ++i) g[i] = 0.f;
+        for (int i = 0; i < N; ++i) g[i] = T(0);
 #pragma unroll
-        for (int i = 0; i < NH; ++i) h[i] = 0.f;
+        for (int i = 0; i < NH; ++i) h[i] = T(0);
     }
-    __device__ static FJet var(float x, int i) {
+    GSN_HD static FJet var(T x, int i) {
         FJet r(x);
-        r.g[i] = 1.f;
+        r.g[i] = T(1);
         return r;
     }
 };
 
-template <int N>
-__device__ __forceinline__ FJet<N> operator+(const FJet<N>& a, const FJet<N>& b) {
-    FJet<N> r;
+template <int N, class T>
+GSN_HD inline FJet<N, T> operator+(const FJet<N, T>& a, const FJet<N, T>& b) {
+    FJet<N, T> r;
     r.v = a.v + b.v;
 #pragma unroll
     for (int i = 0; i < N; ++i) r.g[i] = a.g[i] + b.g[i];
 #pragma unroll
-    for (int i = 0; i < FJet<N>::NH; ++i) r.h[i] = a.h[i] + b.h[i];
+    for (int i = 0; i < FJet<N, T>::NH; ++i) r.h[i] = a.h[i] + b.h[i];
     return r;
 }
-template <int N>
-__device__ __forceinline__ FJet<N> operator-(const FJet<N>& a, const FJet<N>& b) {
-    FJet<N> r;
+template <int N, class T>
+GSN_HD inline FJet<N, T> operator-(const FJet<N, T>& a, const FJet<N, T>& b) {
+    FJet<N, T> r;
     r.v = a.v - b.v;
 #pragma unroll
     for (int i = 0; i < N; ++i) r.g[i] = a.g[i] - b.g[i];
 #pragma unroll
-    for (int i = 0; i < FJet<N>::NH; ++i) r.h[i] = a.h[i] - b.h[i];
+    for (int i = 0; i < FJet<N, T>::NH; ++i) r.h[i] = a.h[i] - b.h[i];
     return r;
 }
-template <int N>
-__device__ __forceinline__ FJet<N> operator-(const FJet<N>& a) {
-    FJet<N> r;
+template <int N, class T>
+GSN_HD inline FJet<N, T> operator-(const FJet<N, T>& a) {
+    FJet<N, T> r;
     r.v = -a.v;
 #pragma unroll
     for (int i = 0; i < N; ++i) r.g[i] = -a.g[i];
 #pragma unroll
-    for (int i = 0; i < FJet<N>::NH; ++i) r.h[i] = -a.h[i];
+    for (int i = 0; i < FJet<N, T>::NH; ++i) r.h[i] = -a.h[i];
     return r;
 }
-template <int N>
-__device__ __forceinline__ FJet<N> operator*(const FJet<N>& a, const FJet<N>& b) {
-    FJet<N> r;
+template <int N, class T>
+GSN_HD inline FJet<N, T> operator*(const FJet<N, T>& a, const FJet<N, T>& b) {
+    FJet<N, T> r;
     r.v = a.v * b.v;
 #pragma unroll
     for (int i = 0; i < N; ++i) r.g[i] = a.g[i] * b.v + a.v * b.g[i];
@@ -159,30 +205,30 @@ __device__ __forceinline__ FJet<N> operator*(const FJet<N>& a, const FJet<N>& b)
             r.h[idx] = a.h[idx] * b.v + a.v * b.h[idx] + a.g[i] * b.g[j] + a.g[j] * b.g[i];
     return r;
 }
-template <int N>
-__device__ __forceinline__ FJet<N> operator*(float c, const FJet<N>& a) {
-    FJet<N> r;
+template <int N, class T>
+GSN_HD inline FJet<N, T> operator*(T c, const FJet<N, T>& a) {
+    FJet<N, T> r;
     r.v = c * a.v;
 #pragma unroll
     for (int i = 0; i < N; ++i) r.g[i] = c * a.g[i];
 #pragma unroll
-    for (int i = 0; i < FJet<N>::NH; ++i) r.h[i] = c * a.h[i];
+    for (int i = 0; i < FJet<N, T>::NH; ++i) r.h[i] = c * a.h[i];
     return r;
 }
-template <int N>
-__device__ __forceinline__ FJet<N> operator*(const FJet<N>& a, float c) { return c * a; }
-template <int N>
-__device__ __forceinline__ FJet<N> operator+(const FJet<N>& a, float c) { FJet<N> r = a; r.v += c; return r; }
-template <int N>
-__device__ __forceinline__ FJet<N> operator-(const FJet<N>& a, float c) { FJet<N> r = a; r.v -= c; return r; }
-template <int N>
-__device__ __forceinline__ FJet<N> operator-(float c, const FJet<N>& a) { FJet<N> r = -a; r.v += c; return r; }
-template <int N>
-__device__ __forceinline__ FJet<N> operator+(float c, const FJet<N>& a) { return a + c; }
+template <int N, class T>
+GSN_HD inline FJet<N, T> operator*(const FJet<N, T>& a, T c) { return c * a; }
+template <int N, class T>
+GSN_HD inline FJet<N, T> operator+(const FJet<N, T>& a, T c) { FJet<N, T> r = a; r.v += c; return r; }
+template <int N, class T>
+GSN_HD inline FJet<N, T> operator-(const FJet<N, T>& a, T c) { FJet<N, T> r = a; r.v -= c; return r; }
+template <int N, class T>
+GSN_HD inline FJet<N, T> operator-(T c, const FJet<N, T>& a) { FJet<N, T> r = -a; r.v += c; return r; }
+template <int N, class T>
+GSN_HD inline FJet<N, T> operator+(T c, const FJet<N, T>& a) { return a + c; }
 
-template <int N>
-__device__ __forceinline__ FJet<N> compose(const FJet<N>& a, float f, float d1, float d2) {
-    FJet<N> r;
+template <int N, class T>
+GSN_HD inline FJet<N, T> compose(const FJet<N, T>& a, T f, T d1, T d2) {
+    FJet<N, T> r;
     r.v = f;
 #pragma unroll
     for (int i = 0; i < N; ++i) r.g[i] = d1 * a.g[i];
@@ -193,20 +239,22 @@ __device__ __forceinline__ FJet<N> compose(const FJet<N>& a, float f, float d1, 
         for (int j = i; j < N; ++j, ++idx) r.h[idx] = d1 * a.h[idx] + d2 * a.g[i] * a.g[j];
     return r;
 }
-template <int N>
-__device__ __forceinline__ FJet<N> jrecip(const FJet<N>& a) {
-    const float x = a.v, ix = 1.0f / x;
-    return compose(a, ix, -ix * ix, 2.0f * ix * ix * ix);
+template <int N, class T>
+GSN_HD inline FJet<N, T> jrecip(const FJet<N, T>& a) {
+    const T x = a.v, ix = T(1) / x;
+    return compose(a, ix, -ix * ix, T(2) * ix * ix * ix);
 }
-template <int N>
-__device__ __forceinline__ FJet<N> jsqrt(const FJet<N>& a) {
-    const float s = sqrtf(a.v);
-    return compose(a, s, 0.5f / s, -0.25f / (s * a.v));
+template <int N, class T>
+GSN_HD inline FJet<N, T> jsqrt(const FJet<N, T>& a) {
+    const T s = sqrt(a.v);
+    return compose(a, s, T(0.5) / s, T(-0.25) / (s * a.v));
 }
-__device__ __forceinline__ float jrecip(float x) { return 1.0f / x; }
-__device__ __forceinline__ float jsqrt(float x) { return sqrtf(x); }
+GSN_HD inline float jrecip(float x) { return 1.0f / x; }
+GSN_HD inline float jsqrt(float x) { return sqrtf(x); }
+GSN_HD inline double jrecip(double x) { return 1.0 / x; }
+GSN_HD inline double jsqrt(double x) { return sqrt(x); }
 
-__device__ __forceinline__ int tri_index(int i, int j, int n) {
+GSN_HD inline int tri_index(int i, int j, int n) {
     // packed upper-triangle index of (i, j), i <= j, row by row
     return i * n - (i * (i - 1)) / 2 + (j - i);
 }

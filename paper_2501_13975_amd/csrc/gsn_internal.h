@@ -39,10 +39,11 @@ struct gsn_frame {
     // per tile / pixel
     DevBuf ranges;      // uint2 [tiles]
     DevBuf img;         // float [3][H][W]
+    DevBuf img64;       // double [3][H][W], the same colour before rounding
     DevBuf Tfin;        // float [H][W]
     DevBuf ncontrib;    // u32 [H][W]
     DevBuf dL, hd;      // float [3][H][W] loss maps
-    DevBuf coef;        // float [3][8][H][W] SSIM coefficient maps
+    DevBuf coef;        // double [3][8][H][W] SSIM coefficient maps
     DevBuf zstats;      // float [GSN_NZ][n], optional debug copy
     DevBuf loss_part;   // double [2][nblocks]
     // sort / scan scratch
@@ -74,11 +75,12 @@ void launch_emit_pairs(const uint32_t* sorted_ids, const uint32_t* offsets, uint
                        uint32_t tiles_x, uint32_t* keys, uint32_t* vals, uint32_t* pair_off, hipStream_t s);
 void launch_tile_ranges(const uint32_t* keys, uint32_t pairs, uint2* ranges, hipStream_t s);
 void launch_raster_fwd(const uint2* ranges, const uint32_t* ids, const float4* rec, uint32_t n, const DevCam& cam,
-                       const DevRenderOpts& ro, float* img, float* Tfin, uint32_t* ncontrib, hipStream_t s);
+                       const DevRenderOpts& ro, float* img, double* img64, float* Tfin, uint32_t* ncontrib,
+                       hipStream_t s);
 void launch_downsample2x(const float* src, int W, int H, float* dst, hipStream_t s);
 
 // ---- launchers (loss.hip)
-void launch_loss_maps(const float* img, const float* tgt, int W, int H, float lambda, float* coef, float* dL,
+void launch_loss_maps(const float* img, const float* tgt, int W, int H, float lambda, double* coef, float* dL,
                       float* hd, double* part, int* nparts, hipStream_t s);
 void launch_loss_reduce(const double* part, int nparts, int W, int H, double* out, hipStream_t s);
 

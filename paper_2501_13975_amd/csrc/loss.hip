@@ -25,9 +25,9 @@
 namespace {
 
 constexpr int T = 16, HALO = 5, R = T + 2 * HALO;  // 26
-constexpr float kC1 = 0.0001f, kC2 = 0.0009f;
+constexpr double kC1 = 0.01 * 0.01, kC2 = 0.03 * 0.03;
 
-__device__ __forceinline__ void window_weights(float* g, float* g2) {
+__device__ __forceinline__ void window_weights(double* g, double* g2) {
     // normalised 1D Gaussian, sigma 1.5; the 2D window is the outer product
     if (threadIdx.x < 11) {
         double s = 0.0, v[11];
@@ -36,17 +36,17 @@ __device__ __forceinline__ void window_weights(float* g, float* g2) {
             s += v[i];
         }
         const double gi = v[threadIdx.x] / s;
-        g[threadIdx.x] = (float)gi;
-        g2[threadIdx.x] = (float)(gi * gi);
+        g[threadIdx.x] = gi;
+        g2[threadIdx.x] = gi * gi;
     }
 }
 
 __global__ __launch_bounds__(256) void ssim_coef_kernel(const float* __restrict__ img, const float* __restrict__ tgt,
-                                                         int W, int H, float* __restrict__ coef,
+                                                         int W, int H, double* __restrict__ coef,
                                                          double* __restrict__ part) {
-    __shared__ float g[11], g2[11];
-    __shared__ float sc[R][R], st[R][R];
-    __shared__ float hs[5][R][T];
+    __shared__ double g[11], g2[11];
+    __shared__ double sc[R][R], st[R][R];
+    __shared__ double hs[5][R][T];
     const int ch = blockIdx.z;
     const int x0 = blockIdx.x * T - HALO, y0 = blockIdx.y * T - HALO;
     const size_t np = (size_t)W * H;
@@ -56,16 +56,16 @@ __global__ __launch_bounds__(256) void ssim_coef_kernel(const float* __restrict_
     for (int i = threadIdx.x; i < R * R; i += 256) {
         const int yy = i / R, xx = i % R, x = x0 + xx, y = y0 + yy;
         const bool in = x >= 0 && y >= 0 && x < W && y < H;
-        sc[yy][xx] = in ? I[(size_t)y * W + x] : 0.f;
-        st[yy][xx] = in ? Tg[(size_t)y * W + x] : 0.f;
+        sc[yy][xx] = in ? (double)I[(size_t)y * W + x] : 0.0;
+        st[yy][xx] = in ? (double)Tg[(size_t)y * W + x] : 0.0;
     }
     __syncthreads();
     for (int i = threadIdx.x; i < R * T; i += 256) {
         const int yy = i / T, xx = i % T;
-        float a = 0, b = 0, c = 0, d = 0, e = 0;
+        double a = 0, b = 0, c = 0, d = 0, e = 0;
 #pragma unroll
         for (int k = 0; k < 11; ++k) {
-            const float u = sc[yy][xx + k], v = st[yy][xx + k], w = g[k];
+            const double u = sc[yy][xx + k], v = st[yy][xx + k], w = g[k];
             a += w * u;
             b += w * v;
             c += w * u * u;
@@ -83,28 +83,28 @@ __global__ __launch_bounds__(256) void ssim_coef_kernel(const float* __restrict_
     const int x = blockIdx.x * T + lx, y = blockIdx.y * T + ly;
     double l2 = 0.0, ls = 0.0;
     if (x < W && y < H) {
-        float m[5] = {0, 0, 0, 0, 0};
+        double m[5] = {0, 0, 0, 0, 0};
 #pragma unroll
         for (int k = 0; k < 11; ++k)
 #pragma unroll
             for (int q = 0; q < 5; ++q) m[q] += g[k] * hs[q][ly + k][lx];
-        const float mu = m[0], mut = m[1];
-        const float f0 = 2.f * mu * mut + kC1;
-        const float f1 = 2.f * (m[4] - mu * mut) + kC2;
-        const float f2 = mu * mu + mut * mut + kC1;
-        const float f3 = (m[2] - mu * mu) + (m[3] - mut * mut) + kC2;
-        const float F = (f0 * f1) / (f2 * f3);
-        const float i0 = 1.f / f0, i1 = 1.f / f1, i2 = 1.f / f2, i3 = 1.f / f3;
-        const float a0 = 2.f * mut * i0 - 2.f * mut * i1 - 2.f * mu * i2 + 2.f * mu * i3;
-        const float a1 = 2.f * i1, a2 = 2.f * i3;
-        const float b0 = a0 * a0 - 4.f * mut * mut * i0 * i0 - 4.f * mut * mut * i1 * i1 - 2.f * i2 +
-                         4.f * mu * mu * i2 * i2 + 2.f * i3 + 4.f * mu * mu * i3 * i3;
-        const float bt = 2.f * a0 * a1 + 8.f * mut * i1 * i1;
-        const float bc = -2.f * a0 * a2 - 8.f * mu * i3 * i3;
-        const float bcc = 8.f * i3 * i3;
-        const float btc = -8.f * i1 * i3;
+        const double mu = m[0], mut = m[1];
+        const double f0 = 2.0 * mu * mut + kC1;
+        const double f1 = 2.0 * (m[4] - mu * mut) + kC2;
+        const double f2 = mu * mu + mut * mut + kC1;
+        const double f3 = (m[2] - mu * mu) + (m[3] - mut * mut) + kC2;
+        const double F = (f0 * f1) / (f2 * f3);
+        const double i0 = 1.0 / f0, i1 = 1.0 / f1, i2 = 1.0 / f2, i3 = 1.0 / f3;
+        const double a0 = 2.0 * mut * i0 - 2.0 * mut * i1 - 2.0 * mu * i2 + 2.0 * mu * i3;
+        const double a1 = 2.0 * i1, a2 = 2.0 * i3;
+        const double b0 = a0 * a0 - 4.0 * mut * mut * i0 * i0 - 4.0 * mut * mut * i1 * i1 - 2.0 * i2 +
+                          4.0 * mu * mu * i2 * i2 + 2.0 * i3 + 4.0 * mu * mu * i3 * i3;
+        const double bt = 2.0 * a0 * a1 + 8.0 * mut * i1 * i1;
+        const double bc = -2.0 * a0 * a2 - 8.0 * mu * i3 * i3;
+        const double bcc = 8.0 * i3 * i3;
+        const double btc = -8.0 * i1 * i3;
         const size_t pi = (size_t)y * W + x;
-        float* cf = coef + (size_t)ch * 8 * np;
+        double* cf = coef + (size_t)ch * 8 * np;
         cf[0 * np + pi] = F * a0;
         cf[1 * np + pi] = F * a1;
         cf[2 * np + pi] = F * a2;
@@ -115,7 +115,7 @@ __global__ __launch_bounds__(256) void ssim_coef_kernel(const float* __restrict_
         cf[7 * np + pi] = F * btc;
         const double r = (double)sc[ly + HALO][lx + HALO] - (double)st[ly + HALO][lx + HALO];
         l2 = r * r;
-        ls = 1.0 - (double)F;
+        ls = 1.0 - F;
     }
     // deterministic block reduction in double
     __shared__ double red[2][256];
@@ -138,29 +138,29 @@ __global__ __launch_bounds__(256) void ssim_coef_kernel(const float* __restrict_
 }
 
 __global__ __launch_bounds__(256) void ssim_grad_kernel(const float* __restrict__ img, const float* __restrict__ tgt,
-                                                         int W, int H, float lambda, const float* __restrict__ coef,
+                                                         int W, int H, float lambda, const double* __restrict__ coef,
                                                          float* __restrict__ dL, float* __restrict__ hd) {
-    __shared__ float g[11], g2[11];
-    __shared__ float sm[8][R][R];
-    __shared__ float hs[8][R][T];
+    __shared__ double g[11], g2[11];
+    __shared__ double sm[8][R][R];
+    __shared__ double hs[8][R][T];
     const int ch = blockIdx.z;
     const int x0 = blockIdx.x * T - HALO, y0 = blockIdx.y * T - HALO;
     const size_t np = (size_t)W * H;
-    const float* cf = coef + (size_t)ch * 8 * np;
+    const double* cf = coef + (size_t)ch * 8 * np;
     window_weights(g, g2);
     for (int i = threadIdx.x; i < R * R; i += 256) {
         const int yy = i / R, xx = i % R, x = x0 + xx, y = y0 + yy;
         const bool in = x >= 0 && y >= 0 && x < W && y < H;
         const size_t pi = (size_t)y * W + x;
 #pragma unroll
-        for (int q = 0; q < 8; ++q) sm[q][yy][xx] = in ? cf[q * np + pi] : 0.f;
+        for (int q = 0; q < 8; ++q) sm[q][yy][xx] = in ? cf[q * np + pi] : 0.0;
     }
     __syncthreads();
     for (int i = threadIdx.x; i < R * T; i += 256) {
         const int yy = i / T, xx = i % T;
 #pragma unroll
         for (int q = 0; q < 8; ++q) {
-            float a = 0.f;
+            double a = 0.0;
 #pragma unroll
             for (int k = 0; k < 11; ++k) a += (q < 3 ? g[k] : g2[k]) * sm[q][yy][xx + k];
             hs[q][yy][xx] = a;
@@ -170,21 +170,21 @@ __global__ __launch_bounds__(256) void ssim_grad_kernel(const float* __restrict_
     const int lx = threadIdx.x % T, ly = threadIdx.x / T;
     const int x = blockIdx.x * T + lx, y = blockIdx.y * T + ly;
     if (x >= W || y >= H) return;
-    float v[8];
+    double v[8];
 #pragma unroll
     for (int q = 0; q < 8; ++q) {
-        float a = 0.f;
+        double a = 0.0;
 #pragma unroll
         for (int k = 0; k < 11; ++k) a += (q < 3 ? g[k] : g2[k]) * hs[q][ly + k][lx];
         v[q] = a;
     }
     const size_t pi = (size_t)y * W + x;
-    const float c = img[ch * np + pi], t = tgt[ch * np + pi];
-    const float norm = 1.0f / (3.0f * (float)np);
-    const float d1 = v[0] + t * v[1] - c * v[2];
-    const float d2 = v[3] + t * v[4] + c * v[5] + c * c * v[6] + c * t * v[7] - v[2];
-    dL[ch * np + pi] = (c - t) * norm - lambda * norm * d1;
-    hd[ch * np + pi] = norm - lambda * norm * d2;
+    const double c = img[ch * np + pi], t = tgt[ch * np + pi];
+    const double norm = 1.0 / (3.0 * (double)np);
+    const double d1 = v[0] + t * v[1] - c * v[2];
+    const double d2 = v[3] + t * v[4] + c * v[5] + c * c * v[6] + c * t * v[7] - v[2];
+    dL[ch * np + pi] = (float)((c - t) * norm - (double)lambda * norm * d1);
+    hd[ch * np + pi] = (float)(norm - (double)lambda * norm * d2);
 }
 
 __global__ void loss_reduce_kernel(const double* __restrict__ part, int nparts, double npix, double* __restrict__ out) {
@@ -212,7 +212,7 @@ __global__ void loss_reduce_kernel(const double* __restrict__ part, int nparts, 
 
 }  // namespace
 
-void launch_loss_maps(const float* img, const float* tgt, int W, int H, float lambda, float* coef, float* dL,
+void launch_loss_maps(const float* img, const float* tgt, int W, int H, float lambda, double* coef, float* dL,
                       float* hd, double* part, int* nparts, hipStream_t s) {
     dim3 grid((W + T - 1) / T, (H + T - 1) / T, 3);
     *nparts = (int)(grid.x * grid.y * grid.z);

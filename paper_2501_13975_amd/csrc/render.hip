@@ -129,8 +129,33 @@ __global__ __launch_bounds__(kThreads) void preprocess_kernel(
     depth_key[k] = __float_as_uint(b.tz);
     ntiles[k] = (uint32_t)((b.x1 - b.x0) * (b.y1 - b.y0));
     rect[k] = make_uint2((uint32_t)b.x0 | ((uint32_t)b.y0 << 16), (uint32_t)b.x1 | ((uint32_t)b.y1 << 16));
-    const float idet = 1.0f / b.det;
-    // view direction from the camera centre and SH colour c~ = sum_i Y_i(r) c_i
+    // compositing record in the splat's principal frame (see device_common.h)
+    float l1, l2, fc, fs;
+    {
+        const float qn = rsqrtf(rot[k] * rot[k] + rot[n + k] * rot[n + k] + rot[2 * n + k] * rot[2 * n + k] +
+                                rot[3 * n + k] * rot[3 * n + k]);
+        const float w = rot[k] * qn, x = rot[n + k] * qn, y = rot[2 * n + k] * qn, z = rot[3 * n + k] * qn;
+        const float Rq[3][3] = {{1.f - 2.f * (y * y + z * z), 2.f * (x * y - w * z), 2.f * (x * z + w * y)},
+                                {2.f * (x * y + w * z), 1.f - 2.f * (x * x + z * z), 2.f * (y * z - w * x)},
+                                {2.f * (x * z - w * y), 2.f * (y * z + w * x), 1.f - 2.f * (x * x + y * y)}};
+        const float iz = 1.0f / b.tz;
+        const float J00 = cam.fx * iz, J02 = -cam.fx * b.tx * iz * iz;
+        const float J11 = cam.fy * iz, J12 = -cam.fy * b.ty * iz * iz;
+        const float sv[3] = {scale[k], scale[n + k], scale[2 * n + k]};
+        float A[2][3];
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            float m0 = 0.f, m1 = 0.f;
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                m0 += (J00 * cam.R[c] + J02 * cam.R[6 + c]) * Rq[c][a];
+                m1 += (J11 * cam.R[3 + c] + J12 * cam.R[6 + c]) * Rq[c][a];
+            }
+            A[0][a] = m0 * sv[a];
+            A[1][a] = m1 * sv[a];
+        }
+        principal_frame<float>(A, ro.kappa, l1, l2, fc, fs);
+    }
     const float dx = px - cam.o[0], dy = py - cam.o[1], dz = pz - cam.o[2];
     const float il = rsqrtf(dx * dx + dy * dy + dz * dz);
     float Y[16];
@@ -142,9 +167,9 @@ __global__ __launch_bounds__(kThreads) void preprocess_kernel(
         for (int i = 0; i < K; ++i) acc += Y[i] * sh[((size_t)ch * K + i) * n + k];
         col[ch] = acc;
     }
-    rec[k] = make_float4(b.u, b.v, b.cyy * idet, -b.cxy * idet);
-    rec[n + k] = make_float4(b.cxx * idet, opac[k], col[0], col[1]);
-    rec[2 * (size_t)n + k] = make_float4(col[2], 0.f, 0.f, 0.f);
+    rec[k] = make_float4(b.u, b.v, 1.0f / l1, 1.0f / l2);
+    rec[n + k] = make_float4(fc, fs, opac[k], col[0]);
+    rec[2 * (size_t)n + k] = make_float4(col[1], col[2], 0.f, 0.f);
 }
 
 // ---------------------------------------------------------------------------
@@ -357,18 +382,20 @@ __global__ void tile_ranges_kernel(const uint32_t* __restrict__ keys, uint32_t p
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(GSN_BLOCK) void raster_fwd_kernel(
     const uint2* __restrict__ ranges, const uint32_t* __restrict__ ids, const float4* __restrict__ rec, uint32_t n,
-    DevCam cam, DevRenderOpts ro, float* __restrict__ img, float* __restrict__ Tfin,
+    DevCam cam, DevRenderOpts ro, float* __restrict__ img, double* __restrict__ img64, float* __restrict__ Tfin,
     uint32_t* __restrict__ ncontrib) {
     __shared__ float4 s_a[GSN_BLOCK];
     __shared__ float4 s_b[GSN_BLOCK];
-    __shared__ float s_c[GSN_BLOCK];
+    __shared__ float2 s_c[GSN_BLOCK];
     const int tile = blockIdx.x;
     const int tx = tile % cam.tiles_x, ty = tile / cam.tiles_x;
     const int px = tx * GSN_TILE + (threadIdx.x % GSN_TILE);
     const int py = ty * GSN_TILE + (threadIdx.x / GSN_TILE);
     const bool inside = px < cam.W && py < cam.H;
     const uint2 rg = ranges[tile];
-    float T = 1.0f, C0 = 0.f, C1 = 0.f, C2 = 0.f;
+    // colour accumulated in double: the backward pass subtracts partial sums from it
+    float T = 1.0f;
+    double C0 = 0.0, C1 = 0.0, C2 = 0.0;
     uint32_t last = 0;
     bool done = !inside;
     const float fpx = (float)px, fpy = (float)py;
@@ -379,32 +406,39 @@ __global__ __launch_bounds__(GSN_BLOCK) void raster_fwd_kernel(
             const uint32_t id = ids[e];
             s_a[threadIdx.x] = rec[id];
             s_b[threadIdx.x] = rec[n + id];
-            s_c[threadIdx.x] = rec[2 * (size_t)n + id].x;
+            const float4 c4 = rec[2 * (size_t)n + id];
+            s_c[threadIdx.x] = make_float2(c4.x, c4.y);
         }
         __syncthreads();
         const int cnt = min((uint32_t)GSN_BLOCK, rg.y - base);
         for (int j = 0; j < cnt && !done; ++j) {
             const float4 a = s_a[j], b = s_b[j];
-            const SplatEval ev = eval_splat(a.x, a.y, a.z, a.w, b.x, b.y, fpx, fpy, ro.alpha_max);
+            const SplatEval ev = eval_splat(a.x, a.y, a.z, a.w, b.x, b.y, b.z, fpx, fpy, ro.alpha_max);
             if (ev.alpha < ro.alpha_min) continue;
             const float Tn = T * (1.0f - ev.alpha);
             if (Tn < ro.T_min) {
                 done = true;
                 break;
             }
-            const float w = ev.alpha * T;
-            C0 += w * b.z;
-            C1 += w * b.w;
-            C2 += w * s_c[j];
+            const double w = (double)(ev.alpha * T);
+            const float2 cc = s_c[j];
+            C0 += w * (double)b.w;
+            C1 += w * (double)cc.x;
+            C2 += w * (double)cc.y;
             T = Tn;
             last = base + j + 1 - rg.x;
         }
     }
     if (inside) {
         const size_t np = (size_t)cam.W * cam.H, pi = (size_t)py * cam.W + px;
-        img[pi] = C0 + T * ro.bg[0];
-        img[np + pi] = C1 + T * ro.bg[1];
-        img[2 * np + pi] = C2 + T * ro.bg[2];
+        const double c0 = C0 + (double)(T * ro.bg[0]), c1 = C1 + (double)(T * ro.bg[1]),
+                     c2 = C2 + (double)(T * ro.bg[2]);
+        img[pi] = (float)c0;
+        img[np + pi] = (float)c1;
+        img[2 * np + pi] = (float)c2;
+        img64[pi] = c0;
+        img64[np + pi] = c1;
+        img64[2 * np + pi] = c2;
         Tfin[pi] = T;
         ncontrib[pi] = last;
     }
@@ -493,9 +527,10 @@ void launch_tile_ranges(const uint32_t* keys, uint32_t pairs, uint2* ranges, hip
 }
 
 void launch_raster_fwd(const uint2* ranges, const uint32_t* ids, const float4* rec, uint32_t n, const DevCam& cam,
-                       const DevRenderOpts& ro, float* img, float* Tfin, uint32_t* ncontrib, hipStream_t s) {
+                       const DevRenderOpts& ro, float* img, double* img64, float* Tfin, uint32_t* ncontrib,
+                       hipStream_t s) {
     const int tiles = cam.tiles_x * cam.tiles_y;
-    raster_fwd_kernel<<<tiles, GSN_BLOCK, 0, s>>>(ranges, ids, rec, n, cam, ro, img, Tfin, ncontrib);
+    raster_fwd_kernel<<<tiles, GSN_BLOCK, 0, s>>>(ranges, ids, rec, n, cam, ro, img, img64, Tfin, ncontrib);
 }
 
 void launch_downsample2x(const float* src, int W, int H, float* dst, hipStream_t s) {

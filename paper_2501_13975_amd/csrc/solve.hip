@@ -4,15 +4,19 @@
 // and solves, in the reduced coordinates of the primary camera:
 //   position: Delta p = U Delta v, U an orthonormal basis of the plane normal to
 //             the view direction r_k, (U^T H_p U) Delta v = -U^T g_p;
-//   rotation: q(theta) = (cos(theta/2), sin(theta/2) r_k) q, with
-//             dq/dtheta = (0, r_k)/2 q and d2q/dtheta2 = -q/4 at theta = 0;
+//   rotation: q(theta) = (cos(theta/2), sin(theta/2) r_k) q is the left rotation by
+//             omega = theta r_k, so g_theta = r^T g_omega and H_theta = r^T H_omega r;
 //   scaling:  Newton restricted to the row space of T = d lambda/d s (lambda the
 //             eigenvalues of the primary 2D covariance), Delta s = T^T a;
 //   opacity:  log barrier -alpha_s [ln sigma + ln(1 - sigma)];
 //   colour:   per channel G = sum_v s_v Y(r_v) Y(r_v)^T, g = sum_v gamma_v Y(r_v).
 // Every group is damped by the same rule: Cholesky of H + mu_j I,
-// mu_j = mu0 10^j, accepted when all pivots are positive and min/max pivot is at
-// least pivot_min, else the scaled gradient step.  The colour system has rank at
+// mu_j = mu0 10^j with mu0 = damp_rel |H|_F / sqrt(n) + damp_abs / (3 |I|), accepted
+// when every pivot exceeds pivot_min (|H|_F / sqrt(n) + mu_j) and min/max pivot is at
+// least pivot_min, else the
+// scaled gradient step; the step is then clamped to the group's trust radius.
+// The small systems are solved in double precision (the FP64 vector rate of
+// gfx950 equals its unpacked FP32 rate, and this pass is bound by memory).  The colour system has rank at
 // most V (number of views that see the kernel); when V < K it is solved in view
 // space, (B B^T + mu S^-1) y = -S^-1 gamma, Delta = B^T y, which equals the
 // damped K x K solve exactly and is far better conditioned.
@@ -22,64 +26,74 @@ namespace {
 
 constexpr int VMAX = 9;
 
-// Damped solve of a 1x1 or 2x2 symmetric system (H packed xx, xy, yy for n = 2).
-__device__ int damped_small(int n, const float* H, const float* g, const gsn_solve_opts& o, float abs_scale,
-                            float* x) {
-    const float md = n == 1 ? H[0] : 0.5f * (H[0] + H[2]);
-    const float ma = n == 1 ? fabsf(H[0]) : 0.5f * (fabsf(H[0]) + fabsf(H[2]));
-    float mu = o.damp_rel * fmaxf(md, 0.f) + o.damp_abs * abs_scale;
+// Damped solve of a 1x1 or 2x2 symmetric system (H packed xx, xy, yy for n = 2) in double.
+__device__ int damped_small(int n, const double* H, const double* g, const gsn_solve_opts& o, double abs_scale,
+                            double* x) {
+    // scale of H: Frobenius norm / sqrt(n), invariant to the reduced basis
+    const double ma = n == 1 ? fabs(H[0]) : sqrt(0.5 * (H[0] * H[0] + 2.0 * H[1] * H[1] + H[2] * H[2]));
+    double mu = (double)o.damp_rel * ma + (double)o.damp_abs * abs_scale;
     for (int j = 0; j <= o.max_escalations; ++j) {
+        // every pivot must exceed pivot_min times the size of H + mu I
+        const double floor = (double)o.pivot_min * (ma + mu);
         if (n == 1) {
-            const float d = H[0] + mu;
-            if (d > 0.f) {
+            const double d = H[0] + mu;
+            if (d > floor) {
                 x[0] = -g[0] / d;
                 return j;
             }
         } else {
-            const float a = H[0] + mu, b = H[1], c = H[2] + mu;
-            if (a > 0.f) {
-                const float l10 = b / a;
-                const float d2 = c - l10 * b;
-                if (d2 > 0.f && fminf(a, d2) >= o.pivot_min * fmaxf(a, d2)) {
-                    // forward/back substitution with L = [[1, 0], [l10, 1]], D = diag(a, d2)
-                    const float y0 = -g[0], y1 = -g[1] - l10 * y0;
+            const double a = H[0] + mu, b = H[1], c = H[2] + mu;
+            if (a > floor) {
+                const double l10 = b / a;
+                const double d2 = c - l10 * b;
+                if (d2 > floor && fmin(a, d2) >= (double)o.pivot_min * fmax(a, d2)) {
+                    // L D L^T with L = [[1, 0], [l10, 1]], D = diag(a, d2)
+                    const double y0 = -g[0], y1 = -g[1] - l10 * y0;
                     x[1] = y1 / d2;
                     x[0] = (y0 - b * x[1]) / a;
                     return j;
                 }
             }
         }
-        if (j < o.max_escalations) mu *= 10.f;
+        if (j < o.max_escalations) mu *= 10.0;
     }
-    const float den = ma + mu;
+    const double den = ma + mu;
     for (int i = 0; i < n; ++i) x[i] = -g[i] / den;
     return -1;
 }
 
-// Cholesky solve of an m x m SPD system held in a VMAX x VMAX register array.
-__device__ bool chol_solve_v(int m, float A[VMAX][VMAX], const float* b, float* x) {
-    float L[VMAX][VMAX];
+__device__ void clamp_norm(int n, double* x, double radius) {
+    double nn = 0.0;
+    for (int i = 0; i < n; ++i) nn += x[i] * x[i];
+    nn = sqrt(nn);
+    if (nn > radius && nn > 0.0)
+        for (int i = 0; i < n; ++i) x[i] *= radius / nn;
+}
+
+// Cholesky solve of an m x m SPD system held in a VMAX x VMAX register array (double).
+__device__ bool chol_solve_v(int m, double A[VMAX][VMAX], const double* b, double* x) {
+    double L[VMAX][VMAX];
 #pragma unroll
     for (int i = 0; i < VMAX; ++i) {
         if (i >= m) break;
 #pragma unroll
         for (int j = 0; j <= i; ++j) {
-            float s = A[i][j];
+            double s = A[i][j];
 #pragma unroll
             for (int k = 0; k < j; ++k) s -= L[i][k] * L[j][k];
             if (i == j) {
-                if (!(s > 0.f)) return false;
-                L[i][i] = sqrtf(s);
+                if (!(s > 0.0)) return false;
+                L[i][i] = sqrt(s);
             } else {
                 L[i][j] = s / L[j][j];
             }
         }
     }
-    float y[VMAX];
+    double y[VMAX];
 #pragma unroll
     for (int i = 0; i < VMAX; ++i) {
         if (i >= m) break;
-        float s = b[i];
+        double s = b[i];
 #pragma unroll
         for (int k = 0; k < i; ++k) s -= L[i][k] * y[k];
         y[i] = s / L[i][i];
@@ -87,7 +101,7 @@ __device__ bool chol_solve_v(int m, float A[VMAX][VMAX], const float* b, float* 
 #pragma unroll
     for (int i = VMAX - 1; i >= 0; --i) {
         if (i >= m) continue;
-        float s = y[i];
+        double s = y[i];
 #pragma unroll
         for (int k = i + 1; k < VMAX; ++k)
             if (k < m) s -= L[k][i] * x[k];
@@ -96,7 +110,8 @@ __device__ bool chol_solve_v(int m, float A[VMAX][VMAX], const float* b, float* 
     return true;
 }
 
-__device__ __forceinline__ void qmul(const float a[4], const float b[4], float r[4]) {
+template <class T>
+__device__ __forceinline__ void qmul(const T a[4], const T b[4], T r[4]) {
     r[0] = a[0] * b[0] - a[1] * b[1] - a[2] * b[2] - a[3] * b[3];
     r[1] = a[0] * b[1] + b[0] * a[1] + a[2] * b[3] - a[3] * b[2];
     r[2] = a[0] * b[2] + b[0] * a[2] + a[3] * b[1] - a[1] * b[3];
@@ -112,105 +127,102 @@ __global__ __launch_bounds__(128) void solve_kernel(const float* __restrict__ po
     if (k >= n) return;
     const size_t N = (size_t)n;
     const int NS = GSN_STEP_BASE + 3 * K;
-    auto B = [&](int row) { return blk[(size_t)row * N + k]; };
-    if (!(B(34) > 0.f)) {
+    auto B = [&](int row) { return (double)blk[(size_t)row * N + k]; };
+    if (!(B(29) > 0.0)) {
         for (int r = 0; r < NS; ++r) st[(size_t)r * N + k] = 0.f;
-        for (int r = 0; r < 4; ++r) fl[(size_t)r * N + k] = -2;
-        fl[4 * N + k] = -2;
+        for (int r = 0; r < 5; ++r) fl[(size_t)r * N + k] = -2;
         return;
     }
-    const float abs_scale = 1.0f / (3.0f * (float)o.npix_primary);
-    float p[3], q[4], s[3];
+    const double abs_scale = 1.0 / (3.0 * (double)o.npix_primary);
+    double p[3], q[4], s[3];
     for (int a = 0; a < 3; ++a) p[a] = pos[a * N + k];
     for (int a = 0; a < 4; ++a) q[a] = rot[a * N + k];
     for (int a = 0; a < 3; ++a) s[a] = scale[a * N + k];
-    const float sig = opac[k];
-    float r[3] = {p[0] - c.o[0], p[1] - c.o[1], p[2] - c.o[2]};
+    const double sig = opac[k];
+    double r[3];
     {
-        const float il = 1.0f / sqrtf(r[0] * r[0] + r[1] * r[1] + r[2] * r[2]);
+        // camera centre -R^T t in double from the float camera
+        double oc[3];
+        for (int i = 0; i < 3; ++i)
+            oc[i] = -((double)c.R[i] * c.t[0] + (double)c.R[3 + i] * c.t[1] + (double)c.R[6 + i] * c.t[2]);
+        for (int a = 0; a < 3; ++a) r[a] = p[a] - oc[a];
+        const double il = 1.0 / sqrt(r[0] * r[0] + r[1] * r[1] + r[2] * r[2]);
         for (int a = 0; a < 3; ++a) r[a] *= il;
     }
-    for (int a = 0; a < 3; ++a) st[(4 + a) * N + k] = r[a];
+    for (int a = 0; a < 3; ++a) st[(4 + a) * N + k] = (float)r[a];
     // ---- position
     {
-        float uy[3] = {-r[1] * r[0], 1.0f - r[1] * r[1], -r[1] * r[2]};
-        float nn = uy[0] * uy[0] + uy[1] * uy[1] + uy[2] * uy[2];
-        if (nn < 1e-12f) {
-            uy[0] = 1.0f - r[0] * r[0];
+        double uy[3] = {-r[1] * r[0], 1.0 - r[1] * r[1], -r[1] * r[2]};
+        double nn = uy[0] * uy[0] + uy[1] * uy[1] + uy[2] * uy[2];
+        if (nn < 1e-12) {
+            uy[0] = 1.0 - r[0] * r[0];
             uy[1] = -r[0] * r[1];
             uy[2] = -r[0] * r[2];
             nn = uy[0] * uy[0] + uy[1] * uy[1] + uy[2] * uy[2];
         }
-        const float inn = 1.0f / sqrtf(nn);
+        const double inn = 1.0 / sqrt(nn);
         for (int a = 0; a < 3; ++a) uy[a] *= inn;
-        const float ux[3] = {r[1] * uy[2] - r[2] * uy[1], r[2] * uy[0] - r[0] * uy[2], r[0] * uy[1] - r[1] * uy[0]};
-        const float Hp[3][3] = {{B(3), B(4), B(5)}, {B(4), B(6), B(7)}, {B(5), B(7), B(8)}};
-        const float gp[3] = {B(0), B(1), B(2)};
-        const float* U[2] = {ux, uy};
-        float H2[3], g2[2], dv[2];
-        for (int i = 0; i < 2; ++i) {
-            g2[i] = U[i][0] * gp[0] + U[i][1] * gp[1] + U[i][2] * gp[2];
+        const double ux[3] = {r[1] * uy[2] - r[2] * uy[1], r[2] * uy[0] - r[0] * uy[2], r[0] * uy[1] - r[1] * uy[0]};
+        const double Hp[3][3] = {{B(3), B(4), B(5)}, {B(4), B(6), B(7)}, {B(5), B(7), B(8)}};
+        const double gp[3] = {B(0), B(1), B(2)};
+        double HU[3][2];
+        for (int a = 0; a < 3; ++a) {
+            HU[a][0] = Hp[a][0] * ux[0] + Hp[a][1] * ux[1] + Hp[a][2] * ux[2];
+            HU[a][1] = Hp[a][0] * uy[0] + Hp[a][1] * uy[1] + Hp[a][2] * uy[2];
         }
-        float HU[3][2];
-        for (int a = 0; a < 3; ++a)
-            for (int j = 0; j < 2; ++j) HU[a][j] = Hp[a][0] * U[j][0] + Hp[a][1] * U[j][1] + Hp[a][2] * U[j][2];
+        double H2[3], g2[2], dv[2];
+        g2[0] = ux[0] * gp[0] + ux[1] * gp[1] + ux[2] * gp[2];
+        g2[1] = uy[0] * gp[0] + uy[1] * gp[1] + uy[2] * gp[2];
         H2[0] = ux[0] * HU[0][0] + ux[1] * HU[1][0] + ux[2] * HU[2][0];
         H2[1] = ux[0] * HU[0][1] + ux[1] * HU[1][1] + ux[2] * HU[2][1];
         H2[2] = uy[0] * HU[0][1] + uy[1] * HU[1][1] + uy[2] * HU[2][1];
         fl[0 * N + k] = damped_small(2, H2, g2, o, abs_scale, dv);
-        for (int a = 0; a < 3; ++a) st[(size_t)a * N + k] = ux[a] * dv[0] + uy[a] * dv[1];
+        clamp_norm(2, dv, (double)o.trust_pos * fmax(s[0], fmax(s[1], s[2])));
+        for (int a = 0; a < 3; ++a) st[(size_t)a * N + k] = (float)(ux[a] * dv[0] + uy[a] * dv[1]);
     }
-    // ---- rotation about r
+    // ---- rotation about r: omega = theta r
     {
-        const float rq[4] = {0.f, 0.5f * r[0], 0.5f * r[1], 0.5f * r[2]};
-        float t[4];
-        qmul(rq, q, t);
-        const float gq[4] = {B(9), B(10), B(11), B(12)};
-        float Hq[4][4];
-        int idx = 13;
-        for (int a = 0; a < 4; ++a)
-            for (int b = a; b < 4; ++b, ++idx) Hq[a][b] = Hq[b][a] = B(idx);
-        float gt = 0.f, Ht = 0.f, gqq = 0.f;
-        for (int a = 0; a < 4; ++a) {
-            gt += gq[a] * t[a];
-            gqq += gq[a] * q[a];
-            for (int b = 0; b < 4; ++b) Ht += t[a] * Hq[a][b] * t[b];
+        const double Hw[3][3] = {{B(12), B(13), B(14)}, {B(13), B(15), B(16)}, {B(14), B(16), B(17)}};
+        double gt = 0.0, Ht = 0.0;
+        for (int a = 0; a < 3; ++a) {
+            gt += r[a] * B(9 + a);
+            for (int b = 0; b < 3; ++b) Ht += r[a] * Hw[a][b] * r[b];
         }
-        Ht += -0.25f * gqq;
-        float th;
+        double th;
         fl[1 * N + k] = damped_small(1, &Ht, &gt, o, abs_scale, &th);
-        st[3 * N + k] = th;
+        clamp_norm(1, &th, (double)o.trust_rot);
+        st[3 * N + k] = (float)th;
     }
-    // ---- scaling in the row space of d lambda / d s
+    // ---- scaling in the row space of d lambda / d s (unit rows)
     {
-        float tf[3];
+        double tf[3];
         for (int i = 0; i < 3; ++i) tf[i] = c.R[3 * i] * p[0] + c.R[3 * i + 1] * p[1] + c.R[3 * i + 2] * p[2] + c.t[i];
-        const float iz = 1.0f / tf[2];
-        const float J00 = c.fx * iz, J02 = -c.fx * tf[0] * iz * iz, J11 = c.fy * iz, J12 = -c.fy * tf[1] * iz * iz;
-        float M[2][3];
+        const double iz = 1.0 / tf[2];
+        const double J00 = c.fx * iz, J02 = -c.fx * tf[0] * iz * iz, J11 = c.fy * iz, J12 = -c.fy * tf[1] * iz * iz;
+        double M[2][3];
         for (int kk = 0; kk < 3; ++kk) {
             M[0][kk] = J00 * c.R[kk] + J02 * c.R[6 + kk];
             M[1][kk] = J11 * c.R[3 + kk] + J12 * c.R[6 + kk];
         }
-        const float qn = 1.0f / sqrtf(q[0] * q[0] + q[1] * q[1] + q[2] * q[2] + q[3] * q[3]);
-        const float w = q[0] * qn, x = q[1] * qn, y = q[2] * qn, z = q[3] * qn;
-        const float Rq[3][3] = {{1.f - 2.f * (y * y + z * z), 2.f * (x * y - w * z), 2.f * (x * z + w * y)},
-                                {2.f * (x * y + w * z), 1.f - 2.f * (x * x + z * z), 2.f * (y * z - w * x)},
-                                {2.f * (x * z - w * y), 2.f * (y * z + w * x), 1.f - 2.f * (x * x + y * y)}};
-        float MR[2][3];
+        const double qn = 1.0 / sqrt(q[0] * q[0] + q[1] * q[1] + q[2] * q[2] + q[3] * q[3]);
+        const double w = q[0] * qn, x = q[1] * qn, y = q[2] * qn, z = q[3] * qn;
+        const double Rq[3][3] = {{1.0 - 2.0 * (y * y + z * z), 2.0 * (x * y - w * z), 2.0 * (x * z + w * y)},
+                                 {2.0 * (x * y + w * z), 1.0 - 2.0 * (x * x + z * z), 2.0 * (y * z - w * x)},
+                                 {2.0 * (x * z - w * y), 2.0 * (y * z + w * x), 1.0 - 2.0 * (x * x + y * y)}};
+        double MR[2][3];
         for (int i = 0; i < 2; ++i)
             for (int a = 0; a < 3; ++a) MR[i][a] = M[i][0] * Rq[0][a] + M[i][1] * Rq[1][a] + M[i][2] * Rq[2][a];
-        float sxx = kappa, sxy = 0.f, syy = kappa;
+        double sxx = kappa, sxy = 0.0, syy = kappa;
         for (int a = 0; a < 3; ++a) {
-            const float s2 = s[a] * s[a];
+            const double s2 = s[a] * s[a];
             sxx += MR[0][a] * MR[0][a] * s2;
             sxy += MR[0][a] * MR[1][a] * s2;
             syy += MR[1][a] * MR[1][a] * s2;
         }
-        const float mid = 0.5f * (sxx + syy);
-        const float rad = sqrtf(0.25f * (sxx - syy) * (sxx - syy) + sxy * sxy);
-        const float l2 = mid + rad;
-        float v2[2];
+        const double mid = 0.5 * (sxx + syy);
+        const double rad = sqrt(0.25 * (sxx - syy) * (sxx - syy) + sxy * sxy);
+        const double l2 = mid + rad;
+        double v2[2];
         if (sxx >= syy) {
             v2[0] = l2 - syy;
             v2[1] = sxy;
@@ -218,93 +230,102 @@ __global__ __launch_bounds__(128) void solve_kernel(const float* __restrict__ po
             v2[0] = sxy;
             v2[1] = l2 - sxx;
         }
-        float vn = sqrtf(v2[0] * v2[0] + v2[1] * v2[1]);
-        if (vn == 0.f) {
-            v2[0] = 1.f;
-            v2[1] = 0.f;
-            vn = 1.f;
+        double vn = sqrt(v2[0] * v2[0] + v2[1] * v2[1]);
+        if (vn == 0.0) {
+            v2[0] = 1.0;
+            v2[1] = 0.0;
+            vn = 1.0;
         }
         v2[0] /= vn;
         v2[1] /= vn;
-        const float v1[2] = {-v2[1], v2[0]};
-        float Tm[2][3];
+        const double v1[2] = {-v2[1], v2[0]};
+        double Tm[2][3];
         for (int a = 0; a < 3; ++a) {
-            const float e1 = v1[0] * MR[0][a] + v1[1] * MR[1][a];
-            const float e2 = v2[0] * MR[0][a] + v2[1] * MR[1][a];
-            Tm[0][a] = 2.f * s[a] * e1 * e1;
-            Tm[1][a] = 2.f * s[a] * e2 * e2;
+            const double e1 = v1[0] * MR[0][a] + v1[1] * MR[1][a];
+            const double e2 = v2[0] * MR[0][a] + v2[1] * MR[1][a];
+            Tm[0][a] = 2.0 * s[a] * e1 * e1;
+            Tm[1][a] = 2.0 * s[a] * e2 * e2;
         }
-        const float Hs[3][3] = {{B(26), B(27), B(28)}, {B(27), B(29), B(30)}, {B(28), B(30), B(31)}};
-        const float gs[3] = {B(23), B(24), B(25)};
-        float HT[3][2];
+        // only the row space of T matters; unit rows keep the reduced system well scaled
+        for (int i = 0; i < 2; ++i) {
+            const double tn = sqrt(Tm[i][0] * Tm[i][0] + Tm[i][1] * Tm[i][1] + Tm[i][2] * Tm[i][2]);
+            if (tn > 0.0)
+                for (int a = 0; a < 3; ++a) Tm[i][a] /= tn;
+        }
+        const double Hs[3][3] = {{B(21), B(22), B(23)}, {B(22), B(24), B(25)}, {B(23), B(25), B(26)}};
+        const double gs[3] = {B(18), B(19), B(20)};
+        double HT[3][2];
         for (int a = 0; a < 3; ++a)
             for (int j = 0; j < 2; ++j) HT[a][j] = Hs[a][0] * Tm[j][0] + Hs[a][1] * Tm[j][1] + Hs[a][2] * Tm[j][2];
-        float H2[3], g2[2], av[2];
+        double H2[3], g2[2], av[2];
         for (int i = 0; i < 2; ++i) g2[i] = Tm[i][0] * gs[0] + Tm[i][1] * gs[1] + Tm[i][2] * gs[2];
         H2[0] = Tm[0][0] * HT[0][0] + Tm[0][1] * HT[1][0] + Tm[0][2] * HT[2][0];
         H2[1] = Tm[0][0] * HT[0][1] + Tm[0][1] * HT[1][1] + Tm[0][2] * HT[2][1];
         H2[2] = Tm[1][0] * HT[0][1] + Tm[1][1] * HT[1][1] + Tm[1][2] * HT[2][1];
         fl[2 * N + k] = damped_small(2, H2, g2, o, abs_scale, av);
-        for (int a = 0; a < 3; ++a) st[(7 + a) * N + k] = Tm[0][a] * av[0] + Tm[1][a] * av[1];
+        double dsv[3];
+        for (int a = 0; a < 3; ++a) dsv[a] = Tm[0][a] * av[0] + Tm[1][a] * av[1];
+        clamp_norm(3, dsv, (double)o.trust_scale * sqrt(s[0] * s[0] + s[1] * s[1] + s[2] * s[2]));
+        for (int a = 0; a < 3; ++a) st[(7 + a) * N + k] = (float)dsv[a];
     }
     // ---- opacity with the log barrier
     {
-        const float as = o.barrier_beta * abs_scale;
-        const float gB = as * (1.0f / (1.0f - sig) - 1.0f / sig);
-        const float hB = as * (1.0f / (sig * sig) + 1.0f / ((1.0f - sig) * (1.0f - sig)));
-        const float H1 = B(33) + hB, g1 = B(32) + gB;
-        float ds;
+        const double as = (double)o.barrier_beta * abs_scale;
+        const double gB = as * (1.0 / (1.0 - sig) - 1.0 / sig);
+        const double hB = as * (1.0 / (sig * sig) + 1.0 / ((1.0 - sig) * (1.0 - sig)));
+        const double H1 = B(28) + hB, g1 = B(27) + gB;
+        double ds;
         fl[3 * N + k] = damped_small(1, &H1, &g1, o, abs_scale, &ds);
-        st[10 * N + k] = ds;
+        st[10 * N + k] = (float)ds;
     }
     // ---- colour, per channel
     {
         int vidx[VMAX];
         int nv = 0;
         for (int v = 0; v < V && v < VMAX; ++v)
-            if (B(GSN_BLK_BASE + GSN_BLK_VIEW * v + 9) > 0.f) vidx[nv++] = v;
+            if (B(GSN_BLK_BASE + GSN_BLK_VIEW * v + 9) > 0.0) vidx[nv++] = v;
         fl[4 * N + k] = nv;
-        float Yv[VMAX][16];
+        double Yv[VMAX][16];
         for (int i = 0; i < VMAX; ++i) {
             if (i >= nv) break;
             const int vb = GSN_BLK_BASE + GSN_BLK_VIEW * vidx[i];
-            sh_basis_dev<float>(K, B(vb + 6), B(vb + 7), B(vb + 8), Yv[i]);
+            sh_basis_dev<double>(K, B(vb + 6), B(vb + 7), B(vb + 8), Yv[i]);
         }
         for (int ch = 0; ch < 3; ++ch) {
-            float dsh[16];
-            for (int i = 0; i < K; ++i) dsh[i] = 0.f;
-            float smax = 0.f;
-            for (int i = 0; i < nv; ++i) smax = fmaxf(smax, fabsf(B(GSN_BLK_BASE + GSN_BLK_VIEW * vidx[i] + 3 + ch)));
-            if (smax > 0.f) {
-                float sv[VMAX], gv[VMAX];
-                float md = 0.f;  // mean diagonal of G = sum_v s_v Y Y^T
+            double dsh[16];
+            for (int i = 0; i < K; ++i) dsh[i] = 0.0;
+            double smax = 0.0;
+            for (int i = 0; i < nv; ++i) smax = fmax(smax, fabs(B(GSN_BLK_BASE + GSN_BLK_VIEW * vidx[i] + 3 + ch)));
+            if (smax > 0.0) {
+                double sv[VMAX], gv[VMAX];
+                double md = 0.0;  // mean diagonal of G = sum_v s_v Y Y^T
                 for (int i = 0; i < VMAX; ++i) {
                     if (i >= nv) break;
                     const int vb = GSN_BLK_BASE + GSN_BLK_VIEW * vidx[i];
-                    sv[i] = fmaxf(fabsf(B(vb + 3 + ch)), o.sh_floor * smax);
+                    sv[i] = fmax(fabs(B(vb + 3 + ch)), (double)o.sh_floor * smax);
                     gv[i] = B(vb + ch);
-                    float yy = 0.f;
+                    double yy = 0.0;
                     for (int a = 0; a < K; ++a) yy += Yv[i][a] * Yv[i][a];
                     md += sv[i] * yy;
                 }
-                md /= (float)K;
-                const float mu = o.damp_rel * md + o.damp_abs * abs_scale;
-                float A[VMAX][VMAX], rhs[VMAX], y[VMAX];
+                md /= (double)K;
+                const double mu = (double)o.damp_rel * md + (double)o.damp_abs * abs_scale;
+                double A[VMAX][VMAX], rhs[VMAX], y[VMAX];
                 if (nv < K) {
                     // view space: (B B^T + mu S^-1) y = -S^-1 gamma, Delta = B^T y
                     for (int i = 0; i < VMAX; ++i) {
                         if (i >= nv) break;
                         for (int j = 0; j < VMAX; ++j) {
                             if (j >= nv) break;
-                            float d = 0.f;
+                            double d = 0.0;
                             for (int a = 0; a < K; ++a) d += Yv[i][a] * Yv[j][a];
-                            A[i][j] = d + (i == j ? mu / sv[i] : 0.f);
+                            A[i][j] = d + (i == j ? mu / sv[i] : 0.0);
                         }
                         rhs[i] = -gv[i] / sv[i];
                     }
                     if (chol_solve_v(nv, A, rhs, y))
                         for (int a = 0; a < K; ++a) {
-                            float acc = 0.f;
+                            double acc = 0.0;
                             for (int i = 0; i < nv; ++i) acc += Yv[i][a] * y[i];
                             dsh[a] = acc;
                         }
@@ -314,11 +335,11 @@ __global__ __launch_bounds__(128) void solve_kernel(const float* __restrict__ po
                         if (a >= K) break;
                         for (int b = 0; b < VMAX; ++b) {
                             if (b >= K) break;
-                            float d = a == b ? mu : 0.f;
+                            double d = a == b ? mu : 0.0;
                             for (int i = 0; i < nv; ++i) d += sv[i] * Yv[i][a] * Yv[i][b];
                             A[a][b] = d;
                         }
-                        float gg = 0.f;
+                        double gg = 0.0;
                         for (int i = 0; i < nv; ++i) gg += gv[i] * Yv[i][a];
                         rhs[a] = -gg;
                     }
@@ -326,7 +347,7 @@ __global__ __launch_bounds__(128) void solve_kernel(const float* __restrict__ po
                         for (int a = 0; a < K; ++a) dsh[a] = y[a];
                 }
             }
-            for (int a = 0; a < K; ++a) st[(GSN_STEP_BASE + ch * K + a) * N + k] = dsh[a];
+            for (int a = 0; a < K; ++a) st[(GSN_STEP_BASE + ch * K + a) * N + k] = (float)dsh[a];
         }
     }
 }
@@ -348,7 +369,7 @@ __global__ __launch_bounds__(256) void apply_kernel(float* __restrict__ pos, flo
         const float dq[4] = {cosf(0.5f * th), sh2 * st[4 * N + k], sh2 * st[5 * N + k], sh2 * st[6 * N + k]};
         float q[4], r[4];
         for (int a = 0; a < 4; ++a) q[a] = rot[a * N + k];
-        qmul(dq, q, r);
+        qmul<float>(dq, q, r);
         const float il = 1.0f / sqrtf(r[0] * r[0] + r[1] * r[1] + r[2] * r[2] + r[3] * r[3]);
         for (int a = 0; a < 4; ++a) rot[a * N + k] = r[a] * il;
     }

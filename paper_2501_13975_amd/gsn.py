@@ -14,7 +14,7 @@ import torch
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libgsn.so")
 
-GSN_BLK_BASE, GSN_BLK_VIEW, GSN_STEP_BASE, GSN_NZ = 35, 10, 11, 44
+GSN_BLK_BASE, GSN_BLK_VIEW, GSN_STEP_BASE, GSN_NZ = 30, 10, 11, 44
 STATUS = {0: "GSN_OK", -1: "GSN_E_INVALID", -2: "GSN_E_SHAPE", -3: "GSN_E_CAPACITY", -4: "GSN_E_HIP",
           -5: "GSN_E_NOMEM"}
 
@@ -50,6 +50,7 @@ def lib():
             "gsn_frame_lists": [P, P, P, P, P, P, P],
             "gsn_frame_zstats": [P, P, P],
             "gsn_frame_loss_maps": [P, P, P, P],
+            "gsn_frame_records": [P, P, P],
         }.items():
             fn = getattr(L, name)
             fn.argtypes = args
@@ -91,7 +92,8 @@ class CSolveOpts(ctypes.Structure):
     _fields_ = [("damp_rel", ctypes.c_float), ("damp_abs", ctypes.c_float), ("pivot_min", ctypes.c_float),
                 ("max_escalations", ctypes.c_int32), ("barrier_beta", ctypes.c_float),
                 ("sh_floor", ctypes.c_float), ("scale_floor", ctypes.c_float), ("opac_ftb", ctypes.c_float),
-                ("npix_primary", ctypes.c_int32), ("kappa", ctypes.c_float)]
+                ("npix_primary", ctypes.c_int32), ("kappa", ctypes.c_float), ("trust_pos", ctypes.c_float),
+                ("trust_rot", ctypes.c_float), ("trust_scale", ctypes.c_float)]
 
 
 class CBlocks(ctypes.Structure):
@@ -112,10 +114,11 @@ def loss_opts(lambda_ssim=0.2, weight=1.0, keep_zstats=False):
     return CLossOpts(lambda_ssim, weight, int(keep_zstats))
 
 
-def solve_opts(npix_primary, kappa=0.3, damp_rel=1e-3, damp_abs=1e-12, pivot_min=1e-6, max_escalations=7,
-               barrier_beta=1e-2, sh_floor=1e-3, scale_floor=0.1, opac_ftb=0.995):
+def solve_opts(npix_primary, kappa=0.3, damp_rel=1e-3, damp_abs=1e-12, pivot_min=1e-3, max_escalations=7,
+               barrier_beta=1e-2, sh_floor=1e-3, scale_floor=0.1, opac_ftb=0.995, trust_pos=2.0, trust_rot=0.5,
+               trust_scale=0.5):
     return CSolveOpts(damp_rel, damp_abs, pivot_min, max_escalations, barrier_beta, sh_floor, scale_floor,
-                      opac_ftb, int(npix_primary), kappa)
+                      opac_ftb, int(npix_primary), kappa, trust_pos, trust_rot, trust_scale)
 
 
 def camera(c) -> CCamera:
@@ -204,6 +207,12 @@ class Frame:
         h = torch.zeros(3, H, W, dtype=torch.float32, device=self.ctx.device)
         self.ctx._check(lib().gsn_frame_loss_maps(self.ctx.h, self.h, _ptr(dL), _ptr(h)))
         return dL, h
+
+    def records(self, n):
+        """[12, n]: mx, my, q1, q2, cos, sin, sigma, colour (3), 0, 0 (see gsn_frame_records)."""
+        out = torch.zeros(3 * 4 * max(n, 1), dtype=torch.float32, device=self.ctx.device)
+        self.ctx._check(lib().gsn_frame_records(self.ctx.h, self.h, _ptr(out)))
+        return out[:12 * n].view(3, n, 4).permute(0, 2, 1).reshape(12, n)
 
     def zstats(self, n):
         out = torch.zeros(GSN_NZ * max(n, 1), dtype=torch.float32, device=self.ctx.device)

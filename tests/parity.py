@@ -10,7 +10,10 @@ from oracle import oracle as O
 TOL_IMAGE = 1e-5
 TOL_GRAD = 1e-5
 TOL_STEP = 1e-4
-MARGIN = 1e-4  # oracle pixels whose threshold decisions sit this close to a threshold are not compared
+# Oracle pixels whose threshold decisions (alpha_min, alpha_max, T_min) sit within this relative
+# distance of the threshold are not compared element-wise: ten times the single-precision error of
+# alpha and of the transmittance product, so the two sides may take such a decision differently.
+MARGIN = 1e-5
 
 
 def rel_inf(a, b):
@@ -54,29 +57,29 @@ def zstats_gpu_to_full(z):
 
 
 def blocks_gpu_to_oracle_view(blk, slot):
-    """GPU blocks rows [35 + 10 V][n] -> oracle per-view layout [n, 56] for one single-view accumulation."""
+    """GPU blocks rows [30 + 10 V][n] -> oracle per-view layout [n, 48] for one single-view accumulation."""
     n = blk.shape[1]
-    out = np.zeros((n, 56))
+    out = np.zeros((n, 48))
     out[:, 0:3] = blk[0:3].T
     out[:, 3:12] = sym_from_packed(blk[3:9], 3).reshape(n, 9)
-    out[:, 12:16] = blk[9:13].T
-    out[:, 16:32] = sym_from_packed(blk[13:23], 4).reshape(n, 16)
-    out[:, 32:35] = blk[23:26].T
-    out[:, 35:44] = sym_from_packed(blk[26:32], 3).reshape(n, 9)
-    out[:, 44] = blk[32]
-    out[:, 45] = blk[33]
-    vb = 35 + 10 * slot
-    out[:, 46] = blk[vb + 9]
-    out[:, 47:50] = blk[vb:vb + 3].T
-    out[:, 50:53] = blk[vb + 3:vb + 6].T
-    out[:, 53:56] = blk[vb + 6:vb + 9].T
+    out[:, 12:15] = blk[9:12].T
+    out[:, 15:24] = sym_from_packed(blk[12:18], 3).reshape(n, 9)
+    out[:, 24:27] = blk[18:21].T
+    out[:, 27:36] = sym_from_packed(blk[21:27], 3).reshape(n, 9)
+    out[:, 36] = blk[27]
+    out[:, 37] = blk[28]
+    vb = 30 + 10 * slot
+    out[:, 38] = blk[vb + 9]
+    out[:, 39:42] = blk[vb:vb + 3].T
+    out[:, 42:45] = blk[vb + 3:vb + 6].T
+    out[:, 45:48] = blk[vb + 6:vb + 9].T
     return out
 
 
 BLOCK_GROUPS = {
-    "g_p": slice(0, 3), "H_p": slice(3, 12), "g_q": slice(12, 16), "H_q": slice(16, 32),
-    "g_s": slice(32, 35), "H_s": slice(35, 44), "g_sigma": slice(44, 45), "H_sigma": slice(45, 46),
-    "coverage": slice(46, 47), "gamma": slice(47, 50), "s_colour": slice(50, 53),
+    "g_p": slice(0, 3), "H_p": slice(3, 12), "g_omega": slice(12, 15), "H_omega": slice(15, 24),
+    "g_s": slice(24, 27), "H_s": slice(27, 36), "g_sigma": slice(36, 37), "H_sigma": slice(37, 38),
+    "coverage": slice(38, 39), "gamma": slice(39, 42), "s_colour": slice(42, 45),
 }
 STEP_GROUPS = {"position": slice(0, 3), "rotation": slice(3, 4), "scale": slice(7, 10), "opacity": slice(10, 11)}
 
@@ -102,6 +105,7 @@ def gpu_view(ctx, gsn, dg, cam, target_t, lam, blocks, slot, keep=True):
                loss=loss.cpu().numpy(), pairs=fr.info()[0])
     if keep:
         out["z"] = fr.zstats(dg.n).cpu().numpy()
+        out["rec"] = fr.records(dg.n).cpu().numpy()
     fr.close()
     return out
 
@@ -136,3 +140,74 @@ def compare_binning(gv, ov, n):
 
 def pixel_mask(ov, margin=MARGIN):
     return ov["fr"].margin >= margin
+
+
+def near_threshold_kernels(fr, n, margin=MARGIN):
+    """Kernels composited (up to and including the stopping entry) at any pixel whose oracle
+    threshold decisions sit within `margin` of a threshold; their statistics may legitimately
+    differ between single- and double-precision compositing."""
+    bad = np.zeros(n, bool)
+    amb = fr.margin < margin
+    if fr.tile_start is None or not amb.any():
+        return bad
+    tx = (fr.cam.width + 15) // 16
+    for y, x in zip(*np.nonzero(amb)):
+        t = (y // 16) * tx + x // 16
+        lst = fr.ids[fr.tile_start[t]:fr.tile_start[t + 1]]
+        bad[lst[:int(fr.ncontrib[y, x]) + 1]] = True
+    return bad
+
+
+def zstats_to_frame(Z, fc, fs):
+    """Oracle statistics [n, 91] over (pi_x, pi_y, Q_xx, Q_xy, Q_yy, sigma, c~) -> the same in each
+    kernel's principal frame (pi' = V^T pi, Q' = V^T Q V, V = [[c, -s], [s, c]])."""
+    n = Z.shape[0]
+    g = Z[:, :9].copy()
+    H = Z[:, 9:90].reshape(n, 9, 9).copy()
+    L = np.zeros((n, 9, 9))
+    c, s = np.asarray(fc, np.float64), np.asarray(fs, np.float64)
+    L[:, 0, 0], L[:, 0, 1], L[:, 1, 0], L[:, 1, 1] = c, -s, s, c
+    # (Q_xx, Q_xy, Q_yy) = Lq (Q'_11, Q'_12, Q'_22) for Q = V Q' V^T
+    L[:, 2, 2], L[:, 2, 3], L[:, 2, 4] = c * c, -2 * c * s, s * s
+    L[:, 3, 2], L[:, 3, 3], L[:, 3, 4] = c * s, c * c - s * s, -c * s
+    L[:, 4, 2], L[:, 4, 3], L[:, 4, 4] = s * s, 2 * c * s, c * c
+    for i in range(5, 9):
+        L[:, i, i] = 1.0
+    gl = np.einsum("nij,ni->nj", L, g)
+    Hl = np.einsum("nia,nij,njb->nab", L, H, L)
+    out = Z.copy()
+    out[:, :9] = gl
+    out[:, 9:90] = Hl.reshape(n, 81)
+    return out
+
+
+def gpu_blocks_to_summed(gb, V):
+    """GPU blocks rows [30 + 10 V][n] -> the oracle's summed solve layout [n][39 + 10 V]."""
+    n = gb.shape[1]
+    S = np.zeros((n, 39 + 10 * V))
+    S[:, 0:3] = gb[0:3].T
+    S[:, 3:12] = sym_from_packed(gb[3:9], 3).reshape(n, 9)
+    S[:, 12:15] = gb[9:12].T
+    S[:, 15:24] = sym_from_packed(gb[12:18], 3).reshape(n, 9)
+    S[:, 24:27] = gb[18:21].T
+    S[:, 27:36] = sym_from_packed(gb[21:27], 3).reshape(n, 9)
+    S[:, 36], S[:, 37], S[:, 38] = gb[27], gb[28], gb[29]
+    for v in range(V):
+        S[:, 39 + 10 * v:49 + 10 * v] = gb[30 + 10 * v:40 + 10 * v].T
+    return S
+
+
+def step_sensitivity(g, cam, o, summed, V, rel=1e-5, trials=4, seed=0):
+    """Per kernel and group, the largest change of the oracle's step when its inputs carry
+    relative noise `rel` (the precision the blocks are required to have), divided by the
+    group's largest step: how precisely the step is determined by blocks of that accuracy."""
+    rng = np.random.default_rng(seed)
+    base, dec = O.solve(g, cam, o, summed, V)
+    dev = np.zeros((summed.shape[0], len(STEP_GROUPS) + 1))
+    for _ in range(trials):
+        noisy = summed * (1.0 + rel * rng.standard_normal(summed.shape))
+        st, _ = O.solve(g, cam, o, noisy, V)
+        for i, sl in enumerate(list(STEP_GROUPS.values()) + [slice(11, None)]):
+            den = max(np.max(np.abs(base[:, sl])), 1e-300)
+            dev[:, i] = np.maximum(dev[:, i], np.max(np.abs(st[:, sl] - base[:, sl]), axis=1) / den)
+    return dev

@@ -53,28 +53,46 @@ def loss_value(g, cam, tgt, o):
 
 GROUPS = {  # group -> (array name, slice of the block gradient, slice of the block Hessian, size)
     "p": ("pos", slice(0, 3), slice(3, 12), 3),
-    "q": ("rot", slice(12, 16), slice(16, 32), 4),
-    "s": ("scale", slice(32, 35), slice(35, 44), 3),
+    "w": ("rot", slice(12, 15), slice(15, 24), 3),  # left rotation vector: q <- exp(w/2) q
+    "s": ("scale", slice(24, 27), slice(27, 36), 3),
 }
 
 
-def param_ref(g, group, k, i):
-    arr = getattr(g, GROUPS[group][0]) if group in GROUPS else g.opac
-    return (arr, (i, k)) if group in GROUPS else (arr, (k,))
+def qmul(a, b):
+    return np.array([a[0] * b[0] - a[1] * b[1] - a[2] * b[2] - a[3] * b[3],
+                     a[0] * b[1] + a[1] * b[0] + a[2] * b[3] - a[3] * b[2],
+                     a[0] * b[2] + a[2] * b[0] + a[3] * b[1] - a[1] * b[3],
+                     a[0] * b[3] + a[3] * b[0] + a[1] * b[2] - a[2] * b[1]])
+
+
+def qexp(w):
+    """Unit quaternion of the rotation vector w (exact exponential map)."""
+    th = float(np.linalg.norm(w))
+    if th == 0.0:
+        return np.array([1.0, 0.0, 0.0, 0.0])
+    return np.concatenate([[math.cos(th / 2)], math.sin(th / 2) * np.asarray(w) / th])
+
+
+def perturbed(g, group, k, delta):
+    """Copy of g with kernel k's group moved by delta (rotation: q <- exp(delta/2) q)."""
+    g2 = g.copy()
+    if group == "w":
+        g2.rot[:, k] = qmul(qexp(delta), g.rot[:, k])
+    elif group in GROUPS:
+        getattr(g2, GROUPS[group][0])[:, k] += delta
+    else:
+        g2.opac[k] += delta[0]
+    return g2
 
 
 def fd_grad(g, cam, tgt, o, group, k, h=1e-6):
     n = GROUPS[group][3] if group in GROUPS else 1
     out = np.zeros(n)
     for i in range(n):
-        arr, idx = param_ref(g, group, k, i)
-        x0 = arr[idx]
-        arr[idx] = x0 + h
-        lp = loss_value(g, cam, tgt, o)
-        arr[idx] = x0 - h
-        lm = loss_value(g, cam, tgt, o)
-        arr[idx] = x0
-        out[i] = (lp - lm) / (2 * h)
+        e = np.zeros(n)
+        e[i] = h
+        out[i] = (loss_value(perturbed(g, group, k, e), cam, tgt, o)
+                  - loss_value(perturbed(g, group, k, -e), cam, tgt, o)) / (2 * h)
     return out
 
 
@@ -85,14 +103,10 @@ def fd_hess(g, cam, tgt, o, group, k, h=1e-4):
         for j in range(i, n):
             vals = []
             for si, sj in ((1, 1), (1, -1), (-1, 1), (-1, -1)):
-                ai, ii = param_ref(g, group, k, i)
-                aj, jj = param_ref(g, group, k, j)
-                xi, xj = ai[ii], aj[jj]
-                ai[ii] = xi + si * h
-                aj[jj] = aj[jj] + sj * h
-                vals.append(loss_value(g, cam, tgt, o))
-                ai[ii] = xi
-                aj[jj] = xj
+                d = np.zeros(n)
+                d[i] += si * h
+                d[j] += sj * h
+                vals.append(loss_value(perturbed(g, group, k, d), cam, tgt, o))
             out[i, j] = out[j, i] = (vals[0] - vals[1] - vals[2] + vals[3]) / (4 * h * h)
     return out
 
@@ -343,9 +357,9 @@ def test_block_gradients_by_finite_differences(fd_setup, lam):
             fd = fd_grad(g, cam, tgt, o, grp, k)
             assert rel_err(B[k, gs], fd) < 1e-6, (k, grp)
         fd = fd_grad(g, cam, tgt, o, "o", k)
-        assert rel_err(B[k, 44:45], fd) < 1e-6
+        assert rel_err(B[k, 36:37], fd) < 1e-6
         # SH: dL/dc_{ch,i} = gamma_ch Y_i(r)
-        Y = O.sh_basis(g.K, B[k, 53:56])
+        Y = O.sh_basis(g.K, B[k, 45:48])
         for ch in range(3):
             for i in range(g.K):
                 h = 1e-6
@@ -355,7 +369,7 @@ def test_block_gradients_by_finite_differences(fd_setup, lam):
                 g.sh[ch, i, k] = x0 - h
                 lm = loss_value(g, cam, tgt, o)
                 g.sh[ch, i, k] = x0
-                assert B[k, 47 + ch] * Y[i] == pytest.approx((lp - lm) / (2 * h), rel=1e-6, abs=1e-11)
+                assert B[k, 39 + ch] * Y[i] == pytest.approx((lp - lm) / (2 * h), rel=1e-6, abs=1e-11)
 
 
 def test_block_hessians_by_finite_differences_l2(fd_setup):
@@ -370,9 +384,9 @@ def test_block_hessians_by_finite_differences_l2(fd_setup):
             Hb = B[k, hs].reshape(n, n)
             assert np.allclose(Hb, Hb.T, rtol=0, atol=1e-12 * np.max(np.abs(Hb)))
             assert rel_err(Hb, fd) < 1e-5, (k, grp)
-        assert rel_err(B[k, 45:46], fd_hess(g, cam, tgt, o, "o", k).ravel()) < 1e-5
+        assert rel_err(B[k, 37:38], fd_hess(g, cam, tgt, o, "o", k).ravel()) < 1e-5
         # SH: L2 is quadratic in the coefficients, H = s Y Y^T exactly
-        Y = O.sh_basis(g.K, B[k, 53:56])
+        Y = O.sh_basis(g.K, B[k, 45:48])
         h = 0.1  # exactly quadratic: a large step has no truncation error and little roundoff
         for ch in range(3):
             x0 = g.sh[ch, 1, k]
@@ -381,7 +395,7 @@ def test_block_hessians_by_finite_differences_l2(fd_setup):
                 g.sh[ch, 1, k] = x0 + d
                 vals.append(loss_value(g, cam, tgt, o))
             g.sh[ch, 1, k] = x0
-            assert (vals[0] - 2 * vals[1] + vals[2]) / h ** 2 == pytest.approx(B[k, 50 + ch] * Y[1] ** 2, rel=1e-6)
+            assert (vals[0] - 2 * vals[1] + vals[2]) / h ** 2 == pytest.approx(B[k, 42 + ch] * Y[1] ** 2, rel=1e-6)
 
 
 def test_block_hessians_compose_image_derivatives_with_loss_maps(fd_setup):
@@ -497,7 +511,7 @@ def test_zero_gradient_at_ground_truth():
     _, dL, hd = O.loss(fr.img, tgt, 0.2)
     assert np.max(np.abs(dL)) < 1e-15
     B = O.blocks(cfg.gt, fr, dL, hd)
-    for sl in (slice(0, 3), slice(12, 16), slice(32, 35), slice(44, 45), slice(47, 50)):
+    for sl in (slice(0, 3), slice(12, 15), slice(24, 27), slice(36, 37), slice(39, 42)):
         assert np.max(np.abs(B[:, sl])) < 1e-14
 
 
@@ -583,9 +597,11 @@ def test_reduced_steps_satisfy_their_damped_newton_equations():
         Hp = S[k, 3:12].reshape(3, 3)
         dp = st[k, 0:3]
         assert abs(r @ dp) < 1e-12 * max(1.0, np.linalg.norm(dp))
-        # mu is damp_rel * mean diag of U^T H U = damp_rel * trace(P H)/2, escalated by 10^j
-        mu0 = 1e-3 * max(np.trace(P @ Hp) / 2, 0) + 1e-12 / (3 * 32 * 28)
+        # mu0 = damp_rel |U^T H U|_F / sqrt(2) (= |P H P|_F / sqrt(2), basis-free), escalated by 10^j
+        mu0 = 1e-3 * np.linalg.norm(P @ Hp @ P) / np.sqrt(2) + 1e-12 / (3 * 32 * 28)
         mu = mu0 * 10.0 ** dec[k, 0]
+        if np.linalg.norm(dp) >= 2.0 * g.scale[:, k].max() * (1 - 1e-12):
+            continue  # clamped to the trust radius
         resid = P @ (Hp @ dp + mu * dp + S[k, 0:3])
         assert np.linalg.norm(resid) < 1e-9 * (np.linalg.norm(P @ S[k, 0:3]) + 1e-300)
 
@@ -601,13 +617,13 @@ def test_colour_step_lies_in_span_of_view_bases_and_matches_pinv():
     for k in range(g.n):
         if res["dec"][k, 0] == -2 or res["dec"][k, 4] < 2:
             continue
-        Ys = [O.sh_basis(16, S[k, 47 + 10 * v + 6:47 + 10 * v + 9]) for v in range(2)]
+        Ys = [O.sh_basis(16, S[k, 39 + 10 * v + 6:39 + 10 * v + 9]) for v in range(2)]
         Bm = np.stack(Ys)
         for ch in range(3):
-            svals = np.array([S[k, 47 + 10 * v + 3 + ch] for v in range(2)])
+            svals = np.array([S[k, 39 + 10 * v + 3 + ch] for v in range(2)])
             sfl = np.maximum(np.abs(svals), 1e-3 * np.max(np.abs(svals)))
             G = Bm.T @ np.diag(sfl) @ Bm
-            gg = Bm.T @ np.array([S[k, 47 + 10 * v + ch] for v in range(2)])
+            gg = Bm.T @ np.array([S[k, 39 + 10 * v + ch] for v in range(2)])
             assert np.linalg.matrix_rank(G, tol=1e-10 * np.max(np.abs(G))) <= 2
             d = st[k, 11 + ch * 16:11 + (ch + 1) * 16]
             assert np.allclose(d, -np.linalg.pinv(G, rcond=1e-12) @ gg, rtol=1e-4,
@@ -667,9 +683,9 @@ def test_opacity_barrier_newton_closed_form():
         if dec[k, 3] < 0:
             continue
         s = g.opac[k]
-        H = S[k, 45] + a * (1 / s ** 2 + 1 / (1 - s) ** 2)
-        gg = S[k, 44] + a * (1 / (1 - s) - 1 / s)
-        mu = (1e-3 * max(H, 0) + 1e-12 / (3 * 32 * 28)) * 10.0 ** dec[k, 3]
+        H = S[k, 37] + a * (1 / s ** 2 + 1 / (1 - s) ** 2)
+        gg = S[k, 36] + a * (1 / (1 - s) - 1 / s)
+        mu = (1e-3 * abs(H) + 1e-12 / (3 * 32 * 28)) * 10.0 ** dec[k, 3]
         assert st[k, 10] == pytest.approx(-gg / (H + mu), rel=1e-12)
         new = res["new"].opac[k]
         assert 0 < new < 1
