@@ -257,6 +257,40 @@ gsn_status gsn_frame_records(gsn_ctx* ctx, const gsn_frame* frame, float* d_out)
  * ([3][H][W] floats each) of the last gsn_accumulate_hessian on this frame. */
 gsn_status gsn_frame_loss_maps(gsn_ctx* ctx, const gsn_frame* frame, float* d_dL, float* d_h);
 
+/* ------------------------------------------------------------ measurement */
+
+/* Stages timed by the profiler. */
+typedef enum {
+    GSN_STAGE_PROJECT = 0,     /* per-kernel projection and binning decisions */
+    GSN_STAGE_SORT = 1,        /* depth sort, pair emission, tile partition, ranges */
+    GSN_STAGE_RASTER_FWD = 2,  /* forward compositing */
+    GSN_STAGE_LOSS = 3,        /* loss value and per-pixel derivative maps */
+    GSN_STAGE_RASTER_BWD = 4,  /* backward compositing and per-tile statistics */
+    GSN_STAGE_CHAIN = 5,       /* per-kernel reduction and chain rule */
+    GSN_STAGE_SOLVE = 6,       /* local Newton solves */
+    GSN_STAGE_APPLY = 7,       /* parameter update */
+    GSN_STAGE_COUNT = 8
+} gsn_stage;
+
+/* Work counters gathered while profiling. */
+typedef enum {
+    GSN_COUNT_FWD_EVALS = 0,   /* (pixel, list entry) evaluations in the forward pass */
+    GSN_COUNT_BWD_EVALS = 1,   /* (pixel, list entry) evaluations in the backward pass */
+    GSN_COUNT_BWD_ACTIVE = 2,  /* of which contributed (alpha >= alpha_min) */
+    GSN_COUNT_PAIRS = 3,       /* (tile, kernel) pairs binned */
+    GSN_COUNT_N = 4
+} gsn_counter;
+
+/* Turns stage timing on or off and clears what was accumulated.  While on,
+ * every stage is bracketed by HIP events on the context's stream (a few
+ * microseconds of overhead per stage) and the raster passes count their work. */
+gsn_status gsn_profile_enable(gsn_ctx* ctx, int32_t on);
+/* Synchronises the stream and returns, per stage, the summed event time in
+ * milliseconds (h_ms[GSN_STAGE_COUNT]) and the number of timed launches
+ * (h_launches[GSN_STAGE_COUNT]), and the work counters
+ * (h_counts[GSN_COUNT_N]).  Any pointer may be NULL. */
+gsn_status gsn_profile_read(gsn_ctx* ctx, double* h_ms, int64_t* h_launches, int64_t* h_counts);
+
 #ifdef __cplusplus
 }
 #endif

@@ -11,7 +11,7 @@ CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libgsn.so")
 SOURCES = ["api.hip", "render.hip", "loss.hip", "backward.hip", "solve.hip"]
-HEADERS = ["device_common.h", "gsn_internal.h"]
+HEADERS = ["device_common.h", "gsn_internal.h", "chain.h"]
 ARCH = os.environ.get("GSN_OFFLOAD_ARCH", "gfx950")
 
 FLAGS = [

@@ -36,6 +36,27 @@ void buf_free(DevBuf& b) {
     b.bytes = 0;
 }
 
+StageTimer::StageTimer(gsn_ctx* c, int stage) : ctx(c) {
+    if (!ctx || !ctx->prof) return;
+    ProfRec r;
+    r.stage = stage;
+    for (hipEvent_t* e : {&r.start, &r.stop}) {
+        if (!ctx->pool.empty()) {
+            *e = ctx->pool.back();
+            ctx->pool.pop_back();
+        } else if (hipEventCreate(e) != hipSuccess) {
+            return;
+        }
+    }
+    if (hipEventRecord(r.start, ctx->stream) != hipSuccess) return;
+    ctx->recs.push_back(r);
+    idx = (int)ctx->recs.size() - 1;
+}
+
+StageTimer::~StageTimer() {
+    if (idx >= 0) (void)hipEventRecord(ctx->recs[idx].stop, ctx->stream);
+}
+
 namespace {
 
 gsn_status fail(gsn_ctx* ctx, gsn_status st, const char* fmt, ...) __attribute__((format(printf, 3, 4)));
@@ -116,7 +137,59 @@ gsn_status gsn_create(gsn_ctx** out, int32_t device, void* hip_stream) {
 }
 
 gsn_status gsn_destroy(gsn_ctx* ctx) {
+    if (!ctx) return GSN_OK;
+    (void)hipSetDevice(ctx->device);
+    (void)hipStreamSynchronize(ctx->stream);
+    for (const ProfRec& r : ctx->recs) {
+        (void)hipEventDestroy(r.start);
+        (void)hipEventDestroy(r.stop);
+    }
+    for (hipEvent_t e : ctx->pool) (void)hipEventDestroy(e);
+    if (ctx->d_counts) (void)hipFree(ctx->d_counts);
     delete ctx;
+    return GSN_OK;
+}
+
+gsn_status gsn_profile_enable(gsn_ctx* ctx, int32_t on) {
+    if (!ctx) return GSN_E_INVALID;
+    HIP_TRY(ctx, hipSetDevice(ctx->device));
+    HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+    for (const ProfRec& r : ctx->recs) {
+        ctx->pool.push_back(r.start);
+        ctx->pool.push_back(r.stop);
+    }
+    ctx->recs.clear();
+    ctx->pairs_counted = 0;
+    if (on && !ctx->d_counts)
+        HIP_TRY(ctx, hipMalloc((void**)&ctx->d_counts, GSN_COUNT_N * sizeof(unsigned long long)));
+    if (ctx->d_counts) launch_fill_u32(reinterpret_cast<uint32_t*>(ctx->d_counts), 0u, 2 * GSN_COUNT_N, ctx->stream);
+    HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+    ctx->prof = on != 0;
+    return GSN_OK;
+}
+
+gsn_status gsn_profile_read(gsn_ctx* ctx, double* h_ms, int64_t* h_launches, int64_t* h_counts) {
+    if (!ctx) return GSN_E_INVALID;
+    HIP_TRY(ctx, hipSetDevice(ctx->device));
+    HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+    double ms[GSN_STAGE_COUNT] = {0};
+    int64_t nl[GSN_STAGE_COUNT] = {0};
+    for (const ProfRec& r : ctx->recs) {
+        float t = 0.f;
+        HIP_TRY(ctx, hipEventElapsedTime(&t, r.start, r.stop));
+        ms[r.stage] += t;
+        nl[r.stage] += 1;
+    }
+    for (int i = 0; i < GSN_STAGE_COUNT; ++i) {
+        if (h_ms) h_ms[i] = ms[i];
+        if (h_launches) h_launches[i] = nl[i];
+    }
+    if (h_counts) {
+        unsigned long long c[GSN_COUNT_N] = {0};
+        if (ctx->d_counts) HIP_TRY(ctx, hipMemcpy(c, ctx->d_counts, sizeof c, hipMemcpyDeviceToHost));
+        for (int i = 0; i < GSN_COUNT_N; ++i) h_counts[i] = (int64_t)c[i];
+        h_counts[GSN_COUNT_PAIRS] = ctx->pairs_counted;
+    }
     return GSN_OK;
 }
 
@@ -202,20 +275,26 @@ gsn_status gsn_render(gsn_ctx* ctx, const gsn_gaussians* g, const gsn_camera* ca
     HIP_TRY(ctx, buf_reserve(f->hist, (size_t)256 * ((nn + 4095) / 4096) * 8));
     HIP_TRY(ctx, buf_reserve(f->scan_tmp, scan_tmp_bytes((uint32_t)nn)));
     uint32_t* d_total = bp<uint32_t>(f->total);
-    // 1. projection and binning decisions
-    launch_preprocess(*g, f->cam, f->ro, bp<float4>(f->rec), bp<uint2>(f->rect), bp<uint32_t>(f->keys_a),
-                      bp<uint32_t>(f->ids_a), bp<uint32_t>(f->ntiles), s);
-    HIP_TRY(ctx, hipGetLastError());
-    // 2. depth order of the kernels: stable radix sort of (depth bits, id)
-    HIP_TRY(ctx, radix_sort_pairs(bp<uint32_t>(f->keys_a), bp<uint32_t>(f->ids_a), bp<uint32_t>(f->keys_b),
-                                  bp<uint32_t>(f->ids_b), (uint32_t)n, 0, 32, f->hist, f->scan_tmp, s));
-    // 3. pair offsets in depth order
-    launch_gather_u32(bp<uint32_t>(f->ntiles), bp<uint32_t>(f->ids_a), bp<uint32_t>(f->keys_b), (uint32_t)n, s);
-    if (n > 0) {
-        HIP_TRY(ctx, exclusive_scan_u32(bp<uint32_t>(f->keys_b), bp<uint32_t>(f->offsets), (uint32_t)n, d_total,
-                                        f->scan_tmp, s));
-    } else {
-        launch_fill_u32(d_total, 0u, 1, s);
+    {
+        // 1. projection and binning decisions
+        StageTimer st_(ctx, GSN_STAGE_PROJECT);
+        launch_preprocess(*g, f->cam, f->ro, bp<float4>(f->rec), bp<uint2>(f->rect), bp<uint32_t>(f->keys_a),
+                          bp<uint32_t>(f->ids_a), bp<uint32_t>(f->ntiles), s);
+        HIP_TRY(ctx, hipGetLastError());
+    }
+    {
+        // 2. depth order of the kernels: stable radix sort of (depth bits, id)
+        StageTimer st_(ctx, GSN_STAGE_SORT);
+        HIP_TRY(ctx, radix_sort_pairs(bp<uint32_t>(f->keys_a), bp<uint32_t>(f->ids_a), bp<uint32_t>(f->keys_b),
+                                      bp<uint32_t>(f->ids_b), (uint32_t)n, 0, 32, f->hist, f->scan_tmp, s));
+        // 3. pair offsets in depth order
+        launch_gather_u32(bp<uint32_t>(f->ntiles), bp<uint32_t>(f->ids_a), bp<uint32_t>(f->keys_b), (uint32_t)n, s);
+        if (n > 0) {
+            HIP_TRY(ctx, exclusive_scan_u32(bp<uint32_t>(f->keys_b), bp<uint32_t>(f->offsets), (uint32_t)n, d_total,
+                                            f->scan_tmp, s));
+        } else {
+            launch_fill_u32(d_total, 0u, 1, s);
+        }
     }
     HIP_TRY(ctx, hipMemcpyAsync(f->h_total, d_total, 4, hipMemcpyDeviceToHost, s));
     HIP_TRY(ctx, hipStreamSynchronize(s));
@@ -229,20 +308,28 @@ gsn_status gsn_render(gsn_ctx* ctx, const gsn_gaussians* g, const gsn_camera* ca
     HIP_TRY(ctx, buf_reserve(f->pv_a, pp * 4));
     HIP_TRY(ctx, buf_reserve(f->pk_b, pp * 4));
     HIP_TRY(ctx, buf_reserve(f->pv_b, pp * 4));
-    // 4. pairs in depth order, then a stable partition by tile id
-    launch_emit_pairs(bp<uint32_t>(f->ids_a), bp<uint32_t>(f->offsets), (uint32_t)n, bp<uint2>(f->rect),
-                      (uint32_t)f->tiles_x, bp<uint32_t>(f->pk_a), bp<uint32_t>(f->pv_a), bp<uint32_t>(f->pair_off),
-                      s);
-    int tile_bits = 1;
-    while ((1ull << tile_bits) < tiles) ++tile_bits;
-    HIP_TRY(ctx, radix_sort_pairs(bp<uint32_t>(f->pk_a), bp<uint32_t>(f->pv_a), bp<uint32_t>(f->pk_b),
-                                  bp<uint32_t>(f->pv_b), P, 0, tile_bits, f->hist, f->scan_tmp, s));
-    launch_fill_u32(bp<uint32_t>(f->ranges), 0u, 2 * tiles, s);
-    launch_tile_ranges(bp<uint32_t>(f->pk_a), P, bp<uint2>(f->ranges), s);
-    // 5. front-to-back compositing
-    launch_raster_fwd(bp<uint2>(f->ranges), bp<uint32_t>(f->pv_a), bp<float4>(f->rec), (uint32_t)n, f->cam, f->ro,
-                      bp<float>(f->img), bp<double>(f->img64), bp<float>(f->Tfin), bp<uint32_t>(f->ncontrib), s);
-    HIP_TRY(ctx, hipGetLastError());
+    {
+        // 4. pairs in depth order, then a stable partition by tile id
+        StageTimer st_(ctx, GSN_STAGE_SORT);
+        launch_emit_pairs(bp<uint32_t>(f->ids_a), bp<uint32_t>(f->offsets), (uint32_t)n, bp<uint2>(f->rect),
+                          (uint32_t)f->tiles_x, bp<uint32_t>(f->pk_a), bp<uint32_t>(f->pv_a),
+                          bp<uint32_t>(f->pair_off), s);
+        int tile_bits = 1;
+        while ((1ull << tile_bits) < tiles) ++tile_bits;
+        HIP_TRY(ctx, radix_sort_pairs(bp<uint32_t>(f->pk_a), bp<uint32_t>(f->pv_a), bp<uint32_t>(f->pk_b),
+                                      bp<uint32_t>(f->pv_b), P, 0, tile_bits, f->hist, f->scan_tmp, s));
+        launch_fill_u32(bp<uint32_t>(f->ranges), 0u, 2 * tiles, s);
+        launch_tile_ranges(bp<uint32_t>(f->pk_a), P, bp<uint2>(f->ranges), s);
+    }
+    if (ctx->prof) ctx->pairs_counted += P;
+    {
+        // 5. front-to-back compositing
+        StageTimer st_(ctx, GSN_STAGE_RASTER_FWD);
+        launch_raster_fwd(bp<uint2>(f->ranges), bp<uint32_t>(f->pv_a), bp<float4>(f->rec), (uint32_t)n, f->cam,
+                          f->ro, bp<float>(f->img), bp<double>(f->img64), bp<float>(f->Tfin),
+                          bp<uint32_t>(f->ncontrib), prof_counts(ctx), s);
+        HIP_TRY(ctx, hipGetLastError());
+    }
     if (d_rgb_out) HIP_TRY(ctx, hipMemcpyAsync(d_rgb_out, f->img.p, 3 * npx * 4, hipMemcpyDeviceToDevice, s));
     if (d_T_out) HIP_TRY(ctx, hipMemcpyAsync(d_T_out, f->Tfin.p, npx * 4, hipMemcpyDeviceToDevice, s));
     f->rendered = true;
@@ -269,22 +356,31 @@ gsn_status gsn_accumulate_hessian(gsn_ctx* ctx, const gsn_gaussians* g, const gs
     HIP_TRY(ctx, buf_reserve(f->coef, 24 * npx * 8));
     const int nparts = ((f->W + 15) / 16) * ((f->H + 15) / 16) * 3;
     HIP_TRY(ctx, buf_reserve(f->loss_part, (size_t)2 * nparts * sizeof(double)));
-    int np_out = 0;
-    launch_loss_maps(bp<float>(f->img), d_target, f->W, f->H, opts->lambda_ssim, bp<double>(f->coef),
-                     bp<float>(f->dL), bp<float>(f->hd), bp<double>(f->loss_part), &np_out, s);
-    if (d_loss_out) launch_loss_reduce(bp<double>(f->loss_part), np_out, f->W, f->H, d_loss_out, s);
-    HIP_TRY(ctx, hipGetLastError());
+    {
+        StageTimer st_(ctx, GSN_STAGE_LOSS);
+        int np_out = 0;
+        launch_loss_maps(bp<float>(f->img), d_target, f->W, f->H, opts->lambda_ssim, bp<double>(f->coef),
+                         bp<float>(f->dL), bp<float>(f->hd), bp<double>(f->loss_part), &np_out, s);
+        if (d_loss_out) launch_loss_reduce(bp<double>(f->loss_part), np_out, f->W, f->H, d_loss_out, s);
+        HIP_TRY(ctx, hipGetLastError());
+    }
     const size_t pp = std::max<size_t>((size_t)f->pairs, 1);
     HIP_TRY(ctx, buf_reserve(f->partial, pp * GSN_NZ * 4));
     HIP_TRY(ctx, buf_reserve(f->flags, (pp + 3) / 4 * 4));
-    launch_fill_u32(bp<uint32_t>(f->flags), 0u, (pp + 3) / 4, s);
-    if (f->pairs > 0) launch_raster_bwd(*f, bp<float>(f->dL), bp<float>(f->hd), s);
     float* zs = nullptr;
     if (opts->keep_zstats) {
         HIP_TRY(ctx, buf_reserve(f->zstats, (size_t)std::max(f->n, 1) * GSN_NZ * 4));
         zs = bp<float>(f->zstats);
     }
-    launch_reduce_chain(*f, *g, opts->weight, view_slot, *b, zs, s);
+    {
+        StageTimer st_(ctx, GSN_STAGE_RASTER_BWD);
+        launch_fill_u32(bp<uint32_t>(f->flags), 0u, (pp + 3) / 4, s);
+        if (f->pairs > 0) launch_raster_bwd(*f, bp<float>(f->dL), bp<float>(f->hd), prof_counts(ctx), s);
+    }
+    {
+        StageTimer st_(ctx, GSN_STAGE_CHAIN);
+        launch_reduce_chain(*f, *g, opts->weight, view_slot, *b, zs, s);
+    }
     HIP_TRY(ctx, hipGetLastError());
     return GSN_OK;
 }
@@ -302,6 +398,7 @@ gsn_status gsn_local_newton_solve(gsn_ctx* ctx, const gsn_gaussians* g, const gs
     if (o->npix_primary <= 0 || o->max_escalations < 0 || o->max_escalations > 30)
         return fail(ctx, GSN_E_INVALID, "solve option out of range");
     HIP_TRY(ctx, hipSetDevice(ctx->device));
+    StageTimer st_(ctx, GSN_STAGE_SOLVE);
     launch_solve(*g, make_devcam(*primary), o->kappa, *b, *o, *st, ctx->stream);
     HIP_TRY(ctx, hipGetLastError());
     return GSN_OK;
@@ -314,6 +411,7 @@ gsn_status gsn_apply_step(gsn_ctx* ctx, gsn_gaussians* g, const gsn_steps* st, c
     if (r != GSN_OK) return r;
     if (st->n != g->n || st->sh_degree != g->sh_degree) return fail(ctx, GSN_E_SHAPE, "steps do not match gaussians");
     HIP_TRY(ctx, hipSetDevice(ctx->device));
+    StageTimer st_(ctx, GSN_STAGE_APPLY);
     launch_apply(*g, *st, *o, group_mask, ctx->stream);
     HIP_TRY(ctx, hipGetLastError());
     return GSN_OK;

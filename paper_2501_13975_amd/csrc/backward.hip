@@ -23,10 +23,10 @@
 // and colour needs.
 //
 // raster_bwd: one 256-thread workgroup per tile re-traverses the tile's
-// depth-ordered list front to back with the forward pass's decisions,
-// computes each pixel's contribution to the 44 statistics of the current
-// splat, reduces them across the wave by shuffles and across the four waves in
-// LDS, and writes the tile's partial sum at the (tile, kernel) pair's slot.
+// depth-ordered list front to back with the forward pass's decisions, stages
+// the contributing (pixel, splat) pairs of each round in LDS, and sums each
+// splat's 44 statistics over its pairs (see raster_bwd_kernel); the tile's
+// partial sum is written at the (tile, kernel) pair's slot.
 // reduce_chain: one thread per kernel sums its pair slots in a fixed order (no
 // atomics: results are deterministic), then applies the chain rule through the
 // projection with second-order jets and adds the attribute blocks.
@@ -35,47 +35,103 @@
 
 namespace {
 
-constexpr int SB = 16;  // list entries reduced per LDS round
+constexpr int BS = 32;      // list entries examined per round
+constexpr int PMAX = 2048;  // active (pixel, entry) pairs staged per round
+constexpr int GRP = 8;      // threads that sum one entry's pairs
 
-__device__ __forceinline__ float wave_sum(float v) {
+// Contribution of one active (pixel, splat) pair to the 44 statistics (see the header comment).
+__device__ __forceinline__ void pair_terms(const float4 a, const float4 b, float G, float T, const float av[3],
+                                           float dx, float dy, const float dl[3], const float hh[3], float amax,
+                                           float* z) {
+    const float sig = b.z, q1 = a.z, q2 = a.w;
+    const float sGraw = sig * G;
+    const bool clamped = sGraw > amax;
+    const float al = clamped ? amax : sGraw;
+    const float wT = al * T;
+    const float A1 = dl[0] * av[0] + dl[1] * av[1] + dl[2] * av[2];
+    const float A2 = hh[0] * av[0] * av[0] + hh[1] * av[1] * av[1] + hh[2] * av[2] * av[2];
 #pragma unroll
-    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
-    return v;
+    for (int f = 0; f < GSN_NZ; ++f) z[f] = 0.f;
+#pragma unroll
+    for (int ch = 0; ch < 3; ++ch) {
+        z[6 + ch] = dl[ch] * wT;
+        z[39 + ch] = hh[ch] * wT * wT;
+    }
+    z[43] = wT;
+    if (clamped) return;
+    const float u[5] = {-q1 * dx, -q2 * dy, -0.5f * dx * dx, -dx * dy, -0.5f * dy * dy};
+    const float k1 = A1 * sGraw;
+    const float k2 = A2 * sGraw * sGraw + k1;
+#pragma unroll
+    for (int i = 0; i < 5; ++i) z[i] = k1 * u[i];
+    z[5] = A1 * G;
+    // H_ww: k2 u u^T + k1 d2f, d2f has -Q' on (pi', pi') and -d' on (pi', Q')
+    int idx = 9;
+#pragma unroll
+    for (int i = 0; i < 5; ++i)
+#pragma unroll
+        for (int j = i; j < 5; ++j, ++idx) z[idx] = k2 * u[i] * u[j];
+    z[9 + 0] -= k1 * q1;  // (pi'_1, pi'_1)
+    z[9 + 2] -= k1 * dx;  // (pi'_1, Q'_11)
+    z[9 + 3] -= k1 * dy;  // (pi'_1, Q'_12)
+    z[9 + 5] -= k1 * q2;  // (pi'_2, pi'_2)
+    z[9 + 7] -= k1 * dx;  // (pi'_2, Q'_12)
+    z[9 + 8] -= k1 * dy;  // (pi'_2, Q'_22)
+#pragma unroll
+    for (int ch = 0; ch < 3; ++ch) {
+        const float bch = sGraw * T * (hh[ch] * av[ch] * al + dl[ch]);
+#pragma unroll
+        for (int i = 0; i < 5; ++i) z[24 + i * 3 + ch] = bch * u[i];
+    }
+    z[42] = A2 * G * G;
 }
 
+// One workgroup per tile.  Each round examines up to BS list entries:
+//  (a) every pixel evaluates which of them it composited (alpha >= alpha_min and
+//      before its stopping entry) -> one ballot mask per (entry, wave);
+//  (b) a scan over (entry, wave) gives every active (pixel, entry) pair a slot in
+//      LDS; the round keeps the longest prefix of entries whose pairs fit;
+//  (c) every pixel walks its active entries front to back (transmittance, colour
+//      behind the splat) and stores (T, G, a_R, a_G, a_B) in the pair's slot;
+//  (d) GRP threads per entry sum the 44 statistics over that entry's pairs in
+//      double, in pixel order, and write the tile's partial sum at the
+//      (tile, kernel) pair's slot.  Only contributing pairs do the 44-term work.
 __global__ __launch_bounds__(GSN_BLOCK) void raster_bwd_kernel(
     const uint2* __restrict__ ranges, const uint32_t* __restrict__ ids, const float4* __restrict__ rec,
     const uint2* __restrict__ rect, const uint32_t* __restrict__ pair_off, uint32_t n, DevCam cam, DevRenderOpts ro,
     const double* __restrict__ img64, const uint32_t* __restrict__ ncontrib, const float* __restrict__ dLm,
-    const float* __restrict__ hdm, float* __restrict__ partial, uint8_t* __restrict__ flags) {
-    __shared__ float4 s_a[GSN_BLOCK];
-    __shared__ float4 s_b[GSN_BLOCK];
-    __shared__ float2 s_c[GSN_BLOCK];
-    __shared__ uint32_t s_slot[GSN_BLOCK];
-    __shared__ float red[SB][GSN_BLOCK / 64][GSN_NZ];
-    __shared__ uint32_t s_act[SB][GSN_BLOCK / 64];
-    __shared__ uint32_t s_max;
+    const float* __restrict__ hdm, float* __restrict__ partial, uint8_t* __restrict__ flags,
+    unsigned long long* __restrict__ counts) {
+    __shared__ float4 r_a[BS], r_b[BS];
+    __shared__ float4 r_c[BS];
+    __shared__ uint32_t r_slot[BS];
+    __shared__ float s_dl[3][GSN_BLOCK], s_h[3][GSN_BLOCK];
+    __shared__ uint64_t s_mask[BS][GSN_BLOCK / 64];
+    __shared__ uint32_t s_off[BS * (GSN_BLOCK / 64) + 1];
+    __shared__ float4 s_pa[PMAX];
+    __shared__ float s_pb[PMAX];
+    __shared__ uint8_t s_pix[PMAX];
+    __shared__ uint32_t s_max, s_J;
+    const int tid = threadIdx.x;
     const int tile = blockIdx.x;
     const int tx = tile % cam.tiles_x, ty = tile / cam.tiles_x;
-    const int px = tx * GSN_TILE + (threadIdx.x % GSN_TILE);
-    const int py = ty * GSN_TILE + (threadIdx.x / GSN_TILE);
+    const int px = tx * GSN_TILE + (tid % GSN_TILE);
+    const int py = ty * GSN_TILE + (tid / GSN_TILE);
     const bool inside = px < cam.W && py < cam.H;
-    const int lane = __lane_id(), wave = threadIdx.x / 64;
+    const int lane = __lane_id(), wave = tid / 64;
+    const uint64_t lt_mask = lane == 0 ? 0ull : (~0ull >> (64 - lane));
     const uint2 rg = ranges[tile];
     const size_t np = (size_t)cam.W * cam.H, pi = (size_t)py * cam.W + px;
     double cf[3] = {0, 0, 0};
-    float dl[3] = {0, 0, 0}, hh[3] = {0, 0, 0};
     uint32_t nc = 0;
-    if (inside) {
 #pragma unroll
-        for (int ch = 0; ch < 3; ++ch) {
-            cf[ch] = img64[ch * np + pi];
-            dl[ch] = dLm[ch * np + pi];
-            hh[ch] = hdm[ch * np + pi];
-        }
-        nc = ncontrib[pi];
+    for (int ch = 0; ch < 3; ++ch) {
+        s_dl[ch][tid] = inside ? dLm[ch * np + pi] : 0.f;
+        s_h[ch][tid] = inside ? hdm[ch * np + pi] : 0.f;
+        if (inside) cf[ch] = img64[ch * np + pi];
     }
-    if (threadIdx.x == 0) s_max = 0;
+    if (inside) nc = ncontrib[pi];
+    if (tid == 0) s_max = 0;
     __syncthreads();
     {
         uint32_t m = nc;
@@ -85,113 +141,133 @@ __global__ __launch_bounds__(GSN_BLOCK) void raster_bwd_kernel(
     }
     __syncthreads();
     const uint32_t end = rg.x + s_max;
-    // front-to-back sums in double, in the same order as the forward pass, so that the colour
-    // behind a splat, S = c - sum(front..k), carries no cancellation error
     float T = 1.f;
     double Ca0 = 0.0, Ca1 = 0.0, Ca2 = 0.0;
     const float fpx = (float)px, fpy = (float)py;
-    for (uint32_t base = rg.x; base < end; base += GSN_BLOCK) {
-        const uint32_t e = base + threadIdx.x;
-        if (e < end) {
-            const uint32_t id = ids[e];
-            s_a[threadIdx.x] = rec[id];
-            s_b[threadIdx.x] = rec[n + id];
-            const float4 c4 = rec[2 * (size_t)n + id];
-            s_c[threadIdx.x] = make_float2(c4.x, c4.y);
+    uint32_t n_eval = 0, n_act = 0;
+    for (uint32_t pos = rg.x; pos < end;) {
+        const int cnt = (int)min((uint32_t)BS, end - pos);
+        if (tid < cnt) {
+            const uint32_t id = ids[pos + tid];
+            r_a[tid] = rec[id];
+            r_b[tid] = rec[n + id];
+            r_c[tid] = rec[2 * (size_t)n + id];
             const uint2 rc = rect[id];
             const uint32_t x0 = rc.x & 0xffffu, y0 = rc.x >> 16, x1 = rc.y & 0xffffu;
-            s_slot[threadIdx.x] = pair_off[id] + ((uint32_t)ty - y0) * (x1 - x0) + ((uint32_t)tx - x0);
+            r_slot[tid] = pair_off[id] + ((uint32_t)ty - y0) * (x1 - x0) + ((uint32_t)tx - x0);
         }
         __syncthreads();
-        const int cnt = (int)min((uint32_t)GSN_BLOCK, end - base);
-        for (int jb = 0; jb < cnt; jb += SB) {
-            const int nj = min(SB, cnt - jb);
-            for (int jj = 0; jj < nj; ++jj) {
-                const int j = jb + jj;
-                const uint32_t local = base + j - rg.x;
-                float z[GSN_NZ];
+        // (a) which of the round's entries this pixel composited
+        uint32_t bits = 0;
+        for (int j = 0; j < cnt; ++j) {
+            if (pos + j - rg.x >= nc) break;
+            const SplatEval ev = eval_splat(r_a[j], r_b[j], r_c[j], fpx, fpy, ro.alpha_max);
+            if (ev.alpha >= ro.alpha_min) bits |= 1u << j;
+        }
+        for (int j = 0; j < cnt; ++j) {
+            const uint64_t m = __ballot((bits >> j) & 1u);
+            if (lane == 0) s_mask[j][wave] = m;
+        }
+        __syncthreads();
+        // (b) slots: exclusive scan of the pair counts in (entry, wave) order, by wave 0
+        if (wave == 0) {
+            const int e0 = 2 * lane, e1 = 2 * lane + 1;  // 128 (entry, wave) cells, two per lane
+            const uint32_t c0 = (e0 / 4 < cnt) ? (uint32_t)__popcll(s_mask[e0 / 4][e0 % 4]) : 0u;
+            const uint32_t c1 = (e1 / 4 < cnt) ? (uint32_t)__popcll(s_mask[e1 / 4][e1 % 4]) : 0u;
+            uint32_t v = c0 + c1;
 #pragma unroll
-                for (int f = 0; f < GSN_NZ; ++f) z[f] = 0.f;
-                bool act = false;
-                if (local < nc) {
-                    const float4 a = s_a[j], b = s_b[j];
-                    const float2 cc = s_c[j];
-                    const float sig = b.z, q1 = a.z, q2 = a.w;
-                    const float ct[3] = {b.w, cc.x, cc.y};
-                    const SplatEval ev = eval_splat(a.x, a.y, q1, q2, b.x, b.y, sig, fpx, fpy, ro.alpha_max);
-                    if (ev.alpha >= ro.alpha_min) {
-                        act = true;
-                        const float al = ev.alpha, wT = al * T;
-                        const double wd = (double)wT;
-                        Ca0 += wd * (double)ct[0];
-                        Ca1 += wd * (double)ct[1];
-                        Ca2 += wd * (double)ct[2];
-                        const float inv = 1.0f / (1.0f - al);
-                        const float av[3] = {T * ct[0] - (float)(cf[0] - Ca0) * inv,
-                                             T * ct[1] - (float)(cf[1] - Ca1) * inv,
-                                             T * ct[2] - (float)(cf[2] - Ca2) * inv};
-                        const float A1 = dl[0] * av[0] + dl[1] * av[1] + dl[2] * av[2];
-                        const float A2 = hh[0] * av[0] * av[0] + hh[1] * av[1] * av[1] + hh[2] * av[2] * av[2];
+            for (int d = 1; d < 64; d <<= 1) {
+                const uint32_t o = __shfl_up(v, d, 64);
+                if (lane >= d) v += o;
+            }
+            const uint32_t excl = v - (c0 + c1);
+            s_off[e0] = excl;
+            s_off[e1] = excl + c0;
+            if (lane == 63) s_off[BS * 4] = v;
+        }
+        __syncthreads();
+        if (tid == 0) {
+            // longest prefix of entries whose pairs fit in PMAX (one entry has at most 256)
+            int J = cnt;
+            while (s_off[J * 4] > (uint32_t)PMAX) --J;
+            s_J = (uint32_t)J;
+        }
+        __syncthreads();
+        const int J = (int)s_J;
+        // (c) front to back over the pixel's active entries of the prefix
+        for (int j = 0; j < J; ++j) {
+            if (pos + j - rg.x >= nc) break;
+            ++n_eval;
+            if (!((bits >> j) & 1u)) continue;
+            ++n_act;
+            const float4 b = r_b[j], cc = r_c[j];
+            const SplatEval ev = eval_splat(r_a[j], b, cc, fpx, fpy, ro.alpha_max);
+            const float al = ev.alpha, wT = al * T;
+            const double wd = (double)wT;
+            Ca0 += wd * (double)b.w;
+            Ca1 += wd * (double)cc.x;
+            Ca2 += wd * (double)cc.y;
+            const float inv = 1.0f / (1.0f - al);
+            const uint32_t slot = s_off[j * 4 + wave] + (uint32_t)__popcll(s_mask[j][wave] & lt_mask);
+            s_pa[slot] = make_float4(T, ev.G, T * b.w - (float)(cf[0] - Ca0) * inv, T * cc.x - (float)(cf[1] - Ca1) * inv);
+            s_pb[slot] = T * cc.y - (float)(cf[2] - Ca2) * inv;
+            s_pix[slot] = (uint8_t)tid;
+            T *= (1.0f - al);
+        }
+        __syncthreads();
+        // (d) GRP threads per entry accumulate its pairs in double, in pixel order
+        {
+            const int e = tid / GRP, r = tid % GRP;
+            double acc[GSN_NZ];
 #pragma unroll
-                        for (int ch = 0; ch < 3; ++ch) {
-                            z[6 + ch] = dl[ch] * wT;
-                            z[39 + ch] = hh[ch] * wT * wT;
-                        }
-                        z[43] = wT;
-                        if (!ev.clamped) {
-                            const float G = ev.G, dx = ev.d1, dy = ev.d2;
-                            const float u[5] = {-q1 * dx, -q2 * dy, -0.5f * dx * dx, -dx * dy, -0.5f * dy * dy};
-                            const float sG = sig * G;
-                            const float k1 = A1 * sG;
-                            const float k2 = A2 * sG * sG + k1;
+            for (int f = 0; f < GSN_NZ; ++f) acc[f] = 0.0;
+            uint32_t p0 = 0, p1 = 0;
+            if (e < J) {
+                p0 = s_off[e * 4];
+                p1 = s_off[e * 4 + 4];
+                const float4 a = r_a[e], b = r_b[e], cl = r_c[e];
+                for (uint32_t i = p0 + r; i < p1; i += GRP) {
+                    const float4 pa = s_pa[i];
+                    const int p = s_pix[i];
+                    const float av[3] = {pa.z, pa.w, s_pb[i]};
+                    const float dl[3] = {s_dl[0][p], s_dl[1][p], s_dl[2][p]};
+                    const float hh[3] = {s_h[0][p], s_h[1][p], s_h[2][p]};
+                    const float ddx = (a.x - (float)(tx * GSN_TILE + (p % GSN_TILE))) + cl.z;
+                    const float ddy = (a.y - (float)(ty * GSN_TILE + (p / GSN_TILE))) + cl.w;
+                    const float d1 = b.x * ddx + b.y * ddy, d2 = b.x * ddy - b.y * ddx;
+                    float z[GSN_NZ];
+                    pair_terms(a, b, pa.y, pa.x, av, d1, d2, dl, hh, ro.alpha_max, z);
 #pragma unroll
-                            for (int i = 0; i < 5; ++i) z[i] = k1 * u[i];
-                            z[5] = A1 * G;
-                            // H_ww: k2 u u^T + k1 d2f, d2f has -Q' on (pi', pi') and -d' on (pi', Q')
-                            int idx = 9;
-#pragma unroll
-                            for (int i = 0; i < 5; ++i)
-#pragma unroll
-                                for (int jx = i; jx < 5; ++jx, ++idx) z[idx] = k2 * u[i] * u[jx];
-                            z[9 + 0] -= k1 * q1;    // (pi'_1, pi'_1)
-                            z[9 + 2] -= k1 * dx;    // (pi'_1, Q'_11)
-                            z[9 + 3] -= k1 * dy;    // (pi'_1, Q'_12)
-                            z[9 + 5] -= k1 * q2;    // (pi'_2, pi'_2)
-                            z[9 + 7] -= k1 * dx;    // (pi'_2, Q'_12)
-                            z[9 + 8] -= k1 * dy;    // (pi'_2, Q'_22)
-#pragma unroll
-                            for (int ch = 0; ch < 3; ++ch) {
-                                const float bch = sG * T * (hh[ch] * av[ch] * al + dl[ch]);
-#pragma unroll
-                                for (int i = 0; i < 5; ++i) z[24 + i * 3 + ch] = bch * u[i];
-                            }
-                            z[42] = A2 * G * G;
-                        }
-                        T *= (1.0f - al);
-                    }
-                }
-                const uint64_t any = __ballot(act);
-                if (any) {
-#pragma unroll
-                    for (int f = 0; f < GSN_NZ; ++f) z[f] = wave_sum(z[f]);
-                }
-                // each wave owns its own LDS row: no barrier is needed inside this loop
-                if (lane == 0) {
-#pragma unroll
-                    for (int f = 0; f < GSN_NZ; ++f) red[jj][wave][f] = any ? z[f] : 0.f;
-                    s_act[jj][wave] = any ? 1u : 0u;
+                    for (int f = 0; f < GSN_NZ; ++f) acc[f] += (double)z[f];
                 }
             }
-            __syncthreads();
-            for (int idx = threadIdx.x; idx < nj * GSN_NZ; idx += GSN_BLOCK) {
-                const int jj = idx / GSN_NZ, f = idx % GSN_NZ;
-                if (!(s_act[jj][0] | s_act[jj][1] | s_act[jj][2] | s_act[jj][3])) continue;
-                const float v = ((red[jj][0][f] + red[jj][1][f]) + red[jj][2][f]) + red[jj][3][f];
-                const uint32_t slot = s_slot[jb + jj];
-                partial[(size_t)slot * GSN_NZ + f] = v;
-                if (f == 0) flags[slot] = 1;
+#pragma unroll
+            for (int off = 1; off < GRP; off <<= 1)
+#pragma unroll
+                for (int f = 0; f < GSN_NZ; ++f) acc[f] += __shfl_xor(acc[f], off, 64);
+            if (e < J && r == 0 && p1 > p0) {
+                const uint32_t slot = r_slot[e];
+                float4* dst = reinterpret_cast<float4*>(partial + (size_t)slot * GSN_NZ);
+#pragma unroll
+                for (int f = 0; f < GSN_NZ / 4; ++f)
+                    dst[f] = make_float4((float)acc[4 * f], (float)acc[4 * f + 1], (float)acc[4 * f + 2],
+                                         (float)acc[4 * f + 3]);
+                flags[slot] = 1;
             }
-            __syncthreads();
+        }
+        __syncthreads();
+        pos += (uint32_t)J;
+    }
+    if (counts) {
+        __shared__ unsigned long long s_cnt[2];
+        if (tid == 0) s_cnt[0] = s_cnt[1] = 0;
+        __syncthreads();
+        atomicAdd(&s_cnt[0], (unsigned long long)n_eval);
+        atomicAdd(&s_cnt[1], (unsigned long long)n_act);
+        __syncthreads();
+        if (tid == 0) {
+            atomicAdd(&counts[GSN_COUNT_BWD_EVALS], s_cnt[0]);
+            atomicAdd(&counts[GSN_COUNT_BWD_ACTIVE], s_cnt[1]);
         }
     }
 }
@@ -254,12 +330,12 @@ __global__ __launch_bounds__(128) void reduce_chain_kernel(
     }
     {
         double g[3], H[6];
-        chain_rotation(kp, cam, kappa, z, g, H);
+        chain_rotation(kp, cam, kappa, zd, g, H);
 #pragma unroll
         for (int a = 0; a < 3; ++a) blk[(9 + a) * N + k] += (float)(weight * g[a]);
 #pragma unroll
         for (int a = 0; a < 6; ++a) blk[(12 + a) * N + k] += (float)(weight * H[a]);
-        chain_scale(kp, cam, kappa, z, g, H);
+        chain_scale(kp, cam, kappa, zd, g, H);
 #pragma unroll
         for (int a = 0; a < 3; ++a) blk[(18 + a) * N + k] += (float)(weight * g[a]);
 #pragma unroll
@@ -284,12 +360,12 @@ __global__ __launch_bounds__(128) void reduce_chain_kernel(
 
 }  // namespace
 
-void launch_raster_bwd(const gsn_frame& f, const float* dL, const float* hd, hipStream_t s) {
+void launch_raster_bwd(const gsn_frame& f, const float* dL, const float* hd, unsigned long long* counts, hipStream_t s) {
     const int tiles = f.tiles_x * f.tiles_y;
     raster_bwd_kernel<<<tiles, GSN_BLOCK, 0, s>>>(
         bp<uint2>(f.ranges), bp<uint32_t>(f.pv_a), bp<float4>(f.rec),
         bp<uint2>(f.rect), bp<uint32_t>(f.pair_off), (uint32_t)f.n, f.cam, f.ro, bp<double>(f.img64),
-        bp<uint32_t>(f.ncontrib), dL, hd, bp<float>(f.partial), bp<uint8_t>(f.flags));
+        bp<uint32_t>(f.ncontrib), dL, hd, bp<float>(f.partial), bp<uint8_t>(f.flags), counts);
 }
 
 void launch_reduce_chain(const gsn_frame& f, const gsn_gaussians& g, float weight, int slot, const gsn_blocks& b,

@@ -167,8 +167,9 @@ GSN_HD inline void chain_position(const KParams& kp, const float* shk, int K, co
     chain_accumulate<3, 8, float>(zj, gz, Hz, g, H);
 }
 
-// Statistics of Q' = (Q'_11, Q'_12, Q'_22) in double: entries 2..4 of the (pi', Q') block.
-GSN_HD inline void q_stats(const float* z, double gz[3], double Hz[3][3]) {
+// Statistics of Q' = (Q'_11, Q'_12, Q'_22): entries 2..4 of the (pi', Q') block, kept in the
+// double precision of the per-kernel sums (the rotation and scale Hessians cancel strongly).
+GSN_HD inline void q_stats(const double* z, double gz[3], double Hz[3][3]) {
     const int pk[3][3] = {{9 + 9, 9 + 10, 9 + 11}, {9 + 10, 9 + 12, 9 + 13}, {9 + 11, 9 + 13, 9 + 14}};
 #pragma unroll
     for (int i = 0; i < 3; ++i) {
@@ -179,7 +180,7 @@ GSN_HD inline void q_stats(const float* z, double gz[3], double Hz[3][3]) {
 }
 
 // Scale: A = M R diag(s) is linear in s.
-GSN_HD inline void chain_scale(const KParams& kp, const DevCam& c, float kappa, const float* z, double* g, double* H) {
+GSN_HD inline void chain_scale(const KParams& kp, const DevCam& c, float kappa, const double* z, double* g, double* H) {
     typedef FJet<3, double> J;
     double tf[3];
 #pragma unroll
@@ -208,7 +209,7 @@ GSN_HD inline void chain_scale(const KParams& kp, const DevCam& c, float kappa, 
 // Rotation in the tangent space of left rotations: R(omega) = exp([omega]_x) R0, i.e.
 // q(omega) = exp(omega/2) * q0.  To second order at omega = 0,
 // A(omega) = M (B0 + omega x B0 + (1/2) omega x (omega x B0)) with B0 = R0 diag(s).
-GSN_HD inline void chain_rotation(const KParams& kp, const DevCam& c, float kappa, const float* z, double* g,
+GSN_HD inline void chain_rotation(const KParams& kp, const DevCam& c, float kappa, const double* z, double* g,
                                   double* H) {
     typedef FJet<3, double> J;
     double tf[3];

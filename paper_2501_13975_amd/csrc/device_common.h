@@ -31,7 +31,8 @@ struct DevRenderOpts {
 // of its 2D covariance, e1 = (c, s) and e2 = (-s, c), with eigenvalues
 // lambda1 >= lambda2, so that the conic is Q' = diag(q1, q2), q_i = 1/lambda_i.
 // Record (three float4 per kernel):
-//   (mx, my, q1, q2), (c, s, sigma, colour_R), (colour_G, colour_B, -, -).
+//   (mx, my, q1, q2), (c, s, sigma, colour_R), (colour_G, colour_B, mx_lo, my_lo),
+// where the mean is mx + mx_lo, my + my_lo (a float pair carrying double precision).
 // Working in this frame keeps the per-pixel derivative terms of thin splats
 // well conditioned (in the image frame their conic derivatives are nearly
 // collinear and rounding destroys the minor directions).
@@ -45,17 +46,19 @@ struct SplatEval {
     bool clamped;
 };
 
-__device__ __forceinline__ SplatEval eval_splat(float mx, float my, float q1, float q2, float c, float s,
-                                                float sig, float px, float py, float amax) {
+__device__ __forceinline__ SplatEval eval_splat(const float4 a, const float4 b, const float4 c4, float px,
+                                                float py, float amax) {
     SplatEval e;
-    const float dx = mx - px, dy = my - py;
+    const float mx = a.x, my = a.y, q1 = a.z, q2 = a.w, c = b.x, s = b.y, sig = b.z;
+    // mx - px is exact near the splat (Sterbenz), so the offset keeps the low word's precision
+    const float dx = (mx - px) + c4.z, dy = (my - py) + c4.w;
     e.d1 = c * dx + s * dy;
     e.d2 = c * dy - s * dx;
     const float power = -0.5f * (q1 * e.d1 * e.d1 + q2 * e.d2 * e.d2);
     e.G = __expf(power);
-    const float a = sig * e.G;
-    e.clamped = a > amax;
-    e.alpha = e.clamped ? amax : a;
+    const float al = sig * e.G;
+    e.clamped = al > amax;
+    e.alpha = e.clamped ? amax : al;
     return e;
 }
 

@@ -4,6 +4,7 @@
 #include <stdint.h>
 
 #include <string>
+#include <vector>
 
 #include "../../include/gsn.h"
 #include "device_common.h"
@@ -51,11 +52,31 @@ struct gsn_frame {
     uint32_t* h_total = nullptr;  // pinned host word
 };
 
+struct ProfRec {
+    int stage;
+    hipEvent_t start, stop;
+};
+
 struct gsn_ctx {
     int device = 0;
     hipStream_t stream = nullptr;
     std::string err;
+    // measurement (gsn_profile_enable)
+    bool prof = false;
+    std::vector<ProfRec> recs;
+    std::vector<hipEvent_t> pool;
+    unsigned long long* d_counts = nullptr;  // GSN_COUNT_N device counters
+    int64_t pairs_counted = 0;
 };
+
+// Brackets one stage with events when profiling is on.
+struct StageTimer {
+    gsn_ctx* ctx;
+    int idx = -1;
+    StageTimer(gsn_ctx* c, int stage);
+    ~StageTimer();
+};
+inline unsigned long long* prof_counts(const gsn_ctx* c) { return c->prof ? c->d_counts : nullptr; }
 
 // ---- launchers (render.hip)
 void launch_fill_u32(uint32_t* p, uint32_t v, size_t n, hipStream_t s);
@@ -76,7 +97,7 @@ void launch_emit_pairs(const uint32_t* sorted_ids, const uint32_t* offsets, uint
 void launch_tile_ranges(const uint32_t* keys, uint32_t pairs, uint2* ranges, hipStream_t s);
 void launch_raster_fwd(const uint2* ranges, const uint32_t* ids, const float4* rec, uint32_t n, const DevCam& cam,
                        const DevRenderOpts& ro, float* img, double* img64, float* Tfin, uint32_t* ncontrib,
-                       hipStream_t s);
+                       unsigned long long* counts, hipStream_t s);
 void launch_downsample2x(const float* src, int W, int H, float* dst, hipStream_t s);
 
 // ---- launchers (loss.hip)
@@ -85,7 +106,7 @@ void launch_loss_maps(const float* img, const float* tgt, int W, int H, float la
 void launch_loss_reduce(const double* part, int nparts, int W, int H, double* out, hipStream_t s);
 
 // ---- launchers (backward.hip)
-void launch_raster_bwd(const gsn_frame& f, const float* dL, const float* hd, hipStream_t s);
+void launch_raster_bwd(const gsn_frame& f, const float* dL, const float* hd, unsigned long long* counts, hipStream_t s);
 void launch_reduce_chain(const gsn_frame& f, const gsn_gaussians& g, float weight, int slot, const gsn_blocks& b,
                          float* zstats_out, hipStream_t s);
 

@@ -8,6 +8,7 @@
 #include <algorithm>
 
 #include "gsn_internal.h"
+#include "chain.h"
 
 namespace {
 
@@ -129,47 +130,48 @@ __global__ __launch_bounds__(kThreads) void preprocess_kernel(
     depth_key[k] = __float_as_uint(b.tz);
     ntiles[k] = (uint32_t)((b.x1 - b.x0) * (b.y1 - b.y0));
     rect[k] = make_uint2((uint32_t)b.x0 | ((uint32_t)b.y0 << 16), (uint32_t)b.x1 | ((uint32_t)b.y1 << 16));
-    // compositing record in the splat's principal frame (see device_common.h)
-    float l1, l2, fc, fs;
+    // Compositing record in the splat's principal frame (see device_common.h), evaluated in
+    // double from the float attributes: the mean is kept as a float pair (hi + lo) because the
+    // single-precision pixel coordinate of a mean (ulp 1.2e-4 at x = 1920) would shift a thin
+    // splat's Gaussian across its minor axis by a visible fraction of its width.
+    double tf[3];
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+        tf[i] = (double)cam.R[3 * i] * px + (double)cam.R[3 * i + 1] * py + (double)cam.R[3 * i + 2] * pz +
+                (double)cam.t[i];
+    double M[2][3], iz;
+    persp_M<double>(tf, cam, M, iz);
+    double Rq[3][3];
     {
-        const float qn = rsqrtf(rot[k] * rot[k] + rot[n + k] * rot[n + k] + rot[2 * n + k] * rot[2 * n + k] +
-                                rot[3 * n + k] * rot[3 * n + k]);
-        const float w = rot[k] * qn, x = rot[n + k] * qn, y = rot[2 * n + k] * qn, z = rot[3 * n + k] * qn;
-        const float Rq[3][3] = {{1.f - 2.f * (y * y + z * z), 2.f * (x * y - w * z), 2.f * (x * z + w * y)},
-                                {2.f * (x * y + w * z), 1.f - 2.f * (x * x + z * z), 2.f * (y * z - w * x)},
-                                {2.f * (x * z - w * y), 2.f * (y * z + w * x), 1.f - 2.f * (x * x + y * y)}};
-        const float iz = 1.0f / b.tz;
-        const float J00 = cam.fx * iz, J02 = -cam.fx * b.tx * iz * iz;
-        const float J11 = cam.fy * iz, J12 = -cam.fy * b.ty * iz * iz;
-        const float sv[3] = {scale[k], scale[n + k], scale[2 * n + k]};
-        float A[2][3];
-#pragma unroll
-        for (int a = 0; a < 3; ++a) {
-            float m0 = 0.f, m1 = 0.f;
-#pragma unroll
-            for (int c = 0; c < 3; ++c) {
-                m0 += (J00 * cam.R[c] + J02 * cam.R[6 + c]) * Rq[c][a];
-                m1 += (J11 * cam.R[3 + c] + J12 * cam.R[6 + c]) * Rq[c][a];
-            }
-            A[0][a] = m0 * sv[a];
-            A[1][a] = m1 * sv[a];
-        }
-        principal_frame<float>(A, ro.kappa, l1, l2, fc, fs);
+        const float q[4] = {rot[k], rot[n + k], rot[2 * n + k], rot[3 * n + k]};
+        quat_rot<double>(q, Rq);
     }
-    const float dx = px - cam.o[0], dy = py - cam.o[1], dz = pz - cam.o[2];
-    const float il = rsqrtf(dx * dx + dy * dy + dz * dz);
-    float Y[16];
-    sh_basis_dev<float>(K, dx * il, dy * il, dz * il, Y);
+    double A[2][3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        const double sa = scale[(size_t)a * n + k];
+#pragma unroll
+        for (int i = 0; i < 2; ++i) A[i][a] = (M[i][0] * Rq[0][a] + M[i][1] * Rq[1][a] + M[i][2] * Rq[2][a]) * sa;
+    }
+    double l1, l2, fc, fs;
+    principal_frame<double>(A, (double)ro.kappa, l1, l2, fc, fs);
+    const double mu = (double)cam.fx * tf[0] * iz + (double)cam.cx;
+    const double mv = (double)cam.fy * tf[1] * iz + (double)cam.cy;
+    const float mu_hi = (float)mu, mv_hi = (float)mv;
+    const double dx = (double)px - cam.o[0], dy = (double)py - cam.o[1], dz = (double)pz - cam.o[2];
+    const double il = 1.0 / sqrt(dx * dx + dy * dy + dz * dz);
+    double Y[16];
+    sh_basis_dev<double>(K, dx * il, dy * il, dz * il, Y);
     float col[3];
 #pragma unroll
     for (int ch = 0; ch < 3; ++ch) {
-        float acc = 0.f;
-        for (int i = 0; i < K; ++i) acc += Y[i] * sh[((size_t)ch * K + i) * n + k];
-        col[ch] = acc;
+        double acc = 0.0;
+        for (int i = 0; i < K; ++i) acc += Y[i] * (double)sh[((size_t)ch * K + i) * n + k];
+        col[ch] = (float)acc;
     }
-    rec[k] = make_float4(b.u, b.v, 1.0f / l1, 1.0f / l2);
-    rec[n + k] = make_float4(fc, fs, opac[k], col[0]);
-    rec[2 * (size_t)n + k] = make_float4(col[1], col[2], 0.f, 0.f);
+    rec[k] = make_float4(mu_hi, mv_hi, (float)(1.0 / l1), (float)(1.0 / l2));
+    rec[n + k] = make_float4((float)fc, (float)fs, opac[k], col[0]);
+    rec[2 * (size_t)n + k] = make_float4(col[1], col[2], (float)(mu - (double)mu_hi), (float)(mv - (double)mv_hi));
 }
 
 // ---------------------------------------------------------------------------
@@ -383,10 +385,10 @@ __global__ void tile_ranges_kernel(const uint32_t* __restrict__ keys, uint32_t p
 __global__ __launch_bounds__(GSN_BLOCK) void raster_fwd_kernel(
     const uint2* __restrict__ ranges, const uint32_t* __restrict__ ids, const float4* __restrict__ rec, uint32_t n,
     DevCam cam, DevRenderOpts ro, float* __restrict__ img, double* __restrict__ img64, float* __restrict__ Tfin,
-    uint32_t* __restrict__ ncontrib) {
+    uint32_t* __restrict__ ncontrib, unsigned long long* __restrict__ counts) {
     __shared__ float4 s_a[GSN_BLOCK];
     __shared__ float4 s_b[GSN_BLOCK];
-    __shared__ float2 s_c[GSN_BLOCK];
+    __shared__ float4 s_c[GSN_BLOCK];
     const int tile = blockIdx.x;
     const int tx = tile % cam.tiles_x, ty = tile / cam.tiles_x;
     const int px = tx * GSN_TILE + (threadIdx.x % GSN_TILE);
@@ -399,6 +401,7 @@ __global__ __launch_bounds__(GSN_BLOCK) void raster_fwd_kernel(
     uint32_t last = 0;
     bool done = !inside;
     const float fpx = (float)px, fpy = (float)py;
+    uint32_t evals = 0;
     for (uint32_t base = rg.x; base < rg.y; base += GSN_BLOCK) {
         if (__syncthreads_count(done) == GSN_BLOCK) break;
         const uint32_t e = base + threadIdx.x;
@@ -406,14 +409,14 @@ __global__ __launch_bounds__(GSN_BLOCK) void raster_fwd_kernel(
             const uint32_t id = ids[e];
             s_a[threadIdx.x] = rec[id];
             s_b[threadIdx.x] = rec[n + id];
-            const float4 c4 = rec[2 * (size_t)n + id];
-            s_c[threadIdx.x] = make_float2(c4.x, c4.y);
+            s_c[threadIdx.x] = rec[2 * (size_t)n + id];
         }
         __syncthreads();
         const int cnt = min((uint32_t)GSN_BLOCK, rg.y - base);
         for (int j = 0; j < cnt && !done; ++j) {
-            const float4 a = s_a[j], b = s_b[j];
-            const SplatEval ev = eval_splat(a.x, a.y, a.z, a.w, b.x, b.y, b.z, fpx, fpy, ro.alpha_max);
+            const float4 a = s_a[j], b = s_b[j], cc = s_c[j];
+            const SplatEval ev = eval_splat(a, b, cc, fpx, fpy, ro.alpha_max);
+            ++evals;
             if (ev.alpha < ro.alpha_min) continue;
             const float Tn = T * (1.0f - ev.alpha);
             if (Tn < ro.T_min) {
@@ -421,13 +424,20 @@ __global__ __launch_bounds__(GSN_BLOCK) void raster_fwd_kernel(
                 break;
             }
             const double w = (double)(ev.alpha * T);
-            const float2 cc = s_c[j];
             C0 += w * (double)b.w;
             C1 += w * (double)cc.x;
             C2 += w * (double)cc.y;
             T = Tn;
             last = base + j + 1 - rg.x;
         }
+    }
+    if (counts) {
+        __shared__ unsigned long long s_evals;
+        if (threadIdx.x == 0) s_evals = 0;
+        __syncthreads();
+        atomicAdd(&s_evals, (unsigned long long)evals);
+        __syncthreads();
+        if (threadIdx.x == 0) atomicAdd(&counts[GSN_COUNT_FWD_EVALS], s_evals);
     }
     if (inside) {
         const size_t np = (size_t)cam.W * cam.H, pi = (size_t)py * cam.W + px;
@@ -528,9 +538,9 @@ void launch_tile_ranges(const uint32_t* keys, uint32_t pairs, uint2* ranges, hip
 
 void launch_raster_fwd(const uint2* ranges, const uint32_t* ids, const float4* rec, uint32_t n, const DevCam& cam,
                        const DevRenderOpts& ro, float* img, double* img64, float* Tfin, uint32_t* ncontrib,
-                       hipStream_t s) {
+                       unsigned long long* counts, hipStream_t s) {
     const int tiles = cam.tiles_x * cam.tiles_y;
-    raster_fwd_kernel<<<tiles, GSN_BLOCK, 0, s>>>(ranges, ids, rec, n, cam, ro, img, img64, Tfin, ncontrib);
+    raster_fwd_kernel<<<tiles, GSN_BLOCK, 0, s>>>(ranges, ids, rec, n, cam, ro, img, img64, Tfin, ncontrib, counts);
 }
 
 void launch_downsample2x(const float* src, int W, int H, float* dst, hipStream_t s) {

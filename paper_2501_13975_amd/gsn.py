@@ -51,6 +51,8 @@ def lib():
             "gsn_frame_zstats": [P, P, P],
             "gsn_frame_loss_maps": [P, P, P, P],
             "gsn_frame_records": [P, P, P],
+            "gsn_profile_enable": [P, ctypes.c_int32],
+            "gsn_profile_read": [P, P, P, P],
         }.items():
             fn = getattr(L, name)
             fn.argtypes = args
@@ -265,6 +267,23 @@ class Context:
         cg, cs = g.c(), steps.c()
         self._check(lib().gsn_apply_step(self.h, ctypes.byref(cg), ctypes.byref(cs), ctypes.byref(so),
                                          int(group_mask)))
+
+    STAGES = ("project", "sort", "raster_fwd", "loss", "raster_bwd", "chain", "solve", "apply")
+    COUNTERS = ("fwd_evals", "bwd_evals", "bwd_active", "pairs")
+
+    def profile_enable(self, on=True):
+        self._check(lib().gsn_profile_enable(self.h, int(bool(on))))
+
+    def profile_read(self):
+        """{stage: (ms, launches)}, {counter: value}; synchronises the stream."""
+        import numpy as np
+        ms = np.zeros(8, np.float64)
+        nl = np.zeros(8, np.int64)
+        cnt = np.zeros(4, np.int64)
+        self._check(lib().gsn_profile_read(self.h, ms.ctypes.data_as(ctypes.c_void_p),
+                                           nl.ctypes.data_as(ctypes.c_void_p), cnt.ctypes.data_as(ctypes.c_void_p)))
+        return ({s: (float(ms[i]), int(nl[i])) for i, s in enumerate(self.STAGES)},
+                {c: int(cnt[i]) for i, c in enumerate(self.COUNTERS)})
 
     def blocks_zero(self, blocks: "Blocks"):
         cb = blocks.c()

@@ -84,7 +84,8 @@ def _check_view(gsn, ctx, g, cam, tgt, lam, label):
     if dump:
         os.makedirs(dump, exist_ok=True)
         np.savez_compressed(os.path.join(dump, f"view_{label}.npz"), gpu_z=gv["z"], gpu_rec=gv["rec"], orc_z=ov["z"],
-                            gpu_blocks=blk, orc_blocks=ov["blocks"])
+                            gpu_blocks=blk, orc_blocks=ov["blocks"], gpu_img=gv["img"], gpu_dL=gv["dL"],
+                            gpu_h=gv["h"], orc_img=fr.img, orc_dL=ov["dL"], orc_h=ov["hd"])
     assert errs["img"] < TOL_IMAGE and errs["T"] < TOL_IMAGE
     assert errs["ncontrib_mismatch"] == 0
     assert errs["loss_L2"] < TOL_GRAD and errs["loss_S"] < TOL_GRAD
