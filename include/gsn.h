@@ -248,8 +248,10 @@ gsn_status gsn_frame_lists(gsn_ctx* ctx, const gsn_frame* frame, uint32_t* d_ran
  * sum alpha T (1). */
 gsn_status gsn_frame_zstats(gsn_ctx* ctx, const gsn_frame* frame, float* d_out);
 /* Copy of the projected kernels of the last render (float [12][n]): image
- * position (2), conic in the principal frame q1 = 1/lambda1, q2 = 1/lambda2 (2),
- * principal axis (cos, sin) (2), opacity (1), view-dependent colour (3), 0, 0.
+ * position, high word (2), conic in the principal frame q1 = 1/lambda1,
+ * q2 = 1/lambda2 (2), principal axis (cos, sin) (2), opacity (1), view-dependent
+ * colour (3), image position, low word (2): the position is the sum of the two
+ * words (evaluated in double, kept as a float pair).
  * The per-kernel statistics of gsn_frame_zstats are expressed in this
  * principal frame. */
 gsn_status gsn_frame_records(gsn_ctx* ctx, const gsn_frame* frame, float* d_out);

@@ -217,7 +217,7 @@ gsn_status gsn_frame_destroy(gsn_ctx* ctx, gsn_frame* f) {
     (void)hipStreamSynchronize(ctx->stream);
     DevBuf* all[] = {&f->rec, &f->rect, &f->depth_key, &f->ntiles, &f->ids_a, &f->ids_b, &f->keys_a, &f->keys_b,
                      &f->offsets, &f->pair_off, &f->pk_a, &f->pv_a, &f->pk_b, &f->pv_b, &f->partial, &f->flags,
-                     &f->ranges, &f->img, &f->img64, &f->Tfin, &f->ncontrib, &f->dL, &f->hd, &f->coef, &f->zstats,
+                     &f->ranges, &f->img, &f->img64, &f->Tfin, &f->ncontrib, &f->dL, &f->hd, &f->coef, &f->zsum, &f->zstats,
                      &f->loss_part, &f->hist, &f->scan_tmp, &f->total};
     for (DevBuf* b : all) buf_free(*b);
     if (f->h_total) (void)hipHostFree(f->h_total);
@@ -367,6 +367,7 @@ gsn_status gsn_accumulate_hessian(gsn_ctx* ctx, const gsn_gaussians* g, const gs
     const size_t pp = std::max<size_t>((size_t)f->pairs, 1);
     HIP_TRY(ctx, buf_reserve(f->partial, pp * GSN_NZ * 4));
     HIP_TRY(ctx, buf_reserve(f->flags, (pp + 3) / 4 * 4));
+    HIP_TRY(ctx, buf_reserve(f->zsum, (size_t)std::max(f->n, 1) * GSN_NZ * 8));
     float* zs = nullptr;
     if (opts->keep_zstats) {
         HIP_TRY(ctx, buf_reserve(f->zstats, (size_t)std::max(f->n, 1) * GSN_NZ * 4));

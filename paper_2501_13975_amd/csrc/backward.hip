@@ -27,9 +27,10 @@
 // the contributing (pixel, splat) pairs of each round in LDS, and sums each
 // splat's 44 statistics over its pairs (see raster_bwd_kernel); the tile's
 // partial sum is written at the (tile, kernel) pair's slot.
-// reduce_chain: one thread per kernel sums its pair slots in a fixed order (no
-// atomics: results are deterministic), then applies the chain rule through the
-// projection with second-order jets and adds the attribute blocks.
+// reduce_pairs: one wave per kernel sums its pair slots in a fixed order (no
+// atomics: results are deterministic); chain_pos / chain_rs: one thread per
+// kernel applies the chain rule through the projection with second-order jets
+// and adds the attribute blocks (position, opacity, colour / rotation, scale).
 #include "gsn_internal.h"
 #include "chain.h"
 
@@ -272,74 +273,80 @@ __global__ __launch_bounds__(GSN_BLOCK) void raster_bwd_kernel(
     }
 }
 
-__global__ __launch_bounds__(128) void reduce_chain_kernel(
-    const float* __restrict__ pos, const float* __restrict__ rot, const float* __restrict__ scale,
-    const float* __restrict__ sh, int n, int K, const uint2* __restrict__ rect, const uint32_t* __restrict__ pair_off,
-    const float* __restrict__ partial, const uint8_t* __restrict__ flags, const float4* __restrict__ rec, DevCam cam,
-    float kappa, float weight, int slot, float* __restrict__ blk, float* __restrict__ zstats) {
-    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+// One wave per kernel: the kernel's (tile, kernel) slots are scanned 64 at a time,
+// and lane f < 44 adds statistic f of every slot the backward pass wrote, in slot
+// order and in double (deterministic, coalesced 176-byte reads per slot).
+__global__ __launch_bounds__(256) void reduce_pairs_kernel(int n, const uint2* __restrict__ rect,
+                                                           const uint32_t* __restrict__ pair_off,
+                                                           const float* __restrict__ partial,
+                                                           const uint8_t* __restrict__ flags,
+                                                           double* __restrict__ zsum) {
+    const int k = blockIdx.x * (blockDim.x / 64) + threadIdx.x / 64;
+    const int lane = __lane_id();
     if (k >= n) return;
     const uint2 rc = rect[k];
     const uint32_t nt = ((rc.y & 0xffffu) - (rc.x & 0xffffu)) * ((rc.y >> 16) - (rc.x >> 16));
-    // the kernel's tile partials, summed in double in slot order
-    double zd[GSN_NZ];
-#pragma unroll
-    for (int f = 0; f < GSN_NZ; ++f) zd[f] = 0.0;
     const uint32_t off = pair_off[k];
-    for (uint32_t i = 0; i < nt; ++i) {
-        const uint32_t sl = off + i;
-        if (!flags[sl]) continue;
-        const float4* pp = reinterpret_cast<const float4*>(partial + (size_t)sl * GSN_NZ);
-#pragma unroll
-        for (int f = 0; f < GSN_NZ / 4; ++f) {
-            const float4 v = pp[f];
-            zd[4 * f] += v.x;
-            zd[4 * f + 1] += v.y;
-            zd[4 * f + 2] += v.z;
-            zd[4 * f + 3] += v.w;
+    double acc = 0.0;
+    for (uint32_t base = 0; base < nt; base += 64) {
+        const bool fl = base + lane < nt && flags[off + base + lane] != 0;
+        uint64_t m = __ballot(fl);
+        while (m) {
+            const int i = __ffsll((unsigned long long)m) - 1;
+            m &= m - 1;
+            if (lane < GSN_NZ) acc += (double)partial[(size_t)(off + base + i) * GSN_NZ + lane];
         }
     }
-    float z[GSN_NZ];
-#pragma unroll
-    for (int f = 0; f < GSN_NZ; ++f) z[f] = (float)zd[f];
-    if (zstats) {
-#pragma unroll
-        for (int f = 0; f < GSN_NZ; ++f) zstats[(size_t)f * n + k] = z[f];
-    }
-    if (!(z[43] > 0.f)) return;
-    KParams kp;
+    if (lane < GSN_NZ) zsum[(size_t)k * GSN_NZ + lane] = acc;
+}
+
+__device__ __forceinline__ void load_kparams(const float* __restrict__ pos, const float* __restrict__ rot,
+                                             const float* __restrict__ scale, const float4* __restrict__ rec, int n,
+                                             int k, KParams& kp) {
 #pragma unroll
     for (int a = 0; a < 3; ++a) kp.p[a] = pos[(size_t)a * n + k];
 #pragma unroll
     for (int a = 0; a < 4; ++a) kp.q[a] = rot[(size_t)a * n + k];
 #pragma unroll
     for (int a = 0; a < 3; ++a) kp.s[a] = scale[(size_t)a * n + k];
-    float shk[48];
-    for (int i = 0; i < 3 * K; ++i) shk[i] = sh[(size_t)i * n + k];
     const float4 r1 = rec[(size_t)n + k];
     kp.fc = r1.x;
     kp.fs = r1.y;
+}
+
+// One thread per kernel: position, opacity and per-view colour blocks from the summed
+// statistics (single precision), and the optional float copy of the statistics.
+__global__ __launch_bounds__(128) void chain_pos_kernel(
+    const float* __restrict__ pos, const float* __restrict__ rot, const float* __restrict__ scale,
+    const float* __restrict__ sh, int n, int K, const double* __restrict__ zsum, const float4* __restrict__ rec,
+    DevCam cam, float kappa, float weight, int slot, float* __restrict__ blk, float* __restrict__ zstats) {
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= n) return;
+    float z[GSN_NZ];
+    {
+        const double2* zp = reinterpret_cast<const double2*>(zsum + (size_t)k * GSN_NZ);
+#pragma unroll
+        for (int f = 0; f < GSN_NZ / 2; ++f) {
+            const double2 v = zp[f];
+            z[2 * f] = (float)v.x;
+            z[2 * f + 1] = (float)v.y;
+        }
+    }
+    if (zstats) {
+#pragma unroll
+        for (int f = 0; f < GSN_NZ; ++f) zstats[(size_t)f * n + k] = z[f];
+    }
+    if (!(z[43] > 0.f)) return;
+    KParams kp;
+    load_kparams(pos, rot, scale, rec, n, k, kp);
     const size_t N = (size_t)n;
     {
         float g[3], H[6];
-        chain_position(kp, shk, K, cam, kappa, z, g, H);
+        chain_position(kp, sh + k, N, K, cam, kappa, z, g, H);
 #pragma unroll
         for (int a = 0; a < 3; ++a) blk[a * N + k] += weight * g[a];
 #pragma unroll
         for (int a = 0; a < 6; ++a) blk[(3 + a) * N + k] += weight * H[a];
-    }
-    {
-        double g[3], H[6];
-        chain_rotation(kp, cam, kappa, zd, g, H);
-#pragma unroll
-        for (int a = 0; a < 3; ++a) blk[(9 + a) * N + k] += (float)(weight * g[a]);
-#pragma unroll
-        for (int a = 0; a < 6; ++a) blk[(12 + a) * N + k] += (float)(weight * H[a]);
-        chain_scale(kp, cam, kappa, zd, g, H);
-#pragma unroll
-        for (int a = 0; a < 3; ++a) blk[(18 + a) * N + k] += (float)(weight * g[a]);
-#pragma unroll
-        for (int a = 0; a < 6; ++a) blk[(21 + a) * N + k] += (float)(weight * H[a]);
     }
     blk[27 * N + k] += weight * z[5];
     blk[28 * N + k] += weight * z[42];
@@ -358,6 +365,34 @@ __global__ __launch_bounds__(128) void reduce_chain_kernel(
     blk[(vb + 9) * N + k] = z[43];
 }
 
+// One thread per kernel: rotation and scale blocks, in double from the double sums of the
+// conic statistics (both Hessians cancel strongly for thin splats).
+__global__ __launch_bounds__(128) void chain_rs_kernel(
+    const float* __restrict__ pos, const float* __restrict__ rot, const float* __restrict__ scale, int n,
+    const double* __restrict__ zsum, const float4* __restrict__ rec, DevCam cam, float kappa, float weight,
+    float* __restrict__ blk) {
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= n) return;
+    const double* zk = zsum + (size_t)k * GSN_NZ;
+    if (!(zk[43] > 0.0)) return;
+    double gq[3], Hq[3][3];
+    q_stats(zk, gq, Hq);
+    KParams kp;
+    load_kparams(pos, rot, scale, rec, n, k, kp);
+    const size_t N = (size_t)n;
+    double g[3], H[6];
+    chain_rotation(kp, cam, kappa, gq, Hq, g, H);
+#pragma unroll
+    for (int a = 0; a < 3; ++a) blk[(9 + a) * N + k] += (float)(weight * g[a]);
+#pragma unroll
+    for (int a = 0; a < 6; ++a) blk[(12 + a) * N + k] += (float)(weight * H[a]);
+    chain_scale(kp, cam, kappa, gq, Hq, g, H);
+#pragma unroll
+    for (int a = 0; a < 3; ++a) blk[(18 + a) * N + k] += (float)(weight * g[a]);
+#pragma unroll
+    for (int a = 0; a < 6; ++a) blk[(21 + a) * N + k] += (float)(weight * H[a]);
+}
+
 }  // namespace
 
 void launch_raster_bwd(const gsn_frame& f, const float* dL, const float* hd, unsigned long long* counts, hipStream_t s) {
@@ -372,8 +407,12 @@ void launch_reduce_chain(const gsn_frame& f, const gsn_gaussians& g, float weigh
                          float* zstats_out, hipStream_t s) {
     if (g.n == 0) return;
     const int K = (g.sh_degree + 1) * (g.sh_degree + 1);
-    reduce_chain_kernel<<<(g.n + 127) / 128, 128, 0, s>>>(
-        g.d_pos, g.d_rot, g.d_scale, g.d_sh, g.n, K, bp<uint2>(f.rect), bp<uint32_t>(f.pair_off),
-        bp<float>(f.partial), bp<uint8_t>(f.flags), bp<float4>(f.rec), f.cam, f.ro.kappa, weight, slot, b.d_data,
-        zstats_out);
+    reduce_pairs_kernel<<<(g.n + 3) / 4, 256, 0, s>>>(g.n, bp<uint2>(f.rect), bp<uint32_t>(f.pair_off),
+                                                      bp<float>(f.partial), bp<uint8_t>(f.flags),
+                                                      bp<double>(f.zsum));
+    chain_pos_kernel<<<(g.n + 127) / 128, 128, 0, s>>>(g.d_pos, g.d_rot, g.d_scale, g.d_sh, g.n, K,
+                                                       bp<double>(f.zsum), bp<float4>(f.rec), f.cam, f.ro.kappa,
+                                                       weight, slot, b.d_data, zstats_out);
+    chain_rs_kernel<<<(g.n + 127) / 128, 128, 0, s>>>(g.d_pos, g.d_rot, g.d_scale, g.n, bp<double>(f.zsum),
+                                                      bp<float4>(f.rec), f.cam, f.ro.kappa, weight, b.d_data);
 }

@@ -111,8 +111,9 @@ GSN_HD inline void chain_accumulate(const FJet<N, T>* zj, const T* gz, const T H
 // Position: z = (pi', Q', c~) as functions of p (pi through the projection, Q through the
 // perspective Jacobian, c~ through the view direction of the SH colour), in the
 // splat's principal frame (pi' = V^T pi, Q' = (V^T M R S)(V^T M R S)^T + kappa I inverted).
-GSN_HD inline void chain_position(const KParams& kp, const float* shk, int K, const DevCam& c, float kappa,
-                                  const float* z, float* g, float* H) {
+// The kernel's SH coefficient (ch, i) is shk[(ch K + i) stride].
+GSN_HD inline void chain_position(const KParams& kp, const float* shk, size_t stride, int K, const DevCam& c,
+                                  float kappa, const float* z, float* g, float* H) {
     typedef FJet<3> J;
     J p[3] = {J::var(kp.p[0], 0), J::var(kp.p[1], 1), J::var(kp.p[2], 2)};
     J t[3];
@@ -139,14 +140,11 @@ GSN_HD inline void chain_position(const KParams& kp, const float* shk, int K, co
     {
         const J d0 = p[0] - c.o[0], d1 = p[1] - c.o[1], d2 = p[2] - c.o[2];
         const J il = jrecip(jsqrt(d0 * d0 + d1 * d1 + d2 * d2));
-        J Y[16];
-        sh_basis_dev<J>(K, d0 * il, d1 * il, d2 * il, Y);
+        zj[5] = zj[6] = zj[7] = J(0.f);
+        sh_basis_visit<J>(K, d0 * il, d1 * il, d2 * il, [&](int i, const J& y) {
 #pragma unroll
-        for (int ch = 0; ch < 3; ++ch) {
-            J acc(0.f);
-            for (int i = 0; i < K; ++i) acc = acc + shk[ch * K + i] * Y[i];
-            zj[5 + ch] = acc;
-        }
+            for (int ch = 0; ch < 3; ++ch) zj[5 + ch] = zj[5 + ch] + shk[((size_t)ch * K + i) * stride] * y;
+        });
     }
     // H_z over (pi_x, pi_y, Q_xx, Q_xy, Q_yy, c~_R, c~_G, c~_B)
     float Hz[8][8];
@@ -169,7 +167,7 @@ GSN_HD inline void chain_position(const KParams& kp, const float* shk, int K, co
 
 // Statistics of Q' = (Q'_11, Q'_12, Q'_22): entries 2..4 of the (pi', Q') block, kept in the
 // double precision of the per-kernel sums (the rotation and scale Hessians cancel strongly).
-GSN_HD inline void q_stats(const double* z, double gz[3], double Hz[3][3]) {
+GSN_HD inline void q_stats(const double* __restrict__ z, double gz[3], double Hz[3][3]) {
     const int pk[3][3] = {{9 + 9, 9 + 10, 9 + 11}, {9 + 10, 9 + 12, 9 + 13}, {9 + 11, 9 + 13, 9 + 14}};
 #pragma unroll
     for (int i = 0; i < 3; ++i) {
@@ -179,66 +177,145 @@ GSN_HD inline void q_stats(const double* z, double gz[3], double Hz[3][3]) {
     }
 }
 
-// Scale: A = M R diag(s) is linear in s.
-GSN_HD inline void chain_scale(const KParams& kp, const DevCam& c, float kappa, const double* z, double* g, double* H) {
+// The six quantities of Sigma = A A^T + kappa I that the conic needs are bilinear in A,
+// F(A) = B_f(A, A): the entries sxx, syy, sxy of A A^T and the three 2x2 minors of A
+// (Cauchy-Binet).  B_f(X, Y) for f = 0..5:
+template <int F>
+GSN_HD inline double conic_bilinear(const double X[2][3], const double Y[2][3]) {
+    if (F == 0) return X[0][0] * Y[0][0] + X[0][1] * Y[0][1] + X[0][2] * Y[0][2];
+    if (F == 1) return X[1][0] * Y[1][0] + X[1][1] * Y[1][1] + X[1][2] * Y[1][2];
+    if (F == 2) return X[0][0] * Y[1][0] + X[0][1] * Y[1][1] + X[0][2] * Y[1][2];
+    if (F == 3) return X[0][0] * Y[1][1] - X[0][1] * Y[1][0];
+    if (F == 4) return X[0][0] * Y[1][2] - X[0][2] * Y[1][0];
+    return X[0][1] * Y[1][2] - X[0][2] * Y[1][1];
+}
+
+// Second-order jet of F_f(A(y)) at y = 0 from A0 = A(0), D[i] = dA/dy_i and (if the map is
+// not linear) E(i, j) = d2A/dy_i dy_j:
+//   dF = B(D_i, A0) + B(A0, D_i),  d2F = B(D_i, D_j) + B(D_j, D_i) + B(E_ij, A0) + B(A0, E_ij).
+template <int F, class EFn>
+GSN_HD inline FJet<3, double> bilinear_jet(const double A0[2][3], const double D[3][2][3], EFn E, bool quadratic) {
+    FJet<3, double> r;
+    r.v = conic_bilinear<F>(A0, A0);
+#pragma unroll
+    for (int i = 0; i < 3; ++i) r.g[i] = conic_bilinear<F>(D[i], A0) + conic_bilinear<F>(A0, D[i]);
+    int idx = 0;
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int j = i; j < 3; ++j, ++idx) {
+            double h = conic_bilinear<F>(D[i], D[j]) + conic_bilinear<F>(D[j], D[i]);
+            if (quadratic) {
+                double Eij[2][3];
+                E(i, j, Eij);
+                h += conic_bilinear<F>(Eij, A0) + conic_bilinear<F>(A0, Eij);
+            }
+            r.h[idx] = h;
+        }
+    return r;
+}
+
+// Jets of the conic Q = Sigma^{-1} = (syy, -sxy, sxx) / det, det = sum of squared minors +
+// kappa (sxx0 + syy0) + kappa^2 (the form of conic_from_A), with only scalar jets live.
+template <class EFn>
+GSN_HD inline void conic_jets(const double A0[2][3], const double D[3][2][3], EFn E, bool quadratic, double kappa,
+                              FJet<3, double> Q[3]) {
     typedef FJet<3, double> J;
+    const J sxx0 = bilinear_jet<0>(A0, D, E, quadratic);
+    const J syy0 = bilinear_jet<1>(A0, D, E, quadratic);
+    J det = kappa * (sxx0 + syy0) + kappa * kappa;
+    {
+        const J m = bilinear_jet<3>(A0, D, E, quadratic);
+        det = det + m * m;
+    }
+    {
+        const J m = bilinear_jet<4>(A0, D, E, quadratic);
+        det = det + m * m;
+    }
+    {
+        const J m = bilinear_jet<5>(A0, D, E, quadratic);
+        det = det + m * m;
+    }
+    const J idet = jrecip(det);
+    const J sxy = bilinear_jet<2>(A0, D, E, quadratic);
+    Q[0] = (syy0 + kappa) * idet;
+    Q[1] = -(sxy * idet);
+    Q[2] = (sxx0 + kappa) * idet;
+}
+
+// M' (rows of the perspective Jacobian times the camera rotation, in the splat's principal
+// frame) and R(q) for one kernel, in double.
+GSN_HD inline void frame_M_R(const KParams& kp, const DevCam& c, double M[2][3], double Rq[3][3]) {
     double tf[3];
 #pragma unroll
     for (int i = 0; i < 3; ++i)
         tf[i] = (double)c.R[3 * i] * kp.p[0] + (double)c.R[3 * i + 1] * kp.p[1] + (double)c.R[3 * i + 2] * kp.p[2] +
                 c.t[i];
-    double M[2][3], iz;
+    double iz;
     persp_M<double>(tf, c, M, iz);
     to_frame(M, kp.fc, kp.fs);
-    double Rq[3][3];
     quat_rot<double>(kp.q, Rq);
-    J A[2][3];
+}
+
+// Scale: A = M' R diag(s) is linear in s, dA/ds_a has the single column a of M' R.
+GSN_HD inline void chain_scale(const KParams& kp, const DevCam& c, float kappa, const double gz[3],
+                               const double Hz[3][3], double* g, double* H) {
+    double M[2][3], Rq[3][3];
+    frame_M_R(kp, c, M, Rq);
+    double A0[2][3], D[3][2][3];
 #pragma unroll
-    for (int a = 0; a < 3; ++a) {
-        const J sv = J::var((double)kp.s[a], a);
+    for (int a = 0; a < 3; ++a)
 #pragma unroll
-        for (int i = 0; i < 2; ++i) A[i][a] = (M[i][0] * Rq[0][a] + M[i][1] * Rq[1][a] + M[i][2] * Rq[2][a]) * sv;
-    }
-    J Q[3];
-    conic_from_A(A, (double)kappa, Q);
-    double gz[3], Hz[3][3];
-    q_stats(z, gz, Hz);
+        for (int i = 0; i < 2; ++i) {
+            const double mr = M[i][0] * Rq[0][a] + M[i][1] * Rq[1][a] + M[i][2] * Rq[2][a];
+            A0[i][a] = mr * kp.s[a];
+#pragma unroll
+            for (int b = 0; b < 3; ++b) D[b][i][a] = b == a ? mr : 0.0;
+        }
+    FJet<3, double> Q[3];
+    conic_jets(A0, D, [](int, int, double[2][3]) {}, false, (double)kappa, Q);
     chain_accumulate<3, 3, double>(Q, gz, Hz, g, H);
 }
 
 // Rotation in the tangent space of left rotations: R(omega) = exp([omega]_x) R0, i.e.
-// q(omega) = exp(omega/2) * q0.  To second order at omega = 0,
-// A(omega) = M (B0 + omega x B0 + (1/2) omega x (omega x B0)) with B0 = R0 diag(s).
-GSN_HD inline void chain_rotation(const KParams& kp, const DevCam& c, float kappa, const double* z, double* g,
-                                  double* H) {
-    typedef FJet<3, double> J;
-    double tf[3];
+// q(omega) = exp(omega/2) * q0.  With B0 = R0 diag(s) and A(omega) = M' R(omega) R0^T B0:
+//   dA/domega_i = M' [e_i]_x B0,
+//   d2A/domega_i domega_j = (1/2) (M' e_j)(e_i^T B0) + (1/2) (M' e_i)(e_j^T B0) - delta_ij M' B0
+// (from [e_i]_x [e_j]_x = e_j e_i^T - delta_ij I).
+GSN_HD inline void chain_rotation(const KParams& kp, const DevCam& c, float kappa, const double gz[3],
+                                  const double Hz[3][3], double* g, double* H) {
+    double M[2][3], Rq[3][3];
+    frame_M_R(kp, c, M, Rq);
+    double B0[3][3];
 #pragma unroll
-    for (int i = 0; i < 3; ++i)
-        tf[i] = (double)c.R[3 * i] * kp.p[0] + (double)c.R[3 * i + 1] * kp.p[1] + (double)c.R[3 * i + 2] * kp.p[2] +
-                c.t[i];
-    double M[2][3], iz;
-    persp_M<double>(tf, c, M, iz);
-    to_frame(M, kp.fc, kp.fs);
-    double Rq[3][3];
-    quat_rot<double>(kp.q, Rq);
-    const J w[3] = {J::var(0.0, 0), J::var(0.0, 1), J::var(0.0, 2)};
-    J A[2][3];
+    for (int r = 0; r < 3; ++r)
 #pragma unroll
-    for (int a = 0; a < 3; ++a) {
-        const double b[3] = {Rq[0][a] * kp.s[a], Rq[1][a] * kp.s[a], Rq[2][a] * kp.s[a]};
-        // c1 = w x b (linear), c2 = w x c1 (quadratic)
-        const J c1[3] = {w[1] * b[2] - w[2] * b[1], w[2] * b[0] - w[0] * b[2], w[0] * b[1] - w[1] * b[0]};
-        const J c2[3] = {w[1] * c1[2] - w[2] * c1[1], w[2] * c1[0] - w[0] * c1[2], w[0] * c1[1] - w[1] * c1[0]};
-        J col[3];
+        for (int a = 0; a < 3; ++a) B0[r][a] = Rq[r][a] * kp.s[a];
+    double A0[2][3], D[3][2][3];
 #pragma unroll
-        for (int k = 0; k < 3; ++k) col[k] = (c1[k] + 0.5 * c2[k]) + b[k];
+    for (int i = 0; i < 2; ++i)
 #pragma unroll
-        for (int i = 0; i < 2; ++i) A[i][a] = M[i][0] * col[0] + M[i][1] * col[1] + M[i][2] * col[2];
-    }
-    J Q[3];
-    conic_from_A(A, (double)kappa, Q);
-    double gz[3], Hz[3][3];
-    q_stats(z, gz, Hz);
+        for (int a = 0; a < 3; ++a) A0[i][a] = M[i][0] * B0[0][a] + M[i][1] * B0[1][a] + M[i][2] * B0[2][a];
+#pragma unroll
+    for (int k = 0; k < 3; ++k)
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            // column a of [e_k]_x B0 = e_k x B0[:, a]
+            const double b0 = B0[0][a], b1 = B0[1][a], b2 = B0[2][a];
+            const double cx = k == 0 ? 0.0 : (k == 1 ? b2 : -b1);
+            const double cy = k == 0 ? -b2 : (k == 1 ? 0.0 : b0);
+            const double cz = k == 0 ? b1 : (k == 1 ? -b0 : 0.0);
+#pragma unroll
+            for (int i = 0; i < 2; ++i) D[k][i][a] = M[i][0] * cx + M[i][1] * cy + M[i][2] * cz;
+        }
+    auto E = [&](int i, int j, double out[2][3]) {
+#pragma unroll
+        for (int r = 0; r < 2; ++r)
+#pragma unroll
+            for (int a = 0; a < 3; ++a)
+                out[r][a] = 0.5 * (M[r][j] * B0[i][a] + M[r][i] * B0[j][a]) - (i == j ? A0[r][a] : 0.0);
+    };
+    FJet<3, double> Q[3];
+    conic_jets(A0, D, E, true, (double)kappa, Q);
     chain_accumulate<3, 3, double>(Q, gz, Hz, g, H);
 }

@@ -109,28 +109,35 @@ GSN_HD inline void principal_frame(const T A[2][3], T kappa, T& l1, T& l2, T& c,
 #define SH_C3D 0.37317633259011546f
 #define SH_C3E 1.44530572132027737f
 
-template <class T>
-GSN_HD inline void sh_basis_dev(int K, const T& x, const T& y, const T& z, T* Y) {
-    Y[0] = T(SH_C0);
+// Visits (i, Y_i) for i < K in order, so that callers accumulate without holding an
+// array of basis values (jets of 16 basis functions would not fit in registers).
+template <class T, class F>
+GSN_HD inline void sh_basis_visit(int K, const T& x, const T& y, const T& z, F f) {
+    f(0, T(SH_C0));
     if (K <= 1) return;
-    Y[1] = -SH_C1 * y;
-    Y[2] = SH_C1 * z;
-    Y[3] = -SH_C1 * x;
+    f(1, -SH_C1 * y);
+    f(2, SH_C1 * z);
+    f(3, -SH_C1 * x);
     if (K <= 4) return;
     const T xx = x * x, yy = y * y, zz = z * z;
-    Y[4] = SH_C2A * (x * y);
-    Y[5] = SH_C2A * (y * z);
-    Y[6] = SH_C2B * (2.0f * zz - xx - yy);
-    Y[7] = SH_C2A * (x * z);
-    Y[8] = SH_C2C * (xx - yy);
+    f(4, SH_C2A * (x * y));
+    f(5, SH_C2A * (y * z));
+    f(6, SH_C2B * (2.0f * zz - xx - yy));
+    f(7, SH_C2A * (x * z));
+    f(8, SH_C2C * (xx - yy));
     if (K <= 9) return;
-    Y[9] = SH_C3A * (y * (3.0f * xx - yy));
-    Y[10] = SH_C3B * (x * y * z);
-    Y[11] = SH_C3C * (y * (4.0f * zz - xx - yy));
-    Y[12] = SH_C3D * (z * (2.0f * zz - 3.0f * xx - 3.0f * yy));
-    Y[13] = SH_C3C * (x * (4.0f * zz - xx - yy));
-    Y[14] = SH_C3E * (z * (xx - yy));
-    Y[15] = SH_C3A * (x * (xx - 3.0f * yy));
+    f(9, SH_C3A * (y * (3.0f * xx - yy)));
+    f(10, SH_C3B * (x * y * z));
+    f(11, SH_C3C * (y * (4.0f * zz - xx - yy)));
+    f(12, SH_C3D * (z * (2.0f * zz - 3.0f * xx - 3.0f * yy)));
+    f(13, SH_C3C * (x * (4.0f * zz - xx - yy)));
+    f(14, SH_C3E * (z * (xx - yy)));
+    f(15, SH_C3A * (x * (xx - 3.0f * yy)));
+}
+
+template <class T>
+GSN_HD inline void sh_basis_dev(int K, const T& x, const T& y, const T& z, T* Y) {
+    sh_basis_visit<T>(K, x, y, z, [&](int i, const T& v) { Y[i] = v; });
 }
 
 // ----------------------------------------------------------------------------

@@ -26,7 +26,7 @@ struct gsn_frame {
     DevCam cam{};
     DevRenderOpts ro{};
     // per kernel
-    DevBuf rec;         // float4 [3][n]: (mx, my, qxx, qxy), (qyy, sigma, r, g), (b, -, -, -)
+    DevBuf rec;         // float4 [3][n]: (mx, my, q1, q2), (c, s, sigma, R), (G, B, mx_lo, my_lo)
     DevBuf rect;        // uint2 [n]: (x0 | y0 << 16, x1 | y1 << 16)
     DevBuf depth_key;   // u32 [n], 0xffffffff when culled
     DevBuf ntiles;      // u32 [n]
@@ -45,6 +45,7 @@ struct gsn_frame {
     DevBuf ncontrib;    // u32 [H][W]
     DevBuf dL, hd;      // float [3][H][W] loss maps
     DevBuf coef;        // double [3][8][H][W] SSIM coefficient maps
+    DevBuf zsum;        // double [n][GSN_NZ] per-kernel sums of the pair partials
     DevBuf zstats;      // float [GSN_NZ][n], optional debug copy
     DevBuf loss_part;   // double [2][nblocks]
     // sort / scan scratch

@@ -160,15 +160,12 @@ __global__ __launch_bounds__(kThreads) void preprocess_kernel(
     const float mu_hi = (float)mu, mv_hi = (float)mv;
     const double dx = (double)px - cam.o[0], dy = (double)py - cam.o[1], dz = (double)pz - cam.o[2];
     const double il = 1.0 / sqrt(dx * dx + dy * dy + dz * dz);
-    double Y[16];
-    sh_basis_dev<double>(K, dx * il, dy * il, dz * il, Y);
-    float col[3];
+    double acc[3] = {0.0, 0.0, 0.0};
+    sh_basis_visit<double>(K, dx * il, dy * il, dz * il, [&](int i, double y) {
 #pragma unroll
-    for (int ch = 0; ch < 3; ++ch) {
-        double acc = 0.0;
-        for (int i = 0; i < K; ++i) acc += Y[i] * (double)sh[((size_t)ch * K + i) * n + k];
-        col[ch] = (float)acc;
-    }
+        for (int ch = 0; ch < 3; ++ch) acc[ch] += y * (double)sh[((size_t)ch * K + i) * n + k];
+    });
+    const float col[3] = {(float)acc[0], (float)acc[1], (float)acc[2]};
     rec[k] = make_float4(mu_hi, mv_hi, (float)(1.0 / l1), (float)(1.0 / l2));
     rec[n + k] = make_float4((float)fc, (float)fs, opac[k], col[0]);
     rec[2 * (size_t)n + k] = make_float4(col[1], col[2], (float)(mu - (double)mu_hi), (float)(mv - (double)mv_hi));

@@ -197,6 +197,44 @@ def gpu_blocks_to_summed(gb, V):
     return S
 
 
+def packed_from_sym(M):
+    """[n, 3, 3] symmetric -> packed upper triangle rows [6][n] (row by row)."""
+    return np.stack([M[:, i, j] for i in range(3) for j in range(i, 3)])
+
+
+def summed_to_gpu_blocks(S, V):
+    """The oracle's summed solve layout [n][39 + 10 V] -> the library's block rows [30 + 10 V][n]."""
+    n = S.shape[0]
+    gb = np.zeros((30 + 10 * V, n))
+    gb[0:3] = S[:, 0:3].T
+    gb[3:9] = packed_from_sym(S[:, 3:12].reshape(n, 3, 3))
+    gb[9:12] = S[:, 12:15].T
+    gb[12:18] = packed_from_sym(S[:, 15:24].reshape(n, 3, 3))
+    gb[18:21] = S[:, 24:27].T
+    gb[21:27] = packed_from_sym(S[:, 27:36].reshape(n, 3, 3))
+    gb[27], gb[28], gb[29] = S[:, 36], S[:, 37], S[:, 38]
+    for v in range(V):
+        gb[30 + 10 * v:40 + 10 * v] = S[:, 39 + 10 * v:49 + 10 * v].T
+    return gb
+
+
+def oracle_frames(g, cam, kappa=0.3):
+    """Principal frame (c, s) of each kernel's FP64 projected covariance: e1 = (c, s) is the
+    eigenvector of the larger eigenvalue, picked from the better conditioned of the two
+    eigenvector formulas (the convention the library's records state)."""
+    out, _ = O.project64(g, cam, kappa=kappa)
+    sxx, sxy, syy = out[:, 2], out[:, 3], out[:, 4]
+    half = 0.5 * (sxx - syy)
+    l1 = 0.5 * (sxx + syy) + np.sqrt(half * half + sxy * sxy)
+    vx, vy = l1 - syy, sxy.copy()
+    alt = np.abs(sxy) + np.abs(l1 - sxx) > np.abs(vx) + np.abs(vy)
+    vx = np.where(alt, sxy, vx)
+    vy = np.where(alt, l1 - sxx, vy)
+    nn = np.hypot(vx, vy)
+    safe = np.where(nn > 0, nn, 1.0)
+    return np.where(nn > 0, vx / safe, 1.0), np.where(nn > 0, vy / safe, 0.0)
+
+
 def step_sensitivity(g, cam, o, summed, V, rel=1e-5, trials=4, seed=0):
     """Per kernel and group, the largest change of the oracle's step when its inputs carry
     relative noise `rel` (the precision the blocks are required to have), divided by the
