@@ -105,6 +105,7 @@ __global__ __launch_bounds__(GSN_BLOCK) void raster_bwd_kernel(
     unsigned long long* __restrict__ counts) {
     __shared__ float4 r_a[BS], r_b[BS];
     __shared__ float4 r_c[BS];
+    __shared__ float4 r_box[BS];
     __shared__ uint32_t r_slot[BS];
     __shared__ float s_dl[3][GSN_BLOCK], s_h[3][GSN_BLOCK];
     __shared__ uint64_t s_mask[BS][GSN_BLOCK / 64];
@@ -120,6 +121,8 @@ __global__ __launch_bounds__(GSN_BLOCK) void raster_bwd_kernel(
     const int py = ty * GSN_TILE + (tid / GSN_TILE);
     const bool inside = px < cam.W && py < cam.H;
     const int lane = __lane_id(), wave = tid / 64;
+    const float wx0 = (float)(tx * GSN_TILE), wx1 = wx0 + (float)(GSN_TILE - 1);
+    const float wy0 = (float)(ty * GSN_TILE + wave * 4), wy1 = wy0 + 3.0f;
     const uint64_t lt_mask = lane == 0 ? 0ull : (~0ull >> (64 - lane));
     const uint2 rg = ranges[tile];
     const size_t np = (size_t)cam.W * cam.H, pi = (size_t)py * cam.W + px;
@@ -153,6 +156,7 @@ __global__ __launch_bounds__(GSN_BLOCK) void raster_bwd_kernel(
             r_a[tid] = rec[id];
             r_b[tid] = rec[n + id];
             r_c[tid] = rec[2 * (size_t)n + id];
+            r_box[tid] = splat_alpha_box(r_a[tid], r_b[tid], r_c[tid], ro.alpha_min);
             const uint2 rc = rect[id];
             const uint32_t x0 = rc.x & 0xffffu, y0 = rc.x >> 16, x1 = rc.y & 0xffffu;
             r_slot[tid] = pair_off[id] + ((uint32_t)ty - y0) * (x1 - x0) + ((uint32_t)tx - x0);
@@ -162,6 +166,8 @@ __global__ __launch_bounds__(GSN_BLOCK) void raster_bwd_kernel(
         uint32_t bits = 0;
         for (int j = 0; j < cnt; ++j) {
             if (pos + j - rg.x >= nc) break;
+            if (box_misses(r_box[j], wx0, wx1, wy0, wy1)) continue;  // uniform across the wave
+            ++n_eval;
             const SplatEval ev = eval_splat(r_a[j], r_b[j], r_c[j], fpx, fpy, ro.alpha_max);
             if (ev.alpha >= ro.alpha_min) bits |= 1u << j;
         }
@@ -198,7 +204,6 @@ __global__ __launch_bounds__(GSN_BLOCK) void raster_bwd_kernel(
         // (c) front to back over the pixel's active entries of the prefix
         for (int j = 0; j < J; ++j) {
             if (pos + j - rg.x >= nc) break;
-            ++n_eval;
             if (!((bits >> j) & 1u)) continue;
             ++n_act;
             const float4 b = r_b[j], cc = r_c[j];

@@ -62,6 +62,28 @@ __device__ __forceinline__ SplatEval eval_splat(const float4 a, const float4 b, 
     return e;
 }
 
+// Axis-aligned box (x_lo, x_hi, y_lo, y_hi), in pixel coordinates, that holds every
+// pixel centre at which the splat can reach alpha >= alpha_min: the ellipse
+// d'^T Q' d' <= 2 ln(sigma / alpha_min), widened by a relative 1e-3 and 0.02 px so
+// that single-precision rounding of the per-pixel test can never reach outside it.
+// A splat with sigma < alpha_min composites nowhere (empty box).  Used to skip list
+// entries for a whole wave without changing any per-pixel decision.
+__device__ __forceinline__ float4 splat_alpha_box(const float4 a, const float4 b, const float4 c4, float alpha_min) {
+    const float sig = b.z;
+    if (!(sig >= alpha_min)) return make_float4(1.f, -1.f, 1.f, -1.f);
+    const float r2 = 2.0f * __logf(sig / alpha_min);
+    const float c = b.x, s = b.y, i1 = 1.0f / a.z, i2 = 1.0f / a.w;
+    const float ex = sqrtf(fmaxf(r2, 0.f) * (c * c * i1 + s * s * i2)) * 1.001f + 0.02f;
+    const float ey = sqrtf(fmaxf(r2, 0.f) * (s * s * i1 + c * c * i2)) * 1.001f + 0.02f;
+    const float mx = a.x + c4.z, my = a.y + c4.w;
+    return make_float4(mx - ex, mx + ex, my - ey, my + ey);
+}
+
+// True when the box misses the pixel rows y0..y1 and columns x0..x1 (inclusive).
+__device__ __forceinline__ bool box_misses(const float4 box, float x0, float x1, float y0, float y1) {
+    return box.y < x0 || box.x > x1 || box.w < y0 || box.z > y1;
+}
+
 // Principal frame of Sigma = A A^T + kappa I (A = J W R S, 2x3): eigenvalues from the
 // trace and the Cauchy-Binet determinant (sum of squared 2x2 minors), the minor one as
 // det / lambda1 so that neither cancels.

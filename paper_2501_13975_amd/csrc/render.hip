@@ -386,12 +386,16 @@ __global__ __launch_bounds__(GSN_BLOCK) void raster_fwd_kernel(
     __shared__ float4 s_a[GSN_BLOCK];
     __shared__ float4 s_b[GSN_BLOCK];
     __shared__ float4 s_c[GSN_BLOCK];
+    __shared__ float4 s_box[GSN_BLOCK];
     const int tile = blockIdx.x;
     const int tx = tile % cam.tiles_x, ty = tile / cam.tiles_x;
     const int px = tx * GSN_TILE + (threadIdx.x % GSN_TILE);
     const int py = ty * GSN_TILE + (threadIdx.x / GSN_TILE);
     const bool inside = px < cam.W && py < cam.H;
     const uint2 rg = ranges[tile];
+    // the wave's pixel block: 16 columns by 4 rows
+    const float wx0 = (float)(tx * GSN_TILE), wx1 = wx0 + (float)(GSN_TILE - 1);
+    const float wy0 = (float)(ty * GSN_TILE + (threadIdx.x / 64) * 4), wy1 = wy0 + 3.0f;
     // colour accumulated in double: the backward pass subtracts partial sums from it
     float T = 1.0f;
     double C0 = 0.0, C1 = 0.0, C2 = 0.0;
@@ -407,10 +411,12 @@ __global__ __launch_bounds__(GSN_BLOCK) void raster_fwd_kernel(
             s_a[threadIdx.x] = rec[id];
             s_b[threadIdx.x] = rec[n + id];
             s_c[threadIdx.x] = rec[2 * (size_t)n + id];
+            s_box[threadIdx.x] = splat_alpha_box(s_a[threadIdx.x], s_b[threadIdx.x], s_c[threadIdx.x], ro.alpha_min);
         }
         __syncthreads();
         const int cnt = min((uint32_t)GSN_BLOCK, rg.y - base);
         for (int j = 0; j < cnt && !done; ++j) {
+            if (box_misses(s_box[j], wx0, wx1, wy0, wy1)) continue;  // uniform across the wave
             const float4 a = s_a[j], b = s_b[j], cc = s_c[j];
             const SplatEval ev = eval_splat(a, b, cc, fpx, fpy, ro.alpha_max);
             ++evals;
