@@ -308,9 +308,14 @@ gsn_status gsn_render(gsn_ctx* ctx, const gsn_gaussians* g, const gsn_camera* ca
     HIP_TRY(ctx, buf_reserve(f->pv_a, pp * 4));
     HIP_TRY(ctx, buf_reserve(f->pk_b, pp * 4));
     HIP_TRY(ctx, buf_reserve(f->pv_b, pp * 4));
+    // per-pair statistics of the backward pass and their written-flags (cleared once per render: which
+    // slots the backward pass writes depends only on this render, not on the loss)
+    HIP_TRY(ctx, buf_reserve(f->partial, pp * GSN_NZ * 4));
+    HIP_TRY(ctx, buf_reserve(f->flags, (pp + 3) / 4 * 4));
     {
         // 4. pairs in depth order, then a stable partition by tile id
         StageTimer st_(ctx, GSN_STAGE_SORT);
+        launch_fill_u32(bp<uint32_t>(f->flags), 0u, (pp + 3) / 4, s);
         launch_emit_pairs(bp<uint32_t>(f->ids_a), bp<uint32_t>(f->offsets), (uint32_t)n, bp<uint2>(f->rect),
                           (uint32_t)f->tiles_x, bp<uint32_t>(f->pk_a), bp<uint32_t>(f->pv_a),
                           bp<uint32_t>(f->pair_off), s);
@@ -364,9 +369,6 @@ gsn_status gsn_accumulate_hessian(gsn_ctx* ctx, const gsn_gaussians* g, const gs
         if (d_loss_out) launch_loss_reduce(bp<double>(f->loss_part), np_out, f->W, f->H, d_loss_out, s);
         HIP_TRY(ctx, hipGetLastError());
     }
-    const size_t pp = std::max<size_t>((size_t)f->pairs, 1);
-    HIP_TRY(ctx, buf_reserve(f->partial, pp * GSN_NZ * 4));
-    HIP_TRY(ctx, buf_reserve(f->flags, (pp + 3) / 4 * 4));
     HIP_TRY(ctx, buf_reserve(f->zsum, (size_t)std::max(f->n, 1) * GSN_NZ * 8));
     float* zs = nullptr;
     if (opts->keep_zstats) {
@@ -375,7 +377,6 @@ gsn_status gsn_accumulate_hessian(gsn_ctx* ctx, const gsn_gaussians* g, const gs
     }
     {
         StageTimer st_(ctx, GSN_STAGE_RASTER_BWD);
-        launch_fill_u32(bp<uint32_t>(f->flags), 0u, (pp + 3) / 4, s);
         if (f->pairs > 0) launch_raster_bwd(*f, bp<float>(f->dL), bp<float>(f->hd), prof_counts(ctx), s);
     }
     {

@@ -36,9 +36,9 @@
 
 namespace {
 
-constexpr int BS = 32;      // list entries examined per round
-constexpr int PMAX = 2048;  // active (pixel, entry) pairs staged per round
-constexpr int GRP = 8;      // threads that sum one entry's pairs
+constexpr int PMAX = 896;   // composited (pixel, entry) pairs staged per round
+constexpr int GRP = 4;      // threads that sum one small entry's pairs
+constexpr int BIG = 32;     // entries with more pairs are summed by a whole wave
 
 // Contribution of one active (pixel, splat) pair to the 44 statistics (see the header comment).
 __device__ __forceinline__ void pair_terms(const float4 a, const float4 b, float G, float T, const float av[3],
@@ -87,33 +87,70 @@ __device__ __forceinline__ void pair_terms(const float4 a, const float4 b, float
     z[42] = A2 * G * G;
 }
 
-// One workgroup per tile.  Each round examines up to BS list entries:
-//  (a) every pixel evaluates which of them it composited (alpha >= alpha_min and
-//      before its stopping entry) -> one ballot mask per (entry, wave);
-//  (b) a scan over (entry, wave) gives every active (pixel, entry) pair a slot in
-//      LDS; the round keeps the longest prefix of entries whose pairs fit;
-//  (c) every pixel walks its active entries front to back (transmittance, colour
-//      behind the splat) and stores (T, G, a_R, a_G, a_B) in the pair's slot;
-//  (d) GRP threads per entry sum the 44 statistics over that entry's pairs in
-//      double, in pixel order, and write the tile's partial sum at the
-//      (tile, kernel) pair's slot.  Only contributing pairs do the 44-term work.
-__global__ __launch_bounds__(GSN_BLOCK) void raster_bwd_kernel(
+// Adds the statistics of staged pair i (slot in LDS) of the splat (a, b, c4) to acc.
+__device__ __forceinline__ void pair_stats(const float4 a, const float4 b, const float4 cl, const float4* s_pa,
+                                           const float* s_pb, const uint8_t* s_pix, const float (*s_dl)[GSN_BLOCK],
+                                           const float (*s_h)[GSN_BLOCK], uint32_t i, int tx, int ty, float amax,
+                                           float* acc) {
+    const float4 pa = s_pa[i];
+    const int p = s_pix[i];
+    const float av[3] = {pa.z, pa.w, s_pb[i]};
+    const float dl[3] = {s_dl[0][p], s_dl[1][p], s_dl[2][p]};
+    const float hh[3] = {s_h[0][p], s_h[1][p], s_h[2][p]};
+    const float ddx = (a.x - (float)(tx * GSN_TILE + (p % GSN_TILE))) + cl.z;
+    const float ddy = (a.y - (float)(ty * GSN_TILE + (p / GSN_TILE))) + cl.w;
+    const float d1 = b.x * ddx + b.y * ddy, d2 = b.x * ddy - b.y * ddx;
+    float z[GSN_NZ];
+    pair_terms(a, b, pa.y, pa.x, av, d1, d2, dl, hh, amax, z);
+#pragma unroll
+    for (int f = 0; f < GSN_NZ; ++f) acc[f] += z[f];
+}
+
+__device__ __forceinline__ void write_partial(float* __restrict__ partial, uint8_t* __restrict__ flags, uint32_t slot,
+                                              const float* acc) {
+    float4* dst = reinterpret_cast<float4*>(partial + (size_t)slot * GSN_NZ);
+#pragma unroll
+    for (int f = 0; f < GSN_NZ / 4; ++f) dst[f] = make_float4(acc[4 * f], acc[4 * f + 1], acc[4 * f + 2], acc[4 * f + 3]);
+    flags[slot] = 1;
+}
+
+// One workgroup per tile.  List entries are staged in LDS in batches of 256 (one per
+// thread, with each entry's alpha-support box tested against the four 16 x 4 pixel
+// bands of the tile's waves, giving each wave the ordered list of entries that may
+// composite in it).  Per batch:
+//  (a) every pixel evaluates its wave's entries that come before its stopping entry:
+//      a 256-bit mask of composited entries per pixel, and one ballot per
+//      (entry, wave);
+// then, in rounds that each take the longest run of entries whose composited
+// (pixel, entry) pairs fit in LDS (usually the whole batch):
+//  (b) a block scan over the (entry, wave) ballot counts gives every pair a slot;
+//  (c) every pixel walks its composited entries front to back (transmittance,
+//      colour behind the splat) and stores (T, G, a_R, a_G, a_B) in the pair's slot;
+//  (d) for every entry with pairs, the 44 statistics are summed over its pairs in a
+//      fixed order (GRP threads per entry, or a whole wave for an entry with more
+//      than BIG pairs) and the tile's partial sum is written at the (tile, kernel)
+//      pair's slot.  Only contributing pairs do the 44-term work.
+__global__ __launch_bounds__(GSN_BLOCK, 3) void raster_bwd_kernel(
     const uint2* __restrict__ ranges, const uint32_t* __restrict__ ids, const float4* __restrict__ rec,
     const uint2* __restrict__ rect, const uint32_t* __restrict__ pair_off, uint32_t n, DevCam cam, DevRenderOpts ro,
     const double* __restrict__ img64, const uint32_t* __restrict__ ncontrib, const float* __restrict__ dLm,
     const float* __restrict__ hdm, float* __restrict__ partial, uint8_t* __restrict__ flags,
     unsigned long long* __restrict__ counts) {
-    __shared__ float4 r_a[BS], r_b[BS];
-    __shared__ float4 r_c[BS];
-    __shared__ float4 r_box[BS];
-    __shared__ uint32_t r_slot[BS];
+    constexpr int NW = GSN_BLOCK / 64;
+    __shared__ float4 r_a[GSN_BLOCK], r_b[GSN_BLOCK], r_c[GSN_BLOCK];
+    __shared__ uint32_t r_slot[GSN_BLOCK];
+    __shared__ uint8_t r_list[NW][GSN_BLOCK];
+    __shared__ uint32_t r_cnt[NW][NW];  // [band][loader wave]
     __shared__ float s_dl[3][GSN_BLOCK], s_h[3][GSN_BLOCK];
-    __shared__ uint64_t s_mask[BS][GSN_BLOCK / 64];
-    __shared__ uint32_t s_off[BS * (GSN_BLOCK / 64) + 1];
+    __shared__ uint64_t s_mask[GSN_BLOCK][NW];
+    __shared__ uint32_t s_off[GSN_BLOCK * NW + 1];
+    __shared__ uint32_t s_wsum[NW];
+    __shared__ uint8_t s_act[GSN_BLOCK];  // entries of the round with pairs, at most BIG of them
+    __shared__ uint32_t s_nact[NW];
     __shared__ float4 s_pa[PMAX];
     __shared__ float s_pb[PMAX];
     __shared__ uint8_t s_pix[PMAX];
-    __shared__ uint32_t s_max, s_J;
+    __shared__ uint32_t s_max;
     const int tid = threadIdx.x;
     const int tile = blockIdx.x;
     const int tx = tile % cam.tiles_x, ty = tile / cam.tiles_x;
@@ -121,8 +158,8 @@ __global__ __launch_bounds__(GSN_BLOCK) void raster_bwd_kernel(
     const int py = ty * GSN_TILE + (tid / GSN_TILE);
     const bool inside = px < cam.W && py < cam.H;
     const int lane = __lane_id(), wave = tid / 64;
-    const float wx0 = (float)(tx * GSN_TILE), wx1 = wx0 + (float)(GSN_TILE - 1);
-    const float wy0 = (float)(ty * GSN_TILE + wave * 4), wy1 = wy0 + 3.0f;
+    const float tx0 = (float)(tx * GSN_TILE), tx1 = tx0 + (float)(GSN_TILE - 1);
+    const float ty0 = (float)(ty * GSN_TILE);
     const uint64_t lt_mask = lane == 0 ? 0ull : (~0ull >> (64 - lane));
     const uint2 rg = ranges[tile];
     const size_t np = (size_t)cam.W * cam.H, pi = (size_t)py * cam.W + px;
@@ -149,120 +186,199 @@ __global__ __launch_bounds__(GSN_BLOCK) void raster_bwd_kernel(
     double Ca0 = 0.0, Ca1 = 0.0, Ca2 = 0.0;
     const float fpx = (float)px, fpy = (float)py;
     uint32_t n_eval = 0, n_act = 0;
-    for (uint32_t pos = rg.x; pos < end;) {
-        const int cnt = (int)min((uint32_t)BS, end - pos);
-        if (tid < cnt) {
-            const uint32_t id = ids[pos + tid];
-            r_a[tid] = rec[id];
-            r_b[tid] = rec[n + id];
-            r_c[tid] = rec[2 * (size_t)n + id];
-            r_box[tid] = splat_alpha_box(r_a[tid], r_b[tid], r_c[tid], ro.alpha_min);
+    for (uint32_t base = rg.x; base < end; base += GSN_BLOCK) {
+        const int bcnt = (int)min((uint32_t)GSN_BLOCK, end - base);
+        // stage the batch: one entry per thread, its slot and its band mask
+#pragma unroll
+        for (int w = 0; w < NW; ++w) s_mask[tid][w] = 0ull;
+        uint32_t bandmask = 0;
+        if (tid < bcnt) {
+            const uint32_t id = ids[base + tid];
+            const float4 a = rec[id], b = rec[n + id], c4 = rec[2 * (size_t)n + id];
+            r_a[tid] = a;
+            r_b[tid] = b;
+            r_c[tid] = c4;
+            const float4 box = splat_alpha_box(a, b, c4, ro.alpha_min);
+#pragma unroll
+            for (int w = 0; w < NW; ++w)
+                if (!box_misses(box, tx0, tx1, ty0 + 4.f * w, ty0 + 4.f * w + 3.f)) bandmask |= 1u << w;
             const uint2 rc = rect[id];
             const uint32_t x0 = rc.x & 0xffffu, y0 = rc.x >> 16, x1 = rc.y & 0xffffu;
             r_slot[tid] = pair_off[id] + ((uint32_t)ty - y0) * (x1 - x0) + ((uint32_t)tx - x0);
         }
+        uint64_t bal[NW];
+#pragma unroll
+        for (int w = 0; w < NW; ++w) {
+            bal[w] = __ballot((bandmask >> w) & 1u);
+            if (lane == 0) r_cnt[w][wave] = (uint32_t)__popcll(bal[w]);
+        }
         __syncthreads();
-        // (a) which of the round's entries this pixel composited
-        uint32_t bits = 0;
-        for (int j = 0; j < cnt; ++j) {
-            if (pos + j - rg.x >= nc) break;
-            if (box_misses(r_box[j], wx0, wx1, wy0, wy1)) continue;  // uniform across the wave
+#pragma unroll
+        for (int w = 0; w < NW; ++w) {
+            if ((bandmask >> w) & 1u) {
+                uint32_t off = 0;
+#pragma unroll
+                for (int v = 0; v < NW; ++v) off += v < wave ? r_cnt[w][v] : 0u;
+                r_list[w][off + (uint32_t)__popcll(bal[w] & lt_mask)] = (uint8_t)tid;
+            }
+        }
+        uint32_t nl = 0;
+#pragma unroll
+        for (int v = 0; v < NW; ++v) nl += r_cnt[wave][v];
+        __syncthreads();
+        // (a) which of the batch's entries this pixel composited (256-bit mask, word by word)
+        uint64_t bits[NW] = {0ull, 0ull, 0ull, 0ull};
+        for (uint32_t i = 0; i < nl; ++i) {
+            const int j = r_list[wave][i];
+            if (base + j - rg.x >= nc) break;
             ++n_eval;
             const SplatEval ev = eval_splat(r_a[j], r_b[j], r_c[j], fpx, fpy, ro.alpha_max);
-            if (ev.alpha >= ro.alpha_min) bits |= 1u << j;
+            if (ev.alpha >= ro.alpha_min) {
+#pragma unroll
+                for (int w = 0; w < NW; ++w)
+                    if ((j >> 6) == w) bits[w] |= 1ull << (j & 63);
+            }
         }
-        for (int j = 0; j < cnt; ++j) {
-            const uint64_t m = __ballot((bits >> j) & 1u);
+        for (uint32_t i = 0; i < nl; ++i) {  // uniform across the wave
+            const int j = r_list[wave][i];
+            uint64_t word = 0;
+#pragma unroll
+            for (int w = 0; w < NW; ++w)
+                if ((j >> 6) == w) word = bits[w];
+            const uint64_t m = __ballot((word >> (j & 63)) & 1ull);
             if (lane == 0) s_mask[j][wave] = m;
         }
         __syncthreads();
-        // (b) slots: exclusive scan of the pair counts in (entry, wave) order, by wave 0
-        if (wave == 0) {
-            const int e0 = 2 * lane, e1 = 2 * lane + 1;  // 128 (entry, wave) cells, two per lane
-            const uint32_t c0 = (e0 / 4 < cnt) ? (uint32_t)__popcll(s_mask[e0 / 4][e0 % 4]) : 0u;
-            const uint32_t c1 = (e1 / 4 < cnt) ? (uint32_t)__popcll(s_mask[e1 / 4][e1 % 4]) : 0u;
-            uint32_t v = c0 + c1;
+        for (int r0 = 0; r0 < bcnt;) {
+            // (b) slots: block-wide exclusive scan of the pair counts of entries r0.. in (entry, wave) order;
+            // thread t owns the four cells of entry t
+            {
+                uint32_t c[NW], tot = 0;
 #pragma unroll
-            for (int d = 1; d < 64; d <<= 1) {
-                const uint32_t o = __shfl_up(v, d, 64);
-                if (lane >= d) v += o;
+                for (int w = 0; w < NW; ++w) {
+                    c[w] = tid >= r0 ? (uint32_t)__popcll(s_mask[tid][w]) : 0u;
+                    tot += c[w];
+                }
+                uint32_t v = tot;
+#pragma unroll
+                for (int d = 1; d < 64; d <<= 1) {
+                    const uint32_t o = __shfl_up(v, d, 64);
+                    if (lane >= d) v += o;
+                }
+                if (lane == 63) s_wsum[wave] = v;
+                __syncthreads();
+                uint32_t sb = 0;
+#pragma unroll
+                for (int w = 0; w < NW; ++w) sb += w < wave ? s_wsum[w] : 0u;
+                uint32_t o = sb + v - tot;
+#pragma unroll
+                for (int w = 0; w < NW; ++w) {
+                    s_off[tid * NW + w] = o;
+                    o += c[w];
+                }
+                if (tid == GSN_BLOCK - 1) s_off[GSN_BLOCK * NW] = o;
             }
-            const uint32_t excl = v - (c0 + c1);
-            s_off[e0] = excl;
-            s_off[e1] = excl + c0;
-            if (lane == 63) s_off[BS * 4] = v;
-        }
-        __syncthreads();
-        if (tid == 0) {
-            // longest prefix of entries whose pairs fit in PMAX (one entry has at most 256)
-            int J = cnt;
-            while (s_off[J * 4] > (uint32_t)PMAX) --J;
-            s_J = (uint32_t)J;
-        }
-        __syncthreads();
-        const int J = (int)s_J;
-        // (c) front to back over the pixel's active entries of the prefix
-        for (int j = 0; j < J; ++j) {
-            if (pos + j - rg.x >= nc) break;
-            if (!((bits >> j) & 1u)) continue;
-            ++n_act;
-            const float4 b = r_b[j], cc = r_c[j];
-            const SplatEval ev = eval_splat(r_a[j], b, cc, fpx, fpy, ro.alpha_max);
-            const float al = ev.alpha, wT = al * T;
-            const double wd = (double)wT;
-            Ca0 += wd * (double)b.w;
-            Ca1 += wd * (double)cc.x;
-            Ca2 += wd * (double)cc.y;
-            const float inv = 1.0f / (1.0f - al);
-            const uint32_t slot = s_off[j * 4 + wave] + (uint32_t)__popcll(s_mask[j][wave] & lt_mask);
-            s_pa[slot] = make_float4(T, ev.G, T * b.w - (float)(cf[0] - Ca0) * inv, T * cc.x - (float)(cf[1] - Ca1) * inv);
-            s_pb[slot] = T * cc.y - (float)(cf[2] - Ca2) * inv;
-            s_pix[slot] = (uint8_t)tid;
-            T *= (1.0f - al);
-        }
-        __syncthreads();
-        // (d) GRP threads per entry accumulate its pairs in double, in pixel order
-        {
-            const int e = tid / GRP, r = tid % GRP;
-            double acc[GSN_NZ];
+            __syncthreads();
+            // the round takes entries r0..r1-1: the largest r1 <= bcnt with s_off[r1 * NW] <= PMAX
+            // (one entry has at most 256 pairs, so r1 > r0)
+            int lo = r0 + 1, hi = bcnt;
+            while (lo < hi) {
+                const int mid = (lo + hi + 1) >> 1;
+                if (s_off[mid * NW] <= (uint32_t)PMAX) lo = mid; else hi = mid - 1;
+            }
+            const int r1 = lo;
+            // (c) front to back over the pixel's composited entries r0..r1-1
 #pragma unroll
-            for (int f = 0; f < GSN_NZ; ++f) acc[f] = 0.0;
-            uint32_t p0 = 0, p1 = 0;
-            if (e < J) {
-                p0 = s_off[e * 4];
-                p1 = s_off[e * 4 + 4];
-                const float4 a = r_a[e], b = r_b[e], cl = r_c[e];
-                for (uint32_t i = p0 + r; i < p1; i += GRP) {
-                    const float4 pa = s_pa[i];
-                    const int p = s_pix[i];
-                    const float av[3] = {pa.z, pa.w, s_pb[i]};
-                    const float dl[3] = {s_dl[0][p], s_dl[1][p], s_dl[2][p]};
-                    const float hh[3] = {s_h[0][p], s_h[1][p], s_h[2][p]};
-                    const float ddx = (a.x - (float)(tx * GSN_TILE + (p % GSN_TILE))) + cl.z;
-                    const float ddy = (a.y - (float)(ty * GSN_TILE + (p / GSN_TILE))) + cl.w;
-                    const float d1 = b.x * ddx + b.y * ddy, d2 = b.x * ddy - b.y * ddx;
-                    float z[GSN_NZ];
-                    pair_terms(a, b, pa.y, pa.x, av, d1, d2, dl, hh, ro.alpha_max, z);
-#pragma unroll
-                    for (int f = 0; f < GSN_NZ; ++f) acc[f] += (double)z[f];
+            for (int w = 0; w < NW; ++w) {
+                const int wlo = w * 64, whi = wlo + 64;
+                if (r1 <= wlo || r0 >= whi) continue;
+                uint64_t rem = bits[w];
+                if (r0 > wlo) rem &= ~0ull << (r0 - wlo);
+                if (r1 < whi) rem &= (1ull << (r1 - wlo)) - 1ull;
+                while (rem) {
+                    const int j = wlo + __ffsll((unsigned long long)rem) - 1;
+                    rem &= rem - 1;
+                    ++n_act;
+                    const float4 b = r_b[j], cc = r_c[j];
+                    const SplatEval ev = eval_splat(r_a[j], b, cc, fpx, fpy, ro.alpha_max);
+                    const float al = ev.alpha, wT = al * T;
+                    const double wd = (double)wT;
+                    Ca0 += wd * (double)b.w;
+                    Ca1 += wd * (double)cc.x;
+                    Ca2 += wd * (double)cc.y;
+                    const float inv = 1.0f / (1.0f - al);
+                    const uint32_t slot = s_off[j * NW + wave] + (uint32_t)__popcll(s_mask[j][wave] & lt_mask);
+                    s_pa[slot] = make_float4(T, ev.G, T * b.w - (float)(cf[0] - Ca0) * inv,
+                                             T * cc.x - (float)(cf[1] - Ca1) * inv);
+                    s_pb[slot] = T * cc.y - (float)(cf[2] - Ca2) * inv;
+                    s_pix[slot] = (uint8_t)tid;
+                    T *= (1.0f - al);
                 }
             }
+            // entries of the round with 1..BIG pairs, compacted in order
+            const uint32_t pc = (tid >= r0 && tid < r1) ? s_off[(tid + 1) * NW] - s_off[tid * NW] : 0u;
+            const bool small = pc > 0 && pc <= (uint32_t)BIG;
+            const uint64_t sbal = __ballot(small);
+            if (lane == 0) s_nact[wave] = (uint32_t)__popcll(sbal);
+            __syncthreads();
+            {
+                uint32_t off = 0, nsmall = 0;
 #pragma unroll
-            for (int off = 1; off < GRP; off <<= 1)
+                for (int w = 0; w < NW; ++w) {
+                    off += w < wave ? s_nact[w] : 0u;
+                    nsmall += s_nact[w];
+                }
+                if (small) s_act[off + (uint32_t)__popcll(sbal & lt_mask)] = (uint8_t)tid;
+                __syncthreads();
+                // (d) small entries: GRP threads each, groups dealt the compacted entries in turn
+                const int grp = tid / GRP, r = tid % GRP;
+                for (uint32_t k0 = 0; k0 < nsmall; k0 += GSN_BLOCK / GRP) {  // uniform across the block
+                    const uint32_t k = k0 + (uint32_t)grp;
+                    float acc[GSN_NZ];
 #pragma unroll
-                for (int f = 0; f < GSN_NZ; ++f) acc[f] += __shfl_xor(acc[f], off, 64);
-            if (e < J && r == 0 && p1 > p0) {
-                const uint32_t slot = r_slot[e];
-                float4* dst = reinterpret_cast<float4*>(partial + (size_t)slot * GSN_NZ);
+                    for (int f = 0; f < GSN_NZ; ++f) acc[f] = 0.f;
+                    int e = 0;
+                    if (k < nsmall) {
+                        e = s_act[k];
+                        const uint32_t q0 = s_off[e * NW], q1 = s_off[(e + 1) * NW];
+                        for (uint32_t i = q0 + r; i < q1; i += GRP)
+                            pair_stats(r_a[e], r_b[e], r_c[e], s_pa, s_pb, s_pix, s_dl, s_h, i, tx, ty, ro.alpha_max,
+                                       acc);
+                    }
 #pragma unroll
-                for (int f = 0; f < GSN_NZ / 4; ++f)
-                    dst[f] = make_float4((float)acc[4 * f], (float)acc[4 * f + 1], (float)acc[4 * f + 2],
-                                         (float)acc[4 * f + 3]);
-                flags[slot] = 1;
+                    for (int off2 = 1; off2 < GRP; off2 <<= 1)
+#pragma unroll
+                        for (int f = 0; f < GSN_NZ; ++f) acc[f] += __shfl_xor(acc[f], off2, 64);
+                    if (k < nsmall && r == 0) write_partial(partial, flags, r_slot[e], acc);
+                }
             }
+            // (d) big entries: a whole wave each, dealt to the waves in turn
+            {
+                int kb = 0;
+                for (int w = 0; w < NW; ++w) {
+                    const int e = w * 64 + lane;
+                    const bool big = e >= r0 && e < r1 && s_off[(e + 1) * NW] - s_off[e * NW] > (uint32_t)BIG;
+                    for (uint64_t m = __ballot(big); m; m &= m - 1, ++kb) {  // uniform across the wave
+                        if (kb % NW != wave) continue;
+                        const int eb = w * 64 + __ffsll((unsigned long long)m) - 1;
+                        float acc[GSN_NZ];
+#pragma unroll
+                        for (int f = 0; f < GSN_NZ; ++f) acc[f] = 0.f;
+                        const uint32_t q0 = s_off[eb * NW], q1 = s_off[(eb + 1) * NW];
+                        for (uint32_t i = q0 + lane; i < q1; i += 64)
+                            pair_stats(r_a[eb], r_b[eb], r_c[eb], s_pa, s_pb, s_pix, s_dl, s_h, i, tx, ty,
+                                       ro.alpha_max, acc);
+#pragma unroll
+                        for (int off2 = 1; off2 < 64; off2 <<= 1)
+#pragma unroll
+                            for (int f = 0; f < GSN_NZ; ++f) acc[f] += __shfl_xor(acc[f], off2, 64);
+                        if (lane == 0) write_partial(partial, flags, r_slot[eb], acc);
+                    }
+                }
+            }
+            r0 = r1;
+            __syncthreads();
         }
-        __syncthreads();
-        pos += (uint32_t)J;
     }
     if (counts) {
         __shared__ unsigned long long s_cnt[2];

@@ -377,25 +377,31 @@ __global__ void tile_ranges_kernel(const uint32_t* __restrict__ keys, uint32_t p
 }
 
 // ---------------------------------------------------------------------------
-// Forward compositing, one workgroup per tile, one thread per pixel.
+// Forward compositing, one workgroup per tile, one thread per pixel.  Records are
+// staged in LDS in batches of 256 list entries; each wave (a band of 16 x 4 pixels)
+// gets the ordered list of the batch's entries whose alpha-support box meets its
+// band, so a wave only steps through entries that can composite in it.
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(GSN_BLOCK) void raster_fwd_kernel(
     const uint2* __restrict__ ranges, const uint32_t* __restrict__ ids, const float4* __restrict__ rec, uint32_t n,
     DevCam cam, DevRenderOpts ro, float* __restrict__ img, double* __restrict__ img64, float* __restrict__ Tfin,
     uint32_t* __restrict__ ncontrib, unsigned long long* __restrict__ counts) {
+    constexpr int NW = GSN_BLOCK / 64;
     __shared__ float4 s_a[GSN_BLOCK];
     __shared__ float4 s_b[GSN_BLOCK];
     __shared__ float4 s_c[GSN_BLOCK];
-    __shared__ float4 s_box[GSN_BLOCK];
+    __shared__ uint8_t s_list[NW][GSN_BLOCK];
+    __shared__ uint32_t s_cnt[NW][NW];  // [band][loader wave]
     const int tile = blockIdx.x;
     const int tx = tile % cam.tiles_x, ty = tile / cam.tiles_x;
     const int px = tx * GSN_TILE + (threadIdx.x % GSN_TILE);
     const int py = ty * GSN_TILE + (threadIdx.x / GSN_TILE);
     const bool inside = px < cam.W && py < cam.H;
     const uint2 rg = ranges[tile];
-    // the wave's pixel block: 16 columns by 4 rows
-    const float wx0 = (float)(tx * GSN_TILE), wx1 = wx0 + (float)(GSN_TILE - 1);
-    const float wy0 = (float)(ty * GSN_TILE + (threadIdx.x / 64) * 4), wy1 = wy0 + 3.0f;
+    const int lane = __lane_id(), wave = threadIdx.x / 64;
+    const uint64_t lt_mask = lane == 0 ? 0ull : (~0ull >> (64 - lane));
+    const float tx0 = (float)(tx * GSN_TILE), tx1 = tx0 + (float)(GSN_TILE - 1);
+    const float ty0 = (float)(ty * GSN_TILE);
     // colour accumulated in double: the backward pass subtracts partial sums from it
     float T = 1.0f;
     double C0 = 0.0, C1 = 0.0, C2 = 0.0;
@@ -406,17 +412,40 @@ __global__ __launch_bounds__(GSN_BLOCK) void raster_fwd_kernel(
     for (uint32_t base = rg.x; base < rg.y; base += GSN_BLOCK) {
         if (__syncthreads_count(done) == GSN_BLOCK) break;
         const uint32_t e = base + threadIdx.x;
+        uint32_t bandmask = 0;
         if (e < rg.y) {
             const uint32_t id = ids[e];
-            s_a[threadIdx.x] = rec[id];
-            s_b[threadIdx.x] = rec[n + id];
-            s_c[threadIdx.x] = rec[2 * (size_t)n + id];
-            s_box[threadIdx.x] = splat_alpha_box(s_a[threadIdx.x], s_b[threadIdx.x], s_c[threadIdx.x], ro.alpha_min);
+            const float4 a = rec[id], b = rec[n + id], c4 = rec[2 * (size_t)n + id];
+            s_a[threadIdx.x] = a;
+            s_b[threadIdx.x] = b;
+            s_c[threadIdx.x] = c4;
+            const float4 box = splat_alpha_box(a, b, c4, ro.alpha_min);
+#pragma unroll
+            for (int w = 0; w < NW; ++w)
+                if (!box_misses(box, tx0, tx1, ty0 + 4.f * w, ty0 + 4.f * w + 3.f)) bandmask |= 1u << w;
+        }
+        uint64_t bal[NW];
+#pragma unroll
+        for (int w = 0; w < NW; ++w) {
+            bal[w] = __ballot((bandmask >> w) & 1u);
+            if (lane == 0) s_cnt[w][wave] = (uint32_t)__popcll(bal[w]);
         }
         __syncthreads();
-        const int cnt = min((uint32_t)GSN_BLOCK, rg.y - base);
-        for (int j = 0; j < cnt && !done; ++j) {
-            if (box_misses(s_box[j], wx0, wx1, wy0, wy1)) continue;  // uniform across the wave
+#pragma unroll
+        for (int w = 0; w < NW; ++w) {
+            if ((bandmask >> w) & 1u) {
+                uint32_t off = 0;
+#pragma unroll
+                for (int v = 0; v < NW; ++v) off += v < wave ? s_cnt[w][v] : 0u;
+                s_list[w][off + (uint32_t)__popcll(bal[w] & lt_mask)] = (uint8_t)threadIdx.x;
+            }
+        }
+        __syncthreads();
+        uint32_t nl = 0;
+#pragma unroll
+        for (int v = 0; v < NW; ++v) nl += s_cnt[wave][v];
+        for (uint32_t i = 0; i < nl && !done; ++i) {
+            const int j = s_list[wave][i];
             const float4 a = s_a[j], b = s_b[j], cc = s_c[j];
             const SplatEval ev = eval_splat(a, b, cc, fpx, fpy, ro.alpha_max);
             ++evals;
