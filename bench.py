@@ -25,18 +25,32 @@ sys.path.insert(0, ROOT)
 
 METRIC = "Newton sweeps/s, 1M Gaussians @1080p: plain FP32 vs mixed+learned at equal PSNR"
 
-# Peak figures of one MI355X (published): HBM3E bandwidth and the FP32 vector rate.
+# Peak figures of one MI355X.  HBM3E: 8 TB/s (published).  Vector ALU: 256 CUs x 4 SIMDs x
+# 16 lanes x 2 FLOP per FMA x 2.4 GHz = 78.6 TFLOP/s for unpacked FP32 and for FP64; the
+# published 157.3 TFLOP/s FP32 figure needs packed FP32 instructions, which this library is
+# built without.
 PEAK_HBM_GBS = 8000.0
-PEAK_FP32_TFLOPS = 157.3
+PEAK_ALU_TFLOPS = 78.6
 
-# Algorithmic FLOPs per unit of work, counted from the kernel sources (see DESIGN.md):
-#   forward: per (pixel, list entry) evaluation of the splat (offset, frame rotation,
-#            quadratic form, exp, alpha, threshold tests) and per contribution the blend.
-#   backward: the same evaluation, and per contributing (pixel, splat) pair the
-#            44 projected-space gradient/Hessian terms.
+# Algorithmic FLOPs per unit of work, counted from the kernel sources:
+#   one (pixel, list entry) evaluation of a splat: offset with the mean's low word (4),
+#     rotation into the principal frame (6), quadratic form and exponent scale (6), exp (1),
+#     times opacity (1) = 18;
+#   one forward contribution: transmittance update (2), alpha T (1), three double
+#     colour accumulations (6) = 9;
+#   one backward contributing (pixel, splat) pair: transmittance and colour-behind bookkeeping
+#     with the alpha derivatives a_ch (35), offsets in the principal frame (10), the 44
+#     projected-space terms (115) and their accumulation (44) = 204.
 FLOP_EVAL = 18
 FLOP_FWD_BLEND = 9
-FLOP_BWD_TERMS = 156
+FLOP_BWD_PAIR = 204
+# Bytes one backward launch must move per unit: a staged list entry reads its 48-byte record,
+# 8-byte rectangle and 4-byte pair offset (60); a written (tile, kernel) partial is 44 floats
+# plus its flag (177); per pixel the loss gradient and Hessian maps (6 floats), the final colour
+# (3 doubles) and the stopping index (52).
+BYTES_BWD_ENTRY = 60
+BYTES_BWD_PARTIAL = 177
+BYTES_BWD_PIXEL = 52
 
 
 def log(msg):
@@ -93,29 +107,33 @@ def gpu_run(args):
     return elapsed, stages, counts, loss, cfg
 
 
-def roofline(stages, counts, steps):
-    """Roofline figure of the stage that takes the most time."""
+def roofline(stages, counts, steps, pixels_per_step):
+    """Roofline figure of the stage that takes the most time (one kernel per stage launch)."""
     dom = max(stages, key=lambda s: stages[s][0])
     ms, launches = stages[dom]
-    per_launch_s = ms * 1e-3 / max(launches, 1)
-    if dom == "raster_bwd":
-        flops = FLOP_EVAL * counts["bwd_evals"] + FLOP_BWD_TERMS * counts["bwd_active"]
-        achieved = flops / max(launches, 1) / per_launch_s / 1e12
-        return dict(kernel="raster_bwd", bound="alu", achieved=round(achieved, 3), peak=PEAK_FP32_TFLOPS,
-                    unit="TFLOP/s", frac=round(achieved / PEAK_FP32_TFLOPS, 5), traffic=None,
-                    avg_launch_ms=round(ms / max(launches, 1), 4), launches=launches)
-    if dom == "raster_fwd":
-        flops = FLOP_EVAL * counts["fwd_evals"] + FLOP_FWD_BLEND * counts["bwd_active"]
-        achieved = flops / max(launches, 1) / per_launch_s / 1e12
-        return dict(kernel="raster_fwd", bound="alu", achieved=round(achieved, 3), peak=PEAK_FP32_TFLOPS,
-                    unit="TFLOP/s", frac=round(achieved / PEAK_FP32_TFLOPS, 5), traffic=None,
-                    avg_launch_ms=round(ms / max(launches, 1), 4), launches=launches)
+    launches = max(launches, 1)
+    per_launch_s = ms * 1e-3 / launches
+    out = dict(kernel=dom, avg_launch_ms=round(ms / launches, 4), launches=launches)
+    if dom in ("raster_bwd", "raster_fwd"):
+        if dom == "raster_bwd":
+            flops = FLOP_EVAL * counts["bwd_evals"] + FLOP_BWD_PAIR * counts["bwd_active"]
+            nbytes = (BYTES_BWD_ENTRY * counts["pairs"] + BYTES_BWD_PARTIAL * counts["partials"]
+                      + BYTES_BWD_PIXEL * pixels_per_step * steps)
+            out["algorithmic_bytes_per_launch"] = round(nbytes / launches)
+            out["hbm_fraction"] = round(nbytes / launches / per_launch_s / 1e9 / PEAK_HBM_GBS, 5)
+        else:
+            flops = FLOP_EVAL * counts["fwd_evals"] + FLOP_FWD_BLEND * counts["bwd_active"]
+        achieved = flops / launches / per_launch_s / 1e12
+        out.update(bound="alu", achieved=round(achieved, 3), peak=PEAK_ALU_TFLOPS, unit="TFLOP/s",
+                   frac=round(achieved / PEAK_ALU_TFLOPS, 5), traffic=None,
+                   algorithmic_flops_per_launch=round(flops / launches))
+        return out
     # sort/bin: 28 algorithmic bytes per (tile, kernel) pair (write key/value, read per tile, write list)
     nbytes = 28.0 * counts["pairs"]
-    achieved = nbytes / max(launches, 1) / per_launch_s / 1e9
-    return dict(kernel=dom, bound="hbm", achieved=round(achieved, 1), peak=PEAK_HBM_GBS, unit="GB/s",
-                frac=round(achieved / PEAK_HBM_GBS, 5), traffic=None, avg_launch_ms=round(ms / max(launches, 1), 4),
-                launches=launches)
+    achieved = nbytes / launches / per_launch_s / 1e9
+    out.update(bound="hbm", achieved=round(achieved, 1), peak=PEAK_HBM_GBS, unit="GB/s",
+               frac=round(achieved / PEAK_HBM_GBS, 5), traffic=None)
+    return out
 
 
 def cpu_baseline(cfg, budget_s):
@@ -178,7 +196,8 @@ def main():
     elapsed, stages, counts, loss, cfg = gpu_run(args)
     ms_per_step = elapsed * 1e3 / args.steps
     value = args.steps / elapsed
-    rl = roofline(stages, counts, args.steps)
+    pixels = cfg.width * cfg.height + cfg.n_secondary * (cfg.width // 2) * (cfg.height // 2)
+    rl = roofline(stages, counts, args.steps, pixels)
     cpu = None
     if not args.no_cpu_baseline:
         log("[bench] timing the oracle on a bounded sample ...")

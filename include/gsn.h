@@ -280,7 +280,8 @@ typedef enum {
     GSN_COUNT_BWD_EVALS = 1,   /* (pixel, list entry) evaluations in the backward pass */
     GSN_COUNT_BWD_ACTIVE = 2,  /* of which contributed (alpha >= alpha_min) */
     GSN_COUNT_PAIRS = 3,       /* (tile, kernel) pairs binned */
-    GSN_COUNT_N = 4
+    GSN_COUNT_PARTIALS = 4,    /* (tile, kernel) partial statistics written by the backward pass */
+    GSN_COUNT_N = 5
 } gsn_counter;
 
 /* Turns stage timing on or off and clears what was accumulated.  While on,

@@ -37,8 +37,7 @@
 namespace {
 
 constexpr int PMAX = 896;   // composited (pixel, entry) pairs staged per round
-constexpr int GRP = 4;      // threads that sum one small entry's pairs
-constexpr int BIG = 32;     // entries with more pairs are summed by a whole wave
+constexpr int BIG = 16;     // entries with more pairs are summed by 16 lanes, others by 4
 
 // Contribution of one active (pixel, splat) pair to the 44 statistics (see the header comment).
 __device__ __forceinline__ void pair_terms(const float4 a, const float4 b, float G, float T, const float av[3],
@@ -87,6 +86,24 @@ __device__ __forceinline__ void pair_terms(const float4 a, const float4 b, float
     z[42] = A2 * G * G;
 }
 
+// Cross-lane sums with DPP row operations (no LDS traffic): quad_sum leaves in every lane
+// the sum over its group of 4 lanes, row_sum the sum over its row of 16 lanes.
+template <int CTRL>
+__device__ __forceinline__ float dpp_mov(float v) {
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xF, 0xF, false));
+}
+__device__ __forceinline__ float quad_sum(float v) {
+    v += dpp_mov<0xB1>(v);  // quad_perm [1, 0, 3, 2]
+    v += dpp_mov<0x4E>(v);  // quad_perm [2, 3, 0, 1]
+    return v;
+}
+__device__ __forceinline__ float row_sum(float v) {
+    v = quad_sum(v);
+    v += dpp_mov<0x141>(v);  // row_half_mirror: the other quad of the half row
+    v += dpp_mov<0x140>(v);  // row_mirror: the other half of the row
+    return v;
+}
+
 // Adds the statistics of staged pair i (slot in LDS) of the splat (a, b, c4) to acc.
 __device__ __forceinline__ void pair_stats(const float4 a, const float4 b, const float4 cl, const float4* s_pa,
                                            const float* s_pb, const uint8_t* s_pix, const float (*s_dl)[GSN_BLOCK],
@@ -127,9 +144,9 @@ __device__ __forceinline__ void write_partial(float* __restrict__ partial, uint8
 //  (c) every pixel walks its composited entries front to back (transmittance,
 //      colour behind the splat) and stores (T, G, a_R, a_G, a_B) in the pair's slot;
 //  (d) for every entry with pairs, the 44 statistics are summed over its pairs in a
-//      fixed order (GRP threads per entry, or a whole wave for an entry with more
-//      than BIG pairs) and the tile's partial sum is written at the (tile, kernel)
-//      pair's slot.  Only contributing pairs do the 44-term work.
+//      fixed order (4 lanes per entry, or 16 for an entry with more than BIG pairs)
+//      and the tile's partial sum is written at the (tile, kernel) pair's slot.
+//      Only contributing pairs do the 44-term work.
 __global__ __launch_bounds__(GSN_BLOCK, 3) void raster_bwd_kernel(
     const uint2* __restrict__ ranges, const uint32_t* __restrict__ ids, const float4* __restrict__ rec,
     const uint2* __restrict__ rect, const uint32_t* __restrict__ pair_off, uint32_t n, DevCam cam, DevRenderOpts ro,
@@ -145,8 +162,8 @@ __global__ __launch_bounds__(GSN_BLOCK, 3) void raster_bwd_kernel(
     __shared__ uint64_t s_mask[GSN_BLOCK][NW];
     __shared__ uint32_t s_off[GSN_BLOCK * NW + 1];
     __shared__ uint32_t s_wsum[NW];
-    __shared__ uint8_t s_act[GSN_BLOCK];  // entries of the round with pairs, at most BIG of them
-    __shared__ uint32_t s_nact[NW];
+    __shared__ uint8_t s_act[GSN_BLOCK], s_big[GSN_BLOCK];  // entries of the round with <= BIG / > BIG pairs
+    __shared__ uint32_t s_nact[NW], s_nbig[NW];
     __shared__ float4 s_pa[PMAX];
     __shared__ float s_pb[PMAX];
     __shared__ uint8_t s_pix[PMAX];
@@ -185,7 +202,7 @@ __global__ __launch_bounds__(GSN_BLOCK, 3) void raster_bwd_kernel(
     float T = 1.f;
     double Ca0 = 0.0, Ca1 = 0.0, Ca2 = 0.0;
     const float fpx = (float)px, fpy = (float)py;
-    uint32_t n_eval = 0, n_act = 0;
+    uint32_t n_eval = 0, n_act = 0, n_part = 0;
     for (uint32_t base = rg.x; base < end; base += GSN_BLOCK) {
         const int bcnt = (int)min((uint32_t)GSN_BLOCK, end - base);
         // stage the batch: one entry per thread, its slot and its band mask
@@ -315,24 +332,34 @@ __global__ __launch_bounds__(GSN_BLOCK, 3) void raster_bwd_kernel(
                     T *= (1.0f - al);
                 }
             }
-            // entries of the round with 1..BIG pairs, compacted in order
+            // (d) per-entry sums.  Entries of the round with 1..BIG pairs go to groups of 4 lanes, larger
+            // ones to groups of 16; a group sums its entry's pairs lane-strided and then across its lanes
+            // with DPP row operations, so every sum is taken in one fixed order.
             const uint32_t pc = (tid >= r0 && tid < r1) ? s_off[(tid + 1) * NW] - s_off[tid * NW] : 0u;
-            const bool small = pc > 0 && pc <= (uint32_t)BIG;
-            const uint64_t sbal = __ballot(small);
-            if (lane == 0) s_nact[wave] = (uint32_t)__popcll(sbal);
+            const bool small = pc > 0 && pc <= (uint32_t)BIG, large = pc > (uint32_t)BIG;
+            const uint64_t sbal = __ballot(small), lbal = __ballot(large);
+            if (lane == 0) {
+                s_nact[wave] = (uint32_t)__popcll(sbal);
+                s_nbig[wave] = (uint32_t)__popcll(lbal);
+            }
             __syncthreads();
+            uint32_t nsmall = 0, nlarge = 0;
             {
-                uint32_t off = 0, nsmall = 0;
+                uint32_t off = 0, offb = 0;
 #pragma unroll
                 for (int w = 0; w < NW; ++w) {
                     off += w < wave ? s_nact[w] : 0u;
+                    offb += w < wave ? s_nbig[w] : 0u;
                     nsmall += s_nact[w];
+                    nlarge += s_nbig[w];
                 }
                 if (small) s_act[off + (uint32_t)__popcll(sbal & lt_mask)] = (uint8_t)tid;
-                __syncthreads();
-                // (d) small entries: GRP threads each, groups dealt the compacted entries in turn
-                const int grp = tid / GRP, r = tid % GRP;
-                for (uint32_t k0 = 0; k0 < nsmall; k0 += GSN_BLOCK / GRP) {  // uniform across the block
+                if (large) s_big[offb + (uint32_t)__popcll(lbal & lt_mask)] = (uint8_t)tid;
+            }
+            __syncthreads();
+            {
+                const int grp = tid / 4, r = tid % 4;
+                for (uint32_t k0 = 0; k0 < nsmall; k0 += GSN_BLOCK / 4) {  // uniform across the block
                     const uint32_t k = k0 + (uint32_t)grp;
                     float acc[GSN_NZ];
 #pragma unroll
@@ -341,38 +368,38 @@ __global__ __launch_bounds__(GSN_BLOCK, 3) void raster_bwd_kernel(
                     if (k < nsmall) {
                         e = s_act[k];
                         const uint32_t q0 = s_off[e * NW], q1 = s_off[(e + 1) * NW];
-                        for (uint32_t i = q0 + r; i < q1; i += GRP)
+                        for (uint32_t i = q0 + r; i < q1; i += 4)
                             pair_stats(r_a[e], r_b[e], r_c[e], s_pa, s_pb, s_pix, s_dl, s_h, i, tx, ty, ro.alpha_max,
                                        acc);
                     }
 #pragma unroll
-                    for (int off2 = 1; off2 < GRP; off2 <<= 1)
-#pragma unroll
-                        for (int f = 0; f < GSN_NZ; ++f) acc[f] += __shfl_xor(acc[f], off2, 64);
-                    if (k < nsmall && r == 0) write_partial(partial, flags, r_slot[e], acc);
+                    for (int f = 0; f < GSN_NZ; ++f) acc[f] = quad_sum(acc[f]);
+                    if (k < nsmall && r == 0) {
+                        write_partial(partial, flags, r_slot[e], acc);
+                        ++n_part;
+                    }
                 }
             }
-            // (d) big entries: a whole wave each, dealt to the waves in turn
             {
-                int kb = 0;
-                for (int w = 0; w < NW; ++w) {
-                    const int e = w * 64 + lane;
-                    const bool big = e >= r0 && e < r1 && s_off[(e + 1) * NW] - s_off[e * NW] > (uint32_t)BIG;
-                    for (uint64_t m = __ballot(big); m; m &= m - 1, ++kb) {  // uniform across the wave
-                        if (kb % NW != wave) continue;
-                        const int eb = w * 64 + __ffsll((unsigned long long)m) - 1;
-                        float acc[GSN_NZ];
+                const int grp = tid / 16, r = tid % 16;
+                for (uint32_t k0 = 0; k0 < nlarge; k0 += GSN_BLOCK / 16) {  // uniform across the block
+                    const uint32_t k = k0 + (uint32_t)grp;
+                    float acc[GSN_NZ];
 #pragma unroll
-                        for (int f = 0; f < GSN_NZ; ++f) acc[f] = 0.f;
-                        const uint32_t q0 = s_off[eb * NW], q1 = s_off[(eb + 1) * NW];
-                        for (uint32_t i = q0 + lane; i < q1; i += 64)
-                            pair_stats(r_a[eb], r_b[eb], r_c[eb], s_pa, s_pb, s_pix, s_dl, s_h, i, tx, ty,
-                                       ro.alpha_max, acc);
+                    for (int f = 0; f < GSN_NZ; ++f) acc[f] = 0.f;
+                    int e = 0;
+                    if (k < nlarge) {
+                        e = s_big[k];
+                        const uint32_t q0 = s_off[e * NW], q1 = s_off[(e + 1) * NW];
+                        for (uint32_t i = q0 + r; i < q1; i += 16)
+                            pair_stats(r_a[e], r_b[e], r_c[e], s_pa, s_pb, s_pix, s_dl, s_h, i, tx, ty, ro.alpha_max,
+                                       acc);
+                    }
 #pragma unroll
-                        for (int off2 = 1; off2 < 64; off2 <<= 1)
-#pragma unroll
-                            for (int f = 0; f < GSN_NZ; ++f) acc[f] += __shfl_xor(acc[f], off2, 64);
-                        if (lane == 0) write_partial(partial, flags, r_slot[eb], acc);
+                    for (int f = 0; f < GSN_NZ; ++f) acc[f] = row_sum(acc[f]);
+                    if (k < nlarge && r == 0) {
+                        write_partial(partial, flags, r_slot[e], acc);
+                        ++n_part;
                     }
                 }
             }
@@ -381,15 +408,17 @@ __global__ __launch_bounds__(GSN_BLOCK, 3) void raster_bwd_kernel(
         }
     }
     if (counts) {
-        __shared__ unsigned long long s_cnt[2];
-        if (tid == 0) s_cnt[0] = s_cnt[1] = 0;
+        __shared__ unsigned long long s_cnt[3];
+        if (tid == 0) s_cnt[0] = s_cnt[1] = s_cnt[2] = 0;
         __syncthreads();
         atomicAdd(&s_cnt[0], (unsigned long long)n_eval);
         atomicAdd(&s_cnt[1], (unsigned long long)n_act);
+        atomicAdd(&s_cnt[2], (unsigned long long)n_part);
         __syncthreads();
         if (tid == 0) {
             atomicAdd(&counts[GSN_COUNT_BWD_EVALS], s_cnt[0]);
             atomicAdd(&counts[GSN_COUNT_BWD_ACTIVE], s_cnt[1]);
+            atomicAdd(&counts[GSN_COUNT_PARTIALS], s_cnt[2]);
         }
     }
 }

@@ -269,7 +269,7 @@ class Context:
                                          int(group_mask)))
 
     STAGES = ("project", "sort", "raster_fwd", "loss", "raster_bwd", "chain", "solve", "apply")
-    COUNTERS = ("fwd_evals", "bwd_evals", "bwd_active", "pairs")
+    COUNTERS = ("fwd_evals", "bwd_evals", "bwd_active", "pairs", "partials")
 
     def profile_enable(self, on=True):
         self._check(lib().gsn_profile_enable(self.h, int(bool(on))))
@@ -279,7 +279,7 @@ class Context:
         import numpy as np
         ms = np.zeros(8, np.float64)
         nl = np.zeros(8, np.int64)
-        cnt = np.zeros(4, np.int64)
+        cnt = np.zeros(len(self.COUNTERS), np.int64)
         self._check(lib().gsn_profile_read(self.h, ms.ctypes.data_as(ctypes.c_void_p),
                                            nl.ctypes.data_as(ctypes.c_void_p), cnt.ctypes.data_as(ctypes.c_void_p)))
         return ({s: (float(ms[i]), int(nl[i])) for i, s in enumerate(self.STAGES)},
