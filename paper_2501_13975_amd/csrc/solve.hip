@@ -24,8 +24,6 @@
 
 namespace {
 
-constexpr int VMAX = 9;
-
 // Damped solve of a 1x1 or 2x2 symmetric system (H packed xx, xy, yy for n = 2) in double.
 __device__ int damped_small(int n, const double* H, const double* g, const gsn_solve_opts& o, double abs_scale,
                             double* x) {
@@ -70,44 +68,149 @@ __device__ void clamp_norm(int n, double* x, double radius) {
         for (int i = 0; i < n; ++i) x[i] *= radius / nn;
 }
 
-// Cholesky solve of an m x m SPD system held in a VMAX x VMAX register array (double).
-__device__ bool chol_solve_v(int m, double A[VMAX][VMAX], const double* b, double* x) {
-    double L[VMAX][VMAX];
+// Cholesky solve of an m x m SPD system (m <= VM) held in a VM x VM register array (double).
+// Loops run to the compile-time bound with guards, so the arrays stay in registers.
+template <int VM>
+__device__ __forceinline__ bool chol_solve_v(int m, const double A[VM][VM], const double* b, double* x) {
+    double L[VM][VM];
+    bool ok = true;
 #pragma unroll
-    for (int i = 0; i < VMAX; ++i) {
-        if (i >= m) break;
+    for (int i = 0; i < VM; ++i) {
 #pragma unroll
         for (int j = 0; j <= i; ++j) {
-            double s = A[i][j];
+            if (i < m) {
+                double s = A[i][j];
 #pragma unroll
-            for (int k = 0; k < j; ++k) s -= L[i][k] * L[j][k];
-            if (i == j) {
-                if (!(s > 0.0)) return false;
-                L[i][i] = sqrt(s);
-            } else {
-                L[i][j] = s / L[j][j];
+                for (int k = 0; k < j; ++k) s -= L[i][k] * L[j][k];
+                if (i == j) {
+                    ok = ok && s > 0.0;
+                    L[i][i] = sqrt(fmax(s, 1e-300));
+                } else {
+                    L[i][j] = s / L[j][j];
+                }
             }
         }
     }
-    double y[VMAX];
+    double y[VM];
 #pragma unroll
-    for (int i = 0; i < VMAX; ++i) {
-        if (i >= m) break;
-        double s = b[i];
+    for (int i = 0; i < VM; ++i) {
+        if (i < m) {
+            double s = b[i];
 #pragma unroll
-        for (int k = 0; k < i; ++k) s -= L[i][k] * y[k];
-        y[i] = s / L[i][i];
+            for (int k = 0; k < i; ++k) s -= L[i][k] * y[k];
+            y[i] = s / L[i][i];
+        }
     }
 #pragma unroll
-    for (int i = VMAX - 1; i >= 0; --i) {
-        if (i >= m) continue;
-        double s = y[i];
+    for (int i = VM - 1; i >= 0; --i) {
+        if (i < m) {
+            double s = y[i];
 #pragma unroll
-        for (int k = i + 1; k < VMAX; ++k)
-            if (k < m) s -= L[k][i] * x[k];
-        x[i] = s / L[i][i];
+            for (int k = i + 1; k < VM; ++k)
+                if (k < m) s -= L[k][i] * x[k];
+            x[i] = s / L[i][i];
+        }
     }
-    return true;
+    return ok;
+}
+
+// Colour step of one kernel, per channel, in view space (the system has rank at most the
+// number of views nv that see the kernel):  with B the nv x K matrix of basis rows Y(r_v),
+// S = diag(s_v) and gamma the per-view gradients, (B B^T + mu S^-1) y = -S^-1 gamma and
+// Delta = B^T y, which equals the damped coefficient-space solve (B^T S B + mu I) Delta =
+// -B^T gamma for every nv.  The basis rows are re-evaluated instead of stored.
+template <int VM, class RowFn>
+__device__ __forceinline__ void colour_solve(int K, int V, RowFn B, const gsn_solve_opts& o, double abs_scale,
+                                             float* __restrict__ st, size_t N, int k, int32_t* __restrict__ fl) {
+    int vb[VM];
+    int nv = 0;
+#pragma unroll
+    for (int v = 0; v < VM; ++v) {
+        vb[v] = 0;
+        if (v < V && B(GSN_BLK_BASE + GSN_BLK_VIEW * v + 9) > 0.0) {
+#pragma unroll
+            for (int i = 0; i < VM; ++i)
+                if (i == nv) vb[i] = GSN_BLK_BASE + GSN_BLK_VIEW * v;
+            ++nv;
+        }
+    }
+    fl[4 * N + k] = nv;
+    // Gram matrix of the basis rows
+    double Gm[VM][VM];
+#pragma unroll
+    for (int i = 0; i < VM; ++i)
+#pragma unroll
+        for (int j = 0; j < VM; ++j) Gm[i][j] = 0.0;
+#pragma unroll
+    for (int i = 0; i < VM; ++i) {
+        if (i < nv) {
+            double yi[16];
+            sh_basis_dev<double>(K, B(vb[i] + 6), B(vb[i] + 7), B(vb[i] + 8), yi);
+#pragma unroll
+            for (int j = 0; j <= i; ++j) {
+                if (j < nv) {
+                    double d = 0.0;
+                    sh_basis_visit<double>(K, B(vb[j] + 6), B(vb[j] + 7), B(vb[j] + 8),
+                                           [&](int a, double yj) { d += yi[a] * yj; });
+                    Gm[i][j] = d;
+                    Gm[j][i] = d;
+                }
+            }
+        }
+    }
+    double ych[3][VM];
+#pragma unroll
+    for (int ch = 0; ch < 3; ++ch) {
+#pragma unroll
+        for (int i = 0; i < VM; ++i) ych[ch][i] = 0.0;
+        double smax = 0.0;
+#pragma unroll
+        for (int i = 0; i < VM; ++i)
+            if (i < nv) smax = fmax(smax, fabs(B(vb[i] + 3 + ch)));
+        if (!(smax > 0.0)) continue;
+        double sv[VM], md = 0.0;  // md: mean diagonal of G = sum_v s_v Y Y^T
+#pragma unroll
+        for (int i = 0; i < VM; ++i) {
+            sv[i] = 1.0;
+            if (i < nv) {
+                sv[i] = fmax(fabs(B(vb[i] + 3 + ch)), (double)o.sh_floor * smax);
+                md += sv[i] * Gm[i][i];
+            }
+        }
+        md /= (double)K;
+        const double mu = (double)o.damp_rel * md + (double)o.damp_abs * abs_scale;
+        double A[VM][VM], rhs[VM], y[VM];
+#pragma unroll
+        for (int i = 0; i < VM; ++i) {
+#pragma unroll
+            for (int j = 0; j < VM; ++j) A[i][j] = Gm[i][j] + (i == j ? mu / sv[i] : 0.0);
+            rhs[i] = i < nv ? -B(vb[i] + ch) / sv[i] : 0.0;
+        }
+        if (chol_solve_v<VM>(nv, A, rhs, y)) {
+#pragma unroll
+            for (int i = 0; i < VM; ++i)
+                if (i < nv) ych[ch][i] = y[i];
+        }
+    }
+    // Delta_ch = B^T y_ch
+    double dsh[3][16];
+#pragma unroll
+    for (int ch = 0; ch < 3; ++ch)
+#pragma unroll
+        for (int a = 0; a < 16; ++a) dsh[ch][a] = 0.0;
+#pragma unroll
+    for (int i = 0; i < VM; ++i) {
+        if (i < nv)
+            sh_basis_visit<double>(K, B(vb[i] + 6), B(vb[i] + 7), B(vb[i] + 8), [&](int a, double ya) {
+#pragma unroll
+                for (int ch = 0; ch < 3; ++ch) dsh[ch][a] += ya * ych[ch][i];
+            });
+    }
+#pragma unroll
+    for (int ch = 0; ch < 3; ++ch)
+#pragma unroll
+        for (int a = 0; a < 16; ++a)
+            if (a < K) st[(GSN_STEP_BASE + ch * K + a) * N + k] = (float)dsh[ch][a];
 }
 
 template <class T>
@@ -118,6 +221,7 @@ __device__ __forceinline__ void qmul(const T a[4], const T b[4], T r[4]) {
     r[3] = a[0] * b[3] + b[0] * a[3] + a[1] * b[2] - a[2] * b[1];
 }
 
+template <int VM>
 __global__ __launch_bounds__(128) void solve_kernel(const float* __restrict__ pos, const float* __restrict__ rot,
                                                      const float* __restrict__ scale, const float* __restrict__ opac,
                                                      int n, int K, DevCam c, float kappa,
@@ -279,77 +383,7 @@ __global__ __launch_bounds__(128) void solve_kernel(const float* __restrict__ po
         st[10 * N + k] = (float)ds;
     }
     // ---- colour, per channel
-    {
-        int vidx[VMAX];
-        int nv = 0;
-        for (int v = 0; v < V && v < VMAX; ++v)
-            if (B(GSN_BLK_BASE + GSN_BLK_VIEW * v + 9) > 0.0) vidx[nv++] = v;
-        fl[4 * N + k] = nv;
-        double Yv[VMAX][16];
-        for (int i = 0; i < VMAX; ++i) {
-            if (i >= nv) break;
-            const int vb = GSN_BLK_BASE + GSN_BLK_VIEW * vidx[i];
-            sh_basis_dev<double>(K, B(vb + 6), B(vb + 7), B(vb + 8), Yv[i]);
-        }
-        for (int ch = 0; ch < 3; ++ch) {
-            double dsh[16];
-            for (int i = 0; i < K; ++i) dsh[i] = 0.0;
-            double smax = 0.0;
-            for (int i = 0; i < nv; ++i) smax = fmax(smax, fabs(B(GSN_BLK_BASE + GSN_BLK_VIEW * vidx[i] + 3 + ch)));
-            if (smax > 0.0) {
-                double sv[VMAX], gv[VMAX];
-                double md = 0.0;  // mean diagonal of G = sum_v s_v Y Y^T
-                for (int i = 0; i < VMAX; ++i) {
-                    if (i >= nv) break;
-                    const int vb = GSN_BLK_BASE + GSN_BLK_VIEW * vidx[i];
-                    sv[i] = fmax(fabs(B(vb + 3 + ch)), (double)o.sh_floor * smax);
-                    gv[i] = B(vb + ch);
-                    double yy = 0.0;
-                    for (int a = 0; a < K; ++a) yy += Yv[i][a] * Yv[i][a];
-                    md += sv[i] * yy;
-                }
-                md /= (double)K;
-                const double mu = (double)o.damp_rel * md + (double)o.damp_abs * abs_scale;
-                double A[VMAX][VMAX], rhs[VMAX], y[VMAX];
-                if (nv < K) {
-                    // view space: (B B^T + mu S^-1) y = -S^-1 gamma, Delta = B^T y
-                    for (int i = 0; i < VMAX; ++i) {
-                        if (i >= nv) break;
-                        for (int j = 0; j < VMAX; ++j) {
-                            if (j >= nv) break;
-                            double d = 0.0;
-                            for (int a = 0; a < K; ++a) d += Yv[i][a] * Yv[j][a];
-                            A[i][j] = d + (i == j ? mu / sv[i] : 0.0);
-                        }
-                        rhs[i] = -gv[i] / sv[i];
-                    }
-                    if (chol_solve_v(nv, A, rhs, y))
-                        for (int a = 0; a < K; ++a) {
-                            double acc = 0.0;
-                            for (int i = 0; i < nv; ++i) acc += Yv[i][a] * y[i];
-                            dsh[a] = acc;
-                        }
-                } else {
-                    // coefficient space: (sum_v s_v Y Y^T + mu I) Delta = -sum_v gamma_v Y  (K <= nv <= VMAX)
-                    for (int a = 0; a < VMAX; ++a) {
-                        if (a >= K) break;
-                        for (int b = 0; b < VMAX; ++b) {
-                            if (b >= K) break;
-                            double d = a == b ? mu : 0.0;
-                            for (int i = 0; i < nv; ++i) d += sv[i] * Yv[i][a] * Yv[i][b];
-                            A[a][b] = d;
-                        }
-                        double gg = 0.0;
-                        for (int i = 0; i < nv; ++i) gg += gv[i] * Yv[i][a];
-                        rhs[a] = -gg;
-                    }
-                    if (chol_solve_v(K, A, rhs, y))
-                        for (int a = 0; a < K; ++a) dsh[a] = y[a];
-                }
-            }
-            for (int a = 0; a < K; ++a) st[(GSN_STEP_BASE + ch * K + a) * N + k] = (float)dsh[a];
-        }
-    }
+    colour_solve<VM>(K, V, B, o, abs_scale, st, N, k, fl);
 }
 
 __global__ __launch_bounds__(256) void apply_kernel(float* __restrict__ pos, float* __restrict__ rot,
@@ -392,8 +426,13 @@ void launch_solve(const gsn_gaussians& g, const DevCam& cam, float kappa, const 
                   const gsn_solve_opts& o, const gsn_steps& st, hipStream_t s) {
     if (g.n == 0) return;
     const int K = (g.sh_degree + 1) * (g.sh_degree + 1);
-    solve_kernel<<<(g.n + 127) / 128, 128, 0, s>>>(g.d_pos, g.d_rot, g.d_scale, g.d_opac, g.n, K, cam, kappa,
-                                                   b.d_data, b.n_views, o, st.d_data, st.d_flags);
+    // the hot path has a primary and up to three secondaries: a 4-view kernel keeps its arrays in registers
+    if (b.n_views <= 4)
+        solve_kernel<4><<<(g.n + 127) / 128, 128, 0, s>>>(g.d_pos, g.d_rot, g.d_scale, g.d_opac, g.n, K, cam, kappa,
+                                                          b.d_data, b.n_views, o, st.d_data, st.d_flags);
+    else
+        solve_kernel<9><<<(g.n + 127) / 128, 128, 0, s>>>(g.d_pos, g.d_rot, g.d_scale, g.d_opac, g.n, K, cam, kappa,
+                                                          b.d_data, b.n_views, o, st.d_data, st.d_flags);
 }
 
 void launch_apply(const gsn_gaussians& g, const gsn_steps& st, const gsn_solve_opts& o, uint32_t mask,
