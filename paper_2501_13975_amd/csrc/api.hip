@@ -216,7 +216,7 @@ gsn_status gsn_frame_destroy(gsn_ctx* ctx, gsn_frame* f) {
     (void)hipSetDevice(ctx->device);
     (void)hipStreamSynchronize(ctx->stream);
     DevBuf* all[] = {&f->rec, &f->rect, &f->depth_key, &f->ntiles, &f->ids_a, &f->ids_b, &f->keys_a, &f->keys_b,
-                     &f->offsets, &f->pair_off, &f->pk_a, &f->pv_a, &f->pk_b, &f->pv_b, &f->partial, &f->flags,
+                     &f->offsets, &f->pair_off, &f->pk_a, &f->pv_a, &f->pk_b, &f->pv_b, &f->partial, &f->flags, &f->kflag,
                      &f->ranges, &f->img, &f->img64, &f->Tfin, &f->ncontrib, &f->dL, &f->hd, &f->coef, &f->zsum, &f->zstats,
                      &f->loss_part, &f->hist, &f->scan_tmp, &f->total};
     for (DevBuf* b : all) buf_free(*b);
@@ -312,10 +312,12 @@ gsn_status gsn_render(gsn_ctx* ctx, const gsn_gaussians* g, const gsn_camera* ca
     // slots the backward pass writes depends only on this render, not on the loss)
     HIP_TRY(ctx, buf_reserve(f->partial, pp * GSN_NZ * 4));
     HIP_TRY(ctx, buf_reserve(f->flags, (pp + 3) / 4 * 4));
+    HIP_TRY(ctx, buf_reserve(f->kflag, (nn + 3) / 4 * 4));
     {
         // 4. pairs in depth order, then a stable partition by tile id
         StageTimer st_(ctx, GSN_STAGE_SORT);
         launch_fill_u32(bp<uint32_t>(f->flags), 0u, (pp + 3) / 4, s);
+        launch_fill_u32(bp<uint32_t>(f->kflag), 0u, (nn + 3) / 4, s);
         launch_emit_pairs(bp<uint32_t>(f->ids_a), bp<uint32_t>(f->offsets), (uint32_t)n, bp<uint2>(f->rect),
                           (uint32_t)f->tiles_x, bp<uint32_t>(f->pk_a), bp<uint32_t>(f->pv_a),
                           bp<uint32_t>(f->pair_off), s);

@@ -27,8 +27,8 @@
 // the contributing (pixel, splat) pairs of each round in LDS, and sums each
 // splat's 44 statistics over its pairs (see raster_bwd_kernel); the tile's
 // partial sum is written at the (tile, kernel) pair's slot.
-// reduce_pairs: one wave per kernel sums its pair slots in a fixed order (no
-// atomics: results are deterministic); chain_pos / chain_rs: one thread per
+// reduce_pairs: one wave per kernel sums its written pair slots in a fixed order
+// (no atomics: results are deterministic); chain_pos / chain_rs: one thread per
 // kernel applies the chain rule through the projection with second-order jets
 // and adds the attribute blocks (position, opacity, colour / rotation, scale).
 #include "gsn_internal.h"
@@ -152,10 +152,10 @@ __global__ __launch_bounds__(GSN_BLOCK, 3) void raster_bwd_kernel(
     const uint2* __restrict__ rect, const uint32_t* __restrict__ pair_off, uint32_t n, DevCam cam, DevRenderOpts ro,
     const double* __restrict__ img64, const uint32_t* __restrict__ ncontrib, const float* __restrict__ dLm,
     const float* __restrict__ hdm, float* __restrict__ partial, uint8_t* __restrict__ flags,
-    unsigned long long* __restrict__ counts) {
+    uint8_t* __restrict__ kflag, unsigned long long* __restrict__ counts) {
     constexpr int NW = GSN_BLOCK / 64;
     __shared__ float4 r_a[GSN_BLOCK], r_b[GSN_BLOCK], r_c[GSN_BLOCK];
-    __shared__ uint32_t r_slot[GSN_BLOCK];
+    __shared__ uint32_t r_slot[GSN_BLOCK], r_id[GSN_BLOCK];
     __shared__ uint8_t r_list[NW][GSN_BLOCK];
     __shared__ uint32_t r_cnt[NW][NW];  // [band][loader wave]
     __shared__ float s_dl[3][GSN_BLOCK], s_h[3][GSN_BLOCK];
@@ -222,6 +222,7 @@ __global__ __launch_bounds__(GSN_BLOCK, 3) void raster_bwd_kernel(
             const uint2 rc = rect[id];
             const uint32_t x0 = rc.x & 0xffffu, y0 = rc.x >> 16, x1 = rc.y & 0xffffu;
             r_slot[tid] = pair_off[id] + ((uint32_t)ty - y0) * (x1 - x0) + ((uint32_t)tx - x0);
+            r_id[tid] = id;
         }
         uint64_t bal[NW];
 #pragma unroll
@@ -376,6 +377,7 @@ __global__ __launch_bounds__(GSN_BLOCK, 3) void raster_bwd_kernel(
                     for (int f = 0; f < GSN_NZ; ++f) acc[f] = quad_sum(acc[f]);
                     if (k < nsmall && r == 0) {
                         write_partial(partial, flags, r_slot[e], acc);
+                        kflag[r_id[e]] = 1;
                         ++n_part;
                     }
                 }
@@ -399,6 +401,7 @@ __global__ __launch_bounds__(GSN_BLOCK, 3) void raster_bwd_kernel(
                     for (int f = 0; f < GSN_NZ; ++f) acc[f] = row_sum(acc[f]);
                     if (k < nlarge && r == 0) {
                         write_partial(partial, flags, r_slot[e], acc);
+                        kflag[r_id[e]] = 1;
                         ++n_part;
                     }
                 }
@@ -423,17 +426,25 @@ __global__ __launch_bounds__(GSN_BLOCK, 3) void raster_bwd_kernel(
     }
 }
 
-// One wave per kernel: the kernel's (tile, kernel) slots are scanned 64 at a time,
-// and lane f < 44 adds statistic f of every slot the backward pass wrote, in slot
-// order and in double (deterministic, coalesced 176-byte reads per slot).
+// One wave per kernel: the kernel's (tile, kernel) slots are scanned 64 at a time, and lane
+// f < 44 adds statistic f of every slot the backward pass wrote, in slot order and in double
+// (deterministic, coalesced 176-byte reads per slot).  Most kernels have no written slot in a
+// view (their kernel flag is clear): for them only the coverage entry is written (zero), which
+// the chain kernels test first.
 __global__ __launch_bounds__(256) void reduce_pairs_kernel(int n, const uint2* __restrict__ rect,
                                                            const uint32_t* __restrict__ pair_off,
                                                            const float* __restrict__ partial,
                                                            const uint8_t* __restrict__ flags,
+                                                           const uint8_t* __restrict__ kflag,
                                                            double* __restrict__ zsum) {
     const int k = blockIdx.x * (blockDim.x / 64) + threadIdx.x / 64;
     const int lane = __lane_id();
     if (k >= n) return;
+    double* zk = zsum + (size_t)k * GSN_NZ;
+    if (!kflag[k]) {
+        if (lane == 0) zk[GSN_NZ - 1] = 0.0;
+        return;
+    }
     const uint2 rc = rect[k];
     const uint32_t nt = ((rc.y & 0xffffu) - (rc.x & 0xffffu)) * ((rc.y >> 16) - (rc.x >> 16));
     const uint32_t off = pair_off[k];
@@ -447,7 +458,7 @@ __global__ __launch_bounds__(256) void reduce_pairs_kernel(int n, const uint2* _
             if (lane < GSN_NZ) acc += (double)partial[(size_t)(off + base + i) * GSN_NZ + lane];
         }
     }
-    if (lane < GSN_NZ) zsum[(size_t)k * GSN_NZ + lane] = acc;
+    if (lane < GSN_NZ) zk[lane] = acc;
 }
 
 __device__ __forceinline__ void load_kparams(const float* __restrict__ pos, const float* __restrict__ rot,
@@ -472,6 +483,13 @@ __global__ __launch_bounds__(128) void chain_pos_kernel(
     DevCam cam, float kappa, float weight, int slot, float* __restrict__ blk, float* __restrict__ zstats) {
     const int k = blockIdx.x * blockDim.x + threadIdx.x;
     if (k >= n) return;
+    if (!(zsum[(size_t)k * GSN_NZ + GSN_NZ - 1] > 0.0)) {  // no pixel of this view composited the kernel
+        if (zstats) {
+#pragma unroll
+            for (int f = 0; f < GSN_NZ; ++f) zstats[(size_t)f * n + k] = 0.f;
+        }
+        return;
+    }
     float z[GSN_NZ];
     {
         const double2* zp = reinterpret_cast<const double2*>(zsum + (size_t)k * GSN_NZ);
@@ -550,7 +568,7 @@ void launch_raster_bwd(const gsn_frame& f, const float* dL, const float* hd, uns
     raster_bwd_kernel<<<tiles, GSN_BLOCK, 0, s>>>(
         bp<uint2>(f.ranges), bp<uint32_t>(f.pv_a), bp<float4>(f.rec),
         bp<uint2>(f.rect), bp<uint32_t>(f.pair_off), (uint32_t)f.n, f.cam, f.ro, bp<double>(f.img64),
-        bp<uint32_t>(f.ncontrib), dL, hd, bp<float>(f.partial), bp<uint8_t>(f.flags), counts);
+        bp<uint32_t>(f.ncontrib), dL, hd, bp<float>(f.partial), bp<uint8_t>(f.flags), bp<uint8_t>(f.kflag), counts);
 }
 
 void launch_reduce_chain(const gsn_frame& f, const gsn_gaussians& g, float weight, int slot, const gsn_blocks& b,
@@ -559,7 +577,7 @@ void launch_reduce_chain(const gsn_frame& f, const gsn_gaussians& g, float weigh
     const int K = (g.sh_degree + 1) * (g.sh_degree + 1);
     reduce_pairs_kernel<<<(g.n + 3) / 4, 256, 0, s>>>(g.n, bp<uint2>(f.rect), bp<uint32_t>(f.pair_off),
                                                       bp<float>(f.partial), bp<uint8_t>(f.flags),
-                                                      bp<double>(f.zsum));
+                                                      bp<uint8_t>(f.kflag), bp<double>(f.zsum));
     chain_pos_kernel<<<(g.n + 127) / 128, 128, 0, s>>>(g.d_pos, g.d_rot, g.d_scale, g.d_sh, g.n, K,
                                                        bp<double>(f.zsum), bp<float4>(f.rec), f.cam, f.ro.kappa,
                                                        weight, slot, b.d_data, zstats_out);

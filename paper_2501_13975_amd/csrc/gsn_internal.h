@@ -36,7 +36,8 @@ struct gsn_frame {
     // per pair
     DevBuf pk_a, pv_a, pk_b, pv_b;  // u32 [pairs] (tile, id) ping-pong
     DevBuf partial;     // float [pairs][GSN_NZ]
-    DevBuf flags;       // u8 [pairs]
+    DevBuf flags;       // u8 [pairs], partial written
+    DevBuf kflag;       // u8 [n], some partial of the kernel written
     // per tile / pixel
     DevBuf ranges;      // uint2 [tiles]
     DevBuf img;         // float [3][H][W]
