@@ -281,7 +281,8 @@ typedef enum {
     GSN_COUNT_BWD_ACTIVE = 2,  /* of which contributed (alpha >= alpha_min) */
     GSN_COUNT_PAIRS = 3,       /* (tile, kernel) pairs binned */
     GSN_COUNT_PARTIALS = 4,    /* (tile, kernel) partial statistics written by the backward pass */
-    GSN_COUNT_N = 5
+    GSN_COUNT_FWD_STAGED = 5,  /* list entries the forward pass staged (read) before its tiles finished */
+    GSN_COUNT_N = 6
 } gsn_counter;
 
 /* Turns stage timing on or off and clears what was accumulated.  While on,

@@ -408,12 +408,13 @@ __global__ __launch_bounds__(GSN_BLOCK) void raster_fwd_kernel(
     uint32_t last = 0;
     bool done = !inside;
     const float fpx = (float)px, fpy = (float)py;
-    uint32_t evals = 0;
+    uint32_t evals = 0, staged = 0;
     for (uint32_t base = rg.x; base < rg.y; base += GSN_BLOCK) {
         if (__syncthreads_count(done) == GSN_BLOCK) break;
         const uint32_t e = base + threadIdx.x;
         uint32_t bandmask = 0;
         if (e < rg.y) {
+            ++staged;
             const uint32_t id = ids[e];
             const float4 a = rec[id], b = rec[n + id], c4 = rec[2 * (size_t)n + id];
             s_a[threadIdx.x] = a;
@@ -464,12 +465,16 @@ __global__ __launch_bounds__(GSN_BLOCK) void raster_fwd_kernel(
         }
     }
     if (counts) {
-        __shared__ unsigned long long s_evals;
-        if (threadIdx.x == 0) s_evals = 0;
+        __shared__ unsigned long long s_evals, s_staged;
+        if (threadIdx.x == 0) s_evals = s_staged = 0;
         __syncthreads();
         atomicAdd(&s_evals, (unsigned long long)evals);
+        atomicAdd(&s_staged, (unsigned long long)staged);
         __syncthreads();
-        if (threadIdx.x == 0) atomicAdd(&counts[GSN_COUNT_FWD_EVALS], s_evals);
+        if (threadIdx.x == 0) {
+            atomicAdd(&counts[GSN_COUNT_FWD_EVALS], s_evals);
+            atomicAdd(&counts[GSN_COUNT_FWD_STAGED], s_staged);
+        }
     }
     if (inside) {
         const size_t np = (size_t)cam.W * cam.H, pi = (size_t)py * cam.W + px;

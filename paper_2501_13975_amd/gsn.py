@@ -269,7 +269,7 @@ class Context:
                                          int(group_mask)))
 
     STAGES = ("project", "sort", "raster_fwd", "loss", "raster_bwd", "chain", "solve", "apply")
-    COUNTERS = ("fwd_evals", "bwd_evals", "bwd_active", "pairs", "partials")
+    COUNTERS = ("fwd_evals", "bwd_evals", "bwd_active", "pairs", "partials", "fwd_staged")
 
     def profile_enable(self, on=True):
         self._check(lib().gsn_profile_enable(self.h, int(bool(on))))
