@@ -915,6 +915,136 @@ extern "C" {
 // Every step is then clamped to its group's trust radius.
 enum { S_COUNT_BASE = 39, S_VIEW = 10, ST_DPOS = 0, ST_DTH = 3, ST_AXIS = 4, ST_DS = 7, ST_DO = 10, ST_DSH = 11 };
 
+}  // extern "C"
+
+namespace {
+
+// The reduced local systems of one kernel (Sec. 4.2, position / rotation / scaling /
+// opacity paragraphs) built from its summed blocks B in the primary camera's frame:
+//   position: U = [u_x u_y] orthonormal in the plane normal to the view axis r,
+//             H = U^T H_p U, g = U^T g_p;
+//   rotation: the left rotation omega = theta r: H = r^T H_omega r, g = r . g_omega;
+//   scaling:  the rows of T = d lambda / d s (unit length), H = T H_s T^T, g = T g_s;
+//   opacity:  H_sigma + h_B, g_sigma + g_B with the log barrier.
+struct Reduced {
+    double r[3], ux[3], uy[3];
+    double Hp[4], gp[2];
+    double Ht, gt;
+    double T2[2][3], Hs[4], gs[2];
+    double Ho, go;
+};
+
+void reduce_systems(const double* B, const double p[3], const double q[4], const double s[3], double sig,
+                    const Cam& c, double kappa, const double* o, double abs_scale, Reduced& R) {
+    double rn = 0.0;
+    for (int a = 0; a < 3; ++a) { R.r[a] = p[a] - c.o[a]; rn += R.r[a] * R.r[a]; }
+    rn = std::sqrt(rn);
+    for (int a = 0; a < 3; ++a) R.r[a] /= rn;
+    const double* r = R.r;
+    // position
+    {
+        double* uy = R.uy;
+        uy[0] = -r[1] * r[0]; uy[1] = 1.0 - r[1] * r[1]; uy[2] = -r[1] * r[2];  // (I - r r^T) e_y
+        double nn = uy[0] * uy[0] + uy[1] * uy[1] + uy[2] * uy[2];
+        if (nn < 1e-12) {
+            uy[0] = 1.0 - r[0] * r[0]; uy[1] = -r[0] * r[1]; uy[2] = -r[0] * r[2];
+            nn = uy[0] * uy[0] + uy[1] * uy[1] + uy[2] * uy[2];
+        }
+        nn = std::sqrt(nn);
+        for (int a = 0; a < 3; ++a) uy[a] /= nn;
+        double* ux = R.ux;
+        ux[0] = r[1] * uy[2] - r[2] * uy[1]; ux[1] = r[2] * uy[0] - r[0] * uy[2]; ux[2] = r[0] * uy[1] - r[1] * uy[0];
+        const double* U[2] = {ux, uy};
+        for (int i = 0; i < 2; ++i) {
+            R.gp[i] = 0.0;
+            for (int a = 0; a < 3; ++a) R.gp[i] += U[i][a] * B[0 + a];
+            for (int j = 0; j < 2; ++j) {
+                double acc = 0.0;
+                for (int a = 0; a < 3; ++a)
+                    for (int b = 0; b < 3; ++b) acc += U[i][a] * B[3 + a * 3 + b] * U[j][b];
+                R.Hp[i * 2 + j] = acc;
+            }
+        }
+    }
+    // rotation
+    R.gt = 0.0;
+    R.Ht = 0.0;
+    for (int a = 0; a < 3; ++a) {
+        R.gt += r[a] * B[12 + a];
+        for (int b = 0; b < 3; ++b) R.Ht += r[a] * B[15 + a * 3 + b] * r[b];
+    }
+    // scaling
+    {
+        double sp[3] = {p[0], p[1], p[2]}, sq[4] = {q[0], q[1], q[2], q[3]}, ss[3] = {s[0], s[1], s[2]};
+        double shk0[48] = {0};
+        const Proj<double> P = project<double>(sp, sq, ss, shk0, 1, c, kappa);
+        double (*T2)[3] = R.T2;
+        for (int i = 0; i < 2; ++i)
+            for (int a = 0; a < 3; ++a) T2[i][a] = 0.0;
+        if (P.ok) {
+            const double a_ = P.cov[0], b_ = P.cov[1], c_ = P.cov[2];
+            const double mid = 0.5 * (a_ + c_), rad = std::sqrt(0.25 * (a_ - c_) * (a_ - c_) + b_ * b_);
+            const double l2 = mid + rad;
+            double v2[2];
+            if (a_ >= c_) { v2[0] = l2 - c_; v2[1] = b_; } else { v2[0] = b_; v2[1] = l2 - a_; }
+            double vn = std::sqrt(v2[0] * v2[0] + v2[1] * v2[1]);
+            if (vn == 0.0) { v2[0] = 1.0; v2[1] = 0.0; vn = 1.0; }
+            v2[0] /= vn; v2[1] /= vn;
+            const double v1[2] = {-v2[1], v2[0]};
+            // M = J W and the rotation of the kernel at the current state
+            double t3[3];
+            for (int i = 0; i < 3; ++i) t3[i] = c.R[3 * i] * p[0] + c.R[3 * i + 1] * p[1] + c.R[3 * i + 2] * p[2] + c.t[i];
+            const double iz = 1.0 / t3[2];
+            const double J00 = c.fx * iz, J02 = -c.fx * t3[0] * iz * iz, J11 = c.fy * iz, J12 = -c.fy * t3[1] * iz * iz;
+            double M[2][3];
+            for (int kk = 0; kk < 3; ++kk) {
+                M[0][kk] = J00 * c.R[kk] + J02 * c.R[6 + kk];
+                M[1][kk] = J11 * c.R[3 + kk] + J12 * c.R[6 + kk];
+            }
+            const double qn = std::sqrt(q[0] * q[0] + q[1] * q[1] + q[2] * q[2] + q[3] * q[3]);
+            const double w = q[0] / qn, x = q[1] / qn, y = q[2] / qn, z = q[3] / qn;
+            const double Rq[3][3] = {{1 - 2 * (y * y + z * z), 2 * (x * y - w * z), 2 * (x * z + w * y)},
+                                     {2 * (x * y + w * z), 1 - 2 * (x * x + z * z), 2 * (y * z - w * x)},
+                                     {2 * (x * z - w * y), 2 * (y * z + w * x), 1 - 2 * (x * x + y * y)}};
+            const double* vv[2] = {v1, v2};  // rows: lambda_min, lambda_max
+            for (int i = 0; i < 2; ++i) {
+                for (int a = 0; a < 3; ++a) {
+                    double e = 0.0;  // v_i^T M R e_a
+                    for (int b = 0; b < 2; ++b)
+                        for (int kk = 0; kk < 3; ++kk) e += vv[i][b] * M[b][kk] * Rq[kk][a];
+                    T2[i][a] = 2.0 * s[a] * e * e;
+                }
+                // only the row space of T matters; unit rows keep the reduced system well scaled
+                const double tn = std::sqrt(T2[i][0] * T2[i][0] + T2[i][1] * T2[i][1] + T2[i][2] * T2[i][2]);
+                if (tn > 0.0)
+                    for (int a = 0; a < 3; ++a) T2[i][a] /= tn;
+            }
+        }
+        for (int i = 0; i < 2; ++i) {
+            R.gs[i] = 0.0;
+            for (int a = 0; a < 3; ++a) R.gs[i] += T2[i][a] * B[24 + a];
+            for (int j = 0; j < 2; ++j) {
+                double acc = 0.0;
+                for (int a = 0; a < 3; ++a)
+                    for (int b = 0; b < 3; ++b) acc += T2[i][a] * B[27 + a * 3 + b] * T2[j][b];
+                R.Hs[i * 2 + j] = acc;
+            }
+        }
+    }
+    // opacity with the log barrier -alpha_s [ln sigma + ln(1 - sigma)]
+    {
+        const double as = o[O_BARRIER_BETA] * abs_scale;
+        const double gB = as * (1.0 / (1.0 - sig) - 1.0 / sig);
+        const double hB = as * (1.0 / (sig * sig) + 1.0 / ((1.0 - sig) * (1.0 - sig)));
+        R.Ho = B[37] + hB;
+        R.go = B[36] + gB;
+    }
+}
+
+}  // namespace
+
+extern "C" {
+
 int orc_solve(int n, int K, const double* pos, const double* rot, const double* scale, const double* opac,
               const double* cam, const double* o, int V, const double* blocks, double* steps, int32_t* dec,
               double* cond) {
@@ -938,125 +1068,37 @@ int orc_solve(int n, int K, const double* pos, const double* rot, const double* 
         for (int a = 0; a < 4; ++a) q[a] = rot[(size_t)a * n + k];
         for (int a = 0; a < 3; ++a) s[a] = scale[(size_t)a * n + k];
         const double sig = opac[k];
-        // view axis r_k of the primary camera
-        double r[3], rn = 0.0;
-        for (int a = 0; a < 3; ++a) { r[a] = p[a] - c.o[a]; rn += r[a] * r[a]; }
-        rn = std::sqrt(rn);
-        for (int a = 0; a < 3; ++a) r[a] /= rn;
-        for (int a = 0; a < 3; ++a) st[ST_AXIS + a] = r[a];
-
-        // Position: Delta p = U Delta v with U an orthonormal basis of the plane normal to r.
+        Reduced R;
+        reduce_systems(B, p, q, s, sig, c, kappa, o, abs_scale, R);
+        for (int a = 0; a < 3; ++a) st[ST_AXIS + a] = R.r[a];
+        // position: Delta p = U Delta v
         {
-            double uy[3] = {-r[1] * r[0], 1.0 - r[1] * r[1], -r[1] * r[2]};  // (I - r r^T) e_y
-            double nn = uy[0] * uy[0] + uy[1] * uy[1] + uy[2] * uy[2];
-            if (nn < 1e-12) {
-                uy[0] = 1.0 - r[0] * r[0]; uy[1] = -r[0] * r[1]; uy[2] = -r[0] * r[2];
-                nn = uy[0] * uy[0] + uy[1] * uy[1] + uy[2] * uy[2];
-            }
-            nn = std::sqrt(nn);
-            for (int a = 0; a < 3; ++a) uy[a] /= nn;
-            const double ux[3] = {r[1] * uy[2] - r[2] * uy[1], r[2] * uy[0] - r[0] * uy[2], r[0] * uy[1] - r[1] * uy[0]};
-            const double* U[2] = {ux, uy};
-            double H2[4], g2[2], dv[2];
-            for (int i = 0; i < 2; ++i) {
-                g2[i] = 0.0;
-                for (int a = 0; a < 3; ++a) g2[i] += U[i][a] * B[0 + a];
-                for (int j = 0; j < 2; ++j) {
-                    double acc = 0.0;
-                    for (int a = 0; a < 3; ++a)
-                        for (int b = 0; b < 3; ++b) acc += U[i][a] * B[3 + a * 3 + b] * U[j][b];
-                    H2[i * 2 + j] = acc;
-                }
-            }
-            dk[0] = damped_solve(2, H2, g2, o, dv, &cnd[0]);
+            double H2[4] = {R.Hp[0], R.Hp[1], R.Hp[2], R.Hp[3]}, dv[2];
+            dk[0] = damped_solve(2, H2, R.gp, o, dv, &cnd[0]);
             clamp_norm(2, dv, o[O_TRUST_POS] * std::max(s[0], std::max(s[1], s[2])));
-            for (int a = 0; a < 3; ++a) st[ST_DPOS + a] = ux[a] * dv[0] + uy[a] * dv[1];
+            for (int a = 0; a < 3; ++a) st[ST_DPOS + a] = R.ux[a] * dv[0] + R.uy[a] * dv[1];
         }
-        // Rotation: q(theta) = dq(theta) * q with dq = [cos(theta/2), sin(theta/2) r], the left
-        // rotation by omega = theta r: g_theta = r . g_omega, H_theta = r^T H_omega r.
+        // rotation: q(theta) = dq(theta) * q with dq = [cos(theta/2), sin(theta/2) r]
         {
-            double gt = 0.0, Ht = 0.0;
-            for (int a = 0; a < 3; ++a) {
-                gt += r[a] * B[12 + a];
-                for (int b = 0; b < 3; ++b) Ht += r[a] * B[15 + a * 3 + b] * r[b];
-            }
             double th;
-            dk[1] = damped_solve(1, &Ht, &gt, o, &th, &cnd[1]);
+            dk[1] = damped_solve(1, &R.Ht, &R.gt, o, &th, &cnd[1]);
             clamp_norm(1, &th, o[O_TRUST_ROT]);
             st[ST_DTH] = th;
         }
-        // Scaling: Newton restricted to the row space of T = d lambda / d s, where
-        // lambda are the eigenvalues of the primary's 2D covariance.
+        // scaling: Delta s = T^T a
         {
-            double sp[3] = {p[0], p[1], p[2]}, sq[4] = {q[0], q[1], q[2], q[3]}, ss[3] = {s[0], s[1], s[2]};
-            double shk0[48] = {0};
-            const Proj<double> P = project<double>(sp, sq, ss, shk0, 1, c, kappa);
-            double T2[2][3] = {{0, 0, 0}, {0, 0, 0}};
-            if (P.ok) {
-                const double a_ = P.cov[0], b_ = P.cov[1], c_ = P.cov[2];
-                const double mid = 0.5 * (a_ + c_), rad = std::sqrt(0.25 * (a_ - c_) * (a_ - c_) + b_ * b_);
-                const double l2 = mid + rad;
-                double v2[2];
-                if (a_ >= c_) { v2[0] = l2 - c_; v2[1] = b_; } else { v2[0] = b_; v2[1] = l2 - a_; }
-                double vn = std::sqrt(v2[0] * v2[0] + v2[1] * v2[1]);
-                if (vn == 0.0) { v2[0] = 1.0; v2[1] = 0.0; vn = 1.0; }
-                v2[0] /= vn; v2[1] /= vn;
-                const double v1[2] = {-v2[1], v2[0]};
-                // M = J W and the rotation of the kernel at the current state
-                double t3[3];
-                for (int i = 0; i < 3; ++i) t3[i] = c.R[3 * i] * p[0] + c.R[3 * i + 1] * p[1] + c.R[3 * i + 2] * p[2] + c.t[i];
-                const double iz = 1.0 / t3[2];
-                const double J00 = c.fx * iz, J02 = -c.fx * t3[0] * iz * iz, J11 = c.fy * iz, J12 = -c.fy * t3[1] * iz * iz;
-                double M[2][3];
-                for (int kk = 0; kk < 3; ++kk) {
-                    M[0][kk] = J00 * c.R[kk] + J02 * c.R[6 + kk];
-                    M[1][kk] = J11 * c.R[3 + kk] + J12 * c.R[6 + kk];
-                }
-                const double qn = std::sqrt(q[0] * q[0] + q[1] * q[1] + q[2] * q[2] + q[3] * q[3]);
-                const double w = q[0] / qn, x = q[1] / qn, y = q[2] / qn, z = q[3] / qn;
-                const double Rq[3][3] = {{1 - 2 * (y * y + z * z), 2 * (x * y - w * z), 2 * (x * z + w * y)},
-                                         {2 * (x * y + w * z), 1 - 2 * (x * x + z * z), 2 * (y * z - w * x)},
-                                         {2 * (x * z - w * y), 2 * (y * z + w * x), 1 - 2 * (x * x + y * y)}};
-                const double* vv[2] = {v1, v2};  // rows: lambda_min, lambda_max
-                for (int i = 0; i < 2; ++i) {
-                    for (int a = 0; a < 3; ++a) {
-                        double e = 0.0;  // v_i^T M R e_a
-                        for (int b = 0; b < 2; ++b)
-                            for (int kk = 0; kk < 3; ++kk) e += vv[i][b] * M[b][kk] * Rq[kk][a];
-                        T2[i][a] = 2.0 * s[a] * e * e;
-                    }
-                    // only the row space of T matters; unit rows keep the reduced system well scaled
-                    const double tn = std::sqrt(T2[i][0] * T2[i][0] + T2[i][1] * T2[i][1] + T2[i][2] * T2[i][2]);
-                    if (tn > 0.0)
-                        for (int a = 0; a < 3; ++a) T2[i][a] /= tn;
-                }
-            }
-            double H2[4], g2[2], av[2];
-            for (int i = 0; i < 2; ++i) {
-                g2[i] = 0.0;
-                for (int a = 0; a < 3; ++a) g2[i] += T2[i][a] * B[24 + a];
-                for (int j = 0; j < 2; ++j) {
-                    double acc = 0.0;
-                    for (int a = 0; a < 3; ++a)
-                        for (int b = 0; b < 3; ++b) acc += T2[i][a] * B[27 + a * 3 + b] * T2[j][b];
-                    H2[i * 2 + j] = acc;
-                }
-            }
-            dk[2] = damped_solve(2, H2, g2, o, av, &cnd[2]);
+            double av[2];
+            dk[2] = damped_solve(2, R.Hs, R.gs, o, av, &cnd[2]);
             // the rows of T are unit but not orthogonal, so the clamp acts on Delta s itself
             double dsv[3];
-            for (int a = 0; a < 3; ++a) dsv[a] = T2[0][a] * av[0] + T2[1][a] * av[1];
+            for (int a = 0; a < 3; ++a) dsv[a] = R.T2[0][a] * av[0] + R.T2[1][a] * av[1];
             clamp_norm(3, dsv, o[O_TRUST_SCALE] * std::sqrt(s[0] * s[0] + s[1] * s[1] + s[2] * s[2]));
             for (int a = 0; a < 3; ++a) st[ST_DS + a] = dsv[a];
         }
-        // Opacity with the log barrier -alpha_s [ln sigma + ln(1 - sigma)].
+        // opacity with the log barrier
         {
-            const double as = o[O_BARRIER_BETA] * abs_scale;
-            const double gB = as * (1.0 / (1.0 - sig) - 1.0 / sig);
-            const double hB = as * (1.0 / (sig * sig) + 1.0 / ((1.0 - sig) * (1.0 - sig)));
-            const double H1 = B[37] + hB, g1 = B[36] + gB;
             double ds;
-            dk[3] = damped_solve(1, &H1, &g1, o, &ds, &cnd[3]);
+            dk[3] = damped_solve(1, &R.Ho, &R.go, o, &ds, &cnd[3]);
             st[ST_DO] = ds;
         }
         // Colour: per channel, G = sum_v s~_v b_v b_v^T, g = sum_v gamma_v b_v, b_v = Y(r_v).
@@ -1096,6 +1138,77 @@ int orc_solve(int n, int K, const double* pos, const double* rot, const double* 
         }
         if (cond)
             for (int i = 0; i < 4; ++i) cond[(size_t)k * 4 + i] = cnd[i];
+    }
+    return 0;
+}
+
+// Features of the learned step scale (one 16-vector per kernel) from the summed blocks of
+// the primary view alone, in the reduced coordinates of the solve.  With
+// L(x) = log10(x + 1e-30) / 10:
+//   0, 1  L(|lambda|) of the larger / smaller eigenvalue of the reduced position Hessian,
+//   2     sign of its smaller eigenvalue (+1 when >= 0),
+//   3, 4  L(|H_theta|), sign of H_theta,
+//   5, 6  L(|lambda|) of the reduced scaling Hessian's eigenvalues (larger, smaller),
+//   7     sign of its smaller eigenvalue,
+//   8     L(|H_sigma + h_B|),
+//   9     L(sum over channels of |s|, the primary view's colour Hessian diagonal),
+//   10    L(primary coverage w),
+//   11-14 L(|g|) of the reduced position, rotation, scaling and opacity gradients,
+//   15    L(opacity).
+// ok[k] = 1 when the kernel is visible in the primary view and every L argument lies in
+// [1e-30, 1e30] (so that no feature leaves [-3, 3]).
+int orc_features(int n, int K, const double* pos, const double* rot, const double* scale, const double* opac,
+                 const double* cam, const double* o, int V, const double* blocks, double* feat, uint8_t* ok) {
+    const Cam c = load_cam(cam);
+    const int NB = S_COUNT_BASE + V * S_VIEW;
+    const double kappa = o[O_SMOOTH] != 0.0 ? 0.0 : o[O_KAPPA];
+    const double abs_scale = 1.0 / (3.0 * o[O_NPIX_PRIMARY]);
+    (void)K;
+#pragma omp parallel for schedule(static)
+    for (int k = 0; k < n; ++k) {
+        const double* B = blocks + (size_t)k * NB;
+        double* f = feat + (size_t)k * 16;
+        std::fill(f, f + 16, 0.0);
+        ok[k] = 0;
+        if (!(B[38] > 0.0)) continue;
+        double p[3], q[4], s[3];
+        for (int a = 0; a < 3; ++a) p[a] = pos[(size_t)a * n + k];
+        for (int a = 0; a < 4; ++a) q[a] = rot[(size_t)a * n + k];
+        for (int a = 0; a < 3; ++a) s[a] = scale[(size_t)a * n + k];
+        Reduced R;
+        reduce_systems(B, p, q, s, opac[k], c, kappa, o, abs_scale, R);
+        bool in_range = true;
+        auto L = [&](double x) {
+            const double v = std::log10(x + 1e-30) / 10.0;
+            if (!(v >= -3.0 && v <= 3.0)) in_range = false;
+            return std::min(3.0, std::max(-3.0, v));
+        };
+        auto eig2 = [](const double* H, double& hi, double& lo) {
+            const double mid = 0.5 * (H[0] + H[3]);
+            const double rad = std::sqrt(0.25 * (H[0] - H[3]) * (H[0] - H[3]) + H[1] * H[1]);
+            hi = mid + rad;
+            lo = mid - rad;
+        };
+        double hi, lo;
+        eig2(R.Hp, hi, lo);
+        f[0] = L(std::fabs(hi));
+        f[1] = L(std::fabs(lo));
+        f[2] = lo >= 0.0 ? 1.0 : -1.0;
+        f[3] = L(std::fabs(R.Ht));
+        f[4] = R.Ht >= 0.0 ? 1.0 : -1.0;
+        eig2(R.Hs, hi, lo);
+        f[5] = L(std::fabs(hi));
+        f[6] = L(std::fabs(lo));
+        f[7] = lo >= 0.0 ? 1.0 : -1.0;
+        f[8] = L(std::fabs(R.Ho));
+        f[9] = L(std::fabs(B[S_COUNT_BASE + 3]) + std::fabs(B[S_COUNT_BASE + 4]) + std::fabs(B[S_COUNT_BASE + 5]));
+        f[10] = L(B[38]);
+        f[11] = L(std::sqrt(R.gp[0] * R.gp[0] + R.gp[1] * R.gp[1]));
+        f[12] = L(std::fabs(R.gt));
+        f[13] = L(std::sqrt(R.gs[0] * R.gs[0] + R.gs[1] * R.gs[1]));
+        f[14] = L(std::fabs(R.go));
+        f[15] = L(opac[k]);
+        ok[k] = in_range ? 1 : 0;
     }
     return 0;
 }
