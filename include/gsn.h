@@ -205,9 +205,75 @@ gsn_status gsn_local_newton_solve(gsn_ctx* ctx, const gsn_gaussians* g, const gs
  * renormalised with dq = (cos(theta/2), sin(theta/2) r_k); s <- max(s + Delta s,
  * scale_floor s); sigma <- sigma + Delta sigma clipped to the fraction
  * opac_ftb of the way to 0 or 1; SH += Delta SH (Sec. 4.2).
+ * d_scale: NULL, or device float [5][n] multiplying each kernel's step of each
+ * group (position, rotation, scaling, opacity, colour) before it is applied
+ * (the learned step scale, see gsn_mlp_infer).
  * Errors: GSN_E_SHAPE (steps.n != g->n). */
 gsn_status gsn_apply_step(gsn_ctx* ctx, gsn_gaussians* g, const gsn_steps* steps,
-                          const gsn_solve_opts* opts, uint32_t group_mask);
+                          const gsn_solve_opts* opts, const float* d_scale, uint32_t group_mask);
+
+/* ------------------------------------------------- learned step scale
+ * The overshoot control of Sec. 4.3 (eq. tildel) adds the blocks of the
+ * |N_t| nearest training views to the primary's.  The learned form predicts,
+ * per kernel and group, the scale alpha that the full rule applies along the
+ * primary-only step, so that most sweeps render only the primary view:
+ *   features (gsn_step_features) from the primary view's blocks alone,
+ *   network 16 -> 32 (ReLU) -> 5, alpha = 1.5 sigmoid(.) (gsn_mlp_infer),
+ *   labels alpha_eff = <Delta_aug, Delta_prim> / |Delta_prim|^2 clipped to
+ *   [0, 1.5] from a sweep that runs the full rule (gsn_step_labels),
+ *   training by mean squared error and Adam (gsn_mlp_train_step). */
+#define GSN_MLP_IN 16
+#define GSN_MLP_HID 32
+#define GSN_MLP_OUT 5
+#define GSN_MLP_PARAMS 709
+/* Network state, device buffers owned by the caller: d_params float [709]
+ * master weights laid out W1 [32][16] row-major, b1 [32], W2 [5][32]
+ * row-major, b2 [5]; d_m, d_v float [709] Adam moments; d_half fp16 [709]
+ * inference copy; step: Adam steps taken (advanced by gsn_mlp_train_step). */
+typedef struct {
+    float* d_params;
+    float* d_m;
+    float* d_v;
+    uint16_t* d_half;
+    int32_t step;
+} gsn_mlp;
+typedef struct {
+    float lr, beta1, beta2, eps;
+} gsn_adam_opts;
+
+/* Features of every kernel (device float [16][n], layout feature-major) from
+ * blocks holding only the primary view (slot 0), in the reduced coordinates of
+ * gsn_local_newton_solve.  With L(x) = log10(x + 1e-30) / 10 clipped to [-3, 3]:
+ * 0, 1 L(|lambda|) of the reduced position Hessian's larger / smaller
+ * eigenvalue; 2 sign of the smaller; 3, 4 L(|H_theta|), sign; 5, 6, 7 the same
+ * for the reduced scaling Hessian; 8 L(|H_sigma + h_B|); 9 L(sum of |s| of the
+ * primary's colour Hessian diagonal); 10 L(primary coverage); 11-14 L(|g|) of
+ * the reduced position, rotation, scaling and opacity gradients; 15 L(opacity).
+ * d_ok (device u8 [n]) is 1 for kernels visible in the primary whose features
+ * all lie inside [-3, 3] before clipping.  Errors: GSN_E_SHAPE. */
+gsn_status gsn_step_features(gsn_ctx* ctx, const gsn_gaussians* g, const gsn_camera* primary,
+                             const gsn_blocks* blocks, const gsn_solve_opts* opts, float* d_feat,
+                             uint8_t* d_ok);
+/* Labels from the primary-only steps (prim) and the full-rule steps (aug) of
+ * the same sweep: d_label, d_mask device float [5][n]; the mask is 1 where the
+ * kernel is visible in the primary and |Delta_prim|^2 > 1e-30 for the group. */
+gsn_status gsn_step_labels(gsn_ctx* ctx, const gsn_steps* prim, const gsn_steps* aug, float* d_label,
+                           float* d_mask);
+/* Zeroes the Adam moments and the step count and refreshes the fp16 copy from
+ * the master weights. */
+gsn_status gsn_mlp_reset(gsn_ctx* ctx, gsn_mlp* mlp);
+/* alpha (device float [5][n]) for every kernel from its features, with the
+ * fp16 weights and FP32 accumulation; kernels with d_ok[k] == 0 get 0 (no
+ * step until a sweep that runs the full rule). */
+gsn_status gsn_mlp_infer(gsn_ctx* ctx, const gsn_mlp* mlp, int32_t n, const float* d_feat,
+                         const uint8_t* d_ok, float* d_alpha);
+/* One Adam step on the mean squared error over the entries with mask 1
+ * (features [16][n], labels and mask [5][n]); writes the loss before the step
+ * to d_loss (device double, may be NULL) and the gradient to d_grad (device
+ * float [709], may be NULL).  Gradient partials are summed in a fixed order:
+ * results are deterministic.  Errors: GSN_E_INVALID (n < 0, null buffers). */
+gsn_status gsn_mlp_train_step(gsn_ctx* ctx, gsn_mlp* mlp, int32_t n, const float* d_feat, const float* d_label,
+                              const float* d_mask, const gsn_adam_opts* adam, double* d_loss, float* d_grad);
 
 /* ---------------------------------------------------------------- helpers */
 

@@ -258,8 +258,16 @@ def solve(g, cam, o, summed, V, with_cond=False):
     return (steps, dec, cond) if with_cond else (steps, dec)
 
 
-def apply(g, steps, dec, o, mask=31) -> G64:
+def apply(g, steps, dec, o, mask=31, scale=None) -> G64:
+    """Applies the steps; scale [n][5] (optional) multiplies each group's step of each kernel
+    (position, rotation angle, scaling, opacity, colour) before it is applied."""
     out = G64.of(g).copy()
+    if scale is not None:
+        steps = np.array(steps, np.float64)
+        sc = np.asarray(scale, np.float64)
+        K = out.K
+        for gi, sl in enumerate([slice(0, 3), slice(3, 4), slice(7, 10), slice(10, 11), slice(11, 11 + 3 * K)]):
+            steps[:, sl] *= sc[:, gi:gi + 1]
     lib().orc_apply(ctypes.c_int(out.n), ctypes.c_int(out.K), _p(out.pos), _p(out.rot), _p(out.scale),
                     _p(out.opac), _p(out.sh), _p(o), _p(np.ascontiguousarray(steps)),
                     _p(np.ascontiguousarray(dec)), ctypes.c_int(mask))

@@ -146,6 +146,8 @@ gsn_status gsn_destroy(gsn_ctx* ctx) {
     }
     for (hipEvent_t e : ctx->pool) (void)hipEventDestroy(e);
     if (ctx->d_counts) (void)hipFree(ctx->d_counts);
+    buf_free(ctx->mlp_part);
+    buf_free(ctx->mlp_stat);
     delete ctx;
     return GSN_OK;
 }
@@ -409,14 +411,84 @@ gsn_status gsn_local_newton_solve(gsn_ctx* ctx, const gsn_gaussians* g, const gs
 }
 
 gsn_status gsn_apply_step(gsn_ctx* ctx, gsn_gaussians* g, const gsn_steps* st, const gsn_solve_opts* o,
-                          uint32_t group_mask) {
+                          const float* d_scale, uint32_t group_mask) {
     if (!ctx || !st || !o) return fail(ctx, GSN_E_INVALID, "null argument");
     gsn_status r = check_gaussians(ctx, g);
     if (r != GSN_OK) return r;
     if (st->n != g->n || st->sh_degree != g->sh_degree) return fail(ctx, GSN_E_SHAPE, "steps do not match gaussians");
     HIP_TRY(ctx, hipSetDevice(ctx->device));
     StageTimer st_(ctx, GSN_STAGE_APPLY);
-    launch_apply(*g, *st, *o, group_mask, ctx->stream);
+    launch_apply(*g, *st, *o, d_scale, group_mask, ctx->stream);
+    HIP_TRY(ctx, hipGetLastError());
+    return GSN_OK;
+}
+
+gsn_status gsn_step_features(gsn_ctx* ctx, const gsn_gaussians* g, const gsn_camera* primary,
+                             const gsn_blocks* b, const gsn_solve_opts* o, float* d_feat, uint8_t* d_ok) {
+    if (!ctx || !b || !o) return fail(ctx, GSN_E_INVALID, "null argument");
+    gsn_status r = check_gaussians(ctx, g);
+    if (r != GSN_OK) return r;
+    if ((r = check_camera(ctx, primary)) != GSN_OK) return r;
+    if (b->n != g->n) return fail(ctx, GSN_E_SHAPE, "n mismatch");
+    if (g->n > 0 && (!b->d_data || !d_feat || !d_ok)) return fail(ctx, GSN_E_INVALID, "null device array");
+    if (o->npix_primary <= 0) return fail(ctx, GSN_E_INVALID, "npix_primary must be positive");
+    HIP_TRY(ctx, hipSetDevice(ctx->device));
+    launch_features(*g, make_devcam(*primary), o->kappa, *b, *o, d_feat, d_ok, ctx->stream);
+    HIP_TRY(ctx, hipGetLastError());
+    return GSN_OK;
+}
+
+gsn_status gsn_step_labels(gsn_ctx* ctx, const gsn_steps* prim, const gsn_steps* aug, float* d_label,
+                           float* d_mask) {
+    if (!ctx || !prim || !aug) return fail(ctx, GSN_E_INVALID, "null argument");
+    if (prim->n != aug->n || prim->sh_degree != aug->sh_degree) return fail(ctx, GSN_E_SHAPE, "steps differ in shape");
+    if (prim->n < 0 || prim->sh_degree < 0 || prim->sh_degree > 3) return fail(ctx, GSN_E_SHAPE, "bad steps shape");
+    if (prim->n > 0 && (!prim->d_data || !prim->d_flags || !aug->d_data || !d_label || !d_mask))
+        return fail(ctx, GSN_E_INVALID, "null device array");
+    HIP_TRY(ctx, hipSetDevice(ctx->device));
+    const int K = (prim->sh_degree + 1) * (prim->sh_degree + 1);
+    launch_labels(prim->n, K, prim->d_data, prim->d_flags, aug->d_data, d_label, d_mask, ctx->stream);
+    HIP_TRY(ctx, hipGetLastError());
+    return GSN_OK;
+}
+
+gsn_status gsn_mlp_reset(gsn_ctx* ctx, gsn_mlp* mlp) {
+    if (!ctx || !mlp || !mlp->d_params || !mlp->d_m || !mlp->d_v || !mlp->d_half)
+        return fail(ctx, GSN_E_INVALID, "null argument");
+    HIP_TRY(ctx, hipSetDevice(ctx->device));
+    mlp->step = 0;
+    launch_mlp_reset(*mlp, ctx->stream);
+    HIP_TRY(ctx, hipGetLastError());
+    return GSN_OK;
+}
+
+gsn_status gsn_mlp_infer(gsn_ctx* ctx, const gsn_mlp* mlp, int32_t n, const float* d_feat, const uint8_t* d_ok,
+                         float* d_alpha) {
+    if (!ctx || !mlp || !mlp->d_half) return fail(ctx, GSN_E_INVALID, "null argument");
+    if (n < 0) return fail(ctx, GSN_E_INVALID, "n < 0");
+    if (n > 0 && (!d_feat || !d_ok || !d_alpha)) return fail(ctx, GSN_E_INVALID, "null device array");
+    HIP_TRY(ctx, hipSetDevice(ctx->device));
+    launch_mlp_infer(mlp->d_half, n, d_feat, d_ok, d_alpha, ctx->stream);
+    HIP_TRY(ctx, hipGetLastError());
+    return GSN_OK;
+}
+
+gsn_status gsn_mlp_train_step(gsn_ctx* ctx, gsn_mlp* mlp, int32_t n, const float* d_feat, const float* d_label,
+                              const float* d_mask, const gsn_adam_opts* a, double* d_loss, float* d_grad) {
+    if (!ctx || !mlp || !a || !mlp->d_params || !mlp->d_m || !mlp->d_v || !mlp->d_half)
+        return fail(ctx, GSN_E_INVALID, "null argument");
+    if (n < 0) return fail(ctx, GSN_E_INVALID, "n < 0");
+    if (n > 0 && (!d_feat || !d_label || !d_mask)) return fail(ctx, GSN_E_INVALID, "null device array");
+    if (!(a->lr > 0.f) || !(a->beta1 >= 0.f && a->beta1 < 1.f) || !(a->beta2 >= 0.f && a->beta2 < 1.f) ||
+        !(a->eps > 0.f))
+        return fail(ctx, GSN_E_INVALID, "Adam option out of range");
+    HIP_TRY(ctx, hipSetDevice(ctx->device));
+    const int nb = std::max(mlp_grad_blocks(n), 1);
+    HIP_TRY(ctx, buf_reserve(ctx->mlp_part, (size_t)nb * GSN_MLP_PARAMS * 4));
+    HIP_TRY(ctx, buf_reserve(ctx->mlp_stat, (size_t)nb * 2 * 8));
+    mlp->step += 1;
+    launch_mlp_train(*mlp, n, d_feat, d_label, d_mask, bp<float>(ctx->mlp_part), bp<double>(ctx->mlp_stat), *a,
+                     d_grad, d_loss, ctx->stream);
     HIP_TRY(ctx, hipGetLastError());
     return GSN_OK;
 }

@@ -69,6 +69,8 @@ struct gsn_ctx {
     std::vector<hipEvent_t> pool;
     unsigned long long* d_counts = nullptr;  // GSN_COUNT_N device counters
     int64_t pairs_counted = 0;
+    // gradient partials of gsn_mlp_train_step
+    DevBuf mlp_part, mlp_stat;
 };
 
 // Brackets one stage with events when profiling is on.
@@ -115,5 +117,14 @@ void launch_reduce_chain(const gsn_frame& f, const gsn_gaussians& g, float weigh
 // ---- launchers (solve.hip)
 void launch_solve(const gsn_gaussians& g, const DevCam& cam, float kappa, const gsn_blocks& b,
                   const gsn_solve_opts& o, const gsn_steps& st, hipStream_t s);
-void launch_apply(const gsn_gaussians& g, const gsn_steps& st, const gsn_solve_opts& o, uint32_t mask,
-                  hipStream_t s);
+void launch_apply(const gsn_gaussians& g, const gsn_steps& st, const gsn_solve_opts& o, const float* scale,
+                  uint32_t mask, hipStream_t s);
+void launch_features(const gsn_gaussians& g, const DevCam& cam, float kappa, const gsn_blocks& b,
+                     const gsn_solve_opts& o, float* feat, uint8_t* ok, hipStream_t s);
+void launch_labels(int n, int K, const float* sp, const int32_t* fp, const float* sa, float* label, float* mask,
+                   hipStream_t s);
+void launch_mlp_infer(const uint16_t* wh, int n, const float* feat, const uint8_t* ok, float* out, hipStream_t s);
+int mlp_grad_blocks(int n);
+void launch_mlp_train(gsn_mlp& mlp, int n, const float* feat, const float* label, const float* mask, float* part,
+                      double* stat, const gsn_adam_opts& a, float* grad_out, double* loss, hipStream_t s);
+void launch_mlp_reset(gsn_mlp& mlp, hipStream_t s);

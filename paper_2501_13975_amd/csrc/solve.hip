@@ -21,6 +21,7 @@
 // space, (B B^T + mu S^-1) y = -S^-1 gamma, Delta = B^T y, which equals the
 // damped K x K solve exactly and is far better conditioned.
 #include "gsn_internal.h"
+#include "reduced.h"
 
 namespace {
 
@@ -238,148 +239,38 @@ __global__ __launch_bounds__(128) void solve_kernel(const float* __restrict__ po
         return;
     }
     const double abs_scale = 1.0 / (3.0 * (double)o.npix_primary);
-    double p[3], q[4], s[3];
-    for (int a = 0; a < 3; ++a) p[a] = pos[a * N + k];
-    for (int a = 0; a < 4; ++a) q[a] = rot[a * N + k];
+    double s[3];
     for (int a = 0; a < 3; ++a) s[a] = scale[a * N + k];
-    const double sig = opac[k];
-    double r[3];
+    Reduced R;
+    reduce_systems(pos, rot, scale, opac, n, k, c, kappa, B, o, abs_scale, R);
+    for (int a = 0; a < 3; ++a) st[(4 + a) * N + k] = (float)R.r[a];
+    // ---- position: Delta p = U Delta v
     {
-        // camera centre -R^T t in double from the float camera
-        double oc[3];
-        for (int i = 0; i < 3; ++i)
-            oc[i] = -((double)c.R[i] * c.t[0] + (double)c.R[3 + i] * c.t[1] + (double)c.R[6 + i] * c.t[2]);
-        for (int a = 0; a < 3; ++a) r[a] = p[a] - oc[a];
-        const double il = 1.0 / sqrt(r[0] * r[0] + r[1] * r[1] + r[2] * r[2]);
-        for (int a = 0; a < 3; ++a) r[a] *= il;
-    }
-    for (int a = 0; a < 3; ++a) st[(4 + a) * N + k] = (float)r[a];
-    // ---- position
-    {
-        double uy[3] = {-r[1] * r[0], 1.0 - r[1] * r[1], -r[1] * r[2]};
-        double nn = uy[0] * uy[0] + uy[1] * uy[1] + uy[2] * uy[2];
-        if (nn < 1e-12) {
-            uy[0] = 1.0 - r[0] * r[0];
-            uy[1] = -r[0] * r[1];
-            uy[2] = -r[0] * r[2];
-            nn = uy[0] * uy[0] + uy[1] * uy[1] + uy[2] * uy[2];
-        }
-        const double inn = 1.0 / sqrt(nn);
-        for (int a = 0; a < 3; ++a) uy[a] *= inn;
-        const double ux[3] = {r[1] * uy[2] - r[2] * uy[1], r[2] * uy[0] - r[0] * uy[2], r[0] * uy[1] - r[1] * uy[0]};
-        const double Hp[3][3] = {{B(3), B(4), B(5)}, {B(4), B(6), B(7)}, {B(5), B(7), B(8)}};
-        const double gp[3] = {B(0), B(1), B(2)};
-        double HU[3][2];
-        for (int a = 0; a < 3; ++a) {
-            HU[a][0] = Hp[a][0] * ux[0] + Hp[a][1] * ux[1] + Hp[a][2] * ux[2];
-            HU[a][1] = Hp[a][0] * uy[0] + Hp[a][1] * uy[1] + Hp[a][2] * uy[2];
-        }
-        double H2[3], g2[2], dv[2];
-        g2[0] = ux[0] * gp[0] + ux[1] * gp[1] + ux[2] * gp[2];
-        g2[1] = uy[0] * gp[0] + uy[1] * gp[1] + uy[2] * gp[2];
-        H2[0] = ux[0] * HU[0][0] + ux[1] * HU[1][0] + ux[2] * HU[2][0];
-        H2[1] = ux[0] * HU[0][1] + ux[1] * HU[1][1] + ux[2] * HU[2][1];
-        H2[2] = uy[0] * HU[0][1] + uy[1] * HU[1][1] + uy[2] * HU[2][1];
-        fl[0 * N + k] = damped_small(2, H2, g2, o, abs_scale, dv);
+        double dv[2];
+        fl[0 * N + k] = damped_small(2, R.Hp, R.gp, o, abs_scale, dv);
         clamp_norm(2, dv, (double)o.trust_pos * fmax(s[0], fmax(s[1], s[2])));
-        for (int a = 0; a < 3; ++a) st[(size_t)a * N + k] = (float)(ux[a] * dv[0] + uy[a] * dv[1]);
+        for (int a = 0; a < 3; ++a) st[(size_t)a * N + k] = (float)(R.ux[a] * dv[0] + R.uy[a] * dv[1]);
     }
     // ---- rotation about r: omega = theta r
     {
-        const double Hw[3][3] = {{B(12), B(13), B(14)}, {B(13), B(15), B(16)}, {B(14), B(16), B(17)}};
-        double gt = 0.0, Ht = 0.0;
-        for (int a = 0; a < 3; ++a) {
-            gt += r[a] * B(9 + a);
-            for (int b = 0; b < 3; ++b) Ht += r[a] * Hw[a][b] * r[b];
-        }
         double th;
-        fl[1 * N + k] = damped_small(1, &Ht, &gt, o, abs_scale, &th);
+        fl[1 * N + k] = damped_small(1, &R.Ht, &R.gt, o, abs_scale, &th);
         clamp_norm(1, &th, (double)o.trust_rot);
         st[3 * N + k] = (float)th;
     }
-    // ---- scaling in the row space of d lambda / d s (unit rows)
+    // ---- scaling in the row space of d lambda / d s: Delta s = T^T a
     {
-        double tf[3];
-        for (int i = 0; i < 3; ++i) tf[i] = c.R[3 * i] * p[0] + c.R[3 * i + 1] * p[1] + c.R[3 * i + 2] * p[2] + c.t[i];
-        const double iz = 1.0 / tf[2];
-        const double J00 = c.fx * iz, J02 = -c.fx * tf[0] * iz * iz, J11 = c.fy * iz, J12 = -c.fy * tf[1] * iz * iz;
-        double M[2][3];
-        for (int kk = 0; kk < 3; ++kk) {
-            M[0][kk] = J00 * c.R[kk] + J02 * c.R[6 + kk];
-            M[1][kk] = J11 * c.R[3 + kk] + J12 * c.R[6 + kk];
-        }
-        const double qn = 1.0 / sqrt(q[0] * q[0] + q[1] * q[1] + q[2] * q[2] + q[3] * q[3]);
-        const double w = q[0] * qn, x = q[1] * qn, y = q[2] * qn, z = q[3] * qn;
-        const double Rq[3][3] = {{1.0 - 2.0 * (y * y + z * z), 2.0 * (x * y - w * z), 2.0 * (x * z + w * y)},
-                                 {2.0 * (x * y + w * z), 1.0 - 2.0 * (x * x + z * z), 2.0 * (y * z - w * x)},
-                                 {2.0 * (x * z - w * y), 2.0 * (y * z + w * x), 1.0 - 2.0 * (x * x + y * y)}};
-        double MR[2][3];
-        for (int i = 0; i < 2; ++i)
-            for (int a = 0; a < 3; ++a) MR[i][a] = M[i][0] * Rq[0][a] + M[i][1] * Rq[1][a] + M[i][2] * Rq[2][a];
-        double sxx = kappa, sxy = 0.0, syy = kappa;
-        for (int a = 0; a < 3; ++a) {
-            const double s2 = s[a] * s[a];
-            sxx += MR[0][a] * MR[0][a] * s2;
-            sxy += MR[0][a] * MR[1][a] * s2;
-            syy += MR[1][a] * MR[1][a] * s2;
-        }
-        const double mid = 0.5 * (sxx + syy);
-        const double rad = sqrt(0.25 * (sxx - syy) * (sxx - syy) + sxy * sxy);
-        const double l2 = mid + rad;
-        double v2[2];
-        if (sxx >= syy) {
-            v2[0] = l2 - syy;
-            v2[1] = sxy;
-        } else {
-            v2[0] = sxy;
-            v2[1] = l2 - sxx;
-        }
-        double vn = sqrt(v2[0] * v2[0] + v2[1] * v2[1]);
-        if (vn == 0.0) {
-            v2[0] = 1.0;
-            v2[1] = 0.0;
-            vn = 1.0;
-        }
-        v2[0] /= vn;
-        v2[1] /= vn;
-        const double v1[2] = {-v2[1], v2[0]};
-        double Tm[2][3];
-        for (int a = 0; a < 3; ++a) {
-            const double e1 = v1[0] * MR[0][a] + v1[1] * MR[1][a];
-            const double e2 = v2[0] * MR[0][a] + v2[1] * MR[1][a];
-            Tm[0][a] = 2.0 * s[a] * e1 * e1;
-            Tm[1][a] = 2.0 * s[a] * e2 * e2;
-        }
-        // only the row space of T matters; unit rows keep the reduced system well scaled
-        for (int i = 0; i < 2; ++i) {
-            const double tn = sqrt(Tm[i][0] * Tm[i][0] + Tm[i][1] * Tm[i][1] + Tm[i][2] * Tm[i][2]);
-            if (tn > 0.0)
-                for (int a = 0; a < 3; ++a) Tm[i][a] /= tn;
-        }
-        const double Hs[3][3] = {{B(21), B(22), B(23)}, {B(22), B(24), B(25)}, {B(23), B(25), B(26)}};
-        const double gs[3] = {B(18), B(19), B(20)};
-        double HT[3][2];
-        for (int a = 0; a < 3; ++a)
-            for (int j = 0; j < 2; ++j) HT[a][j] = Hs[a][0] * Tm[j][0] + Hs[a][1] * Tm[j][1] + Hs[a][2] * Tm[j][2];
-        double H2[3], g2[2], av[2];
-        for (int i = 0; i < 2; ++i) g2[i] = Tm[i][0] * gs[0] + Tm[i][1] * gs[1] + Tm[i][2] * gs[2];
-        H2[0] = Tm[0][0] * HT[0][0] + Tm[0][1] * HT[1][0] + Tm[0][2] * HT[2][0];
-        H2[1] = Tm[0][0] * HT[0][1] + Tm[0][1] * HT[1][1] + Tm[0][2] * HT[2][1];
-        H2[2] = Tm[1][0] * HT[0][1] + Tm[1][1] * HT[1][1] + Tm[1][2] * HT[2][1];
-        fl[2 * N + k] = damped_small(2, H2, g2, o, abs_scale, av);
+        double av[2];
+        fl[2 * N + k] = damped_small(2, R.Hs, R.gs, o, abs_scale, av);
         double dsv[3];
-        for (int a = 0; a < 3; ++a) dsv[a] = Tm[0][a] * av[0] + Tm[1][a] * av[1];
+        for (int a = 0; a < 3; ++a) dsv[a] = R.T[0][a] * av[0] + R.T[1][a] * av[1];
         clamp_norm(3, dsv, (double)o.trust_scale * sqrt(s[0] * s[0] + s[1] * s[1] + s[2] * s[2]));
         for (int a = 0; a < 3; ++a) st[(7 + a) * N + k] = (float)dsv[a];
     }
     // ---- opacity with the log barrier
     {
-        const double as = (double)o.barrier_beta * abs_scale;
-        const double gB = as * (1.0 / (1.0 - sig) - 1.0 / sig);
-        const double hB = as * (1.0 / (sig * sig) + 1.0 / ((1.0 - sig) * (1.0 - sig)));
-        const double H1 = B(28) + hB, g1 = B(27) + gB;
         double ds;
-        fl[3 * N + k] = damped_small(1, &H1, &g1, o, abs_scale, &ds);
+        fl[3 * N + k] = damped_small(1, &R.Ho, &R.go, o, abs_scale, &ds);
         st[10 * N + k] = (float)ds;
     }
     // ---- colour, per channel
@@ -390,34 +281,38 @@ __global__ __launch_bounds__(256) void apply_kernel(float* __restrict__ pos, flo
                                                      float* __restrict__ scale, float* __restrict__ opac,
                                                      float* __restrict__ sh, int n, int K,
                                                      const float* __restrict__ st, const int32_t* __restrict__ fl,
-                                                     gsn_solve_opts o, uint32_t mask) {
+                                                     const float* __restrict__ gscale, gsn_solve_opts o,
+                                                     uint32_t mask) {
     const int k = blockIdx.x * blockDim.x + threadIdx.x;
     if (k >= n) return;
     const size_t N = (size_t)n;
     if (fl[k] == -2) return;
+    float a[5] = {1.f, 1.f, 1.f, 1.f, 1.f};
+    if (gscale)
+        for (int i = 0; i < 5; ++i) a[i] = gscale[i * N + k];
     if (mask & 1u)
-        for (int a = 0; a < 3; ++a) pos[a * N + k] += st[a * N + k];
+        for (int c = 0; c < 3; ++c) pos[c * N + k] += a[0] * st[c * N + k];
     if (mask & 2u) {
-        const float th = st[3 * N + k];
+        const float th = a[1] * st[3 * N + k];
         const float sh2 = sinf(0.5f * th);
         const float dq[4] = {cosf(0.5f * th), sh2 * st[4 * N + k], sh2 * st[5 * N + k], sh2 * st[6 * N + k]};
         float q[4], r[4];
-        for (int a = 0; a < 4; ++a) q[a] = rot[a * N + k];
+        for (int c = 0; c < 4; ++c) q[c] = rot[c * N + k];
         qmul<float>(dq, q, r);
         const float il = 1.0f / sqrtf(r[0] * r[0] + r[1] * r[1] + r[2] * r[2] + r[3] * r[3]);
-        for (int a = 0; a < 4; ++a) rot[a * N + k] = r[a] * il;
+        for (int c = 0; c < 4; ++c) rot[c * N + k] = r[c] * il;
     }
     if (mask & 4u)
-        for (int a = 0; a < 3; ++a) {
-            const float s = scale[a * N + k];
-            scale[a * N + k] = fmaxf(s + st[(7 + a) * N + k], o.scale_floor * s);
+        for (int c = 0; c < 3; ++c) {
+            const float s = scale[c * N + k];
+            scale[c * N + k] = fmaxf(s + a[2] * st[(7 + c) * N + k], o.scale_floor * s);
         }
     if (mask & 8u) {
         const float sg = opac[k];
-        opac[k] = fminf(fmaxf(sg + st[10 * N + k], sg - o.opac_ftb * sg), sg + o.opac_ftb * (1.0f - sg));
+        opac[k] = fminf(fmaxf(sg + a[3] * st[10 * N + k], sg - o.opac_ftb * sg), sg + o.opac_ftb * (1.0f - sg));
     }
     if (mask & 16u)
-        for (int i = 0; i < 3 * K; ++i) sh[i * N + k] += st[(GSN_STEP_BASE + i) * N + k];
+        for (int i = 0; i < 3 * K; ++i) sh[i * N + k] += a[4] * st[(GSN_STEP_BASE + i) * N + k];
 }
 
 }  // namespace
@@ -435,10 +330,10 @@ void launch_solve(const gsn_gaussians& g, const DevCam& cam, float kappa, const 
                                                           b.d_data, b.n_views, o, st.d_data, st.d_flags);
 }
 
-void launch_apply(const gsn_gaussians& g, const gsn_steps& st, const gsn_solve_opts& o, uint32_t mask,
-                  hipStream_t s) {
+void launch_apply(const gsn_gaussians& g, const gsn_steps& st, const gsn_solve_opts& o, const float* scale,
+                  uint32_t mask, hipStream_t s) {
     if (g.n == 0) return;
     const int K = (g.sh_degree + 1) * (g.sh_degree + 1);
     apply_kernel<<<(g.n + 255) / 256, 256, 0, s>>>(g.d_pos, g.d_rot, g.d_scale, g.d_opac, g.d_sh, g.n, K,
-                                                   st.d_data, st.d_flags, o, mask);
+                                                   st.d_data, st.d_flags, scale, o, mask);
 }

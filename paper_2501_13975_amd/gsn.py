@@ -42,7 +42,12 @@ def lib():
             "gsn_render": [P, P, P, P, P, P, P],
             "gsn_accumulate_hessian": [P, P, P, P, P, ctypes.c_int32, P, P],
             "gsn_local_newton_solve": [P, P, P, P, P, P],
-            "gsn_apply_step": [P, P, P, P, ctypes.c_uint32],
+            "gsn_apply_step": [P, P, P, P, P, ctypes.c_uint32],
+            "gsn_step_features": [P, P, P, P, P, P, P],
+            "gsn_step_labels": [P, P, P, P, P],
+            "gsn_mlp_reset": [P, P],
+            "gsn_mlp_infer": [P, P, ctypes.c_int32, P, P, P],
+            "gsn_mlp_train_step": [P, P, ctypes.c_int32, P, P, P, P, P, P],
             "gsn_blocks_zero": [P, P],
             "gsn_downsample2x": [P, P, ctypes.c_int32, ctypes.c_int32, P],
             "gsn_camera_knn": [P, ctypes.c_int32, P, ctypes.c_int32, P],
@@ -263,10 +268,36 @@ class Context:
         self._check(lib().gsn_local_newton_solve(self.h, ctypes.byref(cg), ctypes.byref(primary),
                                                  ctypes.byref(cb), ctypes.byref(so), ctypes.byref(cs)))
 
-    def apply_step(self, g, steps: "Steps", so: CSolveOpts, group_mask=31):
+    def apply_step(self, g, steps: "Steps", so: CSolveOpts, group_mask=31, scale=None):
+        """scale: None or a device float tensor [5, n] (per-group multipliers of the steps)."""
         cg, cs = g.c(), steps.c()
         self._check(lib().gsn_apply_step(self.h, ctypes.byref(cg), ctypes.byref(cs), ctypes.byref(so),
-                                         int(group_mask)))
+                                         _ptr(scale), int(group_mask)))
+
+    def step_features(self, g, primary: CCamera, blocks: "Blocks", so: CSolveOpts, feat, ok):
+        """feat: device float [16, n]; ok: device uint8 [n]."""
+        cg, cb = g.c(), blocks.c()
+        self._check(lib().gsn_step_features(self.h, ctypes.byref(cg), ctypes.byref(primary), ctypes.byref(cb),
+                                            ctypes.byref(so), _ptr(feat), _ptr(ok)))
+
+    def step_labels(self, prim: "Steps", aug: "Steps", label, mask):
+        """label, mask: device float [5, n]."""
+        cp, ca = prim.c(), aug.c()
+        self._check(lib().gsn_step_labels(self.h, ctypes.byref(cp), ctypes.byref(ca), _ptr(label), _ptr(mask)))
+
+    def mlp_reset(self, mlp: "MLP"):
+        self._check(lib().gsn_mlp_reset(self.h, ctypes.byref(mlp.cs)))
+
+    def mlp_infer(self, mlp: "MLP", feat, ok, alpha):
+        n = int(ok.numel())
+        self._check(lib().gsn_mlp_infer(self.h, ctypes.byref(mlp.cs), n, _ptr(feat), _ptr(ok), _ptr(alpha)))
+
+    def mlp_train_step(self, mlp: "MLP", feat, label, mask, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8,
+                       loss=None, grad=None):
+        n = int(label.shape[1]) if label.dim() == 2 else 0
+        a = CAdamOpts(lr, beta1, beta2, eps)
+        self._check(lib().gsn_mlp_train_step(self.h, ctypes.byref(mlp.cs), n, _ptr(feat), _ptr(label), _ptr(mask),
+                                             ctypes.byref(a), _ptr(loss), _ptr(grad)))
 
     STAGES = ("project", "sort", "raster_fwd", "loss", "raster_bwd", "chain", "solve", "apply")
     COUNTERS = ("fwd_evals", "bwd_evals", "bwd_active", "pairs", "partials", "fwd_staged")
@@ -291,6 +322,38 @@ class Context:
 
     def downsample2x(self, src, W, H, dst):
         self._check(lib().gsn_downsample2x(self.h, _ptr(src), int(W), int(H), _ptr(dst)))
+
+
+GSN_MLP_PARAMS = 709
+
+
+class CMlp(ctypes.Structure):
+    _fields_ = [("d_params", ctypes.c_void_p), ("d_m", ctypes.c_void_p), ("d_v", ctypes.c_void_p),
+                ("d_half", ctypes.c_void_p), ("step", ctypes.c_int32)]
+
+
+class CAdamOpts(ctypes.Structure):
+    _fields_ = [("lr", ctypes.c_float), ("beta1", ctypes.c_float), ("beta2", ctypes.c_float),
+                ("eps", ctypes.c_float)]
+
+
+class MLP:
+    """Step-scale network state as device tensors (FP32 master weights, Adam moments, FP16 copy)."""
+
+    def __init__(self, params, device):
+        import numpy as np
+        p = np.asarray(params, np.float32).reshape(-1)
+        if p.size != GSN_MLP_PARAMS:
+            raise ValueError(f"expected {GSN_MLP_PARAMS} parameters")
+        self.params = torch.tensor(p, device=device)
+        self.m = torch.zeros(GSN_MLP_PARAMS, dtype=torch.float32, device=device)
+        self.v = torch.zeros(GSN_MLP_PARAMS, dtype=torch.float32, device=device)
+        self.half = torch.zeros(GSN_MLP_PARAMS, dtype=torch.float16, device=device)
+        self.cs = CMlp(_ptr(self.params), _ptr(self.m), _ptr(self.v), _ptr(self.half), 0)
+
+    @property
+    def step(self):
+        return int(self.cs.step)
 
 
 class Blocks:

@@ -5,6 +5,13 @@ its blocks, render and accumulate each of its K nearest cameras at half
 resolution (secondary targets, overshoot control), solve every kernel's local
 Newton systems and apply the steps.  All of it runs in libgsn; this class owns
 the device buffers and issues the calls.
+
+Learned form (``enable_learned``): every ``every``-th sweep runs the full rule
+and also trains the step-scale network on it (labels: how much of the
+primary-only step the full-rule step keeps, per kernel and group); the other
+sweeps render only the primary view and scale its Newton step by the network's
+prediction.  Kernels whose features fall outside the trained range take no step
+on a learned sweep.
 """
 from __future__ import annotations
 
@@ -67,6 +74,63 @@ class LocalNewtonTrainer:
         so = self.solve_opts(t)
         self.ctx.local_newton_solve(self.g, self.ccams[t], self.blocks, so, self.steps)
         self.ctx.apply_step(self.g, self.steps, so, group_mask)
+
+    # ------------------------------------------------------------ learned form
+    def enable_learned(self, params, every=4, lr=1e-3):
+        n = self.g.n
+        self.mlp = gsn.MLP(params, self.dev)
+        self.ctx.mlp_reset(self.mlp)
+        self.every = int(every)
+        self.lr = float(lr)
+        self.feat = torch.zeros(16, max(n, 1), dtype=torch.float32, device=self.dev)
+        self.ok = torch.zeros(max(n, 1), dtype=torch.uint8, device=self.dev)
+        self.alpha = torch.zeros(5, max(n, 1), dtype=torch.float32, device=self.dev)
+        self.label = torch.zeros(5, max(n, 1), dtype=torch.float32, device=self.dev)
+        self.mask = torch.zeros(5, max(n, 1), dtype=torch.float32, device=self.dev)
+        self.steps_prim = gsn.Steps(n, self.g.sh_degree, self.dev)
+        self.mlp_loss = torch.zeros(1, dtype=torch.float64, device=self.dev)
+        # per full-rule sweep: sum |alpha_mlp - alpha_eff| and number of labelled entries
+        self.err_log = []
+
+    def _accumulate_primary(self, t):
+        self.ctx.blocks_zero(self.blocks)
+        fr = self.frames[0]
+        self.ctx.render(self.g, self.ccams[t], self.ro, fr)
+        self.ctx.accumulate_hessian(self.g, fr, self.targets[t], self.lo, 0, self.blocks, self.loss[0])
+
+    def _accumulate_secondaries(self, t):
+        for slot, j in enumerate(self.knn[t], start=1):
+            fr = self.frames[slot]
+            self.ctx.render(self.g, self.chalf[j], self.ro, fr)
+            self.ctx.accumulate_hessian(self.g, fr, self.half_targets[j], self.lo, slot, self.blocks, self.loss[slot])
+
+    def sweep_learned(self, t, i, group_mask=31):
+        """Sweep i of the learned form on training image t."""
+        so = self.solve_opts(t)
+        n = self.g.n
+        self._accumulate_primary(t)
+        prim = self.steps_prim if i % self.every == 0 else self.steps
+        self.ctx.local_newton_solve(self.g, self.ccams[t], self.blocks, so, prim)
+        self.ctx.step_features(self.g, self.ccams[t], self.blocks, so, self.feat[:, :n], self.ok[:n])
+        self.ctx.mlp_infer(self.mlp, self.feat[:, :n], self.ok[:n], self.alpha[:, :n])
+        if i % self.every != 0:
+            self.ctx.apply_step(self.g, self.steps, so, group_mask, scale=self.alpha[:, :n])
+            return
+        # full rule: the secondaries' blocks join the primary's; label and train, then apply the full step
+        self._accumulate_secondaries(t)
+        self.ctx.local_newton_solve(self.g, self.ccams[t], self.blocks, so, self.steps)
+        self.ctx.step_labels(self.steps_prim, self.steps, self.label[:, :n], self.mask[:, :n])
+        m = self.mask[:, :n]
+        self.err_log.append(torch.stack([((self.alpha[:, :n] - self.label[:, :n]).abs() * m).sum(), m.sum()]))
+        self.ctx.mlp_train_step(self.mlp, self.feat[:, :n], self.label[:, :n], m, lr=self.lr, loss=self.mlp_loss)
+        self.ctx.apply_step(self.g, self.steps, so, group_mask)
+
+    def learned_error(self):
+        """Mean |alpha_mlp - alpha_eff| over the labelled entries of the full-rule sweeps so far."""
+        if not self.err_log:
+            return None
+        e = torch.stack(self.err_log).sum(0).cpu().numpy()
+        return float(e[0] / max(e[1], 1.0))
 
     def close(self):
         for f in self.frames:
