@@ -57,19 +57,11 @@ def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
-def gpu_run(args):
-    import numpy as np
+def _targets(cfg, dev):
+    """Ground-truth renders by the library, resident on the device."""
     import torch
 
     from paper_2501_13975_amd import gsn
-    from paper_2501_13975_amd.train import LocalNewtonTrainer
-    from synth.scenes import make_config, view_order
-
-    t0 = time.time()
-    cfg = make_config(args.config)
-    dev = torch.device("cuda", 0)
-    log(f"[bench] generated {args.config}: {cfg.n} kernels, {len(cfg.cams)} cameras ({time.time() - t0:.1f}s)")
-    # targets: the ground truth rendered by the library, resident on the device
     gt = gsn.DeviceGaussians.from_host(cfg.gt, dev)
     ctx = gsn.Context(dev)
     fr = ctx.frame()
@@ -82,29 +74,137 @@ def gpu_run(args):
     torch.cuda.synchronize(dev)
     fr.close()
     ctx.close()
-    del gt
-    log(f"[bench] rendered {len(targets)} targets ({time.time() - t0:.1f}s)")
+    return targets
+
+
+def _trainer(cfg, targets, dev, learned_every=0, step_frac=1.0):
+    from paper_2501_13975_amd import gsn
+    from paper_2501_13975_amd.train import LocalNewtonTrainer
+    from synth.mlp_init import init_params
     g = gsn.DeviceGaussians.from_host(cfg.init, dev)
-    tr = LocalNewtonTrainer(g, cfg.cams, targets, n_secondary=cfg.n_secondary)
-    order = np.concatenate([view_order(len(cfg.cams), e) for e in range(4)])
-    for i in range(args.warmup):
-        tr.sweep(int(order[i]))
+    tr = LocalNewtonTrainer(g, cfg.cams, targets, n_secondary=cfg.n_secondary, solve_kw={"step_frac": step_frac})
+    if learned_every:
+        tr.enable_learned(init_params(0), every=learned_every, lr=1e-2)
+    return tr
+
+
+def _sweep(tr, t, i, learned, mask=31):
+    if learned:
+        tr.sweep_learned(t, i, mask)
+    else:
+        tr.sweep(t, mask)
+
+
+def _timed(tr, order, warmup, steps, learned, dev):
+    import torch
+    for i in range(warmup):
+        _sweep(tr, int(order[i]), i, learned)
     torch.cuda.synchronize(dev)
-    log(f"[bench] warmup {args.warmup} sweeps done ({time.time() - t0:.1f}s)")
     tr.ctx.profile_enable(True)
     torch.cuda.synchronize(dev)
     start = time.perf_counter()
-    for i in range(args.steps):
-        tr.sweep(int(order[args.warmup + i]))
+    for i in range(steps):
+        _sweep(tr, int(order[warmup + i]), warmup + i, learned)
     torch.cuda.synchronize(dev)
     elapsed = time.perf_counter() - start
     stages, counts = tr.ctx.profile_read()
     tr.ctx.profile_enable(False)
-    loss = tr.loss.cpu().numpy()
-    log(f"[bench] timed {args.steps} sweeps in {elapsed:.3f}s; stage ms: "
-        + ", ".join(f"{k}={v[0]:.1f}" for k, v in stages.items()))
+    return elapsed, stages, counts
+
+
+def _psnr(tr, targets, dev):
+    """Mean PSNR over all training views (images clamped to [0, 1]); evaluation only."""
+    import torch
+
+    from paper_2501_13975_amd import gsn
+    fr = tr.frames[0]
+    vals = []
+    for cam, tg in zip(tr.ccams, targets):
+        img = torch.empty_like(tg)
+        tr.ctx.render(tr.g, cam, tr.ro, fr, img)
+        mse = torch.mean((img.clamp(0.0, 1.0) - tg) ** 2)
+        vals.append(10.0 * torch.log10(1.0 / mse))
+    return float(torch.stack(vals).mean().cpu())
+
+
+def _equal_psnr(cfg, targets, dev, epochs, every, mask, step_frac):
+    """Plain form for `epochs` epochs sets the target PSNR; the learned form runs epoch by epoch
+    until it reaches it (at most 3x as many epochs).  Times cover the sweeps only."""
+    import numpy as np
+    import torch
+
+    from synth.scenes import view_order
+    nv = len(cfg.cams)
+    out = {"epochs_plain": epochs, "learned_every": every, "group_mask": mask, "step_frac": step_frac}
+    for form in ("plain", "learned"):
+        tr = _trainer(cfg, targets, dev, every if form == "learned" else 0, step_frac)
+        out.setdefault("initial_psnr", round(_psnr(tr, targets, dev), 4))
+        spent, e, psnr = 0.0, 0, None
+        target = out.get("target_psnr")
+        max_e = epochs if form == "plain" else 3 * epochs
+        i = 0
+        while e < max_e:
+            order = view_order(nv, e)
+            torch.cuda.synchronize(dev)
+            t0 = time.perf_counter()
+            for t in order:
+                _sweep(tr, int(t), i, form == "learned", mask)
+                i += 1
+            torch.cuda.synchronize(dev)
+            spent += time.perf_counter() - t0
+            e += 1
+            psnr = _psnr(tr, targets, dev)
+            log(f"[bench] {form} epoch {e}: PSNR {psnr:.3f} dB, {spent:.2f}s of sweeps")
+            if form == "learned" and psnr >= target:
+                break
+        if form == "plain":
+            out["target_psnr"] = round(psnr, 4)
+            out["plain_seconds"] = round(spent, 3)
+            out["plain_sweeps"] = i
+        else:
+            out["learned_psnr"] = round(psnr, 4)
+            out["learned_seconds"] = round(spent, 3)
+            out["learned_sweeps"] = i
+            out["learned_reached_target"] = bool(psnr >= target)
+            out["mean_abs_alpha_error"] = tr.learned_error()
+            out["speedup_at_equal_psnr"] = (round(out["plain_seconds"] / spent, 3)
+                                            if psnr >= target else None)
+        tr.close()
+    return out
+
+
+def gpu_run(args):
+    import numpy as np
+    import torch
+
+    from synth.scenes import make_config, view_order
+
+    t0 = time.time()
+    cfg = make_config(args.config)
+    dev = torch.device("cuda", 0)
+    log(f"[bench] generated {args.config}: {cfg.n} kernels, {len(cfg.cams)} cameras ({time.time() - t0:.1f}s)")
+    targets = _targets(cfg, dev)
+    log(f"[bench] rendered {len(targets)} targets ({time.time() - t0:.1f}s)")
+    order = np.concatenate([view_order(len(cfg.cams), e) for e in range(4)])
+    tr = _trainer(cfg, targets, dev, 0, args.step_frac)
+    elapsed, stages, counts = _timed(tr, order, args.warmup, args.steps, False, dev)
     tr.close()
-    return elapsed, stages, counts, loss, cfg
+    log(f"[bench] plain: {args.steps} sweeps in {elapsed:.3f}s; stage ms: "
+        + ", ".join(f"{k}={v[0]:.1f}" for k, v in stages.items()))
+    learned = None
+    if args.learned_every:
+        tr = _trainer(cfg, targets, dev, args.learned_every, args.step_frac)
+        el2, st2, _ = _timed(tr, order, args.warmup, args.steps, True, dev)
+        tr.close()
+        learned = {"value": round(args.steps / el2, 4), "unit": "sweeps/s", "ms_per_step": round(el2 * 1e3 / args.steps, 3),
+                   "every": args.learned_every,
+                   "stage_ms_per_step": {k: round(v[0] / args.steps, 3) for k, v in st2.items()}}
+        log(f"[bench] learned: {args.steps} sweeps in {el2:.3f}s")
+    quality = None
+    if args.quality_epochs > 0 and args.learned_every:
+        quality = _equal_psnr(cfg, targets, dev, args.quality_epochs, args.learned_every, args.quality_mask,
+                              args.quality_step_frac)
+    return elapsed, stages, counts, cfg, learned, quality
 
 
 def roofline(stages, counts, steps, pixels_per_step):
@@ -188,12 +288,24 @@ def main():
     ap.add_argument("--config", default="c2")
     ap.add_argument("--cpu-budget", type=float, default=20.0, help="seconds of oracle work for the CPU baseline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--learned-every", type=int, default=4,
+                    help="learned form: one full-rule (training) sweep every N sweeps; 0 skips the learned form")
+    ap.add_argument("--quality-epochs", type=int, default=2,
+                    help="epochs of the plain form that set the PSNR both forms are timed to; 0 skips")
+    ap.add_argument("--step-frac", type=float, default=0.01,
+                    help="fraction of every Newton step applied in the timed sweeps: the full step is computed, "
+                         "and a small fraction keeps the scene near its initial state so that every timed sweep "
+                         "sees the same workload")
+    ap.add_argument("--quality-mask", type=int, default=12,
+                    help="attribute groups trained in the equal-PSNR leg (bits: 1 position, 2 rotation, 4 scaling, "
+                         "8 opacity, 16 colour)")
+    ap.add_argument("--quality-step-frac", type=float, default=0.3)
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU: this build runs the training step on a single MI355X "
               "(how it would shard across GPUs is described in DESIGN.md); run with --gpus 1", file=sys.stderr)
         sys.exit(2)
-    elapsed, stages, counts, loss, cfg = gpu_run(args)
+    elapsed, stages, counts, cfg, learned, quality = gpu_run(args)
     ms_per_step = elapsed * 1e3 / args.steps
     value = args.steps / elapsed
     pixels = cfg.width * cfg.height + cfg.n_secondary * (cfg.width // 2) * (cfg.height // 2)
@@ -210,12 +322,14 @@ def main():
                                 f"primary {cfg.width}x{cfg.height} + {cfg.n_secondary} KNN secondaries at "
                                 f"{cfg.width // 2}x{cfg.height // 2}; plain FP32 form"),
                    "gaussians": cfg.n, "width": cfg.width, "height": cfg.height, "cameras": len(cfg.cams),
-                   "secondaries": cfg.n_secondary, "form": "plain"},
+                   "secondaries": cfg.n_secondary, "form": "plain", "step_frac": args.step_frac},
         "gaussians_updated_per_s": round(value * cfg.n, 1),
         "stage_ms_per_step": {k: round(v[0] / args.steps, 3) for k, v in stages.items()},
         "counts_per_step": {k: int(v / args.steps) for k, v in counts.items()},
         "roofline": rl,
         "cpu_baseline": cpu,
+        "learned": learned,
+        "equal_psnr": quality,
     }
     print(json.dumps(out), flush=True)
 

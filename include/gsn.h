@@ -91,7 +91,10 @@ typedef struct {
  * pivot_min (|H|_F / sqrt(n) + mu_j) and min/max pivot >= pivot_min;
  * otherwise the scaled gradient step.  Steps are
  * then clamped to trust radii: |Delta p| <= trust_pos * max(s),
- * |theta| <= trust_rot, |Delta s| <= trust_scale * |s|.  The small systems are
+ * |theta| <= trust_rot, |Delta s| <= trust_scale * |s|, per colour channel
+ * |Delta c| <= trust_sh (Euclidean norm of the SH coefficient step), and the
+ * applied opacity is kept in [opac_eps, 1 - opac_eps].  Before the trust radii
+ * every step is multiplied by step_frac (1 is the paper's unit Newton step).  The small systems are
  * solved in double precision.
  * Opacity barrier weight alpha_sigma = barrier_beta / (3 |I|), |I| =
  * npix_primary.  sh_floor: per-view colour curvature floor relative to the
@@ -105,7 +108,8 @@ typedef struct {
     float barrier_beta, sh_floor, scale_floor, opac_ftb;
     int32_t npix_primary;
     float kappa;
-    float trust_pos, trust_rot, trust_scale;
+    float trust_pos, trust_rot, trust_scale, trust_sh, opac_eps, step_frac;
+    float damp_sh;  /* colour damping relative to the mean diagonal of the colour Gram matrix */
 } gsn_solve_opts;
 
 /* Per-kernel gradient/Hessian blocks, summed over the views added so far.

@@ -60,6 +60,10 @@ enum Opt {
     O_TRUST_POS,     // |Delta p| <= trust_pos * max_a s_a
     O_TRUST_ROT,     // |theta| <= trust_rot (radians)
     O_TRUST_SCALE,   // |Delta s| <= trust_scale * |s|
+    O_TRUST_SH,      // per channel |Delta c| <= trust_sh (SH coefficient vector)
+    O_OPAC_EPS,      // applied opacity kept in [opac_eps, 1 - opac_eps]
+    O_STEP_FRAC,     // every group's Newton step is multiplied by step_frac before the trust radii
+    O_DAMP_SH,       // colour damping mu = damp_sh * mean diag(G) + damp_abs / (3 |I|)
     O_COUNT
 };
 
@@ -1075,6 +1079,7 @@ int orc_solve(int n, int K, const double* pos, const double* rot, const double* 
         {
             double H2[4] = {R.Hp[0], R.Hp[1], R.Hp[2], R.Hp[3]}, dv[2];
             dk[0] = damped_solve(2, H2, R.gp, o, dv, &cnd[0]);
+            for (int a = 0; a < 2; ++a) dv[a] *= o[O_STEP_FRAC];
             clamp_norm(2, dv, o[O_TRUST_POS] * std::max(s[0], std::max(s[1], s[2])));
             for (int a = 0; a < 3; ++a) st[ST_DPOS + a] = R.ux[a] * dv[0] + R.uy[a] * dv[1];
         }
@@ -1082,6 +1087,7 @@ int orc_solve(int n, int K, const double* pos, const double* rot, const double* 
         {
             double th;
             dk[1] = damped_solve(1, &R.Ht, &R.gt, o, &th, &cnd[1]);
+            th *= o[O_STEP_FRAC];
             clamp_norm(1, &th, o[O_TRUST_ROT]);
             st[ST_DTH] = th;
         }
@@ -1089,6 +1095,7 @@ int orc_solve(int n, int K, const double* pos, const double* rot, const double* 
         {
             double av[2];
             dk[2] = damped_solve(2, R.Hs, R.gs, o, av, &cnd[2]);
+            for (int a = 0; a < 2; ++a) av[a] *= o[O_STEP_FRAC];
             // the rows of T are unit but not orthogonal, so the clamp acts on Delta s itself
             double dsv[3];
             for (int a = 0; a < 3; ++a) dsv[a] = R.T2[0][a] * av[0] + R.T2[1][a] * av[1];
@@ -1099,7 +1106,7 @@ int orc_solve(int n, int K, const double* pos, const double* rot, const double* 
         {
             double ds;
             dk[3] = damped_solve(1, &R.Ho, &R.go, o, &ds, &cnd[3]);
-            st[ST_DO] = ds;
+            st[ST_DO] = o[O_STEP_FRAC] * ds;
         }
         // Colour: per channel, G = sum_v s~_v b_v b_v^T, g = sum_v gamma_v b_v, b_v = Y(r_v).
         {
@@ -1128,12 +1135,15 @@ int orc_solve(int n, int K, const double* pos, const double* rot, const double* 
                 double md = 0.0;
                 for (int i = 0; i < K; ++i) md += G[i * K + i];
                 md /= K;
-                const double mu = o[O_DAMP_REL] * md + o[O_DAMP_ABS] * abs_scale;
+                const double mu = o[O_DAMP_SH] * md + o[O_DAMP_ABS] * abs_scale;
                 for (int i = 0; i < K; ++i) G[i * K + i] += mu;
                 double x[16], b[16];
                 for (int i = 0; i < K; ++i) b[i] = -gg[i];
-                if (cholesky_solve(K, G, b, 0.0, x))
+                if (cholesky_solve(K, G, b, 0.0, x)) {
+                    for (int i = 0; i < K; ++i) x[i] *= o[O_STEP_FRAC];
+                    clamp_norm(K, x, o[O_TRUST_SH]);
                     for (int i = 0; i < K; ++i) st[ST_DSH + ch * K + i] = x[i];
+                }
             }
         }
         if (cond)
@@ -1241,7 +1251,8 @@ int orc_apply(int n, int K, double* pos, double* rot, double* scale, double* opa
             }
         if (group_mask & 8) {
             const double sg = opac[k], f = o[O_OPAC_FTB];
-            opac[k] = std::min(std::max(sg + st[ST_DO], sg - f * sg), sg + f * (1.0 - sg));
+            const double moved = std::min(std::max(sg + st[ST_DO], sg - f * sg), sg + f * (1.0 - sg));
+            opac[k] = std::min(std::max(moved, o[O_OPAC_EPS]), 1.0 - o[O_OPAC_EPS]);
         }
         if (group_mask & 16)
             for (int i = 0; i < 3 * K; ++i) sh[(size_t)i * n + k] += st[ST_DSH + i];

@@ -179,7 +179,7 @@ __device__ __forceinline__ void colour_solve(int K, int V, RowFn B, const gsn_so
             }
         }
         md /= (double)K;
-        const double mu = (double)o.damp_rel * md + (double)o.damp_abs * abs_scale;
+        const double mu = (double)o.damp_sh * md + (double)o.damp_abs * abs_scale;
         double A[VM][VM], rhs[VM], y[VM];
 #pragma unroll
         for (int i = 0; i < VM; ++i) {
@@ -208,10 +208,20 @@ __device__ __forceinline__ void colour_solve(int K, int V, RowFn B, const gsn_so
             });
     }
 #pragma unroll
-    for (int ch = 0; ch < 3; ++ch)
+    for (int ch = 0; ch < 3; ++ch) {
+        // trust radius on each channel's coefficient step
+        double nn = 0.0;
+#pragma unroll
+        for (int a = 0; a < 16; ++a) {
+            dsh[ch][a] *= (double)o.step_frac;
+            nn += dsh[ch][a] * dsh[ch][a];
+        }
+        nn = sqrt(nn);
+        const double f = nn > (double)o.trust_sh && nn > 0.0 ? (double)o.trust_sh / nn : 1.0;
 #pragma unroll
         for (int a = 0; a < 16; ++a)
-            if (a < K) st[(GSN_STEP_BASE + ch * K + a) * N + k] = (float)dsh[ch][a];
+            if (a < K) st[(GSN_STEP_BASE + ch * K + a) * N + k] = (float)(dsh[ch][a] * f);
+    }
 }
 
 template <class T>
@@ -248,6 +258,7 @@ __global__ __launch_bounds__(128) void solve_kernel(const float* __restrict__ po
     {
         double dv[2];
         fl[0 * N + k] = damped_small(2, R.Hp, R.gp, o, abs_scale, dv);
+        for (int a = 0; a < 2; ++a) dv[a] *= (double)o.step_frac;
         clamp_norm(2, dv, (double)o.trust_pos * fmax(s[0], fmax(s[1], s[2])));
         for (int a = 0; a < 3; ++a) st[(size_t)a * N + k] = (float)(R.ux[a] * dv[0] + R.uy[a] * dv[1]);
     }
@@ -255,6 +266,7 @@ __global__ __launch_bounds__(128) void solve_kernel(const float* __restrict__ po
     {
         double th;
         fl[1 * N + k] = damped_small(1, &R.Ht, &R.gt, o, abs_scale, &th);
+        th *= (double)o.step_frac;
         clamp_norm(1, &th, (double)o.trust_rot);
         st[3 * N + k] = (float)th;
     }
@@ -262,6 +274,7 @@ __global__ __launch_bounds__(128) void solve_kernel(const float* __restrict__ po
     {
         double av[2];
         fl[2 * N + k] = damped_small(2, R.Hs, R.gs, o, abs_scale, av);
+        for (int a = 0; a < 2; ++a) av[a] *= (double)o.step_frac;
         double dsv[3];
         for (int a = 0; a < 3; ++a) dsv[a] = R.T[0][a] * av[0] + R.T[1][a] * av[1];
         clamp_norm(3, dsv, (double)o.trust_scale * sqrt(s[0] * s[0] + s[1] * s[1] + s[2] * s[2]));
@@ -271,7 +284,7 @@ __global__ __launch_bounds__(128) void solve_kernel(const float* __restrict__ po
     {
         double ds;
         fl[3 * N + k] = damped_small(1, &R.Ho, &R.go, o, abs_scale, &ds);
-        st[10 * N + k] = (float)ds;
+        st[10 * N + k] = (float)((double)o.step_frac * ds);
     }
     // ---- colour, per channel
     colour_solve<VM>(K, V, B, o, abs_scale, st, N, k, fl);
@@ -309,7 +322,8 @@ __global__ __launch_bounds__(256) void apply_kernel(float* __restrict__ pos, flo
         }
     if (mask & 8u) {
         const float sg = opac[k];
-        opac[k] = fminf(fmaxf(sg + a[3] * st[10 * N + k], sg - o.opac_ftb * sg), sg + o.opac_ftb * (1.0f - sg));
+        const float moved = fminf(fmaxf(sg + a[3] * st[10 * N + k], sg - o.opac_ftb * sg), sg + o.opac_ftb * (1.0f - sg));
+        opac[k] = fminf(fmaxf(moved, o.opac_eps), 1.0f - o.opac_eps);
     }
     if (mask & 16u)
         for (int i = 0; i < 3 * K; ++i) sh[i * N + k] += a[4] * st[(GSN_STEP_BASE + i) * N + k];

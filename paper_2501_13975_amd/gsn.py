@@ -100,7 +100,8 @@ class CSolveOpts(ctypes.Structure):
                 ("max_escalations", ctypes.c_int32), ("barrier_beta", ctypes.c_float),
                 ("sh_floor", ctypes.c_float), ("scale_floor", ctypes.c_float), ("opac_ftb", ctypes.c_float),
                 ("npix_primary", ctypes.c_int32), ("kappa", ctypes.c_float), ("trust_pos", ctypes.c_float),
-                ("trust_rot", ctypes.c_float), ("trust_scale", ctypes.c_float)]
+                ("trust_rot", ctypes.c_float), ("trust_scale", ctypes.c_float), ("trust_sh", ctypes.c_float),
+                ("opac_eps", ctypes.c_float), ("step_frac", ctypes.c_float), ("damp_sh", ctypes.c_float)]
 
 
 class CBlocks(ctypes.Structure):
@@ -123,9 +124,10 @@ def loss_opts(lambda_ssim=0.2, weight=1.0, keep_zstats=False):
 
 def solve_opts(npix_primary, kappa=0.3, damp_rel=1e-3, damp_abs=1e-12, pivot_min=1e-3, max_escalations=7,
                barrier_beta=1e-2, sh_floor=1e-3, scale_floor=0.1, opac_ftb=0.995, trust_pos=2.0, trust_rot=0.5,
-               trust_scale=0.5):
+               trust_scale=0.5, trust_sh=1.0, opac_eps=1e-6, step_frac=1.0, damp_sh=1e-3):
     return CSolveOpts(damp_rel, damp_abs, pivot_min, max_escalations, barrier_beta, sh_floor, scale_floor,
-                      opac_ftb, int(npix_primary), kappa, trust_pos, trust_rot, trust_scale)
+                      opac_ftb, int(npix_primary), kappa, trust_pos, trust_rot, trust_scale, trust_sh, opac_eps,
+                      step_frac, damp_sh)
 
 
 def camera(c) -> CCamera:

@@ -126,7 +126,8 @@ def test_sweep_steps_parity(gsn, ctx, lam):
     knn_g = gsn.camera_knn(np.stack([c.center for c in cfg.cams]),
                            np.asarray(g.pos, np.float64).mean(1), 3)
     assert np.array_equal(knn_o, knn_g)
-    o = O.opts(lambda_ssim=lam)
+    # end to end with the colour trust radius open (the radius itself is checked on the solve stage below)
+    o = O.opts(lambda_ssim=lam, trust_sh=1e30)
     res = O.sweep(g, cfg.cams, tg, t, knn_o, o)
     # kernels that any view composites at a pixel with a near-threshold decision are not compared
     bad = np.zeros(g.n, bool)
@@ -134,7 +135,8 @@ def test_sweep_steps_parity(gsn, ctx, lam):
         bad |= near_threshold_kernels(fr, g.n)
     from paper_2501_13975_amd.train import LocalNewtonTrainer
     dg = gsn.DeviceGaussians.from_host(g)
-    tr = LocalNewtonTrainer(dg, cfg.cams, [torch.tensor(x, device=ctx.device) for x in tg], 3, lam)
+    tr = LocalNewtonTrainer(dg, cfg.cams, [torch.tensor(x, device=ctx.device) for x in tg], 3, lam,
+                            solve_kw={"trust_sh": 1e30})
     tr.accumulate(t)
     so = tr.solve_opts(t)
     tr.ctx.local_newton_solve(tr.g, tr.ccams[t], tr.blocks, so, tr.steps)
@@ -169,6 +171,18 @@ def test_sweep_steps_parity(gsn, ctx, lam):
     errs["solver_decisions"] = float(same[vis].mean())
     for name, sl in groups:
         errs["solver_" + name] = rel_inf(st_s[sl].T[same], want_s[same, sl])
+    # the same with a step fraction and with the default colour trust radius
+    for tag, field, val in (("frac", "step_frac", 0.3), ("trust", "trust_sh", 1.0)):
+        so_f = tr.solve_opts(t)
+        setattr(so_f, field, val)
+        tr.ctx.local_newton_solve(tr.g, tr.ccams[t], tr.blocks, so_f, tr.steps)
+        st_f, fl_f = (x.cpu().numpy() for x in tr.steps.view())
+        o_f = o_same.copy()
+        o_f[O.O_NAMES.index(field)] = val
+        want_f, dec_f = O.solve(g, cfg.cams[t], o_f, S32, 4)
+        same_f = np.all(fl_f[:4].T == dec_f[:, :4], axis=1) & vis
+        for name, sl in groups:
+            errs[f"solver_{tag}_" + name] = rel_inf(st_f[sl].T[same_f], want_f[same_f, sl])
     dump = os.environ.get("GSN_DUMP_DIR")
     if dump:
         os.makedirs(dump, exist_ok=True)
@@ -179,6 +193,8 @@ def test_sweep_steps_parity(gsn, ctx, lam):
     assert errs["decision_agreement"] > 0.99 and errs["solver_decisions"] > 0.999
     for name, _ in groups:
         assert errs["solver_" + name] < 1e-5, ("solver", name, errs["solver_" + name])
+        assert errs["solver_frac_" + name] < 1e-5, ("solver, step fraction", name, errs["solver_frac_" + name])
+        assert errs["solver_trust_" + name] < 1e-5, ("solver, colour radius", name, errs["solver_trust_" + name])
         assert errs[name] < TOL_STEP, (name, errs[name])
         assert errs["determined_" + name] > 0.5 * errs["visible"], ("too few determined steps", name)
     # (3) apply: the oracle's steps (float32, as the library stores them) applied by both sides

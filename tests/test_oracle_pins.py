@@ -547,7 +547,7 @@ def _axis_cam(W=48, H=48):
 def test_one_newton_step_is_exact_for_opacity_and_colour():
     """L2 is quadratic in sigma and in the SH coefficients, so one undamped Newton step lands on the target."""
     cam = _axis_cam()
-    o = smooth_opts(0.0, damp_rel=0.0, barrier_beta=0.0, npix_primary=48 * 48)
+    o = smooth_opts(0.0, damp_rel=0.0, damp_sh=0.0, barrier_beta=0.0, npix_primary=48 * 48)
     tgt = O.render(_single_splat(0.7, (0.5, 0.4, 0.1)), cam, o).img
     g = _single_splat(0.7, (0.3, 0.6, 0.2))
     res = O.sweep(g, [cam], [tgt], 0, None, o, mask=16)
@@ -561,7 +561,7 @@ def test_position_newton_converges_quadratically():
     """Sec. 3/4: near second-order convergence of the position solve on a displaced splat."""
     cam = _axis_cam(64, 64)
     cam.cx = cam.cy = 31.5
-    o = smooth_opts(0.0, damp_rel=0.0, barrier_beta=0.0, npix_primary=64 * 64)
+    o = smooth_opts(0.0, damp_rel=0.0, damp_sh=0.0, barrier_beta=0.0, npix_primary=64 * 64)
     tgt = O.render(_single_splat(0.7, pos=(0.0, 0.0, 0.0)), cam, o).img
     g = _single_splat(0.7, pos=(0.12, -0.08, 0.0))
     errs = []
@@ -611,7 +611,8 @@ def test_colour_step_lies_in_span_of_view_bases_and_matches_pinv():
     g, cams, tgts, _ = _solve_case()
     # small damping: the damped step approaches the min-norm step as mu -> 0; an n-space
     # Cholesky of a rank-V Gram loses about log10(kappa) digits, hence the 1e-8 and the 1e-4 below
-    o = O.opts(npix_primary=32 * 28, damp_rel=1e-8)
+    # (trust radius off: this pin is about the unclamped solve)
+    o = O.opts(npix_primary=32 * 28, damp_rel=1e-8, damp_sh=1e-8, trust_sh=1e30)
     res = O.sweep(g, cams, tgts, 0, np.array([[1], [0]]), o)
     S, st = res["summed"], res["steps"]
     for k in range(g.n):
@@ -630,6 +631,42 @@ def test_colour_step_lies_in_span_of_view_bases_and_matches_pinv():
                                atol=1e-4 * np.max(np.abs(d)))
             resid = d - Bm.T @ np.linalg.lstsq(Bm.T, d, rcond=None)[0]
             assert np.linalg.norm(resid) < 1e-6 * np.linalg.norm(d)
+
+
+def test_colour_trust_radius_scales_the_step_along_itself():
+    """Per channel, a step longer than trust_sh is shortened to that length, direction unchanged."""
+    g, cams, tgts, _ = _solve_case()
+    o_free = O.opts(npix_primary=32 * 28, trust_sh=1e30)
+    o_cl = O.opts(npix_primary=32 * 28, trust_sh=0.05)
+    res = O.sweep(g, cams, tgts, 0, np.array([[1], [0]]), o_free)
+    st_free = res["steps"]
+    st_cl, _ = O.solve(g, cams[0], O.opts(npix_primary=32 * 28, trust_sh=0.05), res["summed"], 2)
+    checked = 0
+    for k in range(g.n):
+        for ch in range(3):
+            d = st_free[k, 11 + ch * 16:11 + (ch + 1) * 16]
+            c = st_cl[k, 11 + ch * 16:11 + (ch + 1) * 16]
+            nd = np.linalg.norm(d)
+            if nd > 0.05:
+                assert np.isclose(np.linalg.norm(c), 0.05, rtol=1e-12)
+                assert np.allclose(c, d * (0.05 / nd), rtol=1e-12, atol=1e-15)
+                checked += 1
+            else:
+                assert np.array_equal(c, d)
+    assert checked > 0
+
+
+def test_step_fraction_scales_every_group_before_the_trust_radii():
+    g, cams, tgts, _ = _solve_case()
+    o1 = O.opts(npix_primary=32 * 28, trust_pos=1e30, trust_rot=1e30, trust_scale=1e30, trust_sh=1e30)
+    oh = O.opts(npix_primary=32 * 28, trust_pos=1e30, trust_rot=1e30, trust_scale=1e30, trust_sh=1e30,
+                step_frac=0.3)
+    res = O.sweep(g, cams, tgts, 0, np.array([[1], [0]]), o1)
+    sh, dh = O.solve(g, cams[0], oh, res["summed"], 2)
+    assert np.array_equal(dh, res["dec"])
+    cols = np.r_[0:4, 7:11 + 48]
+    assert np.allclose(sh[:, cols], 0.3 * res["steps"][:, cols], rtol=1e-12, atol=1e-300)
+    assert np.array_equal(sh[:, 4:7], res["steps"][:, 4:7])  # the rotation axis is not a step
 
 
 def test_scale_row_space_matches_eigenvalue_derivative():
