@@ -216,6 +216,40 @@ gsn_status gsn_local_newton_solve(gsn_ctx* ctx, const gsn_gaussians* g, const gs
 gsn_status gsn_apply_step(gsn_ctx* ctx, gsn_gaussians* g, const gsn_steps* steps,
                           const gsn_solve_opts* opts, const float* d_scale, uint32_t group_mask);
 
+/* ------------------------------------------------- batched solve
+ * The local Newton solves of several scenes (Sec. 4.2, eq. local_newton) in
+ * one persistent launch: a grid sized to the device walks the concatenated
+ * kernel index space of all scenes, every kernel solving all of its groups
+ * (sizes 1, 2 reduced, 3 and the per-channel colour systems) exactly as
+ * gsn_local_newton_solve does, so the results are identical to per-scene
+ * calls.  Each item's pointers are borrowed for the call (the graph form
+ * below keeps them). */
+typedef struct {
+    const gsn_gaussians* g;
+    const gsn_camera* primary;
+    const gsn_blocks* blocks;
+    const gsn_solve_opts* opts;
+    gsn_steps* steps;
+} gsn_solve_item;
+/* Errors: GSN_E_INVALID (count < 1 or > 64, null pointers), GSN_E_SHAPE and
+ * GSN_E_CAPACITY as for gsn_local_newton_solve, per item. */
+gsn_status gsn_solve_batched(gsn_ctx* ctx, const gsn_solve_item* items, int32_t count);
+/* Launch-shape autotuner of the batched solve: times block sizes {64, 128,
+ * 256} and persistent grids of {1, 2, 4, 8} workgroups per compute unit on the
+ * given items (the solves run, and rerun, on the real buffers), keeps the
+ * fastest for later gsn_solve_batched and graph calls on this context and
+ * returns it (h_block, h_grid may be NULL).  Synchronises the stream. */
+gsn_status gsn_solve_tune(gsn_ctx* ctx, const gsn_solve_item* items, int32_t count, int32_t* h_block,
+                          int32_t* h_grid);
+/* A HIP graph holding one batched solve of the given items: the scene table is
+ * copied to device memory owned by the graph and the launch is captured on a
+ * stream of the library's own; gsn_graph_launch replays it on the context's
+ * stream (the items' buffers must stay valid and keep their sizes). */
+typedef struct gsn_graph gsn_graph;
+gsn_status gsn_solve_graph_create(gsn_ctx* ctx, const gsn_solve_item* items, int32_t count, gsn_graph** out);
+gsn_status gsn_graph_launch(gsn_ctx* ctx, gsn_graph* graph);
+gsn_status gsn_graph_destroy(gsn_ctx* ctx, gsn_graph* graph);
+
 /* ------------------------------------------------- learned step scale
  * The overshoot control of Sec. 4.3 (eq. tildel) adds the blocks of the
  * |N_t| nearest training views to the primary's.  The learned form predicts,

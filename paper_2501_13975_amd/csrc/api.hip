@@ -148,6 +148,7 @@ gsn_status gsn_destroy(gsn_ctx* ctx) {
     if (ctx->d_counts) (void)hipFree(ctx->d_counts);
     buf_free(ctx->mlp_part);
     buf_free(ctx->mlp_stat);
+    buf_free(ctx->solve_table);
     delete ctx;
     return GSN_OK;
 }
@@ -407,6 +408,204 @@ gsn_status gsn_local_newton_solve(gsn_ctx* ctx, const gsn_gaussians* g, const gs
     StageTimer st_(ctx, GSN_STAGE_SOLVE);
     launch_solve(*g, make_devcam(*primary), o->kappa, *b, *o, *st, ctx->stream);
     HIP_TRY(ctx, hipGetLastError());
+    return GSN_OK;
+}
+
+// Validates the items of a batched solve and builds the host scene table.
+static gsn_status build_solve_table(gsn_ctx* ctx, const gsn_solve_item* items, int32_t count,
+                                    std::vector<SolveScene>& table, long long& total, int& max_views) {
+    if (!items || count < 1 || count > GSN_SOLVE_MAX_SCENES)
+        return fail(ctx, GSN_E_INVALID, "count %d not in 1..%d", count, GSN_SOLVE_MAX_SCENES);
+    table.clear();
+    total = 0;
+    max_views = 1;
+    for (int i = 0; i < count; ++i) {
+        const gsn_solve_item& it = items[i];
+        if (!it.g || !it.primary || !it.blocks || !it.opts || !it.steps)
+            return fail(ctx, GSN_E_INVALID, "item %d: null pointer", i);
+        gsn_status r = check_gaussians(ctx, it.g);
+        if (r != GSN_OK) return r;
+        if ((r = check_camera(ctx, it.primary)) != GSN_OK) return r;
+        const gsn_blocks& b = *it.blocks;
+        const gsn_steps& st = *it.steps;
+        const gsn_solve_opts& o = *it.opts;
+        if (b.n != it.g->n || st.n != it.g->n) return fail(ctx, GSN_E_SHAPE, "item %d: n mismatch", i);
+        if (st.sh_degree != it.g->sh_degree) return fail(ctx, GSN_E_SHAPE, "item %d: steps sh_degree differs", i);
+        if (b.n_views < 1 || b.n_views > 9) return fail(ctx, GSN_E_CAPACITY, "item %d: n_views not in 1..9", i);
+        if (it.g->n > 0 && (!b.d_data || !st.d_data || !st.d_flags))
+            return fail(ctx, GSN_E_INVALID, "item %d: null device array", i);
+        if (o.npix_primary <= 0 || o.max_escalations < 0 || o.max_escalations > 30)
+            return fail(ctx, GSN_E_INVALID, "item %d: solve option out of range", i);
+        SolveScene sc;
+        sc.pos = it.g->d_pos;
+        sc.rot = it.g->d_rot;
+        sc.scale = it.g->d_scale;
+        sc.opac = it.g->d_opac;
+        sc.n = it.g->n;
+        sc.K = (it.g->sh_degree + 1) * (it.g->sh_degree + 1);
+        sc.V = b.n_views;
+        sc.cam = make_devcam(*it.primary);
+        sc.kappa = o.kappa;
+        sc.blk = b.d_data;
+        sc.o = o;
+        sc.st = st.d_data;
+        sc.fl = st.d_flags;
+        sc.first = total;
+        total += it.g->n;
+        max_views = std::max(max_views, b.n_views);
+        table.push_back(sc);
+    }
+    return GSN_OK;
+}
+
+static void default_solve_shape(gsn_ctx* ctx, int& block, int& grid) {
+    if (ctx->solve_block > 0) {
+        block = ctx->solve_block;
+        grid = ctx->solve_grid;
+        return;
+    }
+    int cus = 256;
+    (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, ctx->device);
+    block = 128;
+    grid = 4 * cus;
+}
+
+gsn_status gsn_solve_batched(gsn_ctx* ctx, const gsn_solve_item* items, int32_t count) {
+    if (!ctx) return GSN_E_INVALID;
+    std::vector<SolveScene> table;
+    long long total = 0;
+    int max_views = 1;
+    gsn_status r = build_solve_table(ctx, items, count, table, total, max_views);
+    if (r != GSN_OK) return r;
+    HIP_TRY(ctx, hipSetDevice(ctx->device));
+    // the stream may still read an earlier table: wait before overwriting it
+    HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+    HIP_TRY(ctx, buf_reserve(ctx->solve_table, table.size() * sizeof(SolveScene)));
+    HIP_TRY(ctx, hipMemcpy(ctx->solve_table.p, table.data(), table.size() * sizeof(SolveScene),
+                           hipMemcpyHostToDevice));
+    int block, grid;
+    default_solve_shape(ctx, block, grid);
+    StageTimer st_(ctx, GSN_STAGE_SOLVE);
+    launch_solve_batched(bp<SolveScene>(ctx->solve_table), count, total, max_views, block, grid, ctx->stream);
+    HIP_TRY(ctx, hipGetLastError());
+    return GSN_OK;
+}
+
+gsn_status gsn_solve_tune(gsn_ctx* ctx, const gsn_solve_item* items, int32_t count, int32_t* h_block,
+                          int32_t* h_grid) {
+    if (!ctx) return GSN_E_INVALID;
+    std::vector<SolveScene> table;
+    long long total = 0;
+    int max_views = 1;
+    gsn_status r = build_solve_table(ctx, items, count, table, total, max_views);
+    if (r != GSN_OK) return r;
+    HIP_TRY(ctx, hipSetDevice(ctx->device));
+    HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+    HIP_TRY(ctx, buf_reserve(ctx->solve_table, table.size() * sizeof(SolveScene)));
+    HIP_TRY(ctx, hipMemcpy(ctx->solve_table.p, table.data(), table.size() * sizeof(SolveScene),
+                           hipMemcpyHostToDevice));
+    int cus = 256;
+    (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, ctx->device);
+    hipEvent_t e0, e1;
+    HIP_TRY(ctx, hipEventCreate(&e0));
+    HIP_TRY(ctx, hipEventCreate(&e1));
+    float best = 1e30f;
+    int best_block = 128, best_grid = 4 * cus;
+    const int blocks[3] = {64, 128, 256}, per_cu[4] = {1, 2, 4, 8};
+    for (int bi = 0; bi < 3; ++bi)
+        for (int pi = 0; pi < 4; ++pi) {
+            const int grid = per_cu[pi] * cus;
+            float ms_min = 1e30f;
+            for (int rep = 0; rep < 3; ++rep) {  // the first run warms the caches
+                (void)hipEventRecord(e0, ctx->stream);
+                launch_solve_batched(bp<SolveScene>(ctx->solve_table), count, total, max_views, blocks[bi], grid,
+                                     ctx->stream);
+                (void)hipEventRecord(e1, ctx->stream);
+                hipError_t e = hipEventSynchronize(e1);
+                if (e != hipSuccess) {
+                    (void)hipEventDestroy(e0);
+                    (void)hipEventDestroy(e1);
+                    return fail(ctx, GSN_E_HIP, "tuning launch: %s", hipGetErrorString(e));
+                }
+                float ms = 0.f;
+                (void)hipEventElapsedTime(&ms, e0, e1);
+                if (rep > 0) ms_min = std::min(ms_min, ms);
+            }
+            if (ms_min < best) {
+                best = ms_min;
+                best_block = blocks[bi];
+                best_grid = grid;
+            }
+        }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    HIP_TRY(ctx, hipGetLastError());
+    ctx->solve_block = best_block;
+    ctx->solve_grid = best_grid;
+    if (h_block) *h_block = best_block;
+    if (h_grid) *h_grid = best_grid;
+    return GSN_OK;
+}
+
+gsn_status gsn_solve_graph_create(gsn_ctx* ctx, const gsn_solve_item* items, int32_t count, gsn_graph** out) {
+    if (!ctx || !out) return fail(ctx, GSN_E_INVALID, "null argument");
+    *out = nullptr;
+    std::vector<SolveScene> table;
+    long long total = 0;
+    int max_views = 1;
+    gsn_status r = build_solve_table(ctx, items, count, table, total, max_views);
+    if (r != GSN_OK) return r;
+    HIP_TRY(ctx, hipSetDevice(ctx->device));
+    gsn_graph* gr = new gsn_graph();
+    hipStream_t cs = nullptr;
+    auto cleanup = [&]() {
+        if (cs) (void)hipStreamDestroy(cs);
+        if (gr->exec) (void)hipGraphExecDestroy(gr->exec);
+        if (gr->graph) (void)hipGraphDestroy(gr->graph);
+        buf_free(gr->table);
+        delete gr;
+    };
+    hipError_t e = buf_reserve(gr->table, table.size() * sizeof(SolveScene));
+    if (e == hipSuccess)
+        e = hipMemcpy(gr->table.p, table.data(), table.size() * sizeof(SolveScene), hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipStreamCreateWithFlags(&cs, hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+    if (e == hipSuccess) {
+        int block, grid;
+        default_solve_shape(ctx, block, grid);
+        launch_solve_batched(bp<SolveScene>(gr->table), count, total, max_views, block, grid, cs);
+        hipError_t el = hipGetLastError();
+        e = hipStreamEndCapture(cs, &gr->graph);
+        if (e == hipSuccess) e = el;
+    }
+    if (e == hipSuccess) e = hipGraphInstantiate(&gr->exec, gr->graph, nullptr, nullptr, 0);
+    if (e != hipSuccess) {
+        cleanup();
+        return fail(ctx, GSN_E_HIP, "graph capture: %s", hipGetErrorString(e));
+    }
+    (void)hipStreamDestroy(cs);
+    *out = gr;
+    return GSN_OK;
+}
+
+gsn_status gsn_graph_launch(gsn_ctx* ctx, gsn_graph* gr) {
+    if (!ctx || !gr || !gr->exec) return fail(ctx, GSN_E_INVALID, "null graph");
+    HIP_TRY(ctx, hipSetDevice(ctx->device));
+    StageTimer st_(ctx, GSN_STAGE_SOLVE);
+    HIP_TRY(ctx, hipGraphLaunch(gr->exec, ctx->stream));
+    return GSN_OK;
+}
+
+gsn_status gsn_graph_destroy(gsn_ctx* ctx, gsn_graph* gr) {
+    if (!gr) return GSN_OK;
+    if (ctx) {
+        (void)hipSetDevice(ctx->device);
+        (void)hipStreamSynchronize(ctx->stream);
+    }
+    if (gr->exec) (void)hipGraphExecDestroy(gr->exec);
+    if (gr->graph) (void)hipGraphDestroy(gr->graph);
+    buf_free(gr->table);
+    delete gr;
     return GSN_OK;
 }
 

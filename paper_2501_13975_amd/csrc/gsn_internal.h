@@ -71,6 +71,15 @@ struct gsn_ctx {
     int64_t pairs_counted = 0;
     // gradient partials of gsn_mlp_train_step
     DevBuf mlp_part, mlp_stat;
+    // batched solve: scene table and the tuned launch shape (0 = not tuned)
+    DevBuf solve_table;
+    int solve_block = 0, solve_grid = 0;
+};
+
+struct gsn_graph {
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    DevBuf table;
 };
 
 // Brackets one stage with events when profiling is on.
@@ -119,6 +128,22 @@ void launch_solve(const gsn_gaussians& g, const DevCam& cam, float kappa, const 
                   const gsn_solve_opts& o, const gsn_steps& st, hipStream_t s);
 void launch_apply(const gsn_gaussians& g, const gsn_steps& st, const gsn_solve_opts& o, const float* scale,
                   uint32_t mask, hipStream_t s);
+// One scene of a batched solve (device-side table entry).
+#define GSN_SOLVE_MAX_SCENES 64
+#define GSN_SOLVE_MAX_BLOCK 256
+struct SolveScene {
+    const float *pos, *rot, *scale, *opac;
+    int n, K, V;
+    DevCam cam;
+    float kappa;
+    const float* blk;
+    gsn_solve_opts o;
+    float* st;
+    int32_t* fl;
+    long long first;  // index of the scene's first kernel in the concatenated index space
+};
+void launch_solve_batched(const SolveScene* d_scenes, int count, long long total, int max_views, int block,
+                          int grid, hipStream_t s);
 void launch_features(const gsn_gaussians& g, const DevCam& cam, float kappa, const gsn_blocks& b,
                      const gsn_solve_opts& o, float* feat, uint8_t* ok, hipStream_t s);
 void launch_labels(int n, int K, const float* sp, const int32_t* fp, const float* sa, float* label, float* mask,

@@ -232,14 +232,12 @@ __device__ __forceinline__ void qmul(const T a[4], const T b[4], T r[4]) {
     r[3] = a[0] * b[3] + b[0] * a[3] + a[1] * b[2] - a[2] * b[1];
 }
 
+// The local solves of kernel k of one scene (all groups), writing its steps and decisions.
 template <int VM>
-__global__ __launch_bounds__(128) void solve_kernel(const float* __restrict__ pos, const float* __restrict__ rot,
-                                                     const float* __restrict__ scale, const float* __restrict__ opac,
-                                                     int n, int K, DevCam c, float kappa,
-                                                     const float* __restrict__ blk, int V, gsn_solve_opts o,
-                                                     float* __restrict__ st, int32_t* __restrict__ fl) {
-    const int k = blockIdx.x * blockDim.x + threadIdx.x;
-    if (k >= n) return;
+__device__ __forceinline__ void solve_one(int k, const float* __restrict__ pos, const float* __restrict__ rot,
+                                          const float* __restrict__ scale, const float* __restrict__ opac, int n,
+                                          int K, const DevCam& c, float kappa, const float* __restrict__ blk, int V,
+                                          const gsn_solve_opts& o, float* __restrict__ st, int32_t* __restrict__ fl) {
     const size_t N = (size_t)n;
     const int NS = GSN_STEP_BASE + 3 * K;
     auto B = [&](int row) { return (double)blk[(size_t)row * N + k]; };
@@ -288,6 +286,39 @@ __global__ __launch_bounds__(128) void solve_kernel(const float* __restrict__ po
     }
     // ---- colour, per channel
     colour_solve<VM>(K, V, B, o, abs_scale, st, N, k, fl);
+}
+
+template <int VM>
+__global__ __launch_bounds__(128) void solve_kernel(const float* __restrict__ pos, const float* __restrict__ rot,
+                                                     const float* __restrict__ scale, const float* __restrict__ opac,
+                                                     int n, int K, DevCam c, float kappa,
+                                                     const float* __restrict__ blk, int V, gsn_solve_opts o,
+                                                     float* __restrict__ st, int32_t* __restrict__ fl) {
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= n) return;
+    solve_one<VM>(k, pos, rot, scale, opac, n, K, c, kappa, blk, V, o, st, fl);
+}
+
+// Several scenes in one persistent launch: the threads of a grid sized to the device walk
+// the concatenated kernel index space (scene s owns [first[s], first[s + 1])) in strides;
+// each kernel's solve is the per-scene solve, so the results are identical.
+template <int VM, int BLOCK>
+__global__ __launch_bounds__(BLOCK) void solve_batched_kernel(const SolveScene* __restrict__ scenes, int count,
+                                                               long long total) {
+    __shared__ long long s_first[GSN_SOLVE_MAX_SCENES + 1];
+    for (int i = threadIdx.x; i <= count; i += blockDim.x) s_first[i] = i < count ? scenes[i].first : total;
+    __syncthreads();
+    const long long stride = (long long)gridDim.x * blockDim.x;
+    for (long long gi = (long long)blockIdx.x * blockDim.x + threadIdx.x; gi < total; gi += stride) {
+        int lo = 0, hi = count - 1;  // last scene whose first index <= gi
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (s_first[mid] <= gi) lo = mid; else hi = mid - 1;
+        }
+        const SolveScene& sc = scenes[lo];
+        solve_one<VM>((int)(gi - s_first[lo]), sc.pos, sc.rot, sc.scale, sc.opac, sc.n, sc.K, sc.cam, sc.kappa,
+                      sc.blk, sc.V, sc.o, sc.st, sc.fl);
+    }
 }
 
 __global__ __launch_bounds__(256) void apply_kernel(float* __restrict__ pos, float* __restrict__ rot,
@@ -342,6 +373,26 @@ void launch_solve(const gsn_gaussians& g, const DevCam& cam, float kappa, const 
     else
         solve_kernel<9><<<(g.n + 127) / 128, 128, 0, s>>>(g.d_pos, g.d_rot, g.d_scale, g.d_opac, g.n, K, cam, kappa,
                                                           b.d_data, b.n_views, o, st.d_data, st.d_flags);
+}
+
+template <int BLOCK>
+static void launch_batched_block(const SolveScene* d_scenes, int count, long long total, int max_views, int grid,
+                                 hipStream_t s) {
+    if (max_views <= 4)
+        solve_batched_kernel<4, BLOCK><<<grid, BLOCK, 0, s>>>(d_scenes, count, total);
+    else
+        solve_batched_kernel<9, BLOCK><<<grid, BLOCK, 0, s>>>(d_scenes, count, total);
+}
+
+void launch_solve_batched(const SolveScene* d_scenes, int count, long long total, int max_views, int block,
+                          int grid, hipStream_t s) {
+    if (total == 0) return;
+    if (block == 64)
+        launch_batched_block<64>(d_scenes, count, total, max_views, grid, s);
+    else if (block == 256)
+        launch_batched_block<256>(d_scenes, count, total, max_views, grid, s);
+    else
+        launch_batched_block<128>(d_scenes, count, total, max_views, grid, s);
 }
 
 void launch_apply(const gsn_gaussians& g, const gsn_steps& st, const gsn_solve_opts& o, const float* scale,

@@ -44,6 +44,10 @@ def lib():
             "gsn_local_newton_solve": [P, P, P, P, P, P],
             "gsn_apply_step": [P, P, P, P, P, ctypes.c_uint32],
             "gsn_step_features": [P, P, P, P, P, P, P],
+            "gsn_solve_batched": [P, P, ctypes.c_int32],
+            "gsn_solve_tune": [P, P, ctypes.c_int32, P, P],
+            "gsn_solve_graph_create": [P, P, ctypes.c_int32, ctypes.POINTER(P)],
+            "gsn_graph_launch": [P, P], "gsn_graph_destroy": [P, P],
             "gsn_step_labels": [P, P, P, P, P],
             "gsn_mlp_reset": [P, P],
             "gsn_mlp_infer": [P, P, ctypes.c_int32, P, P, P],
@@ -276,6 +280,33 @@ class Context:
         self._check(lib().gsn_apply_step(self.h, ctypes.byref(cg), ctypes.byref(cs), ctypes.byref(so),
                                          _ptr(scale), int(group_mask)))
 
+    def _items(self, items):
+        """items: list of (DeviceGaussians, CCamera, Blocks, CSolveOpts, Steps) -> C array (+ keep-alive)."""
+        keep = []
+        arr = (CSolveItem * len(items))()
+        for i, (g, cam, blocks, so, steps) in enumerate(items):
+            cg, cb, cs = g.c(), blocks.c(), steps.c()
+            keep += [cg, cb, cs, cam, so]
+            arr[i] = CSolveItem(ctypes.addressof(cg), ctypes.addressof(cam), ctypes.addressof(cb),
+                                ctypes.addressof(so), ctypes.addressof(cs))
+        return arr, keep
+
+    def solve_batched(self, items):
+        arr, keep = self._items(items)
+        self._check(lib().gsn_solve_batched(self.h, arr, len(items)))
+
+    def solve_tune(self, items):
+        arr, keep = self._items(items)
+        b, gr = ctypes.c_int32(), ctypes.c_int32()
+        self._check(lib().gsn_solve_tune(self.h, arr, len(items), ctypes.byref(b), ctypes.byref(gr)))
+        return int(b.value), int(gr.value)
+
+    def solve_graph(self, items) -> "SolveGraph":
+        arr, keep = self._items(items)
+        h = ctypes.c_void_p()
+        self._check(lib().gsn_solve_graph_create(self.h, arr, len(items), ctypes.byref(h)))
+        return SolveGraph(self, h)
+
     def step_features(self, g, primary: CCamera, blocks: "Blocks", so: CSolveOpts, feat, ok):
         """feat: device float [16, n]; ok: device uint8 [n]."""
         cg, cb = g.c(), blocks.c()
@@ -332,6 +363,26 @@ GSN_MLP_PARAMS = 709
 class CMlp(ctypes.Structure):
     _fields_ = [("d_params", ctypes.c_void_p), ("d_m", ctypes.c_void_p), ("d_v", ctypes.c_void_p),
                 ("d_half", ctypes.c_void_p), ("step", ctypes.c_int32)]
+
+
+class CSolveItem(ctypes.Structure):
+    _fields_ = [("g", ctypes.c_void_p), ("primary", ctypes.c_void_p), ("blocks", ctypes.c_void_p),
+                ("opts", ctypes.c_void_p), ("steps", ctypes.c_void_p)]
+
+
+class SolveGraph:
+    """A captured batched solve; launch() replays it on the context's stream."""
+
+    def __init__(self, ctx, h):
+        self.ctx, self.h = ctx, h
+
+    def launch(self):
+        self.ctx._check(lib().gsn_graph_launch(self.ctx.h, self.h))
+
+    def close(self):
+        if self.h is not None:
+            lib().gsn_graph_destroy(self.ctx.h, self.h)
+            self.h = None
 
 
 class CAdamOpts(ctypes.Structure):
