@@ -173,6 +173,52 @@ def _equal_psnr(cfg, targets, dev, epochs, every, mask, step_frac):
     return out
 
 
+def _batched_solve_leg(dev, reps=20):
+    """The eight scenes of 20k-800k kernels at 1280x720: blocks from one primary and three
+    secondary views each, then the solves of all scenes timed as one launch per scene, as
+    one batched launch (autotuned shape) and as a replayed HIP graph."""
+    import numpy as np
+    import torch
+
+    from paper_2501_13975_amd import gsn
+    from paper_2501_13975_amd.train import LocalNewtonTrainer
+    from synth.scenes import C3_SIZES, make_config
+    trs, items, total = [], [], 0
+    for i in range(len(C3_SIZES)):
+        cfg = make_config(f"c3_{i}")
+        targets = _targets(cfg, dev)
+        g = gsn.DeviceGaussians.from_host(cfg.init, dev)
+        tr = LocalNewtonTrainer(g, cfg.cams, targets, n_secondary=cfg.n_secondary)
+        tr.accumulate(0)
+        trs.append(tr)
+        items.append((tr.g, tr.ccams[0], tr.blocks, tr.solve_opts(0), tr.steps))
+        total += cfg.n
+    torch.cuda.synchronize(dev)
+    ctx = trs[0].ctx
+
+    def timed(fn):
+        fn()
+        torch.cuda.synchronize(dev)
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            fn()
+        torch.cuda.synchronize(dev)
+        return (time.perf_counter() - t0) * 1e3 / reps
+
+    per_scene = timed(lambda: [tr.ctx.local_newton_solve(*it[:4], it[4]) for tr, it in zip(trs, items)])
+    block, grid = ctx.solve_tune(items)
+    batched = timed(lambda: ctx.solve_batched(items))
+    graph = ctx.solve_graph(items)
+    graphed = timed(graph.launch)
+    graph.close()
+    for tr in trs:
+        tr.close()
+    return {"scenes": len(C3_SIZES), "kernels": total, "views": "1280x720 + 3 half-resolution secondaries",
+            "ms_per_scene_launches": round(per_scene, 4), "ms_batched": round(batched, 4),
+            "ms_graph": round(graphed, 4), "tuned_block": block, "tuned_grid": grid,
+            "kernels_solved_per_s_graph": round(total / (graphed * 1e-3), 1)}
+
+
 def gpu_run(args):
     import numpy as np
     import torch
@@ -200,11 +246,15 @@ def gpu_run(args):
                    "every": args.learned_every,
                    "stage_ms_per_step": {k: round(v[0] / args.steps, 3) for k, v in st2.items()}}
         log(f"[bench] learned: {args.steps} sweeps in {el2:.3f}s")
+    batched = None
+    if args.batched_leg:
+        batched = _batched_solve_leg(dev)
+        log(f"[bench] batched solve: {batched}")
     quality = None
     if args.quality_epochs > 0 and args.learned_every:
         quality = _equal_psnr(cfg, targets, dev, args.quality_epochs, args.learned_every, args.quality_mask,
                               args.quality_step_frac)
-    return elapsed, stages, counts, cfg, learned, quality
+    return elapsed, stages, counts, cfg, learned, quality, batched
 
 
 def roofline(stages, counts, steps, pixels_per_step):
@@ -300,12 +350,14 @@ def main():
                     help="attribute groups trained in the equal-PSNR leg (bits: 1 position, 2 rotation, 4 scaling, "
                          "8 opacity, 16 colour)")
     ap.add_argument("--quality-step-frac", type=float, default=0.3)
+    ap.add_argument("--no-batched-leg", dest="batched_leg", action="store_false",
+                    help="skip timing the batched solve of the eight 20k-800k scenes")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU: this build runs the training step on a single MI355X "
               "(how it would shard across GPUs is described in DESIGN.md); run with --gpus 1", file=sys.stderr)
         sys.exit(2)
-    elapsed, stages, counts, cfg, learned, quality = gpu_run(args)
+    elapsed, stages, counts, cfg, learned, quality, batched = gpu_run(args)
     ms_per_step = elapsed * 1e3 / args.steps
     value = args.steps / elapsed
     pixels = cfg.width * cfg.height + cfg.n_secondary * (cfg.width // 2) * (cfg.height // 2)
@@ -330,6 +382,7 @@ def main():
         "cpu_baseline": cpu,
         "learned": learned,
         "equal_psnr": quality,
+        "batched_solve": batched,
     }
     print(json.dumps(out), flush=True)
 

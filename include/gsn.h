@@ -235,7 +235,8 @@ typedef struct {
  * GSN_E_CAPACITY as for gsn_local_newton_solve, per item. */
 gsn_status gsn_solve_batched(gsn_ctx* ctx, const gsn_solve_item* items, int32_t count);
 /* Launch-shape autotuner of the batched solve: times block sizes {64, 128,
- * 256} and persistent grids of {1, 2, 4, 8} workgroups per compute unit on the
+ * 256} and grids of {1, 2, 4, 8, 16} workgroups per compute unit or one thread
+ * per kernel on the
  * given items (the solves run, and rerun, on the real buffers), keeps the
  * fastest for later gsn_solve_batched and graph calls on this context and
  * returns it (h_block, h_grid may be NULL).  Synchronises the stream. */

@@ -511,10 +511,12 @@ gsn_status gsn_solve_tune(gsn_ctx* ctx, const gsn_solve_item* items, int32_t cou
     HIP_TRY(ctx, hipEventCreate(&e1));
     float best = 1e30f;
     int best_block = 128, best_grid = 4 * cus;
-    const int blocks[3] = {64, 128, 256}, per_cu[4] = {1, 2, 4, 8};
+    // persistent grids of 1..16 workgroups per compute unit, and the full grid (one thread per kernel)
+    const int blocks[3] = {64, 128, 256}, per_cu[6] = {1, 2, 4, 8, 16, 0};
     for (int bi = 0; bi < 3; ++bi)
-        for (int pi = 0; pi < 4; ++pi) {
-            const int grid = per_cu[pi] * cus;
+        for (int pi = 0; pi < 6; ++pi) {
+            const long long full = (total + blocks[bi] - 1) / blocks[bi];
+            const int grid = per_cu[pi] ? per_cu[pi] * cus : (int)std::min<long long>(full, 1ll << 30);
             float ms_min = 1e30f;
             for (int rep = 0; rep < 3; ++rep) {  // the first run warms the caches
                 (void)hipEventRecord(e0, ctx->stream);

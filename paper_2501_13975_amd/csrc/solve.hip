@@ -303,7 +303,7 @@ __global__ __launch_bounds__(128) void solve_kernel(const float* __restrict__ po
 // the concatenated kernel index space (scene s owns [first[s], first[s + 1])) in strides;
 // each kernel's solve is the per-scene solve, so the results are identical.
 template <int VM, int BLOCK>
-__global__ __launch_bounds__(BLOCK) void solve_batched_kernel(const SolveScene* __restrict__ scenes, int count,
+__global__ __launch_bounds__(BLOCK, 3) void solve_batched_kernel(const SolveScene* __restrict__ scenes, int count,
                                                                long long total) {
     __shared__ long long s_first[GSN_SOLVE_MAX_SCENES + 1];
     for (int i = threadIdx.x; i <= count; i += blockDim.x) s_first[i] = i < count ? scenes[i].first : total;
