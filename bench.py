@@ -78,11 +78,14 @@ def _targets(cfg, dev):
 
 
 def _trainer(cfg, targets, dev, learned_every=0, step_frac=1.0):
+    """The plain form (FP64 small solves), or with learned_every the mixed + learned form (BF16
+    matrix-core colour Grams, FP32 solves with FP64 for flagged systems, learned step scale)."""
     from paper_2501_13975_amd import gsn
     from paper_2501_13975_amd.train import LocalNewtonTrainer
     from synth.mlp_init import init_params
     g = gsn.DeviceGaussians.from_host(cfg.init, dev)
-    tr = LocalNewtonTrainer(g, cfg.cams, targets, n_secondary=cfg.n_secondary, solve_kw={"step_frac": step_frac})
+    kw = {"step_frac": step_frac, "precision": 1 if learned_every else 0}
+    tr = LocalNewtonTrainer(g, cfg.cams, targets, n_secondary=cfg.n_secondary, solve_kw=kw)
     if learned_every:
         tr.enable_learned(init_params(0), every=learned_every, lr=1e-2)
     return tr

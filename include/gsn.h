@@ -110,6 +110,12 @@ typedef struct {
     float kappa;
     float trust_pos, trust_rot, trust_scale, trust_sh, opac_eps, step_frac;
     float damp_sh;  /* colour damping relative to the mean diagonal of the colour Gram matrix */
+    /* 0: plain form (reduced systems and solves in FP64); 1: mixed form (n_views <= 4):
+     * colour Gram matrices from BF16 matrix-core products with one BF16 correction of the
+     * basis rounding and FP32 accumulation, reduced systems and solves in FP32, and FP64
+     * again for position or rotation systems whose pivots pass their tests by less than a
+     * factor of 10 (counted as GSN_COUNT_FP64_SOLVES while profiling). */
+    int32_t precision;
 } gsn_solve_opts;
 
 /* Per-kernel gradient/Hessian blocks, summed over the views added so far.
@@ -216,14 +222,22 @@ gsn_status gsn_local_newton_solve(gsn_ctx* ctx, const gsn_gaussians* g, const gs
 gsn_status gsn_apply_step(gsn_ctx* ctx, gsn_gaussians* g, const gsn_steps* steps,
                           const gsn_solve_opts* opts, const float* d_scale, uint32_t group_mask);
 
+/* The colour Gram matrices of the mixed form: for every kernel, B B^T over the
+ * views that see it (coverage > 0, at most 4, in slot order), B the rows of the
+ * SH basis Y(r_v) (Appendix A.2), from BF16 matrix-core products with FP32
+ * accumulation; upper triangle written to d_out (device float [10][n], entry
+ * (i, j), i <= j, at row 4 i - i (i - 1) / 2 + j - i).  Errors: GSN_E_SHAPE
+ * (n_views > 4). */
+gsn_status gsn_sh_gram(gsn_ctx* ctx, const gsn_blocks* blocks, int32_t sh_degree, float* d_out);
+
 /* ------------------------------------------------- batched solve
  * The local Newton solves of several scenes (Sec. 4.2, eq. local_newton) in
  * one persistent launch: a grid sized to the device walks the concatenated
  * kernel index space of all scenes, every kernel solving all of its groups
  * (sizes 1, 2 reduced, 3 and the per-channel colour systems) exactly as
  * gsn_local_newton_solve does, so the results are identical to per-scene
- * calls.  Each item's pointers are borrowed for the call (the graph form
- * below keeps them). */
+ * calls (plain form: opts.precision must be 0).  Each item's pointers are
+ * borrowed for the call (the graph form below keeps them). */
 typedef struct {
     const gsn_gaussians* g;
     const gsn_camera* primary;
@@ -387,7 +401,8 @@ typedef enum {
     GSN_COUNT_PAIRS = 3,       /* (tile, kernel) pairs binned */
     GSN_COUNT_PARTIALS = 4,    /* (tile, kernel) partial statistics written by the backward pass */
     GSN_COUNT_FWD_STAGED = 5,  /* list entries the forward pass staged (read) before its tiles finished */
-    GSN_COUNT_N = 6
+    GSN_COUNT_FP64_SOLVES = 6, /* kernels whose position or rotation system the mixed form re-solved in FP64 */
+    GSN_COUNT_N = 7
 } gsn_counter;
 
 /* Turns stage timing on or off and clears what was accumulated.  While on,

@@ -149,6 +149,7 @@ gsn_status gsn_destroy(gsn_ctx* ctx) {
     buf_free(ctx->mlp_part);
     buf_free(ctx->mlp_stat);
     buf_free(ctx->solve_table);
+    buf_free(ctx->gram);
     delete ctx;
     return GSN_OK;
 }
@@ -404,9 +405,31 @@ gsn_status gsn_local_newton_solve(gsn_ctx* ctx, const gsn_gaussians* g, const gs
     if (g->n > 0 && (!b->d_data || !st->d_data || !st->d_flags)) return fail(ctx, GSN_E_INVALID, "null device array");
     if (o->npix_primary <= 0 || o->max_escalations < 0 || o->max_escalations > 30)
         return fail(ctx, GSN_E_INVALID, "solve option out of range");
+    if (o->precision != 0 && o->precision != 1) return fail(ctx, GSN_E_INVALID, "precision must be 0 or 1");
+    if (o->precision == 1 && b->n_views > 4) return fail(ctx, GSN_E_SHAPE, "the mixed form takes at most 4 views");
     HIP_TRY(ctx, hipSetDevice(ctx->device));
+    if (o->precision == 1) HIP_TRY(ctx, buf_reserve(ctx->gram, (size_t)std::max(g->n, 1) * 10 * 4));
     StageTimer st_(ctx, GSN_STAGE_SOLVE);
-    launch_solve(*g, make_devcam(*primary), o->kappa, *b, *o, *st, ctx->stream);
+    if (o->precision == 1) {
+        const int K = (g->sh_degree + 1) * (g->sh_degree + 1);
+        launch_sh_gram(b->d_data, g->n, K, b->n_views, bp<float>(ctx->gram), ctx->stream);
+        unsigned long long* n64 = ctx->prof && ctx->d_counts ? ctx->d_counts + GSN_COUNT_FP64_SOLVES : nullptr;
+        launch_solve_mixed(*g, make_devcam(*primary), o->kappa, *b, *o, bp<float>(ctx->gram), *st, n64,
+                           ctx->stream);
+    } else {
+        launch_solve(*g, make_devcam(*primary), o->kappa, *b, *o, *st, ctx->stream);
+    }
+    HIP_TRY(ctx, hipGetLastError());
+    return GSN_OK;
+}
+
+gsn_status gsn_sh_gram(gsn_ctx* ctx, const gsn_blocks* b, int32_t sh_degree, float* d_out) {
+    if (!ctx || !b) return fail(ctx, GSN_E_INVALID, "null argument");
+    if (sh_degree < 0 || sh_degree > 3) return fail(ctx, GSN_E_SHAPE, "sh_degree must be 0..3");
+    if (b->n_views < 1 || b->n_views > 4) return fail(ctx, GSN_E_SHAPE, "n_views must be 1..4");
+    if (b->n > 0 && (!b->d_data || !d_out)) return fail(ctx, GSN_E_INVALID, "null device array");
+    HIP_TRY(ctx, hipSetDevice(ctx->device));
+    launch_sh_gram(b->d_data, b->n, (sh_degree + 1) * (sh_degree + 1), b->n_views, d_out, ctx->stream);
     HIP_TRY(ctx, hipGetLastError());
     return GSN_OK;
 }
@@ -436,6 +459,7 @@ static gsn_status build_solve_table(gsn_ctx* ctx, const gsn_solve_item* items, i
             return fail(ctx, GSN_E_INVALID, "item %d: null device array", i);
         if (o.npix_primary <= 0 || o.max_escalations < 0 || o.max_escalations > 30)
             return fail(ctx, GSN_E_INVALID, "item %d: solve option out of range", i);
+        if (o.precision != 0) return fail(ctx, GSN_E_INVALID, "item %d: the batched solve runs the plain form", i);
         SolveScene sc;
         sc.pos = it.g->d_pos;
         sc.rot = it.g->d_rot;

@@ -74,6 +74,8 @@ struct gsn_ctx {
     // batched solve: scene table and the tuned launch shape (0 = not tuned)
     DevBuf solve_table;
     int solve_block = 0, solve_grid = 0;
+    // colour Gram matrices of the mixed form
+    DevBuf gram;
 };
 
 struct gsn_graph {
@@ -144,6 +146,10 @@ struct SolveScene {
 };
 void launch_solve_batched(const SolveScene* d_scenes, int count, long long total, int max_views, int block,
                           int grid, hipStream_t s);
+void launch_sh_gram(const float* blk, int n, int K, int V, float* gram, hipStream_t s);
+void launch_solve_mixed(const gsn_gaussians& g, const DevCam& cam, float kappa, const gsn_blocks& b,
+                        const gsn_solve_opts& o, const float* gram, const gsn_steps& st, unsigned long long* n_fp64,
+                        hipStream_t s);
 void launch_features(const gsn_gaussians& g, const DevCam& cam, float kappa, const gsn_blocks& b,
                      const gsn_solve_opts& o, float* feat, uint8_t* ok, hipStream_t s);
 void launch_labels(int n, int K, const float* sp, const int32_t* fp, const float* sa, float* label, float* mask,

@@ -20,44 +20,54 @@
 // most V (number of views that see the kernel); when V < K it is solved in view
 // space, (B B^T + mu S^-1) y = -S^-1 gamma, Delta = B^T y, which equals the
 // damped K x K solve exactly and is far better conditioned.
+#include <limits>
+
 #include "gsn_internal.h"
 #include "reduced.h"
 
 namespace {
 
-// Damped solve of a 1x1 or 2x2 symmetric system (H packed xx, xy, yy for n = 2) in double.
-__device__ int damped_small(int n, const double* H, const double* g, const gsn_solve_opts& o, double abs_scale,
-                            double* x) {
+// Damped solve of a 1x1 or 2x2 symmetric system (H packed xx, xy, yy for n = 2) in precision T.
+// *near (if given) is set when the accepted attempt passed its pivot tests by less than a factor
+// of 10 or the gradient fallback was taken: the mixed form recomputes such systems in double.
+template <class T>
+__device__ int damped_small(int n, const T* H, const T* g, const gsn_solve_opts& o, T abs_scale, T* x,
+                            bool* near = nullptr) {
     // scale of H: Frobenius norm / sqrt(n), invariant to the reduced basis
-    const double ma = n == 1 ? fabs(H[0]) : sqrt(0.5 * (H[0] * H[0] + 2.0 * H[1] * H[1] + H[2] * H[2]));
-    double mu = (double)o.damp_rel * ma + (double)o.damp_abs * abs_scale;
+    const T ma = n == 1 ? fabs(H[0]) : sqrt(T(0.5) * (H[0] * H[0] + T(2) * H[1] * H[1] + H[2] * H[2]));
+    T mu = (T)o.damp_rel * ma + (T)o.damp_abs * abs_scale;
+    const T pmin = (T)o.pivot_min;
     for (int j = 0; j <= o.max_escalations; ++j) {
         // every pivot must exceed pivot_min times the size of H + mu I
-        const double floor = (double)o.pivot_min * (ma + mu);
+        const T floor = pmin * (ma + mu);
         if (n == 1) {
-            const double d = H[0] + mu;
+            const T d = H[0] + mu;
             if (d > floor) {
                 x[0] = -g[0] / d;
+                if (near) *near = d < T(10) * floor;
                 return j;
             }
         } else {
-            const double a = H[0] + mu, b = H[1], c = H[2] + mu;
+            const T a = H[0] + mu, b = H[1], c = H[2] + mu;
             if (a > floor) {
-                const double l10 = b / a;
-                const double d2 = c - l10 * b;
-                if (d2 > floor && fmin(a, d2) >= (double)o.pivot_min * fmax(a, d2)) {
+                const T l10 = b / a;
+                const T d2 = c - l10 * b;
+                if (d2 > floor && fmin(a, d2) >= pmin * fmax(a, d2)) {
                     // L D L^T with L = [[1, 0], [l10, 1]], D = diag(a, d2)
-                    const double y0 = -g[0], y1 = -g[1] - l10 * y0;
+                    const T y0 = -g[0], y1 = -g[1] - l10 * y0;
                     x[1] = y1 / d2;
                     x[0] = (y0 - b * x[1]) / a;
+                    if (near)
+                        *near = fmin(a, d2) < T(10) * floor || fmin(a, d2) < T(10) * pmin * fmax(a, d2);
                     return j;
                 }
             }
         }
-        if (j < o.max_escalations) mu *= 10.0;
+        if (j < o.max_escalations) mu *= T(10);
     }
-    const double den = ma + mu;
+    const T den = ma + mu;
     for (int i = 0; i < n; ++i) x[i] = -g[i] / den;
+    if (near) *near = true;
     return -1;
 }
 
@@ -71,32 +81,32 @@ __device__ void clamp_norm(int n, double* x, double radius) {
 
 // Cholesky solve of an m x m SPD system (m <= VM) held in a VM x VM register array (double).
 // Loops run to the compile-time bound with guards, so the arrays stay in registers.
-template <int VM>
-__device__ __forceinline__ bool chol_solve_v(int m, const double A[VM][VM], const double* b, double* x) {
-    double L[VM][VM];
+template <int VM, class T = double>
+__device__ __forceinline__ bool chol_solve_v(int m, const T A[VM][VM], const T* b, T* x) {
+    T L[VM][VM];
     bool ok = true;
 #pragma unroll
     for (int i = 0; i < VM; ++i) {
 #pragma unroll
         for (int j = 0; j <= i; ++j) {
             if (i < m) {
-                double s = A[i][j];
+                T s = A[i][j];
 #pragma unroll
                 for (int k = 0; k < j; ++k) s -= L[i][k] * L[j][k];
                 if (i == j) {
-                    ok = ok && s > 0.0;
-                    L[i][i] = sqrt(fmax(s, 1e-300));
+                    ok = ok && s > T(0);
+                    L[i][i] = sqrt(fmax(s, std::numeric_limits<T>::min()));
                 } else {
                     L[i][j] = s / L[j][j];
                 }
             }
         }
     }
-    double y[VM];
+    T y[VM];
 #pragma unroll
     for (int i = 0; i < VM; ++i) {
         if (i < m) {
-            double s = b[i];
+            T s = b[i];
 #pragma unroll
             for (int k = 0; k < i; ++k) s -= L[i][k] * y[k];
             y[i] = s / L[i][i];
@@ -105,7 +115,7 @@ __device__ __forceinline__ bool chol_solve_v(int m, const double A[VM][VM], cons
 #pragma unroll
     for (int i = VM - 1; i >= 0; --i) {
         if (i < m) {
-            double s = y[i];
+            T s = y[i];
 #pragma unroll
             for (int k = i + 1; k < VM; ++k)
                 if (k < m) s -= L[k][i] * x[k];
@@ -187,7 +197,7 @@ __device__ __forceinline__ void colour_solve(int K, int V, RowFn B, const gsn_so
             for (int j = 0; j < VM; ++j) A[i][j] = Gm[i][j] + (i == j ? mu / sv[i] : 0.0);
             rhs[i] = i < nv ? -B(vb[i] + ch) / sv[i] : 0.0;
         }
-        if (chol_solve_v<VM>(nv, A, rhs, y)) {
+        if (chol_solve_v<VM, double>(nv, A, rhs, y)) {
 #pragma unroll
             for (int i = 0; i < VM; ++i)
                 if (i < nv) ych[ch][i] = y[i];
@@ -274,7 +284,7 @@ __device__ __forceinline__ void solve_one(int k, const float* __restrict__ pos, 
         fl[2 * N + k] = damped_small(2, R.Hs, R.gs, o, abs_scale, av);
         for (int a = 0; a < 2; ++a) av[a] *= (double)o.step_frac;
         double dsv[3];
-        for (int a = 0; a < 3; ++a) dsv[a] = R.T[0][a] * av[0] + R.T[1][a] * av[1];
+        for (int a = 0; a < 3; ++a) dsv[a] = R.T_[0][a] * av[0] + R.T_[1][a] * av[1];
         clamp_norm(3, dsv, (double)o.trust_scale * sqrt(s[0] * s[0] + s[1] * s[1] + s[2] * s[2]));
         for (int a = 0; a < 3; ++a) st[(7 + a) * N + k] = (float)dsv[a];
     }
@@ -286,6 +296,268 @@ __device__ __forceinline__ void solve_one(int k, const float* __restrict__ pos, 
     }
     // ---- colour, per channel
     colour_solve<VM>(K, V, B, o, abs_scale, st, N, k, fl);
+}
+
+// ---------------------------------------------------------------------------
+// Mixed-precision form.  The colour Gram matrices B B^T (B: the basis rows Y(r_v) of the
+// views that see a kernel) come from BF16 matrix-core products with FP32 accumulation: with
+// Y = Y_hi + Y_lo (both BF16), G = Y_hi Y_hi^T + Y_hi Y_lo^T + Y_lo Y_hi^T, one correction
+// of the BF16 rounding.  The reduced systems and all solves run in FP32; a position or
+// rotation system whose pivots pass their tests by less than a factor of 10 (or that falls
+// back to the gradient step) is solved again in FP64.
+// ---------------------------------------------------------------------------
+typedef short bf16x4 __attribute__((ext_vector_type(4)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ short to_bf16(float x) {
+    // round to nearest even (finite inputs)
+    const uint32_t u = __float_as_uint(x);
+    return (short)((u + 0x7fffu + ((u >> 16) & 1u)) >> 16);
+}
+__device__ __forceinline__ float from_bf16(short h) { return __uint_as_float(((uint32_t)(uint16_t)h) << 16); }
+
+// Compacted list of the views that see kernel k (coverage > 0), at most 4.
+__device__ __forceinline__ int active_views(const float* __restrict__ blk, size_t N, int k, int V, int vb[4]) {
+    int nv = 0;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+        vb[v] = 0;
+        if (v < V && blk[(size_t)(GSN_BLK_BASE + GSN_BLK_VIEW * v + 9) * N + k] > 0.f) {
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+                if (i == nv) vb[i] = GSN_BLK_BASE + GSN_BLK_VIEW * v;
+            ++nv;
+        }
+    }
+    return nv;
+}
+
+// One wave per 16 kernels, four 16x16x16 BF16 products per group of 4 kernels: row
+// i = 4 q + v of the operand is the basis row of view v of kernel q, so the 4 x 4 diagonal
+// blocks of Y Y^T are the kernels' Gram matrices.  With the operand layout of the instruction
+// (lane l holds row l % 16, columns 4 (l / 16) .. + 3; the result lane l holds column l % 16,
+// rows 4 (l / 16) .. + 3) the B operand of Y^T is the lane's own A operand.  The upper
+// triangle of each Gram matrix is written to gram [10][n].
+__global__ __launch_bounds__(256) void sh_gram_kernel(const float* __restrict__ blk, int n, int K, int V,
+                                                       float* __restrict__ gram) {
+    const int lane = __lane_id();
+    const int wave = (int)(blockIdx.x * (blockDim.x / 64) + threadIdx.x / 64);
+    const size_t N = (size_t)n;
+    const int row = lane % 16, q = row / 4, v = row % 4, c0 = 4 * (lane / 16);
+#pragma unroll
+    for (int grp = 0; grp < 4; ++grp) {
+        const int base = wave * 16 + grp * 4;
+        if (base >= n) break;  // uniform across the wave
+        const int k = base + q;
+        float y[4] = {0.f, 0.f, 0.f, 0.f};
+        if (k < n) {
+            int vb[4];
+            const int nv = active_views(blk, N, k, V, vb);
+            if (v < nv) {
+                const float rx = blk[(size_t)(vb[v] + 6) * N + k], ry = blk[(size_t)(vb[v] + 7) * N + k],
+                            rz = blk[(size_t)(vb[v] + 8) * N + k];
+                sh_basis_visit<float>(K, rx, ry, rz, [&](int a, float ya) {
+#pragma unroll
+                    for (int t = 0; t < 4; ++t)
+                        if (a == c0 + t) y[t] = ya;
+                });
+            }
+        }
+        bf16x4 hi, lo;
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+            hi[t] = to_bf16(y[t]);
+            lo[t] = to_bf16(y[t] - from_bf16(hi[t]));
+        }
+        f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+        acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(hi, hi, acc, 0, 0, 0);
+        acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(hi, lo, acc, 0, 0, 0);
+        acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(lo, hi, acc, 0, 0, 0);
+        // result lane l holds column j = l % 16, rows 4 (l / 16) + r: a diagonal block when l / 16 == j / 4
+        const int j = lane % 16, qr = lane / 16;
+        const int kk = base + qr;
+        if (qr == j / 4 && kk < n) {
+            const int cj = j % 4;
+#pragma unroll
+            for (int r = 0; r < 4; ++r)
+                if (r <= cj) gram[(size_t)(r * 4 - (r * (r - 1)) / 2 + (cj - r)) * N + kk] = acc[r];
+        }
+    }
+}
+
+// Colour step of the mixed form (FP32), from the matrix-core Gram matrices.
+template <class RowFn>
+__device__ __forceinline__ void colour_solve_mixed(int K, int V, RowFn B, const float* __restrict__ gram,
+                                                   const gsn_solve_opts& o, float abs_scale,
+                                                   float* __restrict__ st, size_t N, int k,
+                                                   int32_t* __restrict__ fl, const float* __restrict__ blk) {
+    int vb[4];
+    const int nv = active_views(blk, N, k, V, vb);
+    fl[4 * N + k] = nv;
+    float Gm[4][4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = i; j < 4; ++j) {
+            const float g = gram[(size_t)(i * 4 - (i * (i - 1)) / 2 + (j - i)) * N + k];
+            Gm[i][j] = g;
+            Gm[j][i] = g;
+        }
+    float ych[3][4];
+#pragma unroll
+    for (int ch = 0; ch < 3; ++ch) {
+#pragma unroll
+        for (int i = 0; i < 4; ++i) ych[ch][i] = 0.f;
+        float smax = 0.f;
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+            if (i < nv) smax = fmaxf(smax, fabsf((float)B(vb[i] + 3 + ch)));
+        if (!(smax > 0.f)) continue;
+        float sv[4], md = 0.f;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            sv[i] = 1.f;
+            if (i < nv) {
+                sv[i] = fmaxf(fabsf((float)B(vb[i] + 3 + ch)), o.sh_floor * smax);
+                md += sv[i] * Gm[i][i];
+            }
+        }
+        md /= (float)K;
+        const float mu = o.damp_sh * md + o.damp_abs * abs_scale;
+        float A[4][4], rhs[4], y[4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+#pragma unroll
+            for (int j = 0; j < 4; ++j) A[i][j] = Gm[i][j] + (i == j ? mu / sv[i] : 0.f);
+            rhs[i] = i < nv ? -(float)B(vb[i] + ch) / sv[i] : 0.f;
+        }
+        if (chol_solve_v<4, float>(nv, A, rhs, y)) {
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+                if (i < nv) ych[ch][i] = y[i];
+        }
+    }
+    float dsh[3][16];
+#pragma unroll
+    for (int ch = 0; ch < 3; ++ch)
+#pragma unroll
+        for (int a = 0; a < 16; ++a) dsh[ch][a] = 0.f;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        if (i < nv)
+            sh_basis_visit<float>(K, (float)B(vb[i] + 6), (float)B(vb[i] + 7), (float)B(vb[i] + 8), [&](int a, float ya) {
+#pragma unroll
+                for (int ch = 0; ch < 3; ++ch) dsh[ch][a] += ya * ych[ch][i];
+            });
+    }
+#pragma unroll
+    for (int ch = 0; ch < 3; ++ch) {
+        float nn = 0.f;
+#pragma unroll
+        for (int a = 0; a < 16; ++a) {
+            dsh[ch][a] *= o.step_frac;
+            nn += dsh[ch][a] * dsh[ch][a];
+        }
+        nn = sqrtf(nn);
+        const float f = nn > o.trust_sh && nn > 0.f ? o.trust_sh / nn : 1.f;
+#pragma unroll
+        for (int a = 0; a < 16; ++a)
+            if (a < K) st[(GSN_STEP_BASE + ch * K + a) * N + k] = dsh[ch][a] * f;
+    }
+}
+
+__device__ void clamp_norm_f(int n, float* x, float radius) {
+    float nn = 0.f;
+    for (int i = 0; i < n; ++i) nn += x[i] * x[i];
+    nn = sqrtf(nn);
+    if (nn > radius && nn > 0.f)
+        for (int i = 0; i < n; ++i) x[i] *= radius / nn;
+}
+
+// The local solves of kernel k in the mixed form.
+__device__ __forceinline__ void solve_one_mixed(int k, const float* __restrict__ pos, const float* __restrict__ rot,
+                                                const float* __restrict__ scale, const float* __restrict__ opac,
+                                                int n, int K, const DevCam& c, float kappa,
+                                                const float* __restrict__ blk, int V, const gsn_solve_opts& o,
+                                                const float* __restrict__ gram, float* __restrict__ st,
+                                                int32_t* __restrict__ fl, unsigned long long* __restrict__ n_fp64) {
+    const size_t N = (size_t)n;
+    const int NS = GSN_STEP_BASE + 3 * K;
+    auto Bf = [&](int row) { return blk[(size_t)row * N + k]; };
+    if (!(Bf(29) > 0.f)) {
+        for (int r = 0; r < NS; ++r) st[(size_t)r * N + k] = 0.f;
+        for (int r = 0; r < 5; ++r) fl[(size_t)r * N + k] = -2;
+        return;
+    }
+    const float abs_scale = 1.0f / (3.0f * (float)o.npix_primary);
+    float s[3];
+    for (int a = 0; a < 3; ++a) s[a] = scale[a * N + k];
+    ReducedT<float> R;
+    reduce_systems(pos, rot, scale, opac, n, k, c, kappa, Bf, o, abs_scale, R);
+    for (int a = 0; a < 3; ++a) st[(4 + a) * N + k] = R.r[a];
+    bool redo_p = false, redo_r = false;
+    // ---- position, rotation: FP32, and FP64 where the pivots flag ill-conditioning
+    float dv[2], th;
+    int jp = damped_small(2, R.Hp, R.gp, o, abs_scale, dv, &redo_p);
+    int jr = damped_small(1, &R.Ht, &R.gt, o, abs_scale, &th, &redo_r);
+    if (redo_p || redo_r) {
+        auto Bd = [&](int row) { return (double)blk[(size_t)row * N + k]; };
+        Reduced Rd;
+        const double abs_d = 1.0 / (3.0 * (double)o.npix_primary);
+        reduce_systems(pos, rot, scale, opac, n, k, c, kappa, Bd, o, abs_d, Rd);
+        if (redo_p) {
+            double d[2];
+            jp = damped_small(2, Rd.Hp, Rd.gp, o, abs_d, d);
+            dv[0] = (float)d[0];
+            dv[1] = (float)d[1];
+            for (int a = 0; a < 3; ++a) {
+                R.ux[a] = (float)Rd.ux[a];
+                R.uy[a] = (float)Rd.uy[a];
+            }
+        }
+        if (redo_r) {
+            double d;
+            jr = damped_small(1, &Rd.Ht, &Rd.gt, o, abs_d, &d);
+            th = (float)d;
+        }
+        if (n_fp64) atomicAdd(n_fp64, 1ull);
+    }
+    fl[0 * N + k] = jp;
+    for (int a = 0; a < 2; ++a) dv[a] *= o.step_frac;
+    clamp_norm_f(2, dv, o.trust_pos * fmaxf(s[0], fmaxf(s[1], s[2])));
+    for (int a = 0; a < 3; ++a) st[(size_t)a * N + k] = R.ux[a] * dv[0] + R.uy[a] * dv[1];
+    fl[1 * N + k] = jr;
+    th *= o.step_frac;
+    clamp_norm_f(1, &th, o.trust_rot);
+    st[3 * N + k] = th;
+    // ---- scaling and opacity in FP32
+    {
+        float av[2];
+        fl[2 * N + k] = damped_small(2, R.Hs, R.gs, o, abs_scale, av);
+        for (int a = 0; a < 2; ++a) av[a] *= o.step_frac;
+        float dsv[3];
+        for (int a = 0; a < 3; ++a) dsv[a] = R.T_[0][a] * av[0] + R.T_[1][a] * av[1];
+        clamp_norm_f(3, dsv, o.trust_scale * sqrtf(s[0] * s[0] + s[1] * s[1] + s[2] * s[2]));
+        for (int a = 0; a < 3; ++a) st[(7 + a) * N + k] = dsv[a];
+    }
+    {
+        float ds;
+        fl[3 * N + k] = damped_small(1, &R.Ho, &R.go, o, abs_scale, &ds);
+        st[10 * N + k] = o.step_frac * ds;
+    }
+    colour_solve_mixed(K, V, Bf, gram, o, abs_scale, st, N, k, fl, blk);
+}
+
+__global__ __launch_bounds__(128) void solve_mixed_kernel(const float* __restrict__ pos, const float* __restrict__ rot,
+                                                           const float* __restrict__ scale,
+                                                           const float* __restrict__ opac, int n, int K, DevCam c,
+                                                           float kappa, const float* __restrict__ blk, int V,
+                                                           gsn_solve_opts o, const float* __restrict__ gram,
+                                                           float* __restrict__ st, int32_t* __restrict__ fl,
+                                                           unsigned long long* __restrict__ n_fp64) {
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= n) return;
+    solve_one_mixed(k, pos, rot, scale, opac, n, K, c, kappa, blk, V, o, gram, st, fl, n_fp64);
 }
 
 template <int VM>
@@ -382,6 +654,21 @@ static void launch_batched_block(const SolveScene* d_scenes, int count, long lon
         solve_batched_kernel<4, BLOCK><<<grid, BLOCK, 0, s>>>(d_scenes, count, total);
     else
         solve_batched_kernel<9, BLOCK><<<grid, BLOCK, 0, s>>>(d_scenes, count, total);
+}
+
+void launch_sh_gram(const float* blk, int n, int K, int V, float* gram, hipStream_t s) {
+    if (n == 0) return;
+    const int waves = (n + 15) / 16;
+    sh_gram_kernel<<<(waves + 3) / 4, 256, 0, s>>>(blk, n, K, V, gram);
+}
+
+void launch_solve_mixed(const gsn_gaussians& g, const DevCam& cam, float kappa, const gsn_blocks& b,
+                        const gsn_solve_opts& o, const float* gram, const gsn_steps& st, unsigned long long* n_fp64,
+                        hipStream_t s) {
+    if (g.n == 0) return;
+    const int K = (g.sh_degree + 1) * (g.sh_degree + 1);
+    solve_mixed_kernel<<<(g.n + 127) / 128, 128, 0, s>>>(g.d_pos, g.d_rot, g.d_scale, g.d_opac, g.n, K, cam, kappa,
+                                                         b.d_data, b.n_views, o, gram, st.d_data, st.d_flags, n_fp64);
 }
 
 void launch_solve_batched(const SolveScene* d_scenes, int count, long long total, int max_views, int block,

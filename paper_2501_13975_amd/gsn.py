@@ -45,6 +45,7 @@ def lib():
             "gsn_apply_step": [P, P, P, P, P, ctypes.c_uint32],
             "gsn_step_features": [P, P, P, P, P, P, P],
             "gsn_solve_batched": [P, P, ctypes.c_int32],
+            "gsn_sh_gram": [P, P, ctypes.c_int32, P],
             "gsn_solve_tune": [P, P, ctypes.c_int32, P, P],
             "gsn_solve_graph_create": [P, P, ctypes.c_int32, ctypes.POINTER(P)],
             "gsn_graph_launch": [P, P], "gsn_graph_destroy": [P, P],
@@ -105,7 +106,8 @@ class CSolveOpts(ctypes.Structure):
                 ("sh_floor", ctypes.c_float), ("scale_floor", ctypes.c_float), ("opac_ftb", ctypes.c_float),
                 ("npix_primary", ctypes.c_int32), ("kappa", ctypes.c_float), ("trust_pos", ctypes.c_float),
                 ("trust_rot", ctypes.c_float), ("trust_scale", ctypes.c_float), ("trust_sh", ctypes.c_float),
-                ("opac_eps", ctypes.c_float), ("step_frac", ctypes.c_float), ("damp_sh", ctypes.c_float)]
+                ("opac_eps", ctypes.c_float), ("step_frac", ctypes.c_float), ("damp_sh", ctypes.c_float),
+                ("precision", ctypes.c_int32)]
 
 
 class CBlocks(ctypes.Structure):
@@ -128,10 +130,12 @@ def loss_opts(lambda_ssim=0.2, weight=1.0, keep_zstats=False):
 
 def solve_opts(npix_primary, kappa=0.3, damp_rel=1e-3, damp_abs=1e-12, pivot_min=1e-3, max_escalations=7,
                barrier_beta=1e-2, sh_floor=1e-3, scale_floor=0.1, opac_ftb=0.995, trust_pos=2.0, trust_rot=0.5,
-               trust_scale=0.5, trust_sh=1.0, opac_eps=1e-6, step_frac=1.0, damp_sh=1e-3):
+               trust_scale=0.5, trust_sh=1.0, opac_eps=1e-6, step_frac=1.0, damp_sh=1e-3, precision=0):
+    """precision 0: plain form; 1: mixed form (BF16 matrix-core colour Grams, FP32 solves, FP64 for
+    ill-conditioned position and rotation systems)."""
     return CSolveOpts(damp_rel, damp_abs, pivot_min, max_escalations, barrier_beta, sh_floor, scale_floor,
                       opac_ftb, int(npix_primary), kappa, trust_pos, trust_rot, trust_scale, trust_sh, opac_eps,
-                      step_frac, damp_sh)
+                      step_frac, damp_sh, int(precision))
 
 
 def camera(c) -> CCamera:
@@ -291,6 +295,11 @@ class Context:
                                 ctypes.addressof(so), ctypes.addressof(cs))
         return arr, keep
 
+    def sh_gram(self, blocks: "Blocks", sh_degree, out):
+        """out: device float [10, n]."""
+        cb = blocks.c()
+        self._check(lib().gsn_sh_gram(self.h, ctypes.byref(cb), int(sh_degree), _ptr(out)))
+
     def solve_batched(self, items):
         arr, keep = self._items(items)
         self._check(lib().gsn_solve_batched(self.h, arr, len(items)))
@@ -333,7 +342,7 @@ class Context:
                                              ctypes.byref(a), _ptr(loss), _ptr(grad)))
 
     STAGES = ("project", "sort", "raster_fwd", "loss", "raster_bwd", "chain", "solve", "apply")
-    COUNTERS = ("fwd_evals", "bwd_evals", "bwd_active", "pairs", "partials", "fwd_staged")
+    COUNTERS = ("fwd_evals", "bwd_evals", "bwd_active", "pairs", "partials", "fwd_staged", "fp64_solves")
 
     def profile_enable(self, on=True):
         self._check(lib().gsn_profile_enable(self.h, int(bool(on))))
