@@ -260,6 +260,20 @@ def gpu_run(args):
     return elapsed, stages, counts, cfg, learned, quality, batched
 
 
+def _measured_traffic(kernel):
+    """HBM bytes per launch of `kernel` from the committed counter summary, or None when the
+    kernel's source changed since the counters were taken."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", f"{kernel}_c2_traffic.txt")
+    if not os.path.exists(path):
+        return None
+    d = json.loads(open(path).read())
+    src = b"".join(open(os.path.join(ROOT, f), "rb").read() for f in d["sources"])
+    if hashlib.sha256(src).hexdigest() != d["source_sha256"]:
+        return None
+    return d["fetch_bytes_per_launch"] + d["write_bytes_per_launch"]
+
+
 def roofline(stages, counts, steps, pixels_per_step):
     """Roofline figure of the stage that takes the most time (one kernel per stage launch)."""
     dom = max(stages, key=lambda s: stages[s][0])
@@ -278,7 +292,7 @@ def roofline(stages, counts, steps, pixels_per_step):
             flops = FLOP_EVAL * counts["fwd_evals"] + FLOP_FWD_BLEND * counts["bwd_active"]
         achieved = flops / launches / per_launch_s / 1e12
         out.update(bound="alu", achieved=round(achieved, 3), peak=PEAK_ALU_TFLOPS, unit="TFLOP/s",
-                   frac=round(achieved / PEAK_ALU_TFLOPS, 5), traffic=None,
+                   frac=round(achieved / PEAK_ALU_TFLOPS, 5), traffic=_measured_traffic(dom),
                    algorithmic_flops_per_launch=round(flops / launches))
         return out
     # sort/bin: 28 algorithmic bytes per (tile, kernel) pair (write key/value, read per tile, write list)
