@@ -322,7 +322,7 @@ gsn_status gsn_render(gsn_ctx* ctx, const gsn_gaussians* g, const gsn_camera* ca
         StageTimer st_(ctx, GSN_STAGE_SORT);
         launch_fill_u32(bp<uint32_t>(f->flags), 0u, (pp + 3) / 4, s);
         launch_fill_u32(bp<uint32_t>(f->kflag), 0u, (nn + 3) / 4, s);
-        launch_emit_pairs(bp<uint32_t>(f->ids_a), bp<uint32_t>(f->offsets), (uint32_t)n, bp<uint2>(f->rect),
+        launch_emit_pairs(bp<uint32_t>(f->ids_a), bp<uint32_t>(f->offsets), (uint32_t)n, P, bp<uint2>(f->rect),
                           (uint32_t)f->tiles_x, bp<uint32_t>(f->pk_a), bp<uint32_t>(f->pv_a),
                           bp<uint32_t>(f->pair_off), s);
         int tile_bits = 1;

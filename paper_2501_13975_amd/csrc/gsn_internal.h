@@ -107,8 +107,9 @@ size_t scan_tmp_bytes(uint32_t n);
 hipError_t exclusive_scan_u32(const uint32_t* in, uint32_t* out, uint32_t n, uint32_t* d_total,
                               DevBuf& scan_tmp, hipStream_t s);
 void launch_gather_u32(const uint32_t* src, const uint32_t* idx, uint32_t* dst, uint32_t n, hipStream_t s);
-void launch_emit_pairs(const uint32_t* sorted_ids, const uint32_t* offsets, uint32_t n, const uint2* rect,
-                       uint32_t tiles_x, uint32_t* keys, uint32_t* vals, uint32_t* pair_off, hipStream_t s);
+void launch_emit_pairs(const uint32_t* sorted_ids, const uint32_t* offsets, uint32_t n, uint32_t pairs,
+                       const uint2* rect, uint32_t tiles_x, uint32_t* keys, uint32_t* vals, uint32_t* pair_off,
+                       hipStream_t s);
 void launch_tile_ranges(const uint32_t* keys, uint32_t pairs, uint2* ranges, hipStream_t s);
 void launch_raster_fwd(const uint2* ranges, const uint32_t* ids, const float4* rec, uint32_t n, const DevCam& cam,
                        const DevRenderOpts& ro, float* img, double* img64, float* Tfin, uint32_t* ncontrib,

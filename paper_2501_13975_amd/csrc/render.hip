@@ -44,7 +44,7 @@ struct BinOut {
     bool vis;
 };
 
-__device__ __noinline__ BinOut bin_spec(float px, float py, float pz, float qw, float qx, float qy, float qz,
+__device__ __forceinline__ BinOut bin_spec(float px, float py, float pz, float qw, float qx, float qy, float qz,
                                         float s0, float s1, float s2, const DevCam& c, float kappa, float rsig) {
 #pragma clang fp contract(off)
     BinOut b;
@@ -295,15 +295,37 @@ __global__ __launch_bounds__(kThreads) void radix_hist_kernel(const uint32_t* __
     hist[(size_t)threadIdx.x * nb + blockIdx.x] = cnt[threadIdx.x];
 }
 
+// Stable scatter of one 8-bit digit pass.  The tile's items are first ranked within their digit
+// (ballot peers per wave, running counts per digit) and placed in LDS in digit order; the
+// second pass writes them out by LDS position, so that consecutive threads write consecutive
+// addresses of one digit's run (coalesced), instead of scattering item by item.
 __global__ __launch_bounds__(kThreads) void radix_scatter_kernel(
     const uint32_t* __restrict__ kin, const uint32_t* __restrict__ vin, uint32_t n, int shift, uint32_t nb,
-    const uint32_t* __restrict__ offs, uint32_t* __restrict__ kout, uint32_t* __restrict__ vout) {
-    __shared__ uint32_t base_d[256];
-    __shared__ uint32_t running[256];
+    const uint32_t* __restrict__ hist, const uint32_t* __restrict__ offs, uint32_t* __restrict__ kout,
+    uint32_t* __restrict__ vout) {
+    __shared__ uint32_t base_d[256], lstart[256], running[256];
     __shared__ uint32_t wcnt[kThreads / 64][256];
+    __shared__ uint32_t wsum[kThreads / 64];
+    __shared__ uint32_t sk[kRsTile], sv[kRsTile];
     const int tid = threadIdx.x, lane = __lane_id(), wave = tid / 64;
     base_d[tid] = offs[(size_t)tid * nb + blockIdx.x];
     running[tid] = 0;
+    {
+        // local start of each digit: exclusive scan of the tile's digit counts
+        const uint32_t c = hist[(size_t)tid * nb + blockIdx.x];
+        uint32_t v = c;
+#pragma unroll
+        for (int d = 1; d < 64; d <<= 1) {
+            const uint32_t o = __shfl_up(v, d, 64);
+            if (lane >= d) v += o;
+        }
+        if (lane == 63) wsum[wave] = v;
+        __syncthreads();
+        uint32_t sb = 0;
+#pragma unroll
+        for (int w = 0; w < kThreads / 64; ++w) sb += w < wave ? wsum[w] : 0u;
+        lstart[tid] = sb + v - c;
+    }
     const uint64_t lt_mask = (lane == 0) ? 0ull : ((~0ull) >> (64 - lane));
     const size_t base = (size_t)blockIdx.x * kRsTile;
     for (int it = 0; it < kRsItems; ++it) {
@@ -327,10 +349,10 @@ __global__ __launch_bounds__(kThreads) void radix_scatter_kernel(
         if (valid && rank == 0) wcnt[wave][d] = __popcll(peers);
         __syncthreads();
         if (valid) {
-            uint32_t pos = base_d[d] + running[d] + rank;
+            uint32_t pos = lstart[d] + running[d] + rank;
             for (int w = 0; w < wave; ++w) pos += wcnt[w][d];
-            kout[pos] = key;
-            vout[pos] = val;
+            sk[pos] = key;
+            sv[pos] = val;
         }
         __syncthreads();
         uint32_t add = 0;
@@ -338,6 +360,14 @@ __global__ __launch_bounds__(kThreads) void radix_scatter_kernel(
         for (int w = 0; w < kThreads / 64; ++w) add += wcnt[w][tid];
         running[tid] += add;
         __syncthreads();
+    }
+    const uint32_t cnt = (uint32_t)min((size_t)kRsTile, (size_t)n - base);
+    for (uint32_t j = tid; j < cnt; j += kThreads) {
+        const uint32_t key = sk[j];
+        const uint32_t d = (key >> shift) & 255u;
+        const uint32_t gpos = base_d[d] + (j - lstart[d]);
+        kout[gpos] = key;
+        vout[gpos] = sv[j];
     }
 }
 
@@ -349,23 +379,64 @@ __global__ void gather_u32_kernel(const uint32_t* __restrict__ src, const uint32
 
 // One thread per depth rank: writes the kernel's (tile, id) pairs, row-major
 // over its rectangle, at its scanned offset.
-__global__ void emit_pairs_kernel(const uint32_t* __restrict__ sorted_ids, const uint32_t* __restrict__ offsets,
-                                  uint32_t n, const uint2* __restrict__ rect, uint32_t tiles_x,
-                                  uint32_t* __restrict__ keys, uint32_t* __restrict__ vals,
-                                  uint32_t* __restrict__ pair_off) {
+// Each kernel's slot range: pair_off[id] = offsets[depth rank].
+__global__ void pair_off_kernel(const uint32_t* __restrict__ sorted_ids, const uint32_t* __restrict__ offsets,
+                                uint32_t n, uint32_t* __restrict__ pair_off) {
     const uint32_t r = blockIdx.x * blockDim.x + threadIdx.x;
-    if (r >= n) return;
-    const uint32_t id = sorted_ids[r];
-    const uint32_t off = offsets[r];
-    pair_off[id] = off;
-    const uint2 rc = rect[id];
-    const uint32_t x0 = rc.x & 0xffffu, y0 = rc.x >> 16, x1 = rc.y & 0xffffu, y1 = rc.y >> 16;
-    uint32_t i = off;
-    for (uint32_t ty = y0; ty < y1; ++ty)
-        for (uint32_t tx = x0; tx < x1; ++tx, ++i) {
-            keys[i] = ty * tiles_x + tx;
-            vals[i] = id;
+    if (r < n) pair_off[sorted_ids[r]] = offsets[r];
+}
+
+// Pairs in depth order, emitted by contiguous chunks of kEmitChunk pair slots per workgroup so
+// that the writes are coalesced: the workgroup stages the (few) kernels whose ranges meet its
+// chunk, and each thread finds the kernel of its slot by binary search over their offsets.
+// Kernel r (depth rank) owns slots [offsets[r], offsets[r] + ntiles) in row-major tile order.
+constexpr int kEmitChunk = 2048;
+
+__global__ __launch_bounds__(kThreads) void emit_pairs_kernel(const uint32_t* __restrict__ sorted_ids,
+                                                               const uint32_t* __restrict__ offsets, uint32_t n,
+                                                               uint32_t pairs, const uint2* __restrict__ rect,
+                                                               uint32_t tiles_x, uint32_t* __restrict__ keys,
+                                                               uint32_t* __restrict__ vals) {
+    __shared__ uint32_t s_off[kEmitChunk], s_id[kEmitChunk];
+    __shared__ uint2 s_rect[kEmitChunk];
+    __shared__ uint32_t s_r0, s_cnt;
+    const uint32_t p0 = blockIdx.x * (uint32_t)kEmitChunk;
+    const uint32_t p1 = min(pairs, p0 + (uint32_t)kEmitChunk);
+    if (threadIdx.x == 0) {
+        // last rank whose range starts at or before p (offsets are non-decreasing, offsets[0] = 0)
+        auto last_le = [&](uint32_t p) {
+            uint32_t lo = 0, hi = n - 1;
+            while (lo < hi) {
+                const uint32_t mid = (lo + hi + 1) >> 1;
+                if (offsets[mid] <= p) lo = mid; else hi = mid - 1;
+            }
+            return lo;
+        };
+        const uint32_t r0 = last_le(p0), r1 = last_le(p1 - 1);
+        s_r0 = r0;
+        s_cnt = r1 - r0 + 1;  // kernels with pairs own distinct offsets: at most kEmitChunk of them
+    }
+    __syncthreads();
+    const uint32_t r0 = s_r0, cnt = s_cnt;
+    for (uint32_t j = threadIdx.x; j < cnt; j += blockDim.x) {
+        const uint32_t id = sorted_ids[r0 + j];
+        s_off[j] = offsets[r0 + j];
+        s_id[j] = id;
+        s_rect[j] = rect[id];
+    }
+    __syncthreads();
+    for (uint32_t p = p0 + threadIdx.x; p < p1; p += blockDim.x) {
+        uint32_t lo = 0, hi = cnt - 1;
+        while (lo < hi) {
+            const uint32_t mid = (lo + hi + 1) >> 1;
+            if (s_off[mid] <= p) lo = mid; else hi = mid - 1;
         }
+        const uint2 rc = s_rect[lo];
+        const uint32_t x0 = rc.x & 0xffffu, y0 = rc.x >> 16, x1 = rc.y & 0xffffu;
+        const uint32_t w = x1 - x0, i = p - s_off[lo];
+        keys[p] = (y0 + i / w) * tiles_x + x0 + i % w;
+        vals[p] = s_id[lo];
+    }
 }
 
 __global__ void tile_ranges_kernel(const uint32_t* __restrict__ keys, uint32_t pairs, uint2* __restrict__ ranges) {
@@ -547,7 +618,7 @@ hipError_t radix_sort_pairs(uint32_t* k0, uint32_t* v0, uint32_t* k1, uint32_t* 
         radix_hist_kernel<<<nb, kThreads, 0, s>>>(ka, n, shift, nb, h);
         e = exclusive_scan_u32(h, o, 256 * nb, nullptr, scan_tmp, s);
         if (e != hipSuccess) return e;
-        radix_scatter_kernel<<<nb, kThreads, 0, s>>>(ka, va, n, shift, nb, o, kb, vb);
+        radix_scatter_kernel<<<nb, kThreads, 0, s>>>(ka, va, n, shift, nb, h, o, kb, vb);
         uint32_t* t = ka; ka = kb; kb = t;
         t = va; va = vb; vb = t;
     }
@@ -563,10 +634,14 @@ void launch_gather_u32(const uint32_t* src, const uint32_t* idx, uint32_t* dst, 
     if (n) gather_u32_kernel<<<(n + kThreads - 1) / kThreads, kThreads, 0, s>>>(src, idx, dst, n);
 }
 
-void launch_emit_pairs(const uint32_t* sorted_ids, const uint32_t* offsets, uint32_t n, const uint2* rect,
-                       uint32_t tiles_x, uint32_t* keys, uint32_t* vals, uint32_t* pair_off, hipStream_t s) {
-    if (n) emit_pairs_kernel<<<(n + kThreads - 1) / kThreads, kThreads, 0, s>>>(sorted_ids, offsets, n, rect, tiles_x,
-                                                                               keys, vals, pair_off);
+void launch_emit_pairs(const uint32_t* sorted_ids, const uint32_t* offsets, uint32_t n, uint32_t pairs,
+                       const uint2* rect, uint32_t tiles_x, uint32_t* keys, uint32_t* vals, uint32_t* pair_off,
+                       hipStream_t s) {
+    if (n == 0) return;
+    pair_off_kernel<<<(n + kThreads - 1) / kThreads, kThreads, 0, s>>>(sorted_ids, offsets, n, pair_off);
+    if (pairs)
+        emit_pairs_kernel<<<(pairs + kEmitChunk - 1) / kEmitChunk, kThreads, 0, s>>>(sorted_ids, offsets, n, pairs,
+                                                                                    rect, tiles_x, keys, vals);
 }
 
 void launch_tile_ranges(const uint32_t* keys, uint32_t pairs, uint2* ranges, hipStream_t s) {
