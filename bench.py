@@ -77,15 +77,17 @@ def _targets(cfg, dev):
     return targets
 
 
-def _trainer(cfg, targets, dev, learned_every=0, step_frac=1.0):
+def _trainer(cfg, targets, dev, learned_every=0, step_frac=1.0, n_secondary=None, gauss_newton=False):
     """The plain form (FP64 small solves), or with learned_every the mixed + learned form (BF16
-    matrix-core colour Grams, FP32 solves with FP64 for flagged systems, learned step scale)."""
+    matrix-core colour Grams, FP32 solves with FP64 for flagged systems, learned step scale).
+    n_secondary overrides the workload's |N_t|; gauss_newton selects the local Gauss-Newton blocks."""
     from paper_2501_13975_amd import gsn
     from paper_2501_13975_amd.train import LocalNewtonTrainer
     from synth.mlp_init import init_params
     g = gsn.DeviceGaussians.from_host(cfg.init, dev)
     kw = {"step_frac": step_frac, "precision": 1 if learned_every else 0}
-    tr = LocalNewtonTrainer(g, cfg.cams, targets, n_secondary=cfg.n_secondary, solve_kw=kw)
+    K = cfg.n_secondary if n_secondary is None else n_secondary
+    tr = LocalNewtonTrainer(g, cfg.cams, targets, n_secondary=K, solve_kw=kw, gauss_newton=gauss_newton)
     if learned_every:
         tr.enable_learned(init_params(0), every=learned_every, lr=1e-2)
     return tr
@@ -113,6 +115,22 @@ def _timed(tr, order, warmup, steps, learned, dev):
     stages, counts = tr.ctx.profile_read()
     tr.ctx.profile_enable(False)
     return elapsed, stages, counts
+
+
+def _sweep_times(tr, order, start, n, learned, dev):
+    """Per-sweep wall times (ms) of n more sweeps, each synchronised: median and p10/p90."""
+    import numpy as np
+    import torch
+    ts = []
+    for i in range(n):
+        torch.cuda.synchronize(dev)
+        t0 = time.perf_counter()
+        _sweep(tr, int(order[start + i]), start + i, learned)
+        torch.cuda.synchronize(dev)
+        ts.append((time.perf_counter() - t0) * 1e3)
+    p10, p50, p90 = np.percentile(ts, [10, 50, 90])
+    return {"sweeps": n, "p10_ms": round(float(p10), 3), "median_ms": round(float(p50), 3),
+            "p90_ms": round(float(p90), 3)}
 
 
 def _psnr(tr, targets, dev):
@@ -176,6 +194,171 @@ def _equal_psnr(cfg, targets, dev, epochs, every, mask, step_frac):
     return out
 
 
+def _variant_rates(cfg, targets, dev, order, warmup, steps, step_frac):
+    """Sweep rate of the plain form on the benchmark workload with |N_t| = 0 and 8 secondaries
+    (Sec. 4.3) and with the local Gauss-Newton blocks at |N_t| = 3."""
+    out = {}
+    for name, K, gn in (("secondaries_0", 0, False), ("secondaries_8", 8, False), ("gauss_newton", None, True)):
+        tr = _trainer(cfg, targets, dev, 0, step_frac, n_secondary=K, gauss_newton=gn)
+        el, st, cn = _timed(tr, order, warmup, steps, False, dev)
+        tr.close()
+        out[name] = {"value": round(steps / el, 4), "unit": "sweeps/s", "ms_per_step": round(el * 1e3 / steps, 3),
+                     "stage_ms_per_step": {k: round(v[0] / steps, 3) for k, v in st.items()},
+                     "counts_per_step": {k: int(v / steps) for k, v in cn.items()}}
+        log(f"[bench] {name}: {steps / el:.2f} sweeps/s")
+    return out
+
+
+def _overshoot_leg(dev, epochs, mask, step_frac):
+    """|N_t| ablation and the Gauss-Newton variant on the 100k-kernel, 50-camera 1024x768 scene.
+
+    Overshoot at a view switch (Sec. 4.3): for every sweep on image t, the relative change of
+    the L2 loss of the image trained next (t') across the sweep, (L_t'(after) - L_t'(before)) /
+    L_t'(before); a spike is a sweep that raises it.  Also the primary's own relative change,
+    the mean PSNR over all views after the epochs and the seconds spent in sweeps."""
+    import numpy as np
+    import torch
+
+    from synth.scenes import make_config, view_order
+    cfg = make_config("c1")
+    targets = _targets(cfg, dev)
+    nv = len(cfg.cams)
+    out = {"workload": (f"{cfg.n} Gaussians SH3, {nv} cameras at {cfg.width}x{cfg.height}, "
+                        f"secondaries at half resolution"),
+           "epochs": epochs, "group_mask": mask, "step_frac": step_frac, "runs": {}}
+    for name, K, gn in (("secondaries_0", 0, False), ("secondaries_3", 3, False), ("secondaries_8", 8, False),
+                        ("gauss_newton_3", 3, True)):
+        tr = _trainer(cfg, targets, dev, 0, step_frac, n_secondary=K, gauss_newton=gn)
+        img = torch.empty_like(targets[0])
+
+        def l2(v):
+            tr.ctx.render(tr.g, tr.ccams[v], tr.ro, tr.frames[0], img)
+            return torch.mean((img - targets[v]) ** 2)
+
+        p0 = _psnr(tr, targets, dev)
+        rows, spent = [], 0.0
+        for e in range(epochs):
+            order = view_order(nv, e)
+            for i, t in enumerate(order):
+                t, nxt = int(t), int(order[(i + 1) % nv])
+                before = torch.stack([l2(t), l2(nxt)])
+                torch.cuda.synchronize(dev)
+                t0 = time.perf_counter()
+                tr.sweep(t, mask)
+                torch.cuda.synchronize(dev)
+                spent += time.perf_counter() - t0
+                rows.append(torch.cat([before, torch.stack([l2(t), l2(nxt)])]))
+        r = torch.stack(rows).double().cpu().numpy()
+        prim = (r[:, 2] - r[:, 0]) / r[:, 0]
+        nxt = (r[:, 3] - r[:, 1]) / r[:, 1]
+        psnr = _psnr(tr, targets, dev)
+        tr.close()
+        out["runs"][name] = {"secondaries": K, "gauss_newton": gn, "sweeps": len(r),
+                             "psnr_initial": round(p0, 4), "psnr_final": round(psnr, 4),
+                             "primary_rel_change_mean": round(float(prim.mean()), 6),
+                             "next_view_rel_change_mean": round(float(nxt.mean()), 6),
+                             "next_view_rel_change_p90": round(float(np.percentile(nxt, 90)), 6),
+                             "spike_fraction": round(float((nxt > 0).mean()), 4),
+                             "sweep_seconds": round(spent, 3)}
+        log(f"[bench] overshoot {name}: {out['runs'][name]}")
+    return out
+
+
+def _order_leg(dev, epochs, step_frac):
+    """Schedules and optimisation order on the 100k-kernel, 50-camera 1024x768 scene (Sec. 4.2,
+    Sec. 5): every group trained, for `epochs` epochs, by the jacobi sweep, by the series sweep
+    in the paper's order (position, rotation, scaling, opacity, colour) and by the series sweep
+    in the reverse order (colour first).  Mean PSNR over all views and seconds of sweeps."""
+    import torch
+
+    from synth.scenes import make_config, view_order
+    cfg = make_config("c1")
+    targets = _targets(cfg, dev)
+    nv = len(cfg.cams)
+    out = {"workload": f"{cfg.n} Gaussians SH3, {nv} cameras at {cfg.width}x{cfg.height}, 3 secondaries",
+           "epochs": epochs, "step_frac": step_frac, "runs": {}}
+    for name, order in (("jacobi", None), ("series_p_q_s_o_c", (1, 2, 4, 8, 16)),
+                        ("series_c_o_s_q_p", (16, 8, 4, 2, 1))):
+        tr = _trainer(cfg, targets, dev, 0, step_frac)
+        p0 = _psnr(tr, targets, dev)
+        spent, curve = 0.0, []
+        for e in range(epochs):
+            torch.cuda.synchronize(dev)
+            t0 = time.perf_counter()
+            for t in view_order(nv, e):
+                if order is None:
+                    tr.sweep(int(t), 31)
+                else:
+                    tr.sweep_series(int(t), order)
+            torch.cuda.synchronize(dev)
+            spent += time.perf_counter() - t0
+            curve.append(round(_psnr(tr, targets, dev), 4))
+        tr.close()
+        out["runs"][name] = {"psnr_initial": round(p0, 4), "psnr_per_epoch": curve, "sweep_seconds": round(spent, 3)}
+        log(f"[bench] order {name}: {out['runs'][name]}")
+    return out
+
+
+# Adam learning rates of the first-order baseline (position, rotation, linear scale, opacity, SH):
+# the usual 3DGS rates carried over to these parameterisations (log-scale 5e-3 at s ~ 0.02, logit
+# opacity 0.05 at sigma ~ 0.5).
+ADAM_LR = (1.6e-4, 1e-3, 1e-4, 1.25e-2, 2.5e-3)
+
+
+def _first_order_leg(dev, newton_epochs, max_epochs, mask, step_frac):
+    """Newton sweeps against Adam iterations on the same gradients, 100k-kernel scene (Sec. 1
+    and Sec. 5 claim far fewer Newton iterations than first-order ones).  The Newton form
+    (jacobi, 3 secondaries) trains `newton_epochs` epochs and sets the target PSNR; Adam (the
+    primary view's gradient, one image per iteration) runs with the learning rates ADAM_LR
+    scaled by 0.3, 1 and 3 until it reaches the target or `max_epochs` epochs."""
+    import torch
+
+    from synth.scenes import make_config, view_order
+    cfg = make_config("c1")
+    targets = _targets(cfg, dev)
+    nv = len(cfg.cams)
+    out = {"workload": f"{cfg.n} Gaussians SH3, {nv} cameras at {cfg.width}x{cfg.height}",
+           "group_mask": mask, "newton_step_frac": step_frac, "adam_lr": list(ADAM_LR)}
+    tr = _trainer(cfg, targets, dev, 0, step_frac)
+    out["psnr_initial"] = round(_psnr(tr, targets, dev), 4)
+    spent = 0.0
+    for e in range(newton_epochs):
+        torch.cuda.synchronize(dev)
+        t0 = time.perf_counter()
+        for t in view_order(nv, e):
+            tr.sweep(int(t), mask)
+        torch.cuda.synchronize(dev)
+        spent += time.perf_counter() - t0
+    target = _psnr(tr, targets, dev)
+    tr.close()
+    out["newton"] = {"sweeps": newton_epochs * nv, "psnr": round(target, 4), "seconds": round(spent, 3)}
+    runs = {}
+    for f in (0.3, 1.0, 3.0):
+        lr = [x * f for x in ADAM_LR]
+        tr = _trainer(cfg, targets, dev, 0, 1.0, n_secondary=0)
+        spent, curve, reached = 0.0, [], None
+        for e in range(max_epochs):
+            torch.cuda.synchronize(dev)
+            t0 = time.perf_counter()
+            for t in view_order(nv, e):
+                tr.sweep_first_order(int(t), lr, adam=True, group_mask=mask)
+            torch.cuda.synchronize(dev)
+            spent += time.perf_counter() - t0
+            p = _psnr(tr, targets, dev)
+            curve.append(round(p, 4))
+            if p >= target:
+                reached = (e + 1) * nv
+                break
+        tr.close()
+        runs[f"lr_x{f:g}"] = {"psnr_per_epoch": curve, "iterations_to_target": reached, "seconds": round(spent, 3)}
+        log(f"[bench] adam lr x{f:g}: {runs[f'lr_x{f:g}']}")
+    out["adam"] = runs
+    best = [r["iterations_to_target"] for r in runs.values() if r["iterations_to_target"]]
+    out["iterations_ratio"] = round(min(best) / out["newton"]["sweeps"], 3) if best else None
+    log(f"[bench] first-order vs Newton: {out}")
+    return out
+
+
 def _batched_solve_leg(dev, reps=20):
     """The eight scenes of 20k-800k kernels at 1280x720: blocks from one primary and three
     secondary views each, then the solves of all scenes timed as one launch per scene, as
@@ -234,9 +417,10 @@ def gpu_run(args):
     log(f"[bench] generated {args.config}: {cfg.n} kernels, {len(cfg.cams)} cameras ({time.time() - t0:.1f}s)")
     targets = _targets(cfg, dev)
     log(f"[bench] rendered {len(targets)} targets ({time.time() - t0:.1f}s)")
-    order = np.concatenate([view_order(len(cfg.cams), e) for e in range(4)])
+    order = np.concatenate([view_order(len(cfg.cams), e) for e in range(8)])
     tr = _trainer(cfg, targets, dev, 0, args.step_frac)
     elapsed, stages, counts = _timed(tr, order, args.warmup, args.steps, False, dev)
+    dist = _sweep_times(tr, order, args.warmup + args.steps, 30, False, dev)
     tr.close()
     log(f"[bench] plain: {args.steps} sweeps in {elapsed:.3f}s; stage ms: "
         + ", ".join(f"{k}={v[0]:.1f}" for k, v in stages.items()))
@@ -249,6 +433,18 @@ def gpu_run(args):
                    "every": args.learned_every,
                    "stage_ms_per_step": {k: round(v[0] / args.steps, 3) for k, v in st2.items()}}
         log(f"[bench] learned: {args.steps} sweeps in {el2:.3f}s")
+    variants = None
+    if args.variants_leg:
+        variants = _variant_rates(cfg, targets, dev, order, args.warmup, args.steps, args.step_frac)
+    overshoot = None
+    if args.overshoot_epochs > 0:
+        overshoot = _overshoot_leg(dev, args.overshoot_epochs, args.quality_mask, args.quality_step_frac)
+    order_exp = None
+    if args.order_epochs > 0:
+        order_exp = _order_leg(dev, args.order_epochs, args.order_step_frac)
+    first_order = None
+    if args.first_order_epochs > 0:
+        first_order = _first_order_leg(dev, 1, args.first_order_epochs, args.quality_mask, args.quality_step_frac)
     batched = None
     if args.batched_leg:
         batched = _batched_solve_leg(dev)
@@ -257,7 +453,7 @@ def gpu_run(args):
     if args.quality_epochs > 0 and args.learned_every:
         quality = _equal_psnr(cfg, targets, dev, args.quality_epochs, args.learned_every, args.quality_mask,
                               args.quality_step_frac)
-    return elapsed, stages, counts, cfg, learned, quality, batched
+    return elapsed, stages, counts, cfg, learned, quality, batched, variants, overshoot, order_exp, first_order, dist
 
 
 def _measured_traffic(kernel):
@@ -350,8 +546,8 @@ def cpu_baseline(cfg, budget_s):
 def main():
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--steps", type=int, default=100)
+    ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--config", default="c2")
     ap.add_argument("--cpu-budget", type=float, default=20.0, help="seconds of oracle work for the CPU baseline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -369,12 +565,24 @@ def main():
     ap.add_argument("--quality-step-frac", type=float, default=0.3)
     ap.add_argument("--no-batched-leg", dest="batched_leg", action="store_false",
                     help="skip timing the batched solve of the eight 20k-800k scenes")
+    ap.add_argument("--no-variants-leg", dest="variants_leg", action="store_false",
+                    help="skip timing |N_t| = 0, 8 and the Gauss-Newton blocks on the benchmark workload")
+    ap.add_argument("--overshoot-epochs", type=int, default=1,
+                    help="epochs of the |N_t| / Gauss-Newton overshoot comparison on the 100k scene; 0 skips")
+    ap.add_argument("--order-epochs", type=int, default=1,
+                    help="epochs of the jacobi / series-order comparison on the 100k scene; 0 skips")
+    ap.add_argument("--order-step-frac", type=float, default=0.1,
+                    help="step fraction of the order comparison (it trains every group)")
+    ap.add_argument("--first-order-epochs", type=int, default=10,
+                    help="at most this many epochs of Adam against one epoch of Newton sweeps on the 100k "
+                         "scene; 0 skips")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU: this build runs the training step on a single MI355X "
               "(how it would shard across GPUs is described in DESIGN.md); run with --gpus 1", file=sys.stderr)
         sys.exit(2)
-    elapsed, stages, counts, cfg, learned, quality, batched = gpu_run(args)
+    (elapsed, stages, counts, cfg, learned, quality, batched, variants, overshoot, order_exp,
+     first_order, dist) = gpu_run(args)
     ms_per_step = elapsed * 1e3 / args.steps
     value = args.steps / elapsed
     pixels = cfg.width * cfg.height + cfg.n_secondary * (cfg.width // 2) * (cfg.height // 2)
@@ -393,6 +601,7 @@ def main():
                    "gaussians": cfg.n, "width": cfg.width, "height": cfg.height, "cameras": len(cfg.cams),
                    "secondaries": cfg.n_secondary, "form": "plain", "step_frac": args.step_frac},
         "gaussians_updated_per_s": round(value * cfg.n, 1),
+        "sweep_ms_distribution": dist,
         "stage_ms_per_step": {k: round(v[0] / args.steps, 3) for k, v in stages.items()},
         "counts_per_step": {k: int(v / args.steps) for k, v in counts.items()},
         "roofline": rl,
@@ -400,6 +609,10 @@ def main():
         "learned": learned,
         "equal_psnr": quality,
         "batched_solve": batched,
+        "variants": variants,
+        "overshoot": overshoot,
+        "schedule_order": order_exp,
+        "first_order": first_order,
     }
     print(json.dumps(out), flush=True)
 

@@ -77,12 +77,20 @@ typedef struct {
 
 /* Loss options (Sec. 4.2): L = L2 + lambda_ssim * L_S, with an 11x11 Gaussian
  * SSIM window (sigma 1.5).  weight multiplies this view's gradient and
- * Hessian before they are added to the blocks (1 for every target, Sec. 4.3). */
+ * Hessian before they are added to the blocks (1 for every target, Sec. 4.3).
+ * gauss_newton nonzero: local Gauss-Newton blocks, H = sum over pixels and
+ * channels of h dc/dy dc/dy^T; the terms of eq. local_hessian_gradient that
+ * multiply the loss gradient by second derivatives of the image (through the
+ * splat's alpha and through the projection) are left out, as the paper's
+ * discussion of the position-Hessian cost suggests (Sec. 6).  Gradients, the
+ * opacity and colour blocks (the image is linear in both) are unchanged;
+ * the other blocks are positive semidefinite wherever h >= 0. */
 typedef struct {
     float lambda_ssim;
     float weight;
     int32_t keep_zstats; /* nonzero: keep this view's per-kernel projected-space
                             statistics in the frame for gsn_frame_zstats */
+    int32_t gauss_newton;
 } gsn_loss_opts;
 
 /* Solve options.  Damping: Cholesky of H + mu_j I, mu_j = mu0 10^j for
@@ -221,6 +229,36 @@ gsn_status gsn_local_newton_solve(gsn_ctx* ctx, const gsn_gaussians* g, const gs
  * Errors: GSN_E_SHAPE (steps.n != g->n). */
 gsn_status gsn_apply_step(gsn_ctx* ctx, gsn_gaussians* g, const gsn_steps* steps,
                           const gsn_solve_opts* opts, const float* d_scale, uint32_t group_mask);
+
+/* First-order baseline on the same gradients (the comparison behind the paper's
+ * claims of fewer iterations than first-order training, Sec. 1 and Sec. 5).
+ * lr: learning rates of the groups position, rotation (left rotation vector,
+ * radians), scaling (linear scale), opacity, colour (SH coefficients).
+ * adam = 0: gradient descent x <- x - lr g.  adam = 1: Adam (Kingma and Ba,
+ * 2015) with moments beta1, beta2, eps and bias corrections for step count
+ * step >= 1. */
+typedef struct {
+    float lr[5];
+    float beta1, beta2, eps;
+    int32_t adam;
+    int32_t step;
+} gsn_first_order_opts;
+
+/* One first-order step for every kernel the primary view sees (blocks row 29 >
+ * 0), from the gradients in `blocks` (the SH gradient of channel ch is the sum
+ * over view slots of gamma_ch Y(r), with the basis of Sec. 4.2's colour
+ * paragraph), for the groups in group_mask (bits as gsn_apply_step).  Updates
+ * as gsn_apply_step: q <- exp(omega/2) q renormalised for the rotation step
+ * omega = -lr u; s <- max(s - lr u, scale_floor s); sigma clipped to
+ * [opac_eps, 1 - opac_eps] (scale_floor and opac_eps from `opts`).
+ * d_state: device float [2][10 + 3K][n] (first then second moments; entries
+ * per kernel position 3, omega 3, scale 3, opacity 1, colour [3][K]), owned by
+ * the caller and zeroed by it before step 1; may be NULL when adam = 0.
+ * Errors: GSN_E_SHAPE (blocks.n != g->n), GSN_E_INVALID (null state with
+ * adam = 1, step < 1, negative learning rate, beta outside [0, 1)). */
+gsn_status gsn_first_order_step(gsn_ctx* ctx, gsn_gaussians* g, const gsn_blocks* blocks,
+                                const gsn_solve_opts* opts, const gsn_first_order_opts* fo, float* d_state,
+                                uint32_t group_mask);
 
 /* The colour Gram matrices of the mixed form: for every kernel, B B^T over the
  * views that see it (coverage > 0, at most 4, in slot order), B the rows of the

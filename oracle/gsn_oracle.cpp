@@ -64,6 +64,7 @@ enum Opt {
     O_OPAC_EPS,      // applied opacity kept in [opac_eps, 1 - opac_eps]
     O_STEP_FRAC,     // every group's Newton step is multiplied by step_frac before the trust radii
     O_DAMP_SH,       // colour damping mu = damp_sh * mean diag(G) + damp_abs / (3 |I|)
+    O_GAUSS_NEWTON,  // 1 = local Gauss-Newton blocks: H = sum_ch h_ch J_ch J_ch^T (no dL_ch d2c_ch term)
     O_COUNT
 };
 
@@ -596,13 +597,16 @@ int orc_loss(int W, int H, const double* img, const double* tgt, double lambda, 
 // constant alpha_max.  Gradient and Hessian of the loss follow eq.
 // local_hessian_gradient with the per-pixel diagonal image Hessian h:
 //     g += sum_ch dL_ch dc_ch/dy,   H += sum_ch h_ch dc_ch/dy dc_ch/dy^T + dL_ch d2c_ch/dy2.
+// The local Gauss-Newton variant (the cheaper Hessian the paper's discussion of
+// the position-Hessian cost (Sec. 6) points to) keeps only the first term of H:
+// the image Hessian pulled back by the first derivatives of the image.
 // ---------------------------------------------------------------------------
 namespace {
 
 template <int N>
 void pixel_accum(const Jet<N> pi[2], const Jet<N> Q[3], const Jet<N>& sig, const Jet<N> ct[3], double x,
                  double y, double T, const double A[3], bool clamped, double amax, const double dL[3],
-                 const double hd[3], double* g, double* H) {
+                 const double hd[3], bool gauss_newton, double* g, double* H) {
     const Jet<N> dx = pi[0] - x, dy = pi[1] - y;
     const Jet<N> f = -0.5 * (Q[0] * dx * dx + Q[2] * dy * dy) - Q[1] * dx * dy;
     const Jet<N> a = clamped ? Jet<N>(amax) : sig * exp(f);
@@ -610,7 +614,8 @@ void pixel_accum(const Jet<N> pi[2], const Jet<N> Q[3], const Jet<N>& sig, const
         const Jet<N> c = T * (a * ct[ch] + (1.0 - a) * A[ch]);
         for (int i = 0; i < N; ++i) {
             g[i] += dL[ch] * c.g[i];
-            for (int j = 0; j < N; ++j) H[i * N + j] += hd[ch] * c.g[i] * c.g[j] + dL[ch] * c.h[i][j];
+            for (int j = 0; j < N; ++j)
+                H[i * N + j] += hd[ch] * c.g[i] * c.g[j] + (gauss_newton ? 0.0 : dL[ch] * c.h[i][j]);
         }
     }
 }
@@ -704,6 +709,7 @@ int orc_blocks(int n, int K, const double* pos, const double* rot, const double*
     const bool smooth = o[O_SMOOTH] != 0.0;
     const double kappa = smooth ? 0.0 : o[O_KAPPA];
     const double amax = o[O_ALPHA_MAX];
+    const bool gn = o[O_GAUSS_NEWTON] != 0.0;
     std::vector<int32_t> all;
     if (smooth) all = depth_order(rec);
 #pragma omp parallel for schedule(dynamic, 1)
@@ -753,10 +759,14 @@ int orc_blocks(int n, int K, const double* pos, const double* rot, const double*
         for_each_pixel_of(k, rec, c, o, tile_start, ids, rect, n, all, dL, hd,
                           [&](double x, double y, double T, const double* A, double alpha, bool clamped,
                               const double* dl, const double* hh) {
-                              pixel_accum<3>(PP.pi, PP.Q, sig3, PP.ct, x, y, T, A, clamped, amax, dl, hh, B + B_GP, B + B_HP);
-                              pixel_accum<3>(PW.pi, PW.Q, sig3, PW.ct, x, y, T, A, clamped, amax, dl, hh, B + B_GW, B + B_HW);
-                              pixel_accum<3>(PS.pi, PS.Q, sig3, PS.ct, x, y, T, A, clamped, amax, dl, hh, B + B_GS, B + B_HS);
-                              pixel_accum<1>(opi, oQ, osig, oct, x, y, T, A, clamped, amax, dl, hh, B + B_GO, B + B_HO);
+                              pixel_accum<3>(PP.pi, PP.Q, sig3, PP.ct, x, y, T, A, clamped, amax, dl, hh, gn,
+                                             B + B_GP, B + B_HP);
+                              pixel_accum<3>(PW.pi, PW.Q, sig3, PW.ct, x, y, T, A, clamped, amax, dl, hh, gn,
+                                             B + B_GW, B + B_HW);
+                              pixel_accum<3>(PS.pi, PS.Q, sig3, PS.ct, x, y, T, A, clamped, amax, dl, hh, gn,
+                                             B + B_GS, B + B_HS);
+                              pixel_accum<1>(opi, oQ, osig, oct, x, y, T, A, clamped, amax, dl, hh, gn,
+                                             B + B_GO, B + B_HO);
                               // colour: dc_ch/dc~_ch = alpha T, and c is linear in c~
                               for (int ch = 0; ch < 3; ++ch) {
                                   B[B_GAM + ch] += dl[ch] * alpha * T;
@@ -781,6 +791,7 @@ int orc_zstats(int n, int K, const double* pos, const double* rot, const double*
     const std::vector<Rec> rec = project_all(S, c, o);
     const bool smooth = o[O_SMOOTH] != 0.0;
     const double amax = o[O_ALPHA_MAX];
+    const bool gn = o[O_GAUSS_NEWTON] != 0.0;
     std::vector<int32_t> all;
     if (smooth) all = depth_order(rec);
     const int NZ = 9 + 81 + 1;
@@ -798,7 +809,7 @@ int orc_zstats(int n, int K, const double* pos, const double* rot, const double*
         for_each_pixel_of(k, rec, c, o, tile_start, ids, rect, n, all, dL, hd,
                           [&](double x, double y, double T, const double* A, double alpha, bool clamped,
                               const double* dl, const double* hh) {
-                              pixel_accum<9>(pi, Q, sig, ct, x, y, T, A, clamped, amax, dl, hh, Z, Z + 9);
+                              pixel_accum<9>(pi, Q, sig, ct, x, y, T, A, clamped, amax, dl, hh, gn, Z, Z + 9);
                               Z[90] += alpha * T;
                           });
     }

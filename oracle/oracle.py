@@ -26,13 +26,13 @@ LIB = os.path.join(HERE, "liboracle.so")
 O_NAMES = ["tile", "alpha_min", "alpha_max", "T_min", "kappa", "radius_sigma", "smooth",
            "bg_r", "bg_g", "bg_b", "lambda_ssim", "barrier_beta", "damp_rel", "damp_abs",
            "pivot_min", "max_esc", "sh_floor", "scale_floor", "opac_ftb", "npix_primary", "trust_pos",
-           "trust_rot", "trust_scale", "trust_sh", "opac_eps", "step_frac", "damp_sh"]
+           "trust_rot", "trust_scale", "trust_sh", "opac_eps", "step_frac", "damp_sh", "gauss_newton"]
 DEFAULTS = dict(tile=16, alpha_min=1.0 / 255.0, alpha_max=0.99, T_min=1e-4, kappa=0.3,
                 radius_sigma=3.0, smooth=0, bg_r=0.0, bg_g=0.0, bg_b=0.0, lambda_ssim=0.2,
                 barrier_beta=1e-2, damp_rel=1e-3, damp_abs=1e-12, pivot_min=1e-3, max_esc=7,
                 sh_floor=1e-3, scale_floor=0.1, opac_ftb=0.995, npix_primary=1.0, trust_pos=2.0,
                 trust_rot=0.5, trust_scale=0.5, trust_sh=1.0, opac_eps=1e-6, step_frac=1.0,
-                damp_sh=1e-3)
+                damp_sh=1e-3, gauss_newton=0)
 B_COUNT = 48
 NB_BASE, NB_VIEW = 39, 10
 
@@ -330,6 +330,18 @@ def sweep(g, cams, targets, t, knn_table=None, o=None, mask=31):
     new = apply(g64, steps, dec, o, mask)
     return dict(new=new, steps=steps, dec=dec, cond=cond, summed=summed, per_view=per_view,
                 losses=losses, frames=frames, opts=o)
+
+
+def sweep_series(g, cams, targets, t, knn_table=None, o=None, order=(1, 2, 4, 8, 16)):
+    """Series schedule (Sec. 4.2): one sweep per group mask in `order`, each linearised at the
+    state the previous groups left and applying only its own group.  Returns the final state
+    and the per-stage sweep results."""
+    stages = []
+    for m in order:
+        res = sweep(g, cams, targets, t, knn_table, o, m)
+        stages.append(res)
+        g = res["new"]
+    return g, stages
 
 
 def psnr(img, tgt):

@@ -10,7 +10,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libgsn.so")
-SOURCES = ["api.hip", "render.hip", "loss.hip", "backward.hip", "solve.hip", "learned.hip"]
+SOURCES = ["api.hip", "render.hip", "loss.hip", "backward.hip", "solve.hip", "learned.hip", "first_order.hip"]
 HEADERS = ["device_common.h", "gsn_internal.h", "chain.h", "reduced.h"]
 ARCH = os.environ.get("GSN_OFFLOAD_ARCH", "gfx950")
 

@@ -383,11 +383,12 @@ gsn_status gsn_accumulate_hessian(gsn_ctx* ctx, const gsn_gaussians* g, const gs
     }
     {
         StageTimer st_(ctx, GSN_STAGE_RASTER_BWD);
-        if (f->pairs > 0) launch_raster_bwd(*f, bp<float>(f->dL), bp<float>(f->hd), prof_counts(ctx), s);
+        if (f->pairs > 0)
+            launch_raster_bwd(*f, bp<float>(f->dL), bp<float>(f->hd), opts->gauss_newton != 0, prof_counts(ctx), s);
     }
     {
         StageTimer st_(ctx, GSN_STAGE_CHAIN);
-        launch_reduce_chain(*f, *g, opts->weight, view_slot, *b, zs, s);
+        launch_reduce_chain(*f, *g, opts->weight, view_slot, opts->gauss_newton != 0, *b, zs, s);
     }
     HIP_TRY(ctx, hipGetLastError());
     return GSN_OK;
@@ -644,6 +645,33 @@ gsn_status gsn_apply_step(gsn_ctx* ctx, gsn_gaussians* g, const gsn_steps* st, c
     HIP_TRY(ctx, hipSetDevice(ctx->device));
     StageTimer st_(ctx, GSN_STAGE_APPLY);
     launch_apply(*g, *st, *o, d_scale, group_mask, ctx->stream);
+    HIP_TRY(ctx, hipGetLastError());
+    return GSN_OK;
+}
+
+gsn_status gsn_first_order_step(gsn_ctx* ctx, gsn_gaussians* g, const gsn_blocks* b, const gsn_solve_opts* o,
+                                const gsn_first_order_opts* fo, float* d_state, uint32_t group_mask) {
+    if (!ctx || !b || !o || !fo) return fail(ctx, GSN_E_INVALID, "null argument");
+    gsn_status r = check_gaussians(ctx, g);
+    if (r != GSN_OK) return r;
+    if (b->n != g->n) return fail(ctx, GSN_E_SHAPE, "n mismatch");
+    if (b->n_views < 1 || b->n_views > 9) return fail(ctx, GSN_E_CAPACITY, "n_views %d not in 1..9", b->n_views);
+    if (g->n > 0 && !b->d_data) return fail(ctx, GSN_E_INVALID, "blocks data is NULL");
+    for (int i = 0; i < 5; ++i)
+        if (!(fo->lr[i] >= 0.f)) return fail(ctx, GSN_E_INVALID, "learning rates must be >= 0");
+    double c1 = 1.0, c2 = 1.0;
+    if (fo->adam) {
+        if (g->n > 0 && !d_state) return fail(ctx, GSN_E_INVALID, "Adam needs a moment buffer");
+        if (fo->step < 1) return fail(ctx, GSN_E_INVALID, "Adam step count must be >= 1");
+        if (!(fo->beta1 >= 0.f && fo->beta1 < 1.f && fo->beta2 >= 0.f && fo->beta2 < 1.f && fo->eps >= 0.f))
+            return fail(ctx, GSN_E_INVALID, "Adam moments out of range");
+        c1 = 1.0 / (1.0 - std::pow((double)fo->beta1, fo->step));
+        c2 = 1.0 / (1.0 - std::pow((double)fo->beta2, fo->step));
+    }
+    HIP_TRY(ctx, hipSetDevice(ctx->device));
+    StageTimer st_(ctx, GSN_STAGE_APPLY);
+    launch_first_order(*g, *b, *fo, (float)c1, (float)c2, o->scale_floor, o->opac_eps, fo->adam ? d_state : nullptr,
+                       group_mask, ctx->stream);
     HIP_TRY(ctx, hipGetLastError());
     return GSN_OK;
 }

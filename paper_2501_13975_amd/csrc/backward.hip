@@ -37,9 +37,11 @@
 namespace {
 
 constexpr int PMAX = 896;   // composited (pixel, entry) pairs staged per round
-constexpr int BIG = 16;     // entries with more pairs are summed by 16 lanes, others by 4
+constexpr int BIG = 16;     // entries with more pairs are summed by LG lanes, others by SG
+constexpr int SG = 8, LG = 32;
 
 // Contribution of one active (pixel, splat) pair to the 44 statistics (see the header comment).
+template <bool GN>
 __device__ __forceinline__ void pair_terms(const float4 a, const float4 b, float G, float T, const float av[3],
                                            float dx, float dy, const float dl[3], const float hh[3], float amax,
                                            float* z) {
@@ -61,7 +63,8 @@ __device__ __forceinline__ void pair_terms(const float4 a, const float4 b, float
     if (clamped) return;
     const float u[5] = {-q1 * dx, -q2 * dy, -0.5f * dx * dx, -dx * dy, -0.5f * dy * dy};
     const float k1 = A1 * sGraw;
-    const float k2 = A2 * sGraw * sGraw + k1;
+    // Gauss-Newton keeps only the h-weighted products of first derivatives: no k1 curvature terms
+    const float k2 = GN ? A2 * sGraw * sGraw : A2 * sGraw * sGraw + k1;
 #pragma unroll
     for (int i = 0; i < 5; ++i) z[i] = k1 * u[i];
     z[5] = A1 * G;
@@ -71,15 +74,17 @@ __device__ __forceinline__ void pair_terms(const float4 a, const float4 b, float
     for (int i = 0; i < 5; ++i)
 #pragma unroll
         for (int j = i; j < 5; ++j, ++idx) z[idx] = k2 * u[i] * u[j];
-    z[9 + 0] -= k1 * q1;  // (pi'_1, pi'_1)
-    z[9 + 2] -= k1 * dx;  // (pi'_1, Q'_11)
-    z[9 + 3] -= k1 * dy;  // (pi'_1, Q'_12)
-    z[9 + 5] -= k1 * q2;  // (pi'_2, pi'_2)
-    z[9 + 7] -= k1 * dx;  // (pi'_2, Q'_12)
-    z[9 + 8] -= k1 * dy;  // (pi'_2, Q'_22)
+    if (!GN) {
+        z[9 + 0] -= k1 * q1;  // (pi'_1, pi'_1)
+        z[9 + 2] -= k1 * dx;  // (pi'_1, Q'_11)
+        z[9 + 3] -= k1 * dy;  // (pi'_1, Q'_12)
+        z[9 + 5] -= k1 * q2;  // (pi'_2, pi'_2)
+        z[9 + 7] -= k1 * dx;  // (pi'_2, Q'_12)
+        z[9 + 8] -= k1 * dy;  // (pi'_2, Q'_22)
+    }
 #pragma unroll
     for (int ch = 0; ch < 3; ++ch) {
-        const float bch = sGraw * T * (hh[ch] * av[ch] * al + dl[ch]);
+        const float bch = sGraw * T * (GN ? hh[ch] * av[ch] * al : hh[ch] * av[ch] * al + dl[ch]);
 #pragma unroll
         for (int i = 0; i < 5; ++i) z[24 + i * 3 + ch] = bch * u[i];
     }
@@ -103,8 +108,20 @@ __device__ __forceinline__ float row_sum(float v) {
     v += dpp_mov<0x140>(v);  // row_mirror: the other half of the row
     return v;
 }
+// Sum over aligned groups of G lanes (G = 4, 8, 16, 32 or 64), left in every lane of the group.
+template <int G>
+__device__ __forceinline__ float group_sum(float v) {
+    if (G == 4) return quad_sum(v);
+    if (G == 8) return quad_sum(v) + dpp_mov<0x141>(quad_sum(v));
+    if (G == 16) return row_sum(v);
+    float r = row_sum(v);
+    r += __shfl_xor(r, 16, 64);
+    if (G == 64) r += __shfl_xor(r, 32, 64);
+    return r;
+}
 
 // Adds the statistics of staged pair i (slot in LDS) of the splat (a, b, c4) to acc.
+template <bool GN>
 __device__ __forceinline__ void pair_stats(const float4 a, const float4 b, const float4 cl, const float4* s_pa,
                                            const float* s_pb, const uint8_t* s_pix, const float (*s_dl)[GSN_BLOCK],
                                            const float (*s_h)[GSN_BLOCK], uint32_t i, int tx, int ty, float amax,
@@ -118,7 +135,7 @@ __device__ __forceinline__ void pair_stats(const float4 a, const float4 b, const
     const float ddy = (a.y - (float)(ty * GSN_TILE + (p / GSN_TILE))) + cl.w;
     const float d1 = b.x * ddx + b.y * ddy, d2 = b.x * ddy - b.y * ddx;
     float z[GSN_NZ];
-    pair_terms(a, b, pa.y, pa.x, av, d1, d2, dl, hh, amax, z);
+    pair_terms<GN>(a, b, pa.y, pa.x, av, d1, d2, dl, hh, amax, z);
 #pragma unroll
     for (int f = 0; f < GSN_NZ; ++f) acc[f] += z[f];
 }
@@ -144,9 +161,11 @@ __device__ __forceinline__ void write_partial(float* __restrict__ partial, uint8
 //  (c) every pixel walks its composited entries front to back (transmittance,
 //      colour behind the splat) and stores (T, G, a_R, a_G, a_B) in the pair's slot;
 //  (d) for every entry with pairs, the 44 statistics are summed over its pairs in a
-//      fixed order (4 lanes per entry, or 16 for an entry with more than BIG pairs)
+//      fixed order (SG lanes per entry, or LG for an entry with more than BIG pairs)
 //      and the tile's partial sum is written at the (tile, kernel) pair's slot.
 //      Only contributing pairs do the 44-term work.
+// GN: local Gauss-Newton statistics (no loss-gradient times image-curvature terms).
+template <bool GN>
 __global__ __launch_bounds__(GSN_BLOCK, 3) void raster_bwd_kernel(
     const uint2* __restrict__ ranges, const uint32_t* __restrict__ ids, const float4* __restrict__ rec,
     const uint2* __restrict__ rect, const uint32_t* __restrict__ pair_off, uint32_t n, DevCam cam, DevRenderOpts ro,
@@ -333,8 +352,8 @@ __global__ __launch_bounds__(GSN_BLOCK, 3) void raster_bwd_kernel(
                     T *= (1.0f - al);
                 }
             }
-            // (d) per-entry sums.  Entries of the round with 1..BIG pairs go to groups of 4 lanes, larger
-            // ones to groups of 16; a group sums its entry's pairs lane-strided and then across its lanes
+            // (d) per-entry sums.  Entries of the round with 1..BIG pairs go to groups of SG lanes, larger
+            // ones to groups of LG; a group sums its entry's pairs lane-strided and then across its lanes
             // with DPP row operations, so every sum is taken in one fixed order.
             const uint32_t pc = (tid >= r0 && tid < r1) ? s_off[(tid + 1) * NW] - s_off[tid * NW] : 0u;
             const bool small = pc > 0 && pc <= (uint32_t)BIG, large = pc > (uint32_t)BIG;
@@ -359,8 +378,8 @@ __global__ __launch_bounds__(GSN_BLOCK, 3) void raster_bwd_kernel(
             }
             __syncthreads();
             {
-                const int grp = tid / 4, r = tid % 4;
-                for (uint32_t k0 = 0; k0 < nsmall; k0 += GSN_BLOCK / 4) {  // uniform across the block
+                const int grp = tid / SG, r = tid % SG;
+                for (uint32_t k0 = 0; k0 < nsmall; k0 += GSN_BLOCK / SG) {  // uniform across the block
                     const uint32_t k = k0 + (uint32_t)grp;
                     float acc[GSN_NZ];
 #pragma unroll
@@ -369,12 +388,12 @@ __global__ __launch_bounds__(GSN_BLOCK, 3) void raster_bwd_kernel(
                     if (k < nsmall) {
                         e = s_act[k];
                         const uint32_t q0 = s_off[e * NW], q1 = s_off[(e + 1) * NW];
-                        for (uint32_t i = q0 + r; i < q1; i += 4)
-                            pair_stats(r_a[e], r_b[e], r_c[e], s_pa, s_pb, s_pix, s_dl, s_h, i, tx, ty, ro.alpha_max,
+                        for (uint32_t i = q0 + r; i < q1; i += SG)
+                            pair_stats<GN>(r_a[e], r_b[e], r_c[e], s_pa, s_pb, s_pix, s_dl, s_h, i, tx, ty, ro.alpha_max,
                                        acc);
                     }
 #pragma unroll
-                    for (int f = 0; f < GSN_NZ; ++f) acc[f] = quad_sum(acc[f]);
+                    for (int f = 0; f < GSN_NZ; ++f) acc[f] = group_sum<SG>(acc[f]);
                     if (k < nsmall && r == 0) {
                         write_partial(partial, flags, r_slot[e], acc);
                         kflag[r_id[e]] = 1;
@@ -383,8 +402,8 @@ __global__ __launch_bounds__(GSN_BLOCK, 3) void raster_bwd_kernel(
                 }
             }
             {
-                const int grp = tid / 16, r = tid % 16;
-                for (uint32_t k0 = 0; k0 < nlarge; k0 += GSN_BLOCK / 16) {  // uniform across the block
+                const int grp = tid / LG, r = tid % LG;
+                for (uint32_t k0 = 0; k0 < nlarge; k0 += GSN_BLOCK / LG) {  // uniform across the block
                     const uint32_t k = k0 + (uint32_t)grp;
                     float acc[GSN_NZ];
 #pragma unroll
@@ -393,12 +412,12 @@ __global__ __launch_bounds__(GSN_BLOCK, 3) void raster_bwd_kernel(
                     if (k < nlarge) {
                         e = s_big[k];
                         const uint32_t q0 = s_off[e * NW], q1 = s_off[(e + 1) * NW];
-                        for (uint32_t i = q0 + r; i < q1; i += 16)
-                            pair_stats(r_a[e], r_b[e], r_c[e], s_pa, s_pb, s_pix, s_dl, s_h, i, tx, ty, ro.alpha_max,
+                        for (uint32_t i = q0 + r; i < q1; i += LG)
+                            pair_stats<GN>(r_a[e], r_b[e], r_c[e], s_pa, s_pb, s_pix, s_dl, s_h, i, tx, ty, ro.alpha_max,
                                        acc);
                     }
 #pragma unroll
-                    for (int f = 0; f < GSN_NZ; ++f) acc[f] = row_sum(acc[f]);
+                    for (int f = 0; f < GSN_NZ; ++f) acc[f] = group_sum<LG>(acc[f]);
                     if (k < nlarge && r == 0) {
                         write_partial(partial, flags, r_slot[e], acc);
                         kflag[r_id[e]] = 1;
@@ -477,6 +496,7 @@ __device__ __forceinline__ void load_kparams(const float* __restrict__ pos, cons
 
 // One thread per kernel: position, opacity and per-view colour blocks from the summed
 // statistics (single precision), and the optional float copy of the statistics.
+template <bool GN>
 __global__ __launch_bounds__(128) void chain_pos_kernel(
     const float* __restrict__ pos, const float* __restrict__ rot, const float* __restrict__ scale,
     const float* __restrict__ sh, int n, int K, const double* __restrict__ zsum, const float4* __restrict__ rec,
@@ -510,7 +530,7 @@ __global__ __launch_bounds__(128) void chain_pos_kernel(
     const size_t N = (size_t)n;
     {
         float g[3], H[6];
-        chain_position(kp, sh + k, N, K, cam, kappa, z, g, H);
+        chain_position(kp, sh + k, N, K, cam, kappa, z, GN, g, H);
 #pragma unroll
         for (int a = 0; a < 3; ++a) blk[a * N + k] += weight * g[a];
 #pragma unroll
@@ -535,6 +555,7 @@ __global__ __launch_bounds__(128) void chain_pos_kernel(
 
 // One thread per kernel: rotation and scale blocks, in double from the double sums of the
 // conic statistics (both Hessians cancel strongly for thin splats).
+template <bool GN>
 __global__ __launch_bounds__(128) void chain_rs_kernel(
     const float* __restrict__ pos, const float* __restrict__ rot, const float* __restrict__ scale, int n,
     const double* __restrict__ zsum, const float4* __restrict__ rec, DevCam cam, float kappa, float weight,
@@ -549,12 +570,12 @@ __global__ __launch_bounds__(128) void chain_rs_kernel(
     load_kparams(pos, rot, scale, rec, n, k, kp);
     const size_t N = (size_t)n;
     double g[3], H[6];
-    chain_rotation(kp, cam, kappa, gq, Hq, g, H);
+    chain_rotation(kp, cam, kappa, gq, Hq, GN, g, H);
 #pragma unroll
     for (int a = 0; a < 3; ++a) blk[(9 + a) * N + k] += (float)(weight * g[a]);
 #pragma unroll
     for (int a = 0; a < 6; ++a) blk[(12 + a) * N + k] += (float)(weight * H[a]);
-    chain_scale(kp, cam, kappa, gq, Hq, g, H);
+    chain_scale(kp, cam, kappa, gq, Hq, GN, g, H);
 #pragma unroll
     for (int a = 0; a < 3; ++a) blk[(18 + a) * N + k] += (float)(weight * g[a]);
 #pragma unroll
@@ -563,24 +584,27 @@ __global__ __launch_bounds__(128) void chain_rs_kernel(
 
 }  // namespace
 
-void launch_raster_bwd(const gsn_frame& f, const float* dL, const float* hd, unsigned long long* counts, hipStream_t s) {
+void launch_raster_bwd(const gsn_frame& f, const float* dL, const float* hd, bool gauss_newton,
+                       unsigned long long* counts, hipStream_t s) {
     const int tiles = f.tiles_x * f.tiles_y;
-    raster_bwd_kernel<<<tiles, GSN_BLOCK, 0, s>>>(
+    auto kern = gauss_newton ? raster_bwd_kernel<true> : raster_bwd_kernel<false>;
+    kern<<<tiles, GSN_BLOCK, 0, s>>>(
         bp<uint2>(f.ranges), bp<uint32_t>(f.pv_a), bp<float4>(f.rec),
         bp<uint2>(f.rect), bp<uint32_t>(f.pair_off), (uint32_t)f.n, f.cam, f.ro, bp<double>(f.img64),
         bp<uint32_t>(f.ncontrib), dL, hd, bp<float>(f.partial), bp<uint8_t>(f.flags), bp<uint8_t>(f.kflag), counts);
 }
 
-void launch_reduce_chain(const gsn_frame& f, const gsn_gaussians& g, float weight, int slot, const gsn_blocks& b,
-                         float* zstats_out, hipStream_t s) {
+void launch_reduce_chain(const gsn_frame& f, const gsn_gaussians& g, float weight, int slot, bool gauss_newton,
+                         const gsn_blocks& b, float* zstats_out, hipStream_t s) {
     if (g.n == 0) return;
     const int K = (g.sh_degree + 1) * (g.sh_degree + 1);
     reduce_pairs_kernel<<<(g.n + 3) / 4, 256, 0, s>>>(g.n, bp<uint2>(f.rect), bp<uint32_t>(f.pair_off),
                                                       bp<float>(f.partial), bp<uint8_t>(f.flags),
                                                       bp<uint8_t>(f.kflag), bp<double>(f.zsum));
-    chain_pos_kernel<<<(g.n + 127) / 128, 128, 0, s>>>(g.d_pos, g.d_rot, g.d_scale, g.d_sh, g.n, K,
-                                                       bp<double>(f.zsum), bp<float4>(f.rec), f.cam, f.ro.kappa,
-                                                       weight, slot, b.d_data, zstats_out);
-    chain_rs_kernel<<<(g.n + 127) / 128, 128, 0, s>>>(g.d_pos, g.d_rot, g.d_scale, g.n, bp<double>(f.zsum),
-                                                      bp<float4>(f.rec), f.cam, f.ro.kappa, weight, b.d_data);
+    auto pos_k = gauss_newton ? chain_pos_kernel<true> : chain_pos_kernel<false>;
+    auto rs_k = gauss_newton ? chain_rs_kernel<true> : chain_rs_kernel<false>;
+    pos_k<<<(g.n + 127) / 128, 128, 0, s>>>(g.d_pos, g.d_rot, g.d_scale, g.d_sh, g.n, K, bp<double>(f.zsum),
+                                            bp<float4>(f.rec), f.cam, f.ro.kappa, weight, slot, b.d_data, zstats_out);
+    rs_k<<<(g.n + 127) / 128, 128, 0, s>>>(g.d_pos, g.d_rot, g.d_scale, g.n, bp<double>(f.zsum), bp<float4>(f.rec),
+                                           f.cam, f.ro.kappa, weight, b.d_data);
 }

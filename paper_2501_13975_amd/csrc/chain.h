@@ -77,8 +77,9 @@ GSN_HD inline void conic_from_A(const TT A[2][3], K kappa, TT Q[3]) {
 }
 
 // g_a = sum_i gz_i dz_i/dy_a;  H_ab = sum_ij Hz_ij dz_i/dy_a dz_j/dy_b + sum_i gz_i d2z_i/dy_a dy_b (packed).
+// gn (local Gauss-Newton): the second sum, a loss gradient times curvature of z, is left out.
 template <int N, int NZ, class T>
-GSN_HD inline void chain_accumulate(const FJet<N, T>* zj, const T* gz, const T Hz[NZ][NZ], T* g, T* H) {
+GSN_HD inline void chain_accumulate(const FJet<N, T>* zj, const T* gz, const T Hz[NZ][NZ], bool gn, T* g, T* H) {
 #pragma unroll
     for (int a = 0; a < N; ++a) {
         T acc = T(0);
@@ -103,7 +104,11 @@ GSN_HD inline void chain_accumulate(const FJet<N, T>* zj, const T* gz, const T H
         for (int b = a; b < N; ++b, ++idx) {
             T acc = T(0);
 #pragma unroll
-            for (int i = 0; i < NZ; ++i) acc += zj[i].g[a] * t[i][b] + gz[i] * zj[i].h[idx];
+            for (int i = 0; i < NZ; ++i) acc += zj[i].g[a] * t[i][b];
+            if (!gn) {
+#pragma unroll
+                for (int i = 0; i < NZ; ++i) acc += gz[i] * zj[i].h[idx];
+            }
             H[idx] = acc;
         }
 }
@@ -113,7 +118,7 @@ GSN_HD inline void chain_accumulate(const FJet<N, T>* zj, const T* gz, const T H
 // splat's principal frame (pi' = V^T pi, Q' = (V^T M R S)(V^T M R S)^T + kappa I inverted).
 // The kernel's SH coefficient (ch, i) is shk[(ch K + i) stride].
 GSN_HD inline void chain_position(const KParams& kp, const float* shk, size_t stride, int K, const DevCam& c,
-                                  float kappa, const float* z, float* g, float* H) {
+                                  float kappa, const float* z, bool gn, float* g, float* H) {
     typedef FJet<3> J;
     J p[3] = {J::var(kp.p[0], 0), J::var(kp.p[1], 1), J::var(kp.p[2], 2)};
     J t[3];
@@ -162,7 +167,7 @@ GSN_HD inline void chain_position(const KParams& kp, const float* shk, size_t st
 #pragma unroll
         for (int b = 0; b < 3; ++b) Hz[5 + a][5 + b] = a == b ? z[39 + a] : 0.f;
     const float gz[8] = {z[0], z[1], z[2], z[3], z[4], z[6], z[7], z[8]};
-    chain_accumulate<3, 8, float>(zj, gz, Hz, g, H);
+    chain_accumulate<3, 8, float>(zj, gz, Hz, gn, g, H);
 }
 
 // Statistics of Q' = (Q'_11, Q'_12, Q'_22): entries 2..4 of the (pi', Q') block, kept in the
@@ -259,7 +264,7 @@ GSN_HD inline void frame_M_R(const KParams& kp, const DevCam& c, double M[2][3],
 
 // Scale: A = M' R diag(s) is linear in s, dA/ds_a has the single column a of M' R.
 GSN_HD inline void chain_scale(const KParams& kp, const DevCam& c, float kappa, const double gz[3],
-                               const double Hz[3][3], double* g, double* H) {
+                               const double Hz[3][3], bool gn, double* g, double* H) {
     double M[2][3], Rq[3][3];
     frame_M_R(kp, c, M, Rq);
     double A0[2][3], D[3][2][3];
@@ -274,7 +279,7 @@ GSN_HD inline void chain_scale(const KParams& kp, const DevCam& c, float kappa, 
         }
     FJet<3, double> Q[3];
     conic_jets(A0, D, [](int, int, double[2][3]) {}, false, (double)kappa, Q);
-    chain_accumulate<3, 3, double>(Q, gz, Hz, g, H);
+    chain_accumulate<3, 3, double>(Q, gz, Hz, gn, g, H);
 }
 
 // Rotation in the tangent space of left rotations: R(omega) = exp([omega]_x) R0, i.e.
@@ -283,7 +288,7 @@ GSN_HD inline void chain_scale(const KParams& kp, const DevCam& c, float kappa, 
 //   d2A/domega_i domega_j = (1/2) (M' e_j)(e_i^T B0) + (1/2) (M' e_i)(e_j^T B0) - delta_ij M' B0
 // (from [e_i]_x [e_j]_x = e_j e_i^T - delta_ij I).
 GSN_HD inline void chain_rotation(const KParams& kp, const DevCam& c, float kappa, const double gz[3],
-                                  const double Hz[3][3], double* g, double* H) {
+                                  const double Hz[3][3], bool gn, double* g, double* H) {
     double M[2][3], Rq[3][3];
     frame_M_R(kp, c, M, Rq);
     double B0[3][3];
@@ -317,5 +322,5 @@ GSN_HD inline void chain_rotation(const KParams& kp, const DevCam& c, float kapp
     };
     FJet<3, double> Q[3];
     conic_jets(A0, D, E, true, (double)kappa, Q);
-    chain_accumulate<3, 3, double>(Q, gz, Hz, g, H);
+    chain_accumulate<3, 3, double>(Q, gz, Hz, gn, g, H);
 }

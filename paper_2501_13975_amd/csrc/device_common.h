@@ -131,6 +131,15 @@ GSN_HD inline void principal_frame(const T A[2][3], T kappa, T& l1, T& l2, T& c,
 #define SH_C3D 0.37317633259011546f
 #define SH_C3E 1.44530572132027737f
 
+// Quaternion product r = a b, (w, x, y, z) order.
+template <class T>
+GSN_HD inline void qmul(const T a[4], const T b[4], T r[4]) {
+    r[0] = a[0] * b[0] - a[1] * b[1] - a[2] * b[2] - a[3] * b[3];
+    r[1] = a[0] * b[1] + b[0] * a[1] + a[2] * b[3] - a[3] * b[2];
+    r[2] = a[0] * b[2] + b[0] * a[2] + a[3] * b[1] - a[1] * b[3];
+    r[3] = a[0] * b[3] + b[0] * a[3] + a[1] * b[2] - a[2] * b[1];
+}
+
 // Visits (i, Y_i) for i < K in order, so that callers accumulate without holding an
 // array of basis values (jets of 16 basis functions would not fit in registers).
 template <class T, class F>

@@ -122,15 +122,18 @@ void launch_loss_maps(const float* img, const float* tgt, int W, int H, float la
 void launch_loss_reduce(const double* part, int nparts, int W, int H, double* out, hipStream_t s);
 
 // ---- launchers (backward.hip)
-void launch_raster_bwd(const gsn_frame& f, const float* dL, const float* hd, unsigned long long* counts, hipStream_t s);
-void launch_reduce_chain(const gsn_frame& f, const gsn_gaussians& g, float weight, int slot, const gsn_blocks& b,
-                         float* zstats_out, hipStream_t s);
+void launch_raster_bwd(const gsn_frame& f, const float* dL, const float* hd, bool gauss_newton,
+                       unsigned long long* counts, hipStream_t s);
+void launch_reduce_chain(const gsn_frame& f, const gsn_gaussians& g, float weight, int slot, bool gauss_newton,
+                         const gsn_blocks& b, float* zstats_out, hipStream_t s);
 
 // ---- launchers (solve.hip)
 void launch_solve(const gsn_gaussians& g, const DevCam& cam, float kappa, const gsn_blocks& b,
                   const gsn_solve_opts& o, const gsn_steps& st, hipStream_t s);
 void launch_apply(const gsn_gaussians& g, const gsn_steps& st, const gsn_solve_opts& o, const float* scale,
                   uint32_t mask, hipStream_t s);
+void launch_first_order(const gsn_gaussians& g, const gsn_blocks& b, const gsn_first_order_opts& fo, float c1,
+                        float c2, float scale_floor, float opac_eps, float* state, uint32_t mask, hipStream_t s);
 // One scene of a batched solve (device-side table entry).
 #define GSN_SOLVE_MAX_SCENES 64
 #define GSN_SOLVE_MAX_BLOCK 256

@@ -234,14 +234,6 @@ __device__ __forceinline__ void colour_solve(int K, int V, RowFn B, const gsn_so
     }
 }
 
-template <class T>
-__device__ __forceinline__ void qmul(const T a[4], const T b[4], T r[4]) {
-    r[0] = a[0] * b[0] - a[1] * b[1] - a[2] * b[2] - a[3] * b[3];
-    r[1] = a[0] * b[1] + b[0] * a[1] + a[2] * b[3] - a[3] * b[2];
-    r[2] = a[0] * b[2] + b[0] * a[2] + a[3] * b[1] - a[1] * b[3];
-    r[3] = a[0] * b[3] + b[0] * a[3] + a[1] * b[2] - a[2] * b[1];
-}
-
 // The local solves of kernel k of one scene (all groups), writing its steps and decisions.
 template <int VM>
 __device__ __forceinline__ void solve_one(int k, const float* __restrict__ pos, const float* __restrict__ rot,

@@ -43,6 +43,7 @@ def lib():
             "gsn_accumulate_hessian": [P, P, P, P, P, ctypes.c_int32, P, P],
             "gsn_local_newton_solve": [P, P, P, P, P, P],
             "gsn_apply_step": [P, P, P, P, P, ctypes.c_uint32],
+            "gsn_first_order_step": [P, P, P, P, P, P, ctypes.c_uint32],
             "gsn_step_features": [P, P, P, P, P, P, P],
             "gsn_solve_batched": [P, P, ctypes.c_int32],
             "gsn_sh_gram": [P, P, ctypes.c_int32, P],
@@ -97,7 +98,8 @@ class CRenderOpts(ctypes.Structure):
 
 
 class CLossOpts(ctypes.Structure):
-    _fields_ = [("lambda_ssim", ctypes.c_float), ("weight", ctypes.c_float), ("keep_zstats", ctypes.c_int32)]
+    _fields_ = [("lambda_ssim", ctypes.c_float), ("weight", ctypes.c_float), ("keep_zstats", ctypes.c_int32),
+                ("gauss_newton", ctypes.c_int32)]
 
 
 class CSolveOpts(ctypes.Structure):
@@ -124,8 +126,8 @@ def render_opts(alpha_min=1.0 / 255.0, alpha_max=0.99, T_min=1e-4, kappa=0.3, ra
     return CRenderOpts(16, alpha_min, alpha_max, T_min, kappa, radius_sigma, (ctypes.c_float * 3)(*bg))
 
 
-def loss_opts(lambda_ssim=0.2, weight=1.0, keep_zstats=False):
-    return CLossOpts(lambda_ssim, weight, int(keep_zstats))
+def loss_opts(lambda_ssim=0.2, weight=1.0, keep_zstats=False, gauss_newton=False):
+    return CLossOpts(lambda_ssim, weight, int(keep_zstats), int(gauss_newton))
 
 
 def solve_opts(npix_primary, kappa=0.3, damp_rel=1e-3, damp_abs=1e-12, pivot_min=1e-3, max_escalations=7,
@@ -284,6 +286,16 @@ class Context:
         self._check(lib().gsn_apply_step(self.h, ctypes.byref(cg), ctypes.byref(cs), ctypes.byref(so),
                                          _ptr(scale), int(group_mask)))
 
+    def first_order_step(self, g, blocks: "Blocks", so: CSolveOpts, lr, adam=True, step=1, state=None,
+                         beta1=0.9, beta2=0.999, eps=1e-15, group_mask=31):
+        """One gradient-descent (adam=False) or Adam step from the gradients in `blocks`.
+        lr: five learning rates (position, rotation, scaling, opacity, colour); state: device
+        float tensor [2, 10 + 3K, n] of moments, zeroed before step 1."""
+        cg, cb = g.c(), blocks.c()
+        fo = CFirstOrderOpts((ctypes.c_float * 5)(*[float(x) for x in lr]), beta1, beta2, eps, int(adam), int(step))
+        self._check(lib().gsn_first_order_step(self.h, ctypes.byref(cg), ctypes.byref(cb), ctypes.byref(so),
+                                               ctypes.byref(fo), _ptr(state), int(group_mask)))
+
     def _items(self, items):
         """items: list of (DeviceGaussians, CCamera, Blocks, CSolveOpts, Steps) -> C array (+ keep-alive)."""
         keep = []
@@ -372,6 +384,11 @@ GSN_MLP_PARAMS = 709
 class CMlp(ctypes.Structure):
     _fields_ = [("d_params", ctypes.c_void_p), ("d_m", ctypes.c_void_p), ("d_v", ctypes.c_void_p),
                 ("d_half", ctypes.c_void_p), ("step", ctypes.c_int32)]
+
+
+class CFirstOrderOpts(ctypes.Structure):
+    _fields_ = [("lr", ctypes.c_float * 5), ("beta1", ctypes.c_float), ("beta2", ctypes.c_float),
+                ("eps", ctypes.c_float), ("adam", ctypes.c_int32), ("step", ctypes.c_int32)]
 
 
 class CSolveItem(ctypes.Structure):

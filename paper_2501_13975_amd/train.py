@@ -23,7 +23,7 @@ from . import gsn
 
 class LocalNewtonTrainer:
     def __init__(self, gauss: gsn.DeviceGaussians, cams, targets, n_secondary=3, lambda_ssim=0.2,
-                 render_opts=None, solve_kw=None, device="cuda", keep_zstats=False):
+                 render_opts=None, solve_kw=None, device="cuda", keep_zstats=False, gauss_newton=False):
         self.g = gauss
         self.dev = torch.device(device)
         self.ctx = gsn.Context(self.dev)
@@ -34,7 +34,7 @@ class LocalNewtonTrainer:
         self.targets = targets
         self.n_secondary = int(n_secondary) if len(self.cams) > 1 else 0
         self.ro = render_opts or gsn.render_opts()
-        self.lo = gsn.loss_opts(lambda_ssim, 1.0, keep_zstats)
+        self.lo = gsn.loss_opts(lambda_ssim, 1.0, keep_zstats, gauss_newton)
         self.solve_kw = dict(solve_kw or {})
         V = 1 + self.n_secondary
         self.blocks = gsn.Blocks(gauss.n, V, self.dev)
@@ -70,10 +70,33 @@ class LocalNewtonTrainer:
             self.ctx.accumulate_hessian(self.g, fr, tgt, self.lo, slot, self.blocks, self.loss[slot])
 
     def sweep(self, t, group_mask=31):
+        """Jacobi schedule: every group linearised at the same state, one render and
+        accumulation per view, the steps of the groups in group_mask applied together."""
         self.accumulate(t)
         so = self.solve_opts(t)
         self.ctx.local_newton_solve(self.g, self.ccams[t], self.blocks, so, self.steps)
         self.ctx.apply_step(self.g, self.steps, so, group_mask)
+
+    def sweep_series(self, t, order=(1, 2, 4, 8, 16)):
+        """Series schedule (Sec. 4.2, groups solved one after another: position, rotation,
+        scaling, opacity, colour): for each group mask in `order`, render and accumulate the
+        views at the state the previous groups left, solve, and apply that group only."""
+        for m in order:
+            self.sweep(t, m)
+
+    # ------------------------------------------------------- first-order baseline
+    def sweep_first_order(self, t, lr, adam=True, group_mask=31, beta1=0.9, beta2=0.999, eps=1e-15):
+        """One first-order iteration on image t with the same gradients as a sweep (the blocks'
+        gradient rows, summed over the primary and its secondaries): gradient descent or Adam
+        with per-group learning rates (position, rotation, scaling, opacity, colour)."""
+        if getattr(self, "fo_state", None) is None:
+            K = (self.g.sh_degree + 1) ** 2
+            self.fo_state = torch.zeros(2, 10 + 3 * K, max(self.g.n, 1), dtype=torch.float32, device=self.dev)
+            self.fo_t = 0
+        self.fo_t += 1
+        self.accumulate(t)
+        self.ctx.first_order_step(self.g, self.blocks, self.solve_opts(t), lr, adam=adam, step=self.fo_t,
+                                  state=self.fo_state, beta1=beta1, beta2=beta2, eps=eps, group_mask=group_mask)
 
     # ------------------------------------------------------------ learned form
     def enable_learned(self, params, every=4, lr=1e-3):

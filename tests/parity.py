@@ -84,7 +84,7 @@ BLOCK_GROUPS = {
 STEP_GROUPS = {"position": slice(0, 3), "rotation": slice(3, 4), "scale": slice(7, 10), "opacity": slice(10, 11)}
 
 
-def gpu_view(ctx, gsn, dg, cam, target_t, lam, blocks, slot, keep=True):
+def gpu_view(ctx, gsn, dg, cam, target_t, lam, blocks, slot, keep=True, gn=False):
     """Render + accumulate one view on the GPU; returns numpy copies of every stage."""
     import torch
     fr = ctx.frame()
@@ -94,7 +94,7 @@ def gpu_view(ctx, gsn, dg, cam, target_t, lam, blocks, slot, keep=True):
     T = torch.zeros(cam.height, cam.width, dtype=torch.float32, device=ctx.device)
     ctx.render(dg, ccam, ro, fr, rgb, T)
     loss = torch.zeros(2, dtype=torch.float64, device=ctx.device)
-    ctx.accumulate_hessian(dg, fr, target_t, gsn.loss_opts(lam, 1.0, keep), slot, blocks, loss)
+    ctx.accumulate_hessian(dg, fr, target_t, gsn.loss_opts(lam, 1.0, keep, gn), slot, blocks, loss)
     torch.cuda.synchronize()
     ranges, ids, depth, rect, nc = fr.lists(dg.n, cam.width * cam.height)
     dL, h = fr.loss_maps(cam.height, cam.width)
@@ -110,8 +110,8 @@ def gpu_view(ctx, gsn, dg, cam, target_t, lam, blocks, slot, keep=True):
     return out
 
 
-def oracle_view(g, cam, target, lam, o=None):
-    o = O.opts(lambda_ssim=lam) if o is None else o
+def oracle_view(g, cam, target, lam, o=None, gn=False):
+    o = O.opts(lambda_ssim=lam, gauss_newton=int(gn)) if o is None else o
     fr = O.render(g, cam, o, g32=g)
     parts, dL, hd = O.loss(fr.img, target, lam)
     B = O.blocks(g, fr, dL, hd)
@@ -235,15 +235,31 @@ def oracle_frames(g, cam, kappa=0.3):
     return np.where(nn > 0, vx / safe, 1.0), np.where(nn > 0, vy / safe, 0.0)
 
 
+def _block_groups(V):
+    """Column groups of the oracle's summed layout whose entries are sums of the same per-pixel
+    terms: a float32 sum is accurate to a fraction of the group's largest entry, not of each entry
+    (a small entry can be the cancelled remainder of large terms)."""
+    groups = [slice(0, 3), slice(3, 12), slice(12, 15), slice(15, 24), slice(24, 27), slice(27, 36),
+              slice(36, 37), slice(37, 38), slice(38, 39)]
+    for v in range(V):
+        b = O.NB_BASE + O.NB_VIEW * v
+        groups += [slice(b, b + 3), slice(b + 3, b + 6), slice(b + 6, b + 9), slice(b + 9, b + 10)]
+    return groups
+
+
 def step_sensitivity(g, cam, o, summed, V, rel=1e-5, trials=4, seed=0):
     """Per kernel and group, the largest change of the oracle's step when its inputs carry
-    relative noise `rel` (the precision the blocks are required to have), divided by the
-    group's largest step: how precisely the step is determined by blocks of that accuracy."""
+    noise `rel` times the largest entry of each kernel's block (the precision the blocks are
+    required to have), divided by the group's largest step: how precisely the step is
+    determined by blocks of that accuracy."""
     rng = np.random.default_rng(seed)
     base, dec = O.solve(g, cam, o, summed, V)
     dev = np.zeros((summed.shape[0], len(STEP_GROUPS) + 1))
+    scale = np.zeros_like(summed)
+    for sl in _block_groups(V):
+        scale[:, sl] = np.max(np.abs(summed[:, sl]), axis=1, keepdims=True)
     for _ in range(trials):
-        noisy = summed * (1.0 + rel * rng.standard_normal(summed.shape))
+        noisy = summed + rel * scale * rng.standard_normal(summed.shape)
         st, _ = O.solve(g, cam, o, noisy, V)
         for i, sl in enumerate(list(STEP_GROUPS.values()) + [slice(11, None)]):
             den = max(np.max(np.abs(base[:, sl])), 1e-300)

@@ -44,12 +44,12 @@ def _report(name, errs):
     print(f"\n[{name}] " + " ".join(f"{k}={v:.2e}" for k, v in errs.items()), flush=True)
 
 
-def _check_view(gsn, ctx, g, cam, tgt, lam, label):
+def _check_view(gsn, ctx, g, cam, tgt, lam, label, gn=False):
     dg = gsn.DeviceGaussians.from_host(g)
     blocks = gsn.Blocks(g.n, 1, ctx.device)
     ctx.blocks_zero(blocks)
-    gv = gpu_view(ctx, gsn, dg, cam, torch.tensor(tgt, device=ctx.device), lam, blocks, 0)
-    ov = oracle_view(g, cam, tgt, lam)
+    gv = gpu_view(ctx, gsn, dg, cam, torch.tensor(tgt, device=ctx.device), lam, blocks, 0, gn=gn)
+    ov = oracle_view(g, cam, tgt, lam, gn=gn)
     ntiles = compare_binning(gv, ov, g.n)
     mask = pixel_mask(ov)
     errs = {"tiles": ntiles, "pairs": gv["pairs"], "ambiguous_px": int((~mask).sum())}
@@ -115,19 +115,31 @@ def test_surface_scene_ragged_view_parity(gsn, ctx):
     _check_view(gsn, ctx, cfg.init, cam, tgt, 0.2, "c1-small")
 
 
-@pytest.mark.parametrize("lam", [0.0, 0.2])
-def test_sweep_steps_parity(gsn, ctx, lam):
-    """Primary + 3 half-resolution KNN secondaries, solve and apply (Sec. 4.2-4.3)."""
-    cfg = make_config("c1", n=4000, width=200, height=150, n_views=8)
+def test_gauss_newton_view_parity(gsn, ctx):
+    """Local Gauss-Newton statistics and blocks (no loss-gradient x image-curvature terms)."""
+    cfg = make_config("c1", n=6000, width=250, height=190, n_views=6)
+    cam = cfg.cams[2]
+    tgt = O.render(cfg.gt, cam, O.opts()).img.astype(np.float32)
+    _check_view(gsn, ctx, cfg.init, cam, tgt, 0.2, "c1-small gauss-newton", gn=True)
+
+
+@pytest.mark.parametrize("lam,nsec,gn", [(0.0, 3, False), (0.2, 3, False), (0.2, 0, False), (0.2, 8, False),
+                                         (0.2, 3, True)])
+def test_sweep_steps_parity(gsn, ctx, lam, nsec, gn):
+    """Primary + K half-resolution KNN secondaries (|N_t| in {0, 3, 8}), solve and apply (Sec.
+    4.2-4.3); gn: the local Gauss-Newton blocks."""
+    cfg = make_config("c1", n=4000, width=200, height=150, n_views=10)
     tg = [O.render(cfg.gt, c, O.opts()).img.astype(np.float32) for c in cfg.cams]
     g = cfg.init
     t = 3
-    knn_o = O.camera_knn(cfg.cams, g, 3)
-    knn_g = gsn.camera_knn(np.stack([c.center for c in cfg.cams]),
-                           np.asarray(g.pos, np.float64).mean(1), 3)
-    assert np.array_equal(knn_o, knn_g)
+    V = nsec + 1
+    knn_o = O.camera_knn(cfg.cams, g, nsec) if nsec else None
+    if nsec:
+        knn_g = gsn.camera_knn(np.stack([c.center for c in cfg.cams]),
+                               np.asarray(g.pos, np.float64).mean(1), nsec)
+        assert np.array_equal(knn_o, knn_g)
     # end to end with the colour trust radius open (the radius itself is checked on the solve stage below)
-    o = O.opts(lambda_ssim=lam, trust_sh=1e30)
+    o = O.opts(lambda_ssim=lam, trust_sh=1e30, gauss_newton=int(gn))
     res = O.sweep(g, cfg.cams, tg, t, knn_o, o)
     # kernels that any view composites at a pixel with a near-threshold decision are not compared
     bad = np.zeros(g.n, bool)
@@ -135,8 +147,9 @@ def test_sweep_steps_parity(gsn, ctx, lam):
         bad |= near_threshold_kernels(fr, g.n)
     from paper_2501_13975_amd.train import LocalNewtonTrainer
     dg = gsn.DeviceGaussians.from_host(g)
-    tr = LocalNewtonTrainer(dg, cfg.cams, [torch.tensor(x, device=ctx.device) for x in tg], 3, lam,
-                            solve_kw={"trust_sh": 1e30})
+    tr = LocalNewtonTrainer(dg, cfg.cams, [torch.tensor(x, device=ctx.device) for x in tg], nsec, lam,
+                            solve_kw={"trust_sh": 1e30}, gauss_newton=gn)
+    assert tr.blocks.n_views == V
     tr.accumulate(t)
     so = tr.solve_opts(t)
     tr.ctx.local_newton_solve(tr.g, tr.ccams[t], tr.blocks, so, tr.steps)
@@ -154,7 +167,7 @@ def test_sweep_steps_parity(gsn, ctx, lam):
     o_same = res["opts"]
     gb = tr.blocks.view().cpu().numpy()
     # (1) end to end, where the step is determined at the blocks' precision (1e-5)
-    sens = step_sensitivity(g, cfg.cams[t], o_same, res["summed"], 4)
+    sens = step_sensitivity(g, cfg.cams[t], o_same, res["summed"], V)
     groups = list(STEP_GROUPS.items()) + [("colour", slice(11, 11 + 3 * K))]
     for i, (name, sl) in enumerate(groups):
         ok = keep & (sens[:, i] <= 1e-5)
@@ -163,10 +176,10 @@ def test_sweep_steps_parity(gsn, ctx, lam):
     # (2) the solve stage alone: the oracle's blocks, rounded to the library's float32 storage,
     # solved by the library and by the oracle
     S32 = res["summed"].astype(np.float32).astype(np.float64)
-    tr.blocks.view().copy_(torch.tensor(summed_to_gpu_blocks(S32, 4), dtype=torch.float32, device=ctx.device))
+    tr.blocks.view().copy_(torch.tensor(summed_to_gpu_blocks(S32, V), dtype=torch.float32, device=ctx.device))
     tr.ctx.local_newton_solve(tr.g, tr.ccams[t], tr.blocks, so, tr.steps)
     st_s, fl_s = (x.cpu().numpy() for x in tr.steps.view())
-    want_s, dec_s = O.solve(g, cfg.cams[t], o_same, S32, 4)
+    want_s, dec_s = O.solve(g, cfg.cams[t], o_same, S32, V)
     same = np.all(fl_s[:4].T == dec_s[:, :4], axis=1) & vis
     errs["solver_decisions"] = float(same[vis].mean())
     for name, sl in groups:
@@ -179,17 +192,18 @@ def test_sweep_steps_parity(gsn, ctx, lam):
         st_f, fl_f = (x.cpu().numpy() for x in tr.steps.view())
         o_f = o_same.copy()
         o_f[O.O_NAMES.index(field)] = val
-        want_f, dec_f = O.solve(g, cfg.cams[t], o_f, S32, 4)
+        want_f, dec_f = O.solve(g, cfg.cams[t], o_f, S32, V)
         same_f = np.all(fl_f[:4].T == dec_f[:, :4], axis=1) & vis
         for name, sl in groups:
             errs[f"solver_{tag}_" + name] = rel_inf(st_f[sl].T[same_f], want_f[same_f, sl])
     dump = os.environ.get("GSN_DUMP_DIR")
     if dump:
         os.makedirs(dump, exist_ok=True)
-        np.savez_compressed(os.path.join(dump, f"sweep_lam{lam}.npz"), gpu_blocks=gb, gpu_steps=st, gpu_flags=fl,
+        np.savez_compressed(os.path.join(dump, f"sweep_lam{lam}_N{nsec}_gn{int(gn)}.npz"), gpu_blocks=gb,
+                            gpu_steps=st, gpu_flags=fl,
                             orc_summed=res["summed"], orc_steps=res["steps"], orc_dec=res["dec"], bad=bad,
                             sens=sens)
-    _report(f"sweep-steps lam={lam}", errs)
+    _report(f"sweep-steps lam={lam} |N_t|={nsec} gn={gn}", errs)
     assert errs["decision_agreement"] > 0.99 and errs["solver_decisions"] > 0.999
     for name, _ in groups:
         assert errs["solver_" + name] < 1e-5, ("solver", name, errs["solver_" + name])
@@ -209,6 +223,59 @@ def test_sweep_steps_parity(gsn, ctx, lam):
     for a in ("pos", "rot", "scale", "opac", "sh"):
         assert np.allclose(getattr(new_g, a), getattr(new_o, a), rtol=2e-6, atol=2e-6), a
     tr.close()
+
+
+def test_series_stages_parity(gsn, ctx):
+    """Series schedule (Sec. 4.2: position, rotation, scaling, opacity, colour, each group
+    linearised at the state the previous groups left).  Every stage of the library's
+    sweep_series starts from the oracle's state after the previous stage, rounded to float32,
+    and its applied change of that group matches the oracle's stage on the kernels whose step
+    is determined at the blocks' precision."""
+    from paper_2501_13975_amd.train import LocalNewtonTrainer
+    from synth.scenes import Gaussians
+    cfg = make_config("c1", n=4000, width=200, height=150, n_views=10)
+    tg = [O.render(cfg.gt, c, O.opts()).img.astype(np.float32) for c in cfg.cams]
+    tg_d = [torch.tensor(x, device=ctx.device) for x in tg]
+    t, K, V = 3, 3, 4
+    knn = O.camera_knn(cfg.cams, cfg.init, K)
+    o = O.opts(lambda_ssim=0.2, trust_sh=1e30, step_frac=0.5)
+    state = cfg.init
+    attr = {1: "pos", 2: "rot", 4: "scale", 8: "opac", 16: "sh"}
+    errs = {}
+    for gi, m in enumerate((1, 2, 4, 8, 16)):
+        g32 = Gaussians(*(np.asarray(getattr(state, a), np.float32) for a in ("pos", "rot", "scale", "opac", "sh")),
+                        cfg.init.sh_degree)
+        new_o, stages = O.sweep_series(g32, cfg.cams, tg, t, knn, o, (m,))
+        res = stages[0]
+        dg = gsn.DeviceGaussians.from_host(g32)
+        tr = LocalNewtonTrainer(dg, cfg.cams, tg_d, K, 0.2, solve_kw={"trust_sh": 1e30, "step_frac": 0.5})
+        tr.sweep_series(t, (m,))
+        new_g = dg.to_host()
+        fl = tr.steps.view()[1].cpu().numpy()
+        tr.close()
+        vis = res["dec"][:, 0] != -2
+        agree = np.all(fl[:4].T == res["dec"][:, :4], axis=1)
+        bad = np.zeros(g32.n, bool)
+        for fr in res["frames"]:
+            bad |= near_threshold_kernels(fr, g32.n)
+        sens = step_sensitivity(g32, cfg.cams[t], res["opts"], res["summed"], V)
+        keep = vis & agree & ~bad & (sens[:, gi] <= 1e-5)
+        a = attr[m]
+        base = np.asarray(getattr(g32, a), np.float64)
+        dg_ = (np.asarray(getattr(new_g, a), np.float64) - base)[..., keep]
+        do_ = (np.asarray(getattr(new_o, a), np.float64) - base)[..., keep]
+        errs[f"{a}_kept"] = int(keep.sum())
+        errs[a] = rel_inf(dg_, do_)
+        # the other groups are left alone by this stage
+        for b in attr.values():
+            if b != a:
+                assert np.array_equal(np.asarray(getattr(new_g, b)), np.asarray(getattr(g32, b))), (a, b)
+        # after the geometry stages many kernels are composited at near-threshold pixels
+        assert keep.sum() > 0.3 * vis.sum(), (a, int(keep.sum()), int(vis.sum()))
+        state = new_o
+    _report("series stages", errs)
+    for a in attr.values():
+        assert errs[a] < TOL_STEP, (a, errs[a])
 
 
 def test_edge_cases(gsn, ctx):

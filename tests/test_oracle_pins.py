@@ -437,6 +437,73 @@ def test_block_hessians_compose_image_derivatives_with_loss_maps(fd_setup):
     assert rel_err(B[k, hs].reshape(n, n), H) < 1e-5
 
 
+def _image_jacobian(g, cam, o, group, k, n, h=1e-5):
+    """Central differences of the rendered image with respect to kernel k's group: [n][3][H][W]."""
+    J = []
+    for i in range(n):
+        e = np.zeros(n)
+        e[i] = h
+        J.append((O.render(perturbed(g, group, k, e), cam, o).img
+                  - O.render(perturbed(g, group, k, -e), cam, o).img) / (2 * h))
+    return J
+
+
+@pytest.mark.parametrize("lam", [0.0, 0.2])
+def test_gauss_newton_blocks_are_image_jacobian_products(fd_setup, lam):
+    """Local Gauss-Newton (the cheaper Hessian the discussion of the position-Hessian cost points
+    to, Sec. 6): H = sum_pix sum_ch h dc/dy dc/dy^T with dc/dy from first differences of the image
+    alone, the gradient as in the full blocks, and PSD blocks wherever h >= 0 (lambda = 0)."""
+    g, cam, tgt = fd_setup
+    g = g.copy()
+    o_full = smooth_opts(lam)
+    o_gn = smooth_opts(lam, gauss_newton=1)
+    B, fr, dL, hd = oracle_blocks(g, cam, tgt, o_full)
+    Bg, *_ = oracle_blocks(g, cam, tgt, o_gn)
+    grad_cols = np.r_[0:3, 12:15, 24:27, 36, 38:48]
+    assert np.array_equal(Bg[:, grad_cols], B[:, grad_cols])
+    for k in range(g.n):
+        for grp, (_, _, hs, n) in list(GROUPS.items()) + [("o", (None, None, slice(37, 38), 1))]:
+            J = _image_jacobian(g, cam, o_gn, grp, k, n)
+            Hj = np.array([[np.sum(hd * J[i] * J[j]) for j in range(n)] for i in range(n)])
+            Hb = Bg[k, hs].reshape(n, n)
+            assert rel_err(Hb, Hj) < 1e-6, (k, grp)
+            if lam == 0.0:
+                assert np.min(np.linalg.eigvalsh(Hb)) >= -1e-12 * np.max(np.abs(Hb))
+        # opacity and colour enter the image linearly: nothing is dropped there
+        assert Bg[k, 37] == pytest.approx(B[k, 37], rel=1e-12)
+    # the dropped term is not negligible on this scene: the position blocks differ
+    assert rel_err(Bg[:, 3:12], B[:, 3:12]) > 1e-3
+
+
+def test_gauss_newton_zstats_in_projected_space(fd_setup):
+    """Projected-space Gauss-Newton statistics: J_z^T diag(h) J_z with J_z from a records render."""
+    g, cam, tgt = fd_setup
+    lam = 0.2
+    o = smooth_opts(lam, gauss_newton=1)
+    fr = O.render(g, cam, o)
+    _, dL, hd = O.loss(fr.img, tgt, lam)
+    Z = O.zstats(g, fr, dL, hd)
+    out, ok = O.project64(g, cam, kappa=0.0)
+    rec = np.zeros((g.n, 10))
+    rec[:, 0:2] = out[:, 0:2]
+    rec[:, 2:5] = out[:, 5:8]
+    rec[:, 5] = g.opac
+    rec[:, 6:9] = out[:, 8:11]
+    rec[:, 9] = out[:, 11]
+    W, H = cam.width, cam.height
+    for k in range(g.n):
+        J = []
+        for zi in range(9):
+            h = 1e-6 * max(1.0, abs(rec[k, zi]))
+            r = rec.copy()
+            r[k, zi] += h
+            cp = O.render_z(r, W, H)
+            r[k, zi] -= 2 * h
+            J.append((cp - O.render_z(r, W, H)) / (2 * h))
+        Hj = np.array([[np.sum(hd * J[a] * J[b]) for b in range(9)] for a in range(9)])
+        assert rel_err(Z[k, 9:90].reshape(9, 9), Hj) < 1e-6, k
+
+
 @pytest.mark.parametrize("lam", [0.0, 0.2])
 def test_zstats_by_finite_differences_in_projected_space(fd_setup, lam):
     """Gradient (and at lambda=0 Hessian) w.r.t. z = (pi, Q, sigma, c~) by differences of a records render."""
