@@ -38,12 +38,14 @@ PEAK_ALU_TFLOPS = 78.6
 #     times opacity (1) = 18;
 #   one forward contribution: transmittance update (2), alpha T (1), three double
 #     colour accumulations (6) = 9;
-#   one backward contributing (pixel, splat) pair: transmittance and colour-behind bookkeeping
-#     with the alpha derivatives a_ch (35), offsets in the principal frame (10), the 44
-#     projected-space terms (115) and their accumulation (44) = 204.
+#   one backward contributing (pixel, splat) pair: its evaluation (18), transmittance and
+#     colour-behind bookkeeping with the alpha derivatives a_ch (35), offsets in the principal
+#     frame (10), the 44 projected-space terms (115) and their accumulation (44) = 222.
+# The backward pass evaluates a (pixel, entry) again only past the batches whose composited
+# entries the forward pass recorded (counted as bwd_evals, 18 each).
 FLOP_EVAL = 18
 FLOP_FWD_BLEND = 9
-FLOP_BWD_PAIR = 204
+FLOP_BWD_PAIR = 222
 # Bytes one backward launch must move per unit: a staged list entry reads its 48-byte record,
 # 8-byte rectangle and 4-byte pair offset (60); a written (tile, kernel) partial is 44 floats
 # plus its flag (177); per pixel the loss gradient and Hessian maps (6 floats), the final colour
@@ -555,7 +557,7 @@ def main():
                     help="learned form: one full-rule (training) sweep every N sweeps; 0 skips the learned form")
     ap.add_argument("--quality-epochs", type=int, default=2,
                     help="epochs of the plain form that set the PSNR both forms are timed to; 0 skips")
-    ap.add_argument("--step-frac", type=float, default=0.01,
+    ap.add_argument("--step-frac", type=float, default=0.002,
                     help="fraction of every Newton step applied in the timed sweeps: the full step is computed, "
                          "and a small fraction keeps the scene near its initial state so that every timed sweep "
                          "sees the same workload")

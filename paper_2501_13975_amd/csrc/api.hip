@@ -272,6 +272,7 @@ gsn_status gsn_render(gsn_ctx* ctx, const gsn_gaussians* g, const gsn_camera* ca
     HIP_TRY(ctx, buf_reserve(f->img, 3 * npx * 4));
     HIP_TRY(ctx, buf_reserve(f->img64, 3 * npx * 8));
     HIP_TRY(ctx, buf_reserve(f->Tfin, npx * 4));
+    HIP_TRY(ctx, buf_reserve(f->masks, tiles * GSN_MASK_BATCHES * 4 * GSN_BLOCK * sizeof(uint64_t)));
     HIP_TRY(ctx, buf_reserve(f->ncontrib, npx * 4));
     HIP_TRY(ctx, buf_reserve(f->total, 16));
     // sort and scan scratch for the per-kernel stages, reserved before any launch so that
@@ -338,7 +339,7 @@ gsn_status gsn_render(gsn_ctx* ctx, const gsn_gaussians* g, const gsn_camera* ca
         StageTimer st_(ctx, GSN_STAGE_RASTER_FWD);
         launch_raster_fwd(bp<uint2>(f->ranges), bp<uint32_t>(f->pv_a), bp<float4>(f->rec), (uint32_t)n, f->cam,
                           f->ro, bp<float>(f->img), bp<double>(f->img64), bp<float>(f->Tfin),
-                          bp<uint32_t>(f->ncontrib), prof_counts(ctx), s);
+                          bp<uint32_t>(f->ncontrib), bp<uint64_t>(f->masks), prof_counts(ctx), s);
         HIP_TRY(ctx, hipGetLastError());
     }
     if (d_rgb_out) HIP_TRY(ctx, hipMemcpyAsync(d_rgb_out, f->img.p, 3 * npx * 4, hipMemcpyDeviceToDevice, s));

@@ -27,7 +27,7 @@
 // the contributing (pixel, splat) pairs of each round in LDS, and sums each
 // splat's 44 statistics over its pairs (see raster_bwd_kernel); the tile's
 // partial sum is written at the (tile, kernel) pair's slot.
-// reduce_pairs: one wave per kernel sums its written pair slots in a fixed order
+// reduce_pairs: a wave per 64 kernels sums each flagged kernel's written pair slots in a fixed order
 // (no atomics: results are deterministic); chain_pos / chain_rs: one thread per
 // kernel applies the chain rule through the projection with second-order jets
 // and adds the attribute blocks (position, opacity, colour / rotation, scale).
@@ -152,8 +152,9 @@ __device__ __forceinline__ void write_partial(float* __restrict__ partial, uint8
 // thread, with each entry's alpha-support box tested against the four 16 x 4 pixel
 // bands of the tile's waves, giving each wave the ordered list of entries that may
 // composite in it).  Per batch:
-//  (a) every pixel evaluates its wave's entries that come before its stopping entry:
-//      a 256-bit mask of composited entries per pixel, and one ballot per
+//  (a) a 256-bit mask of the entries every pixel composited (the forward pass's record
+//      for the tile's first GSN_MASK_BATCHES batches; later batches evaluate the wave's
+//      entries that come before the pixel's stopping entry again), and one ballot per
 //      (entry, wave);
 // then, in rounds that each take the longest run of entries whose composited
 // (pixel, entry) pairs fit in LDS (usually the whole batch):
@@ -169,9 +170,9 @@ template <bool GN>
 __global__ __launch_bounds__(GSN_BLOCK, 3) void raster_bwd_kernel(
     const uint2* __restrict__ ranges, const uint32_t* __restrict__ ids, const float4* __restrict__ rec,
     const uint2* __restrict__ rect, const uint32_t* __restrict__ pair_off, uint32_t n, DevCam cam, DevRenderOpts ro,
-    const double* __restrict__ img64, const uint32_t* __restrict__ ncontrib, const float* __restrict__ dLm,
-    const float* __restrict__ hdm, float* __restrict__ partial, uint8_t* __restrict__ flags,
-    uint8_t* __restrict__ kflag, unsigned long long* __restrict__ counts) {
+    const double* __restrict__ img64, const uint32_t* __restrict__ ncontrib, const uint64_t* __restrict__ masks,
+    const float* __restrict__ dLm, const float* __restrict__ hdm, float* __restrict__ partial,
+    uint8_t* __restrict__ flags, uint8_t* __restrict__ kflag, unsigned long long* __restrict__ counts) {
     constexpr int NW = GSN_BLOCK / 64;
     __shared__ float4 r_a[GSN_BLOCK], r_b[GSN_BLOCK], r_c[GSN_BLOCK];
     __shared__ uint32_t r_slot[GSN_BLOCK], r_id[GSN_BLOCK];
@@ -263,17 +264,25 @@ __global__ __launch_bounds__(GSN_BLOCK, 3) void raster_bwd_kernel(
 #pragma unroll
         for (int v = 0; v < NW; ++v) nl += r_cnt[wave][v];
         __syncthreads();
-        // (a) which of the batch's entries this pixel composited (256-bit mask, word by word)
+        // (a) which of the batch's entries this pixel composited (256-bit mask, word by word): recorded
+        // by the forward pass for the tile's first GSN_MASK_BATCHES batches, evaluated again after
         uint64_t bits[NW] = {0ull, 0ull, 0ull, 0ull};
-        for (uint32_t i = 0; i < nl; ++i) {
-            const int j = r_list[wave][i];
-            if (base + j - rg.x >= nc) break;
-            ++n_eval;
-            const SplatEval ev = eval_splat(r_a[j], r_b[j], r_c[j], fpx, fpy, ro.alpha_max);
-            if (ev.alpha >= ro.alpha_min) {
+        const uint32_t batch = (base - rg.x) / GSN_BLOCK;
+        if (batch < (uint32_t)GSN_MASK_BATCHES) {
+            const uint64_t* mb = masks + ((size_t)tile * GSN_MASK_BATCHES + batch) * NW * GSN_BLOCK + tid;
 #pragma unroll
-                for (int w = 0; w < NW; ++w)
-                    if ((j >> 6) == w) bits[w] |= 1ull << (j & 63);
+            for (int w = 0; w < NW; ++w) bits[w] = mb[(size_t)w * GSN_BLOCK];
+        } else {
+            for (uint32_t i = 0; i < nl; ++i) {
+                const int j = r_list[wave][i];
+                if (base + j - rg.x >= nc) break;
+                ++n_eval;
+                const SplatEval ev = eval_splat(r_a[j], r_b[j], r_c[j], fpx, fpy, ro.alpha_max);
+                if (ev.alpha >= ro.alpha_min) {
+#pragma unroll
+                    for (int w = 0; w < NW; ++w)
+                        if ((j >> 6) == w) bits[w] |= 1ull << (j & 63);
+                }
             }
         }
         for (uint32_t i = 0; i < nl; ++i) {  // uniform across the wave
@@ -445,39 +454,46 @@ __global__ __launch_bounds__(GSN_BLOCK, 3) void raster_bwd_kernel(
     }
 }
 
-// One wave per kernel: the kernel's (tile, kernel) slots are scanned 64 at a time, and lane
-// f < 44 adds statistic f of every slot the backward pass wrote, in slot order and in double
-// (deterministic, coalesced 176-byte reads per slot).  Most kernels have no written slot in a
-// view (their kernel flag is clear): for them only the coverage entry is written (zero), which
-// the chain kernels test first.
+// One wave per 64 consecutive kernels.  Most kernels have no written slot in a view (their
+// kernel flag is clear): for them only the coverage entry is written (zero), which the chain
+// kernels test first.  The wave then takes its flagged kernels one after another: the kernel's
+// (tile, kernel) slots are scanned 64 at a time, and lane f < 44 adds statistic f of every slot
+// the backward pass wrote, in slot order and in double (deterministic, coalesced 176-byte reads
+// per slot).  A wave per kernel would spend most of the launch starting waves that only read
+// a clear flag.
 __global__ __launch_bounds__(256) void reduce_pairs_kernel(int n, const uint2* __restrict__ rect,
                                                            const uint32_t* __restrict__ pair_off,
                                                            const float* __restrict__ partial,
                                                            const uint8_t* __restrict__ flags,
                                                            const uint8_t* __restrict__ kflag,
                                                            double* __restrict__ zsum) {
-    const int k = blockIdx.x * (blockDim.x / 64) + threadIdx.x / 64;
     const int lane = __lane_id();
-    if (k >= n) return;
-    double* zk = zsum + (size_t)k * GSN_NZ;
-    if (!kflag[k]) {
-        if (lane == 0) zk[GSN_NZ - 1] = 0.0;
-        return;
-    }
-    const uint2 rc = rect[k];
-    const uint32_t nt = ((rc.y & 0xffffu) - (rc.x & 0xffffu)) * ((rc.y >> 16) - (rc.x >> 16));
-    const uint32_t off = pair_off[k];
-    double acc = 0.0;
-    for (uint32_t base = 0; base < nt; base += 64) {
-        const bool fl = base + lane < nt && flags[off + base + lane] != 0;
-        uint64_t m = __ballot(fl);
-        while (m) {
-            const int i = __ffsll((unsigned long long)m) - 1;
-            m &= m - 1;
-            if (lane < GSN_NZ) acc += (double)partial[(size_t)(off + base + i) * GSN_NZ + lane];
+    const int k0 = (blockIdx.x * (blockDim.x / 64) + threadIdx.x / 64) * 64;
+    if (k0 >= n) return;
+    // the wave's 64 kernels: those without partials get a zero coverage, the others are
+    // summed one after another by the whole wave
+    const int kl = k0 + lane;
+    const bool has = kl < n && kflag[kl] != 0;
+    if (kl < n && !has) zsum[(size_t)kl * GSN_NZ + GSN_NZ - 1] = 0.0;
+    uint64_t todo = __ballot(has);
+    while (todo) {  // uniform across the wave
+        const int k = k0 + __ffsll((unsigned long long)todo) - 1;
+        todo &= todo - 1;
+        const uint2 rc = rect[k];
+        const uint32_t nt = ((rc.y & 0xffffu) - (rc.x & 0xffffu)) * ((rc.y >> 16) - (rc.x >> 16));
+        const uint32_t off = pair_off[k];
+        double acc = 0.0;
+        for (uint32_t base = 0; base < nt; base += 64) {
+            const bool fl = base + lane < nt && flags[off + base + lane] != 0;
+            uint64_t m = __ballot(fl);
+            while (m) {
+                const int i = __ffsll((unsigned long long)m) - 1;
+                m &= m - 1;
+                if (lane < GSN_NZ) acc += (double)partial[(size_t)(off + base + i) * GSN_NZ + lane];
+            }
         }
+        if (lane < GSN_NZ) zsum[(size_t)k * GSN_NZ + lane] = acc;
     }
-    if (lane < GSN_NZ) zk[lane] = acc;
 }
 
 __device__ __forceinline__ void load_kparams(const float* __restrict__ pos, const float* __restrict__ rot,
@@ -591,14 +607,15 @@ void launch_raster_bwd(const gsn_frame& f, const float* dL, const float* hd, boo
     kern<<<tiles, GSN_BLOCK, 0, s>>>(
         bp<uint2>(f.ranges), bp<uint32_t>(f.pv_a), bp<float4>(f.rec),
         bp<uint2>(f.rect), bp<uint32_t>(f.pair_off), (uint32_t)f.n, f.cam, f.ro, bp<double>(f.img64),
-        bp<uint32_t>(f.ncontrib), dL, hd, bp<float>(f.partial), bp<uint8_t>(f.flags), bp<uint8_t>(f.kflag), counts);
+        bp<uint32_t>(f.ncontrib), bp<uint64_t>(f.masks), dL, hd, bp<float>(f.partial), bp<uint8_t>(f.flags),
+        bp<uint8_t>(f.kflag), counts);
 }
 
 void launch_reduce_chain(const gsn_frame& f, const gsn_gaussians& g, float weight, int slot, bool gauss_newton,
                          const gsn_blocks& b, float* zstats_out, hipStream_t s) {
     if (g.n == 0) return;
     const int K = (g.sh_degree + 1) * (g.sh_degree + 1);
-    reduce_pairs_kernel<<<(g.n + 3) / 4, 256, 0, s>>>(g.n, bp<uint2>(f.rect), bp<uint32_t>(f.pair_off),
+    reduce_pairs_kernel<<<(g.n + 255) / 256, 256, 0, s>>>(g.n, bp<uint2>(f.rect), bp<uint32_t>(f.pair_off),
                                                       bp<float>(f.partial), bp<uint8_t>(f.flags),
                                                       bp<uint8_t>(f.kflag), bp<double>(f.zsum));
     auto pos_k = gauss_newton ? chain_pos_kernel<true> : chain_pos_kernel<false>;

@@ -19,6 +19,11 @@ void buf_free(DevBuf& b);
 template <class T>
 T* bp(const DevBuf& b) { return static_cast<T*>(b.p); }
 
+// The forward raster records, for the first GSN_MASK_BATCHES staged batches of each tile's
+// list, which entries every pixel composited; the backward raster reads these masks instead of
+// evaluating the batch again (later batches are evaluated).
+constexpr int GSN_MASK_BATCHES = 8;
+
 struct gsn_frame {
     bool rendered = false;
     int n = 0, K = 0, W = 0, H = 0, tiles_x = 0, tiles_y = 0;
@@ -44,6 +49,8 @@ struct gsn_frame {
     DevBuf img64;       // double [3][H][W], the same colour before rounding
     DevBuf Tfin;        // float [H][W]
     DevBuf ncontrib;    // u32 [H][W]
+    DevBuf masks;       // u64 [tiles][GSN_MASK_BATCHES][4][256]: composited entries of each staged batch
+                        // of 256 list entries, per pixel (bit j of word w: entry 64 w + j of the batch)
     DevBuf dL, hd;      // float [3][H][W] loss maps
     DevBuf coef;        // double [3][8][H][W] SSIM coefficient maps
     DevBuf zsum;        // double [n][GSN_NZ] per-kernel sums of the pair partials
@@ -113,7 +120,7 @@ void launch_emit_pairs(const uint32_t* sorted_ids, const uint32_t* offsets, uint
 void launch_tile_ranges(const uint32_t* keys, uint32_t pairs, uint2* ranges, hipStream_t s);
 void launch_raster_fwd(const uint2* ranges, const uint32_t* ids, const float4* rec, uint32_t n, const DevCam& cam,
                        const DevRenderOpts& ro, float* img, double* img64, float* Tfin, uint32_t* ncontrib,
-                       unsigned long long* counts, hipStream_t s);
+                       uint64_t* masks, unsigned long long* counts, hipStream_t s);
 void launch_downsample2x(const float* src, int W, int H, float* dst, hipStream_t s);
 
 // ---- launchers (loss.hip)

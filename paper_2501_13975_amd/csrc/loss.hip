@@ -17,8 +17,8 @@
 //
 // Pass 1 (one workgroup per 16x16 tile of window centres and channel): moments
 // by separable convolution through LDS, then the eight coefficient maps and the
-// loss partial sums (double).  Pass 2: the eight correlations and the per-pixel
-// gradient dL and diagonal Hessian h.  Pass 3: double-precision reduction of
+// loss partial sums (double).  Pass 2 (32x32 tiles, one map at a time): the eight
+// correlations and the per-pixel gradient dL and diagonal Hessian h.  Pass 3: double-precision reduction of
 // the loss partials in a fixed order.
 #include "gsn_internal.h"
 
@@ -137,54 +137,75 @@ __global__ __launch_bounds__(256) void ssim_coef_kernel(const float* __restrict_
     }
 }
 
+// Pass 2 on 32 x 32 pixel tiles, one coefficient map at a time (the 42 x 42 halo tile of the map
+// and its horizontal correlation in LDS): each thread owns four pixels of a column and keeps
+// their eight correlations in registers.  Halo reads are 1.7x the map instead of 2.6x with 16 x 16
+// tiles, and the small LDS footprint keeps several workgroups per CU.
+constexpr int T2 = 32, R2 = T2 + 2 * HALO;  // 42
+
 __global__ __launch_bounds__(256) void ssim_grad_kernel(const float* __restrict__ img, const float* __restrict__ tgt,
                                                          int W, int H, float lambda, const double* __restrict__ coef,
                                                          float* __restrict__ dL, float* __restrict__ hd) {
     __shared__ double g[11], g2[11];
-    __shared__ double sm[8][R][R];
-    __shared__ double hs[8][R][T];
+    __shared__ double sm[R2][R2];
+    __shared__ double hs[R2][T2];
     const int ch = blockIdx.z;
-    const int x0 = blockIdx.x * T - HALO, y0 = blockIdx.y * T - HALO;
+    const int x0 = blockIdx.x * T2 - HALO, y0 = blockIdx.y * T2 - HALO;
     const size_t np = (size_t)W * H;
     const double* cf = coef + (size_t)ch * 8 * np;
     window_weights(g, g2);
-    for (int i = threadIdx.x; i < R * R; i += 256) {
-        const int yy = i / R, xx = i % R, x = x0 + xx, y = y0 + yy;
-        const bool in = x >= 0 && y >= 0 && x < W && y < H;
-        const size_t pi = (size_t)y * W + x;
+    const int lx = threadIdx.x % T2, ly0 = threadIdx.x / T2;  // rows ly0 + 8 r, r = 0..3
+    // d1 = v0 + t v1 - c v2 and d2 = v3 + t v4 + c v5 + c^2 v6 + c t v7 - v2 are linear in the
+    // correlations v_q, so each map's correlation is folded in as soon as it is taken
+    double cv[4], tv[4], d1[4], d2[4];
 #pragma unroll
-        for (int q = 0; q < 8; ++q) sm[q][yy][xx] = in ? cf[q * np + pi] : 0.0;
+    for (int r = 0; r < 4; ++r) {
+        const int x = blockIdx.x * T2 + lx, y = blockIdx.y * T2 + ly0 + 8 * r;
+        const bool in = x < W && y < H;
+        const size_t pi = in ? (size_t)y * W + x : 0;
+        cv[r] = in ? (double)img[ch * np + pi] : 0.0;
+        tv[r] = in ? (double)tgt[ch * np + pi] : 0.0;
+        d1[r] = d2[r] = 0.0;
     }
-    __syncthreads();
-    for (int i = threadIdx.x; i < R * T; i += 256) {
-        const int yy = i / T, xx = i % T;
-#pragma unroll
-        for (int q = 0; q < 8; ++q) {
+    for (int q = 0; q < 8; ++q) {
+        const double* map = cf + (size_t)q * np;
+        for (int i = threadIdx.x; i < R2 * R2; i += 256) {
+            const int yy = i / R2, xx = i % R2, x = x0 + xx, y = y0 + yy;
+            const bool in = x >= 0 && y >= 0 && x < W && y < H;
+            sm[yy][xx] = in ? map[(size_t)y * W + x] : 0.0;
+        }
+        __syncthreads();
+        const double* wq = q < 3 ? g : g2;
+        for (int i = threadIdx.x; i < R2 * T2; i += 256) {
+            const int yy = i / T2, xx = i % T2;
             double a = 0.0;
 #pragma unroll
-            for (int k = 0; k < 11; ++k) a += (q < 3 ? g[k] : g2[k]) * sm[q][yy][xx + k];
-            hs[q][yy][xx] = a;
+            for (int k = 0; k < 11; ++k) a += wq[k] * sm[yy][xx + k];
+            hs[yy][xx] = a;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int ly = ly0 + 8 * r;
+            double a = 0.0;
+#pragma unroll
+            for (int k = 0; k < 11; ++k) a += wq[k] * hs[ly + k][lx];
+            const double c = cv[r], t = tv[r];
+            const double k1 = q == 0 ? 1.0 : q == 1 ? t : q == 2 ? -c : 0.0;
+            const double k2 = q < 2 ? 0.0 : q == 2 ? -1.0 : q == 3 ? 1.0 : q == 4 ? t : q == 5 ? c : q == 6 ? c * c : c * t;
+            d1[r] += k1 * a;
+            d2[r] += k2 * a;
         }
     }
-    __syncthreads();
-    const int lx = threadIdx.x % T, ly = threadIdx.x / T;
-    const int x = blockIdx.x * T + lx, y = blockIdx.y * T + ly;
-    if (x >= W || y >= H) return;
-    double v[8];
-#pragma unroll
-    for (int q = 0; q < 8; ++q) {
-        double a = 0.0;
-#pragma unroll
-        for (int k = 0; k < 11; ++k) a += (q < 3 ? g[k] : g2[k]) * hs[q][ly + k][lx];
-        v[q] = a;
-    }
-    const size_t pi = (size_t)y * W + x;
-    const double c = img[ch * np + pi], t = tgt[ch * np + pi];
     const double norm = 1.0 / (3.0 * (double)np);
-    const double d1 = v[0] + t * v[1] - c * v[2];
-    const double d2 = v[3] + t * v[4] + c * v[5] + c * c * v[6] + c * t * v[7] - v[2];
-    dL[ch * np + pi] = (float)((c - t) * norm - (double)lambda * norm * d1);
-    hd[ch * np + pi] = (float)(norm - (double)lambda * norm * d2);
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        const int x = blockIdx.x * T2 + lx, y = blockIdx.y * T2 + ly0 + 8 * r;
+        if (x >= W || y >= H) continue;
+        const size_t pi = (size_t)y * W + x;
+        dL[ch * np + pi] = (float)((cv[r] - tv[r]) * norm - (double)lambda * norm * d1[r]);
+        hd[ch * np + pi] = (float)(norm - (double)lambda * norm * d2[r]);
+    }
 }
 
 __global__ void loss_reduce_kernel(const double* __restrict__ part, int nparts, double npix, double* __restrict__ out) {
@@ -217,7 +238,8 @@ void launch_loss_maps(const float* img, const float* tgt, int W, int H, float la
     dim3 grid((W + T - 1) / T, (H + T - 1) / T, 3);
     *nparts = (int)(grid.x * grid.y * grid.z);
     ssim_coef_kernel<<<grid, 256, 0, s>>>(img, tgt, W, H, coef, part);
-    ssim_grad_kernel<<<grid, 256, 0, s>>>(img, tgt, W, H, lambda, coef, dL, hd);
+    dim3 grid2((W + T2 - 1) / T2, (H + T2 - 1) / T2, 3);
+    ssim_grad_kernel<<<grid2, 256, 0, s>>>(img, tgt, W, H, lambda, coef, dL, hd);
 }
 
 void launch_loss_reduce(const double* part, int nparts, int W, int H, double* out, hipStream_t s) {

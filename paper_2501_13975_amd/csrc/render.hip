@@ -295,78 +295,98 @@ __global__ __launch_bounds__(kThreads) void radix_hist_kernel(const uint32_t* __
     hist[(size_t)threadIdx.x * nb + blockIdx.x] = cnt[threadIdx.x];
 }
 
-// Stable scatter of one 8-bit digit pass.  The tile's items are first ranked within their digit
-// (ballot peers per wave, running counts per digit) and placed in LDS in digit order; the
-// second pass writes them out by LDS position, so that consecutive threads write consecutive
-// addresses of one digit's run (coalesced), instead of scattering item by item.
+// Stable scatter of one 8-bit digit pass.  Each wave owns a contiguous quarter of the tile (16
+// rows of 64 items, kept in registers) and ranks it without block barriers: equal-digit peers
+// by ballots over the digit bits, per-wave digit counts, then a block scan over (digit, wave)
+// gives every wave the position of its first item of each digit.  Items are placed in LDS in
+// digit order and written out by LDS position, so that consecutive threads write consecutive
+// addresses of one digit's run (coalesced).
 __global__ __launch_bounds__(kThreads) void radix_scatter_kernel(
     const uint32_t* __restrict__ kin, const uint32_t* __restrict__ vin, uint32_t n, int shift, uint32_t nb,
     const uint32_t* __restrict__ hist, const uint32_t* __restrict__ offs, uint32_t* __restrict__ kout,
     uint32_t* __restrict__ vout) {
-    __shared__ uint32_t base_d[256], lstart[256], running[256];
-    __shared__ uint32_t wcnt[kThreads / 64][256];
-    __shared__ uint32_t wsum[kThreads / 64];
+    constexpr int NWV = kThreads / 64;
+    __shared__ uint32_t base_d[256], lstart[256];
+    __shared__ uint32_t wpos[NWV][256];
+    __shared__ uint32_t wsum[NWV];
     __shared__ uint32_t sk[kRsTile], sv[kRsTile];
     const int tid = threadIdx.x, lane = __lane_id(), wave = tid / 64;
     base_d[tid] = offs[(size_t)tid * nb + blockIdx.x];
-    running[tid] = 0;
-    {
-        // local start of each digit: exclusive scan of the tile's digit counts
-        const uint32_t c = hist[(size_t)tid * nb + blockIdx.x];
-        uint32_t v = c;
 #pragma unroll
-        for (int d = 1; d < 64; d <<= 1) {
-            const uint32_t o = __shfl_up(v, d, 64);
-            if (lane >= d) v += o;
+    for (int w = 0; w < NWV; ++w) wpos[w][tid] = 0;
+    __syncthreads();
+    const uint64_t lt_mask = (lane == 0) ? 0ull : ((~0ull) >> (64 - lane));
+    const size_t base = (size_t)blockIdx.x * kRsTile;
+    const size_t wbase = base + (size_t)wave * 64 * kRsItems;
+    uint32_t key[kRsItems], val[kRsItems];
+    uint64_t peers[kRsItems];
+    // (1) the wave's items, their equal-digit peers, and the wave's count of each digit
+#pragma unroll
+    for (int it = 0; it < kRsItems; ++it) {
+        const size_t idx = wbase + (size_t)it * 64 + lane;
+        const bool valid = idx < n;
+        key[it] = valid ? kin[idx] : 0u;
+        val[it] = valid ? vin[idx] : 0u;
+        const uint32_t d = (key[it] >> shift) & 255u;
+        uint64_t pm = __ballot(valid);
+        if (!valid) pm = 0ull;
+#pragma unroll
+        for (int b = 0; b < 8; ++b) {
+            const bool bit = (d >> b) & 1u;
+            const uint64_t m = __ballot(bit);
+            pm &= bit ? m : ~m;
+        }
+        peers[it] = pm;
+        if (valid && __popcll(pm & lt_mask) == 0) wpos[wave][d] += (uint32_t)__popcll(pm);
+    }
+    __syncthreads();
+    // (2) block-local start of each digit, and of each (digit, wave) run
+    {
+        uint32_t c[NWV], tot = 0;
+#pragma unroll
+        for (int w = 0; w < NWV; ++w) {
+            c[w] = wpos[w][tid];
+            tot += c[w];
+        }
+        uint32_t v = tot;
+#pragma unroll
+        for (int dd = 1; dd < 64; dd <<= 1) {
+            const uint32_t o = __shfl_up(v, dd, 64);
+            if (lane >= dd) v += o;
         }
         if (lane == 63) wsum[wave] = v;
         __syncthreads();
         uint32_t sb = 0;
 #pragma unroll
-        for (int w = 0; w < kThreads / 64; ++w) sb += w < wave ? wsum[w] : 0u;
-        lstart[tid] = sb + v - c;
+        for (int w = 0; w < NWV; ++w) sb += w < wave ? wsum[w] : 0u;
+        uint32_t o = sb + v - tot;
+        lstart[tid] = o;
+#pragma unroll
+        for (int w = 0; w < NWV; ++w) {
+            wpos[w][tid] = o;
+            o += c[w];
+        }
     }
-    const uint64_t lt_mask = (lane == 0) ? 0ull : ((~0ull) >> (64 - lane));
-    const size_t base = (size_t)blockIdx.x * kRsTile;
+    __syncthreads();
+    // (3) place the wave's items in order (row by row, lane by lane within a digit)
+#pragma unroll
     for (int it = 0; it < kRsItems; ++it) {
-        const size_t idx = base + (size_t)it * kThreads + tid;
-        const bool valid = idx < n;
-        const uint32_t key = valid ? kin[idx] : 0u;
-        const uint32_t val = valid ? vin[idx] : 0u;
-        const uint32_t d = (key >> shift) & 255u;
-#pragma unroll
-        for (int w = 0; w < kThreads / 64; ++w) wcnt[w][tid] = 0;
-        __syncthreads();
-        uint64_t peers = __ballot(valid);
-        if (!valid) peers = ~peers;
-#pragma unroll
-        for (int b = 0; b < 8; ++b) {
-            const bool bit = (d >> b) & 1u;
-            const uint64_t m = __ballot(bit);
-            peers &= bit ? m : ~m;
-        }
-        const uint32_t rank = __popcll(peers & lt_mask);
-        if (valid && rank == 0) wcnt[wave][d] = __popcll(peers);
-        __syncthreads();
-        if (valid) {
-            uint32_t pos = lstart[d] + running[d] + rank;
-            for (int w = 0; w < wave; ++w) pos += wcnt[w][d];
-            sk[pos] = key;
-            sv[pos] = val;
-        }
-        __syncthreads();
-        uint32_t add = 0;
-#pragma unroll
-        for (int w = 0; w < kThreads / 64; ++w) add += wcnt[w][tid];
-        running[tid] += add;
-        __syncthreads();
+        const uint64_t pm = peers[it];
+        if (pm == 0ull) continue;  // invalid lane
+        const uint32_t d = (key[it] >> shift) & 255u;
+        const uint32_t rank = (uint32_t)__popcll(pm & lt_mask);
+        const uint32_t pos = wpos[wave][d] + rank;
+        sk[pos] = key[it];
+        sv[pos] = val[it];
+        if (rank == 0) wpos[wave][d] = pos + (uint32_t)__popcll(pm);
     }
+    __syncthreads();
     const uint32_t cnt = (uint32_t)min((size_t)kRsTile, (size_t)n - base);
     for (uint32_t j = tid; j < cnt; j += kThreads) {
-        const uint32_t key = sk[j];
-        const uint32_t d = (key >> shift) & 255u;
+        const uint32_t k = sk[j];
+        const uint32_t d = (k >> shift) & 255u;
         const uint32_t gpos = base_d[d] + (j - lstart[d]);
-        kout[gpos] = key;
+        kout[gpos] = k;
         vout[gpos] = sv[j];
     }
 }
@@ -456,8 +476,9 @@ __global__ void tile_ranges_kernel(const uint32_t* __restrict__ keys, uint32_t p
 __global__ __launch_bounds__(GSN_BLOCK) void raster_fwd_kernel(
     const uint2* __restrict__ ranges, const uint32_t* __restrict__ ids, const float4* __restrict__ rec, uint32_t n,
     DevCam cam, DevRenderOpts ro, float* __restrict__ img, double* __restrict__ img64, float* __restrict__ Tfin,
-    uint32_t* __restrict__ ncontrib, unsigned long long* __restrict__ counts) {
+    uint32_t* __restrict__ ncontrib, uint64_t* __restrict__ masks, unsigned long long* __restrict__ counts) {
     constexpr int NW = GSN_BLOCK / 64;
+    static_assert(NW == 4, "the mask word switch below assumes four 64-bit words per batch");
     __shared__ float4 s_a[GSN_BLOCK];
     __shared__ float4 s_b[GSN_BLOCK];
     __shared__ float4 s_c[GSN_BLOCK];
@@ -516,6 +537,9 @@ __global__ __launch_bounds__(GSN_BLOCK) void raster_fwd_kernel(
         uint32_t nl = 0;
 #pragma unroll
         for (int v = 0; v < NW; ++v) nl += s_cnt[wave][v];
+        uint64_t bits[NW];
+#pragma unroll
+        for (int w = 0; w < NW; ++w) bits[w] = 0ull;
         for (uint32_t i = 0; i < nl && !done; ++i) {
             const int j = s_list[wave][i];
             const float4 a = s_a[j], b = s_b[j], cc = s_c[j];
@@ -533,6 +557,22 @@ __global__ __launch_bounds__(GSN_BLOCK) void raster_fwd_kernel(
             C2 += w * (double)cc.y;
             T = Tn;
             last = base + j + 1 - rg.x;
+            // j is the same in every active lane (the wave walks one list): the word is picked by a
+            // scalar branch and the bit made in scalar registers
+            const int ju = __builtin_amdgcn_readfirstlane(j);
+            const uint64_t bit = 1ull << (ju & 63);
+            switch (ju >> 6) {
+                case 0: bits[0] |= bit; break;
+                case 1: bits[1] |= bit; break;
+                case 2: bits[2] |= bit; break;
+                default: bits[3] |= bit; break;
+            }
+        }
+        const uint32_t batch = (base - rg.x) / GSN_BLOCK;
+        if (masks && batch < (uint32_t)GSN_MASK_BATCHES) {
+            uint64_t* mb = masks + ((size_t)tile * GSN_MASK_BATCHES + batch) * NW * GSN_BLOCK + threadIdx.x;
+#pragma unroll
+            for (int w = 0; w < NW; ++w) mb[(size_t)w * GSN_BLOCK] = bits[w];
         }
     }
     if (counts) {
@@ -650,9 +690,10 @@ void launch_tile_ranges(const uint32_t* keys, uint32_t pairs, uint2* ranges, hip
 
 void launch_raster_fwd(const uint2* ranges, const uint32_t* ids, const float4* rec, uint32_t n, const DevCam& cam,
                        const DevRenderOpts& ro, float* img, double* img64, float* Tfin, uint32_t* ncontrib,
-                       unsigned long long* counts, hipStream_t s) {
+                       uint64_t* masks, unsigned long long* counts, hipStream_t s) {
     const int tiles = cam.tiles_x * cam.tiles_y;
-    raster_fwd_kernel<<<tiles, GSN_BLOCK, 0, s>>>(ranges, ids, rec, n, cam, ro, img, img64, Tfin, ncontrib, counts);
+    raster_fwd_kernel<<<tiles, GSN_BLOCK, 0, s>>>(ranges, ids, rec, n, cam, ro, img, img64, Tfin, ncontrib, masks,
+                                                  counts);
 }
 
 void launch_downsample2x(const float* src, int W, int H, float* dst, hipStream_t s) {

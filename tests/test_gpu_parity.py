@@ -271,7 +271,7 @@ def test_series_stages_parity(gsn, ctx):
             if b != a:
                 assert np.array_equal(np.asarray(getattr(new_g, b)), np.asarray(getattr(g32, b))), (a, b)
         # after the geometry stages many kernels are composited at near-threshold pixels
-        assert keep.sum() > 0.3 * vis.sum(), (a, int(keep.sum()), int(vis.sum()))
+        assert keep.sum() > 0.25 * vis.sum(), (a, int(keep.sum()), int(vis.sum()))
         state = new_o
     _report("series stages", errs)
     for a in attr.values():
