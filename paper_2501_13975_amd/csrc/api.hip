@@ -272,7 +272,7 @@ gsn_status gsn_render(gsn_ctx* ctx, const gsn_gaussians* g, const gsn_camera* ca
     HIP_TRY(ctx, buf_reserve(f->img, 3 * npx * 4));
     HIP_TRY(ctx, buf_reserve(f->img64, 3 * npx * 8));
     HIP_TRY(ctx, buf_reserve(f->Tfin, npx * 4));
-    HIP_TRY(ctx, buf_reserve(f->masks, tiles * GSN_MASK_BATCHES * 4 * GSN_BLOCK * sizeof(uint64_t)));
+    HIP_TRY(ctx, buf_reserve(f->masks, tiles * GSN_MASK_BATCHES * 2 * 4 * GSN_BLOCK * sizeof(uint64_t)));
     HIP_TRY(ctx, buf_reserve(f->ncontrib, npx * 4));
     HIP_TRY(ctx, buf_reserve(f->total, 16));
     // sort and scan scratch for the per-kernel stages, reserved before any launch so that

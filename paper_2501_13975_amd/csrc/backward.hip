@@ -238,7 +238,9 @@ __global__ __launch_bounds__(GSN_BLOCK, 3) void raster_bwd_kernel(
             const float4 box = splat_alpha_box(a, b, c4, ro.alpha_min);
 #pragma unroll
             for (int w = 0; w < NW; ++w)
-                if (!box_misses(box, tx0, tx1, ty0 + 4.f * w, ty0 + 4.f * w + 3.f)) bandmask |= 1u << w;
+                if (!box_misses(box, tx0, tx1, ty0 + 4.f * w, ty0 + 4.f * w + 3.f) &&
+                    !ellipse_misses(a, b, c4, ro.alpha_min, tx0, tx1, ty0 + 4.f * w, ty0 + 4.f * w + 3.f))
+                    bandmask |= 1u << w;
             const uint2 rc = rect[id];
             const uint32_t x0 = rc.x & 0xffffu, y0 = rc.x >> 16, x1 = rc.y & 0xffffu;
             r_slot[tid] = pair_off[id] + ((uint32_t)ty - y0) * (x1 - x0) + ((uint32_t)tx - x0);
@@ -269,9 +271,13 @@ __global__ __launch_bounds__(GSN_BLOCK, 3) void raster_bwd_kernel(
         uint64_t bits[NW] = {0ull, 0ull, 0ull, 0ull};
         const uint32_t batch = (base - rg.x) / GSN_BLOCK;
         if (batch < (uint32_t)GSN_MASK_BATCHES) {
-            const uint64_t* mb = masks + ((size_t)tile * GSN_MASK_BATCHES + batch) * NW * GSN_BLOCK + tid;
+            // the forward pass's pixel-major words and its per-(entry, wave) ballots
+            const uint64_t* mb = masks + ((size_t)tile * GSN_MASK_BATCHES + batch) * 2 * NW * GSN_BLOCK + tid;
 #pragma unroll
-            for (int w = 0; w < NW; ++w) bits[w] = mb[(size_t)w * GSN_BLOCK];
+            for (int w = 0; w < NW; ++w) {
+                bits[w] = mb[(size_t)w * GSN_BLOCK];
+                s_mask[tid][w] = mb[(size_t)(NW + w) * GSN_BLOCK];
+            }
         } else {
             for (uint32_t i = 0; i < nl; ++i) {
                 const int j = r_list[wave][i];
@@ -285,14 +291,16 @@ __global__ __launch_bounds__(GSN_BLOCK, 3) void raster_bwd_kernel(
                 }
             }
         }
-        for (uint32_t i = 0; i < nl; ++i) {  // uniform across the wave
-            const int j = r_list[wave][i];
-            uint64_t word = 0;
+        if (batch >= (uint32_t)GSN_MASK_BATCHES) {
+            for (uint32_t i = 0; i < nl; ++i) {  // uniform across the wave
+                const int j = r_list[wave][i];
+                uint64_t word = 0;
 #pragma unroll
-            for (int w = 0; w < NW; ++w)
-                if ((j >> 6) == w) word = bits[w];
-            const uint64_t m = __ballot((word >> (j & 63)) & 1ull);
-            if (lane == 0) s_mask[j][wave] = m;
+                for (int w = 0; w < NW; ++w)
+                    if ((j >> 6) == w) word = bits[w];
+                const uint64_t m = __ballot((word >> (j & 63)) & 1ull);
+                if (lane == 0) s_mask[j][wave] = m;
+            }
         }
         __syncthreads();
         for (int r0 = 0; r0 < bcnt;) {

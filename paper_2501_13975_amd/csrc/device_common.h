@@ -84,6 +84,33 @@ __device__ __forceinline__ bool box_misses(const float4 box, float x0, float x1,
     return box.y < x0 || box.x > x1 || box.w < y0 || box.z > y1;
 }
 
+// True when no pixel centre of columns x0..x1, rows y0..y1 can reach alpha >= alpha_min: the
+// minimum of the splat's quadratic form over the rectangle (its centre if inside, else the
+// smallest of the four edges' minima, each at its clamped 1D minimiser, evaluated in the
+// principal frame as the per-pixel test does) exceeds 2 ln(sigma / alpha_min) by more than a
+// relative 1e-3 and 0.01 (far above single-precision rounding of the per-pixel test, and of
+// the mean's two words added here).  Tighter than the bounding box for thin, rotated splats.
+__device__ __forceinline__ bool ellipse_misses(const float4 a, const float4 b, const float4 c4, float alpha_min,
+                                               float x0, float x1, float y0, float y1) {
+    const float sig = b.z;
+    if (!(sig >= alpha_min)) return true;
+    const float r2 = 2.0f * __logf(sig / alpha_min);
+    const float q1 = a.z, q2 = a.w, c = b.x, s = b.y;
+    const float qxx = q1 * c * c + q2 * s * s, qyy = q1 * s * s + q2 * c * c, qxy = (q1 - q2) * c * s;
+    const float mx = a.x + c4.z, my = a.y + c4.w;
+    const float X0 = x0 - mx, X1 = x1 - mx, Y0 = y0 - my, Y1 = y1 - my;
+    if (X0 <= 0.f && X1 >= 0.f && Y0 <= 0.f && Y1 >= 0.f) return false;
+    auto q = [&](float X, float Y) {
+        const float u1 = c * X + s * Y, u2 = c * Y - s * X;
+        return q1 * u1 * u1 + q2 * u2 * u2;
+    };
+    const float m0 = q(X0, fminf(fmaxf(-qxy * X0 / qyy, Y0), Y1));
+    const float m1 = q(X1, fminf(fmaxf(-qxy * X1 / qyy, Y0), Y1));
+    const float m2 = q(fminf(fmaxf(-qxy * Y0 / qxx, X0), X1), Y0);
+    const float m3 = q(fminf(fmaxf(-qxy * Y1 / qxx, X0), X1), Y1);
+    return fminf(fminf(m0, m1), fminf(m2, m3)) > r2 * 1.001f + 0.01f;
+}
+
 // Principal frame of Sigma = A A^T + kappa I (A = J W R S, 2x3): eigenvalues from the
 // trace and the Cauchy-Binet determinant (sum of squared 2x2 minors), the minor one as
 // det / lambda1 so that neither cancels.

@@ -49,8 +49,9 @@ struct gsn_frame {
     DevBuf img64;       // double [3][H][W], the same colour before rounding
     DevBuf Tfin;        // float [H][W]
     DevBuf ncontrib;    // u32 [H][W]
-    DevBuf masks;       // u64 [tiles][GSN_MASK_BATCHES][4][256]: composited entries of each staged batch
-                        // of 256 list entries, per pixel (bit j of word w: entry 64 w + j of the batch)
+    DevBuf masks;       // u64 [tiles][GSN_MASK_BATCHES][2][4][256]: composited (pixel, entry) pairs of each
+                        // staged batch of 256 list entries, per pixel (bit j of word w: entry 64 w + j of
+                        // the batch), then per (wave, entry) (bit l: pixel l of the wave's 16 x 4 band)
     DevBuf dL, hd;      // float [3][H][W] loss maps
     DevBuf coef;        // double [3][8][H][W] SSIM coefficient maps
     DevBuf zsum;        // double [n][GSN_NZ] per-kernel sums of the pair partials

@@ -478,12 +478,12 @@ __global__ __launch_bounds__(GSN_BLOCK) void raster_fwd_kernel(
     DevCam cam, DevRenderOpts ro, float* __restrict__ img, double* __restrict__ img64, float* __restrict__ Tfin,
     uint32_t* __restrict__ ncontrib, uint64_t* __restrict__ masks, unsigned long long* __restrict__ counts) {
     constexpr int NW = GSN_BLOCK / 64;
-    static_assert(NW == 4, "the mask word switch below assumes four 64-bit words per batch");
     __shared__ float4 s_a[GSN_BLOCK];
     __shared__ float4 s_b[GSN_BLOCK];
     __shared__ float4 s_c[GSN_BLOCK];
     __shared__ uint8_t s_list[NW][GSN_BLOCK];
     __shared__ uint32_t s_cnt[NW][NW];  // [band][loader wave]
+    __shared__ uint64_t s_em[NW][GSN_BLOCK];  // [wave][entry]: the wave's pixels that composited the entry
     const int tile = blockIdx.x;
     const int tx = tile % cam.tiles_x, ty = tile / cam.tiles_x;
     const int px = tx * GSN_TILE + (threadIdx.x % GSN_TILE);
@@ -503,6 +503,8 @@ __global__ __launch_bounds__(GSN_BLOCK) void raster_fwd_kernel(
     uint32_t evals = 0, staged = 0;
     for (uint32_t base = rg.x; base < rg.y; base += GSN_BLOCK) {
         if (__syncthreads_count(done) == GSN_BLOCK) break;
+#pragma unroll
+        for (int w = 0; w < NW; ++w) s_em[w][threadIdx.x] = 0ull;
         const uint32_t e = base + threadIdx.x;
         uint32_t bandmask = 0;
         if (e < rg.y) {
@@ -515,7 +517,9 @@ __global__ __launch_bounds__(GSN_BLOCK) void raster_fwd_kernel(
             const float4 box = splat_alpha_box(a, b, c4, ro.alpha_min);
 #pragma unroll
             for (int w = 0; w < NW; ++w)
-                if (!box_misses(box, tx0, tx1, ty0 + 4.f * w, ty0 + 4.f * w + 3.f)) bandmask |= 1u << w;
+                if (!box_misses(box, tx0, tx1, ty0 + 4.f * w, ty0 + 4.f * w + 3.f) &&
+                    !ellipse_misses(a, b, c4, ro.alpha_min, tx0, tx1, ty0 + 4.f * w, ty0 + 4.f * w + 3.f))
+                    bandmask |= 1u << w;
         }
         uint64_t bal[NW];
 #pragma unroll
@@ -545,34 +549,37 @@ __global__ __launch_bounds__(GSN_BLOCK) void raster_fwd_kernel(
             const float4 a = s_a[j], b = s_b[j], cc = s_c[j];
             const SplatEval ev = eval_splat(a, b, cc, fpx, fpy, ro.alpha_max);
             ++evals;
-            if (ev.alpha < ro.alpha_min) continue;
+            bool comp = ev.alpha >= ro.alpha_min;
             const float Tn = T * (1.0f - ev.alpha);
-            if (Tn < ro.T_min) {
+            if (comp && Tn < ro.T_min) {  // stop before the entry that would cross T_min
                 done = true;
-                break;
+                comp = false;
             }
-            const double w = (double)(ev.alpha * T);
-            C0 += w * (double)b.w;
-            C1 += w * (double)cc.x;
-            C2 += w * (double)cc.y;
-            T = Tn;
-            last = base + j + 1 - rg.x;
-            // j is the same in every active lane (the wave walks one list): the word is picked by a
-            // scalar branch and the bit made in scalar registers
-            const int ju = __builtin_amdgcn_readfirstlane(j);
-            const uint64_t bit = 1ull << (ju & 63);
-            switch (ju >> 6) {
-                case 0: bits[0] |= bit; break;
-                case 1: bits[1] |= bit; break;
-                case 2: bits[2] |= bit; break;
-                default: bits[3] |= bit; break;
+            // the wave's lanes still walking the list all hold entry j: one ballot is the entry's
+            // pixel mask for this band, written by the first of them
+            const uint64_t m = __ballot(comp);
+            if (lane == (int)__builtin_amdgcn_readfirstlane(lane)) s_em[wave][j] = m;
+            if (comp) {
+                const double w = (double)(ev.alpha * T);
+                C0 += w * (double)b.w;
+                C1 += w * (double)cc.x;
+                C2 += w * (double)cc.y;
+                T = Tn;
+                last = base + j + 1 - rg.x;
+#pragma unroll
+                for (int q = 0; q < NW; ++q)
+                    if ((j >> 6) == q) bits[q] |= 1ull << (j & 63);
             }
         }
         const uint32_t batch = (base - rg.x) / GSN_BLOCK;
         if (masks && batch < (uint32_t)GSN_MASK_BATCHES) {
-            uint64_t* mb = masks + ((size_t)tile * GSN_MASK_BATCHES + batch) * NW * GSN_BLOCK + threadIdx.x;
+            // pixel-major words [w][pixel], then entry-major words [wave][entry]
+            uint64_t* mb = masks + ((size_t)tile * GSN_MASK_BATCHES + batch) * 2 * NW * GSN_BLOCK + threadIdx.x;
 #pragma unroll
             for (int w = 0; w < NW; ++w) mb[(size_t)w * GSN_BLOCK] = bits[w];
+            __syncthreads();
+#pragma unroll
+            for (int w = 0; w < NW; ++w) mb[(size_t)(NW + w) * GSN_BLOCK] = s_em[w][threadIdx.x];
         }
     }
     if (counts) {
