@@ -138,8 +138,9 @@ __global__ __launch_bounds__(256) void ssim_coef_kernel(const float* __restrict_
 }
 
 // Pass 2 on 32 x 32 pixel tiles, one coefficient map at a time (the 42 x 42 halo tile of the map
-// and its horizontal correlation in LDS): each thread owns four pixels of a column and keeps
-// their eight correlations in registers.  Halo reads are 1.7x the map instead of 2.6x with 16 x 16
+// and its horizontal correlation in LDS): each thread owns four consecutive pixels of a column
+// and folds each map's correlation into their derivatives; both correlation passes work on
+// strips of four outputs that share their 14 inputs (a third of the LDS reads).  Halo reads are 1.7x the map instead of 2.6x with 16 x 16
 // tiles, and the small LDS footprint keeps several workgroups per CU.
 constexpr int T2 = 32, R2 = T2 + 2 * HALO;  // 42
 
@@ -154,13 +155,13 @@ __global__ __launch_bounds__(256) void ssim_grad_kernel(const float* __restrict_
     const size_t np = (size_t)W * H;
     const double* cf = coef + (size_t)ch * 8 * np;
     window_weights(g, g2);
-    const int lx = threadIdx.x % T2, ly0 = threadIdx.x / T2;  // rows ly0 + 8 r, r = 0..3
+    const int lx = threadIdx.x % T2, ly0 = 4 * (threadIdx.x / T2);  // rows ly0 .. ly0 + 3
     // d1 = v0 + t v1 - c v2 and d2 = v3 + t v4 + c v5 + c^2 v6 + c t v7 - v2 are linear in the
     // correlations v_q, so each map's correlation is folded in as soon as it is taken
     double cv[4], tv[4], d1[4], d2[4];
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
-        const int x = blockIdx.x * T2 + lx, y = blockIdx.y * T2 + ly0 + 8 * r;
+        const int x = blockIdx.x * T2 + lx, y = blockIdx.y * T2 + ly0 + r;
         const bool in = x < W && y < H;
         const size_t pi = in ? (size_t)y * W + x : 0;
         cv[r] = in ? (double)img[ch * np + pi] : 0.0;
@@ -176,20 +177,30 @@ __global__ __launch_bounds__(256) void ssim_grad_kernel(const float* __restrict_
         }
         __syncthreads();
         const double* wq = q < 3 ? g : g2;
-        for (int i = threadIdx.x; i < R2 * T2; i += 256) {
-            const int yy = i / T2, xx = i % T2;
-            double a = 0.0;
+        // horizontal: strips of four outputs share their 14 inputs
+        for (int i = threadIdx.x; i < R2 * (T2 / 4); i += 256) {
+            const int yy = i / (T2 / 4), xs = 4 * (i % (T2 / 4));
+            double in14[14];
 #pragma unroll
-            for (int k = 0; k < 11; ++k) a += wq[k] * sm[yy][xx + k];
-            hs[yy][xx] = a;
+            for (int k = 0; k < 14; ++k) in14[k] = sm[yy][xs + k];
+#pragma unroll
+            for (int o = 0; o < 4; ++o) {
+                double a = 0.0;
+#pragma unroll
+                for (int k = 0; k < 11; ++k) a += wq[k] * in14[o + k];
+                hs[yy][xs + o] = a;
+            }
         }
         __syncthreads();
+        // vertical: the thread's four rows share their 14 inputs
+        double col[14];
+#pragma unroll
+        for (int k = 0; k < 14; ++k) col[k] = hs[ly0 + k][lx];
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
-            const int ly = ly0 + 8 * r;
             double a = 0.0;
 #pragma unroll
-            for (int k = 0; k < 11; ++k) a += wq[k] * hs[ly + k][lx];
+            for (int k = 0; k < 11; ++k) a += wq[k] * col[r + k];
             const double c = cv[r], t = tv[r];
             const double k1 = q == 0 ? 1.0 : q == 1 ? t : q == 2 ? -c : 0.0;
             const double k2 = q < 2 ? 0.0 : q == 2 ? -1.0 : q == 3 ? 1.0 : q == 4 ? t : q == 5 ? c : q == 6 ? c * c : c * t;
@@ -200,7 +211,7 @@ __global__ __launch_bounds__(256) void ssim_grad_kernel(const float* __restrict_
     const double norm = 1.0 / (3.0 * (double)np);
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
-        const int x = blockIdx.x * T2 + lx, y = blockIdx.y * T2 + ly0 + 8 * r;
+        const int x = blockIdx.x * T2 + lx, y = blockIdx.y * T2 + ly0 + r;
         if (x >= W || y >= H) continue;
         const size_t pi = (size_t)y * W + x;
         dL[ch * np + pi] = (float)((cv[r] - tv[r]) * norm - (double)lambda * norm * d1[r]);

@@ -295,6 +295,34 @@ __global__ __launch_bounds__(kThreads) void radix_hist_kernel(const uint32_t* __
     hist[(size_t)threadIdx.x * nb + blockIdx.x] = cnt[threadIdx.x];
 }
 
+// Exclusive scan of one digit's counts over the workgroups of a pass (one workgroup per digit,
+// kScanTile counts per step with a running carry), and the digit's total.  The scatter adds
+// the exclusive prefix of the 256 digit totals itself, so a pass is three launches.
+__global__ __launch_bounds__(kThreads) void radix_colscan_kernel(const uint32_t* __restrict__ hist, uint32_t nb,
+                                                                  uint32_t* __restrict__ offs,
+                                                                  uint32_t* __restrict__ dtot) {
+    const size_t row = (size_t)blockIdx.x * nb;
+    uint32_t carry = 0;
+    for (uint32_t b0 = 0; b0 < nb; b0 += kScanTile) {  // uniform across the block
+        const uint32_t i0 = b0 + threadIdx.x * kScanItems;
+        uint32_t v[kScanItems], sum = 0;
+#pragma unroll
+        for (int i = 0; i < kScanItems; ++i) {
+            v[i] = i0 + i < nb ? hist[row + i0 + i] : 0u;
+            sum += v[i];
+        }
+        uint32_t tot;
+        uint32_t off = carry + block_excl_scan(sum, &tot);
+#pragma unroll
+        for (int i = 0; i < kScanItems; ++i) {
+            if (i0 + i < nb) offs[row + i0 + i] = off;
+            off += v[i];
+        }
+        carry += tot;
+    }
+    if (threadIdx.x == 0) dtot[blockIdx.x] = carry;
+}
+
 // Stable scatter of one 8-bit digit pass.  Each wave owns a contiguous quarter of the tile (16
 // rows of 64 items, kept in registers) and ranks it without block barriers: equal-digit peers
 // by ballots over the digit bits, per-wave digit counts, then a block scan over (digit, wave)
@@ -303,7 +331,7 @@ __global__ __launch_bounds__(kThreads) void radix_hist_kernel(const uint32_t* __
 // addresses of one digit's run (coalesced).
 __global__ __launch_bounds__(kThreads) void radix_scatter_kernel(
     const uint32_t* __restrict__ kin, const uint32_t* __restrict__ vin, uint32_t n, int shift, uint32_t nb,
-    const uint32_t* __restrict__ hist, const uint32_t* __restrict__ offs, uint32_t* __restrict__ kout,
+    const uint32_t* __restrict__ offs, const uint32_t* __restrict__ dtot, uint32_t* __restrict__ kout,
     uint32_t* __restrict__ vout) {
     constexpr int NWV = kThreads / 64;
     __shared__ uint32_t base_d[256], lstart[256];
@@ -311,7 +339,11 @@ __global__ __launch_bounds__(kThreads) void radix_scatter_kernel(
     __shared__ uint32_t wsum[NWV];
     __shared__ uint32_t sk[kRsTile], sv[kRsTile];
     const int tid = threadIdx.x, lane = __lane_id(), wave = tid / 64;
-    base_d[tid] = offs[(size_t)tid * nb + blockIdx.x];
+    {
+        // global start of digit tid: the totals of the smaller digits, then this workgroup's offset
+        uint32_t tot;
+        base_d[tid] = block_excl_scan(dtot[tid], &tot) + offs[(size_t)tid * nb + blockIdx.x];
+    }
 #pragma unroll
     for (int w = 0; w < NWV; ++w) wpos[w][tid] = 0;
     __syncthreads();
@@ -653,19 +685,20 @@ hipError_t exclusive_scan_u32(const uint32_t* in, uint32_t* out, uint32_t n, uin
 
 hipError_t radix_sort_pairs(uint32_t* k0, uint32_t* v0, uint32_t* k1, uint32_t* v1, uint32_t n, int bit_lo,
                             int bit_hi, DevBuf& hist, DevBuf& scan_tmp, hipStream_t s) {
+    (void)scan_tmp;
     if (n == 0) return hipSuccess;
     const uint32_t nb = (n + kRsTile - 1) / kRsTile;
-    hipError_t e = buf_reserve(hist, (size_t)256 * nb * 4 * 2);
+    hipError_t e = buf_reserve(hist, ((size_t)256 * nb * 2 + 256) * 4);
     if (e != hipSuccess) return e;
     uint32_t* h = bp<uint32_t>(hist);
     uint32_t* o = h + (size_t)256 * nb;
+    uint32_t* dt = o + (size_t)256 * nb;
     int passes = 0;
     uint32_t *ka = k0, *va = v0, *kb = k1, *vb = v1;
     for (int shift = bit_lo; shift < bit_hi; shift += 8, ++passes) {
         radix_hist_kernel<<<nb, kThreads, 0, s>>>(ka, n, shift, nb, h);
-        e = exclusive_scan_u32(h, o, 256 * nb, nullptr, scan_tmp, s);
-        if (e != hipSuccess) return e;
-        radix_scatter_kernel<<<nb, kThreads, 0, s>>>(ka, va, n, shift, nb, h, o, kb, vb);
+        radix_colscan_kernel<<<256, kThreads, 0, s>>>(h, nb, o, dt);
+        radix_scatter_kernel<<<nb, kThreads, 0, s>>>(ka, va, n, shift, nb, o, dt, kb, vb);
         uint32_t* t = ka; ka = kb; kb = t;
         t = va; va = vb; vb = t;
     }
