@@ -44,7 +44,8 @@ constexpr int SG = 8, LG = 32;
 template <bool GN>
 __device__ __forceinline__ void pair_terms(const float4 a, const float4 b, float G, float T, const float av[3],
                                            float dx, float dy, const float dl[3], const float hh[3], float amax,
-                                           float* z) {
+                                           float* acc) {
+    // adds the pair's 44 terms to acc (no 44-register temporary)
     const float sig = b.z, q1 = a.z, q2 = a.w;
     const float sGraw = sig * G;
     const bool clamped = sGraw > amax;
@@ -53,42 +54,43 @@ __device__ __forceinline__ void pair_terms(const float4 a, const float4 b, float
     const float A1 = dl[0] * av[0] + dl[1] * av[1] + dl[2] * av[2];
     const float A2 = hh[0] * av[0] * av[0] + hh[1] * av[1] * av[1] + hh[2] * av[2] * av[2];
 #pragma unroll
-    for (int f = 0; f < GSN_NZ; ++f) z[f] = 0.f;
-#pragma unroll
     for (int ch = 0; ch < 3; ++ch) {
-        z[6 + ch] = dl[ch] * wT;
-        z[39 + ch] = hh[ch] * wT * wT;
+        acc[6 + ch] += dl[ch] * wT;
+        acc[39 + ch] += hh[ch] * wT * wT;
     }
-    z[43] = wT;
+    acc[43] += wT;
     if (clamped) return;
     const float u[5] = {-q1 * dx, -q2 * dy, -0.5f * dx * dx, -dx * dy, -0.5f * dy * dy};
     const float k1 = A1 * sGraw;
     // Gauss-Newton keeps only the h-weighted products of first derivatives: no k1 curvature terms
     const float k2 = GN ? A2 * sGraw * sGraw : A2 * sGraw * sGraw + k1;
 #pragma unroll
-    for (int i = 0; i < 5; ++i) z[i] = k1 * u[i];
-    z[5] = A1 * G;
+    for (int i = 0; i < 5; ++i) acc[i] += k1 * u[i];
+    acc[5] += A1 * G;
     // H_ww: k2 u u^T + k1 d2f, d2f has -Q' on (pi', pi') and -d' on (pi', Q')
     int idx = 9;
 #pragma unroll
     for (int i = 0; i < 5; ++i)
 #pragma unroll
-        for (int j = i; j < 5; ++j, ++idx) z[idx] = k2 * u[i] * u[j];
-    if (!GN) {
-        z[9 + 0] -= k1 * q1;  // (pi'_1, pi'_1)
-        z[9 + 2] -= k1 * dx;  // (pi'_1, Q'_11)
-        z[9 + 3] -= k1 * dy;  // (pi'_1, Q'_12)
-        z[9 + 5] -= k1 * q2;  // (pi'_2, pi'_2)
-        z[9 + 7] -= k1 * dx;  // (pi'_2, Q'_12)
-        z[9 + 8] -= k1 * dy;  // (pi'_2, Q'_22)
-    }
+        for (int j = i; j < 5; ++j, ++idx) {
+            float t = k2 * u[i] * u[j];
+            if (!GN) {
+                if (idx == 9 + 0) t -= k1 * q1;  // (pi'_1, pi'_1)
+                if (idx == 9 + 2) t -= k1 * dx;  // (pi'_1, Q'_11)
+                if (idx == 9 + 3) t -= k1 * dy;  // (pi'_1, Q'_12)
+                if (idx == 9 + 5) t -= k1 * q2;  // (pi'_2, pi'_2)
+                if (idx == 9 + 7) t -= k1 * dx;  // (pi'_2, Q'_12)
+                if (idx == 9 + 8) t -= k1 * dy;  // (pi'_2, Q'_22)
+            }
+            acc[idx] += t;
+        }
 #pragma unroll
     for (int ch = 0; ch < 3; ++ch) {
         const float bch = sGraw * T * (GN ? hh[ch] * av[ch] * al : hh[ch] * av[ch] * al + dl[ch]);
 #pragma unroll
-        for (int i = 0; i < 5; ++i) z[24 + i * 3 + ch] = bch * u[i];
+        for (int i = 0; i < 5; ++i) acc[24 + i * 3 + ch] += bch * u[i];
     }
-    z[42] = A2 * G * G;
+    acc[42] += A2 * G * G;
 }
 
 // Cross-lane sums with DPP row operations (no LDS traffic): quad_sum leaves in every lane
@@ -123,21 +125,20 @@ __device__ __forceinline__ float group_sum(float v) {
 // Adds the statistics of staged pair i (slot in LDS) of the splat (a, b, c4) to acc.
 template <bool GN>
 __device__ __forceinline__ void pair_stats(const float4 a, const float4 b, const float4 cl, const float4* s_pa,
-                                           const float* s_pb, const uint8_t* s_pix, const float (*s_dl)[GSN_BLOCK],
-                                           const float (*s_h)[GSN_BLOCK], uint32_t i, int tx, int ty, float amax,
+                                           const float* s_pb, const uint8_t* s_pix, const float4* s_lm0,
+                                           const float2* s_lm1, uint32_t i, int tx, int ty, float amax,
                                            float* acc) {
     const float4 pa = s_pa[i];
     const int p = s_pix[i];
     const float av[3] = {pa.z, pa.w, s_pb[i]};
-    const float dl[3] = {s_dl[0][p], s_dl[1][p], s_dl[2][p]};
-    const float hh[3] = {s_h[0][p], s_h[1][p], s_h[2][p]};
+    const float4 l0 = s_lm0[p];
+    const float2 l1 = s_lm1[p];
+    const float dl[3] = {l0.x, l0.y, l0.z};
+    const float hh[3] = {l0.w, l1.x, l1.y};
     const float ddx = (a.x - (float)(tx * GSN_TILE + (p % GSN_TILE))) + cl.z;
     const float ddy = (a.y - (float)(ty * GSN_TILE + (p / GSN_TILE))) + cl.w;
     const float d1 = b.x * ddx + b.y * ddy, d2 = b.x * ddy - b.y * ddx;
-    float z[GSN_NZ];
-    pair_terms<GN>(a, b, pa.y, pa.x, av, d1, d2, dl, hh, amax, z);
-#pragma unroll
-    for (int f = 0; f < GSN_NZ; ++f) acc[f] += z[f];
+    pair_terms<GN>(a, b, pa.y, pa.x, av, d1, d2, dl, hh, amax, acc);
 }
 
 __device__ __forceinline__ void write_partial(float* __restrict__ partial, uint8_t* __restrict__ flags, uint32_t slot,
@@ -178,7 +179,8 @@ __global__ __launch_bounds__(GSN_BLOCK, 3) void raster_bwd_kernel(
     __shared__ uint32_t r_slot[GSN_BLOCK], r_id[GSN_BLOCK];
     __shared__ uint8_t r_list[NW][GSN_BLOCK];
     __shared__ uint32_t r_cnt[NW][NW];  // [band][loader wave]
-    __shared__ float s_dl[3][GSN_BLOCK], s_h[3][GSN_BLOCK];
+    __shared__ float4 s_lm0[GSN_BLOCK];  // per pixel: dL_R, dL_G, dL_B, h_R
+    __shared__ float2 s_lm1[GSN_BLOCK];  // h_G, h_B
     __shared__ uint64_t s_mask[GSN_BLOCK][NW];
     __shared__ uint32_t s_off[GSN_BLOCK * NW + 1];
     __shared__ uint32_t s_wsum[NW];
@@ -202,11 +204,16 @@ __global__ __launch_bounds__(GSN_BLOCK, 3) void raster_bwd_kernel(
     const size_t np = (size_t)cam.W * cam.H, pi = (size_t)py * cam.W + px;
     double cf[3] = {0, 0, 0};
     uint32_t nc = 0;
+    {
+        float dlv[3], hv[3];
 #pragma unroll
-    for (int ch = 0; ch < 3; ++ch) {
-        s_dl[ch][tid] = inside ? dLm[ch * np + pi] : 0.f;
-        s_h[ch][tid] = inside ? hdm[ch * np + pi] : 0.f;
-        if (inside) cf[ch] = img64[ch * np + pi];
+        for (int ch = 0; ch < 3; ++ch) {
+            dlv[ch] = inside ? dLm[ch * np + pi] : 0.f;
+            hv[ch] = inside ? hdm[ch * np + pi] : 0.f;
+            if (inside) cf[ch] = img64[ch * np + pi];
+        }
+        s_lm0[tid] = make_float4(dlv[0], dlv[1], dlv[2], hv[0]);
+        s_lm1[tid] = make_float2(hv[1], hv[2]);
     }
     if (inside) nc = ncontrib[pi];
     if (tid == 0) s_max = 0;
@@ -406,7 +413,7 @@ __global__ __launch_bounds__(GSN_BLOCK, 3) void raster_bwd_kernel(
                         e = s_act[k];
                         const uint32_t q0 = s_off[e * NW], q1 = s_off[(e + 1) * NW];
                         for (uint32_t i = q0 + r; i < q1; i += SG)
-                            pair_stats<GN>(r_a[e], r_b[e], r_c[e], s_pa, s_pb, s_pix, s_dl, s_h, i, tx, ty, ro.alpha_max,
+                            pair_stats<GN>(r_a[e], r_b[e], r_c[e], s_pa, s_pb, s_pix, s_lm0, s_lm1, i, tx, ty, ro.alpha_max,
                                        acc);
                     }
 #pragma unroll
@@ -430,7 +437,7 @@ __global__ __launch_bounds__(GSN_BLOCK, 3) void raster_bwd_kernel(
                         e = s_big[k];
                         const uint32_t q0 = s_off[e * NW], q1 = s_off[(e + 1) * NW];
                         for (uint32_t i = q0 + r; i < q1; i += LG)
-                            pair_stats<GN>(r_a[e], r_b[e], r_c[e], s_pa, s_pb, s_pix, s_dl, s_h, i, tx, ty, ro.alpha_max,
+                            pair_stats<GN>(r_a[e], r_b[e], r_c[e], s_pa, s_pb, s_pix, s_lm0, s_lm1, i, tx, ty, ro.alpha_max,
                                        acc);
                     }
 #pragma unroll
@@ -494,10 +501,22 @@ __global__ __launch_bounds__(256) void reduce_pairs_kernel(int n, const uint2* _
         for (uint32_t base = 0; base < nt; base += 64) {
             const bool fl = base + lane < nt && flags[off + base + lane] != 0;
             uint64_t m = __ballot(fl);
-            while (m) {
-                const int i = __ffsll((unsigned long long)m) - 1;
-                m &= m - 1;
-                if (lane < GSN_NZ) acc += (double)partial[(size_t)(off + base + i) * GSN_NZ + lane];
+            while (m) {  // up to four written slots per step: their loads overlap, the adds keep slot order
+                float v[4];
+                int cntv = 0;
+#pragma unroll
+                for (int t = 0; t < 4; ++t) {
+                    v[t] = 0.f;
+                    if (m) {
+                        const int i = __ffsll((unsigned long long)m) - 1;
+                        m &= m - 1;
+                        if (lane < GSN_NZ) v[t] = partial[(size_t)(off + base + i) * GSN_NZ + lane];
+                        ++cntv;
+                    }
+                }
+#pragma unroll
+                for (int t = 0; t < 4; ++t)
+                    if (t < cntv) acc += (double)v[t];
             }
         }
         if (lane < GSN_NZ) zsum[(size_t)k * GSN_NZ + lane] = acc;
