@@ -472,6 +472,34 @@ def _measured_traffic(kernel):
     return d["fetch_bytes_per_launch"] + d["write_bytes_per_launch"]
 
 
+def copy_bandwidth(dev, nbytes=1 << 30, reps=5):
+    """Measured device-to-device copy bandwidth (read + write bytes per second), GB/s."""
+    import torch
+    a = torch.ones(nbytes // 4, dtype=torch.float32, device=dev)
+    b = torch.empty_like(a)
+    b.copy_(a)
+    torch.cuda.synchronize(dev)
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        b.copy_(a)
+    torch.cuda.synchronize(dev)
+    el = time.perf_counter() - t0
+    del a, b
+    return 2.0 * nbytes * reps / el / 1e9
+
+
+def sweep_roofline(value, counts, steps, n, views, pixels_per_step, copy_gbs):
+    """The whole sweep against HBM: the bytes the method must move per sweep,
+    N (708 + 384 V) per kernel set + 28 per emitted pair + 80 per consumed list entry (forward
+    and backward) + 112 per pixel, times sweeps/s, against the 8 TB/s peak and a measured copy."""
+    b_alg = (n * (708 + 384 * views) + 28.0 * counts["pairs"] / steps + 80.0 * counts["fwd_staged"] / steps
+             + 112.0 * pixels_per_step)
+    gbs = b_alg * value / 1e9
+    return {"algorithmic_bytes_per_sweep": round(b_alg), "achieved": round(gbs, 1), "unit": "GB/s",
+            "peak": PEAK_HBM_GBS, "frac": round(gbs / PEAK_HBM_GBS, 5),
+            "copy_gbs": round(copy_gbs, 1), "frac_of_copy": round(gbs / copy_gbs, 5)}
+
+
 def roofline(stages, counts, steps, pixels_per_step):
     """Roofline figure of the stage that takes the most time (one kernel per stage launch)."""
     dom = max(stages, key=lambda s: stages[s][0])
@@ -589,6 +617,9 @@ def main():
     value = args.steps / elapsed
     pixels = cfg.width * cfg.height + cfg.n_secondary * (cfg.width // 2) * (cfg.height // 2)
     rl = roofline(stages, counts, args.steps, pixels)
+    import torch
+    srl = sweep_roofline(value, counts, args.steps, cfg.n, 1 + cfg.n_secondary, pixels,
+                         copy_bandwidth(torch.device("cuda", 0)))
     cpu = None
     if not args.no_cpu_baseline:
         log("[bench] timing the oracle on a bounded sample ...")
@@ -607,6 +638,7 @@ def main():
         "stage_ms_per_step": {k: round(v[0] / args.steps, 3) for k, v in stages.items()},
         "counts_per_step": {k: int(v / args.steps) for k, v in counts.items()},
         "roofline": rl,
+        "sweep_hbm": srl,
         "cpu_baseline": cpu,
         "learned": learned,
         "equal_psnr": quality,

@@ -277,7 +277,7 @@ gsn_status gsn_render(gsn_ctx* ctx, const gsn_gaussians* g, const gsn_camera* ca
     HIP_TRY(ctx, buf_reserve(f->total, 16));
     // sort and scan scratch for the per-kernel stages, reserved before any launch so that
     // no buffer is reallocated while work that uses it may still be queued
-    HIP_TRY(ctx, buf_reserve(f->hist, (size_t)256 * ((nn + 4095) / 4096) * 8));
+    HIP_TRY(ctx, buf_reserve(f->hist, radix_hist_bytes((uint32_t)nn)));
     HIP_TRY(ctx, buf_reserve(f->scan_tmp, scan_tmp_bytes((uint32_t)nn)));
     uint32_t* d_total = bp<uint32_t>(f->total);
     {
@@ -307,7 +307,8 @@ gsn_status gsn_render(gsn_ctx* ctx, const gsn_gaussians* g, const gsn_camera* ca
     f->pairs = P;
     const size_t pp = std::max<size_t>(P, 1);
     // the stream is idle here: growing scratch cannot race with queued work
-    HIP_TRY(ctx, buf_reserve(f->hist, (size_t)256 * ((pp + 4095) / 4096) * 8));
+    HIP_TRY(ctx, buf_reserve(f->hist, radix_hist_bytes((uint32_t)pp)));
+    HIP_TRY(ctx, buf_reserve(f->chunk_first, emit_chunks((uint32_t)pp) * 4 + 4));
     HIP_TRY(ctx, buf_reserve(f->scan_tmp, scan_tmp_bytes((uint32_t)std::max<size_t>(pp, nn))));
     HIP_TRY(ctx, buf_reserve(f->pk_a, pp * 4));
     HIP_TRY(ctx, buf_reserve(f->pv_a, pp * 4));
@@ -325,7 +326,7 @@ gsn_status gsn_render(gsn_ctx* ctx, const gsn_gaussians* g, const gsn_camera* ca
         launch_fill_u32(bp<uint32_t>(f->kflag), 0u, (nn + 3) / 4, s);
         launch_emit_pairs(bp<uint32_t>(f->ids_a), bp<uint32_t>(f->offsets), (uint32_t)n, P, bp<uint2>(f->rect),
                           (uint32_t)f->tiles_x, bp<uint32_t>(f->pk_a), bp<uint32_t>(f->pv_a),
-                          bp<uint32_t>(f->pair_off), s);
+                          bp<uint32_t>(f->pair_off), bp<uint32_t>(f->chunk_first), s);
         int tile_bits = 1;
         while ((1ull << tile_bits) < tiles) ++tile_bits;
         HIP_TRY(ctx, radix_sort_pairs(bp<uint32_t>(f->pk_a), bp<uint32_t>(f->pv_a), bp<uint32_t>(f->pk_b),

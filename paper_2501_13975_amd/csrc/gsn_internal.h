@@ -38,6 +38,7 @@ struct gsn_frame {
     DevBuf ids_a, ids_b, keys_a, keys_b;  // u32 [n] sort ping-pong
     DevBuf offsets;     // u32 [n + 1] pair offset by depth rank
     DevBuf pair_off;    // u32 [n] pair offset by kernel id
+    DevBuf chunk_first; // u32 [pairs / 2048 + 1] depth rank owning the first slot of each emission chunk
     // per pair
     DevBuf pk_a, pv_a, pk_b, pv_b;  // u32 [pairs] (tile, id) ping-pong
     DevBuf partial;     // float [pairs][GSN_NZ]
@@ -117,7 +118,9 @@ hipError_t exclusive_scan_u32(const uint32_t* in, uint32_t* out, uint32_t n, uin
 void launch_gather_u32(const uint32_t* src, const uint32_t* idx, uint32_t* dst, uint32_t n, hipStream_t s);
 void launch_emit_pairs(const uint32_t* sorted_ids, const uint32_t* offsets, uint32_t n, uint32_t pairs,
                        const uint2* rect, uint32_t tiles_x, uint32_t* keys, uint32_t* vals, uint32_t* pair_off,
-                       hipStream_t s);
+                       uint32_t* chunk_first, hipStream_t s);
+size_t emit_chunks(uint32_t pairs);
+size_t radix_hist_bytes(uint32_t n);
 void launch_tile_ranges(const uint32_t* keys, uint32_t pairs, uint2* ranges, hipStream_t s);
 void launch_raster_fwd(const uint2* ranges, const uint32_t* ids, const float4* rec, uint32_t n, const DevCam& cam,
                        const DevRenderOpts& ro, float* img, double* img64, float* Tfin, uint32_t* ncontrib,

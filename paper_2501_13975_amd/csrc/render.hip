@@ -432,41 +432,56 @@ __global__ void gather_u32_kernel(const uint32_t* __restrict__ src, const uint32
 // One thread per depth rank: writes the kernel's (tile, id) pairs, row-major
 // over its rectangle, at its scanned offset.
 // Each kernel's slot range: pair_off[id] = offsets[depth rank].
+// Pairs in depth order are emitted by contiguous chunks of kEmitChunk pair slots per workgroup.
+constexpr int kEmitChunk = 2048;
+
+// One thread per depth rank: the kernel's pair offset by id, and for every chunk whose first slot
+// falls in the rank's range, that rank (the ranges partition the slots, so each chunk's entry is
+// written once).
 __global__ void pair_off_kernel(const uint32_t* __restrict__ sorted_ids, const uint32_t* __restrict__ offsets,
-                                uint32_t n, uint32_t* __restrict__ pair_off) {
+                                uint32_t n, uint32_t pairs, uint32_t* __restrict__ pair_off,
+                                uint32_t* __restrict__ chunk_first) {
     const uint32_t r = blockIdx.x * blockDim.x + threadIdx.x;
-    if (r < n) pair_off[sorted_ids[r]] = offsets[r];
+    if (r >= n) return;
+    const uint32_t o0 = offsets[r], o1 = r + 1 < n ? offsets[r + 1] : pairs;
+    pair_off[sorted_ids[r]] = o0;
+    for (uint32_t c = (o0 + kEmitChunk - 1) / kEmitChunk; (size_t)c * kEmitChunk < o1; ++c) chunk_first[c] = r;
 }
 
-// Pairs in depth order, emitted by contiguous chunks of kEmitChunk pair slots per workgroup so
-// that the writes are coalesced: the workgroup stages the (few) kernels whose ranges meet its
-// chunk, and each thread finds the kernel of its slot by binary search over their offsets.
+// The workgroup stages the (few) kernels whose ranges meet its chunk, so that the writes are
+// coalesced, and each thread finds the kernel of its slot by binary search over their offsets.
 // Kernel r (depth rank) owns slots [offsets[r], offsets[r] + ntiles) in row-major tile order.
-constexpr int kEmitChunk = 2048;
 
 __global__ __launch_bounds__(kThreads) void emit_pairs_kernel(const uint32_t* __restrict__ sorted_ids,
                                                                const uint32_t* __restrict__ offsets, uint32_t n,
                                                                uint32_t pairs, const uint2* __restrict__ rect,
                                                                uint32_t tiles_x, uint32_t* __restrict__ keys,
-                                                               uint32_t* __restrict__ vals) {
+                                                               uint32_t* __restrict__ vals,
+                                                               const uint32_t* __restrict__ chunk_first) {
     __shared__ uint32_t s_off[kEmitChunk], s_id[kEmitChunk];
     __shared__ uint2 s_rect[kEmitChunk];
     __shared__ uint32_t s_r0, s_cnt;
     const uint32_t p0 = blockIdx.x * (uint32_t)kEmitChunk;
     const uint32_t p1 = min(pairs, p0 + (uint32_t)kEmitChunk);
     if (threadIdx.x == 0) {
-        // last rank whose range starts at or before p (offsets are non-decreasing, offsets[0] = 0)
-        auto last_le = [&](uint32_t p) {
-            uint32_t lo = 0, hi = n - 1;
+        // first and last ranks whose ranges meet [p0, p1): the rank owning p0, and the rank owning
+        // the next chunk's first slot unless its range starts there (visible kernels have at least
+        // one pair each, so at most kEmitChunk ranks meet a chunk)
+        const uint32_t r0 = chunk_first[blockIdx.x];
+        uint32_t r1;
+        if (blockIdx.x + 1 < gridDim.x) {
+            r1 = chunk_first[blockIdx.x + 1];
+            if (offsets[r1] >= p1) --r1;
+        } else {
+            uint32_t lo = r0, hi = n - 1;  // last rank whose range starts at or before p1 - 1
             while (lo < hi) {
                 const uint32_t mid = (lo + hi + 1) >> 1;
-                if (offsets[mid] <= p) lo = mid; else hi = mid - 1;
+                if (offsets[mid] <= p1 - 1) lo = mid; else hi = mid - 1;
             }
-            return lo;
-        };
-        const uint32_t r0 = last_le(p0), r1 = last_le(p1 - 1);
+            r1 = lo;
+        }
         s_r0 = r0;
-        s_cnt = r1 - r0 + 1;  // kernels with pairs own distinct offsets: at most kEmitChunk of them
+        s_cnt = r1 - r0 + 1;
     }
     __syncthreads();
     const uint32_t r0 = s_r0, cnt = s_cnt;
@@ -688,7 +703,7 @@ hipError_t radix_sort_pairs(uint32_t* k0, uint32_t* v0, uint32_t* k1, uint32_t* 
     (void)scan_tmp;
     if (n == 0) return hipSuccess;
     const uint32_t nb = (n + kRsTile - 1) / kRsTile;
-    hipError_t e = buf_reserve(hist, ((size_t)256 * nb * 2 + 256) * 4);
+    hipError_t e = buf_reserve(hist, radix_hist_bytes(n));
     if (e != hipSuccess) return e;
     uint32_t* h = bp<uint32_t>(hist);
     uint32_t* o = h + (size_t)256 * nb;
@@ -714,14 +729,22 @@ void launch_gather_u32(const uint32_t* src, const uint32_t* idx, uint32_t* dst, 
     if (n) gather_u32_kernel<<<(n + kThreads - 1) / kThreads, kThreads, 0, s>>>(src, idx, dst, n);
 }
 
+size_t emit_chunks(uint32_t pairs) { return ((size_t)pairs + kEmitChunk - 1) / kEmitChunk; }
+
+size_t radix_hist_bytes(uint32_t n) {
+    const size_t nb = ((size_t)n + kRsTile - 1) / kRsTile;
+    return ((size_t)256 * nb * 2 + 256) * 4;
+}
+
 void launch_emit_pairs(const uint32_t* sorted_ids, const uint32_t* offsets, uint32_t n, uint32_t pairs,
                        const uint2* rect, uint32_t tiles_x, uint32_t* keys, uint32_t* vals, uint32_t* pair_off,
-                       hipStream_t s) {
+                       uint32_t* chunk_first, hipStream_t s) {
     if (n == 0) return;
-    pair_off_kernel<<<(n + kThreads - 1) / kThreads, kThreads, 0, s>>>(sorted_ids, offsets, n, pair_off);
+    pair_off_kernel<<<(n + kThreads - 1) / kThreads, kThreads, 0, s>>>(sorted_ids, offsets, n, pairs, pair_off,
+                                                                       chunk_first);
     if (pairs)
-        emit_pairs_kernel<<<(pairs + kEmitChunk - 1) / kEmitChunk, kThreads, 0, s>>>(sorted_ids, offsets, n, pairs,
-                                                                                    rect, tiles_x, keys, vals);
+        emit_pairs_kernel<<<(uint32_t)emit_chunks(pairs), kThreads, 0, s>>>(sorted_ids, offsets, n, pairs, rect,
+                                                                          tiles_x, keys, vals, chunk_first);
 }
 
 void launch_tile_ranges(const uint32_t* keys, uint32_t pairs, uint2* ranges, hipStream_t s) {
