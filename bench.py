@@ -150,35 +150,42 @@ def _psnr(tr, targets, dev):
     return float(torch.stack(vals).mean().cpu())
 
 
-def _equal_psnr(cfg, targets, dev, epochs, every, mask, step_frac):
-    """Plain form for `epochs` epochs sets the target PSNR; the learned form runs epoch by epoch
-    until it reaches it (at most 3x as many epochs).  Times cover the sweeps only."""
+def _equal_psnr(cfg, targets, dev, epochs, every, mask, step_frac, checks_per_epoch=5):
+    """Plain form for `epochs` epochs sets the target PSNR; the learned form runs until it reaches
+    it (PSNR checked after every fifth of an epoch, at most 3x as many epochs).  Times cover the
+    sweeps only."""
     import numpy as np
     import torch
 
     from synth.scenes import view_order
     nv = len(cfg.cams)
-    out = {"epochs_plain": epochs, "learned_every": every, "group_mask": mask, "step_frac": step_frac}
+    out = {"epochs_plain": epochs, "learned_every": every, "group_mask": mask, "step_frac": step_frac,
+           "psnr_checks_per_epoch": checks_per_epoch}
     for form in ("plain", "learned"):
         tr = _trainer(cfg, targets, dev, every if form == "learned" else 0, step_frac)
         out.setdefault("initial_psnr", round(_psnr(tr, targets, dev), 4))
-        spent, e, psnr = 0.0, 0, None
+        spent, psnr, i = 0.0, None, 0
         target = out.get("target_psnr")
         max_e = epochs if form == "plain" else 3 * epochs
-        i = 0
-        while e < max_e:
+        done = False
+        for e in range(max_e):
             order = view_order(nv, e)
-            torch.cuda.synchronize(dev)
-            t0 = time.perf_counter()
-            for t in order:
-                _sweep(tr, int(t), i, form == "learned", mask)
-                i += 1
-            torch.cuda.synchronize(dev)
-            spent += time.perf_counter() - t0
-            e += 1
-            psnr = _psnr(tr, targets, dev)
-            log(f"[bench] {form} epoch {e}: PSNR {psnr:.3f} dB, {spent:.2f}s of sweeps")
-            if form == "learned" and psnr >= target:
+            bounds = np.linspace(0, nv, checks_per_epoch + 1).astype(int)
+            for c in range(checks_per_epoch):
+                torch.cuda.synchronize(dev)
+                t0 = time.perf_counter()
+                for t in order[bounds[c]:bounds[c + 1]]:
+                    _sweep(tr, int(t), i, form == "learned", mask)
+                    i += 1
+                torch.cuda.synchronize(dev)
+                spent += time.perf_counter() - t0
+                if form == "learned" or c == checks_per_epoch - 1:
+                    psnr = _psnr(tr, targets, dev)
+                if form == "learned" and psnr >= target:
+                    done = True
+                    break
+            log(f"[bench] {form} epoch {e + 1}: PSNR {psnr:.3f} dB, {spent:.2f}s of sweeps")
+            if done:
                 break
         if form == "plain":
             out["target_psnr"] = round(psnr, 4)
@@ -361,6 +368,32 @@ def _first_order_leg(dev, newton_epochs, max_epochs, mask, step_frac):
     return out
 
 
+def _psnr_curve_leg(dev, epochs, mask, step_frac):
+    """Mean PSNR over all views after each epoch of the plain form on the 100k-kernel, 50-camera
+    1024x768 scene (jacobi, 3 secondaries)."""
+    import torch
+
+    from synth.scenes import make_config, view_order
+    cfg = make_config("c1")
+    targets = _targets(cfg, dev)
+    nv = len(cfg.cams)
+    tr = _trainer(cfg, targets, dev, 0, step_frac)
+    out = {"workload": f"{cfg.n} Gaussians SH3, {nv} cameras at {cfg.width}x{cfg.height}, 3 secondaries",
+           "group_mask": mask, "step_frac": step_frac, "psnr_initial": round(_psnr(tr, targets, dev), 4),
+           "psnr_per_epoch": [], "seconds_per_epoch": []}
+    for e in range(epochs):
+        torch.cuda.synchronize(dev)
+        t0 = time.perf_counter()
+        for t in view_order(nv, e):
+            tr.sweep(int(t), mask)
+        torch.cuda.synchronize(dev)
+        out["seconds_per_epoch"].append(round(time.perf_counter() - t0, 4))
+        out["psnr_per_epoch"].append(round(_psnr(tr, targets, dev), 4))
+    tr.close()
+    log(f"[bench] PSNR curve: {out}")
+    return out
+
+
 def _batched_solve_leg(dev, reps=20):
     """The eight scenes of 20k-800k kernels at 1280x720: blocks from one primary and three
     secondary views each, then the solves of all scenes timed as one launch per scene, as
@@ -444,6 +477,9 @@ def gpu_run(args):
     order_exp = None
     if args.order_epochs > 0:
         order_exp = _order_leg(dev, args.order_epochs, args.order_step_frac)
+    curve = None
+    if args.curve_epochs > 0:
+        curve = _psnr_curve_leg(dev, args.curve_epochs, args.quality_mask, args.quality_step_frac)
     first_order = None
     if args.first_order_epochs > 0:
         first_order = _first_order_leg(dev, 1, args.first_order_epochs, args.quality_mask, args.quality_step_frac)
@@ -455,7 +491,8 @@ def gpu_run(args):
     if args.quality_epochs > 0 and args.learned_every:
         quality = _equal_psnr(cfg, targets, dev, args.quality_epochs, args.learned_every, args.quality_mask,
                               args.quality_step_frac)
-    return elapsed, stages, counts, cfg, learned, quality, batched, variants, overshoot, order_exp, first_order, dist
+    return (elapsed, stages, counts, cfg, learned, quality, batched, variants, overshoot, order_exp, first_order, dist,
+            curve)
 
 
 def _measured_traffic(kernel):
@@ -603,6 +640,8 @@ def main():
                     help="epochs of the jacobi / series-order comparison on the 100k scene; 0 skips")
     ap.add_argument("--order-step-frac", type=float, default=0.1,
                     help="step fraction of the order comparison (it trains every group)")
+    ap.add_argument("--curve-epochs", type=int, default=10,
+                    help="epochs of the plain-form PSNR curve on the 100k scene; 0 skips")
     ap.add_argument("--first-order-epochs", type=int, default=10,
                     help="at most this many epochs of Adam against one epoch of Newton sweeps on the 100k "
                          "scene; 0 skips")
@@ -612,7 +651,7 @@ def main():
               "(how it would shard across GPUs is described in DESIGN.md); run with --gpus 1", file=sys.stderr)
         sys.exit(2)
     (elapsed, stages, counts, cfg, learned, quality, batched, variants, overshoot, order_exp,
-     first_order, dist) = gpu_run(args)
+     first_order, dist, curve) = gpu_run(args)
     ms_per_step = elapsed * 1e3 / args.steps
     value = args.steps / elapsed
     pixels = cfg.width * cfg.height + cfg.n_secondary * (cfg.width // 2) * (cfg.height // 2)
@@ -647,6 +686,7 @@ def main():
         "overshoot": overshoot,
         "schedule_order": order_exp,
         "first_order": first_order,
+        "psnr_curve": curve,
     }
     print(json.dumps(out), flush=True)
 

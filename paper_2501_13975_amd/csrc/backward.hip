@@ -163,7 +163,8 @@ __device__ __forceinline__ void write_partial(float* __restrict__ partial, uint8
 //  (c) every pixel walks its composited entries front to back (transmittance,
 //      colour behind the splat) and stores (T, G, a_R, a_G, a_B) in the pair's slot;
 //  (d) for every entry with pairs, the 44 statistics are summed over its pairs in a
-//      fixed order (SG lanes per entry, or LG for an entry with more than BIG pairs)
+//      fixed order (SG lanes per entry, or LG for an entry with more than BIG pairs, handed
+//      out to waves from a block-wide counter)
 //      and the tile's partial sum is written at the (tile, kernel) pair's slot.
 //      Only contributing pairs do the 44-term work.
 // GN: local Gauss-Newton statistics (no loss-gradient times image-curvature terms).
@@ -185,7 +186,7 @@ __global__ __launch_bounds__(GSN_BLOCK, 3) void raster_bwd_kernel(
     __shared__ uint32_t s_off[GSN_BLOCK * NW + 1];
     __shared__ uint32_t s_wsum[NW];
     __shared__ uint8_t s_act[GSN_BLOCK], s_big[GSN_BLOCK];  // entries of the round with <= BIG / > BIG pairs
-    __shared__ uint32_t s_nact[NW], s_nbig[NW];
+    __shared__ uint32_t s_nact[NW], s_nbig[NW], s_work;
     __shared__ float4 s_pa[PMAX];
     __shared__ float s_pb[PMAX];
     __shared__ uint8_t s_pix[PMAX];
@@ -378,7 +379,8 @@ __global__ __launch_bounds__(GSN_BLOCK, 3) void raster_bwd_kernel(
             }
             // (d) per-entry sums.  Entries of the round with 1..BIG pairs go to groups of SG lanes, larger
             // ones to groups of LG; a group sums its entry's pairs lane-strided and then across its lanes
-            // with DPP row operations, so every sum is taken in one fixed order.
+            // with DPP row operations, so every sum is taken in one fixed order.  Waves take the work
+            // from a block-wide counter (large entries first), so they finish the round together.
             const uint32_t pc = (tid >= r0 && tid < r1) ? s_off[(tid + 1) * NW] - s_off[tid * NW] : 0u;
             const bool small = pc > 0 && pc <= (uint32_t)BIG, large = pc > (uint32_t)BIG;
             const uint64_t sbal = __ballot(small), lbal = __ballot(large);
@@ -386,6 +388,7 @@ __global__ __launch_bounds__(GSN_BLOCK, 3) void raster_bwd_kernel(
                 s_nact[wave] = (uint32_t)__popcll(sbal);
                 s_nbig[wave] = (uint32_t)__popcll(lbal);
             }
+            if (tid == 0) s_work = 0;
             __syncthreads();
             uint32_t nsmall = 0, nlarge = 0;
             {
@@ -402,50 +405,54 @@ __global__ __launch_bounds__(GSN_BLOCK, 3) void raster_bwd_kernel(
             }
             __syncthreads();
             {
-                const int grp = tid / SG, r = tid % SG;
-                for (uint32_t k0 = 0; k0 < nsmall; k0 += GSN_BLOCK / SG) {  // uniform across the block
-                    const uint32_t k = k0 + (uint32_t)grp;
+                // whole waves take work units from a block-wide counter, large entries first: a unit is
+                // 64 / LG large entries (one per LG-lane group) or 64 / SG small ones (one per SG-lane group)
+                constexpr uint32_t PL = 64 / LG, PS = 64 / SG;
+                const uint32_t nlu = (nlarge + PL - 1) / PL, nsu = (nsmall + PS - 1) / PS;
+                for (;;) {
+                    uint32_t u = 0;
+                    if (lane == 0) u = atomicAdd(&s_work, 1u);
+                    u = (uint32_t)__shfl((int)u, 0, 64);
+                    if (u >= nlu + nsu) break;  // uniform across the wave
                     float acc[GSN_NZ];
 #pragma unroll
                     for (int f = 0; f < GSN_NZ; ++f) acc[f] = 0.f;
-                    int e = 0;
-                    if (k < nsmall) {
-                        e = s_act[k];
-                        const uint32_t q0 = s_off[e * NW], q1 = s_off[(e + 1) * NW];
-                        for (uint32_t i = q0 + r; i < q1; i += SG)
-                            pair_stats<GN>(r_a[e], r_b[e], r_c[e], s_pa, s_pb, s_pix, s_lm0, s_lm1, i, tx, ty, ro.alpha_max,
-                                       acc);
-                    }
+                    if (u < nlu) {
+                        const int r = lane % LG;
+                        const uint32_t k = u * PL + (uint32_t)(lane / LG);
+                        int e = 0;
+                        if (k < nlarge) {
+                            e = s_big[k];
+                            const uint32_t q0 = s_off[e * NW], q1 = s_off[(e + 1) * NW];
+                            for (uint32_t i = q0 + r; i < q1; i += LG)
+                                pair_stats<GN>(r_a[e], r_b[e], r_c[e], s_pa, s_pb, s_pix, s_lm0, s_lm1, i, tx, ty,
+                                               ro.alpha_max, acc);
+                        }
 #pragma unroll
-                    for (int f = 0; f < GSN_NZ; ++f) acc[f] = group_sum<SG>(acc[f]);
-                    if (k < nsmall && r == 0) {
-                        write_partial(partial, flags, r_slot[e], acc);
-                        kflag[r_id[e]] = 1;
-                        ++n_part;
-                    }
-                }
-            }
-            {
-                const int grp = tid / LG, r = tid % LG;
-                for (uint32_t k0 = 0; k0 < nlarge; k0 += GSN_BLOCK / LG) {  // uniform across the block
-                    const uint32_t k = k0 + (uint32_t)grp;
-                    float acc[GSN_NZ];
+                        for (int f = 0; f < GSN_NZ; ++f) acc[f] = group_sum<LG>(acc[f]);
+                        if (k < nlarge && r == 0) {
+                            write_partial(partial, flags, r_slot[e], acc);
+                            kflag[r_id[e]] = 1;
+                            ++n_part;
+                        }
+                    } else {
+                        const int r = lane % SG;
+                        const uint32_t k = (u - nlu) * PS + (uint32_t)(lane / SG);
+                        int e = 0;
+                        if (k < nsmall) {
+                            e = s_act[k];
+                            const uint32_t q0 = s_off[e * NW], q1 = s_off[(e + 1) * NW];
+                            for (uint32_t i = q0 + r; i < q1; i += SG)
+                                pair_stats<GN>(r_a[e], r_b[e], r_c[e], s_pa, s_pb, s_pix, s_lm0, s_lm1, i, tx, ty,
+                                               ro.alpha_max, acc);
+                        }
 #pragma unroll
-                    for (int f = 0; f < GSN_NZ; ++f) acc[f] = 0.f;
-                    int e = 0;
-                    if (k < nlarge) {
-                        e = s_big[k];
-                        const uint32_t q0 = s_off[e * NW], q1 = s_off[(e + 1) * NW];
-                        for (uint32_t i = q0 + r; i < q1; i += LG)
-                            pair_stats<GN>(r_a[e], r_b[e], r_c[e], s_pa, s_pb, s_pix, s_lm0, s_lm1, i, tx, ty, ro.alpha_max,
-                                       acc);
-                    }
-#pragma unroll
-                    for (int f = 0; f < GSN_NZ; ++f) acc[f] = group_sum<LG>(acc[f]);
-                    if (k < nlarge && r == 0) {
-                        write_partial(partial, flags, r_slot[e], acc);
-                        kflag[r_id[e]] = 1;
-                        ++n_part;
+                        for (int f = 0; f < GSN_NZ; ++f) acc[f] = group_sum<SG>(acc[f]);
+                        if (k < nsmall && r == 0) {
+                            write_partial(partial, flags, r_slot[e], acc);
+                            kflag[r_id[e]] = 1;
+                            ++n_part;
+                        }
                     }
                 }
             }

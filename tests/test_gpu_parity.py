@@ -278,6 +278,32 @@ def test_series_stages_parity(gsn, ctx):
         assert errs[a] < TOL_STEP, (a, errs[a])
 
 
+def test_c0_sweeps_lower_the_loss_like_the_oracle(gsn, ctx):
+    """Five sweeps on the 256-kernel scene at step fraction 0.3: the library's loss before each
+    sweep follows the oracle's run from the same start (each side carries its own state)."""
+    from paper_2501_13975_amd.train import LocalNewtonTrainer
+    cfg = make_config("c0")
+    cam = cfg.cams[0]
+    tgt = O.render(cfg.gt, cam, O.opts()).img.astype(np.float32)
+    g, want = cfg.init, []
+    for _ in range(5):
+        res = O.sweep(g, cfg.cams, [tgt], 0, None, O.opts(step_frac=0.3))
+        want.append(res["losses"][0][0] + 0.2 * res["losses"][0][1])
+        g = res["new"]
+    dg = gsn.DeviceGaussians.from_host(cfg.init)
+    tr = LocalNewtonTrainer(dg, cfg.cams, [torch.tensor(tgt, device=ctx.device)], 0, 0.2,
+                            solve_kw={"step_frac": 0.3})
+    got = []
+    for _ in range(5):
+        tr.sweep(0)
+        lv = tr.loss[0].cpu().numpy()
+        got.append(lv[0] + 0.2 * lv[1])
+    tr.close()
+    _report("c0 sweeps", {f"loss{i}": v for i, v in enumerate(got)})
+    assert all(b < a for a, b in zip(got, got[1:])), got
+    assert np.allclose(got, want, rtol=1e-3, atol=0), (got, want)
+
+
 def test_edge_cases(gsn, ctx):
     """No kernels; every kernel behind the camera; a single kernel."""
     cfg = make_config("c0")
