@@ -277,17 +277,24 @@ size_t scan_tmp_words(uint32_t n) {
 // stable scatter.  Within a workgroup the keys are ranked in order: each
 // wave finds its lanes with equal digit by ballots over the digit bits.
 // ---------------------------------------------------------------------------
-constexpr int kRsItems = 16;
-constexpr int kRsTile = kThreads * kRsItems;
+// Keys per thread of one pass: 16 for the pair passes (tens of millions of keys), 4 for the depth
+// sort of the kernels (about a million keys: 4x the workgroups, so the chip is filled).
+constexpr int kRsItems = 16, kRsItemsSmall = 4;
+constexpr uint32_t kRsSmallN = 1u << 22;
+__host__ __device__ inline uint32_t radix_tile(uint32_t n) {
+    return (uint32_t)kThreads * (n <= kRsSmallN ? kRsItemsSmall : kRsItems);
+}
 
+template <int ITEMS>
 __global__ __launch_bounds__(kThreads) void radix_hist_kernel(const uint32_t* __restrict__ keys, uint32_t n,
                                                                int shift, uint32_t nb, uint32_t* __restrict__ hist) {
+    constexpr int TILE = kThreads * ITEMS;
     __shared__ uint32_t cnt[256];
     cnt[threadIdx.x] = 0;
     __syncthreads();
-    const size_t base = (size_t)blockIdx.x * kRsTile;
+    const size_t base = (size_t)blockIdx.x * TILE;
 #pragma unroll 4
-    for (int i = 0; i < kRsItems; ++i) {
+    for (int i = 0; i < ITEMS; ++i) {
         const size_t idx = base + (size_t)i * kThreads + threadIdx.x;
         if (idx < n) atomicAdd(&cnt[(keys[idx] >> shift) & 255u], 1u);
     }
@@ -329,15 +336,17 @@ __global__ __launch_bounds__(kThreads) void radix_colscan_kernel(const uint32_t*
 // gives every wave the position of its first item of each digit.  Items are placed in LDS in
 // digit order and written out by LDS position, so that consecutive threads write consecutive
 // addresses of one digit's run (coalesced).
+template <int ITEMS>
 __global__ __launch_bounds__(kThreads) void radix_scatter_kernel(
     const uint32_t* __restrict__ kin, const uint32_t* __restrict__ vin, uint32_t n, int shift, uint32_t nb,
     const uint32_t* __restrict__ offs, const uint32_t* __restrict__ dtot, uint32_t* __restrict__ kout,
     uint32_t* __restrict__ vout) {
     constexpr int NWV = kThreads / 64;
+    constexpr int TILE = kThreads * ITEMS;
     __shared__ uint32_t base_d[256], lstart[256];
     __shared__ uint32_t wpos[NWV][256];
     __shared__ uint32_t wsum[NWV];
-    __shared__ uint32_t sk[kRsTile], sv[kRsTile];
+    __shared__ uint32_t sk[TILE], sv[TILE];
     const int tid = threadIdx.x, lane = __lane_id(), wave = tid / 64;
     {
         // global start of digit tid: the totals of the smaller digits, then this workgroup's offset
@@ -348,13 +357,13 @@ __global__ __launch_bounds__(kThreads) void radix_scatter_kernel(
     for (int w = 0; w < NWV; ++w) wpos[w][tid] = 0;
     __syncthreads();
     const uint64_t lt_mask = (lane == 0) ? 0ull : ((~0ull) >> (64 - lane));
-    const size_t base = (size_t)blockIdx.x * kRsTile;
-    const size_t wbase = base + (size_t)wave * 64 * kRsItems;
-    uint32_t key[kRsItems], val[kRsItems];
-    uint64_t peers[kRsItems];
+    const size_t base = (size_t)blockIdx.x * TILE;
+    const size_t wbase = base + (size_t)wave * 64 * ITEMS;
+    uint32_t key[ITEMS], val[ITEMS];
+    uint64_t peers[ITEMS];
     // (1) the wave's items, their equal-digit peers, and the wave's count of each digit
 #pragma unroll
-    for (int it = 0; it < kRsItems; ++it) {
+    for (int it = 0; it < ITEMS; ++it) {
         const size_t idx = wbase + (size_t)it * 64 + lane;
         const bool valid = idx < n;
         key[it] = valid ? kin[idx] : 0u;
@@ -402,7 +411,7 @@ __global__ __launch_bounds__(kThreads) void radix_scatter_kernel(
     __syncthreads();
     // (3) place the wave's items in order (row by row, lane by lane within a digit)
 #pragma unroll
-    for (int it = 0; it < kRsItems; ++it) {
+    for (int it = 0; it < ITEMS; ++it) {
         const uint64_t pm = peers[it];
         if (pm == 0ull) continue;  // invalid lane
         const uint32_t d = (key[it] >> shift) & 255u;
@@ -413,7 +422,7 @@ __global__ __launch_bounds__(kThreads) void radix_scatter_kernel(
         if (rank == 0) wpos[wave][d] = pos + (uint32_t)__popcll(pm);
     }
     __syncthreads();
-    const uint32_t cnt = (uint32_t)min((size_t)kRsTile, (size_t)n - base);
+    const uint32_t cnt = (uint32_t)min((size_t)TILE, (size_t)n - base);
     for (uint32_t j = tid; j < cnt; j += kThreads) {
         const uint32_t k = sk[j];
         const uint32_t d = (k >> shift) & 255u;
@@ -686,7 +695,7 @@ void launch_preprocess(const gsn_gaussians& g, const DevCam& cam, const DevRende
 }
 
 size_t scan_tmp_bytes(uint32_t n) {
-    const size_t hist_words = (size_t)256 * ((n + kRsTile - 1) / kRsTile);
+    const size_t hist_words = (size_t)256 * ((n + radix_tile(n) - 1) / radix_tile(n));
     return 4 * std::max(scan_tmp_words(n), scan_tmp_words((uint32_t)hist_words));
 }
 
@@ -702,7 +711,8 @@ hipError_t radix_sort_pairs(uint32_t* k0, uint32_t* v0, uint32_t* k1, uint32_t* 
                             int bit_hi, DevBuf& hist, DevBuf& scan_tmp, hipStream_t s) {
     (void)scan_tmp;
     if (n == 0) return hipSuccess;
-    const uint32_t nb = (n + kRsTile - 1) / kRsTile;
+    const uint32_t tile = radix_tile(n), nb = (n + tile - 1) / tile;
+    const bool small = n <= kRsSmallN;
     hipError_t e = buf_reserve(hist, radix_hist_bytes(n));
     if (e != hipSuccess) return e;
     uint32_t* h = bp<uint32_t>(hist);
@@ -711,9 +721,11 @@ hipError_t radix_sort_pairs(uint32_t* k0, uint32_t* v0, uint32_t* k1, uint32_t* 
     int passes = 0;
     uint32_t *ka = k0, *va = v0, *kb = k1, *vb = v1;
     for (int shift = bit_lo; shift < bit_hi; shift += 8, ++passes) {
-        radix_hist_kernel<<<nb, kThreads, 0, s>>>(ka, n, shift, nb, h);
+        if (small) radix_hist_kernel<kRsItemsSmall><<<nb, kThreads, 0, s>>>(ka, n, shift, nb, h);
+        else radix_hist_kernel<kRsItems><<<nb, kThreads, 0, s>>>(ka, n, shift, nb, h);
         radix_colscan_kernel<<<256, kThreads, 0, s>>>(h, nb, o, dt);
-        radix_scatter_kernel<<<nb, kThreads, 0, s>>>(ka, va, n, shift, nb, o, dt, kb, vb);
+        if (small) radix_scatter_kernel<kRsItemsSmall><<<nb, kThreads, 0, s>>>(ka, va, n, shift, nb, o, dt, kb, vb);
+        else radix_scatter_kernel<kRsItems><<<nb, kThreads, 0, s>>>(ka, va, n, shift, nb, o, dt, kb, vb);
         uint32_t* t = ka; ka = kb; kb = t;
         t = va; va = vb; vb = t;
     }
@@ -732,7 +744,7 @@ void launch_gather_u32(const uint32_t* src, const uint32_t* idx, uint32_t* dst, 
 size_t emit_chunks(uint32_t pairs) { return ((size_t)pairs + kEmitChunk - 1) / kEmitChunk; }
 
 size_t radix_hist_bytes(uint32_t n) {
-    const size_t nb = ((size_t)n + kRsTile - 1) / kRsTile;
+    const size_t nb = ((size_t)n + radix_tile(n) - 1) / radix_tile(n);
     return ((size_t)256 * nb * 2 + 256) * 4;
 }
 
