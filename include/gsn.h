@@ -197,7 +197,9 @@ gsn_status gsn_render(gsn_ctx* ctx, const gsn_gaussians* g, const gsn_camera* ca
  * kernel and attribute group, and writes this view's colour statistics into
  * view slot `view_slot` (0 = primary target, 1.. = secondary targets, Sec.
  * 4.3).  `g` must be the kernels the frame was rendered from.  Slot 0 also
- * sets the primary coverage row.  d_loss_out (device double[2], may be NULL)
+ * sets the primary coverage row; accumulate slot 0 first in a sweep: the
+ * secondary slots add blocks only for kernels the primary covers (the only
+ * kernels a sweep updates), the others keep what gsn_blocks_zero left.  d_loss_out (device double[2], may be NULL)
  * receives (L2, L_S) of this view.  Blocks are accumulated with a fixed
  * reduction order (no atomics), so results are deterministic.
  * Errors: GSN_E_SHAPE (n differs from the frame's, view_slot outside

@@ -488,14 +488,15 @@ __global__ __launch_bounds__(256) void reduce_pairs_kernel(int n, const uint2* _
                                                            const float* __restrict__ partial,
                                                            const uint8_t* __restrict__ flags,
                                                            const uint8_t* __restrict__ kflag,
+                                                           const float* __restrict__ primary_cov,
                                                            double* __restrict__ zsum) {
     const int lane = __lane_id();
     const int k0 = (blockIdx.x * (blockDim.x / 64) + threadIdx.x / 64) * 64;
     if (k0 >= n) return;
-    // the wave's 64 kernels: those without partials get a zero coverage, the others are
-    // summed one after another by the whole wave
+    // the wave's 64 kernels: those without partials (or, for a secondary view, not seen by the
+    // primary) get a zero coverage, the others are summed one after another by the whole wave
     const int kl = k0 + lane;
-    const bool has = kl < n && kflag[kl] != 0;
+    const bool has = kl < n && kflag[kl] != 0 && (!primary_cov || primary_cov[kl] > 0.f);
     if (kl < n && !has) zsum[(size_t)kl * GSN_NZ + GSN_NZ - 1] = 0.0;
     uint64_t todo = __ballot(has);
     while (todo) {  // uniform across the wave
@@ -651,7 +652,9 @@ void launch_reduce_chain(const gsn_frame& f, const gsn_gaussians& g, float weigh
     const int K = (g.sh_degree + 1) * (g.sh_degree + 1);
     reduce_pairs_kernel<<<(g.n + 255) / 256, 256, 0, s>>>(g.n, bp<uint2>(f.rect), bp<uint32_t>(f.pair_off),
                                                       bp<float>(f.partial), bp<uint8_t>(f.flags),
-                                                      bp<uint8_t>(f.kflag), bp<double>(f.zsum));
+                                                      bp<uint8_t>(f.kflag),
+                                                      slot > 0 ? b.d_data + (size_t)29 * g.n : nullptr,
+                                                      bp<double>(f.zsum));
     auto pos_k = gauss_newton ? chain_pos_kernel<true> : chain_pos_kernel<false>;
     auto rs_k = gauss_newton ? chain_rs_kernel<true> : chain_rs_kernel<false>;
     pos_k<<<(g.n + 127) / 128, 128, 0, s>>>(g.d_pos, g.d_rot, g.d_scale, g.d_sh, g.n, K, bp<double>(f.zsum),

@@ -557,16 +557,34 @@ __global__ __launch_bounds__(GSN_BLOCK) void raster_fwd_kernel(
     bool done = !inside;
     const float fpx = (float)px, fpy = (float)py;
     uint32_t evals = 0, staged = 0;
+    // each thread's entry of the next batch is loaded while the current batch is composited
+    float4 na = make_float4(0.f, 0.f, 0.f, 0.f), nb = na, nc = na;
+    bool nvalid = rg.x + threadIdx.x < rg.y;
+    if (nvalid) {
+        const uint32_t id = ids[rg.x + threadIdx.x];
+        na = rec[id];
+        nb = rec[n + id];
+        nc = rec[2 * (size_t)n + id];
+    }
     for (uint32_t base = rg.x; base < rg.y; base += GSN_BLOCK) {
         if (__syncthreads_count(done) == GSN_BLOCK) break;
 #pragma unroll
         for (int w = 0; w < NW; ++w) s_em[w][threadIdx.x] = 0ull;
-        const uint32_t e = base + threadIdx.x;
+        const float4 a = na, b = nb, c4 = nc;
+        const bool valid = nvalid;
+        {
+            const uint32_t e2 = base + GSN_BLOCK + threadIdx.x;
+            nvalid = e2 < rg.y;
+            if (nvalid) {
+                const uint32_t id = ids[e2];
+                na = rec[id];
+                nb = rec[n + id];
+                nc = rec[2 * (size_t)n + id];
+            }
+        }
         uint32_t bandmask = 0;
-        if (e < rg.y) {
+        if (valid) {
             ++staged;
-            const uint32_t id = ids[e];
-            const float4 a = rec[id], b = rec[n + id], c4 = rec[2 * (size_t)n + id];
             s_a[threadIdx.x] = a;
             s_b[threadIdx.x] = b;
             s_c[threadIdx.x] = c4;
