@@ -366,13 +366,13 @@ gsn_status gsn_accumulate_hessian(gsn_ctx* ctx, const gsn_gaussians* g, const gs
     const size_t npx = (size_t)f->W * f->H;
     HIP_TRY(ctx, buf_reserve(f->dL, 3 * npx * 4));
     HIP_TRY(ctx, buf_reserve(f->hd, 3 * npx * 4));
-    HIP_TRY(ctx, buf_reserve(f->coef, 24 * npx * 8));
+    HIP_TRY(ctx, buf_reserve(f->coef, 24 * npx * 4));
     const int nparts = ((f->W + 15) / 16) * ((f->H + 15) / 16) * 3;
     HIP_TRY(ctx, buf_reserve(f->loss_part, (size_t)2 * nparts * sizeof(double)));
     {
         StageTimer st_(ctx, GSN_STAGE_LOSS);
         int np_out = 0;
-        launch_loss_maps(bp<float>(f->img), d_target, f->W, f->H, opts->lambda_ssim, bp<double>(f->coef),
+        launch_loss_maps(bp<float>(f->img), d_target, f->W, f->H, opts->lambda_ssim, bp<float>(f->coef),
                          bp<float>(f->dL), bp<float>(f->hd), bp<double>(f->loss_part), &np_out, s);
         if (d_loss_out) launch_loss_reduce(bp<double>(f->loss_part), np_out, f->W, f->H, d_loss_out, s);
         HIP_TRY(ctx, hipGetLastError());

@@ -110,17 +110,26 @@ __device__ __forceinline__ float row_sum(float v) {
     v += dpp_mov<0x140>(v);  // row_mirror: the other half of the row
     return v;
 }
-// Sum over aligned groups of G lanes (G = 4, 8, 16, 32 or 64), left in every lane of the group.
+// Sum over aligned groups of G lanes (G = 4, 8, 16, 32 or 64): left in every lane of the group,
+// except for G = 32, where it is in the group's second row (see group_writer).
 template <int G>
 __device__ __forceinline__ float group_sum(float v) {
     if (G == 4) return quad_sum(v);
     if (G == 8) return quad_sum(v) + dpp_mov<0x141>(quad_sum(v));
     if (G == 16) return row_sum(v);
     float r = row_sum(v);
+    if (G == 32) {
+        // row_bcast:15 adds the even row's total into the odd row: the group's total is in its second
+        // row (lanes 16..31 of the group), the first row keeps its own total
+        return r + __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(r), 0x142, 0xA, 0xF, false));
+    }
     r += __shfl_xor(r, 16, 64);
     if (G == 64) r += __shfl_xor(r, 32, 64);
     return r;
 }
+// The lane of a G-lane group that holds the group's total after group_sum.
+template <int G>
+__device__ __forceinline__ constexpr int group_writer() { return G == 32 ? 16 : 0; }
 
 // Adds the statistics of staged pair i (slot in LDS) of the splat (a, b, c4) to acc.
 template <bool GN>
@@ -311,14 +320,15 @@ __global__ __launch_bounds__(GSN_BLOCK, 3) void raster_bwd_kernel(
             }
         }
         __syncthreads();
-        for (int r0 = 0; r0 < bcnt;) {
-            // (b) slots: block-wide exclusive scan of the pair counts of entries r0.. in (entry, wave) order;
-            // thread t owns the four cells of entry t
+        // (b) slots: block-wide exclusive scan of the batch's pair counts in (entry, wave) order, once per
+        // batch; a round's slots are offsets from the scan at its first entry.  Thread t owns the four
+        // cells of entry t.
+        {
             {
                 uint32_t c[NW], tot = 0;
 #pragma unroll
                 for (int w = 0; w < NW; ++w) {
-                    c[w] = tid >= r0 ? (uint32_t)__popcll(s_mask[tid][w]) : 0u;
+                    c[w] = (uint32_t)__popcll(s_mask[tid][w]);
                     tot += c[w];
                 }
                 uint32_t v = tot;
@@ -341,12 +351,15 @@ __global__ __launch_bounds__(GSN_BLOCK, 3) void raster_bwd_kernel(
                 if (tid == GSN_BLOCK - 1) s_off[GSN_BLOCK * NW] = o;
             }
             __syncthreads();
-            // the round takes entries r0..r1-1: the largest r1 <= bcnt with s_off[r1 * NW] <= PMAX
-            // (one entry has at most 256 pairs, so r1 > r0)
+        }
+        for (int r0 = 0; r0 < bcnt;) {
+            // the round takes entries r0..r1-1: the largest r1 <= bcnt with s_off[r1 * NW] - s_off[r0 * NW]
+            // <= PMAX (one entry has at most 256 pairs, so r1 > r0)
+            const uint32_t rbase = s_off[r0 * NW];
             int lo = r0 + 1, hi = bcnt;
             while (lo < hi) {
                 const int mid = (lo + hi + 1) >> 1;
-                if (s_off[mid * NW] <= (uint32_t)PMAX) lo = mid; else hi = mid - 1;
+                if (s_off[mid * NW] - rbase <= (uint32_t)PMAX) lo = mid; else hi = mid - 1;
             }
             const int r1 = lo;
             // (c) front to back over the pixel's composited entries r0..r1-1
@@ -369,7 +382,8 @@ __global__ __launch_bounds__(GSN_BLOCK, 3) void raster_bwd_kernel(
                     Ca1 += wd * (double)cc.x;
                     Ca2 += wd * (double)cc.y;
                     const float inv = 1.0f / (1.0f - al);
-                    const uint32_t slot = s_off[j * NW + wave] + (uint32_t)__popcll(s_mask[j][wave] & lt_mask);
+                    const uint32_t slot =
+                        s_off[j * NW + wave] - rbase + (uint32_t)__popcll(s_mask[j][wave] & lt_mask);
                     s_pa[slot] = make_float4(T, ev.G, T * b.w - (float)(cf[0] - Ca0) * inv,
                                              T * cc.x - (float)(cf[1] - Ca1) * inv);
                     s_pb[slot] = T * cc.y - (float)(cf[2] - Ca2) * inv;
@@ -423,14 +437,14 @@ __global__ __launch_bounds__(GSN_BLOCK, 3) void raster_bwd_kernel(
                         int e = 0;
                         if (k < nlarge) {
                             e = s_big[k];
-                            const uint32_t q0 = s_off[e * NW], q1 = s_off[(e + 1) * NW];
+                            const uint32_t q0 = s_off[e * NW] - rbase, q1 = s_off[(e + 1) * NW] - rbase;
                             for (uint32_t i = q0 + r; i < q1; i += LG)
                                 pair_stats<GN>(r_a[e], r_b[e], r_c[e], s_pa, s_pb, s_pix, s_lm0, s_lm1, i, tx, ty,
                                                ro.alpha_max, acc);
                         }
 #pragma unroll
                         for (int f = 0; f < GSN_NZ; ++f) acc[f] = group_sum<LG>(acc[f]);
-                        if (k < nlarge && r == 0) {
+                        if (k < nlarge && r == group_writer<LG>()) {
                             write_partial(partial, flags, r_slot[e], acc);
                             kflag[r_id[e]] = 1;
                             ++n_part;
@@ -441,14 +455,14 @@ __global__ __launch_bounds__(GSN_BLOCK, 3) void raster_bwd_kernel(
                         int e = 0;
                         if (k < nsmall) {
                             e = s_act[k];
-                            const uint32_t q0 = s_off[e * NW], q1 = s_off[(e + 1) * NW];
+                            const uint32_t q0 = s_off[e * NW] - rbase, q1 = s_off[(e + 1) * NW] - rbase;
                             for (uint32_t i = q0 + r; i < q1; i += SG)
                                 pair_stats<GN>(r_a[e], r_b[e], r_c[e], s_pa, s_pb, s_pix, s_lm0, s_lm1, i, tx, ty,
                                                ro.alpha_max, acc);
                         }
 #pragma unroll
                         for (int f = 0; f < GSN_NZ; ++f) acc[f] = group_sum<SG>(acc[f]);
-                        if (k < nsmall && r == 0) {
+                        if (k < nsmall && r == group_writer<SG>()) {
                             write_partial(partial, flags, r_slot[e], acc);
                             kflag[r_id[e]] = 1;
                             ++n_part;

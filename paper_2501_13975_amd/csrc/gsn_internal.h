@@ -54,7 +54,7 @@ struct gsn_frame {
                         // staged batch of 256 list entries, per pixel (bit j of word w: entry 64 w + j of
                         // the batch), then per (wave, entry) (bit l: pixel l of the wave's 16 x 4 band)
     DevBuf dL, hd;      // float [3][H][W] loss maps
-    DevBuf coef;        // double [3][8][H][W] SSIM coefficient maps
+    DevBuf coef;        // float [3][8][H][W] SSIM coefficient maps (computed in double, stored rounded)
     DevBuf zsum;        // double [n][GSN_NZ] per-kernel sums of the pair partials
     DevBuf zstats;      // float [GSN_NZ][n], optional debug copy
     DevBuf loss_part;   // double [2][nblocks]
@@ -128,7 +128,7 @@ void launch_raster_fwd(const uint2* ranges, const uint32_t* ids, const float4* r
 void launch_downsample2x(const float* src, int W, int H, float* dst, hipStream_t s);
 
 // ---- launchers (loss.hip)
-void launch_loss_maps(const float* img, const float* tgt, int W, int H, float lambda, double* coef, float* dL,
+void launch_loss_maps(const float* img, const float* tgt, int W, int H, float lambda, float* coef, float* dL,
                       float* hd, double* part, int* nparts, hipStream_t s);
 void launch_loss_reduce(const double* part, int nparts, int W, int H, double* out, hipStream_t s);
 

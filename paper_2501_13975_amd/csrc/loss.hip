@@ -16,10 +16,12 @@
 // coefficient map into a correlation with w (three maps) or w^2 (five maps).
 //
 // Pass 1 (one workgroup per 16x16 tile of window centres and channel): moments
-// by separable convolution through LDS, then the eight coefficient maps and the
-// loss partial sums (double).  Pass 2 (32x32 tiles, one map at a time): the eight
-// correlations and the per-pixel gradient dL and diagonal Hessian h.  Pass 3: double-precision reduction of
-// the loss partials in a fixed order.
+// by separable convolution through LDS, then the eight coefficient maps
+// (computed in double and stored in single precision: their rounding moves dL
+// and h by about 5e-8 of the maps' largest values) and the loss partial sums
+// (double).  Pass 2 (32x32 tiles, one map at a time): the eight correlations in
+// double and the per-pixel gradient dL and diagonal Hessian h.  Pass 3:
+// double-precision reduction of the loss partials in a fixed order.
 #include "gsn_internal.h"
 
 namespace {
@@ -42,7 +44,7 @@ __device__ __forceinline__ void window_weights(double* g, double* g2) {
 }
 
 __global__ __launch_bounds__(256) void ssim_coef_kernel(const float* __restrict__ img, const float* __restrict__ tgt,
-                                                         int W, int H, double* __restrict__ coef,
+                                                         int W, int H, float* __restrict__ coef,
                                                          double* __restrict__ part) {
     __shared__ double g[11], g2[11];
     __shared__ double sc[R][R], st[R][R];
@@ -104,15 +106,15 @@ __global__ __launch_bounds__(256) void ssim_coef_kernel(const float* __restrict_
         const double bcc = 8.0 * i3 * i3;
         const double btc = -8.0 * i1 * i3;
         const size_t pi = (size_t)y * W + x;
-        double* cf = coef + (size_t)ch * 8 * np;
-        cf[0 * np + pi] = F * a0;
-        cf[1 * np + pi] = F * a1;
-        cf[2 * np + pi] = F * a2;
-        cf[3 * np + pi] = F * b0;
-        cf[4 * np + pi] = F * bt;
-        cf[5 * np + pi] = F * bc;
-        cf[6 * np + pi] = F * bcc;
-        cf[7 * np + pi] = F * btc;
+        float* cf = coef + (size_t)ch * 8 * np;
+        cf[0 * np + pi] = (float)(F * a0);
+        cf[1 * np + pi] = (float)(F * a1);
+        cf[2 * np + pi] = (float)(F * a2);
+        cf[3 * np + pi] = (float)(F * b0);
+        cf[4 * np + pi] = (float)(F * bt);
+        cf[5 * np + pi] = (float)(F * bc);
+        cf[6 * np + pi] = (float)(F * bcc);
+        cf[7 * np + pi] = (float)(F * btc);
         const double r = (double)sc[ly + HALO][lx + HALO] - (double)st[ly + HALO][lx + HALO];
         l2 = r * r;
         ls = 1.0 - F;
@@ -145,7 +147,7 @@ __global__ __launch_bounds__(256) void ssim_coef_kernel(const float* __restrict_
 constexpr int T2 = 32, R2 = T2 + 2 * HALO;  // 42
 
 __global__ __launch_bounds__(256) void ssim_grad_kernel(const float* __restrict__ img, const float* __restrict__ tgt,
-                                                         int W, int H, float lambda, const double* __restrict__ coef,
+                                                         int W, int H, float lambda, const float* __restrict__ coef,
                                                          float* __restrict__ dL, float* __restrict__ hd) {
     __shared__ double g[11], g2[11];
     __shared__ double sm[R2][R2];
@@ -153,7 +155,7 @@ __global__ __launch_bounds__(256) void ssim_grad_kernel(const float* __restrict_
     const int ch = blockIdx.z;
     const int x0 = blockIdx.x * T2 - HALO, y0 = blockIdx.y * T2 - HALO;
     const size_t np = (size_t)W * H;
-    const double* cf = coef + (size_t)ch * 8 * np;
+    const float* cf = coef + (size_t)ch * 8 * np;
     window_weights(g, g2);
     const int lx = threadIdx.x % T2, ly0 = 4 * (threadIdx.x / T2);  // rows ly0 .. ly0 + 3
     // d1 = v0 + t v1 - c v2 and d2 = v3 + t v4 + c v5 + c^2 v6 + c t v7 - v2 are linear in the
@@ -169,11 +171,11 @@ __global__ __launch_bounds__(256) void ssim_grad_kernel(const float* __restrict_
         d1[r] = d2[r] = 0.0;
     }
     for (int q = 0; q < 8; ++q) {
-        const double* map = cf + (size_t)q * np;
+        const float* map = cf + (size_t)q * np;
         for (int i = threadIdx.x; i < R2 * R2; i += 256) {
             const int yy = i / R2, xx = i % R2, x = x0 + xx, y = y0 + yy;
             const bool in = x >= 0 && y >= 0 && x < W && y < H;
-            sm[yy][xx] = in ? map[(size_t)y * W + x] : 0.0;
+            sm[yy][xx] = in ? (double)map[(size_t)y * W + x] : 0.0;
         }
         __syncthreads();
         const double* wq = q < 3 ? g : g2;
@@ -244,7 +246,7 @@ __global__ void loss_reduce_kernel(const double* __restrict__ part, int nparts, 
 
 }  // namespace
 
-void launch_loss_maps(const float* img, const float* tgt, int W, int H, float lambda, double* coef, float* dL,
+void launch_loss_maps(const float* img, const float* tgt, int W, int H, float lambda, float* coef, float* dL,
                       float* hd, double* part, int* nparts, hipStream_t s) {
     dim3 grid((W + T - 1) / T, (H + T - 1) / T, 3);
     *nparts = (int)(grid.x * grid.y * grid.z);
