@@ -214,6 +214,26 @@ def perturb(g: Gaussians, seed, pos_sigma=0.05, log_scale_sigma=0.2) -> Gaussian
     return out
 
 
+def deep_list_scene(seed: int, n: int = 4000):
+    """A single 16x16 tile whose list is n entries deep: n small, faint kernels (opacity 0.04-0.08,
+    scale about 0.7 px) spread over a 16x16 view at distance 4, so that every pixel keeps
+    compositing far down the depth-sorted list.  Returns (ground truth, perturbed start, camera)."""
+    rng = np.random.default_rng(seed)
+    pos = np.zeros((3, n))
+    pos[0] = rng.uniform(-2.4, 2.4, n)
+    pos[1] = rng.uniform(-2.4, 2.4, n)
+    pos[2] = rng.uniform(-0.5, 0.5, n)
+    q = rng.standard_normal((4, n))
+    q /= np.linalg.norm(q, axis=0)
+    scale = np.exp(rng.normal(math.log(0.2), 0.2, (3, n)))
+    opac = rng.uniform(0.04, 0.08, n)
+    sh = rng.uniform(0.1, 0.9, (3, 1, n)) / Y00
+    gt = Gaussians(pos.astype(np.float32), q.astype(np.float32), scale.astype(np.float32),
+                   opac.astype(np.float32), sh.astype(np.float32), 0)
+    cam = look_at_camera((0.0, 0.0, -4.0), (0.0, 0.0, 0.0), (0.0, -1.0, 0.0), 16, 16, 60.0)
+    return gt, perturb(gt, seed + 1, pos_sigma=0.02), cam
+
+
 @dataclass
 class Config:
     name: str

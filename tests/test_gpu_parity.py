@@ -123,6 +123,26 @@ def test_gauss_newton_view_parity(gsn, ctx):
     _check_view(gsn, ctx, cfg.init, cam, tgt, 0.2, "c1-small gauss-newton", gn=True)
 
 
+def test_deep_tile_list_parity(gsn, ctx):
+    """One 16x16 tile with a 4000-entry list of faint kernels: pixels composite far past the
+    batches whose composited pairs the forward pass records, so the backward pass evaluates
+    the later batches itself and stages their pairs over several LDS rounds.  The target is the
+    ground truth's render at half brightness: every pixel averages thousands of kernels, so a
+    perturbed state renders within a few percent of its own ground truth, and the loss gradient
+    (proportional to that residual) would carry the image's single-precision rounding amplified
+    by the image-to-residual ratio (about 30 here) rather than the backward pass's own error."""
+    from synth.scenes import deep_list_scene
+    gt, g, cam = deep_list_scene(77)
+    fr = O.render(gt, cam, O.opts())
+    assert np.diff(fr.tile_start)[0] == 4000
+    tgt = (0.5 * fr.img).astype(np.float32)
+    ctx.profile_enable(True)
+    _check_view(gsn, ctx, g, cam, tgt, 0.2, "deep-list")
+    _, counts = ctx.profile_read()
+    ctx.profile_enable(False)
+    assert counts["bwd_evals"] > 0  # the evaluation path past the recorded batches ran
+
+
 @pytest.mark.parametrize("lam,nsec,gn", [(0.0, 3, False), (0.2, 3, False), (0.2, 0, False), (0.2, 8, False),
                                          (0.2, 3, True)])
 def test_sweep_steps_parity(gsn, ctx, lam, nsec, gn):
