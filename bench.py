@@ -525,6 +525,17 @@ def copy_bandwidth(dev, nbytes=1 << 30, reps=5):
     return 2.0 * nbytes * reps / el / 1e9
 
 
+def copy_probe(nbytes=1 << 30, reps=3):
+    """A plain device copy of known size, for scaling the FETCH_SIZE / WRITE_SIZE counters."""
+    import torch
+    a = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    for _ in range(reps):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print(f"copied {nbytes} bytes x{reps}", flush=True)
+
+
 def sweep_roofline(value, counts, steps, n, views, pixels_per_step, copy_gbs):
     """The whole sweep against HBM: the bytes the method must move per sweep,
     N (708 + 384 V) per kernel set + 28 per emitted pair + 80 per consumed list entry (forward
@@ -645,7 +656,13 @@ def main():
     ap.add_argument("--first-order-epochs", type=int, default=10,
                     help="at most this many epochs of Adam against one epoch of Newton sweeps on the 100k "
                          "scene; 0 skips")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="only copy 1 GiB on the device three times and exit (the calibration run of the HBM "
+                         "traffic counters)")
     args = ap.parse_args()
+    if args.copy_probe:
+        copy_probe()
+        return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU: this build runs the training step on a single MI355X "
               "(how it would shard across GPUs is described in DESIGN.md); run with --gpus 1", file=sys.stderr)

@@ -381,7 +381,9 @@ __global__ __launch_bounds__(GSN_BLOCK, 3) void raster_bwd_kernel(
                     Ca0 += wd * (double)b.w;
                     Ca1 += wd * (double)cc.x;
                     Ca2 += wd * (double)cc.y;
-                    const float inv = 1.0f / (1.0f - al);
+                    // hardware reciprocal (within 1 ulp; the library's divisions are otherwise correctly
+                    // rounded): only the pair terms use it, no decision depends on it
+                    const float inv = __builtin_amdgcn_rcpf(1.0f - al);
                     const uint32_t slot =
                         s_off[j * NW + wave] - rbase + (uint32_t)__popcll(s_mask[j][wave] & lt_mask);
                     s_pa[slot] = make_float4(T, ev.G, T * b.w - (float)(cf[0] - Ca0) * inv,

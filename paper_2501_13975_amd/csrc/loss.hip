@@ -19,8 +19,9 @@
 // by separable convolution through LDS, then the eight coefficient maps
 // (computed in double and stored in single precision: their rounding moves dL
 // and h by about 5e-8 of the maps' largest values) and the loss partial sums
-// (double).  Pass 2 (32x32 tiles, one map at a time): the eight correlations in
-// double and the per-pixel gradient dL and diagonal Hessian h.  Pass 3:
+// (double).  Pass 2 (32x32 tiles, one map at a time, the next map's halo tile
+// read into registers meanwhile): the eight correlations in double and the
+// per-pixel gradient dL and diagonal Hessian h.  Pass 3:
 // double-precision reduction of the loss partials in a fixed order.
 #include "gsn_internal.h"
 
@@ -119,23 +120,24 @@ __global__ __launch_bounds__(256) void ssim_coef_kernel(const float* __restrict_
         l2 = r * r;
         ls = 1.0 - F;
     }
-    // deterministic block reduction in double
-    __shared__ double red[2][256];
-    red[0][threadIdx.x] = l2;
-    red[1][threadIdx.x] = ls;
-    __syncthreads();
-    for (int s = 128; s > 0; s >>= 1) {
-        if (threadIdx.x < s) {
-            red[0][threadIdx.x] += red[0][threadIdx.x + s];
-            red[1][threadIdx.x] += red[1][threadIdx.x + s];
-        }
-        __syncthreads();
+    // deterministic block reduction in double: a butterfly within each wave, then the four wave
+    // sums in wave order
+    __shared__ double red[2][4];
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+        l2 += __shfl_xor(l2, off, 64);
+        ls += __shfl_xor(ls, off, 64);
     }
+    if (__lane_id() == 0) {
+        red[0][threadIdx.x / 64] = l2;
+        red[1][threadIdx.x / 64] = ls;
+    }
+    __syncthreads();
     if (threadIdx.x == 0) {
         const int nb = gridDim.x * gridDim.y * gridDim.z;
         const int b = (blockIdx.z * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x;
-        part[b] = red[0][0];
-        part[nb + b] = red[1][0];
+        part[b] = ((red[0][0] + red[0][1]) + red[0][2]) + red[0][3];
+        part[nb + b] = ((red[1][0] + red[1][1]) + red[1][2]) + red[1][3];
     }
 }
 
@@ -170,14 +172,28 @@ __global__ __launch_bounds__(256) void ssim_grad_kernel(const float* __restrict_
         tv[r] = in ? (double)tgt[ch * np + pi] : 0.0;
         d1[r] = d2[r] = 0.0;
     }
-    for (int q = 0; q < 8; ++q) {
+    // the halo tile of map q + 1 is loaded into registers while map q is correlated
+    constexpr int NLD = (R2 * R2 + 255) / 256;  // 7 elements per thread
+    float pre[NLD];
+    auto load_map = [&](int q) {
         const float* map = cf + (size_t)q * np;
-        for (int i = threadIdx.x; i < R2 * R2; i += 256) {
+#pragma unroll
+        for (int j = 0; j < NLD; ++j) {
+            const int i = threadIdx.x + 256 * j;
             const int yy = i / R2, xx = i % R2, x = x0 + xx, y = y0 + yy;
-            const bool in = x >= 0 && y >= 0 && x < W && y < H;
-            sm[yy][xx] = in ? (double)map[(size_t)y * W + x] : 0.0;
+            const bool in = i < R2 * R2 && x >= 0 && y >= 0 && x < W && y < H;
+            pre[j] = in ? map[(size_t)y * W + x] : 0.f;
+        }
+    };
+    load_map(0);
+    for (int q = 0; q < 8; ++q) {
+#pragma unroll
+        for (int j = 0; j < NLD; ++j) {
+            const int i = threadIdx.x + 256 * j;
+            if (i < R2 * R2) sm[i / R2][i % R2] = (double)pre[j];
         }
         __syncthreads();
+        if (q + 1 < 8) load_map(q + 1);
         const double* wq = q < 3 ? g : g2;
         // horizontal: strips of four outputs share their 14 inputs
         for (int i = threadIdx.x; i < R2 * (T2 / 4); i += 256) {
