@@ -222,7 +222,7 @@ gsn_status gsn_frame_destroy(gsn_ctx* ctx, gsn_frame* f) {
     DevBuf* all[] = {&f->rec, &f->rect, &f->depth_key, &f->ntiles, &f->ids_a, &f->ids_b, &f->keys_a, &f->keys_b,
                      &f->offsets, &f->pair_off, &f->pk_a, &f->pv_a, &f->pk_b, &f->pv_b, &f->partial, &f->flags, &f->kflag,
                      &f->ranges, &f->img, &f->img64, &f->Tfin, &f->ncontrib, &f->dL, &f->hd, &f->coef, &f->zsum, &f->zstats,
-                     &f->loss_part, &f->hist, &f->scan_tmp, &f->total, &f->masks, &f->chunk_first};
+                     &f->loss_part, &f->hist, &f->scan_tmp, &f->total, &f->masks, &f->chunk_first, &f->tile_order, &f->tile_len, &f->bwd_order};
     for (DevBuf* b : all) buf_free(*b);
     if (f->h_total) (void)hipHostFree(f->h_total);
     delete f;
@@ -269,6 +269,9 @@ gsn_status gsn_render(gsn_ctx* ctx, const gsn_gaussians* g, const gsn_camera* ca
     HIP_TRY(ctx, buf_reserve(f->offsets, (nn + 1) * 4));
     HIP_TRY(ctx, buf_reserve(f->pair_off, nn * 4));
     HIP_TRY(ctx, buf_reserve(f->ranges, tiles * sizeof(uint2)));
+    HIP_TRY(ctx, buf_reserve(f->tile_order, tiles * 4));
+    HIP_TRY(ctx, buf_reserve(f->tile_len, tiles * 4));
+    HIP_TRY(ctx, buf_reserve(f->bwd_order, tiles * 4));
     HIP_TRY(ctx, buf_reserve(f->img, 3 * npx * 4));
     HIP_TRY(ctx, buf_reserve(f->img64, 3 * npx * 8));
     HIP_TRY(ctx, buf_reserve(f->Tfin, npx * 4));
@@ -333,14 +336,18 @@ gsn_status gsn_render(gsn_ctx* ctx, const gsn_gaussians* g, const gsn_camera* ca
                                       bp<uint32_t>(f->pv_b), P, 0, tile_bits, f->hist, f->scan_tmp, s));
         launch_fill_u32(bp<uint32_t>(f->ranges), 0u, 2 * tiles, s);
         launch_tile_ranges(bp<uint32_t>(f->pk_a), P, bp<uint2>(f->ranges), s);
+        launch_tile_order(bp<uint2>(f->ranges), nullptr, (int)tiles, bp<uint32_t>(f->tile_order), s);
     }
     if (ctx->prof) ctx->pairs_counted += P;
     {
         // 5. front-to-back compositing
         StageTimer st_(ctx, GSN_STAGE_RASTER_FWD);
-        launch_raster_fwd(bp<uint2>(f->ranges), bp<uint32_t>(f->pv_a), bp<float4>(f->rec), (uint32_t)n, f->cam,
-                          f->ro, bp<float>(f->img), bp<double>(f->img64), bp<float>(f->Tfin),
-                          bp<uint32_t>(f->ncontrib), bp<uint64_t>(f->masks), prof_counts(ctx), s);
+        launch_raster_fwd(bp<uint2>(f->ranges), bp<uint32_t>(f->tile_order), bp<uint32_t>(f->pv_a),
+                          bp<float4>(f->rec), (uint32_t)n, f->cam, f->ro, bp<float>(f->img), bp<double>(f->img64),
+                          bp<float>(f->Tfin), bp<uint32_t>(f->ncontrib), bp<uint64_t>(f->masks),
+                          bp<uint32_t>(f->tile_len), prof_counts(ctx), s);
+        // the backward pass takes the tiles with the longest composited prefixes first
+        launch_tile_order(nullptr, bp<uint32_t>(f->tile_len), (int)tiles, bp<uint32_t>(f->bwd_order), s);
         HIP_TRY(ctx, hipGetLastError());
     }
     if (d_rgb_out) HIP_TRY(ctx, hipMemcpyAsync(d_rgb_out, f->img.p, 3 * npx * 4, hipMemcpyDeviceToDevice, s));

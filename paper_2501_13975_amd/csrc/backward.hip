@@ -26,7 +26,8 @@
 // depth-ordered list front to back with the forward pass's decisions, stages
 // the contributing (pixel, splat) pairs of each round in LDS, and sums each
 // splat's 44 statistics over its pairs (see raster_bwd_kernel); the tile's
-// partial sum is written at the (tile, kernel) pair's slot.
+// partial sum is written at the (tile, kernel) pair's slot.  Workgroups take the
+// tiles with the longest composited prefixes (recorded by the forward pass) first.
 // reduce_pairs: a wave per 64 kernels sums each flagged kernel's written pair slots in a fixed order
 // (no atomics: results are deterministic); chain_pos / chain_rs: one thread per
 // kernel applies the chain rule through the projection with second-order jets
@@ -179,8 +180,9 @@ __device__ __forceinline__ void write_partial(float* __restrict__ partial, uint8
 // GN: local Gauss-Newton statistics (no loss-gradient times image-curvature terms).
 template <bool GN>
 __global__ __launch_bounds__(GSN_BLOCK, 3) void raster_bwd_kernel(
-    const uint2* __restrict__ ranges, const uint32_t* __restrict__ ids, const float4* __restrict__ rec,
-    const uint2* __restrict__ rect, const uint32_t* __restrict__ pair_off, uint32_t n, DevCam cam, DevRenderOpts ro,
+    const uint2* __restrict__ ranges, const uint32_t* __restrict__ order, const uint32_t* __restrict__ ids,
+    const float4* __restrict__ rec, const uint2* __restrict__ rect, const uint32_t* __restrict__ pair_off, uint32_t n,
+    DevCam cam, DevRenderOpts ro,
     const double* __restrict__ img64, const uint32_t* __restrict__ ncontrib, const uint64_t* __restrict__ masks,
     const float* __restrict__ dLm, const float* __restrict__ hdm, float* __restrict__ partial,
     uint8_t* __restrict__ flags, uint8_t* __restrict__ kflag, unsigned long long* __restrict__ counts) {
@@ -201,7 +203,7 @@ __global__ __launch_bounds__(GSN_BLOCK, 3) void raster_bwd_kernel(
     __shared__ uint8_t s_pix[PMAX];
     __shared__ uint32_t s_max;
     const int tid = threadIdx.x;
-    const int tile = blockIdx.x;
+    const int tile = (int)order[blockIdx.x];
     const int tx = tile % cam.tiles_x, ty = tile / cam.tiles_x;
     const int px = tx * GSN_TILE + (tid % GSN_TILE);
     const int py = ty * GSN_TILE + (tid / GSN_TILE);
@@ -656,7 +658,7 @@ void launch_raster_bwd(const gsn_frame& f, const float* dL, const float* hd, boo
     const int tiles = f.tiles_x * f.tiles_y;
     auto kern = gauss_newton ? raster_bwd_kernel<true> : raster_bwd_kernel<false>;
     kern<<<tiles, GSN_BLOCK, 0, s>>>(
-        bp<uint2>(f.ranges), bp<uint32_t>(f.pv_a), bp<float4>(f.rec),
+        bp<uint2>(f.ranges), bp<uint32_t>(f.bwd_order), bp<uint32_t>(f.pv_a), bp<float4>(f.rec),
         bp<uint2>(f.rect), bp<uint32_t>(f.pair_off), (uint32_t)f.n, f.cam, f.ro, bp<double>(f.img64),
         bp<uint32_t>(f.ncontrib), bp<uint64_t>(f.masks), dL, hd, bp<float>(f.partial), bp<uint8_t>(f.flags),
         bp<uint8_t>(f.kflag), counts);

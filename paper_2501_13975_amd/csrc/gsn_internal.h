@@ -46,6 +46,9 @@ struct gsn_frame {
     DevBuf kflag;       // u8 [n], some partial of the kernel written
     // per tile / pixel
     DevBuf ranges;      // uint2 [tiles]
+    DevBuf tile_order;  // u32 [tiles]: launch order of the forward raster, longest lists first
+    DevBuf tile_len;    // u32 [tiles]: composited prefix of each tile's list (longest over its pixels)
+    DevBuf bwd_order;   // u32 [tiles]: launch order of the backward raster, longest prefixes first
     DevBuf img;         // float [3][H][W]
     DevBuf img64;       // double [3][H][W], the same colour before rounding
     DevBuf Tfin;        // float [H][W]
@@ -122,9 +125,12 @@ void launch_emit_pairs(const uint32_t* sorted_ids, const uint32_t* offsets, uint
 size_t emit_chunks(uint32_t pairs);
 size_t radix_hist_bytes(uint32_t n);
 void launch_tile_ranges(const uint32_t* keys, uint32_t pairs, uint2* ranges, hipStream_t s);
-void launch_raster_fwd(const uint2* ranges, const uint32_t* ids, const float4* rec, uint32_t n, const DevCam& cam,
+// tiles ordered by a length, longest first (coarse: four buckets per octave, any order within one): the
+// list lengths of ranges when lens is null, else lens
+void launch_tile_order(const uint2* ranges, const uint32_t* lens, int tiles, uint32_t* order, hipStream_t s);
+void launch_raster_fwd(const uint2* ranges, const uint32_t* order, const uint32_t* ids, const float4* rec, uint32_t n, const DevCam& cam,
                        const DevRenderOpts& ro, float* img, double* img64, float* Tfin, uint32_t* ncontrib,
-                       uint64_t* masks, unsigned long long* counts, hipStream_t s);
+                       uint64_t* masks, uint32_t* tile_len, unsigned long long* counts, hipStream_t s);
 void launch_downsample2x(const float* src, int W, int H, float* dst, hipStream_t s);
 
 // ---- launchers (loss.hip)

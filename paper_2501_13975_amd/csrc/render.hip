@@ -523,6 +523,43 @@ __global__ void tile_ranges_kernel(const uint32_t* __restrict__ keys, uint32_t p
     if (i == pairs - 1 || keys[i + 1] != k) ranges[k].y = i + 1;
 }
 
+// One workgroup: tiles bucketed by list length (four buckets per octave) and written out longest
+// bucket first, so that the raster passes start their longest tiles first and the short ones fill
+// the end of the launch.  The order within a bucket is whatever the LDS atomics give: every tile is
+// computed independently, so results do not depend on it.
+constexpr int kOrderBuckets = 1 + 32 * 4;
+__device__ __forceinline__ int length_bucket(uint32_t len) {
+    if (len == 0) return 0;
+    const int lz = 31 - __clz((int)len);
+    const uint32_t frac = lz >= 2 ? (len >> (lz - 2)) & 3u : (len << (2 - lz)) & 3u;
+    return 1 + 4 * lz + (int)frac;
+}
+
+__global__ __launch_bounds__(1024) void tile_order_kernel(const uint2* __restrict__ ranges,
+                                                          const uint32_t* __restrict__ lens, int tiles,
+                                                          uint32_t* __restrict__ order) {
+    auto length = [&](int i) -> uint32_t {
+        if (lens) return lens[i];
+        const uint2 r = ranges[i];
+        return r.y - r.x;
+    };
+    __shared__ uint32_t cnt[kOrderBuckets];
+    for (int b = threadIdx.x; b < kOrderBuckets; b += blockDim.x) cnt[b] = 0;
+    __syncthreads();
+    for (int i = threadIdx.x; i < tiles; i += blockDim.x) atomicAdd(&cnt[length_bucket(length(i))], 1u);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        uint32_t acc = 0;
+        for (int b = kOrderBuckets - 1; b >= 0; --b) {
+            const uint32_t c = cnt[b];
+            cnt[b] = acc;
+            acc += c;
+        }
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < tiles; i += blockDim.x) order[atomicAdd(&cnt[length_bucket(length(i))], 1u)] = (uint32_t)i;
+}
+
 // ---------------------------------------------------------------------------
 // Forward compositing, one workgroup per tile, one thread per pixel.  Records are
 // staged in LDS in batches of 256 list entries; each wave (a band of 16 x 4 pixels)
@@ -530,9 +567,10 @@ __global__ void tile_ranges_kernel(const uint32_t* __restrict__ keys, uint32_t p
 // band, so a wave only steps through entries that can composite in it.
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(GSN_BLOCK) void raster_fwd_kernel(
-    const uint2* __restrict__ ranges, const uint32_t* __restrict__ ids, const float4* __restrict__ rec, uint32_t n,
+    const uint2* __restrict__ ranges, const uint32_t* __restrict__ order, const uint32_t* __restrict__ ids, const float4* __restrict__ rec, uint32_t n,
     DevCam cam, DevRenderOpts ro, float* __restrict__ img, double* __restrict__ img64, float* __restrict__ Tfin,
-    uint32_t* __restrict__ ncontrib, uint64_t* __restrict__ masks, unsigned long long* __restrict__ counts) {
+    uint32_t* __restrict__ ncontrib, uint64_t* __restrict__ masks, uint32_t* __restrict__ tile_len,
+    unsigned long long* __restrict__ counts) {
     constexpr int NW = GSN_BLOCK / 64;
     __shared__ float4 s_a[GSN_BLOCK];
     __shared__ float4 s_b[GSN_BLOCK];
@@ -540,7 +578,7 @@ __global__ __launch_bounds__(GSN_BLOCK) void raster_fwd_kernel(
     __shared__ uint8_t s_list[NW][GSN_BLOCK];
     __shared__ uint32_t s_cnt[NW][NW];  // [band][loader wave]
     __shared__ uint64_t s_em[NW][GSN_BLOCK];  // [wave][entry]: the wave's pixels that composited the entry
-    const int tile = blockIdx.x;
+    const int tile = (int)order[blockIdx.x];
     const int tx = tile % cam.tiles_x, ty = tile / cam.tiles_x;
     const int px = tx * GSN_TILE + (threadIdx.x % GSN_TILE);
     const int py = ty * GSN_TILE + (threadIdx.x / GSN_TILE);
@@ -655,6 +693,18 @@ __global__ __launch_bounds__(GSN_BLOCK) void raster_fwd_kernel(
 #pragma unroll
             for (int w = 0; w < NW; ++w) mb[(size_t)(NW + w) * GSN_BLOCK] = s_em[w][threadIdx.x];
         }
+    }
+    {
+        // the tile's composited prefix (the longest over its pixels): the backward pass's work
+        uint32_t m = last;
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) m = max(m, (uint32_t)__shfl_xor((int)m, off, 64));
+        __shared__ uint32_t s_len;
+        if (threadIdx.x == 0) s_len = 0;
+        __syncthreads();
+        if (lane == 0) atomicMax(&s_len, m);
+        __syncthreads();
+        if (threadIdx.x == 0) tile_len[tile] = s_len;
     }
     if (counts) {
         __shared__ unsigned long long s_evals, s_staged;
@@ -781,12 +831,16 @@ void launch_tile_ranges(const uint32_t* keys, uint32_t pairs, uint2* ranges, hip
     if (pairs) tile_ranges_kernel<<<(pairs + kThreads - 1) / kThreads, kThreads, 0, s>>>(keys, pairs, ranges);
 }
 
-void launch_raster_fwd(const uint2* ranges, const uint32_t* ids, const float4* rec, uint32_t n, const DevCam& cam,
+void launch_tile_order(const uint2* ranges, const uint32_t* lens, int tiles, uint32_t* order, hipStream_t s) {
+    if (tiles > 0) tile_order_kernel<<<1, 1024, 0, s>>>(ranges, lens, tiles, order);
+}
+
+void launch_raster_fwd(const uint2* ranges, const uint32_t* order, const uint32_t* ids, const float4* rec, uint32_t n, const DevCam& cam,
                        const DevRenderOpts& ro, float* img, double* img64, float* Tfin, uint32_t* ncontrib,
-                       uint64_t* masks, unsigned long long* counts, hipStream_t s) {
+                       uint64_t* masks, uint32_t* tile_len, unsigned long long* counts, hipStream_t s) {
     const int tiles = cam.tiles_x * cam.tiles_y;
-    raster_fwd_kernel<<<tiles, GSN_BLOCK, 0, s>>>(ranges, ids, rec, n, cam, ro, img, img64, Tfin, ncontrib, masks,
-                                                  counts);
+    raster_fwd_kernel<<<tiles, GSN_BLOCK, 0, s>>>(ranges, order, ids, rec, n, cam, ro, img, img64, Tfin, ncontrib, masks,
+                                                  tile_len, counts);
 }
 
 void launch_downsample2x(const float* src, int W, int H, float* dst, hipStream_t s) {
