@@ -293,10 +293,19 @@ __global__ __launch_bounds__(kThreads) void radix_hist_kernel(const uint32_t* __
     cnt[threadIdx.x] = 0;
     __syncthreads();
     const size_t base = (size_t)blockIdx.x * TILE;
+    const int lane = __lane_id();
+    // a wave holds 64 consecutive keys; runs of equal digits (the pair keys of one splat's tiles
+    // share their high digit) are counted by the run's first lane with one atomic
 #pragma unroll 4
     for (int i = 0; i < ITEMS; ++i) {
         const size_t idx = base + (size_t)i * kThreads + threadIdx.x;
-        if (idx < n) atomicAdd(&cnt[(keys[idx] >> shift) & 255u], 1u);
+        const bool valid = idx < n;
+        const uint32_t d = valid ? (keys[idx] >> shift) & 255u : 256u;
+        const uint32_t prev = (uint32_t)__shfl_up((int)d, 1, 64);
+        const uint64_t heads = __ballot(lane == 0 || d != prev);
+        const uint64_t later = lane == 63 ? 0ull : heads >> (lane + 1);
+        const uint32_t len = later ? (uint32_t)__ffsll((unsigned long long)later) : (uint32_t)(64 - lane);
+        if (valid && ((heads >> lane) & 1ull)) atomicAdd(&cnt[d], len);
     }
     __syncthreads();
     hist[(size_t)threadIdx.x * nb + blockIdx.x] = cnt[threadIdx.x];
