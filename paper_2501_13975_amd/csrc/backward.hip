@@ -516,22 +516,30 @@ __global__ __launch_bounds__(256) void reduce_pairs_kernel(int n, const uint2* _
     const int kl = k0 + lane;
     const bool has = kl < n && kflag[kl] != 0 && (!primary_cov || primary_cov[kl] > 0.f);
     if (kl < n && !has) zsum[(size_t)kl * GSN_NZ + GSN_NZ - 1] = 0.0;
+    // every lane reads its own kernel's slot range up front (one coalesced load instead of a
+    // dependent load per kernel); the wave then takes each kernel's range from its lane
+    uint32_t my_nt = 0, my_off = 0;
+    if (has) {
+        const uint2 rc = rect[kl];
+        my_nt = ((rc.y & 0xffffu) - (rc.x & 0xffffu)) * ((rc.y >> 16) - (rc.x >> 16));
+        my_off = pair_off[kl];
+    }
     uint64_t todo = __ballot(has);
     while (todo) {  // uniform across the wave
-        const int k = k0 + __ffsll((unsigned long long)todo) - 1;
+        const int li = __ffsll((unsigned long long)todo) - 1;
         todo &= todo - 1;
-        const uint2 rc = rect[k];
-        const uint32_t nt = ((rc.y & 0xffffu) - (rc.x & 0xffffu)) * ((rc.y >> 16) - (rc.x >> 16));
-        const uint32_t off = pair_off[k];
+        const int k = k0 + li;
+        const uint32_t nt = (uint32_t)__shfl((int)my_nt, li, 64);
+        const uint32_t off = (uint32_t)__shfl((int)my_off, li, 64);
         double acc = 0.0;
         for (uint32_t base = 0; base < nt; base += 64) {
             const bool fl = base + lane < nt && flags[off + base + lane] != 0;
             uint64_t m = __ballot(fl);
-            while (m) {  // up to four written slots per step: their loads overlap, the adds keep slot order
-                float v[4];
+            while (m) {  // up to eight written slots per step: their loads overlap, the adds keep slot order
+                float v[8];
                 int cntv = 0;
 #pragma unroll
-                for (int t = 0; t < 4; ++t) {
+                for (int t = 0; t < 8; ++t) {
                     v[t] = 0.f;
                     if (m) {
                         const int i = __ffsll((unsigned long long)m) - 1;
@@ -541,7 +549,7 @@ __global__ __launch_bounds__(256) void reduce_pairs_kernel(int n, const uint2* _
                     }
                 }
 #pragma unroll
-                for (int t = 0; t < 4; ++t)
+                for (int t = 0; t < 8; ++t)
                     if (t < cntv) acc += (double)v[t];
             }
         }
