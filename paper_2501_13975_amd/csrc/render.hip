@@ -355,7 +355,7 @@ __global__ __launch_bounds__(kThreads) void radix_scatter_kernel(
     __shared__ uint32_t base_d[256], lstart[256];
     __shared__ uint32_t wpos[NWV][256];
     __shared__ uint32_t wsum[NWV];
-    __shared__ uint32_t sk[TILE], sv[TILE];
+    __shared__ uint2 skv[TILE];  // (key, value)
     const int tid = threadIdx.x, lane = __lane_id(), wave = tid / 64;
     {
         // global start of digit tid: the totals of the smaller digits, then this workgroup's offset
@@ -426,18 +426,17 @@ __global__ __launch_bounds__(kThreads) void radix_scatter_kernel(
         const uint32_t d = (key[it] >> shift) & 255u;
         const uint32_t rank = (uint32_t)__popcll(pm & lt_mask);
         const uint32_t pos = wpos[wave][d] + rank;
-        sk[pos] = key[it];
-        sv[pos] = val[it];
+        skv[pos] = make_uint2(key[it], val[it]);
         if (rank == 0) wpos[wave][d] = pos + (uint32_t)__popcll(pm);
     }
     __syncthreads();
     const uint32_t cnt = (uint32_t)min((size_t)TILE, (size_t)n - base);
     for (uint32_t j = tid; j < cnt; j += kThreads) {
-        const uint32_t k = sk[j];
-        const uint32_t d = (k >> shift) & 255u;
+        const uint2 kv = skv[j];
+        const uint32_t d = (kv.x >> shift) & 255u;
         const uint32_t gpos = base_d[d] + (j - lstart[d]);
-        kout[gpos] = k;
-        vout[gpos] = sv[j];
+        kout[gpos] = kv.x;
+        vout[gpos] = kv.y;
     }
 }
 
