@@ -1,0 +1,105 @@
+"""GPU parity at the benchmark's full size: 1M Gaussians at SH degree 3 on one 1920x1080 view,
+rendered and accumulated by the same library calls and launch shapes the benchmark times (its
+pair lists take the large-sort path).  The per-tile lists are compared bit-exactly over the
+whole frame, the image, transmittance, loss value and loss maps element by element, and the
+blocks of sampled kernels against the oracle's blocks of the same kernels (the oracle computes
+them one kernel at a time).
+
+A frame this size has a few hundred pixels whose threshold decisions sit within rounding of a
+threshold (single- and double-precision compositing may decide them differently, by up to a
+whole splat's colour).  The SSIM window couples every pixel's loss derivatives to the pixels
+within 10 of it (a window of radius 5 around each window centre of radius 5), so the loss maps
+are compared away from those pixels, and the blocks of kernels that any such pixel composited
+are not compared."""
+import numpy as np
+import pytest
+from scipy.ndimage import binary_dilation
+
+from oracle import oracle as O
+from synth.scenes import make_config
+from tests.parity import (BLOCK_GROUPS, TOL_GRAD, TOL_IMAGE, blocks_gpu_to_oracle_view, compare_binning, gpu_view,
+                          near_threshold_kernels, pixel_mask, rel_inf)
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def gsn():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2501_13975_amd import gsn as G
+    return G
+
+
+@pytest.fixture(scope="module")
+def ctx(gsn):
+    c = gsn.Context(0)
+    yield c
+    c.close()
+
+
+def test_full_size_view_parity(gsn, ctx):
+    cfg = make_config("c2")
+    g, cam = cfg.init, cfg.cams[0]
+    lam = 0.2
+    assert (g.n, cam.width, cam.height) == (1_000_000, 1920, 1080)
+    tgt = O.render(cfg.gt, cam, O.opts()).img.astype(np.float32)
+    dg = gsn.DeviceGaussians.from_host(g)
+    blocks = gsn.Blocks(g.n, 1, ctx.device)
+    ctx.blocks_zero(blocks)
+    gv = gpu_view(ctx, gsn, dg, cam, torch.tensor(tgt, device=ctx.device), lam, blocks, 0, keep=False)
+    fr = O.render(g, cam, O.opts(lambda_ssim=lam), g32=g)
+    ov = {"fr": fr}
+    # lists: bit-exact on every tile of the frame
+    assert compare_binning(gv, ov, g.n) == 120 * 68
+    assert gv["pairs"] > 1 << 22  # more pairs than the small-sort threshold
+    # image and compositing decisions
+    mask = pixel_mask(ov)
+    assert (~mask).sum() < 1e-3 * mask.size
+    assert rel_inf(gv["img"][:, mask], fr.img[:, mask]) < TOL_IMAGE
+    assert rel_inf(gv["T"][mask], fr.Tfinal[mask]) < TOL_IMAGE
+    assert np.array_equal(gv["ncontrib"][mask], fr.ncontrib[mask])
+    # loss and its per-pixel derivative maps, away from the ambiguous pixels' SSIM reach
+    parts, dL, hd = O.loss(fr.img, tgt, lam)
+    assert abs(gv["loss"][0] - parts[0]) < TOL_GRAD * abs(parts[0])
+    assert abs(gv["loss"][1] - parts[1]) < TOL_GRAD * abs(parts[1])
+    reach = binary_dilation(~mask, structure=np.ones((21, 21), bool))
+    far = ~reach
+    assert far.sum() > 0.8 * far.size
+    assert rel_inf(gv["dL"][:, far], dL[:, far]) < TOL_GRAD
+    assert rel_inf(gv["h"][:, far], hd[:, far]) < TOL_GRAD
+    # blocks of sampled kernels, none composited at a pixel within that reach (per tile: the list
+    # prefix up to the longest such pixel's last composited entry).  Most of the million kernels
+    # are hidden behind others, so the sample is drawn from the kernels in the front of some
+    # tile's list (the prefix that the tile's median pixel composites or passes): the 32 in the
+    # most such fronts (they set each group's scale) and 368 of the others at random.  Those the
+    # oracle finds composited nowhere must have all-zero blocks on the GPU too.
+    keep = fr.vis.astype(bool) & ~near_threshold_kernels(fr, g.n)
+    tx = (cam.width + 15) // 16
+    ys, xs = np.nonzero(reach)
+    tiles = (ys // 16) * tx + xs // 16
+    deepest = np.full(len(fr.tile_start) - 1, -1, np.int64)
+    np.maximum.at(deepest, tiles, fr.ncontrib[ys, xs].astype(np.int64))
+    for t in np.nonzero(deepest >= 0)[0]:
+        keep[fr.ids[fr.tile_start[t]:fr.tile_start[t] + deepest[t] + 1]] = False
+    assert keep.sum() > 0.5 * g.n
+    front = np.zeros(g.n, np.int64)
+    for t in range(len(fr.tile_start) - 1):
+        ty, tx0 = divmod(t, tx)
+        m = int(np.median(fr.ncontrib[16 * ty:16 * ty + 16, 16 * tx0:16 * tx0 + 16]))
+        front[fr.ids[fr.tile_start[t]:fr.tile_start[t] + m]] += 1
+    front[~keep] = 0
+    big = np.argsort(front)[-32:]
+    rest = np.setdiff1d(np.nonzero(front > 0)[0], big)
+    sel = np.sort(np.concatenate([big, np.random.default_rng(5).choice(rest, 368, replace=False)]))
+    want = O.blocks(g, fr, dL, hd, sel)
+    got = blocks_gpu_to_oracle_view(blocks.view()[:, torch.as_tensor(sel, device=ctx.device)].cpu().numpy(), 0)
+    covered = want[:, 38] > 0
+    assert covered.sum() >= 100
+    assert np.all(got[~covered] == 0.0)
+    got, want = got[covered], want[covered]
+    errs = {name: rel_inf(got[:, sl], want[:, sl]) for name, sl in BLOCK_GROUPS.items()}
+    print("\n[full-size] " + " ".join(f"{k}={v:.2e}" for k, v in errs.items()), flush=True)
+    for name, e in errs.items():
+        assert e < TOL_GRAD, (name, e)
