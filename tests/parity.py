@@ -158,6 +158,28 @@ def near_threshold_kernels(fr, n, margin=MARGIN):
     return bad
 
 
+def ssim_reach(mask, radius=10):
+    """Pixels within `radius` (the SSIM window's reach: a window of radius 5 around each window
+    centre of radius 5) of a pixel outside `mask`; their loss derivatives depend on it."""
+    from scipy.ndimage import binary_dilation
+    return binary_dilation(~mask, structure=np.ones((2 * radius + 1, 2 * radius + 1), bool))
+
+
+def kernels_in_reach(fr, reach, n):
+    """Kernels that may composite at a pixel of `reach`: per tile, the list prefix up to the
+    longest such pixel's last composited entry."""
+    bad = np.zeros(n, bool)
+    if fr.tile_start is None or not reach.any():
+        return bad
+    tx = (fr.cam.width + 15) // 16
+    ys, xs = np.nonzero(reach)
+    deepest = np.full(len(fr.tile_start) - 1, -1, np.int64)
+    np.maximum.at(deepest, (ys // 16) * tx + xs // 16, fr.ncontrib[ys, xs].astype(np.int64))
+    for t in np.nonzero(deepest >= 0)[0]:
+        bad[fr.ids[fr.tile_start[t]:fr.tile_start[t] + deepest[t] + 1]] = True
+    return bad
+
+
 def zstats_to_frame(Z, fc, fs):
     """Oracle statistics [n, 91] over (pi_x, pi_y, Q_xx, Q_xy, Q_yy, sigma, c~) -> the same in each
     kernel's principal frame (pi' = V^T pi, Q' = V^T Q V, V = [[c, -s], [s, c]])."""

@@ -13,12 +13,11 @@ are compared away from those pixels, and the blocks of kernels that any such pix
 are not compared."""
 import numpy as np
 import pytest
-from scipy.ndimage import binary_dilation
 
 from oracle import oracle as O
 from synth.scenes import make_config
 from tests.parity import (BLOCK_GROUPS, TOL_GRAD, TOL_IMAGE, blocks_gpu_to_oracle_view, compare_binning, gpu_view,
-                          near_threshold_kernels, pixel_mask, rel_inf)
+                          kernels_in_reach, near_threshold_kernels, pixel_mask, rel_inf, ssim_reach)
 
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
@@ -64,7 +63,7 @@ def test_full_size_view_parity(gsn, ctx):
     parts, dL, hd = O.loss(fr.img, tgt, lam)
     assert abs(gv["loss"][0] - parts[0]) < TOL_GRAD * abs(parts[0])
     assert abs(gv["loss"][1] - parts[1]) < TOL_GRAD * abs(parts[1])
-    reach = binary_dilation(~mask, structure=np.ones((21, 21), bool))
+    reach = ssim_reach(mask)
     far = ~reach
     assert far.sum() > 0.8 * far.size
     assert rel_inf(gv["dL"][:, far], dL[:, far]) < TOL_GRAD
@@ -75,15 +74,9 @@ def test_full_size_view_parity(gsn, ctx):
     # tile's list (the prefix that the tile's median pixel composites or passes): the 32 in the
     # most such fronts (they set each group's scale) and 368 of the others at random.  Those the
     # oracle finds composited nowhere must have all-zero blocks on the GPU too.
-    keep = fr.vis.astype(bool) & ~near_threshold_kernels(fr, g.n)
-    tx = (cam.width + 15) // 16
-    ys, xs = np.nonzero(reach)
-    tiles = (ys // 16) * tx + xs // 16
-    deepest = np.full(len(fr.tile_start) - 1, -1, np.int64)
-    np.maximum.at(deepest, tiles, fr.ncontrib[ys, xs].astype(np.int64))
-    for t in np.nonzero(deepest >= 0)[0]:
-        keep[fr.ids[fr.tile_start[t]:fr.tile_start[t] + deepest[t] + 1]] = False
+    keep = fr.vis.astype(bool) & ~near_threshold_kernels(fr, g.n) & ~kernels_in_reach(fr, reach, g.n)
     assert keep.sum() > 0.5 * g.n
+    tx = (cam.width + 15) // 16
     front = np.zeros(g.n, np.int64)
     for t in range(len(fr.tile_start) - 1):
         ty, tx0 = divmod(t, tx)
