@@ -38,12 +38,8 @@ def ctx(gsn):
     c.close()
 
 
-def test_full_size_view_parity(gsn, ctx):
-    cfg = make_config("c2")
-    g, cam = cfg.init, cfg.cams[0]
+def _full_size_view(gsn, ctx, g, cam, tgt, tiles, label):
     lam = 0.2
-    assert (g.n, cam.width, cam.height) == (1_000_000, 1920, 1080)
-    tgt = O.render(cfg.gt, cam, O.opts()).img.astype(np.float32)
     dg = gsn.DeviceGaussians.from_host(g)
     blocks = gsn.Blocks(g.n, 1, ctx.device)
     ctx.blocks_zero(blocks)
@@ -51,7 +47,7 @@ def test_full_size_view_parity(gsn, ctx):
     fr = O.render(g, cam, O.opts(lambda_ssim=lam), g32=g)
     ov = {"fr": fr}
     # lists: bit-exact on every tile of the frame
-    assert compare_binning(gv, ov, g.n) == 120 * 68
+    assert compare_binning(gv, ov, g.n) == tiles
     assert gv["pairs"] > 1 << 22  # more pairs than the small-sort threshold
     # image and compositing decisions
     mask = pixel_mask(ov)
@@ -93,6 +89,28 @@ def test_full_size_view_parity(gsn, ctx):
     assert np.all(got[~covered] == 0.0)
     got, want = got[covered], want[covered]
     errs = {name: rel_inf(got[:, sl], want[:, sl]) for name, sl in BLOCK_GROUPS.items()}
-    print("\n[full-size] " + " ".join(f"{k}={v:.2e}" for k, v in errs.items()), flush=True)
+    print(f"\n[{label}] " + " ".join(f"{k}={v:.2e}" for k, v in errs.items()), flush=True)
     for name, e in errs.items():
         assert e < TOL_GRAD, (name, e)
+
+
+@pytest.fixture(scope="module")
+def scene():
+    cfg = make_config("c2")
+    assert (cfg.init.n, cfg.cams[0].width, cfg.cams[0].height) == (1_000_000, 1920, 1080)
+    return cfg
+
+
+def test_full_size_view_parity(gsn, ctx, scene):
+    """The primary view: 1920x1080, 120 x 68 tiles."""
+    cam = scene.cams[0]
+    tgt = O.render(scene.gt, cam, O.opts()).img.astype(np.float32)
+    _full_size_view(gsn, ctx, scene.init, cam, tgt, 120 * 68, "full-size")
+
+
+def test_full_size_secondary_view_parity(gsn, ctx, scene):
+    """A half-resolution secondary view (960x540, 60 x 34 tiles, the last tile row ragged) with its
+    target the 2x2 box downsampling of the full-resolution one, as the sweep forms it."""
+    cam = scene.cams[1]
+    tgt = O.downsample(O.render(scene.gt, cam, O.opts()).img.astype(np.float32)).astype(np.float32)
+    _full_size_view(gsn, ctx, scene.init, cam.downsampled(), tgt, 60 * 34, "full-size secondary")
