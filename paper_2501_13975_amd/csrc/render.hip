@@ -574,7 +574,8 @@ __global__ __launch_bounds__(1024) void tile_order_kernel(const uint2* __restric
 // gets the ordered list of the batch's entries whose alpha-support box meets its
 // band, so a wave only steps through entries that can composite in it.
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(GSN_BLOCK) void raster_fwd_kernel(
+// Six waves per SIMD (at most 80 VGPRs, no spills; six workgroups' LDS fit in a CU).
+__global__ __launch_bounds__(GSN_BLOCK, 6) void raster_fwd_kernel(
     const uint2* __restrict__ ranges, const uint32_t* __restrict__ order, const uint32_t* __restrict__ ids, const float4* __restrict__ rec, uint32_t n,
     DevCam cam, DevRenderOpts ro, float* __restrict__ img, double* __restrict__ img64, float* __restrict__ Tfin,
     uint32_t* __restrict__ ncontrib, uint64_t* __restrict__ masks, uint32_t* __restrict__ tile_len,
