@@ -38,7 +38,7 @@
 namespace {
 
 constexpr int PMAX = 896;   // composited (pixel, entry) pairs staged per round
-constexpr int BIG = 16;     // entries with more pairs are summed by LG lanes, others by SG
+constexpr int BIG = 64;     // entries with more pairs are summed by LG lanes, others by SG
 constexpr int SG = 8, LG = 32;
 
 // Contribution of one active (pixel, splat) pair to the 44 statistics (see the header comment).
