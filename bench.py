@@ -664,8 +664,8 @@ def main():
         copy_probe()
         return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py measures one GPU: this build runs the training step on a single MI355X "
-              "(how it would shard across GPUs is described in DESIGN.md); run with --gpus 1", file=sys.stderr)
+        print("bench.py measures one GPU: the training step runs on a single MI355X; run with --gpus 1",
+              file=sys.stderr)
         sys.exit(2)
     (elapsed, stages, counts, cfg, learned, quality, batched, variants, overshoot, order_exp,
      first_order, dist, curve) = gpu_run(args)
