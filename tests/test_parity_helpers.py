@@ -59,3 +59,32 @@ def test_zstats_frame_rotation_is_orthogonal_change_of_variables():
         g, Hm = Z[k, :9], Z[k, 9:90].reshape(9, 9)
         gf, Hf = Zf[k, :9], Zf[k, 9:90].reshape(9, 9)
         assert np.isclose(g @ x, gf @ xf) and np.isclose(x @ Hm @ x, xf @ Hf @ xf)
+
+
+def test_ssim_reach_is_the_two_window_radius_square():
+    from tests.parity import ssim_reach
+    mask = np.ones((40, 50), bool)
+    mask[20, 3] = False
+    reach = ssim_reach(mask)
+    ys, xs = np.nonzero(reach)
+    assert (ys.min(), ys.max(), xs.min(), xs.max()) == (10, 30, 0, 13)
+    assert reach.sum() == 21 * 14
+    assert not ssim_reach(np.ones((8, 8), bool)).any()
+
+
+def test_kernels_in_reach_takes_each_tile_prefix_to_its_deepest_pixel():
+    from types import SimpleNamespace
+
+    from tests.parity import kernels_in_reach
+    # two 16x16 tiles side by side; tile 0 lists kernels 5, 3, 7, tile 1 lists 1, 2
+    fr = SimpleNamespace(cam=SimpleNamespace(width=32, height=16), tile_start=np.array([0, 3, 5]),
+                         ids=np.array([5, 3, 7, 1, 2]), ncontrib=np.zeros((16, 32), np.int64))
+    fr.ncontrib[4, 2] = 1  # last composited entry of that pixel: index 0 of tile 0's list
+    fr.ncontrib[9, 20] = 2
+    reach = np.zeros((16, 32), bool)
+    reach[4, 2] = True
+    got = kernels_in_reach(fr, reach, 8)
+    # up to and including the entry after the last composited one (the stopping entry)
+    assert np.array_equal(np.nonzero(got)[0], [3, 5])
+    reach[9, 20] = True
+    assert np.array_equal(np.nonzero(kernels_in_reach(fr, reach, 8))[0], [1, 2, 3, 5])
