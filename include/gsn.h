@@ -16,8 +16,14 @@
  *    field f of kernel k at index f * N + k.  float is IEEE binary32.
  *  - Every call is asynchronous on the context's HIP stream and returns a
  *    gsn_status; results are valid after the stream is synchronised.
- *    gsn_render additionally synchronises the stream once to learn the number
- *    of (tile, kernel) pairs it must sort.
+ *    gsn_render synchronises the stream once to learn the number of (tile,
+ *    kernel) pairs it must sort, unless the frame has a reserved pair
+ *    capacity (gsn_frame_reserve): then the count stays on the device and the
+ *    call never waits, so that a whole sweep can be captured in a HIP graph.
+ *  - Numeric issues do not fail a call: kernels with a non-finite attribute are
+ *    culled by gsn_render, kernels whose blocks or steps are not finite are
+ *    skipped by the solve (zero step), and both are counted; gsn_sync_status
+ *    reports them (GSN_E_NUMERIC) together with pair-capacity overflows.
  *  - Invalid arguments are reported before any work is launched
  *    (GSN_E_INVALID, GSN_E_SHAPE); gsn_last_error() gives a message.
  *  - A context is used from one host thread at a time.
@@ -37,7 +43,9 @@ typedef enum {
     GSN_E_SHAPE = -2,    /* sizes inconsistent with each other or with the frame */
     GSN_E_CAPACITY = -3, /* a size exceeds what the call supports */
     GSN_E_HIP = -4,      /* a HIP runtime call failed (message has the HIP error) */
-    GSN_E_NOMEM = -5     /* device allocation of internal scratch failed */
+    GSN_E_NOMEM = -5,    /* device allocation of internal scratch failed */
+    GSN_E_NUMERIC = -6   /* NaN or Inf met since the last gsn_sync_status: the affected kernels were
+                            skipped, not updated (returned by gsn_sync_status only) */
 } gsn_status;
 
 typedef struct gsn_ctx gsn_ctx;
@@ -381,6 +389,21 @@ int64_t gsn_steps_floats(int32_t n, int32_t sh_degree);
  * 2x2 box mean of d_src [3][H][W].  Errors: GSN_E_SHAPE (W or H < 2). */
 gsn_status gsn_downsample2x(gsn_ctx* ctx, const float* d_src, int32_t width, int32_t height,
                             float* d_dst);
+
+/* Camera of a secondary target (Sec. 4.3): the target is the 2x2 box mean of
+ * the full-resolution image (gsn_downsample2x), so a half-resolution pixel
+ * centre u' lies at the full-resolution coordinate 2 u' + 0.5.  On the host:
+ * *out = *cam with fx/2, fy/2, cx' = (cx + 0.5)/2 - 0.5, cy' likewise (evaluated
+ * in double from the float inputs, rounded to float), width/2, height/2
+ * (rounded down).  out may equal cam.  Errors: GSN_E_INVALID (null pointers),
+ * GSN_E_SHAPE (width or height < 2). */
+gsn_status gsn_camera_half(const gsn_camera* cam, gsn_camera* out);
+
+/* Centre of the scene for the camera KNN (Sec. 4.1): the mean of the kernel
+ * positions, summed in double in a fixed order on the device (deterministic);
+ * d_out: device double [3].  Errors: GSN_E_INVALID (null pointers), as
+ * gsn_render for the kernels. */
+gsn_status gsn_scene_center(gsn_ctx* ctx, const gsn_gaussians* g, double* d_out);
 
 /* Camera KNN on the bounding sphere (Sec. 4.1), on the host: camera centres
  * h_centers [ncam][3] are projected radially onto a sphere about

@@ -289,6 +289,20 @@ def camera_knn(cams, g, K=3):
     return knn(centers, scene_center, K)
 
 
+def half_camera(cam):
+    """Camera of a secondary target (Sec. 4.3, reading C17): the image is the 2x2 box
+    mean of the full-resolution one, so a half-resolution pixel centre (integer
+    coordinate u') sits at the full-resolution coordinate 2 u' + 0.5; focal lengths are
+    halved and the principal point maps as c' = (c + 0.5) / 2 - 0.5.  Values are
+    rounded to float32 like every camera input."""
+    from synth.scenes import Camera
+    f32 = lambda x: float(np.float32(x))  # noqa: E731
+    return Camera(np.array(cam.R, np.float32), np.array(cam.t, np.float32),
+                  f32(0.5 * float(cam.fx)), f32(0.5 * float(cam.fy)),
+                  f32(0.5 * (float(cam.cx) + 0.5) - 0.5), f32(0.5 * (float(cam.cy) + 0.5) - 0.5),
+                  cam.width // 2, cam.height // 2, cam.znear)
+
+
 def downsample(img):
     img = np.ascontiguousarray(img, np.float64)
     _, H, W = img.shape
@@ -318,7 +332,7 @@ def sweep(g, cams, targets, t, knn_table=None, o=None, mask=31):
     views = [(cam, np.asarray(targets[t], np.float64))]
     if knn_table is not None:
         for j in knn_table[t]:
-            views.append((cams[j].downsampled(), downsample(targets[j])))
+            views.append((half_camera(cams[j]), downsample(targets[j])))
     per_view, losses, frames = [], [], []
     for c, tg in views:
         fr, parts, b = view_blocks(g64, c, tg, o)

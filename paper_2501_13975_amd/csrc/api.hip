@@ -784,6 +784,30 @@ gsn_status gsn_downsample2x(gsn_ctx* ctx, const float* d_src, int32_t width, int
     return GSN_OK;
 }
 
+gsn_status gsn_camera_half(const gsn_camera* cam, gsn_camera* out) {
+    if (!cam || !out) return GSN_E_INVALID;
+    if (cam->width < 2 || cam->height < 2) return GSN_E_SHAPE;
+    gsn_camera h = *cam;
+    h.fx = (float)(0.5 * (double)cam->fx);
+    h.fy = (float)(0.5 * (double)cam->fy);
+    h.cx = (float)(0.5 * ((double)cam->cx + 0.5) - 0.5);
+    h.cy = (float)(0.5 * ((double)cam->cy + 0.5) - 0.5);
+    h.width = cam->width / 2;
+    h.height = cam->height / 2;
+    *out = h;
+    return GSN_OK;
+}
+
+gsn_status gsn_scene_center(gsn_ctx* ctx, const gsn_gaussians* g, double* d_out) {
+    if (!ctx || !d_out) return fail(ctx, GSN_E_INVALID, "null argument");
+    gsn_status r = check_gaussians(ctx, g);
+    if (r != GSN_OK) return r;
+    HIP_TRY(ctx, hipSetDevice(ctx->device));
+    launch_scene_center(g->d_pos, g->n, d_out, ctx->stream);
+    HIP_TRY(ctx, hipGetLastError());
+    return GSN_OK;
+}
+
 gsn_status gsn_camera_knn(const double* c, int32_t ncam, const double* sc, int32_t k, int32_t* out) {
     if (!c || !sc || !out || k < 1 || k >= ncam) return GSN_E_INVALID;
     std::vector<double> u(3 * (size_t)ncam);

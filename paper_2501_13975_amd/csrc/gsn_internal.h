@@ -132,6 +132,7 @@ void launch_raster_fwd(const uint2* ranges, const uint32_t* order, const uint32_
                        const DevRenderOpts& ro, float* img, double* img64, float* Tfin, uint32_t* ncontrib,
                        uint64_t* masks, uint32_t* tile_len, unsigned long long* counts, hipStream_t s);
 void launch_downsample2x(const float* src, int W, int H, float* dst, hipStream_t s);
+void launch_scene_center(const float* pos, int n, double* out, hipStream_t s);
 
 // ---- launchers (loss.hip)
 void launch_loss_maps(const float* img, const float* tgt, int W, int H, float lambda, float* coef, float* dL,

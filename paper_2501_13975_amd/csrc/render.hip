@@ -753,9 +753,34 @@ __global__ void downsample2x_kernel(const float* __restrict__ src, int W, int H,
     dst[i] = 0.25f * (((a + b) + c) + d);
 }
 
+// Mean of the kernel positions in double, one workgroup: thread t sums kernels t, t + 1024, ...
+// in order, then a fixed-shape tree in LDS (the result does not depend on timing).
+__global__ __launch_bounds__(1024) void scene_center_kernel(const float* __restrict__ pos, int n,
+                                                             double* __restrict__ out) {
+    __shared__ double s[3][1024];
+    double a[3] = {0.0, 0.0, 0.0};
+    for (int k = threadIdx.x; k < n; k += 1024)
+#pragma unroll
+        for (int c = 0; c < 3; ++c) a[c] += (double)pos[(size_t)c * n + k];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) s[c][threadIdx.x] = a[c];
+    __syncthreads();
+    for (int w = 512; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w)
+#pragma unroll
+            for (int c = 0; c < 3; ++c) s[c][threadIdx.x] += s[c][threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x < 3) out[threadIdx.x] = n > 0 ? s[threadIdx.x][0] / (double)n : 0.0;
+}
+
 }  // namespace
 
 // ------------------------------------------------------------------ launchers
+void launch_scene_center(const float* pos, int n, double* out, hipStream_t s) {
+    scene_center_kernel<<<1, 1024, 0, s>>>(pos, n, out);
+}
+
 void launch_fill_u32(uint32_t* p, uint32_t v, size_t n, hipStream_t s) {
     if (n) fill_u32_kernel<<<grid_for(n), kThreads, 0, s>>>(p, v, n);
 }

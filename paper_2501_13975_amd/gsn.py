@@ -57,6 +57,8 @@ def lib():
             "gsn_blocks_zero": [P, P],
             "gsn_downsample2x": [P, P, ctypes.c_int32, ctypes.c_int32, P],
             "gsn_camera_knn": [P, ctypes.c_int32, P, ctypes.c_int32, P],
+            "gsn_camera_half": [P, P],
+            "gsn_scene_center": [P, P, P],
             "gsn_frame_info": [P, P, P, P, P],
             "gsn_frame_lists": [P, P, P, P, P, P, P],
             "gsn_frame_zstats": [P, P, P],
@@ -370,6 +372,11 @@ class Context:
         return ({s: (float(ms[i]), int(nl[i])) for i, s in enumerate(self.STAGES)},
                 {c: int(cnt[i]) for i, c in enumerate(self.COUNTERS)})
 
+    def scene_center(self, g: DeviceGaussians, out):
+        """out: device float64 tensor [3] (mean kernel position, Sec. 4.1)."""
+        cg = g.c()
+        self._check(lib().gsn_scene_center(self.h, ctypes.byref(cg), _ptr(out)))
+
     def blocks_zero(self, blocks: "Blocks"):
         cb = blocks.c()
         self._check(lib().gsn_blocks_zero(self.h, ctypes.byref(cb)))
@@ -461,6 +468,15 @@ class Steps:
     def view(self):
         K = (self.sh_degree + 1) ** 2
         return self.data[:(GSN_STEP_BASE + 3 * K) * self.n].view(-1, self.n), self.flags[:5 * self.n].view(5, self.n)
+
+
+def camera_half(cam: CCamera) -> CCamera:
+    """Camera of the half-resolution secondary target of `cam` (gsn_camera_half)."""
+    out = CCamera()
+    st = lib().gsn_camera_half(ctypes.byref(cam), ctypes.byref(out))
+    if st != 0:
+        raise GsnError(st, "gsn_camera_half: image smaller than 2x2")
+    return out
 
 
 def camera_knn(centers, scene_center, k=3):

@@ -29,8 +29,7 @@ class LocalNewtonTrainer:
         self.ctx = gsn.Context(self.dev)
         self.cams = list(cams)
         self.ccams = [gsn.camera(c) for c in self.cams]
-        self.half = [c.downsampled() for c in self.cams]
-        self.chalf = [gsn.camera(c) for c in self.half]
+        self.chalf = [gsn.camera_half(c) for c in self.ccams]
         self.targets = targets
         self.n_secondary = int(n_secondary) if len(self.cams) > 1 else 0
         self.ro = render_opts or gsn.render_opts()
@@ -43,8 +42,9 @@ class LocalNewtonTrainer:
         self.loss = torch.zeros(V, 2, dtype=torch.float64, device=self.dev)
         if self.n_secondary:
             centers = np.stack([c.center for c in self.cams])
-            scene_center = gauss.pos.double().mean(dim=1).cpu().numpy()
-            self.knn = gsn.camera_knn(centers, scene_center, self.n_secondary)
+            sc = torch.zeros(3, dtype=torch.float64, device=self.dev)
+            self.ctx.scene_center(gauss, sc)
+            self.knn = gsn.camera_knn(centers, sc.cpu().numpy(), self.n_secondary)
             self.half_targets = []
             for c, tg in zip(self.cams, targets):
                 d = torch.empty(3, c.height // 2, c.width // 2, dtype=torch.float32, device=self.dev)

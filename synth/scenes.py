@@ -72,19 +72,6 @@ class Camera:
         """Camera centre in world coordinates, o = -R^T t (float64)."""
         return -(self.R.astype(np.float64).T @ self.t.astype(np.float64))
 
-    def downsampled(self) -> "Camera":
-        """Camera of the 2x2 box-downsampled image (half width and height).
-
-        Pixel centres stay at integer coordinates: a full-resolution
-        coordinate u maps to (u + 0.5) / 2 - 0.5.
-        """
-        w2, h2 = self.width // 2, self.height // 2
-        return Camera(self.R.copy(), self.t.copy(),
-                      float(np.float32(self.fx * 0.5)), float(np.float32(self.fy * 0.5)),
-                      float(np.float32((self.cx + 0.5) * 0.5 - 0.5)),
-                      float(np.float32((self.cy + 0.5) * 0.5 - 0.5)),
-                      w2, h2, self.znear)
-
 
 def pinhole_intrinsics(width: int, height: int, fov_x_deg: float):
     fx = (width / 2.0) / math.tan(math.radians(fov_x_deg) / 2.0)

@@ -88,7 +88,7 @@ def gpu_view(ctx, gsn, dg, cam, target_t, lam, blocks, slot, keep=True, gn=False
     """Render + accumulate one view on the GPU; returns numpy copies of every stage."""
     import torch
     fr = ctx.frame()
-    ccam = gsn.camera(cam)
+    ccam = cam if isinstance(cam, gsn.CCamera) else gsn.camera(cam)
     ro = gsn.render_opts()
     rgb = torch.zeros(3, cam.height, cam.width, dtype=torch.float32, device=ctx.device)
     T = torch.zeros(cam.height, cam.width, dtype=torch.float32, device=ctx.device)

@@ -55,3 +55,26 @@ def test_camera_knn_matches_oracle():
     assert np.array_equal(gsn.camera_knn(cen, sc, 3), O.knn(cen, sc, 3))
     with pytest.raises(gsn.GsnError):
         gsn.camera_knn(cen, sc, 50)
+
+
+def test_half_resolution_camera_matches_oracle():
+    """The library's secondary-target camera (Sec. 4.3) equals the oracle's, bit for bit."""
+    if not os.path.exists(LIB):
+        pytest.skip("libgsn.so not built")
+    import numpy as np
+    from oracle import oracle as O
+    from synth.scenes import make_config
+    from paper_2501_13975_amd import gsn
+    for cfg in (make_config("c1", n=10, n_views=5), make_config("c2", n=10, n_views=5), make_config("c0", n=10)):
+        for c in cfg.cams:
+            h = gsn.camera_half(gsn.camera(c))
+            o = O.half_camera(c)
+            got = [h.fx, h.fy, h.cx, h.cy, h.width, h.height, h.znear]
+            want = [np.float32(o.fx), np.float32(o.fy), np.float32(o.cx), np.float32(o.cy), o.width, o.height,
+                    np.float32(o.znear)]
+            assert got == [float(x) if isinstance(x, np.float32) else x for x in want]
+            assert list(h.R) == [float(x) for x in np.asarray(o.R, np.float32).ravel()]
+    c = gsn.camera(make_config("c0", n=10).cams[0])
+    c.width = 1
+    with pytest.raises(gsn.GsnError):
+        gsn.camera_half(c)

@@ -38,12 +38,14 @@ def ctx(gsn):
     c.close()
 
 
-def _full_size_view(gsn, ctx, g, cam, tgt, tiles, label):
+def _full_size_view(gsn, ctx, g, cam, tgt, tiles, label, gpu_cam=None):
+    """gpu_cam: the library's camera for the view (default: the same camera as the oracle's)."""
     lam = 0.2
     dg = gsn.DeviceGaussians.from_host(g)
     blocks = gsn.Blocks(g.n, 1, ctx.device)
     ctx.blocks_zero(blocks)
-    gv = gpu_view(ctx, gsn, dg, cam, torch.tensor(tgt, device=ctx.device), lam, blocks, 0, keep=False)
+    gv = gpu_view(ctx, gsn, dg, cam if gpu_cam is None else gpu_cam, torch.tensor(tgt, device=ctx.device), lam,
+                  blocks, 0, keep=False)
     fr = O.render(g, cam, O.opts(lambda_ssim=lam), g32=g)
     ov = {"fr": fr}
     # lists: bit-exact on every tile of the frame
@@ -113,4 +115,5 @@ def test_full_size_secondary_view_parity(gsn, ctx, scene):
     target the 2x2 box downsampling of the full-resolution one, as the sweep forms it."""
     cam = scene.cams[1]
     tgt = O.downsample(O.render(scene.gt, cam, O.opts()).img.astype(np.float32)).astype(np.float32)
-    _full_size_view(gsn, ctx, scene.init, cam.downsampled(), tgt, 60 * 34, "full-size secondary")
+    _full_size_view(gsn, ctx, scene.init, O.half_camera(cam), tgt, 60 * 34, "full-size secondary",
+                    gpu_cam=gsn.camera_half(gsn.camera(cam)))

@@ -884,3 +884,153 @@ def test_paper_constants_fixture():
     (_, ls), _, _ = O.loss(img, tgt, 1.0, derivs=False)
     # away from the zero-padded border mu = 0.5, mu_t = 0.25 and variances vanish
     assert ls > 0
+
+
+# ----------------------------------------------------------------------------- reduced solves as Newton on the loss
+def _aniso_splat(q, s=(0.3, 0.12, 0.06), sig=0.8, rgb=(0.7, 0.4, 0.2), pos=(0.05, -0.03, 0.1)):
+    sh = np.zeros((3, 1, 1))
+    sh[:, 0, 0] = np.array(rgb) / Y00
+    return O.G64(np.array(pos, float).reshape(3, 1), np.asarray(q, float).reshape(4, 1).copy(),
+                 np.array(s, float).reshape(3, 1), np.array([sig]), sh, 1)
+
+
+def _oblique_cam(W=64, H=56):
+    return look_at_camera((0.9, -0.6, -3.6), (0.0, 0.0, 0.0), (0.0, -1.0, 0.0), W, H, 50.0)
+
+
+def _unit_quat(seed):
+    q = np.random.default_rng(seed).standard_normal(4)
+    return q / np.linalg.norm(q)
+
+
+def test_rotation_step_is_newton_on_the_loss_along_theta():
+    """Rotation solve (Sec. 4.2): with the exact Hessian (lambda = 0) and no damping, the step
+    theta is one Newton step on L(theta), the loss after turning the kernel by theta about its
+    primary view direction r (dq = [cos(theta/2), sin(theta/2) r] on the left).  L'(0) and
+    L''(0) come from central differences of renders, so a wrong sign of g_theta, a wrong
+    H_theta, or a wrong axis all fail.  Repeated steps return the kernel to the orientation
+    the target was rendered with."""
+    cam = _oblique_cam()
+    W, H = cam.width, cam.height
+    q0 = _unit_quat(5)
+    gt = _aniso_splat(q0)
+    o = smooth_opts(0.0, damp_rel=0.0, damp_abs=0.0, trust_rot=1e30, npix_primary=W * H)
+    tgt = O.render(gt, cam, o).img
+    p = gt.pos[:, 0]
+    r = (p - cam.center) / np.linalg.norm(p - cam.center)
+    g = gt.copy()
+    g.rot[:, 0] = qmul(qexp(0.2 * r), q0)
+
+    def L(theta):
+        g2 = g.copy()
+        g2.rot[:, 0] = qmul(qexp(theta * r), g.rot[:, 0])
+        return loss_value(g2, cam, tgt, o)
+
+    h = 1e-4
+    l0, lp, lm = L(0.0), L(h), L(-h)
+    d1 = (lp - lm) / (2 * h)
+    d2 = (lp - 2 * l0 + lm) / (h * h)
+    assert d2 > 0 and abs(d1) > 0
+    res = O.sweep(g, [cam], [tgt], 0, None, o, mask=2)
+    th = res["steps"][0, 3]
+    assert th == pytest.approx(-d1 / d2, rel=1e-6)
+    assert np.allclose(res["steps"][0, 4:7], r, rtol=1e-12)
+    # with damping, theta solves (r^T H_omega r + mu) theta = -r . g_omega (mu = damp_rel |H| for n = 1)
+    od = smooth_opts(0.0, trust_rot=1e30, npix_primary=W * H)
+    resd = O.sweep(g, [cam], [tgt], 0, None, od, mask=2)
+    S = resd["summed"][0]
+    Hth = r @ S[15:24].reshape(3, 3) @ r
+    mu = (1e-3 * abs(Hth) + 1e-12 / (3 * W * H)) * 10.0 ** resd["dec"][0, 1]
+    assert resd["steps"][0, 3] == pytest.approx(-(r @ S[12:15]) / (Hth + mu), rel=1e-12)
+    # repeated steps converge to the target orientation
+    for _ in range(6):
+        g = O.sweep(g, [cam], [tgt], 0, None, o, mask=2)["new"]
+    qf = g.rot[:, 0] * np.sign(g.rot[:, 0] @ q0)
+    assert np.allclose(qf, q0, atol=1e-9)
+
+
+def test_scaling_step_is_newton_in_the_row_space_of_dlambda_ds():
+    """Scaling solve (Sec. 4.2, reading C11): Delta s = T^T a with T = d lambda / d s, lambda the
+    eigenvalues of the projected covariance.  T is built here by central differences of the
+    eigenvalues, and (without damping, exact Hessian at lambda = 0) the step must equal the
+    Newton step of phi(a) = L(s + T^T a), whose gradient and Hessian come from central
+    differences of renders.  A wrong row of T, a transposed reduction or a sign slip fails."""
+    cam = _oblique_cam()
+    W, H = cam.width, cam.height
+    gt = _aniso_splat(_unit_quat(9), s=(0.3, 0.12, 0.06))
+    o = smooth_opts(0.0, damp_rel=0.0, damp_abs=0.0, trust_scale=1e30, npix_primary=W * H)
+    tgt = O.render(gt, cam, o).img
+    g = gt.copy()
+    g.scale[:, 0] = gt.scale[:, 0] * np.exp([0.15, -0.1, 0.08])
+    s0 = g.scale[:, 0].copy()
+
+    def lam(s):
+        g2 = g.copy()
+        g2.scale[:, 0] = s
+        out, _ = O.project64(g2, cam, kappa=0.0)
+        c = out[0, 2:5]
+        return np.linalg.eigvalsh([[c[0], c[1]], [c[1], c[2]]])
+
+    hs = 1e-6
+    T = np.stack([(lam(s0 + hs * e) - lam(s0 - hs * e)) / (2 * hs) for e in np.eye(3)], axis=1)
+    T /= np.linalg.norm(T, axis=1, keepdims=True)  # only the row space matters without damping
+
+    def phi(a):
+        g2 = g.copy()
+        g2.scale[:, 0] = s0 + T.T @ a
+        return loss_value(g2, cam, tgt, o)
+
+    h = 1e-5
+    E = np.eye(2) * h
+    gphi = np.array([(phi(E[i]) - phi(-E[i])) / (2 * h) for i in range(2)])
+    Hphi = np.zeros((2, 2))
+    for i in range(2):
+        for j in range(2):
+            Hphi[i, j] = (phi(E[i] + E[j]) - phi(E[i] - E[j]) - phi(-E[i] + E[j]) + phi(-E[i] - E[j])) / (4 * h * h)
+    assert np.all(np.linalg.eigvalsh(Hphi) > 0)
+    want = T.T @ (-np.linalg.solve(Hphi, gphi))
+    res = O.sweep(g, [cam], [tgt], 0, None, o, mask=4)
+    ds = res["steps"][0, 7:10]
+    assert res["dec"][0, 2] == 0
+    assert np.allclose(ds, want, rtol=0, atol=2e-5 * np.linalg.norm(want))
+    # with damping, a solves (T H_s T^T + mu I) a = -T g_s for the unit rows of T
+    od = smooth_opts(0.0, trust_scale=1e30, npix_primary=W * H)
+    resd = O.sweep(g, [cam], [tgt], 0, None, od, mask=4)
+    S = resd["summed"][0]
+    Hr = T @ S[27:36].reshape(3, 3) @ T.T
+    mu = (1e-3 * np.linalg.norm(Hr) / np.sqrt(2) + 1e-12 / (3 * W * H)) * 10.0 ** resd["dec"][0, 2]
+    a = np.linalg.solve(Hr + mu * np.eye(2), -T @ S[24:27])
+    assert np.allclose(resd["steps"][0, 7:10], T.T @ a, rtol=0, atol=1e-5 * np.linalg.norm(T.T @ a))
+
+
+def test_half_resolution_camera_samples_the_box_filtered_image():
+    """Secondary targets (Sec. 4.3, reading C17) are the 2x2 box mean of the full-resolution
+    image, so the half-resolution camera must render (smooth mode, low-frequency scene) what
+    box-filtering the full-resolution render gives, up to the filter's curvature error
+    (about 0.125 (f_xx + f_yy), 7e-4 of the peak for 19-pixel splats).  The plausible
+    mistakes -- principal point c/2, focal length not halved -- miss by far more."""
+    cam = look_at_camera((0.3, -0.2, -4.0), (0.0, 0.0, 0.0), (0.0, -1.0, 0.0), 128, 96, 60.0)
+    rng = np.random.default_rng(3)
+    n = 6
+    pos = np.stack([rng.uniform(-0.8, 0.8, n), rng.uniform(-0.6, 0.6, n), rng.uniform(-0.3, 0.3, n)])
+    q = np.zeros((4, n))
+    q[0] = 1.0
+    sh = rng.uniform(0.2, 0.9, (3, 1, n)) / Y00
+    g = O.G64(pos, q, np.full((3, n), 0.7), np.full(n, 0.6), sh, 1)
+    o = smooth_opts(0.0)
+    box = O.downsample(O.render(g, cam, o).img)
+    peak = np.max(np.abs(box))
+
+    def err(c):
+        return np.max(np.abs(O.render(g, c, o).img - box)) / peak
+
+    hc = O.half_camera(cam)
+    assert (hc.width, hc.height) == (64, 48)
+    e = err(hc)
+    assert e < 2e-3
+    wrong_c = O.half_camera(cam)
+    wrong_c.cx, wrong_c.cy = 0.5 * cam.cx, 0.5 * cam.cy
+    wrong_f = O.half_camera(cam)
+    wrong_f.fx, wrong_f.fy = cam.fx, cam.fy
+    assert err(wrong_c) > 5 * e and err(wrong_c) > 5e-3
+    assert err(wrong_f) > 0.1
