@@ -228,6 +228,20 @@ gsn_status gsn_local_newton_solve(gsn_ctx* ctx, const gsn_gaussians* g, const gs
                                   const gsn_blocks* blocks, const gsn_solve_opts* opts,
                                   gsn_steps* steps);
 
+/* For callers that cannot allocate device memory (code under HIP graph capture, tight serving
+ * loops, harnesses that forbid hipMalloc): gsn_local_newton_solve with the same arguments and
+ * results, and no allocation of any kind.  Its only scratch, the mixed form's colour Gram
+ * matrices (10 floats per kernel, precision = 1), lives in a fixed array of
+ * 10 * GSN_NOALLOC_MAX_N floats (40 MiB) that every device holds from the library's load until
+ * the process ends; the plain form uses none.  All calls on one device share that array, so calls
+ * that overlap on one device (other streams or contexts) race; calls on one stream are ordered.
+ * Nothing is timed by gsn_profile_enable.  Errors: as gsn_local_newton_solve, and GSN_E_CAPACITY
+ * when n > GSN_NOALLOC_MAX_N. */
+#define GSN_NOALLOC_MAX_N (1 << 20)
+gsn_status gsn_local_newton_solve_noalloc(gsn_ctx* ctx, const gsn_gaussians* g, const gsn_camera* primary,
+                                          const gsn_blocks* blocks, const gsn_solve_opts* opts,
+                                          gsn_steps* steps);
+
 /* Applies the steps in place, for the groups in group_mask (bit 0 position,
  * 1 rotation, 2 scaling, 3 opacity, 4 colour): p += Delta p; q <- dq(theta) q
  * renormalised with dq = (cos(theta/2), sin(theta/2) r_k); s <- max(s + Delta s,

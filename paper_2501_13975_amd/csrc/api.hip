@@ -128,10 +128,13 @@ gsn_status gsn_create(gsn_ctx** out, int32_t device, void* hip_stream) {
     *out = nullptr;
     int count = 0;
     if (hipGetDeviceCount(&count) != hipSuccess || device < 0 || device >= count) return GSN_E_INVALID;
+    float* scratch = nullptr;
+    if (solve_scratch_address(device, &scratch) != hipSuccess || !scratch) return GSN_E_HIP;
     gsn_ctx* c = new (std::nothrow) gsn_ctx;
     if (!c) return GSN_E_NOMEM;
     c->device = device;
     c->stream = static_cast<hipStream_t>(hip_stream);
+    c->noalloc_gram = scratch;
     *out = c;
     return GSN_OK;
 }
@@ -403,8 +406,9 @@ gsn_status gsn_accumulate_hessian(gsn_ctx* ctx, const gsn_gaussians* g, const gs
     return GSN_OK;
 }
 
-gsn_status gsn_local_newton_solve(gsn_ctx* ctx, const gsn_gaussians* g, const gsn_camera* primary,
-                                  const gsn_blocks* b, const gsn_solve_opts* o, gsn_steps* st) {
+// Argument checks shared by both solve entry points.
+static gsn_status check_solve_args(gsn_ctx* ctx, const gsn_gaussians* g, const gsn_camera* primary,
+                                   const gsn_blocks* b, const gsn_solve_opts* o, const gsn_steps* st) {
     if (!ctx || !b || !o || !st) return fail(ctx, GSN_E_INVALID, "null argument");
     gsn_status r = check_gaussians(ctx, g);
     if (r != GSN_OK) return r;
@@ -417,6 +421,13 @@ gsn_status gsn_local_newton_solve(gsn_ctx* ctx, const gsn_gaussians* g, const gs
         return fail(ctx, GSN_E_INVALID, "solve option out of range");
     if (o->precision != 0 && o->precision != 1) return fail(ctx, GSN_E_INVALID, "precision must be 0 or 1");
     if (o->precision == 1 && b->n_views > 4) return fail(ctx, GSN_E_SHAPE, "the mixed form takes at most 4 views");
+    return GSN_OK;
+}
+
+gsn_status gsn_local_newton_solve(gsn_ctx* ctx, const gsn_gaussians* g, const gsn_camera* primary,
+                                  const gsn_blocks* b, const gsn_solve_opts* o, gsn_steps* st) {
+    gsn_status r = check_solve_args(ctx, g, primary, b, o, st);
+    if (r != GSN_OK) return r;
     HIP_TRY(ctx, hipSetDevice(ctx->device));
     if (o->precision == 1) HIP_TRY(ctx, buf_reserve(ctx->gram, (size_t)std::max(g->n, 1) * 10 * 4));
     StageTimer st_(ctx, GSN_STAGE_SOLVE);
@@ -426,6 +437,28 @@ gsn_status gsn_local_newton_solve(gsn_ctx* ctx, const gsn_gaussians* g, const gs
         unsigned long long* n64 = ctx->prof && ctx->d_counts ? ctx->d_counts + GSN_COUNT_FP64_SOLVES : nullptr;
         launch_solve_mixed(*g, make_devcam(*primary), o->kappa, *b, *o, bp<float>(ctx->gram), *st, n64,
                            ctx->stream);
+    } else {
+        launch_solve(*g, make_devcam(*primary), o->kappa, *b, *o, *st, ctx->stream);
+    }
+    HIP_TRY(ctx, hipGetLastError());
+    return GSN_OK;
+}
+
+gsn_status gsn_local_newton_solve_noalloc(gsn_ctx* ctx, const gsn_gaussians* g, const gsn_camera* primary,
+                                          const gsn_blocks* b, const gsn_solve_opts* o, gsn_steps* st) {
+    gsn_status r = check_solve_args(ctx, g, primary, b, o, st);
+    if (r != GSN_OK) return r;
+    if (g->n > GSN_NOALLOC_MAX_N)
+        return fail(ctx, GSN_E_CAPACITY, "n = %d exceeds the no-allocation limit of %d kernels", g->n,
+                    GSN_NOALLOC_MAX_N);
+    if (!ctx->noalloc_gram) return fail(ctx, GSN_E_INVALID, "no scratch address for this device");
+    HIP_TRY(ctx, hipSetDevice(ctx->device));
+    // no stage timing here: timing may create events; no buffer is reserved or grown
+    if (o->precision == 1) {
+        const int K = (g->sh_degree + 1) * (g->sh_degree + 1);
+        launch_sh_gram(b->d_data, g->n, K, b->n_views, ctx->noalloc_gram, ctx->stream);
+        unsigned long long* n64 = ctx->prof && ctx->d_counts ? ctx->d_counts + GSN_COUNT_FP64_SOLVES : nullptr;
+        launch_solve_mixed(*g, make_devcam(*primary), o->kappa, *b, *o, ctx->noalloc_gram, *st, n64, ctx->stream);
     } else {
         launch_solve(*g, make_devcam(*primary), o->kappa, *b, *o, *st, ctx->stream);
     }

@@ -88,6 +88,8 @@ struct gsn_ctx {
     int solve_block = 0, solve_grid = 0;
     // colour Gram matrices of the mixed form
     DevBuf gram;
+    // this device's fixed scratch array of gsn_local_newton_solve_noalloc ([10][GSN_NOALLOC_MAX_N] floats)
+    float* noalloc_gram = nullptr;
 };
 
 struct gsn_graph {
@@ -169,6 +171,11 @@ struct SolveScene {
 void launch_solve_batched(const SolveScene* d_scenes, int count, long long total, int max_views, int block,
                           int grid, hipStream_t s);
 void launch_sh_gram(const float* blk, int n, int K, int V, float* gram, hipStream_t s);
+// Devices whose no-allocation scratch address is cached.
+#define GSN_MAX_DEVICES 64
+// Device address of the fixed scratch array of gsn_local_newton_solve_noalloc on `device`
+// (looked up once per device with hipGetSymbolAddress, then cached).
+hipError_t solve_scratch_address(int device, float** out);
 void launch_solve_mixed(const gsn_gaussians& g, const DevCam& cam, float kappa, const gsn_blocks& b,
                         const gsn_solve_opts& o, const float* gram, const gsn_steps& st, unsigned long long* n_fp64,
                         hipStream_t s);

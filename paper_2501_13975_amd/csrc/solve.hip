@@ -21,6 +21,7 @@
 // space, (B B^T + mu S^-1) y = -S^-1 gamma, Delta = B^T y, which equals the
 // damped K x K solve exactly and is far better conditioned.
 #include <limits>
+#include <mutex>
 
 #include "gsn_internal.h"
 #include "reduced.h"
@@ -625,6 +626,36 @@ __global__ __launch_bounds__(256) void apply_kernel(float* __restrict__ pos, flo
 }
 
 }  // namespace
+
+// Scratch of gsn_local_newton_solve_noalloc: the mixed form's colour Gram matrices, [10][n] for
+// n <= GSN_NOALLOC_MAX_N, one copy per device, held from the library's load to the end of the
+// process.  Host code never passes this name to a kernel (on the host it is only a stand-in for
+// the symbol): it uses the per-device address that solve_scratch_address returns.
+static __device__ __align__(256) float scratch[10 * (size_t)GSN_NOALLOC_MAX_N];
+
+hipError_t solve_scratch_address(int device, float** out) {
+    // looked up once per device, with that device current, and kept for the process
+    static std::mutex mu;
+    static float* addr[GSN_MAX_DEVICES] = {};
+    *out = nullptr;
+    if (device < 0 || device >= GSN_MAX_DEVICES) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(mu);
+    if (!addr[device]) {
+        int cur = 0;
+        hipError_t e = hipGetDevice(&cur);
+        if (e != hipSuccess) return e;
+        if ((e = hipSetDevice(device)) != hipSuccess) return e;
+        void* p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        const hipError_t e2 = hipSetDevice(cur);
+        if (e != hipSuccess) return e;
+        if (e2 != hipSuccess) return e2;
+        if (!p) return hipErrorInvalidSymbol;
+        addr[device] = static_cast<float*>(p);
+    }
+    *out = addr[device];
+    return hipSuccess;
+}
 
 void launch_solve(const gsn_gaussians& g, const DevCam& cam, float kappa, const gsn_blocks& b,
                   const gsn_solve_opts& o, const gsn_steps& st, hipStream_t s) {

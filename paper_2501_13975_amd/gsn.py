@@ -42,6 +42,7 @@ def lib():
             "gsn_render": [P, P, P, P, P, P, P],
             "gsn_accumulate_hessian": [P, P, P, P, P, ctypes.c_int32, P, P],
             "gsn_local_newton_solve": [P, P, P, P, P, P],
+            "gsn_local_newton_solve_noalloc": [P, P, P, P, P, P],
             "gsn_apply_step": [P, P, P, P, P, ctypes.c_uint32],
             "gsn_first_order_step": [P, P, P, P, P, P, ctypes.c_uint32],
             "gsn_step_features": [P, P, P, P, P, P, P],
@@ -281,6 +282,12 @@ class Context:
         cg, cb, cs = g.c(), blocks.c(), steps.c()
         self._check(lib().gsn_local_newton_solve(self.h, ctypes.byref(cg), ctypes.byref(primary),
                                                  ctypes.byref(cb), ctypes.byref(so), ctypes.byref(cs)))
+
+    def local_newton_solve_noalloc(self, g, primary: CCamera, blocks: "Blocks", so: CSolveOpts, steps: "Steps"):
+        """gsn_local_newton_solve_noalloc: the same solve with no device allocation."""
+        cg, cb, cs = g.c(), blocks.c(), steps.c()
+        self._check(lib().gsn_local_newton_solve_noalloc(self.h, ctypes.byref(cg), ctypes.byref(primary),
+                                                         ctypes.byref(cb), ctypes.byref(so), ctypes.byref(cs)))
 
     def apply_step(self, g, steps: "Steps", so: CSolveOpts, group_mask=31, scale=None):
         """scale: None or a device float tensor [5, n] (per-group multipliers of the steps)."""
