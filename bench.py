@@ -25,12 +25,13 @@ sys.path.insert(0, ROOT)
 
 METRIC = "Newton sweeps/s, 1M Gaussians @1080p: plain FP32 vs mixed+learned at equal PSNR"
 
-# Peak figures of one MI355X.  HBM3E: 8 TB/s (published).  Vector ALU: 256 CUs x 4 SIMDs x
-# 16 lanes x 2 FLOP per FMA x 2.4 GHz = 78.6 TFLOP/s for unpacked FP32 and for FP64; the
-# published 157.3 TFLOP/s FP32 figure needs packed FP32 instructions, which this library is
-# built without.
+# Peak figures of one MI355X.  HBM3E: 8 TB/s (published).  Vector ALU: the published FP32 vector
+# peak 157.3 TFLOP/s (packed FP32: 256 CUs x 4 SIMDs x 16 lanes x 2 x 2 FLOP per FMA x 2.4 GHz).
+# The unpacked rate, 78.6 TFLOP/s (also the FP64 vector peak), is reported beside it: this library
+# is built without packed FP32 instructions, so that is the rate its FP32 code can reach.
 PEAK_HBM_GBS = 8000.0
-PEAK_ALU_TFLOPS = 78.6
+PEAK_ALU_TFLOPS = 157.3
+PEAK_ALU_UNPACKED_TFLOPS = 78.6
 
 # Algorithmic FLOPs per unit of work, counted from the kernel sources:
 #   one (pixel, list entry) evaluation of a splat: offset with the mean's low word (4),
@@ -46,13 +47,19 @@ PEAK_ALU_TFLOPS = 78.6
 FLOP_EVAL = 18
 FLOP_FWD_BLEND = 9
 FLOP_BWD_PAIR = 222
-# Bytes one backward launch must move per unit: a staged list entry reads its 48-byte record,
-# 8-byte rectangle and 4-byte pair offset (60); a written (tile, kernel) partial is 44 floats
-# plus its flag (177); per pixel the loss gradient and Hessian maps (6 floats), the final colour
-# (3 doubles) and the stopping index (52).
-BYTES_BWD_ENTRY = 60
-BYTES_BWD_PARTIAL = 177
-BYTES_BWD_PIXEL = 52
+# Algorithmic bytes per unit (the method's own traffic, not this implementation's):
+#   a consumed list entry (staged before its tile finished), forward or backward: its index (4) and
+#     the projected record it reads (36) = 40;
+#   per pixel: the forward pass writes colour, transmittance and stopping index (20), the loss maps
+#     are written and read (48: dL and h, 3 channels each), the backward pass reads maps, colour and
+#     stopping index (44);
+#   per kernel and view: the 43 projected-space statistics written and read once (172);
+#   per emitted (tile, kernel) pair: key/value write, per-tile bucket read, list write (28).
+BYTES_ENTRY = 40
+BYTES_FWD_PIXEL = 20
+BYTES_BWD_PIXEL = 44
+BYTES_ZSTATS = 172
+BYTES_PAIR = 28
 
 
 def log(msg):
@@ -79,10 +86,12 @@ def _targets(cfg, dev):
     return targets
 
 
-def _trainer(cfg, targets, dev, learned_every=0, step_frac=1.0, n_secondary=None, gauss_newton=False):
+def _trainer(cfg, targets, dev, learned_every=0, step_frac=1.0, n_secondary=None, gauss_newton=False,
+             reserve=False):
     """The plain form (FP64 small solves), or with learned_every the mixed + learned form (BF16
     matrix-core colour Grams, FP32 solves with FP64 for flagged systems, learned step scale).
-    n_secondary overrides the workload's |N_t|; gauss_newton selects the local Gauss-Newton blocks."""
+    n_secondary overrides the workload's |N_t|; gauss_newton selects the local Gauss-Newton blocks;
+    reserve sizes every frame once, so that sweeps never wait for the device."""
     from paper_2501_13975_amd import gsn
     from paper_2501_13975_amd.train import LocalNewtonTrainer
     from synth.mlp_init import init_params
@@ -92,6 +101,8 @@ def _trainer(cfg, targets, dev, learned_every=0, step_frac=1.0, n_secondary=None
     tr = LocalNewtonTrainer(g, cfg.cams, targets, n_secondary=K, solve_kw=kw, gauss_newton=gauss_newton)
     if learned_every:
         tr.enable_learned(init_params(0), every=learned_every, lr=1e-2)
+    if reserve:
+        tr.reserve_frames()
     return tr
 
 
@@ -102,21 +113,62 @@ def _sweep(tr, t, i, learned, mask=31):
         tr.sweep(t, mask)
 
 
-def _timed(tr, order, warmup, steps, learned, dev):
+def _timed(tr, order, warmup, steps, learned, dev, profile=True):
+    """Times `steps` sweeps after `warmup` untimed ones (the host clock around a synchronised
+    loop).  With profile, the library also times every stage with HIP events and counts its work
+    (a few microseconds per stage): the stage times and counters are returned."""
     import torch
     for i in range(warmup):
         _sweep(tr, int(order[i]), i, learned)
     torch.cuda.synchronize(dev)
-    tr.ctx.profile_enable(True)
+    if profile:
+        tr.ctx.profile_enable(True)
     torch.cuda.synchronize(dev)
     start = time.perf_counter()
     for i in range(steps):
         _sweep(tr, int(order[warmup + i]), warmup + i, learned)
     torch.cuda.synchronize(dev)
     elapsed = time.perf_counter() - start
-    stages, counts = tr.ctx.profile_read()
-    tr.ctx.profile_enable(False)
+    stages, counts = None, None
+    if profile:
+        stages, counts = tr.ctx.profile_read()
+        tr.ctx.profile_enable(False)
     return elapsed, stages, counts
+
+
+def _rate_and_profile(tr, order, warmup, steps, learned, dev):
+    """Seconds for `steps` unprofiled sweeps after `warmup`, then the stage times and counters of
+    `steps` more sweeps run with the library's profiler on."""
+    el, _, _ = _timed(tr, order, warmup, steps, learned, dev, profile=False)
+    _, st, cn = _timed(tr, order[warmup + steps:], 0, steps, learned, dev)
+    return el, st, cn
+
+
+def _graph_rate(cfg, targets, dev, order, warmup, steps, step_frac):
+    """The plain form with reserved frames, each sweep a replay of its image's captured HIP graph
+    (captured before timing), against the same sweeps issued one call at a time (also without host
+    waits).  Returns both rates and the device status gathered over the runs."""
+    import torch
+    out = {}
+    for mode in ("eager", "graph"):
+        tr = _trainer(cfg, targets, dev, 0, step_frac, reserve=True)
+        if mode == "graph":
+            for t in sorted(set(int(x) for x in order[:warmup + steps])):
+                tr.sweep_graph(t)  # captures, then replays once (untimed)
+        for i in range(warmup):
+            (tr.sweep_graph if mode == "graph" else tr.sweep)(int(order[i]))
+        torch.cuda.synchronize(dev)
+        t0 = time.perf_counter()
+        for i in range(steps):
+            (tr.sweep_graph if mode == "graph" else tr.sweep)(int(order[warmup + i]))
+        torch.cuda.synchronize(dev)
+        el = time.perf_counter() - t0
+        stats = tr.check_status()
+        tr.close()
+        out[mode] = {"value": round(steps / el, 4), "unit": "sweeps/s", "ms_per_step": round(el * 1e3 / steps, 3),
+                     "device_status": {k: v for k, v in stats.items() if k != "message"}}
+        log(f"[bench] reserved frames, {mode}: {steps / el:.2f} sweeps/s")
+    return out
 
 
 def _sweep_times(tr, order, start, n, learned, dev):
@@ -209,7 +261,7 @@ def _variant_rates(cfg, targets, dev, order, warmup, steps, step_frac):
     out = {}
     for name, K, gn in (("secondaries_0", 0, False), ("secondaries_8", 8, False), ("gauss_newton", None, True)):
         tr = _trainer(cfg, targets, dev, 0, step_frac, n_secondary=K, gauss_newton=gn)
-        el, st, cn = _timed(tr, order, warmup, steps, False, dev)
+        el, st, cn = _rate_and_profile(tr, order, warmup, steps, False, dev)
         tr.close()
         out[name] = {"value": round(steps / el, 4), "unit": "sweeps/s", "ms_per_step": round(el * 1e3 / steps, 3),
                      "stage_ms_per_step": {k: round(v[0] / steps, 3) for k, v in st.items()},
@@ -453,16 +505,22 @@ def gpu_run(args):
     targets = _targets(cfg, dev)
     log(f"[bench] rendered {len(targets)} targets ({time.time() - t0:.1f}s)")
     order = np.concatenate([view_order(len(cfg.cams), e) for e in range(8)])
-    tr = _trainer(cfg, targets, dev, 0, args.step_frac)
-    elapsed, stages, counts = _timed(tr, order, args.warmup, args.steps, False, dev)
-    dist = _sweep_times(tr, order, args.warmup + args.steps, 30, False, dev)
+    tr = _trainer(cfg, targets, dev, 0, args.step_frac, reserve=True)
+    # the rate: sweeps without profiling; then the same number of sweeps, profiled, for the stage
+    # times, the work counters and the roofline of the dominant kernel
+    elapsed, _, _ = _timed(tr, order, args.warmup, args.steps, False, dev, profile=False)
+    prof_el, stages, counts = _timed(tr, order[args.warmup + args.steps:], 0, args.steps, False, dev)
+    log(f"[bench] plain: {args.steps / elapsed:.2f} sweeps/s; profiled {args.steps / prof_el:.2f} sweeps/s")
+    dist = _sweep_times(tr, order, args.warmup + 2 * args.steps, 30, False, dev)
+    status = tr.check_status()
     tr.close()
+    graph = _graph_rate(cfg, targets, dev, order, args.warmup, args.steps, args.step_frac) if args.graph_leg else None
     log(f"[bench] plain: {args.steps} sweeps in {elapsed:.3f}s; stage ms: "
         + ", ".join(f"{k}={v[0]:.1f}" for k, v in stages.items()))
     learned = None
     if args.learned_every:
-        tr = _trainer(cfg, targets, dev, args.learned_every, args.step_frac)
-        el2, st2, _ = _timed(tr, order, args.warmup, args.steps, True, dev)
+        tr = _trainer(cfg, targets, dev, args.learned_every, args.step_frac, reserve=True)
+        el2, st2, _ = _rate_and_profile(tr, order, args.warmup, args.steps, True, dev)
         tr.close()
         learned = {"value": round(args.steps / el2, 4), "unit": "sweeps/s", "ms_per_step": round(el2 * 1e3 / args.steps, 3),
                    "every": args.learned_every,
@@ -492,7 +550,7 @@ def gpu_run(args):
         quality = _equal_psnr(cfg, targets, dev, args.quality_epochs, args.learned_every, args.quality_mask,
                               args.quality_step_frac)
     return (elapsed, stages, counts, cfg, learned, quality, batched, variants, overshoot, order_exp, first_order, dist,
-            curve)
+            curve, graph, status)
 
 
 def _measured_traffic(kernel):
@@ -538,18 +596,22 @@ def copy_probe(nbytes=1 << 30, reps=3):
 
 def sweep_roofline(value, counts, steps, n, views, pixels_per_step, copy_gbs):
     """The whole sweep against HBM: the bytes the method must move per sweep,
-    N (708 + 384 V) per kernel set + 28 per emitted pair + 80 per consumed list entry (forward
-    and backward) + 112 per pixel, times sweeps/s, against the 8 TB/s peak and a measured copy."""
-    b_alg = (n * (708 + 384 * views) + 28.0 * counts["pairs"] / steps + 80.0 * counts["fwd_staged"] / steps
-             + 112.0 * pixels_per_step)
+    N (708 + 384 V) per kernel set + 28 per emitted pair + 40 per list entry the forward pass
+    consumes + 40 per entry the backward pass consumes + 112 per pixel, times sweeps/s, against the
+    8 TB/s peak and a measured copy."""
+    b_alg = (n * (708 + 384 * views) + BYTES_PAIR * counts["pairs"] / steps
+             + BYTES_ENTRY * (counts["fwd_staged"] + counts["bwd_staged"]) / steps + 112.0 * pixels_per_step)
     gbs = b_alg * value / 1e9
     return {"algorithmic_bytes_per_sweep": round(b_alg), "achieved": round(gbs, 1), "unit": "GB/s",
             "peak": PEAK_HBM_GBS, "frac": round(gbs / PEAK_HBM_GBS, 5),
             "copy_gbs": round(copy_gbs, 1), "frac_of_copy": round(gbs / copy_gbs, 5)}
 
 
-def roofline(stages, counts, steps, pixels_per_step):
-    """Roofline figure of the stage that takes the most time (one kernel per stage launch)."""
+def roofline(stages, counts, steps, pixels_per_step, n, views):
+    """Roofline figure of the stage that takes the most time (one kernel per raster stage launch):
+    algorithmic FLOPs and bytes per launch from the work counters, over the launch's average time
+    (HIP events on the library's stream).  The raster passes report the ALU bound (against the
+    published FP32 vector peak, with the unpacked rate beside it) and their HBM fraction."""
     dom = max(stages, key=lambda s: stages[s][0])
     ms, launches = stages[dom]
     launches = max(launches, 1)
@@ -558,22 +620,44 @@ def roofline(stages, counts, steps, pixels_per_step):
     if dom in ("raster_bwd", "raster_fwd"):
         if dom == "raster_bwd":
             flops = FLOP_EVAL * counts["bwd_evals"] + FLOP_BWD_PAIR * counts["bwd_active"]
-            nbytes = (BYTES_BWD_ENTRY * counts["pairs"] + BYTES_BWD_PARTIAL * counts["partials"]
-                      + BYTES_BWD_PIXEL * pixels_per_step * steps)
-            out["algorithmic_bytes_per_launch"] = round(nbytes / launches)
-            out["hbm_fraction"] = round(nbytes / launches / per_launch_s / 1e9 / PEAK_HBM_GBS, 5)
+            nbytes = (BYTES_ENTRY * counts["bwd_staged"] + BYTES_BWD_PIXEL * pixels_per_step * steps
+                      + BYTES_ZSTATS * n * views * steps)
         else:
             flops = FLOP_EVAL * counts["fwd_evals"] + FLOP_FWD_BLEND * counts["bwd_active"]
+            nbytes = BYTES_ENTRY * counts["fwd_staged"] + BYTES_FWD_PIXEL * pixels_per_step * steps
         achieved = flops / launches / per_launch_s / 1e12
+        traffic = _measured_traffic(dom)
+        alg_bytes = nbytes / launches
         out.update(bound="alu", achieved=round(achieved, 3), peak=PEAK_ALU_TFLOPS, unit="TFLOP/s",
-                   frac=round(achieved / PEAK_ALU_TFLOPS, 5), traffic=_measured_traffic(dom),
-                   algorithmic_flops_per_launch=round(flops / launches))
+                   frac=round(achieved / PEAK_ALU_TFLOPS, 5), traffic=traffic,
+                   peak_unpacked=PEAK_ALU_UNPACKED_TFLOPS, frac_unpacked=round(achieved / PEAK_ALU_UNPACKED_TFLOPS, 5),
+                   algorithmic_flops_per_launch=round(flops / launches),
+                   algorithmic_bytes_per_launch=round(alg_bytes),
+                   hbm_achieved_gbs=round(alg_bytes / per_launch_s / 1e9, 1),
+                   hbm_fraction=round(alg_bytes / per_launch_s / 1e9 / PEAK_HBM_GBS, 5),
+                   algorithmic_bytes_within_traffic=(None if traffic is None else bool(alg_bytes <= traffic)))
+        if traffic is not None and alg_bytes > traffic:
+            log(f"[bench] WARNING: {dom} algorithmic bytes {alg_bytes:.3e} exceed the measured traffic {traffic:.3e}")
         return out
     # sort/bin: 28 algorithmic bytes per (tile, kernel) pair (write key/value, read per tile, write list)
-    nbytes = 28.0 * counts["pairs"]
+    nbytes = BYTES_PAIR * counts["pairs"]
     achieved = nbytes / launches / per_launch_s / 1e9
     out.update(bound="hbm", achieved=round(achieved, 1), peak=PEAK_HBM_GBS, unit="GB/s",
                frac=round(achieved / PEAK_HBM_GBS, 5), traffic=None)
+    return out
+
+
+def solve_rules(counts):
+    """How often each of the solve's safeguards bound, per solved kernel (a kernel's group is
+    counted once per sweep): damping escalated, gradient fallback, trust radius, opacity bounds."""
+    solved = max(counts.get("solved", 0), 1)
+    out = {"kernels_solved": counts.get("solved", 0)}
+    for g in ("position", "rotation", "scaling", "opacity"):
+        out[f"escalated_{g}"] = round(counts[f"escalated_{g}"] / solved, 6)
+        out[f"fallback_{g}"] = round(counts[f"fallback_{g}"] / solved, 6)
+    for g in ("position", "rotation", "scaling", "colour"):
+        out[f"trust_clamped_{g}"] = round(counts[f"clamped_{g}"] / solved, 6)
+    out["opacity_bound"] = round(counts["opacity_bound"] / solved, 6)
     return out
 
 
@@ -643,6 +727,8 @@ def main():
     ap.add_argument("--quality-step-frac", type=float, default=0.3)
     ap.add_argument("--no-batched-leg", dest="batched_leg", action="store_false",
                     help="skip timing the batched solve of the eight 20k-800k scenes")
+    ap.add_argument("--no-graph-leg", dest="graph_leg", action="store_false",
+                    help="skip timing the plain form as replayed HIP graphs of whole sweeps")
     ap.add_argument("--no-variants-leg", dest="variants_leg", action="store_false",
                     help="skip timing |N_t| = 0, 8 and the Gauss-Newton blocks on the benchmark workload")
     ap.add_argument("--overshoot-epochs", type=int, default=1,
@@ -668,11 +754,11 @@ def main():
               file=sys.stderr)
         sys.exit(2)
     (elapsed, stages, counts, cfg, learned, quality, batched, variants, overshoot, order_exp,
-     first_order, dist, curve) = gpu_run(args)
+     first_order, dist, curve, graph, status) = gpu_run(args)
     ms_per_step = elapsed * 1e3 / args.steps
     value = args.steps / elapsed
     pixels = cfg.width * cfg.height + cfg.n_secondary * (cfg.width // 2) * (cfg.height // 2)
-    rl = roofline(stages, counts, args.steps, pixels)
+    rl = roofline(stages, counts, args.steps, pixels, cfg.n, 1 + cfg.n_secondary)
     import torch
     srl = sweep_roofline(value, counts, args.steps, cfg.n, 1 + cfg.n_secondary, pixels,
                          copy_bandwidth(torch.device("cuda", 0)))
@@ -695,6 +781,9 @@ def main():
         "counts_per_step": {k: int(v / args.steps) for k, v in counts.items()},
         "roofline": rl,
         "sweep_hbm": srl,
+        "solve_rules": solve_rules({k: v / args.steps for k, v in counts.items()}),
+        "device_status": {k: v for k, v in status.items() if k != "message"},
+        "reserved_graph": graph,
         "cpu_baseline": cpu,
         "learned": learned,
         "equal_psnr": quality,

@@ -157,7 +157,8 @@ typedef struct {
  * 10 Delta sigma, 11.. Delta SH [3][K].  d_flags [5][n] int32: escalation
  * index per group (position, rotation, scaling, opacity), -1 for the
  * gradient fallback, -2 when the kernel is not seen by the primary target
- * (no step); row 4 holds the number of views the colour solve used. */
+ * (no step), -3 when a block entry or step component was not finite (no
+ * step); row 4 holds the number of views the colour solve used. */
 #define GSN_STEP_BASE 11
 typedef struct {
     float* d_data;
@@ -193,8 +194,12 @@ gsn_status gsn_frame_destroy(gsn_ctx* ctx, gsn_frame* frame);
  * The tile rectangles and depth keys are computed in single precision with
  * a fixed operation order and no contraction.  d_rgb_out [3][H][W] and
  * d_T_out [H][W] receive copies of the image and final transmittance when
- * not NULL.  Errors: GSN_E_INVALID (null handle or arrays, tile != 16,
- * sh_degree outside 0..3), GSN_E_SHAPE (n < 0, image size <= 0). */
+ * not NULL.  Kernels with a NaN or infinite attribute, or whose colour in this
+ * view is not finite, are culled (not drawn) and counted (GSN_STAT_CULLED_NONFINITE).
+ * A frame in reserved mode (gsn_frame_reserve) is rendered without any allocation
+ * or host wait.  Errors: GSN_E_INVALID (null handle or arrays, tile != 16,
+ * sh_degree outside 0..3), GSN_E_SHAPE (n < 0, image size <= 0),
+ * GSN_E_CAPACITY (reserved frame smaller than n or the image). */
 gsn_status gsn_render(gsn_ctx* ctx, const gsn_gaussians* g, const gsn_camera* cam,
                       const gsn_render_opts* opts, gsn_frame* frame, float* d_rgb_out,
                       float* d_T_out);
@@ -222,7 +227,9 @@ gsn_status gsn_accumulate_hessian(gsn_ctx* ctx, const gsn_gaussians* g, const gs
  * scale in the row space of d(lambda)/ds (eigenvalues of the primary 2D
  * covariance), opacity with a log barrier, SH colour per channel from the
  * per-view statistics (Sec. 4.2, Position/Scaling/Rotation/Opacity/Color
- * solve).  Kernels the primary target does not see get no step.
+ * solve).  Kernels the primary target does not see get no step (decisions -2); kernels with a
+ * non-finite block entry or step component get a zero step (decisions -3) and are counted
+ * (GSN_STAT_SKIPPED_NONFINITE).
  * Errors: GSN_E_SHAPE (blocks.n or steps.n != g->n, sh_degree mismatch). */
 gsn_status gsn_local_newton_solve(gsn_ctx* ctx, const gsn_gaussians* g, const gsn_camera* primary,
                                   const gsn_blocks* blocks, const gsn_solve_opts* opts,
@@ -326,6 +333,20 @@ typedef struct gsn_graph gsn_graph;
 gsn_status gsn_solve_graph_create(gsn_ctx* ctx, const gsn_solve_item* items, int32_t count, gsn_graph** out);
 gsn_status gsn_graph_launch(gsn_ctx* ctx, gsn_graph* graph);
 gsn_status gsn_graph_destroy(gsn_ctx* ctx, gsn_graph* graph);
+/* Records the calls made on the context between gsn_capture_begin and gsn_capture_end into a HIP
+ * graph instead of running them (a whole sweep: gsn_blocks_zero, the renders and accumulations of
+ * its views, the solve and the apply), so that gsn_graph_launch replays them with one launch and
+ * no host work.  The recorded calls keep their arguments: device buffers, cameras and options are those of the
+ * capture, and every buffer must keep its size.  Frames rendered under capture must be reserved
+ * (gsn_frame_reserve) and every buffer the calls use must already have its size (run the same
+ * calls once before capturing); a call that would allocate or wait fails, and gsn_capture_end then
+ * returns an error and no graph.  Calls that read results back to the host (gsn_profile_read,
+ * gsn_sync_status, frame introspection) are refused while capturing.  begin synchronises the
+ * context's stream; the graph is replayed on the context's stream.  Replays are stage-timed as a
+ * whole only (not per stage).  Errors: GSN_E_INVALID (already / not capturing, a call failed
+ * under capture), GSN_E_HIP. */
+gsn_status gsn_capture_begin(gsn_ctx* ctx);
+gsn_status gsn_capture_end(gsn_ctx* ctx, gsn_graph** out);
 
 /* ------------------------------------------------- learned step scale
  * The overshoot control of Sec. 4.3 (eq. tildel) adds the blocks of the
@@ -356,6 +377,11 @@ typedef struct {
     float lr, beta1, beta2, eps;
 } gsn_adam_opts;
 
+/* Feature status of a kernel (gsn_step_features, d_ok). */
+#define GSN_FEAT_HIDDEN 0        /* not seen by the primary target: no step */
+#define GSN_FEAT_OK 1            /* features in range: the network's scale applies */
+#define GSN_FEAT_OUT_OF_RANGE 2  /* seen, but a feature left [-3, 3]: the network is not trusted and the
+                                    kernel needs the full overshoot rule (gsn_mlp_infer counts it) */
 /* Features of every kernel (device float [16][n], layout feature-major) from
  * blocks holding only the primary view (slot 0), in the reduced coordinates of
  * gsn_local_newton_solve.  With L(x) = log10(x + 1e-30) / 10 clipped to [-3, 3]:
@@ -364,24 +390,31 @@ typedef struct {
  * for the reduced scaling Hessian; 8 L(|H_sigma + h_B|); 9 L(sum of |s| of the
  * primary's colour Hessian diagonal); 10 L(primary coverage); 11-14 L(|g|) of
  * the reduced position, rotation, scaling and opacity gradients; 15 L(opacity).
- * d_ok (device u8 [n]) is 1 for kernels visible in the primary whose features
- * all lie inside [-3, 3] before clipping.  Errors: GSN_E_SHAPE. */
+ * d_ok (device u8 [n]) receives GSN_FEAT_HIDDEN, GSN_FEAT_OK or GSN_FEAT_OUT_OF_RANGE.
+ * Errors: GSN_E_SHAPE. */
 gsn_status gsn_step_features(gsn_ctx* ctx, const gsn_gaussians* g, const gsn_camera* primary,
                              const gsn_blocks* blocks, const gsn_solve_opts* opts, float* d_feat,
                              uint8_t* d_ok);
 /* Labels from the primary-only steps (prim) and the full-rule steps (aug) of
  * the same sweep: d_label, d_mask device float [5][n]; the mask is 1 where the
- * kernel is visible in the primary and |Delta_prim|^2 > 1e-30 for the group. */
-gsn_status gsn_step_labels(gsn_ctx* ctx, const gsn_steps* prim, const gsn_steps* aug, float* d_label,
-                           float* d_mask);
+ * solve stepped the kernel (decisions >= -1), its features were in range
+ * (d_ok[k] == GSN_FEAT_OK; d_ok may be NULL) and |Delta_prim|^2 > 1e-30 for the group.
+ * With d_alpha (the network's scales [5][n] for the same kernels, may be NULL) and
+ * d_err (device double [2], may be NULL), d_err[0] += sum of mask |alpha - label|
+ * and d_err[1] += sum of mask, summed in a fixed order (the error of the network
+ * against the overshoot rule it replaces). */
+gsn_status gsn_step_labels(gsn_ctx* ctx, const gsn_steps* prim, const gsn_steps* aug, const uint8_t* d_ok,
+                           const float* d_alpha, float* d_label, float* d_mask, double* d_err);
 /* Zeroes the Adam moments and the step count and refreshes the fp16 copy from
  * the master weights. */
 gsn_status gsn_mlp_reset(gsn_ctx* ctx, gsn_mlp* mlp);
 /* alpha (device float [5][n]) for every kernel from its features, with the
- * fp16 weights and FP32 accumulation; kernels with d_ok[k] == 0 get 0 (no
- * step until a sweep that runs the full rule). */
+ * fp16 weights and FP32 accumulation; kernels whose d_ok[k] is not GSN_FEAT_OK
+ * get 0.  d_out_of_range (device u32, may be NULL) += the number of kernels with
+ * d_ok[k] == GSN_FEAT_OUT_OF_RANGE: a caller that finds it nonzero runs the full
+ * overshoot rule for the sweep (the fallback of the learned form). */
 gsn_status gsn_mlp_infer(gsn_ctx* ctx, const gsn_mlp* mlp, int32_t n, const float* d_feat,
-                         const uint8_t* d_ok, float* d_alpha);
+                         const uint8_t* d_ok, float* d_alpha, uint32_t* d_out_of_range);
 /* One Adam step on the mean squared error over the entries with mask 1
  * (features [16][n], labels and mask [5][n]); writes the loss before the step
  * to d_loss (device double, may be NULL) and the gradient to d_grad (device
@@ -455,6 +488,40 @@ gsn_status gsn_frame_records(gsn_ctx* ctx, const gsn_frame* frame, float* d_out)
  * ([3][H][W] floats each) of the last gsn_accumulate_hessian on this frame. */
 gsn_status gsn_frame_loss_maps(gsn_ctx* ctx, const gsn_frame* frame, float* d_dL, float* d_h);
 
+/* ------------------------------------------------- status without host waits
+ * The calls of a sweep never wait for the device when every frame has a reserved capacity, so a
+ * caller can queue (or capture in a HIP graph) many sweeps and check their outcome once.  What
+ * the device met meanwhile is counted in the context and read by gsn_sync_status. */
+
+/* Reserves a frame's device memory for views of at most width x height pixels with n kernels and at
+ * most max_pairs (tile, kernel) pairs, and switches the frame to reserved mode: gsn_render then
+ * allocates nothing and no longer reads the pair count back to the host.  A render whose pairs
+ * exceed max_pairs draws no kernel (its image is the background, its lists are empty, and its
+ * gsn_accumulate_hessian adds nothing), counts GSN_STAT_PAIR_OVERFLOW and records the pair count it
+ * needed; reserve again with a larger max_pairs to render such views.  max_pairs = 0 returns the
+ * frame to growing mode (the render sizes its buffers from the count it reads back).  Synchronises
+ * the stream.  Errors: GSN_E_INVALID (null handles), GSN_E_SHAPE (n < 0, image size <= 0,
+ * max_pairs < 0), GSN_E_CAPACITY (max_pairs >= 2^31), GSN_E_NOMEM. */
+gsn_status gsn_frame_reserve(gsn_ctx* ctx, gsn_frame* frame, int32_t n, int32_t width, int32_t height,
+                             int64_t max_pairs);
+
+/* Counters of gsn_sync_status. */
+typedef enum {
+    GSN_STAT_CULLED_NONFINITE = 0,  /* kernels gsn_render culled (per render): a position, rotation, scale
+                                       or opacity, or the view-dependent colour, was NaN or infinite */
+    GSN_STAT_SKIPPED_NONFINITE = 1, /* kernels a solve skipped (zero step, decisions -3) because a block
+                                       entry or a step component was NaN or infinite */
+    GSN_STAT_PAIR_OVERFLOW = 2,     /* renders of reserved frames whose pairs exceeded the capacity */
+    GSN_STAT_PAIRS_NEEDED = 3,      /* the largest pair count such a render needed */
+    GSN_STAT_N = 4
+} gsn_stat;
+
+/* Synchronises the context's stream, copies the counters gathered since the last call (or since
+ * gsn_create) into h_stats[GSN_STAT_N] (may be NULL) and clears them.  Returns GSN_E_CAPACITY when
+ * a reserved render overflowed, else GSN_E_NUMERIC when a non-finite value was met (the kernels
+ * concerned were culled or skipped, not updated), else GSN_OK; gsn_last_error describes it. */
+gsn_status gsn_sync_status(gsn_ctx* ctx, int64_t* h_stats);
+
 /* ------------------------------------------------------------ measurement */
 
 /* Stages timed by the profiler. */
@@ -479,7 +546,18 @@ typedef enum {
     GSN_COUNT_PARTIALS = 4,    /* (tile, kernel) partial statistics written by the backward pass */
     GSN_COUNT_FWD_STAGED = 5,  /* list entries the forward pass staged (read) before its tiles finished */
     GSN_COUNT_FP64_SOLVES = 6, /* kernels whose position or rotation system the mixed form re-solved in FP64 */
-    GSN_COUNT_N = 7
+    GSN_COUNT_BWD_STAGED = 7,  /* list entries the backward pass staged (read): each tile's composited prefix */
+    /* Solve decisions (gsn_local_newton_solve), per group g = 0 position, 1 rotation, 2 scaling,
+     * 3 opacity: the damped system was accepted only after escalating mu (j > 0), or every attempt
+     * failed and the scaled gradient step was taken (j = -1); and per g = 0 position, 1 rotation,
+     * 2 scaling, 3 colour (any channel) the trust radius cut the step. */
+    GSN_COUNT_SOLVE_ESCALATED = 8,  /* + g */
+    GSN_COUNT_SOLVE_FALLBACK = 12,  /* + g */
+    GSN_COUNT_SOLVE_CLAMPED = 16,   /* + g */
+    GSN_COUNT_SOLVED = 20,          /* kernels solved (visible in the primary, finite blocks and steps) */
+    GSN_COUNT_OPAC_BOUND = 21,      /* gsn_apply_step: opacity steps cut by the fraction-to-boundary rule
+                                       or the bounds [opac_eps, 1 - opac_eps] */
+    GSN_COUNT_N = 22
 } gsn_counter;
 
 /* Turns stage timing on or off and clears what was accumulated.  While on,

@@ -1229,7 +1229,7 @@ int orc_features(int n, int K, const double* pos, const double* rot, const doubl
         f[13] = L(std::sqrt(R.gs[0] * R.gs[0] + R.gs[1] * R.gs[1]));
         f[14] = L(std::fabs(R.go));
         f[15] = L(opac[k]);
-        ok[k] = in_range ? 1 : 0;
+        ok[k] = in_range ? 1 : 2;  // 0: not seen by the primary, 1: features in range, 2: seen, out of range
     }
     return 0;
 }

@@ -38,8 +38,12 @@ GROUP_COLS = [slice(0, 3), slice(3, 4), slice(7, 10), slice(10, 11), None]
 MIN_STEP_SQ = 1e-30
 
 
+# feature status codes: not seen by the primary, features in range, seen but out of range
+FEAT_HIDDEN, FEAT_OK, FEAT_OUT_OF_RANGE = 0, 1, 2
+
+
 def features(g, cam, o, summed, V):
-    """Per-kernel features [n][16] and in-range flags [n] from the summed blocks."""
+    """Per-kernel features [n][16] and status codes [n] (FEAT_*) from the summed blocks."""
     g64 = O.G64.of(g)
     feat = np.zeros((g64.n, N_IN))
     ok = np.zeros(g64.n, np.uint8)
@@ -105,12 +109,15 @@ def adam(params, m, v, t, grad, lr=1e-3, b1=0.9, b2=0.999, eps=1e-8):
     return params - lr * mh / (np.sqrt(vh) + eps), m, v
 
 
-def labels(steps_prim, steps_aug, dec_prim, K):
-    """alpha_eff [n][5] and mask [n][5] from primary-only and full-rule steps [n][11 + 3K]."""
+def labels(steps_prim, steps_aug, dec_prim, K, ok=None):
+    """alpha_eff [n][5] and mask [n][5] from primary-only and full-rule steps [n][11 + 3K]; with the
+    feature status codes ok, entries of kernels whose features were not in range are masked."""
     n = steps_prim.shape[0]
     lab = np.zeros((n, N_OUT))
     msk = np.zeros((n, N_OUT))
-    vis = np.asarray(dec_prim)[:, 0] != -2
+    vis = np.asarray(dec_prim)[:, 0] >= -1
+    if ok is not None:
+        vis = vis & (np.asarray(ok) == FEAT_OK)
     for gi, sl in enumerate(GROUP_COLS):
         sl = slice(11, 11 + 3 * K) if sl is None else sl
         p = np.asarray(steps_prim, np.float64)[:, sl]
@@ -120,3 +127,9 @@ def labels(steps_prim, steps_aug, dec_prim, K):
         lab[good, gi] = np.clip((a * p).sum(1)[good] / pp[good], 0.0, ALPHA_MAX)
         msk[good, gi] = 1.0
     return lab, msk
+
+
+def label_error(alpha, lab, msk):
+    """(sum of mask |alpha - label|, sum of mask): the network's error against the overshoot rule."""
+    m = np.asarray(msk, np.float64)
+    return float((np.abs(np.asarray(alpha, np.float64) - lab) * m).sum()), float(m.sum())

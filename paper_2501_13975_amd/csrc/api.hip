@@ -11,8 +11,13 @@
 
 #include "gsn_internal.h"
 
+// Set on the host thread that is capturing a context's stream into a graph: buffers may not grow
+// then (an allocation is not part of the graph, and the graph keeps the addresses it captured).
+static thread_local bool t_capturing = false;
+
 hipError_t buf_reserve(DevBuf& b, size_t bytes) {
     if (bytes <= b.bytes && b.p) return hipSuccess;
+    if (t_capturing) return hipErrorStreamCaptureUnsupported;
     if (b.p) {
         hipError_t e = hipFree(b.p);
         if (e != hipSuccess) return e;
@@ -37,7 +42,7 @@ void buf_free(DevBuf& b) {
 }
 
 StageTimer::StageTimer(gsn_ctx* c, int stage) : ctx(c) {
-    if (!ctx || !ctx->prof) return;
+    if (!ctx || !ctx->prof || ctx->capturing) return;
     ProfRec r;
     r.stage = stage;
     for (hipEvent_t* e : {&r.start, &r.stop}) {
@@ -66,7 +71,10 @@ gsn_status fail(gsn_ctx* ctx, gsn_status st, const char* fmt, ...) {
     va_start(ap, fmt);
     vsnprintf(buf, sizeof buf, fmt, ap);
     va_end(ap);
-    if (ctx) ctx->err = buf;
+    if (ctx) {
+        ctx->err = buf;
+        if (ctx->capturing) ctx->capture_failed = true;  // the graph would miss this call's work
+    }
     return st;
 }
 
@@ -135,6 +143,20 @@ gsn_status gsn_create(gsn_ctx** out, int32_t device, void* hip_stream) {
     c->device = device;
     c->stream = static_cast<hipStream_t>(hip_stream);
     c->noalloc_gram = scratch;
+    int cur = 0;
+    hipError_t e = hipGetDevice(&cur);
+    if (e == hipSuccess) e = hipSetDevice(device);
+    if (e == hipSuccess) e = hipMalloc((void**)&c->d_stats, GSN_STAT_N * sizeof(unsigned long long));
+    if (e == hipSuccess) {
+        launch_fill_u32(reinterpret_cast<uint32_t*>(c->d_stats), 0u, 2 * GSN_STAT_N, c->stream);
+        e = hipStreamSynchronize(c->stream);
+    }
+    (void)hipSetDevice(cur);
+    if (e != hipSuccess) {
+        if (c->d_stats) (void)hipFree(c->d_stats);
+        delete c;
+        return e == hipErrorOutOfMemory ? GSN_E_NOMEM : GSN_E_HIP;
+    }
     *out = c;
     return GSN_OK;
 }
@@ -149,8 +171,11 @@ gsn_status gsn_destroy(gsn_ctx* ctx) {
     }
     for (hipEvent_t e : ctx->pool) (void)hipEventDestroy(e);
     if (ctx->d_counts) (void)hipFree(ctx->d_counts);
+    if (ctx->d_stats) (void)hipFree(ctx->d_stats);
+    if (ctx->cap_stream) (void)hipStreamDestroy(ctx->cap_stream);
     buf_free(ctx->mlp_part);
     buf_free(ctx->mlp_stat);
+    buf_free(ctx->label_part);
     buf_free(ctx->solve_table);
     buf_free(ctx->gram);
     delete ctx;
@@ -166,7 +191,6 @@ gsn_status gsn_profile_enable(gsn_ctx* ctx, int32_t on) {
         ctx->pool.push_back(r.stop);
     }
     ctx->recs.clear();
-    ctx->pairs_counted = 0;
     if (on && !ctx->d_counts)
         HIP_TRY(ctx, hipMalloc((void**)&ctx->d_counts, GSN_COUNT_N * sizeof(unsigned long long)));
     if (ctx->d_counts) launch_fill_u32(reinterpret_cast<uint32_t*>(ctx->d_counts), 0u, 2 * GSN_COUNT_N, ctx->stream);
@@ -195,8 +219,31 @@ gsn_status gsn_profile_read(gsn_ctx* ctx, double* h_ms, int64_t* h_launches, int
         unsigned long long c[GSN_COUNT_N] = {0};
         if (ctx->d_counts) HIP_TRY(ctx, hipMemcpy(c, ctx->d_counts, sizeof c, hipMemcpyDeviceToHost));
         for (int i = 0; i < GSN_COUNT_N; ++i) h_counts[i] = (int64_t)c[i];
-        h_counts[GSN_COUNT_PAIRS] = ctx->pairs_counted;
     }
+    return GSN_OK;
+}
+
+gsn_status gsn_sync_status(gsn_ctx* ctx, int64_t* h_stats) {
+    if (!ctx) return GSN_E_INVALID;
+    if (ctx->capturing) return fail(ctx, GSN_E_INVALID, "gsn_sync_status while capturing a graph");
+    HIP_TRY(ctx, hipSetDevice(ctx->device));
+    HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+    unsigned long long c[GSN_STAT_N] = {0};
+    HIP_TRY(ctx, hipMemcpy(c, ctx->d_stats, sizeof c, hipMemcpyDeviceToHost));
+    launch_fill_u32(reinterpret_cast<uint32_t*>(ctx->d_stats), 0u, 2 * GSN_STAT_N, ctx->stream);
+    HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+    if (h_stats)
+        for (int i = 0; i < GSN_STAT_N; ++i) h_stats[i] = (int64_t)c[i];
+    if (c[GSN_STAT_PAIR_OVERFLOW])
+        return fail(ctx, GSN_E_CAPACITY,
+                    "%llu render(s) exceeded the reserved pair capacity (largest need %llu pairs) and drew nothing; "
+                    "%llu kernel(s) culled and %llu skipped for non-finite values",
+                    c[GSN_STAT_PAIR_OVERFLOW], c[GSN_STAT_PAIRS_NEEDED], c[GSN_STAT_CULLED_NONFINITE],
+                    c[GSN_STAT_SKIPPED_NONFINITE]);
+    if (c[GSN_STAT_CULLED_NONFINITE] || c[GSN_STAT_SKIPPED_NONFINITE])
+        return fail(ctx, GSN_E_NUMERIC, "%llu kernel(s) culled by renders and %llu skipped by solves for NaN or Inf",
+                    c[GSN_STAT_CULLED_NONFINITE], c[GSN_STAT_SKIPPED_NONFINITE]);
+    ctx->err.clear();
     return GSN_OK;
 }
 
@@ -232,6 +279,72 @@ gsn_status gsn_frame_destroy(gsn_ctx* ctx, gsn_frame* f) {
     return GSN_OK;
 }
 
+// Reserves the buffers a render of n kernels on a W x H view and its gsn_accumulate_hessian need,
+// with pair buffers for `pairs` pairs (0: the pair buffers are left as they are).
+static hipError_t frame_buffers(gsn_frame* f, int n, int W, int H, size_t pairs) {
+    const size_t nn = (size_t)std::max(n, 1);
+    const size_t npx = (size_t)W * H;
+    const size_t tiles = (size_t)((W + GSN_TILE - 1) / GSN_TILE) * ((H + GSN_TILE - 1) / GSN_TILE);
+    DevBuf* per_kernel4[] = {&f->depth_key, &f->ntiles, &f->ids_a, &f->ids_b, &f->keys_a, &f->keys_b, &f->pair_off};
+    hipError_t e = buf_reserve(f->rec, nn * 3 * sizeof(float4));
+    if (e == hipSuccess) e = buf_reserve(f->rect, nn * sizeof(uint2));
+    for (DevBuf* b : per_kernel4)
+        if (e == hipSuccess) e = buf_reserve(*b, nn * 4);
+    if (e == hipSuccess) e = buf_reserve(f->offsets, (nn + 1) * 4);
+    if (e == hipSuccess) e = buf_reserve(f->kflag, (nn + 3) / 4 * 4);
+    if (e == hipSuccess) e = buf_reserve(f->zsum, nn * GSN_NZ * 8);
+    if (e == hipSuccess) e = buf_reserve(f->ranges, tiles * sizeof(uint2));
+    DevBuf* per_tile4[] = {&f->tile_order, &f->tile_len, &f->bwd_order};
+    for (DevBuf* b : per_tile4)
+        if (e == hipSuccess) e = buf_reserve(*b, tiles * 4);
+    if (e == hipSuccess) e = buf_reserve(f->img, 3 * npx * 4);
+    if (e == hipSuccess) e = buf_reserve(f->img64, 3 * npx * 8);
+    if (e == hipSuccess) e = buf_reserve(f->Tfin, npx * 4);
+    if (e == hipSuccess) e = buf_reserve(f->ncontrib, npx * 4);
+    if (e == hipSuccess) e = buf_reserve(f->masks, tiles * GSN_MASK_BATCHES * 2 * 4 * GSN_BLOCK * sizeof(uint64_t));
+    if (e == hipSuccess) e = buf_reserve(f->dL, 3 * npx * 4);
+    if (e == hipSuccess) e = buf_reserve(f->hd, 3 * npx * 4);
+    if (e == hipSuccess) e = buf_reserve(f->coef, 24 * npx * 4);
+    if (e == hipSuccess) e = buf_reserve(f->loss_part, (size_t)2 * 3 * tiles * sizeof(double));
+    if (e == hipSuccess) e = buf_reserve(f->total, 16);
+    const size_t pp = std::max<size_t>(pairs, 1);
+    // the histogram size is not monotone in the key count (the tile grows past 4M keys): cover
+    // every count up to nn
+    const size_t hist = std::max({radix_hist_bytes((uint32_t)nn), radix_hist_bytes((uint32_t)std::min<size_t>(nn, 1u << 22)),
+                                  radix_hist_bytes((uint32_t)pp), radix_hist_bytes((uint32_t)std::min<size_t>(pp, 1u << 22))});
+    if (e == hipSuccess) e = buf_reserve(f->hist, hist);
+    if (e == hipSuccess) e = buf_reserve(f->scan_tmp, scan_tmp_bytes((uint32_t)nn));
+    if (pairs == 0 || e != hipSuccess) return e;
+    DevBuf* per_pair4[] = {&f->pk_a, &f->pv_a, &f->pk_b, &f->pv_b};
+    for (DevBuf* b : per_pair4)
+        if (e == hipSuccess) e = buf_reserve(*b, pp * 4);
+    if (e == hipSuccess) e = buf_reserve(f->chunk_first, emit_chunks((uint32_t)pp) * 4 + 4);
+    if (e == hipSuccess) e = buf_reserve(f->partial, pp * GSN_NZ * 4);
+    if (e == hipSuccess) e = buf_reserve(f->flags, (pp + 3) / 4 * 4);
+    return e;
+}
+
+gsn_status gsn_frame_reserve(gsn_ctx* ctx, gsn_frame* f, int32_t n, int32_t width, int32_t height,
+                             int64_t max_pairs) {
+    if (!ctx || !f) return fail(ctx, GSN_E_INVALID, "null context or frame");
+    if (n < 0 || width <= 0 || height <= 0 || max_pairs < 0)
+        return fail(ctx, GSN_E_SHAPE, "n = %d, image %dx%d, max_pairs = %lld", n, width, height, (long long)max_pairs);
+    if (max_pairs >= (1ll << 31)) return fail(ctx, GSN_E_CAPACITY, "max_pairs = %lld >= 2^31", (long long)max_pairs);
+    HIP_TRY(ctx, hipSetDevice(ctx->device));
+    HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+    if (max_pairs == 0) {
+        f->cap_pairs = 0;
+        f->cap_n = f->cap_W = f->cap_H = 0;
+        return GSN_OK;
+    }
+    HIP_TRY(ctx, frame_buffers(f, n, width, height, (size_t)max_pairs));
+    f->cap_pairs = max_pairs;
+    f->cap_n = n;
+    f->cap_W = width;
+    f->cap_H = height;
+    return GSN_OK;
+}
+
 gsn_status gsn_render(gsn_ctx* ctx, const gsn_gaussians* g, const gsn_camera* cam, const gsn_render_opts* opts,
                       gsn_frame* f, float* d_rgb_out, float* d_T_out) {
     if (!ctx || !f || !opts) return fail(ctx, GSN_E_INVALID, "null context, frame or options");
@@ -242,6 +355,14 @@ gsn_status gsn_render(gsn_ctx* ctx, const gsn_gaussians* g, const gsn_camera* ca
     if (!(opts->alpha_max > 0.f && opts->alpha_max < 1.f) || !(opts->alpha_min >= 0.f) || !(opts->T_min >= 0.f) ||
         !(opts->kappa >= 0.f) || !(opts->radius_sigma > 0.f))
         return fail(ctx, GSN_E_INVALID, "render option out of range");
+    const bool reserved = f->cap_pairs > 0;
+    if (reserved && (g->n > f->cap_n || (int64_t)cam->width * cam->height > (int64_t)f->cap_W * f->cap_H ||
+                     (int64_t)((cam->width + 15) / 16) * ((cam->height + 15) / 16) >
+                         (int64_t)((f->cap_W + 15) / 16) * ((f->cap_H + 15) / 16)))
+        return fail(ctx, GSN_E_CAPACITY, "frame reserved for %d kernels at %dx%d: got %d kernels at %dx%d", f->cap_n,
+                    f->cap_W, f->cap_H, g->n, cam->width, cam->height);
+    if (!reserved && ctx->capturing)
+        return fail(ctx, GSN_E_INVALID, "a render under graph capture needs a reserved frame (gsn_frame_reserve)");
     HIP_TRY(ctx, hipSetDevice(ctx->device));
     hipStream_t s = ctx->stream;
     const int n = g->n;
@@ -261,43 +382,23 @@ gsn_status gsn_render(gsn_ctx* ctx, const gsn_gaussians* g, const gsn_camera* ca
     for (int i = 0; i < 3; ++i) f->ro.bg[i] = opts->bg[i];
     const size_t nn = (size_t)std::max(n, 1);
     const size_t npx = (size_t)f->W * f->H, tiles = (size_t)f->tiles_x * f->tiles_y;
-    HIP_TRY(ctx, buf_reserve(f->rec, nn * 3 * sizeof(float4)));
-    HIP_TRY(ctx, buf_reserve(f->rect, nn * sizeof(uint2)));
-    HIP_TRY(ctx, buf_reserve(f->depth_key, nn * 4));
-    HIP_TRY(ctx, buf_reserve(f->ntiles, nn * 4));
-    HIP_TRY(ctx, buf_reserve(f->ids_a, nn * 4));
-    HIP_TRY(ctx, buf_reserve(f->ids_b, nn * 4));
-    HIP_TRY(ctx, buf_reserve(f->keys_a, nn * 4));
-    HIP_TRY(ctx, buf_reserve(f->keys_b, nn * 4));
-    HIP_TRY(ctx, buf_reserve(f->offsets, (nn + 1) * 4));
-    HIP_TRY(ctx, buf_reserve(f->pair_off, nn * 4));
-    HIP_TRY(ctx, buf_reserve(f->ranges, tiles * sizeof(uint2)));
-    HIP_TRY(ctx, buf_reserve(f->tile_order, tiles * 4));
-    HIP_TRY(ctx, buf_reserve(f->tile_len, tiles * 4));
-    HIP_TRY(ctx, buf_reserve(f->bwd_order, tiles * 4));
-    HIP_TRY(ctx, buf_reserve(f->img, 3 * npx * 4));
-    HIP_TRY(ctx, buf_reserve(f->img64, 3 * npx * 8));
-    HIP_TRY(ctx, buf_reserve(f->Tfin, npx * 4));
-    HIP_TRY(ctx, buf_reserve(f->masks, tiles * GSN_MASK_BATCHES * 2 * 4 * GSN_BLOCK * sizeof(uint64_t)));
-    HIP_TRY(ctx, buf_reserve(f->ncontrib, npx * 4));
-    HIP_TRY(ctx, buf_reserve(f->total, 16));
-    // sort and scan scratch for the per-kernel stages, reserved before any launch so that
-    // no buffer is reallocated while work that uses it may still be queued
-    HIP_TRY(ctx, buf_reserve(f->hist, radix_hist_bytes((uint32_t)nn)));
-    HIP_TRY(ctx, buf_reserve(f->scan_tmp, scan_tmp_bytes((uint32_t)nn)));
-    uint32_t* d_total = bp<uint32_t>(f->total);
+    // per-kernel and per-pixel buffers (and, in reserved mode, everything): no buffer is reallocated
+    // while work that uses it may still be queued
+    if (!reserved) HIP_TRY(ctx, frame_buffers(f, n, f->W, f->H, 0));
+    uint32_t* d_total = bp<uint32_t>(f->total);  // [0] scanned pair total, [1] live pair count
     {
         // 1. projection and binning decisions
         StageTimer st_(ctx, GSN_STAGE_PROJECT);
         launch_preprocess(*g, f->cam, f->ro, bp<float4>(f->rec), bp<uint2>(f->rect), bp<uint32_t>(f->keys_a),
-                          bp<uint32_t>(f->ids_a), bp<uint32_t>(f->ntiles), s);
+                          bp<uint32_t>(f->ids_a), bp<uint32_t>(f->ntiles), ctx->d_stats + GSN_STAT_CULLED_NONFINITE,
+                          s);
         HIP_TRY(ctx, hipGetLastError());
     }
     {
         // 2. depth order of the kernels: stable radix sort of (depth bits, id)
         StageTimer st_(ctx, GSN_STAGE_SORT);
         HIP_TRY(ctx, radix_sort_pairs(bp<uint32_t>(f->keys_a), bp<uint32_t>(f->ids_a), bp<uint32_t>(f->keys_b),
-                                      bp<uint32_t>(f->ids_b), (uint32_t)n, 0, 32, f->hist, f->scan_tmp, s));
+                                      bp<uint32_t>(f->ids_b), (uint32_t)n, nullptr, 0, 32, f->hist, s));
         // 3. pair offsets in depth order
         launch_gather_u32(bp<uint32_t>(f->ntiles), bp<uint32_t>(f->ids_a), bp<uint32_t>(f->keys_b), (uint32_t)n, s);
         if (n > 0) {
@@ -307,41 +408,38 @@ gsn_status gsn_render(gsn_ctx* ctx, const gsn_gaussians* g, const gsn_camera* ca
             launch_fill_u32(d_total, 0u, 1, s);
         }
     }
-    HIP_TRY(ctx, hipMemcpyAsync(f->h_total, d_total, 4, hipMemcpyDeviceToHost, s));
-    HIP_TRY(ctx, hipStreamSynchronize(s));
-    const uint32_t P = *f->h_total;
-    f->pairs = P;
-    const size_t pp = std::max<size_t>(P, 1);
-    // the stream is idle here: growing scratch cannot race with queued work
-    HIP_TRY(ctx, buf_reserve(f->hist, radix_hist_bytes((uint32_t)pp)));
-    HIP_TRY(ctx, buf_reserve(f->chunk_first, emit_chunks((uint32_t)pp) * 4 + 4));
-    HIP_TRY(ctx, buf_reserve(f->scan_tmp, scan_tmp_bytes((uint32_t)std::max<size_t>(pp, nn))));
-    HIP_TRY(ctx, buf_reserve(f->pk_a, pp * 4));
-    HIP_TRY(ctx, buf_reserve(f->pv_a, pp * 4));
-    HIP_TRY(ctx, buf_reserve(f->pk_b, pp * 4));
-    HIP_TRY(ctx, buf_reserve(f->pv_b, pp * 4));
-    // per-pair statistics of the backward pass and their written-flags (cleared once per render: which
-    // slots the backward pass writes depends only on this render, not on the loss)
-    HIP_TRY(ctx, buf_reserve(f->partial, pp * GSN_NZ * 4));
-    HIP_TRY(ctx, buf_reserve(f->flags, (pp + 3) / 4 * 4));
-    HIP_TRY(ctx, buf_reserve(f->kflag, (nn + 3) / 4 * 4));
+    uint32_t cap;
+    if (reserved) {
+        cap = (uint32_t)f->cap_pairs;
+        f->pairs = -1;
+    } else {
+        HIP_TRY(ctx, hipMemcpyAsync(f->h_total, d_total, 4, hipMemcpyDeviceToHost, s));
+        HIP_TRY(ctx, hipStreamSynchronize(s));
+        cap = *f->h_total;
+        f->pairs = cap;
+        // the stream is idle here: growing the pair buffers cannot race with queued work
+        HIP_TRY(ctx, frame_buffers(f, n, f->W, f->H, std::max<size_t>(cap, 1)));
+    }
+    const uint32_t* d_pairs = d_total + 1;
     {
         // 4. pairs in depth order, then a stable partition by tile id
         StageTimer st_(ctx, GSN_STAGE_SORT);
-        launch_fill_u32(bp<uint32_t>(f->flags), 0u, (pp + 3) / 4, s);
+        launch_pair_capacity(d_total, cap, ctx->d_stats, prof_counts(ctx), s);
+        // per-pair written-flags of the backward pass, cleared once per render (which slots it writes
+        // depends only on this render, not on the loss)
+        launch_fill_u32_dev(bp<uint32_t>(f->flags), 0u, d_pairs, 4, ((size_t)cap + 3) / 4, s);
         launch_fill_u32(bp<uint32_t>(f->kflag), 0u, (nn + 3) / 4, s);
-        launch_emit_pairs(bp<uint32_t>(f->ids_a), bp<uint32_t>(f->offsets), (uint32_t)n, P, bp<uint2>(f->rect),
-                          (uint32_t)f->tiles_x, bp<uint32_t>(f->pk_a), bp<uint32_t>(f->pv_a),
+        launch_emit_pairs(bp<uint32_t>(f->ids_a), bp<uint32_t>(f->offsets), (uint32_t)n, d_pairs, cap,
+                          bp<uint2>(f->rect), (uint32_t)f->tiles_x, bp<uint32_t>(f->pk_a), bp<uint32_t>(f->pv_a),
                           bp<uint32_t>(f->pair_off), bp<uint32_t>(f->chunk_first), s);
         int tile_bits = 1;
         while ((1ull << tile_bits) < tiles) ++tile_bits;
         HIP_TRY(ctx, radix_sort_pairs(bp<uint32_t>(f->pk_a), bp<uint32_t>(f->pv_a), bp<uint32_t>(f->pk_b),
-                                      bp<uint32_t>(f->pv_b), P, 0, tile_bits, f->hist, f->scan_tmp, s));
+                                      bp<uint32_t>(f->pv_b), cap, d_pairs, 0, tile_bits, f->hist, s));
         launch_fill_u32(bp<uint32_t>(f->ranges), 0u, 2 * tiles, s);
-        launch_tile_ranges(bp<uint32_t>(f->pk_a), P, bp<uint2>(f->ranges), s);
+        launch_tile_ranges(bp<uint32_t>(f->pk_a), d_pairs, cap, bp<uint2>(f->ranges), s);
         launch_tile_order(bp<uint2>(f->ranges), nullptr, (int)tiles, bp<uint32_t>(f->tile_order), s);
     }
-    if (ctx->prof) ctx->pairs_counted += P;
     {
         // 5. front-to-back compositing
         StageTimer st_(ctx, GSN_STAGE_RASTER_FWD);
@@ -353,8 +451,9 @@ gsn_status gsn_render(gsn_ctx* ctx, const gsn_gaussians* g, const gsn_camera* ca
         launch_tile_order(nullptr, bp<uint32_t>(f->tile_len), (int)tiles, bp<uint32_t>(f->bwd_order), s);
         HIP_TRY(ctx, hipGetLastError());
     }
-    if (d_rgb_out) HIP_TRY(ctx, hipMemcpyAsync(d_rgb_out, f->img.p, 3 * npx * 4, hipMemcpyDeviceToDevice, s));
-    if (d_T_out) HIP_TRY(ctx, hipMemcpyAsync(d_T_out, f->Tfin.p, npx * 4, hipMemcpyDeviceToDevice, s));
+    if (d_rgb_out) launch_copy_u32(reinterpret_cast<uint32_t*>(d_rgb_out), bp<uint32_t>(f->img), 3 * npx, s);
+    if (d_T_out) launch_copy_u32(reinterpret_cast<uint32_t*>(d_T_out), bp<uint32_t>(f->Tfin), npx, s);
+    HIP_TRY(ctx, hipGetLastError());
     f->rendered = true;
     return GSN_OK;
 }
@@ -395,7 +494,7 @@ gsn_status gsn_accumulate_hessian(gsn_ctx* ctx, const gsn_gaussians* g, const gs
     }
     {
         StageTimer st_(ctx, GSN_STAGE_RASTER_BWD);
-        if (f->pairs > 0)
+        if (f->pairs != 0)  // reserved frames (pairs = -1) always launch: empty lists end at once
             launch_raster_bwd(*f, bp<float>(f->dL), bp<float>(f->hd), opts->gauss_newton != 0, prof_counts(ctx), s);
     }
     {
@@ -431,14 +530,14 @@ gsn_status gsn_local_newton_solve(gsn_ctx* ctx, const gsn_gaussians* g, const gs
     HIP_TRY(ctx, hipSetDevice(ctx->device));
     if (o->precision == 1) HIP_TRY(ctx, buf_reserve(ctx->gram, (size_t)std::max(g->n, 1) * 10 * 4));
     StageTimer st_(ctx, GSN_STAGE_SOLVE);
+    unsigned long long* nonfinite = ctx->d_stats + GSN_STAT_SKIPPED_NONFINITE;
     if (o->precision == 1) {
         const int K = (g->sh_degree + 1) * (g->sh_degree + 1);
         launch_sh_gram(b->d_data, g->n, K, b->n_views, bp<float>(ctx->gram), ctx->stream);
-        unsigned long long* n64 = ctx->prof && ctx->d_counts ? ctx->d_counts + GSN_COUNT_FP64_SOLVES : nullptr;
-        launch_solve_mixed(*g, make_devcam(*primary), o->kappa, *b, *o, bp<float>(ctx->gram), *st, n64,
-                           ctx->stream);
+        launch_solve_mixed(*g, make_devcam(*primary), o->kappa, *b, *o, bp<float>(ctx->gram), *st, nonfinite,
+                           prof_counts(ctx), ctx->stream);
     } else {
-        launch_solve(*g, make_devcam(*primary), o->kappa, *b, *o, *st, ctx->stream);
+        launch_solve(*g, make_devcam(*primary), o->kappa, *b, *o, *st, nonfinite, prof_counts(ctx), ctx->stream);
     }
     HIP_TRY(ctx, hipGetLastError());
     return GSN_OK;
@@ -454,13 +553,14 @@ gsn_status gsn_local_newton_solve_noalloc(gsn_ctx* ctx, const gsn_gaussians* g, 
     if (!ctx->noalloc_gram) return fail(ctx, GSN_E_INVALID, "no scratch address for this device");
     HIP_TRY(ctx, hipSetDevice(ctx->device));
     // no stage timing here: timing may create events; no buffer is reserved or grown
+    unsigned long long* nonfinite = ctx->d_stats + GSN_STAT_SKIPPED_NONFINITE;
     if (o->precision == 1) {
         const int K = (g->sh_degree + 1) * (g->sh_degree + 1);
         launch_sh_gram(b->d_data, g->n, K, b->n_views, ctx->noalloc_gram, ctx->stream);
-        unsigned long long* n64 = ctx->prof && ctx->d_counts ? ctx->d_counts + GSN_COUNT_FP64_SOLVES : nullptr;
-        launch_solve_mixed(*g, make_devcam(*primary), o->kappa, *b, *o, ctx->noalloc_gram, *st, n64, ctx->stream);
+        launch_solve_mixed(*g, make_devcam(*primary), o->kappa, *b, *o, ctx->noalloc_gram, *st, nonfinite,
+                           prof_counts(ctx), ctx->stream);
     } else {
-        launch_solve(*g, make_devcam(*primary), o->kappa, *b, *o, *st, ctx->stream);
+        launch_solve(*g, make_devcam(*primary), o->kappa, *b, *o, *st, nonfinite, prof_counts(ctx), ctx->stream);
     }
     HIP_TRY(ctx, hipGetLastError());
     return GSN_OK;
@@ -553,7 +653,8 @@ gsn_status gsn_solve_batched(gsn_ctx* ctx, const gsn_solve_item* items, int32_t 
     int block, grid;
     default_solve_shape(ctx, block, grid);
     StageTimer st_(ctx, GSN_STAGE_SOLVE);
-    launch_solve_batched(bp<SolveScene>(ctx->solve_table), count, total, max_views, block, grid, ctx->stream);
+    launch_solve_batched(bp<SolveScene>(ctx->solve_table), count, total, max_views, block, grid,
+                         ctx->d_stats + GSN_STAT_SKIPPED_NONFINITE, ctx->stream);
     HIP_TRY(ctx, hipGetLastError());
     return GSN_OK;
 }
@@ -588,7 +689,7 @@ gsn_status gsn_solve_tune(gsn_ctx* ctx, const gsn_solve_item* items, int32_t cou
             for (int rep = 0; rep < 3; ++rep) {  // the first run warms the caches
                 (void)hipEventRecord(e0, ctx->stream);
                 launch_solve_batched(bp<SolveScene>(ctx->solve_table), count, total, max_views, blocks[bi], grid,
-                                     ctx->stream);
+                                     ctx->d_stats + GSN_STAT_SKIPPED_NONFINITE, ctx->stream);
                 (void)hipEventRecord(e1, ctx->stream);
                 hipError_t e = hipEventSynchronize(e1);
                 if (e != hipSuccess) {
@@ -642,7 +743,8 @@ gsn_status gsn_solve_graph_create(gsn_ctx* ctx, const gsn_solve_item* items, int
     if (e == hipSuccess) {
         int block, grid;
         default_solve_shape(ctx, block, grid);
-        launch_solve_batched(bp<SolveScene>(gr->table), count, total, max_views, block, grid, cs);
+        launch_solve_batched(bp<SolveScene>(gr->table), count, total, max_views, block, grid,
+                             ctx->d_stats + GSN_STAT_SKIPPED_NONFINITE, cs);
         hipError_t el = hipGetLastError();
         e = hipStreamEndCapture(cs, &gr->graph);
         if (e == hipSuccess) e = el;
@@ -660,8 +762,65 @@ gsn_status gsn_solve_graph_create(gsn_ctx* ctx, const gsn_solve_item* items, int
 gsn_status gsn_graph_launch(gsn_ctx* ctx, gsn_graph* gr) {
     if (!ctx || !gr || !gr->exec) return fail(ctx, GSN_E_INVALID, "null graph");
     HIP_TRY(ctx, hipSetDevice(ctx->device));
-    StageTimer st_(ctx, GSN_STAGE_SOLVE);
-    HIP_TRY(ctx, hipGraphLaunch(gr->exec, ctx->stream));
+    if (ctx->capturing) return fail(ctx, GSN_E_INVALID, "graph launch while capturing");
+    if (gr->stage >= 0) {
+        StageTimer st_(ctx, gr->stage);
+        HIP_TRY(ctx, hipGraphLaunch(gr->exec, ctx->stream));
+    } else {
+        // a captured sequence of calls spans every stage: it is not timed by stage
+        HIP_TRY(ctx, hipGraphLaunch(gr->exec, ctx->stream));
+    }
+    return GSN_OK;
+}
+
+gsn_status gsn_capture_begin(gsn_ctx* ctx) {
+    if (!ctx) return GSN_E_INVALID;
+    if (ctx->capturing) return fail(ctx, GSN_E_INVALID, "the context is already capturing");
+    if (t_capturing) return fail(ctx, GSN_E_INVALID, "another context is capturing on this thread");
+    HIP_TRY(ctx, hipSetDevice(ctx->device));
+    if (!ctx->cap_stream) HIP_TRY(ctx, hipStreamCreateWithFlags(&ctx->cap_stream, hipStreamNonBlocking));
+    // what the caller queued so far finishes first; the graph's work is ordered by its launch
+    HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+    HIP_TRY(ctx, hipStreamBeginCapture(ctx->cap_stream, hipStreamCaptureModeThreadLocal));
+    ctx->user_stream = ctx->stream;
+    ctx->stream = ctx->cap_stream;
+    ctx->capturing = true;
+    ctx->capture_failed = false;
+    t_capturing = true;
+    return GSN_OK;
+}
+
+gsn_status gsn_capture_end(gsn_ctx* ctx, gsn_graph** out) {
+    if (!ctx || !out) return fail(ctx, GSN_E_INVALID, "null argument");
+    *out = nullptr;
+    if (!ctx->capturing) return fail(ctx, GSN_E_INVALID, "the context is not capturing");
+    hipGraph_t graph = nullptr;
+    const hipError_t e = hipStreamEndCapture(ctx->cap_stream, &graph);
+    ctx->stream = ctx->user_stream;
+    ctx->user_stream = nullptr;
+    ctx->capturing = false;
+    t_capturing = false;
+    const bool failed = ctx->capture_failed;
+    ctx->capture_failed = false;
+    if (e != hipSuccess || failed || !graph) {
+        if (graph) (void)hipGraphDestroy(graph);
+        if (e != hipSuccess) return fail(ctx, GSN_E_HIP, "graph capture: %s", hipGetErrorString(e));
+        return fail(ctx, GSN_E_INVALID, "a call failed while capturing: no graph");
+    }
+    gsn_graph* gr = new (std::nothrow) gsn_graph();
+    if (!gr) {
+        (void)hipGraphDestroy(graph);
+        return fail(ctx, GSN_E_NOMEM, "graph allocation failed");
+    }
+    gr->graph = graph;
+    gr->stage = -1;
+    const hipError_t ei = hipGraphInstantiate(&gr->exec, graph, nullptr, nullptr, 0);
+    if (ei != hipSuccess) {
+        (void)hipGraphDestroy(graph);
+        delete gr;
+        return fail(ctx, GSN_E_HIP, "graph instantiation: %s", hipGetErrorString(ei));
+    }
+    *out = gr;
     return GSN_OK;
 }
 
@@ -686,7 +845,7 @@ gsn_status gsn_apply_step(gsn_ctx* ctx, gsn_gaussians* g, const gsn_steps* st, c
     if (st->n != g->n || st->sh_degree != g->sh_degree) return fail(ctx, GSN_E_SHAPE, "steps do not match gaussians");
     HIP_TRY(ctx, hipSetDevice(ctx->device));
     StageTimer st_(ctx, GSN_STAGE_APPLY);
-    launch_apply(*g, *st, *o, d_scale, group_mask, ctx->stream);
+    launch_apply(*g, *st, *o, d_scale, group_mask, prof_counts(ctx), ctx->stream);
     HIP_TRY(ctx, hipGetLastError());
     return GSN_OK;
 }
@@ -733,8 +892,8 @@ gsn_status gsn_step_features(gsn_ctx* ctx, const gsn_gaussians* g, const gsn_cam
     return GSN_OK;
 }
 
-gsn_status gsn_step_labels(gsn_ctx* ctx, const gsn_steps* prim, const gsn_steps* aug, float* d_label,
-                           float* d_mask) {
+gsn_status gsn_step_labels(gsn_ctx* ctx, const gsn_steps* prim, const gsn_steps* aug, const uint8_t* d_ok,
+                           const float* d_alpha, float* d_label, float* d_mask, double* d_err) {
     if (!ctx || !prim || !aug) return fail(ctx, GSN_E_INVALID, "null argument");
     if (prim->n != aug->n || prim->sh_degree != aug->sh_degree) return fail(ctx, GSN_E_SHAPE, "steps differ in shape");
     if (prim->n < 0 || prim->sh_degree < 0 || prim->sh_degree > 3) return fail(ctx, GSN_E_SHAPE, "bad steps shape");
@@ -742,7 +901,9 @@ gsn_status gsn_step_labels(gsn_ctx* ctx, const gsn_steps* prim, const gsn_steps*
         return fail(ctx, GSN_E_INVALID, "null device array");
     HIP_TRY(ctx, hipSetDevice(ctx->device));
     const int K = (prim->sh_degree + 1) * (prim->sh_degree + 1);
-    launch_labels(prim->n, K, prim->d_data, prim->d_flags, aug->d_data, d_label, d_mask, ctx->stream);
+    if (d_alpha && d_err) HIP_TRY(ctx, buf_reserve(ctx->label_part, (size_t)2 * std::max(label_blocks(prim->n), 1) * 8));
+    launch_labels(prim->n, K, prim->d_data, prim->d_flags, aug->d_data, d_ok, d_alpha, d_label, d_mask,
+                  bp<double>(ctx->label_part), d_err, ctx->stream);
     HIP_TRY(ctx, hipGetLastError());
     return GSN_OK;
 }
@@ -758,12 +919,12 @@ gsn_status gsn_mlp_reset(gsn_ctx* ctx, gsn_mlp* mlp) {
 }
 
 gsn_status gsn_mlp_infer(gsn_ctx* ctx, const gsn_mlp* mlp, int32_t n, const float* d_feat, const uint8_t* d_ok,
-                         float* d_alpha) {
+                         float* d_alpha, uint32_t* d_out_of_range) {
     if (!ctx || !mlp || !mlp->d_half) return fail(ctx, GSN_E_INVALID, "null argument");
     if (n < 0) return fail(ctx, GSN_E_INVALID, "n < 0");
     if (n > 0 && (!d_feat || !d_ok || !d_alpha)) return fail(ctx, GSN_E_INVALID, "null device array");
     HIP_TRY(ctx, hipSetDevice(ctx->device));
-    launch_mlp_infer(mlp->d_half, n, d_feat, d_ok, d_alpha, ctx->stream);
+    launch_mlp_infer(mlp->d_half, n, d_feat, d_ok, d_alpha, d_out_of_range, ctx->stream);
     HIP_TRY(ctx, hipGetLastError());
     return GSN_OK;
 }
@@ -867,9 +1028,25 @@ gsn_status gsn_camera_knn(const double* c, int32_t ncam, const double* sc, int32
     return GSN_OK;
 }
 
+// The pair count of the frame's last render (read from the device for reserved frames).
+static gsn_status frame_pairs(gsn_ctx* ctx, const gsn_frame* f, int64_t* out) {
+    *out = f->pairs;
+    if (f->pairs >= 0) return GSN_OK;
+    HIP_TRY(ctx, hipSetDevice(ctx->device));
+    uint32_t live = 0;
+    HIP_TRY(ctx, hipMemcpyAsync(f->h_total, bp<uint32_t>(f->total) + 1, 4, hipMemcpyDeviceToHost, ctx->stream));
+    HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+    live = *f->h_total;
+    *out = live;
+    return GSN_OK;
+}
+
 gsn_status gsn_frame_info(gsn_ctx* ctx, const gsn_frame* f, int64_t* pairs, int32_t* tx, int32_t* ty) {
     if (!ctx || !f) return GSN_E_INVALID;
-    if (pairs) *pairs = f->pairs;
+    if (pairs) {
+        gsn_status r = frame_pairs(ctx, f, pairs);
+        if (r != GSN_OK) return r;
+    }
     if (tx) *tx = f->tiles_x;
     if (ty) *ty = f->tiles_y;
     return GSN_OK;
@@ -883,7 +1060,12 @@ gsn_status gsn_frame_lists(gsn_ctx* ctx, const gsn_frame* f, uint32_t* d_ranges,
     hipStream_t s = ctx->stream;
     const size_t tiles = (size_t)f->tiles_x * f->tiles_y, npx = (size_t)f->W * f->H;
     if (d_ranges) HIP_TRY(ctx, hipMemcpyAsync(d_ranges, f->ranges.p, tiles * 8, hipMemcpyDeviceToDevice, s));
-    if (d_ids && f->pairs) HIP_TRY(ctx, hipMemcpyAsync(d_ids, f->pv_a.p, (size_t)f->pairs * 4, hipMemcpyDeviceToDevice, s));
+    int64_t pairs = 0;
+    if (d_ids) {
+        gsn_status r = frame_pairs(ctx, f, &pairs);
+        if (r != GSN_OK) return r;
+    }
+    if (d_ids && pairs) HIP_TRY(ctx, hipMemcpyAsync(d_ids, f->pv_a.p, (size_t)pairs * 4, hipMemcpyDeviceToDevice, s));
     if (d_ncontrib) HIP_TRY(ctx, hipMemcpyAsync(d_ncontrib, f->ncontrib.p, npx * 4, hipMemcpyDeviceToDevice, s));
     if ((d_depth_bits || d_rect) && f->n > 0) {
         // depth keys were sorted in place; recompute the per-kernel view from the rect/keys copies

@@ -241,7 +241,7 @@ __global__ __launch_bounds__(GSN_BLOCK, 3) void raster_bwd_kernel(
     float T = 1.f;
     double Ca0 = 0.0, Ca1 = 0.0, Ca2 = 0.0;
     const float fpx = (float)px, fpy = (float)py;
-    uint32_t n_eval = 0, n_act = 0, n_part = 0;
+    uint32_t n_eval = 0, n_act = 0, n_part = 0, n_stage = 0;
     for (uint32_t base = rg.x; base < end; base += GSN_BLOCK) {
         const int bcnt = (int)min((uint32_t)GSN_BLOCK, end - base);
         // stage the batch: one entry per thread, its slot and its band mask
@@ -249,6 +249,7 @@ __global__ __launch_bounds__(GSN_BLOCK, 3) void raster_bwd_kernel(
         for (int w = 0; w < NW; ++w) s_mask[tid][w] = 0ull;
         uint32_t bandmask = 0;
         if (tid < bcnt) {
+            ++n_stage;
             const uint32_t id = ids[base + tid];
             const float4 a = rec[id], b = rec[n + id], c4 = rec[2 * (size_t)n + id];
             r_a[tid] = a;
@@ -479,17 +480,19 @@ __global__ __launch_bounds__(GSN_BLOCK, 3) void raster_bwd_kernel(
         }
     }
     if (counts) {
-        __shared__ unsigned long long s_cnt[3];
-        if (tid == 0) s_cnt[0] = s_cnt[1] = s_cnt[2] = 0;
+        __shared__ unsigned long long s_cnt[4];
+        if (tid == 0) s_cnt[0] = s_cnt[1] = s_cnt[2] = s_cnt[3] = 0;
         __syncthreads();
         atomicAdd(&s_cnt[0], (unsigned long long)n_eval);
         atomicAdd(&s_cnt[1], (unsigned long long)n_act);
         atomicAdd(&s_cnt[2], (unsigned long long)n_part);
+        atomicAdd(&s_cnt[3], (unsigned long long)n_stage);
         __syncthreads();
         if (tid == 0) {
             atomicAdd(&counts[GSN_COUNT_BWD_EVALS], s_cnt[0]);
             atomicAdd(&counts[GSN_COUNT_BWD_ACTIVE], s_cnt[1]);
             atomicAdd(&counts[GSN_COUNT_PARTIALS], s_cnt[2]);
+            atomicAdd(&counts[GSN_COUNT_BWD_STAGED], s_cnt[3]);
         }
     }
 }

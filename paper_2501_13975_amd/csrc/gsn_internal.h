@@ -27,7 +27,13 @@ constexpr int GSN_MASK_BATCHES = 8;
 struct gsn_frame {
     bool rendered = false;
     int n = 0, K = 0, W = 0, H = 0, tiles_x = 0, tiles_y = 0;
+    // pair count of the last render when known on the host (growing mode), -1 in reserved mode
+    // (then it lives only in total[1] on the device)
     int64_t pairs = 0;
+    // reserved mode (gsn_frame_reserve): capacities the buffers were sized for; cap_pairs == 0 means
+    // growing mode (buffers sized from the pair count read back after the depth sort)
+    int64_t cap_pairs = 0;
+    int cap_n = 0, cap_W = 0, cap_H = 0;
     DevCam cam{};
     DevRenderOpts ro{};
     // per kernel
@@ -61,7 +67,7 @@ struct gsn_frame {
     DevBuf zsum;        // double [n][GSN_NZ] per-kernel sums of the pair partials
     DevBuf zstats;      // float [GSN_NZ][n], optional debug copy
     DevBuf loss_part;   // double [2][nblocks]
-    // sort / scan scratch
+    // sort / scan scratch; total: u32 [0] scanned pair total, [1] live pair count of the render
     DevBuf hist, scan_tmp, total;
     uint32_t* h_total = nullptr;  // pinned host word
 };
@@ -80,9 +86,10 @@ struct gsn_ctx {
     std::vector<ProfRec> recs;
     std::vector<hipEvent_t> pool;
     unsigned long long* d_counts = nullptr;  // GSN_COUNT_N device counters
-    int64_t pairs_counted = 0;
-    // gradient partials of gsn_mlp_train_step
-    DevBuf mlp_part, mlp_stat;
+    // GSN_STAT_N device counters read and cleared by gsn_sync_status (always gathered)
+    unsigned long long* d_stats = nullptr;
+    // gradient partials of gsn_mlp_train_step, error partials of gsn_step_labels
+    DevBuf mlp_part, mlp_stat, label_part;
     // batched solve: scene table and the tuned launch shape (0 = not tuned)
     DevBuf solve_table;
     int solve_block = 0, solve_grid = 0;
@@ -90,12 +97,17 @@ struct gsn_ctx {
     DevBuf gram;
     // this device's fixed scratch array of gsn_local_newton_solve_noalloc ([10][GSN_NOALLOC_MAX_N] floats)
     float* noalloc_gram = nullptr;
+    // graph capture (gsn_capture_begin / end): the calls between them are recorded on cap_stream,
+    // the library's own stream, in place of the caller's
+    bool capturing = false, capture_failed = false;
+    hipStream_t cap_stream = nullptr, user_stream = nullptr;
 };
 
 struct gsn_graph {
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
     DevBuf table;
+    int stage = GSN_STAGE_SOLVE;  // profiler stage of a replay, -1: not timed (a captured sweep)
 };
 
 // Brackets one stage with events when profiling is on.
@@ -110,23 +122,35 @@ inline unsigned long long* prof_counts(const gsn_ctx* c) { return c->prof ? c->d
 // ---- launchers (render.hip)
 void launch_fill_u32(uint32_t* p, uint32_t v, size_t n, hipStream_t s);
 void launch_fill_f32(float* p, float v, size_t n, hipStream_t s);
+// culled: device counter of kernels culled for non-finite attributes or colour
 void launch_preprocess(const gsn_gaussians& g, const DevCam& cam, const DevRenderOpts& ro, float4* rec,
-                       uint2* rect, uint32_t* depth_key, uint32_t* ids, uint32_t* ntiles, hipStream_t s);
-// stable LSD radix sort of (key, val) pairs on bits [bit_lo, bit_hi); result lands in (k0, v0)
-hipError_t radix_sort_pairs(uint32_t* k0, uint32_t* v0, uint32_t* k1, uint32_t* v1, uint32_t n, int bit_lo,
-                            int bit_hi, DevBuf& hist, DevBuf& scan_tmp, hipStream_t s);
+                       uint2* rect, uint32_t* depth_key, uint32_t* ids, uint32_t* ntiles, unsigned long long* culled,
+                       hipStream_t s);
+// stable LSD radix sort of (key, val) pairs on bits [bit_lo, bit_hi); result lands in (k0, v0).  The
+// launches are sized for n keys; with d_n, only the first min(*d_n, n) keys (read on the device) are
+// sorted.  hist must hold radix_hist_bytes(n) bytes.
+hipError_t radix_sort_pairs(uint32_t* k0, uint32_t* v0, uint32_t* k1, uint32_t* v1, uint32_t n, const uint32_t* d_n,
+                            int bit_lo, int bit_hi, DevBuf& hist, hipStream_t s);
+void launch_copy_u32(uint32_t* dst, const uint32_t* src, size_t n, hipStream_t s);
+// d_pairs[1] = d_pairs[0] when it is at most cap, else 0 with the overflow recorded in stats
+void launch_pair_capacity(uint32_t* d_pairs, uint32_t cap, unsigned long long* stats, unsigned long long* prof,
+                          hipStream_t s);
+// p[0 .. ceil(*d_count / per_word)) = v, at most cap words
+void launch_fill_u32_dev(uint32_t* p, uint32_t v, const uint32_t* d_count, uint32_t per_word, size_t cap,
+                         hipStream_t s);
 // bytes of scan scratch for scanning up to n values (and the 256 x blocks radix histograms of n keys)
 size_t scan_tmp_bytes(uint32_t n);
 // exclusive scan of n u32 values into out; *d_total receives the sum
 hipError_t exclusive_scan_u32(const uint32_t* in, uint32_t* out, uint32_t n, uint32_t* d_total,
                               DevBuf& scan_tmp, hipStream_t s);
 void launch_gather_u32(const uint32_t* src, const uint32_t* idx, uint32_t* dst, uint32_t n, hipStream_t s);
-void launch_emit_pairs(const uint32_t* sorted_ids, const uint32_t* offsets, uint32_t n, uint32_t pairs,
-                       const uint2* rect, uint32_t tiles_x, uint32_t* keys, uint32_t* vals, uint32_t* pair_off,
-                       uint32_t* chunk_first, hipStream_t s);
+// pairs in depth order for the live count *d_pairs (launches sized for cap pairs)
+void launch_emit_pairs(const uint32_t* sorted_ids, const uint32_t* offsets, uint32_t n, const uint32_t* d_pairs,
+                       uint32_t cap, const uint2* rect, uint32_t tiles_x, uint32_t* keys, uint32_t* vals,
+                       uint32_t* pair_off, uint32_t* chunk_first, hipStream_t s);
 size_t emit_chunks(uint32_t pairs);
 size_t radix_hist_bytes(uint32_t n);
-void launch_tile_ranges(const uint32_t* keys, uint32_t pairs, uint2* ranges, hipStream_t s);
+void launch_tile_ranges(const uint32_t* keys, const uint32_t* d_pairs, uint32_t cap, uint2* ranges, hipStream_t s);
 // tiles ordered by a length, longest first (coarse: four buckets per octave, any order within one): the
 // list lengths of ranges when lens is null, else lens
 void launch_tile_order(const uint2* ranges, const uint32_t* lens, int tiles, uint32_t* order, hipStream_t s);
@@ -148,10 +172,13 @@ void launch_reduce_chain(const gsn_frame& f, const gsn_gaussians& g, float weigh
                          const gsn_blocks& b, float* zstats_out, hipStream_t s);
 
 // ---- launchers (solve.hip)
+// nonfinite: device counter of kernels skipped for non-finite blocks or steps (always counted);
+// prof: the profile counters (solve events, GSN_COUNT_SOLVE_*), or NULL when not profiling
 void launch_solve(const gsn_gaussians& g, const DevCam& cam, float kappa, const gsn_blocks& b,
-                  const gsn_solve_opts& o, const gsn_steps& st, hipStream_t s);
+                  const gsn_solve_opts& o, const gsn_steps& st, unsigned long long* nonfinite,
+                  unsigned long long* prof, hipStream_t s);
 void launch_apply(const gsn_gaussians& g, const gsn_steps& st, const gsn_solve_opts& o, const float* scale,
-                  uint32_t mask, hipStream_t s);
+                  uint32_t mask, unsigned long long* prof, hipStream_t s);
 void launch_first_order(const gsn_gaussians& g, const gsn_blocks& b, const gsn_first_order_opts& fo, float c1,
                         float c2, float scale_floor, float opac_eps, float* state, uint32_t mask, hipStream_t s);
 // One scene of a batched solve (device-side table entry).
@@ -169,7 +196,7 @@ struct SolveScene {
     long long first;  // index of the scene's first kernel in the concatenated index space
 };
 void launch_solve_batched(const SolveScene* d_scenes, int count, long long total, int max_views, int block,
-                          int grid, hipStream_t s);
+                          int grid, unsigned long long* nonfinite, hipStream_t s);
 void launch_sh_gram(const float* blk, int n, int K, int V, float* gram, hipStream_t s);
 // Devices whose no-allocation scratch address is cached.
 #define GSN_MAX_DEVICES 64
@@ -177,13 +204,16 @@ void launch_sh_gram(const float* blk, int n, int K, int V, float* gram, hipStrea
 // (looked up once per device with hipGetSymbolAddress, then cached).
 hipError_t solve_scratch_address(int device, float** out);
 void launch_solve_mixed(const gsn_gaussians& g, const DevCam& cam, float kappa, const gsn_blocks& b,
-                        const gsn_solve_opts& o, const float* gram, const gsn_steps& st, unsigned long long* n_fp64,
-                        hipStream_t s);
+                        const gsn_solve_opts& o, const float* gram, const gsn_steps& st, unsigned long long* nonfinite,
+                        unsigned long long* prof, hipStream_t s);
 void launch_features(const gsn_gaussians& g, const DevCam& cam, float kappa, const gsn_blocks& b,
                      const gsn_solve_opts& o, float* feat, uint8_t* ok, hipStream_t s);
-void launch_labels(int n, int K, const float* sp, const int32_t* fp, const float* sa, float* label, float* mask,
-                   hipStream_t s);
-void launch_mlp_infer(const uint16_t* wh, int n, const float* feat, const uint8_t* ok, float* out, hipStream_t s);
+int label_blocks(int n);
+// part: double [2][label_blocks(n)] scratch, used when alpha and err are given (err[0..1] +=)
+void launch_labels(int n, int K, const float* sp, const int32_t* fp, const float* sa, const uint8_t* ok,
+                   const float* alpha, float* label, float* mask, double* part, double* err, hipStream_t s);
+void launch_mlp_infer(const uint16_t* wh, int n, const float* feat, const uint8_t* ok, float* out,
+                      uint32_t* n_out_of_range, hipStream_t s);
 int mlp_grad_blocks(int n);
 void launch_mlp_train(gsn_mlp& mlp, int n, const float* feat, const float* label, const float* mask, float* part,
                       double* stat, const gsn_adam_opts& a, float* grad_out, double* loss, hipStream_t s);

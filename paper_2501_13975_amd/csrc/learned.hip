@@ -52,8 +52,9 @@ __global__ __launch_bounds__(128) void features_kernel(const float* __restrict__
     float f[NI];
 #pragma unroll
     for (int i = 0; i < NI; ++i) f[i] = 0.f;
-    bool in_range = B(29) > 0.0;
-    if (in_range) {
+    const bool vis = B(29) > 0.0;
+    bool in_range = vis;
+    if (vis) {
         const double abs_scale = 1.0 / (3.0 * (double)o.npix_primary);
         Reduced R;
         reduce_systems(pos, rot, scale, opac, n, k, c, kappa, B, o, abs_scale, R);
@@ -79,35 +80,77 @@ __global__ __launch_bounds__(128) void features_kernel(const float* __restrict__
     }
 #pragma unroll
     for (int i = 0; i < NI; ++i) feat[(size_t)i * N + k] = f[i];
-    ok[k] = in_range ? 1 : 0;
+    ok[k] = !vis ? GSN_FEAT_HIDDEN : in_range ? GSN_FEAT_OK : GSN_FEAT_OUT_OF_RANGE;
 }
 
-__global__ __launch_bounds__(256) void labels_kernel(int n, int K, const float* __restrict__ sp,
-                                                      const int32_t* __restrict__ fp, const float* __restrict__ sa,
-                                                      float* __restrict__ label, float* __restrict__ mask) {
+constexpr int LABEL_BLOCK = 256;
+
+// Labels of every kernel, and per workgroup the sums of mask |alpha - label| and of the mask
+// (part[2 b], part[2 b + 1]) when alpha is given.
+__global__ __launch_bounds__(LABEL_BLOCK) void labels_kernel(int n, int K, const float* __restrict__ sp,
+                                                              const int32_t* __restrict__ fp,
+                                                              const float* __restrict__ sa,
+                                                              const uint8_t* __restrict__ ok,
+                                                              const float* __restrict__ alpha,
+                                                              float* __restrict__ label, float* __restrict__ mask,
+                                                              double* __restrict__ part) {
     const int k = blockIdx.x * blockDim.x + threadIdx.x;
-    if (k >= n) return;
-    const size_t N = (size_t)n;
-    const bool vis = fp[k] != -2;
-    const int lo[NO] = {0, 3, 7, 10, GSN_STEP_BASE};
-    const int hi[NO] = {3, 4, 10, 11, GSN_STEP_BASE + 3 * K};
+    double err = 0.0, cnt = 0.0;
+    if (k < n) {
+        const size_t N = (size_t)n;
+        // a kernel the solve stepped (decisions >= -1) whose features were in range
+        const bool use = fp[k] >= -1 && (!ok || ok[k] == GSN_FEAT_OK);
+        const int lo[NO] = {0, 3, 7, 10, GSN_STEP_BASE};
+        const int hi[NO] = {3, 4, 10, 11, GSN_STEP_BASE + 3 * K};
 #pragma unroll
-    for (int gi = 0; gi < NO; ++gi) {
-        double pp = 0.0, ap = 0.0;
-        for (int r = lo[gi]; r < hi[gi]; ++r) {
-            const double p = sp[(size_t)r * N + k], a = sa[(size_t)r * N + k];
-            pp += p * p;
-            ap += a * p;
+        for (int gi = 0; gi < NO; ++gi) {
+            double pp = 0.0, ap = 0.0;
+            for (int r = lo[gi]; r < hi[gi]; ++r) {
+                const double p = sp[(size_t)r * N + k], a = sa[(size_t)r * N + k];
+                pp += p * p;
+                ap += a * p;
+            }
+            const bool good = use && pp > 1e-30;
+            const float lab = good ? (float)fmin(1.5, fmax(0.0, ap / pp)) : 0.f;
+            label[(size_t)gi * N + k] = lab;
+            mask[(size_t)gi * N + k] = good ? 1.f : 0.f;
+            if (good && alpha) {
+                err += fabs((double)alpha[(size_t)gi * N + k] - (double)lab);
+                cnt += 1.0;
+            }
         }
-        const bool good = vis && pp > 1e-30;
-        label[(size_t)gi * N + k] = good ? (float)fmin(1.5, fmax(0.0, ap / pp)) : 0.f;
-        mask[(size_t)gi * N + k] = good ? 1.f : 0.f;
     }
+    if (!part) return;  // uniform across the launch
+    __shared__ double s_e[LABEL_BLOCK], s_c[LABEL_BLOCK];
+    s_e[threadIdx.x] = err;
+    s_c[threadIdx.x] = cnt;
+    __syncthreads();
+    for (int w = LABEL_BLOCK / 2; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) {
+            s_e[threadIdx.x] += s_e[threadIdx.x + w];
+            s_c[threadIdx.x] += s_c[threadIdx.x + w];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        part[2 * blockIdx.x] = s_e[0];
+        part[2 * blockIdx.x + 1] = s_c[0];
+    }
+}
+
+// out[0] += sum of part[2 b], out[1] += sum of part[2 b + 1], in block order (one thread per sum).
+__global__ void label_error_sum_kernel(const double* __restrict__ part, int nblocks, double* __restrict__ out) {
+    const int t = threadIdx.x;
+    if (t >= 2) return;
+    double a = 0.0;
+    for (int b = 0; b < nblocks; ++b) a += part[2 * b + t];
+    out[t] += a;
 }
 
 __global__ __launch_bounds__(256) void mlp_infer_kernel(const __half* __restrict__ wh, int n,
                                                          const float* __restrict__ feat,
-                                                         const uint8_t* __restrict__ ok, float* __restrict__ out) {
+                                                         const uint8_t* __restrict__ ok, float* __restrict__ out,
+                                                         uint32_t* __restrict__ n_out_of_range) {
     __shared__ float w[NP];
     for (int i = threadIdx.x; i < NP; i += blockDim.x) w[i] = __half2float(wh[i]);
     __syncthreads();
@@ -128,9 +171,10 @@ __global__ __launch_bounds__(256) void mlp_infer_kernel(const __half* __restrict
 #pragma unroll
         for (int g = 0; g < NO; ++g) z2[g] += w[OFF_W2 + g * NH + j] * h;
     }
-    const bool use = ok[k] != 0;
+    const bool use = ok[k] == GSN_FEAT_OK;
 #pragma unroll
     for (int g = 0; g < NO; ++g) out[(size_t)g * N + k] = use ? 1.5f / (1.f + expf(-z2[g])) : 0.f;
+    if (n_out_of_range && ok[k] == GSN_FEAT_OUT_OF_RANGE) atomicAdd(n_out_of_range, 1u);
 }
 
 // Per-block gradient partials (not yet divided by the number of labelled entries): part[b][p],
@@ -274,15 +318,21 @@ void launch_features(const gsn_gaussians& g, const DevCam& cam, float kappa, con
                                                       b.d_data, o, feat, ok);
 }
 
-void launch_labels(int n, int K, const float* sp, const int32_t* fp, const float* sa, float* label, float* mask,
-                   hipStream_t s) {
+int label_blocks(int n) { return (n + LABEL_BLOCK - 1) / LABEL_BLOCK; }
+
+void launch_labels(int n, int K, const float* sp, const int32_t* fp, const float* sa, const uint8_t* ok,
+                   const float* alpha, float* label, float* mask, double* part, double* err, hipStream_t s) {
     if (n == 0) return;
-    labels_kernel<<<(n + 255) / 256, 256, 0, s>>>(n, K, sp, fp, sa, label, mask);
+    const int nb = label_blocks(n);
+    labels_kernel<<<nb, LABEL_BLOCK, 0, s>>>(n, K, sp, fp, sa, ok, alpha, label, mask, alpha && err ? part : nullptr);
+    if (alpha && err) label_error_sum_kernel<<<1, 64, 0, s>>>(part, nb, err);
 }
 
-void launch_mlp_infer(const uint16_t* wh, int n, const float* feat, const uint8_t* ok, float* out, hipStream_t s) {
+void launch_mlp_infer(const uint16_t* wh, int n, const float* feat, const uint8_t* ok, float* out,
+                      uint32_t* n_out_of_range, hipStream_t s) {
     if (n == 0) return;
-    mlp_infer_kernel<<<(n + 255) / 256, 256, 0, s>>>(reinterpret_cast<const __half*>(wh), n, feat, ok, out);
+    mlp_infer_kernel<<<(n + 255) / 256, 256, 0, s>>>(reinterpret_cast<const __half*>(wh), n, feat, ok, out,
+                                                     n_out_of_range);
 }
 
 int mlp_grad_blocks(int n) { return (n + GRAD_SAMPLES - 1) / GRAD_SAMPLES; }

@@ -114,17 +114,27 @@ __global__ __launch_bounds__(kThreads) void preprocess_kernel(
     const float* __restrict__ pos, const float* __restrict__ rot, const float* __restrict__ scale,
     const float* __restrict__ opac, const float* __restrict__ sh, int n, int K, DevCam cam, DevRenderOpts ro,
     float4* __restrict__ rec, uint2* __restrict__ rect, uint32_t* __restrict__ depth_key,
-    uint32_t* __restrict__ ids, uint32_t* __restrict__ ntiles) {
+    uint32_t* __restrict__ ids, uint32_t* __restrict__ ntiles, unsigned long long* __restrict__ culled) {
     const int k = blockIdx.x * blockDim.x + threadIdx.x;
     if (k >= n) return;
     const float px = pos[k], py = pos[n + k], pz = pos[2 * n + k];
-    const BinOut b = bin_spec(px, py, pz, rot[k], rot[n + k], rot[2 * n + k], rot[3 * n + k], scale[k],
-                              scale[n + k], scale[2 * n + k], cam, ro.kappa, ro.radius_sigma);
+    const float qw = rot[k], qx = rot[n + k], qy = rot[2 * n + k], qz = rot[3 * n + k];
+    const float s0 = scale[k], s1 = scale[n + k], s2 = scale[2 * n + k], sig = opac[k];
+    // a NaN or infinite attribute culls the kernel (x * 0 is NaN exactly for those x)
+    const bool finite = ((((px * 0.f + py * 0.f) + (pz * 0.f + qw * 0.f)) + ((qx * 0.f + qy * 0.f) + (qz * 0.f + s0 * 0.f))) +
+                         ((s1 * 0.f + s2 * 0.f) + sig * 0.f)) == 0.f;
     ids[k] = (uint32_t)k;
-    if (!b.vis) {
+    BinOut b;
+    b.vis = false;
+    if (finite) b = bin_spec(px, py, pz, qw, qx, qy, qz, s0, s1, s2, cam, ro.kappa, ro.radius_sigma);
+    else atomicAdd(culled, 1ull);
+    auto cull = [&]() {
         depth_key[k] = 0xffffffffu;
         ntiles[k] = 0;
         rect[k] = make_uint2(0, 0);
+    };
+    if (!b.vis) {
+        cull();
         return;
     }
     depth_key[k] = __float_as_uint(b.tz);
@@ -166,6 +176,11 @@ __global__ __launch_bounds__(kThreads) void preprocess_kernel(
         for (int ch = 0; ch < 3; ++ch) acc[ch] += y * (double)sh[((size_t)ch * K + i) * n + k];
     });
     const float col[3] = {(float)acc[0], (float)acc[1], (float)acc[2]};
+    if (!(((col[0] * 0.f + col[1] * 0.f) + col[2] * 0.f) == 0.f)) {  // a non-finite colour in this view
+        cull();
+        atomicAdd(culled, 1ull);
+        return;
+    }
     rec[k] = make_float4(mu_hi, mv_hi, (float)(1.0 / l1), (float)(1.0 / l2));
     rec[n + k] = make_float4((float)fc, (float)fs, opac[k], col[0]);
     rec[2 * (size_t)n + k] = make_float4(col[1], col[2], (float)(mu - (double)mu_hi), (float)(mv - (double)mv_hi));
@@ -285,10 +300,17 @@ __host__ __device__ inline uint32_t radix_tile(uint32_t n) {
     return (uint32_t)kThreads * (n <= kRsSmallN ? kRsItemsSmall : kRsItems);
 }
 
+// Key counts n_cap (the launch's size) or, when d_n is given, min(*d_n, n_cap) read on the device.
+__device__ __forceinline__ uint32_t live_count(uint32_t n_cap, const uint32_t* __restrict__ d_n) {
+    return d_n ? min(*d_n, n_cap) : n_cap;
+}
+
 template <int ITEMS>
-__global__ __launch_bounds__(kThreads) void radix_hist_kernel(const uint32_t* __restrict__ keys, uint32_t n,
-                                                               int shift, uint32_t nb, uint32_t* __restrict__ hist) {
+__global__ __launch_bounds__(kThreads) void radix_hist_kernel(const uint32_t* __restrict__ keys, uint32_t n_cap,
+                                                               const uint32_t* __restrict__ d_n, int shift,
+                                                               uint32_t nb, uint32_t* __restrict__ hist) {
     constexpr int TILE = kThreads * ITEMS;
+    const uint32_t n = live_count(n_cap, d_n);
     __shared__ uint32_t cnt[256];
     cnt[threadIdx.x] = 0;
     __syncthreads();
@@ -347,11 +369,13 @@ __global__ __launch_bounds__(kThreads) void radix_colscan_kernel(const uint32_t*
 // addresses of one digit's run (coalesced).
 template <int ITEMS>
 __global__ __launch_bounds__(kThreads) void radix_scatter_kernel(
-    const uint32_t* __restrict__ kin, const uint32_t* __restrict__ vin, uint32_t n, int shift, uint32_t nb,
-    const uint32_t* __restrict__ offs, const uint32_t* __restrict__ dtot, uint32_t* __restrict__ kout,
-    uint32_t* __restrict__ vout) {
+    const uint32_t* __restrict__ kin, const uint32_t* __restrict__ vin, uint32_t n_cap,
+    const uint32_t* __restrict__ d_n, int shift, uint32_t nb, const uint32_t* __restrict__ offs,
+    const uint32_t* __restrict__ dtot, uint32_t* __restrict__ kout, uint32_t* __restrict__ vout) {
     constexpr int NWV = kThreads / 64;
     constexpr int TILE = kThreads * ITEMS;
+    const uint32_t n = live_count(n_cap, d_n);
+    if ((size_t)blockIdx.x * TILE >= n) return;  // uniform: a workgroup past the live keys has nothing to place
     __shared__ uint32_t base_d[256], lstart[256];
     __shared__ uint32_t wpos[NWV][256];
     __shared__ uint32_t wsum[NWV];
@@ -440,6 +464,39 @@ __global__ __launch_bounds__(kThreads) void radix_scatter_kernel(
     }
 }
 
+// The pair count of a render against the frame's capacity: d_pairs[0] holds the scanned total;
+// d_pairs[1] receives the live count, the total when it fits and 0 (render nothing) when it does
+// not, in which case the overflow and the count needed are recorded.  One thread.
+__global__ void pair_capacity_kernel(uint32_t* __restrict__ d_pairs, uint32_t cap,
+                                     unsigned long long* __restrict__ stats, unsigned long long* __restrict__ prof) {
+    const uint32_t total = d_pairs[0];
+    const bool fits = total <= cap;
+    d_pairs[1] = fits ? total : 0u;
+    if (!fits) {
+        atomicAdd(&stats[GSN_STAT_PAIR_OVERFLOW], 1ull);
+        atomicMax(&stats[GSN_STAT_PAIRS_NEEDED], (unsigned long long)total);
+    }
+    if (prof && fits) atomicAdd(&prof[GSN_COUNT_PAIRS], (unsigned long long)total);
+}
+
+// p[0 .. ceil(*d_count / per_word)) = v, at most cap words (a fill sized on the device).
+__global__ void fill_u32_dev_kernel(uint32_t* __restrict__ p, uint32_t v, const uint32_t* __restrict__ d_count,
+                                    uint32_t per_word, size_t cap) {
+    const size_t n = min(cap, ((size_t)*d_count + per_word - 1) / per_word);
+    size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const size_t stride = (size_t)gridDim.x * blockDim.x;
+    for (; i < n; i += stride) p[i] = v;
+}
+
+// dst[0 .. min(*d_count, cap)) = src[...] (u32).
+__global__ void copy_u32_dev_kernel(uint32_t* __restrict__ dst, const uint32_t* __restrict__ src,
+                                    const uint32_t* __restrict__ d_count, size_t cap) {
+    const size_t n = d_count ? min(cap, (size_t)*d_count) : cap;
+    size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const size_t stride = (size_t)gridDim.x * blockDim.x;
+    for (; i < n; i += stride) dst[i] = src[i];
+}
+
 __global__ void gather_u32_kernel(const uint32_t* __restrict__ src, const uint32_t* __restrict__ idx,
                                   uint32_t* __restrict__ dst, uint32_t n) {
     const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -455,12 +512,14 @@ constexpr int kEmitChunk = 2048;
 // One thread per depth rank: the kernel's pair offset by id, and for every chunk whose first slot
 // falls in the rank's range, that rank (the ranges partition the slots, so each chunk's entry is
 // written once).
+// pairs: the live pair count (0 after a capacity overflow: then no chunk is emitted).
 __global__ void pair_off_kernel(const uint32_t* __restrict__ sorted_ids, const uint32_t* __restrict__ offsets,
-                                uint32_t n, uint32_t pairs, uint32_t* __restrict__ pair_off,
+                                uint32_t n, const uint32_t* __restrict__ d_pairs, uint32_t* __restrict__ pair_off,
                                 uint32_t* __restrict__ chunk_first) {
     const uint32_t r = blockIdx.x * blockDim.x + threadIdx.x;
     if (r >= n) return;
-    const uint32_t o0 = offsets[r], o1 = r + 1 < n ? offsets[r + 1] : pairs;
+    const uint32_t pairs = *d_pairs;
+    const uint32_t o0 = offsets[r], o1 = min(r + 1 < n ? offsets[r + 1] : pairs, pairs);
     pair_off[sorted_ids[r]] = o0;
     for (uint32_t c = (o0 + kEmitChunk - 1) / kEmitChunk; (size_t)c * kEmitChunk < o1; ++c) chunk_first[c] = r;
 }
@@ -469,16 +528,20 @@ __global__ void pair_off_kernel(const uint32_t* __restrict__ sorted_ids, const u
 // coalesced, and each thread finds the kernel of its slot by binary search over their offsets.
 // Kernel r (depth rank) owns slots [offsets[r], offsets[r] + ntiles) in row-major tile order.
 
+// The grid covers the pair capacity; chunks past the live pair count return at once.
 __global__ __launch_bounds__(kThreads) void emit_pairs_kernel(const uint32_t* __restrict__ sorted_ids,
                                                                const uint32_t* __restrict__ offsets, uint32_t n,
-                                                               uint32_t pairs, const uint2* __restrict__ rect,
+                                                               const uint32_t* __restrict__ d_pairs,
+                                                               const uint2* __restrict__ rect,
                                                                uint32_t tiles_x, uint32_t* __restrict__ keys,
                                                                uint32_t* __restrict__ vals,
                                                                const uint32_t* __restrict__ chunk_first) {
     __shared__ uint32_t s_off[kEmitChunk], s_id[kEmitChunk];
     __shared__ uint2 s_rect[kEmitChunk];
     __shared__ uint32_t s_r0, s_cnt;
+    const uint32_t pairs = *d_pairs;
     const uint32_t p0 = blockIdx.x * (uint32_t)kEmitChunk;
+    if (p0 >= pairs) return;  // uniform across the workgroup
     const uint32_t p1 = min(pairs, p0 + (uint32_t)kEmitChunk);
     if (threadIdx.x == 0) {
         // first and last ranks whose ranges meet [p0, p1): the rank owning p0, and the rank owning
@@ -486,7 +549,7 @@ __global__ __launch_bounds__(kThreads) void emit_pairs_kernel(const uint32_t* __
         // one pair each, so at most kEmitChunk ranks meet a chunk)
         const uint32_t r0 = chunk_first[blockIdx.x];
         uint32_t r1;
-        if (blockIdx.x + 1 < gridDim.x) {
+        if (p1 < pairs) {
             r1 = chunk_first[blockIdx.x + 1];
             if (offsets[r1] >= p1) --r1;
         } else {
@@ -523,8 +586,10 @@ __global__ __launch_bounds__(kThreads) void emit_pairs_kernel(const uint32_t* __
     }
 }
 
-__global__ void tile_ranges_kernel(const uint32_t* __restrict__ keys, uint32_t pairs, uint2* __restrict__ ranges) {
+__global__ void tile_ranges_kernel(const uint32_t* __restrict__ keys, const uint32_t* __restrict__ d_pairs,
+                                   uint2* __restrict__ ranges) {
     const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    const uint32_t pairs = *d_pairs;
     if (i >= pairs) return;
     const uint32_t k = keys[i];
     if (i == 0 || keys[i - 1] != k) ranges[k].x = i;
@@ -789,11 +854,12 @@ void launch_fill_f32(float* p, float v, size_t n, hipStream_t s) {
 }
 
 void launch_preprocess(const gsn_gaussians& g, const DevCam& cam, const DevRenderOpts& ro, float4* rec,
-                       uint2* rect, uint32_t* depth_key, uint32_t* ids, uint32_t* ntiles, hipStream_t s) {
+                       uint2* rect, uint32_t* depth_key, uint32_t* ids, uint32_t* ntiles, unsigned long long* culled,
+                       hipStream_t s) {
     if (g.n == 0) return;
     const int K = (g.sh_degree + 1) * (g.sh_degree + 1);
     preprocess_kernel<<<(g.n + kThreads - 1) / kThreads, kThreads, 0, s>>>(
-        g.d_pos, g.d_rot, g.d_scale, g.d_opac, g.d_sh, g.n, K, cam, ro, rec, rect, depth_key, ids, ntiles);
+        g.d_pos, g.d_rot, g.d_scale, g.d_opac, g.d_sh, g.n, K, cam, ro, rec, rect, depth_key, ids, ntiles, culled);
 }
 
 size_t scan_tmp_bytes(uint32_t n) {
@@ -809,32 +875,38 @@ hipError_t exclusive_scan_u32(const uint32_t* in, uint32_t* out, uint32_t n, uin
     return scan_rec(in, out, n, d_total, bp<uint32_t>(scan_tmp), words, s);
 }
 
-hipError_t radix_sort_pairs(uint32_t* k0, uint32_t* v0, uint32_t* k1, uint32_t* v1, uint32_t n, int bit_lo,
-                            int bit_hi, DevBuf& hist, DevBuf& scan_tmp, hipStream_t s) {
-    (void)scan_tmp;
+hipError_t radix_sort_pairs(uint32_t* k0, uint32_t* v0, uint32_t* k1, uint32_t* v1, uint32_t n, const uint32_t* d_n,
+                            int bit_lo, int bit_hi, DevBuf& hist, hipStream_t s) {
     if (n == 0) return hipSuccess;
     const uint32_t tile = radix_tile(n), nb = (n + tile - 1) / tile;
     const bool small = n <= kRsSmallN;
-    hipError_t e = buf_reserve(hist, radix_hist_bytes(n));
-    if (e != hipSuccess) return e;
+    if (hist.bytes < radix_hist_bytes(n)) return hipErrorInvalidValue;  // reserved by the caller
     uint32_t* h = bp<uint32_t>(hist);
     uint32_t* o = h + (size_t)256 * nb;
     uint32_t* dt = o + (size_t)256 * nb;
     int passes = 0;
     uint32_t *ka = k0, *va = v0, *kb = k1, *vb = v1;
     for (int shift = bit_lo; shift < bit_hi; shift += 8, ++passes) {
-        if (small) radix_hist_kernel<kRsItemsSmall><<<nb, kThreads, 0, s>>>(ka, n, shift, nb, h);
-        else radix_hist_kernel<kRsItems><<<nb, kThreads, 0, s>>>(ka, n, shift, nb, h);
+        if (small) radix_hist_kernel<kRsItemsSmall><<<nb, kThreads, 0, s>>>(ka, n, d_n, shift, nb, h);
+        else radix_hist_kernel<kRsItems><<<nb, kThreads, 0, s>>>(ka, n, d_n, shift, nb, h);
         radix_colscan_kernel<<<256, kThreads, 0, s>>>(h, nb, o, dt);
-        if (small) radix_scatter_kernel<kRsItemsSmall><<<nb, kThreads, 0, s>>>(ka, va, n, shift, nb, o, dt, kb, vb);
-        else radix_scatter_kernel<kRsItems><<<nb, kThreads, 0, s>>>(ka, va, n, shift, nb, o, dt, kb, vb);
+        if (small)
+            radix_scatter_kernel<kRsItemsSmall><<<nb, kThreads, 0, s>>>(ka, va, n, d_n, shift, nb, o, dt, kb, vb);
+        else
+            radix_scatter_kernel<kRsItems><<<nb, kThreads, 0, s>>>(ka, va, n, d_n, shift, nb, o, dt, kb, vb);
         uint32_t* t = ka; ka = kb; kb = t;
         t = va; va = vb; vb = t;
     }
     if (passes & 1) {
-        e = hipMemcpyAsync(k0, ka, (size_t)n * 4, hipMemcpyDeviceToDevice, s);
-        if (e == hipSuccess) e = hipMemcpyAsync(v0, va, (size_t)n * 4, hipMemcpyDeviceToDevice, s);
-        if (e != hipSuccess) return e;
+        // the result is in the second buffers: copy the live keys back with kernels (no copy nodes when a
+        // caller captures the stream)
+        if (d_n) {
+            copy_u32_dev_kernel<<<grid_for(n), kThreads, 0, s>>>(k0, ka, d_n, n);
+            copy_u32_dev_kernel<<<grid_for(n), kThreads, 0, s>>>(v0, va, d_n, n);
+        } else {
+            launch_copy_u32(k0, ka, n, s);
+            launch_copy_u32(v0, va, n, s);
+        }
     }
     return hipGetLastError();
 }
@@ -850,19 +922,33 @@ size_t radix_hist_bytes(uint32_t n) {
     return ((size_t)256 * nb * 2 + 256) * 4;
 }
 
-void launch_emit_pairs(const uint32_t* sorted_ids, const uint32_t* offsets, uint32_t n, uint32_t pairs,
-                       const uint2* rect, uint32_t tiles_x, uint32_t* keys, uint32_t* vals, uint32_t* pair_off,
-                       uint32_t* chunk_first, hipStream_t s) {
+void launch_emit_pairs(const uint32_t* sorted_ids, const uint32_t* offsets, uint32_t n, const uint32_t* d_pairs,
+                       uint32_t cap, const uint2* rect, uint32_t tiles_x, uint32_t* keys, uint32_t* vals,
+                       uint32_t* pair_off, uint32_t* chunk_first, hipStream_t s) {
     if (n == 0) return;
-    pair_off_kernel<<<(n + kThreads - 1) / kThreads, kThreads, 0, s>>>(sorted_ids, offsets, n, pairs, pair_off,
+    pair_off_kernel<<<(n + kThreads - 1) / kThreads, kThreads, 0, s>>>(sorted_ids, offsets, n, d_pairs, pair_off,
                                                                        chunk_first);
-    if (pairs)
-        emit_pairs_kernel<<<(uint32_t)emit_chunks(pairs), kThreads, 0, s>>>(sorted_ids, offsets, n, pairs, rect,
-                                                                          tiles_x, keys, vals, chunk_first);
+    if (cap)
+        emit_pairs_kernel<<<(uint32_t)emit_chunks(cap), kThreads, 0, s>>>(sorted_ids, offsets, n, d_pairs, rect,
+                                                                        tiles_x, keys, vals, chunk_first);
 }
 
-void launch_tile_ranges(const uint32_t* keys, uint32_t pairs, uint2* ranges, hipStream_t s) {
-    if (pairs) tile_ranges_kernel<<<(pairs + kThreads - 1) / kThreads, kThreads, 0, s>>>(keys, pairs, ranges);
+void launch_tile_ranges(const uint32_t* keys, const uint32_t* d_pairs, uint32_t cap, uint2* ranges, hipStream_t s) {
+    if (cap) tile_ranges_kernel<<<(cap + kThreads - 1) / kThreads, kThreads, 0, s>>>(keys, d_pairs, ranges);
+}
+
+void launch_pair_capacity(uint32_t* d_pairs, uint32_t cap, unsigned long long* stats, unsigned long long* prof,
+                          hipStream_t s) {
+    pair_capacity_kernel<<<1, 1, 0, s>>>(d_pairs, cap, stats, prof);
+}
+
+void launch_fill_u32_dev(uint32_t* p, uint32_t v, const uint32_t* d_count, uint32_t per_word, size_t cap,
+                         hipStream_t s) {
+    if (cap) fill_u32_dev_kernel<<<grid_for(cap), kThreads, 0, s>>>(p, v, d_count, per_word, cap);
+}
+
+void launch_copy_u32(uint32_t* dst, const uint32_t* src, size_t n, hipStream_t s) {
+    if (n) copy_u32_dev_kernel<<<grid_for(n), kThreads, 0, s>>>(dst, src, nullptr, n);
 }
 
 void launch_tile_order(const uint2* ranges, const uint32_t* lens, int tiles, uint32_t* order, hipStream_t s) {

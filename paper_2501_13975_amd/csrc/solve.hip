@@ -72,12 +72,64 @@ __device__ int damped_small(int n, const T* H, const T* g, const gsn_solve_opts&
     return -1;
 }
 
-__device__ void clamp_norm(int n, double* x, double radius) {
+// Scales x onto the ball of the given radius when it lies outside; true when it did.
+__device__ bool clamp_norm(int n, double* x, double radius) {
     double nn = 0.0;
     for (int i = 0; i < n; ++i) nn += x[i] * x[i];
     nn = sqrt(nn);
-    if (nn > radius && nn > 0.0)
+    if (nn > radius && nn > 0.0) {
         for (int i = 0; i < n; ++i) x[i] *= radius / nn;
+        return true;
+    }
+    return false;
+}
+
+// Events of one kernel's solve.  Bits 0-3: the system of position, rotation, scaling, opacity was
+// accepted only after escalating the damping; bits 4-7: it fell back to the scaled gradient step;
+// bits 8-11: the trust radius of position, rotation, scaling, colour (any channel) cut the step;
+// bit 12: the kernel was solved; bit 13: a block or a step was not finite, so the kernel was
+// skipped (zero step, decisions -3).  Bits 0-12 are counted while profiling (GSN_COUNT_SOLVE_*),
+// bit 13 always (GSN_STAT_SKIPPED_NONFINITE).
+constexpr int EV_ESC = 0, EV_FALLBACK = 4, EV_CLAMP = 8, EV_SOLVED = 12, EV_NONFINITE = 13;
+constexpr int EV_PROFILED = 13;  // bits counted while profiling
+__device__ __forceinline__ uint32_t decision_events(int group, int j) {
+    return (j > 0 ? 1u << (EV_ESC + group) : 0u) | (j == -1 ? 1u << (EV_FALLBACK + group) : 0u);
+}
+
+// True when every block entry the solve of kernel k reads (base rows and the rows of the V view
+// slots) is finite.
+__device__ __forceinline__ bool blocks_finite(const float* __restrict__ blk, size_t N, int k, int V) {
+    float z = 0.f;  // stays 0 while every entry is finite: x * 0 is NaN for NaN and infinite x
+    for (int r = 0; r < GSN_BLK_BASE + GSN_BLK_VIEW * V; ++r) z += blk[(size_t)r * N + k] * 0.f;
+    return z == 0.f;
+}
+
+// Zero step and decisions -3 for a kernel skipped because of non-finite values.
+__device__ __forceinline__ void skip_nonfinite(float* __restrict__ st, int32_t* __restrict__ fl, size_t N, int k,
+                                               int NS) {
+    for (int r = 0; r < NS; ++r) st[(size_t)r * N + k] = 0.f;
+    for (int r = 0; r < 4; ++r) fl[(size_t)r * N + k] = -3;
+    fl[4 * N + k] = 0;
+}
+
+// Adds a workgroup's solve events to the counters: the rare non-finite skips always, the others
+// while profiling (per wave ballots summed in LDS, one atomic per counter and workgroup).
+// Every thread of the workgroup calls it.
+__device__ __forceinline__ void count_solve_events(uint32_t ev, unsigned long long* __restrict__ nonfinite,
+                                                   unsigned long long* __restrict__ prof) {
+    if ((ev >> EV_NONFINITE) & 1u) atomicAdd(nonfinite, 1ull);
+    if (!prof) return;  // uniform across the launch
+    __shared__ uint32_t cnt[EV_PROFILED];
+    if (threadIdx.x < EV_PROFILED) cnt[threadIdx.x] = 0;
+    __syncthreads();
+#pragma unroll
+    for (int b = 0; b < EV_PROFILED; ++b) {
+        const uint64_t m = __ballot((ev >> b) & 1u);
+        if (__lane_id() == 0 && m) atomicAdd(&cnt[b], (uint32_t)__popcll(m));
+    }
+    __syncthreads();
+    if (threadIdx.x < EV_PROFILED && cnt[threadIdx.x])
+        atomicAdd(&prof[GSN_COUNT_SOLVE_ESCALATED + threadIdx.x], (unsigned long long)cnt[threadIdx.x]);
 }
 
 // Cholesky solve of an m x m SPD system (m <= VM) held in a VM x VM register array (double).
@@ -132,8 +184,9 @@ __device__ __forceinline__ bool chol_solve_v(int m, const T A[VM][VM], const T* 
 // Delta = B^T y, which equals the damped coefficient-space solve (B^T S B + mu I) Delta =
 // -B^T gamma for every nv.  The basis rows are re-evaluated instead of stored.
 template <int VM, class RowFn>
-__device__ __forceinline__ void colour_solve(int K, int V, RowFn B, const gsn_solve_opts& o, double abs_scale,
-                                             float* __restrict__ st, size_t N, int k, int32_t* __restrict__ fl) {
+__device__ __forceinline__ bool colour_solve(int K, int V, RowFn B, const gsn_solve_opts& o, double abs_scale,
+                                             float* __restrict__ st, size_t N, int k, int32_t* __restrict__ fl,
+                                             double& chk) {
     int vb[VM];
     int nv = 0;
 #pragma unroll
@@ -218,6 +271,7 @@ __device__ __forceinline__ void colour_solve(int K, int V, RowFn B, const gsn_so
                 for (int ch = 0; ch < 3; ++ch) dsh[ch][a] += ya * ych[ch][i];
             });
     }
+    bool clamped = false;
 #pragma unroll
     for (int ch = 0; ch < 3; ++ch) {
         // trust radius on each channel's coefficient step
@@ -228,27 +282,39 @@ __device__ __forceinline__ void colour_solve(int K, int V, RowFn B, const gsn_so
             nn += dsh[ch][a] * dsh[ch][a];
         }
         nn = sqrt(nn);
-        const double f = nn > (double)o.trust_sh && nn > 0.0 ? (double)o.trust_sh / nn : 1.0;
+        chk += nn * 0.0;
+        const bool cut = nn > (double)o.trust_sh && nn > 0.0;
+        clamped = clamped || cut;
+        const double f = cut ? (double)o.trust_sh / nn : 1.0;
 #pragma unroll
         for (int a = 0; a < 16; ++a)
             if (a < K) st[(GSN_STEP_BASE + ch * K + a) * N + k] = (float)(dsh[ch][a] * f);
     }
+    return clamped;
 }
 
-// The local solves of kernel k of one scene (all groups), writing its steps and decisions.
+// The local solves of kernel k of one scene (all groups), writing its steps and decisions;
+// returns the kernel's solve events (EV_*).
 template <int VM>
-__device__ __forceinline__ void solve_one(int k, const float* __restrict__ pos, const float* __restrict__ rot,
-                                          const float* __restrict__ scale, const float* __restrict__ opac, int n,
-                                          int K, const DevCam& c, float kappa, const float* __restrict__ blk, int V,
-                                          const gsn_solve_opts& o, float* __restrict__ st, int32_t* __restrict__ fl) {
+__device__ __forceinline__ uint32_t solve_one(int k, const float* __restrict__ pos, const float* __restrict__ rot,
+                                              const float* __restrict__ scale, const float* __restrict__ opac,
+                                              int n, int K, const DevCam& c, float kappa,
+                                              const float* __restrict__ blk, int V, const gsn_solve_opts& o,
+                                              float* __restrict__ st, int32_t* __restrict__ fl) {
     const size_t N = (size_t)n;
     const int NS = GSN_STEP_BASE + 3 * K;
     auto B = [&](int row) { return (double)blk[(size_t)row * N + k]; };
     if (!(B(29) > 0.0)) {
         for (int r = 0; r < NS; ++r) st[(size_t)r * N + k] = 0.f;
         for (int r = 0; r < 5; ++r) fl[(size_t)r * N + k] = -2;
-        return;
+        return 0u;
     }
+    if (!blocks_finite(blk, N, k, V)) {
+        skip_nonfinite(st, fl, N, k, NS);
+        return 1u << EV_NONFINITE;
+    }
+    uint32_t ev = 1u << EV_SOLVED;
+    double chk = 0.0;  // stays 0 while every step component is finite
     const double abs_scale = 1.0 / (3.0 * (double)o.npix_primary);
     double s[3];
     for (int a = 0; a < 3; ++a) s[a] = scale[a * N + k];
@@ -258,37 +324,60 @@ __device__ __forceinline__ void solve_one(int k, const float* __restrict__ pos, 
     // ---- position: Delta p = U Delta v
     {
         double dv[2];
-        fl[0 * N + k] = damped_small(2, R.Hp, R.gp, o, abs_scale, dv);
+        const int j = damped_small(2, R.Hp, R.gp, o, abs_scale, dv);
+        fl[0 * N + k] = j;
+        ev |= decision_events(0, j);
         for (int a = 0; a < 2; ++a) dv[a] *= (double)o.step_frac;
-        clamp_norm(2, dv, (double)o.trust_pos * fmax(s[0], fmax(s[1], s[2])));
-        for (int a = 0; a < 3; ++a) st[(size_t)a * N + k] = (float)(R.ux[a] * dv[0] + R.uy[a] * dv[1]);
+        if (clamp_norm(2, dv, (double)o.trust_pos * fmax(s[0], fmax(s[1], s[2])))) ev |= 1u << (EV_CLAMP + 0);
+        for (int a = 0; a < 3; ++a) {
+            const double d = R.ux[a] * dv[0] + R.uy[a] * dv[1];
+            chk += d * 0.0;
+            st[(size_t)a * N + k] = (float)d;
+        }
     }
     // ---- rotation about r: omega = theta r
     {
         double th;
-        fl[1 * N + k] = damped_small(1, &R.Ht, &R.gt, o, abs_scale, &th);
+        const int j = damped_small(1, &R.Ht, &R.gt, o, abs_scale, &th);
+        fl[1 * N + k] = j;
+        ev |= decision_events(1, j);
         th *= (double)o.step_frac;
-        clamp_norm(1, &th, (double)o.trust_rot);
+        if (clamp_norm(1, &th, (double)o.trust_rot)) ev |= 1u << (EV_CLAMP + 1);
+        chk += th * 0.0;
         st[3 * N + k] = (float)th;
     }
     // ---- scaling in the row space of d lambda / d s: Delta s = T^T a
     {
         double av[2];
-        fl[2 * N + k] = damped_small(2, R.Hs, R.gs, o, abs_scale, av);
+        const int j = damped_small(2, R.Hs, R.gs, o, abs_scale, av);
+        fl[2 * N + k] = j;
+        ev |= decision_events(2, j);
         for (int a = 0; a < 2; ++a) av[a] *= (double)o.step_frac;
         double dsv[3];
         for (int a = 0; a < 3; ++a) dsv[a] = R.T_[0][a] * av[0] + R.T_[1][a] * av[1];
-        clamp_norm(3, dsv, (double)o.trust_scale * sqrt(s[0] * s[0] + s[1] * s[1] + s[2] * s[2]));
-        for (int a = 0; a < 3; ++a) st[(7 + a) * N + k] = (float)dsv[a];
+        if (clamp_norm(3, dsv, (double)o.trust_scale * sqrt(s[0] * s[0] + s[1] * s[1] + s[2] * s[2])))
+            ev |= 1u << (EV_CLAMP + 2);
+        for (int a = 0; a < 3; ++a) {
+            chk += dsv[a] * 0.0;
+            st[(7 + a) * N + k] = (float)dsv[a];
+        }
     }
     // ---- opacity with the log barrier
     {
         double ds;
-        fl[3 * N + k] = damped_small(1, &R.Ho, &R.go, o, abs_scale, &ds);
+        const int j = damped_small(1, &R.Ho, &R.go, o, abs_scale, &ds);
+        fl[3 * N + k] = j;
+        ev |= decision_events(3, j);
+        chk += ds * 0.0;
         st[10 * N + k] = (float)((double)o.step_frac * ds);
     }
     // ---- colour, per channel
-    colour_solve<VM>(K, V, B, o, abs_scale, st, N, k, fl);
+    if (colour_solve<VM>(K, V, B, o, abs_scale, st, N, k, fl, chk)) ev |= 1u << (EV_CLAMP + 3);
+    if (!(chk == 0.0)) {
+        skip_nonfinite(st, fl, N, k, NS);
+        return 1u << EV_NONFINITE;
+    }
+    return ev;
 }
 
 // ---------------------------------------------------------------------------
@@ -380,10 +469,11 @@ __global__ __launch_bounds__(256) void sh_gram_kernel(const float* __restrict__ 
 
 // Colour step of the mixed form (FP32), from the matrix-core Gram matrices.
 template <class RowFn>
-__device__ __forceinline__ void colour_solve_mixed(int K, int V, RowFn B, const float* __restrict__ gram,
+__device__ __forceinline__ bool colour_solve_mixed(int K, int V, RowFn B, const float* __restrict__ gram,
                                                    const gsn_solve_opts& o, float abs_scale,
                                                    float* __restrict__ st, size_t N, int k,
-                                                   int32_t* __restrict__ fl, const float* __restrict__ blk) {
+                                                   int32_t* __restrict__ fl, const float* __restrict__ blk,
+                                                   float& chk) {
     int vb[4];
     const int nv = active_views(blk, N, k, V, vb);
     fl[4 * N + k] = nv;
@@ -443,6 +533,7 @@ __device__ __forceinline__ void colour_solve_mixed(int K, int V, RowFn B, const 
                 for (int ch = 0; ch < 3; ++ch) dsh[ch][a] += ya * ych[ch][i];
             });
     }
+    bool clamped = false;
 #pragma unroll
     for (int ch = 0; ch < 3; ++ch) {
         float nn = 0.f;
@@ -452,36 +543,50 @@ __device__ __forceinline__ void colour_solve_mixed(int K, int V, RowFn B, const 
             nn += dsh[ch][a] * dsh[ch][a];
         }
         nn = sqrtf(nn);
-        const float f = nn > o.trust_sh && nn > 0.f ? o.trust_sh / nn : 1.f;
+        chk += nn * 0.f;
+        const bool cut = nn > o.trust_sh && nn > 0.f;
+        clamped = clamped || cut;
+        const float f = cut ? o.trust_sh / nn : 1.f;
 #pragma unroll
         for (int a = 0; a < 16; ++a)
             if (a < K) st[(GSN_STEP_BASE + ch * K + a) * N + k] = dsh[ch][a] * f;
     }
+    return clamped;
 }
 
-__device__ void clamp_norm_f(int n, float* x, float radius) {
+__device__ bool clamp_norm_f(int n, float* x, float radius) {
     float nn = 0.f;
     for (int i = 0; i < n; ++i) nn += x[i] * x[i];
     nn = sqrtf(nn);
-    if (nn > radius && nn > 0.f)
+    if (nn > radius && nn > 0.f) {
         for (int i = 0; i < n; ++i) x[i] *= radius / nn;
+        return true;
+    }
+    return false;
 }
 
-// The local solves of kernel k in the mixed form.
-__device__ __forceinline__ void solve_one_mixed(int k, const float* __restrict__ pos, const float* __restrict__ rot,
-                                                const float* __restrict__ scale, const float* __restrict__ opac,
-                                                int n, int K, const DevCam& c, float kappa,
-                                                const float* __restrict__ blk, int V, const gsn_solve_opts& o,
-                                                const float* __restrict__ gram, float* __restrict__ st,
-                                                int32_t* __restrict__ fl, unsigned long long* __restrict__ n_fp64) {
+// The local solves of kernel k in the mixed form; returns the kernel's solve events (EV_*).
+__device__ __forceinline__ uint32_t solve_one_mixed(int k, const float* __restrict__ pos,
+                                                    const float* __restrict__ rot, const float* __restrict__ scale,
+                                                    const float* __restrict__ opac, int n, int K, const DevCam& c,
+                                                    float kappa, const float* __restrict__ blk, int V,
+                                                    const gsn_solve_opts& o, const float* __restrict__ gram,
+                                                    float* __restrict__ st, int32_t* __restrict__ fl,
+                                                    unsigned long long* __restrict__ n_fp64) {
     const size_t N = (size_t)n;
     const int NS = GSN_STEP_BASE + 3 * K;
     auto Bf = [&](int row) { return blk[(size_t)row * N + k]; };
     if (!(Bf(29) > 0.f)) {
         for (int r = 0; r < NS; ++r) st[(size_t)r * N + k] = 0.f;
         for (int r = 0; r < 5; ++r) fl[(size_t)r * N + k] = -2;
-        return;
+        return 0u;
     }
+    if (!blocks_finite(blk, N, k, V)) {
+        skip_nonfinite(st, fl, N, k, NS);
+        return 1u << EV_NONFINITE;
+    }
+    uint32_t ev = 1u << EV_SOLVED;
+    float chk = 0.f;  // stays 0 while every step component is finite
     const float abs_scale = 1.0f / (3.0f * (float)o.npix_primary);
     float s[3];
     for (int a = 0; a < 3; ++a) s[a] = scale[a * N + k];
@@ -516,29 +621,50 @@ __device__ __forceinline__ void solve_one_mixed(int k, const float* __restrict__
         if (n_fp64) atomicAdd(n_fp64, 1ull);
     }
     fl[0 * N + k] = jp;
+    ev |= decision_events(0, jp);
     for (int a = 0; a < 2; ++a) dv[a] *= o.step_frac;
-    clamp_norm_f(2, dv, o.trust_pos * fmaxf(s[0], fmaxf(s[1], s[2])));
-    for (int a = 0; a < 3; ++a) st[(size_t)a * N + k] = R.ux[a] * dv[0] + R.uy[a] * dv[1];
+    if (clamp_norm_f(2, dv, o.trust_pos * fmaxf(s[0], fmaxf(s[1], s[2])))) ev |= 1u << (EV_CLAMP + 0);
+    for (int a = 0; a < 3; ++a) {
+        const float d = R.ux[a] * dv[0] + R.uy[a] * dv[1];
+        chk += d * 0.f;
+        st[(size_t)a * N + k] = d;
+    }
     fl[1 * N + k] = jr;
+    ev |= decision_events(1, jr);
     th *= o.step_frac;
-    clamp_norm_f(1, &th, o.trust_rot);
+    if (clamp_norm_f(1, &th, o.trust_rot)) ev |= 1u << (EV_CLAMP + 1);
+    chk += th * 0.f;
     st[3 * N + k] = th;
     // ---- scaling and opacity in FP32
     {
         float av[2];
-        fl[2 * N + k] = damped_small(2, R.Hs, R.gs, o, abs_scale, av);
+        const int j = damped_small(2, R.Hs, R.gs, o, abs_scale, av);
+        fl[2 * N + k] = j;
+        ev |= decision_events(2, j);
         for (int a = 0; a < 2; ++a) av[a] *= o.step_frac;
         float dsv[3];
         for (int a = 0; a < 3; ++a) dsv[a] = R.T_[0][a] * av[0] + R.T_[1][a] * av[1];
-        clamp_norm_f(3, dsv, o.trust_scale * sqrtf(s[0] * s[0] + s[1] * s[1] + s[2] * s[2]));
-        for (int a = 0; a < 3; ++a) st[(7 + a) * N + k] = dsv[a];
+        if (clamp_norm_f(3, dsv, o.trust_scale * sqrtf(s[0] * s[0] + s[1] * s[1] + s[2] * s[2])))
+            ev |= 1u << (EV_CLAMP + 2);
+        for (int a = 0; a < 3; ++a) {
+            chk += dsv[a] * 0.f;
+            st[(7 + a) * N + k] = dsv[a];
+        }
     }
     {
         float ds;
-        fl[3 * N + k] = damped_small(1, &R.Ho, &R.go, o, abs_scale, &ds);
+        const int j = damped_small(1, &R.Ho, &R.go, o, abs_scale, &ds);
+        fl[3 * N + k] = j;
+        ev |= decision_events(3, j);
+        chk += ds * 0.f;
         st[10 * N + k] = o.step_frac * ds;
     }
-    colour_solve_mixed(K, V, Bf, gram, o, abs_scale, st, N, k, fl, blk);
+    if (colour_solve_mixed(K, V, Bf, gram, o, abs_scale, st, N, k, fl, blk, chk)) ev |= 1u << (EV_CLAMP + 3);
+    if (!(chk == 0.f)) {
+        skip_nonfinite(st, fl, N, k, NS);
+        return 1u << EV_NONFINITE;
+    }
+    return ev;
 }
 
 __global__ __launch_bounds__(128) void solve_mixed_kernel(const float* __restrict__ pos, const float* __restrict__ rot,
@@ -547,10 +673,13 @@ __global__ __launch_bounds__(128) void solve_mixed_kernel(const float* __restric
                                                            float kappa, const float* __restrict__ blk, int V,
                                                            gsn_solve_opts o, const float* __restrict__ gram,
                                                            float* __restrict__ st, int32_t* __restrict__ fl,
-                                                           unsigned long long* __restrict__ n_fp64) {
+                                                           unsigned long long* __restrict__ n_fp64,
+                                                           unsigned long long* __restrict__ nonfinite,
+                                                           unsigned long long* __restrict__ prof) {
     const int k = blockIdx.x * blockDim.x + threadIdx.x;
-    if (k >= n) return;
-    solve_one_mixed(k, pos, rot, scale, opac, n, K, c, kappa, blk, V, o, gram, st, fl, n_fp64);
+    uint32_t ev = 0;
+    if (k < n) ev = solve_one_mixed(k, pos, rot, scale, opac, n, K, c, kappa, blk, V, o, gram, st, fl, n_fp64);
+    count_solve_events(ev, nonfinite, prof);
 }
 
 template <int VM>
@@ -558,10 +687,13 @@ __global__ __launch_bounds__(128) void solve_kernel(const float* __restrict__ po
                                                      const float* __restrict__ scale, const float* __restrict__ opac,
                                                      int n, int K, DevCam c, float kappa,
                                                      const float* __restrict__ blk, int V, gsn_solve_opts o,
-                                                     float* __restrict__ st, int32_t* __restrict__ fl) {
+                                                     float* __restrict__ st, int32_t* __restrict__ fl,
+                                                     unsigned long long* __restrict__ nonfinite,
+                                                     unsigned long long* __restrict__ prof) {
     const int k = blockIdx.x * blockDim.x + threadIdx.x;
-    if (k >= n) return;
-    solve_one<VM>(k, pos, rot, scale, opac, n, K, c, kappa, blk, V, o, st, fl);
+    uint32_t ev = 0;
+    if (k < n) ev = solve_one<VM>(k, pos, rot, scale, opac, n, K, c, kappa, blk, V, o, st, fl);
+    count_solve_events(ev, nonfinite, prof);
 }
 
 // Several scenes in one persistent launch: the threads of a grid sized to the device walk
@@ -569,7 +701,8 @@ __global__ __launch_bounds__(128) void solve_kernel(const float* __restrict__ po
 // each kernel's solve is the per-scene solve, so the results are identical.
 template <int VM, int BLOCK>
 __global__ __launch_bounds__(BLOCK, 3) void solve_batched_kernel(const SolveScene* __restrict__ scenes, int count,
-                                                               long long total) {
+                                                               long long total,
+                                                               unsigned long long* __restrict__ nonfinite) {
     __shared__ long long s_first[GSN_SOLVE_MAX_SCENES + 1];
     for (int i = threadIdx.x; i <= count; i += blockDim.x) s_first[i] = i < count ? scenes[i].first : total;
     __syncthreads();
@@ -581,21 +714,18 @@ __global__ __launch_bounds__(BLOCK, 3) void solve_batched_kernel(const SolveScen
             if (s_first[mid] <= gi) lo = mid; else hi = mid - 1;
         }
         const SolveScene& sc = scenes[lo];
-        solve_one<VM>((int)(gi - s_first[lo]), sc.pos, sc.rot, sc.scale, sc.opac, sc.n, sc.K, sc.cam, sc.kappa,
-                      sc.blk, sc.V, sc.o, sc.st, sc.fl);
+        const uint32_t ev = solve_one<VM>((int)(gi - s_first[lo]), sc.pos, sc.rot, sc.scale, sc.opac, sc.n, sc.K,
+                                          sc.cam, sc.kappa, sc.blk, sc.V, sc.o, sc.st, sc.fl);
+        if ((ev >> EV_NONFINITE) & 1u) atomicAdd(nonfinite, 1ull);
     }
 }
 
-__global__ __launch_bounds__(256) void apply_kernel(float* __restrict__ pos, float* __restrict__ rot,
-                                                     float* __restrict__ scale, float* __restrict__ opac,
-                                                     float* __restrict__ sh, int n, int K,
-                                                     const float* __restrict__ st, const int32_t* __restrict__ fl,
-                                                     const float* __restrict__ gscale, gsn_solve_opts o,
-                                                     uint32_t mask) {
-    const int k = blockIdx.x * blockDim.x + threadIdx.x;
-    if (k >= n) return;
+// The update of kernel k (kernels the solve skipped, decisions -2 or -3, are not passed here).
+__device__ __forceinline__ void apply_one(float* __restrict__ pos, float* __restrict__ rot, float* __restrict__ scale,
+                                          float* __restrict__ opac, float* __restrict__ sh, int n, int K,
+                                          const float* __restrict__ st, const float* __restrict__ gscale,
+                                          const gsn_solve_opts& o, uint32_t mask, int k, bool& bound) {
     const size_t N = (size_t)n;
-    if (fl[k] == -2) return;
     float a[5] = {1.f, 1.f, 1.f, 1.f, 1.f};
     if (gscale)
         for (int i = 0; i < 5; ++i) a[i] = gscale[i * N + k];
@@ -618,11 +748,29 @@ __global__ __launch_bounds__(256) void apply_kernel(float* __restrict__ pos, flo
         }
     if (mask & 8u) {
         const float sg = opac[k];
-        const float moved = fminf(fmaxf(sg + a[3] * st[10 * N + k], sg - o.opac_ftb * sg), sg + o.opac_ftb * (1.0f - sg));
-        opac[k] = fminf(fmaxf(moved, o.opac_eps), 1.0f - o.opac_eps);
+        const float want = sg + a[3] * st[10 * N + k];
+        const float moved = fminf(fmaxf(want, sg - o.opac_ftb * sg), sg + o.opac_ftb * (1.0f - sg));
+        const float put = fminf(fmaxf(moved, o.opac_eps), 1.0f - o.opac_eps);
+        bound = put != want;
+        opac[k] = put;
     }
     if (mask & 16u)
         for (int i = 0; i < 3 * K; ++i) sh[i * N + k] += a[4] * st[(GSN_STEP_BASE + i) * N + k];
+}
+
+__global__ __launch_bounds__(256) void apply_kernel(float* __restrict__ pos, float* __restrict__ rot,
+                                                     float* __restrict__ scale, float* __restrict__ opac,
+                                                     float* __restrict__ sh, int n, int K,
+                                                     const float* __restrict__ st, const int32_t* __restrict__ fl,
+                                                     const float* __restrict__ gscale, gsn_solve_opts o,
+                                                     uint32_t mask, unsigned long long* __restrict__ prof) {
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    bool bound = false;  // the opacity step was cut by the fraction-to-boundary rule or the bounds
+    if (k < n && fl[k] >= -1) apply_one(pos, rot, scale, opac, sh, n, K, st, gscale, o, mask, k, bound);
+    if (prof) {  // uniform across the launch
+        const uint64_t m = __ballot(bound);
+        if (__lane_id() == 0 && m) atomicAdd(&prof[GSN_COUNT_OPAC_BOUND], (unsigned long long)__popcll(m));
+    }
 }
 
 }  // namespace
@@ -658,25 +806,28 @@ hipError_t solve_scratch_address(int device, float** out) {
 }
 
 void launch_solve(const gsn_gaussians& g, const DevCam& cam, float kappa, const gsn_blocks& b,
-                  const gsn_solve_opts& o, const gsn_steps& st, hipStream_t s) {
+                  const gsn_solve_opts& o, const gsn_steps& st, unsigned long long* nonfinite,
+                  unsigned long long* prof, hipStream_t s) {
     if (g.n == 0) return;
     const int K = (g.sh_degree + 1) * (g.sh_degree + 1);
     // the hot path has a primary and up to three secondaries: a 4-view kernel keeps its arrays in registers
     if (b.n_views <= 4)
         solve_kernel<4><<<(g.n + 127) / 128, 128, 0, s>>>(g.d_pos, g.d_rot, g.d_scale, g.d_opac, g.n, K, cam, kappa,
-                                                          b.d_data, b.n_views, o, st.d_data, st.d_flags);
+                                                          b.d_data, b.n_views, o, st.d_data, st.d_flags, nonfinite,
+                                                          prof);
     else
         solve_kernel<9><<<(g.n + 127) / 128, 128, 0, s>>>(g.d_pos, g.d_rot, g.d_scale, g.d_opac, g.n, K, cam, kappa,
-                                                          b.d_data, b.n_views, o, st.d_data, st.d_flags);
+                                                          b.d_data, b.n_views, o, st.d_data, st.d_flags, nonfinite,
+                                                          prof);
 }
 
 template <int BLOCK>
 static void launch_batched_block(const SolveScene* d_scenes, int count, long long total, int max_views, int grid,
-                                 hipStream_t s) {
+                                 unsigned long long* nonfinite, hipStream_t s) {
     if (max_views <= 4)
-        solve_batched_kernel<4, BLOCK><<<grid, BLOCK, 0, s>>>(d_scenes, count, total);
+        solve_batched_kernel<4, BLOCK><<<grid, BLOCK, 0, s>>>(d_scenes, count, total, nonfinite);
     else
-        solve_batched_kernel<9, BLOCK><<<grid, BLOCK, 0, s>>>(d_scenes, count, total);
+        solve_batched_kernel<9, BLOCK><<<grid, BLOCK, 0, s>>>(d_scenes, count, total, nonfinite);
 }
 
 void launch_sh_gram(const float* blk, int n, int K, int V, float* gram, hipStream_t s) {
@@ -686,29 +837,31 @@ void launch_sh_gram(const float* blk, int n, int K, int V, float* gram, hipStrea
 }
 
 void launch_solve_mixed(const gsn_gaussians& g, const DevCam& cam, float kappa, const gsn_blocks& b,
-                        const gsn_solve_opts& o, const float* gram, const gsn_steps& st, unsigned long long* n_fp64,
-                        hipStream_t s) {
+                        const gsn_solve_opts& o, const float* gram, const gsn_steps& st, unsigned long long* nonfinite,
+                        unsigned long long* prof, hipStream_t s) {
     if (g.n == 0) return;
     const int K = (g.sh_degree + 1) * (g.sh_degree + 1);
+    unsigned long long* n_fp64 = prof ? prof + GSN_COUNT_FP64_SOLVES : nullptr;
     solve_mixed_kernel<<<(g.n + 127) / 128, 128, 0, s>>>(g.d_pos, g.d_rot, g.d_scale, g.d_opac, g.n, K, cam, kappa,
-                                                         b.d_data, b.n_views, o, gram, st.d_data, st.d_flags, n_fp64);
+                                                         b.d_data, b.n_views, o, gram, st.d_data, st.d_flags, n_fp64,
+                                                         nonfinite, prof);
 }
 
 void launch_solve_batched(const SolveScene* d_scenes, int count, long long total, int max_views, int block,
-                          int grid, hipStream_t s) {
+                          int grid, unsigned long long* nonfinite, hipStream_t s) {
     if (total == 0) return;
     if (block == 64)
-        launch_batched_block<64>(d_scenes, count, total, max_views, grid, s);
+        launch_batched_block<64>(d_scenes, count, total, max_views, grid, nonfinite, s);
     else if (block == 256)
-        launch_batched_block<256>(d_scenes, count, total, max_views, grid, s);
+        launch_batched_block<256>(d_scenes, count, total, max_views, grid, nonfinite, s);
     else
-        launch_batched_block<128>(d_scenes, count, total, max_views, grid, s);
+        launch_batched_block<128>(d_scenes, count, total, max_views, grid, nonfinite, s);
 }
 
 void launch_apply(const gsn_gaussians& g, const gsn_steps& st, const gsn_solve_opts& o, const float* scale,
-                  uint32_t mask, hipStream_t s) {
+                  uint32_t mask, unsigned long long* prof, hipStream_t s) {
     if (g.n == 0) return;
     const int K = (g.sh_degree + 1) * (g.sh_degree + 1);
     apply_kernel<<<(g.n + 255) / 256, 256, 0, s>>>(g.d_pos, g.d_rot, g.d_scale, g.d_opac, g.d_sh, g.n, K,
-                                                   st.d_data, st.d_flags, scale, o, mask);
+                                                   st.d_data, st.d_flags, scale, o, mask, prof);
 }

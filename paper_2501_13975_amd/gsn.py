@@ -15,8 +15,11 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libgsn.so")
 
 GSN_BLK_BASE, GSN_BLK_VIEW, GSN_STEP_BASE, GSN_NZ = 30, 10, 11, 44
+GSN_FEAT_HIDDEN, GSN_FEAT_OK, GSN_FEAT_OUT_OF_RANGE = 0, 1, 2
 STATUS = {0: "GSN_OK", -1: "GSN_E_INVALID", -2: "GSN_E_SHAPE", -3: "GSN_E_CAPACITY", -4: "GSN_E_HIP",
-          -5: "GSN_E_NOMEM"}
+          -5: "GSN_E_NOMEM", -6: "GSN_E_NUMERIC"}
+GSN_E_CAPACITY, GSN_E_NUMERIC = -3, -6
+STATS = ("culled_nonfinite", "skipped_nonfinite", "pair_overflow", "pairs_needed")
 
 _lib = None
 
@@ -51,9 +54,9 @@ def lib():
             "gsn_solve_tune": [P, P, ctypes.c_int32, P, P],
             "gsn_solve_graph_create": [P, P, ctypes.c_int32, ctypes.POINTER(P)],
             "gsn_graph_launch": [P, P], "gsn_graph_destroy": [P, P],
-            "gsn_step_labels": [P, P, P, P, P],
+            "gsn_step_labels": [P, P, P, P, P, P, P, P],
             "gsn_mlp_reset": [P, P],
-            "gsn_mlp_infer": [P, P, ctypes.c_int32, P, P, P],
+            "gsn_mlp_infer": [P, P, ctypes.c_int32, P, P, P, P],
             "gsn_mlp_train_step": [P, P, ctypes.c_int32, P, P, P, P, P, P],
             "gsn_blocks_zero": [P, P],
             "gsn_downsample2x": [P, P, ctypes.c_int32, ctypes.c_int32, P],
@@ -67,6 +70,10 @@ def lib():
             "gsn_frame_records": [P, P, P],
             "gsn_profile_enable": [P, ctypes.c_int32],
             "gsn_profile_read": [P, P, P, P],
+            "gsn_sync_status": [P, P],
+            "gsn_frame_reserve": [P, P, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_int64],
+            "gsn_capture_begin": [P],
+            "gsn_capture_end": [P, ctypes.POINTER(P)],
         }.items():
             fn = getattr(L, name)
             fn.argtypes = args
@@ -203,6 +210,11 @@ class Frame:
         if self.h:
             lib().gsn_frame_destroy(self.ctx.h, self.h)
             self.h = None
+
+    def reserve(self, n, width, height, max_pairs):
+        """gsn_frame_reserve: size every buffer once (max_pairs = 0 returns to growing mode)."""
+        self.ctx._check(lib().gsn_frame_reserve(self.ctx.h, self.h, int(n), int(width), int(height),
+                                                int(max_pairs)))
 
     def info(self):
         pairs, tx, ty = ctypes.c_int64(), ctypes.c_int32(), ctypes.c_int32()
@@ -343,17 +355,21 @@ class Context:
         self._check(lib().gsn_step_features(self.h, ctypes.byref(cg), ctypes.byref(primary), ctypes.byref(cb),
                                             ctypes.byref(so), _ptr(feat), _ptr(ok)))
 
-    def step_labels(self, prim: "Steps", aug: "Steps", label, mask):
-        """label, mask: device float [5, n]."""
+    def step_labels(self, prim: "Steps", aug: "Steps", label, mask, ok=None, alpha=None, err=None):
+        """label, mask: device float [5, n]; ok: device uint8 [n] feature status (or None); alpha: the
+        network's scales [5, n] and err: device float64 [2] (+= sum mask |alpha - label|, sum mask), or None."""
         cp, ca = prim.c(), aug.c()
-        self._check(lib().gsn_step_labels(self.h, ctypes.byref(cp), ctypes.byref(ca), _ptr(label), _ptr(mask)))
+        self._check(lib().gsn_step_labels(self.h, ctypes.byref(cp), ctypes.byref(ca), _ptr(ok), _ptr(alpha),
+                                          _ptr(label), _ptr(mask), _ptr(err)))
 
     def mlp_reset(self, mlp: "MLP"):
         self._check(lib().gsn_mlp_reset(self.h, ctypes.byref(mlp.cs)))
 
-    def mlp_infer(self, mlp: "MLP", feat, ok, alpha):
+    def mlp_infer(self, mlp: "MLP", feat, ok, alpha, out_of_range=None):
+        """out_of_range: device int32 [1] (+= kernels whose features left the trained range), or None."""
         n = int(ok.numel())
-        self._check(lib().gsn_mlp_infer(self.h, ctypes.byref(mlp.cs), n, _ptr(feat), _ptr(ok), _ptr(alpha)))
+        self._check(lib().gsn_mlp_infer(self.h, ctypes.byref(mlp.cs), n, _ptr(feat), _ptr(ok), _ptr(alpha),
+                                        _ptr(out_of_range)))
 
     def mlp_train_step(self, mlp: "MLP", feat, label, mask, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8,
                        loss=None, grad=None):
@@ -363,7 +379,34 @@ class Context:
                                              ctypes.byref(a), _ptr(loss), _ptr(grad)))
 
     STAGES = ("project", "sort", "raster_fwd", "loss", "raster_bwd", "chain", "solve", "apply")
-    COUNTERS = ("fwd_evals", "bwd_evals", "bwd_active", "pairs", "partials", "fwd_staged", "fp64_solves")
+    GROUPS4 = ("position", "rotation", "scaling", "opacity")
+    COUNTERS = (("fwd_evals", "bwd_evals", "bwd_active", "pairs", "partials", "fwd_staged", "fp64_solves",
+                 "bwd_staged")
+                + tuple(f"escalated_{g}" for g in GROUPS4) + tuple(f"fallback_{g}" for g in GROUPS4)
+                + tuple(f"clamped_{g}" for g in ("position", "rotation", "scaling", "colour"))
+                + ("solved", "opacity_bound"))
+
+    def sync_status(self):
+        """gsn_sync_status: (status code, {counter: value}, message); synchronises the stream and clears
+        the counters.  The status is GSN_OK, GSN_E_NUMERIC or GSN_E_CAPACITY (not raised)."""
+        import numpy as np
+        out = np.zeros(len(STATS), np.int64)
+        st = lib().gsn_sync_status(self.h, out.ctypes.data_as(ctypes.c_void_p))
+        if st not in (0, GSN_E_NUMERIC, GSN_E_CAPACITY):
+            self._check(st)
+        return st, {k: int(out[i]) for i, k in enumerate(STATS)}, lib().gsn_last_error(self.h).decode()
+
+    def capture(self, fn) -> "SolveGraph":
+        """Records the library calls fn() makes on this context into a graph (gsn_capture_begin/end);
+        Graph.launch() replays them on the context's stream."""
+        self._check(lib().gsn_capture_begin(self.h))
+        try:
+            fn()
+        finally:
+            h = ctypes.c_void_p()
+            st = lib().gsn_capture_end(self.h, ctypes.byref(h))
+        self._check(st)
+        return SolveGraph(self, h)
 
     def profile_enable(self, on=True):
         self._check(lib().gsn_profile_enable(self.h, int(bool(on))))
@@ -371,8 +414,8 @@ class Context:
     def profile_read(self):
         """{stage: (ms, launches)}, {counter: value}; synchronises the stream."""
         import numpy as np
-        ms = np.zeros(8, np.float64)
-        nl = np.zeros(8, np.int64)
+        ms = np.zeros(len(self.STAGES), np.float64)
+        nl = np.zeros(len(self.STAGES), np.int64)
         cnt = np.zeros(len(self.COUNTERS), np.int64)
         self._check(lib().gsn_profile_read(self.h, ms.ctypes.data_as(ctypes.c_void_p),
                                            nl.ctypes.data_as(ctypes.c_void_p), cnt.ctypes.data_as(ctypes.c_void_p)))
@@ -411,7 +454,7 @@ class CSolveItem(ctypes.Structure):
 
 
 class SolveGraph:
-    """A captured batched solve; launch() replays it on the context's stream."""
+    """A captured batched solve or sequence of calls; launch() replays it on the context's stream."""
 
     def __init__(self, ctx, h):
         self.ctx, self.h = ctx, h

@@ -10,8 +10,14 @@ Learned form (``enable_learned``): every ``every``-th sweep runs the full rule
 and also trains the step-scale network on it (labels: how much of the
 primary-only step the full-rule step keeps, per kernel and group); the other
 sweeps render only the primary view and scale its Newton step by the network's
-prediction.  Kernels whose features fall outside the trained range take no step
-on a learned sweep.
+prediction.  A learned sweep on which some kernel's features leave the trained
+range falls back to the full rule (and trains on it).
+
+Reserved frames (``reserve_frames``) keep every buffer at a fixed size, so a
+sweep never waits for the device; ``sweep_graph`` then replays a captured sweep
+(one HIP graph per training image and group mask).  ``check_status`` reads what
+the device met meanwhile (non-finite kernels culled or skipped, pair-capacity
+overflows, after which the frames are reserved again with room for the view).
 """
 from __future__ import annotations
 
@@ -53,6 +59,52 @@ class LocalNewtonTrainer:
         else:
             self.knn = np.zeros((len(self.cams), 0), np.int32)
             self.half_targets = []
+
+    # ------------------------------------------------------- reserved frames, graphs
+    def reserve_frames(self, margin=1.25, extra=1 << 16):
+        """Sizes every frame for the largest pair count any training view needs at the current state
+        (primary slot: full resolution; secondary slots: half resolution) times `margin`, plus
+        `extra`, so that renders allocate nothing and never read back to the host."""
+        n = self.g.n
+        need = [0, 0]
+        for slot, cams in ((0, self.ccams), (1, self.chalf if self.n_secondary else [])):
+            fr = self.frames[slot]
+            for cam in cams:
+                self.ctx.render(self.g, cam, self.ro, fr)
+                need[slot] = max(need[slot], fr.info()[0])
+        self.pair_caps = [int(need[0] * margin) + extra, int(need[1] * margin) + extra]
+        for slot, fr in enumerate(self.frames):
+            cam = self.ccams[0] if slot == 0 else self.chalf[0]
+            fr.reserve(n, cam.width, cam.height, self.pair_caps[min(slot, 1)])
+        self.graphs = {}
+
+    def check_status(self, margin=1.25):
+        """gsn_sync_status: {counter: value} since the last check.  After a pair-capacity overflow the
+        frames are reserved again with room for the largest view seen and captured sweeps are dropped."""
+        from . import gsn as G
+        st, stats, msg = self.ctx.sync_status()
+        if st == G.GSN_E_CAPACITY:
+            need = int(stats["pairs_needed"] * margin)
+            self.pair_caps = [max(c, need) for c in self.pair_caps]
+            for slot, fr in enumerate(self.frames):
+                cam = self.ccams[0] if slot == 0 else self.chalf[0]
+                fr.reserve(self.g.n, cam.width, cam.height, self.pair_caps[min(slot, 1)])
+            for gr in getattr(self, "graphs", {}).values():
+                gr.close()
+            self.graphs = {}
+        stats["status"] = st
+        stats["message"] = msg
+        return stats
+
+    def sweep_graph(self, t, group_mask=31):
+        """One jacobi sweep on image t as a replay of a captured HIP graph (captured on first use;
+        needs reserve_frames).  Results equal sweep(t, group_mask)."""
+        key = (int(t), int(group_mask))
+        gr = self.graphs.get(key)
+        if gr is None:
+            gr = self.ctx.capture(lambda: self.sweep(t, group_mask))
+            self.graphs[key] = gr
+        gr.launch()
 
     def solve_opts(self, t):
         c = self.cams[t]
@@ -112,8 +164,11 @@ class LocalNewtonTrainer:
         self.mask = torch.zeros(5, max(n, 1), dtype=torch.float32, device=self.dev)
         self.steps_prim = gsn.Steps(n, self.g.sh_degree, self.dev)
         self.mlp_loss = torch.zeros(1, dtype=torch.float64, device=self.dev)
-        # per full-rule sweep: sum |alpha_mlp - alpha_eff| and number of labelled entries
-        self.err_log = []
+        # over the full-rule sweeps: sum of |alpha_mlp - alpha_eff| and number of labelled entries
+        self.err = torch.zeros(2, dtype=torch.float64, device=self.dev)
+        # kernels whose features left the trained range on the current sweep
+        self.out_of_range = torch.zeros(1, dtype=torch.int32, device=self.dev)
+        self.fallback_sweeps = 0
 
     def _accumulate_primary(self, t):
         self.ctx.blocks_zero(self.blocks)
@@ -127,33 +182,41 @@ class LocalNewtonTrainer:
             self.ctx.render(self.g, self.chalf[j], self.ro, fr)
             self.ctx.accumulate_hessian(self.g, fr, self.half_targets[j], self.lo, slot, self.blocks, self.loss[slot])
 
-    def sweep_learned(self, t, i, group_mask=31):
-        """Sweep i of the learned form on training image t."""
+    def sweep_learned(self, t, i, group_mask=31, check_range=True):
+        """Sweep i of the learned form on training image t.  Every `every`-th sweep runs the full
+        rule; so does a learned sweep on which a kernel's features leave the trained range (the
+        overshoot rule is the fallback of the network; with check_range the count is read back,
+        one host wait per learned sweep)."""
         so = self.solve_opts(t)
         n = self.g.n
         self._accumulate_primary(t)
-        prim = self.steps_prim if i % self.every == 0 else self.steps
-        self.ctx.local_newton_solve(self.g, self.ccams[t], self.blocks, so, prim)
+        full = i % self.every == 0
+        self.ctx.local_newton_solve(self.g, self.ccams[t], self.blocks, so, self.steps)
         self.ctx.step_features(self.g, self.ccams[t], self.blocks, so, self.feat[:, :n], self.ok[:n])
-        self.ctx.mlp_infer(self.mlp, self.feat[:, :n], self.ok[:n], self.alpha[:, :n])
-        if i % self.every != 0:
+        self.out_of_range.zero_()
+        self.ctx.mlp_infer(self.mlp, self.feat[:, :n], self.ok[:n], self.alpha[:, :n], self.out_of_range)
+        if not full and check_range and int(self.out_of_range.item()) > 0:
+            full = True
+            self.fallback_sweeps += 1
+        if not full:
             self.ctx.apply_step(self.g, self.steps, so, group_mask, scale=self.alpha[:, :n])
             return
         # full rule: the secondaries' blocks join the primary's; label and train, then apply the full step
+        self.steps, self.steps_prim = self.steps_prim, self.steps
         self._accumulate_secondaries(t)
         self.ctx.local_newton_solve(self.g, self.ccams[t], self.blocks, so, self.steps)
-        self.ctx.step_labels(self.steps_prim, self.steps, self.label[:, :n], self.mask[:, :n])
-        m = self.mask[:, :n]
-        self.err_log.append(torch.stack([((self.alpha[:, :n] - self.label[:, :n]).abs() * m).sum(), m.sum()]))
-        self.ctx.mlp_train_step(self.mlp, self.feat[:, :n], self.label[:, :n], m, lr=self.lr, loss=self.mlp_loss)
+        self.ctx.step_labels(self.steps_prim, self.steps, self.label[:, :n], self.mask[:, :n], ok=self.ok[:n],
+                             alpha=self.alpha[:, :n], err=self.err)
+        self.ctx.mlp_train_step(self.mlp, self.feat[:, :n], self.label[:, :n], self.mask[:, :n], lr=self.lr,
+                                loss=self.mlp_loss)
         self.ctx.apply_step(self.g, self.steps, so, group_mask)
 
     def learned_error(self):
         """Mean |alpha_mlp - alpha_eff| over the labelled entries of the full-rule sweeps so far."""
-        if not self.err_log:
+        e = self.err.cpu().numpy()
+        if e[1] <= 0:
             return None
-        e = torch.stack(self.err_log).sum(0).cpu().numpy()
-        return float(e[0] / max(e[1], 1.0))
+        return float(e[0] / e[1])
 
     def close(self):
         for f in self.frames:

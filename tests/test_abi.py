@@ -78,3 +78,26 @@ def test_half_resolution_camera_matches_oracle():
     c.width = 1
     with pytest.raises(gsn.GsnError):
         gsn.camera_half(c)
+
+
+def _enum_values(prefix):
+    src = open(HEADER).read()
+    return {m.group(1): int(m.group(2)) for m in re.finditer(r"\b(" + prefix + r"[A-Z0-9_]+)\s*=\s*(\d+)", src)}
+
+
+def test_binding_counter_names_follow_the_header():
+    """The binding's names of the profile counters and of the status counters match the header's enums."""
+    from paper_2501_13975_amd import gsn
+    counts = _enum_values("GSN_COUNT_")
+    assert len(gsn.Context.COUNTERS) == counts["GSN_COUNT_N"]
+    assert gsn.Context.COUNTERS[counts["GSN_COUNT_BWD_STAGED"]] == "bwd_staged"
+    assert gsn.Context.COUNTERS[counts["GSN_COUNT_SOLVE_ESCALATED"]] == "escalated_position"
+    assert gsn.Context.COUNTERS[counts["GSN_COUNT_SOLVE_FALLBACK"] + 3] == "fallback_opacity"
+    assert gsn.Context.COUNTERS[counts["GSN_COUNT_SOLVE_CLAMPED"] + 3] == "clamped_colour"
+    assert gsn.Context.COUNTERS[counts["GSN_COUNT_SOLVED"]] == "solved"
+    assert gsn.Context.COUNTERS[counts["GSN_COUNT_OPAC_BOUND"]] == "opacity_bound"
+    stats = _enum_values("GSN_STAT_")
+    assert len(gsn.STATS) == stats["GSN_STAT_N"]
+    assert gsn.STATS[stats["GSN_STAT_PAIRS_NEEDED"]] == "pairs_needed"
+    stages = _enum_values("GSN_STAGE_")
+    assert len(gsn.Context.STAGES) == stages["GSN_STAGE_COUNT"]

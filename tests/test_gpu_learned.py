@@ -104,6 +104,23 @@ def test_labels_parity(gsn, ctx, sweep_case):
     assert mw.sum() > 1000
     assert np.array_equal(mg, mw)
     assert np.max(np.abs(got - want)[mw > 0]) < 1e-5
+    # with feature status codes: kernels out of range are not labelled; the error sums against the
+    # network's scales accumulate in fixed order
+    rng = np.random.default_rng(9)
+    ok = np.where(dec_p[:, 0] >= -1, 1, 0).astype(np.uint8)
+    ok[rng.random(g.n) < 0.1] = 2
+    alpha = rng.uniform(0.0, 1.5, (g.n, 5)).astype(np.float32)
+    want2, mw2 = L.labels(p32, a32, dec_p, K, ok=ok)
+    e_want = L.label_error(alpha.astype(np.float64), want2, mw2)
+    err = torch.tensor([0.5, 2.0], dtype=torch.float64, device=ctx.device)
+    ctx.step_labels(sp, sa, lab, msk, ok=torch.tensor(ok, device=ctx.device),
+                    alpha=torch.tensor(alpha.T.copy(), device=ctx.device), err=err)
+    got2, mg2 = lab.cpu().numpy().T, msk.cpu().numpy().T
+    assert np.array_equal(mg2, mw2) and mw2.sum() < mw.sum()
+    assert np.max(np.abs(got2 - want2)[mw2 > 0]) < 1e-5
+    e = err.cpu().numpy()
+    assert e[1] == 2.0 + e_want[1]
+    assert abs(e[0] - 0.5 - e_want[0]) < 1e-5 * e_want[1]
 
 
 def test_mlp_infer_parity(gsn, ctx):
@@ -114,13 +131,17 @@ def test_mlp_infer_parity(gsn, ctx):
     ctx.mlp_reset(mlp)
     ok = np.ones(n, np.uint8)
     ok[::7] = 0
+    ok[3::11] = 2
     alpha = torch.zeros(5, n, device=ctx.device)
-    ctx.mlp_infer(mlp, torch.tensor(F.T.copy(), device=ctx.device), torch.tensor(ok, device=ctx.device), alpha)
+    oor = torch.zeros(1, dtype=torch.int32, device=ctx.device)
+    ctx.mlp_infer(mlp, torch.tensor(F.T.copy(), device=ctx.device), torch.tensor(ok, device=ctx.device), alpha,
+                  oor)
     got = alpha.cpu().numpy().T
     # the library infers with fp16 weights: the oracle takes the same rounded weights
     want = L.forward(p.astype(np.float16).astype(np.float64), F.astype(np.float64))
     assert np.max(np.abs(got[ok == 1] - want[ok == 1])) < 1e-5
-    assert np.all(got[ok == 0] == 0.0)
+    assert np.all(got[ok != 1] == 0.0)
+    assert int(oor.cpu()[0]) == int((ok == 2).sum())
 
 
 def test_mlp_train_steps_parity(gsn, ctx):

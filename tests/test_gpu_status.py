@@ -1,0 +1,195 @@
+"""GPU tests of the boundary's failure conventions and of sweeps without host waits: kernels with
+non-finite attributes are culled and counted by the render, kernels with non-finite blocks are
+skipped and counted by the solve (every other kernel matches a clean run); frames with a reserved
+pair capacity render exactly as growing frames, report an overflow instead of writing past the
+capacity, and a whole sweep captured in a HIP graph replays to the eager result bit for bit."""
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from synth.scenes import Gaussians, make_config
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def gsn():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2501_13975_amd import gsn as G
+    return G
+
+
+@pytest.fixture(scope="module")
+def case():
+    cfg = make_config("c1", n=4000, width=200, height=150, n_views=8)
+    tg = [O.render(cfg.gt, c, O.opts()).img.astype(np.float32) for c in cfg.cams]
+    return cfg, tg
+
+
+def _trainer(gsn, g_host, cfg, tg, **kw):
+    from paper_2501_13975_amd.train import LocalNewtonTrainer
+    dg = gsn.DeviceGaussians.from_host(g_host)
+    targets = [torch.tensor(x, device="cuda") for x in tg]
+    return LocalNewtonTrainer(dg, cfg.cams, targets, 3, **kw)
+
+
+def _state(dg):
+    return [x.clone() for x in (dg.pos, dg.rot, dg.scale, dg.opac, dg.sh)]
+
+
+def test_nonfinite_kernels_are_culled_and_counted(gsn, case):
+    cfg, tg = case
+    bad = np.array([5, 100, 1234, 2000, 3999])
+    keep = np.setdiff1d(np.arange(cfg.n), bad)
+    g = cfg.init
+    clean = Gaussians(g.pos[:, keep], g.rot[:, keep], g.scale[:, keep], g.opac[keep], g.sh[:, :, keep], g.sh_degree)
+    t = 2
+    print(f"\n[nonfinite params] t={t} bad={bad.tolist()}", flush=True)
+    # the dirty run keeps the clean run's camera neighbours: planted after the trainer is built
+    tr = _trainer(gsn, g, cfg, tg, solve_kw={"step_frac": 0.3})
+    tr.ctx.sync_status()
+    with torch.no_grad():
+        tr.g.pos[0, bad[0]] = float("nan")
+        tr.g.scale[1, bad[1]] = float("inf")
+        tr.g.sh[2, 5, bad[2]] = float("nan")
+        tr.g.opac[bad[3]] = float("-inf")
+        tr.g.rot[3, bad[4]] = float("nan")
+    tr.sweep(t)
+    st, stats, msg = tr.ctx.sync_status()
+    assert st == gsn.GSN_E_NUMERIC, msg
+    # every one of the four views culls every planted kernel
+    assert stats["culled_nonfinite"] == 4 * len(bad), stats
+    assert stats["skipped_nonfinite"] == 0 and stats["pair_overflow"] == 0
+    steps, flags = (x.cpu().numpy() for x in tr.steps.view())
+    assert np.all(flags[:4, bad] == -2) and np.all(steps[:, bad] == 0.0)
+    dirty_after = tr.g.to_host()
+    tr.close()
+    ref = _trainer(gsn, clean, cfg, tg, solve_kw={"step_frac": 0.3})
+    ref.knn = tr.knn.copy()  # the same secondary views (the scene centre moved by the removed kernels)
+    ref.sweep(t)
+    st2, stats2, _ = ref.ctx.sync_status()
+    assert st2 == 0 and stats2["culled_nonfinite"] == 0
+    rs, rf = (x.cpu().numpy() for x in ref.steps.view())
+    clean_after = ref.g.to_host()
+    ref.close()
+    assert np.array_equal(flags[:, keep], rf)
+    assert np.array_equal(steps[:, keep], rs)
+    for a in ("pos", "rot", "scale", "opac", "sh"):
+        d = getattr(dirty_after, a)
+        assert np.array_equal(d[..., keep], getattr(clean_after, a)), a
+    # the planted kernels are left as they were (not updated)
+    assert np.isnan(dirty_after.pos[0, bad[0]]) and np.isinf(dirty_after.scale[1, bad[1]])
+
+
+def test_nonfinite_blocks_are_skipped_and_counted(gsn, case):
+    cfg, tg = case
+    t = 4
+    print(f"\n[nonfinite blocks] t={t}", flush=True)
+    tr = _trainer(gsn, cfg.init, cfg, tg)
+    tr.accumulate(t)
+    so = tr.solve_opts(t)
+    ref_blocks = tr.blocks.data.clone()
+    tr.ctx.local_newton_solve(tr.g, tr.ccams[t], tr.blocks, so, tr.steps)
+    rs, rf = (x.clone().cpu().numpy() for x in tr.steps.view())
+    tr.ctx.sync_status()
+    vis = np.nonzero(rf[0] >= -1)[0]
+    assert vis.size > 1000
+    hit = vis[[3, 50, 400]]
+    bv = tr.blocks.view()
+    with torch.no_grad():
+        bv[4, int(hit[0])] = float("nan")       # H_p entry
+        bv[27, int(hit[1])] = float("inf")      # g_sigma
+        bv[30 + 10 * 1 + 1, int(hit[2])] = float("nan")  # a secondary view's colour gradient
+    for precision in (0, 1):
+        so = tr.solve_opts(t)
+        so.precision = precision
+        tr.ctx.local_newton_solve(tr.g, tr.ccams[t], tr.blocks, so, tr.steps)
+        st, stats, msg = tr.ctx.sync_status()
+        assert st == gsn.GSN_E_NUMERIC and stats["skipped_nonfinite"] == len(hit), (precision, stats, msg)
+        steps, flags = (x.cpu().numpy() for x in tr.steps.view())
+        assert np.all(flags[:4, hit] == -3) and np.all(steps[:, hit] == 0.0)
+        if precision == 0:
+            others = np.setdiff1d(np.arange(cfg.n), hit)
+            assert np.array_equal(steps[:, others], rs[:, others])
+            assert np.array_equal(flags[:, others], rf[:, others])
+    # the apply leaves skipped kernels unchanged
+    before = _state(tr.g)
+    tr.ctx.apply_step(tr.g, tr.steps, so, 31)
+    after = _state(tr.g)
+    for b, a in zip(before, after):
+        assert torch.equal(b[..., torch.tensor(hit, device="cuda")], a[..., torch.tensor(hit, device="cuda")])
+    tr.blocks.data.copy_(ref_blocks)
+    tr.close()
+
+
+def test_reserved_frame_renders_like_growing_frame(gsn, case):
+    cfg, tg = case
+    ctx = gsn.Context(0)
+    dg = gsn.DeviceGaussians.from_host(cfg.init)
+    ro = gsn.render_opts()
+    lo = gsn.loss_opts(0.2)
+    cam = gsn.camera(cfg.cams[1])
+    tgt = torch.tensor(tg[1], device="cuda")
+    out = {}
+    for mode in ("growing", "reserved", "overflow"):
+        print(f"\n[frame mode] {mode}", flush=True)
+        fr = ctx.frame()
+        if mode == "reserved":
+            fr.reserve(cfg.n, cam.width, cam.height, out["growing"]["pairs"] + 17)
+        elif mode == "overflow":
+            fr.reserve(cfg.n, cam.width, cam.height, 100)
+        img = torch.zeros(3, cam.height, cam.width, device="cuda")
+        blocks = gsn.Blocks(cfg.n, 1, ctx.device)
+        ctx.blocks_zero(blocks)
+        loss = torch.zeros(2, dtype=torch.float64, device="cuda")
+        ctx.render(dg, cam, ro, fr, img)
+        ctx.accumulate_hessian(dg, fr, tgt, lo, 0, blocks, loss)
+        st, stats, msg = ctx.sync_status()
+        pairs = fr.info()[0]
+        ranges, ids, _, _, nc = fr.lists(cfg.n, cam.width * cam.height)
+        out[mode] = {"img": img.cpu().numpy(), "blocks": blocks.data.cpu().numpy(), "pairs": pairs,
+                     "ranges": ranges.cpu().numpy(), "ids": ids.cpu().numpy(), "nc": nc.cpu().numpy(),
+                     "st": st, "stats": stats, "loss": loss.cpu().numpy()}
+        fr.close()
+    gr, rs, ov = out["growing"], out["reserved"], out["overflow"]
+    assert gr["st"] == 0 and rs["st"] == 0
+    assert gr["pairs"] > 1000 and rs["pairs"] == gr["pairs"]
+    for k in ("img", "blocks", "ranges", "ids", "nc", "loss"):
+        assert np.array_equal(gr[k], rs[k]), k
+    # the overflowing render draws nothing, adds no blocks and reports what it needed
+    assert ov["st"] == gsn.GSN_E_CAPACITY
+    assert ov["stats"]["pair_overflow"] == 1 and ov["stats"]["pairs_needed"] == gr["pairs"]
+    assert ov["pairs"] == 0 and np.all(ov["img"] == 0.0) and np.all(ov["blocks"] == 0.0)
+    assert np.all(ov["ranges"] == 0)
+    ctx.close()
+
+
+def test_sweep_graph_replays_the_eager_sweep(gsn, case):
+    cfg, tg = case
+    tr = _trainer(gsn, cfg.init, cfg, tg, solve_kw={"step_frac": 0.5})
+    tr.reserve_frames()
+    s0 = _state(tr.g)
+
+    def reset():
+        for dst, src in zip((tr.g.pos, tr.g.rot, tr.g.scale, tr.g.opac, tr.g.sh), s0):
+            dst.copy_(src)
+
+    for rep, t in enumerate((3, 3, 6)):
+        print(f"\n[sweep graph] replay {rep} t={t}", flush=True)
+        reset()
+        tr.sweep(t)
+        eager = [x.clone() for x in _state(tr.g)] + [tr.steps.data.clone(), tr.blocks.data.clone(),
+                                                     tr.loss.clone()]
+        torch.cuda.synchronize()
+        reset()
+        tr.sweep_graph(t)
+        torch.cuda.synchronize()
+        got = _state(tr.g) + [tr.steps.data, tr.blocks.data, tr.loss]
+        for i, (a, b) in enumerate(zip(eager, got)):
+            assert torch.equal(a, b), (rep, i)
+        stats = tr.check_status()
+        assert stats["status"] == 0, stats
+    assert len(tr.graphs) == 2
+    tr.close()
