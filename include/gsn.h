@@ -228,8 +228,8 @@ gsn_status gsn_accumulate_hessian(gsn_ctx* ctx, const gsn_gaussians* g, const gs
  * covariance), opacity with a log barrier, SH colour per channel from the
  * per-view statistics (Sec. 4.2, Position/Scaling/Rotation/Opacity/Color
  * solve).  Kernels the primary target does not see get no step (decisions -2); kernels with a
- * non-finite block entry or step component get a zero step (decisions -3) and are counted
- * (GSN_STAT_SKIPPED_NONFINITE).
+ * non-finite step component, or a non-finite block entry among those their solve reads, get a
+ * zero step (decisions -3) and are counted (GSN_STAT_SKIPPED_NONFINITE).
  * Errors: GSN_E_SHAPE (blocks.n or steps.n != g->n, sh_degree mismatch). */
 gsn_status gsn_local_newton_solve(gsn_ctx* ctx, const gsn_gaussians* g, const gsn_camera* primary,
                                   const gsn_blocks* blocks, const gsn_solve_opts* opts,
@@ -354,17 +354,17 @@ gsn_status gsn_capture_end(gsn_ctx* ctx, gsn_graph** out);
  * per kernel and group, the scale alpha that the full rule applies along the
  * primary-only step, so that most sweeps render only the primary view:
  *   features (gsn_step_features) from the primary view's blocks alone,
- *   network 16 -> 32 (ReLU) -> 5, alpha = 1.5 sigmoid(.) (gsn_mlp_infer),
+ *   network 17 -> 32 (ReLU) -> 5, alpha = 1.5 sigmoid(.) (gsn_mlp_infer),
  *   labels alpha_eff = <Delta_aug, Delta_prim> / |Delta_prim|^2 clipped to
  *   [0, 1.5] from a sweep that runs the full rule (gsn_step_labels),
  *   training by mean squared error and Adam (gsn_mlp_train_step). */
-#define GSN_MLP_IN 16
+#define GSN_MLP_IN 17
 #define GSN_MLP_HID 32
 #define GSN_MLP_OUT 5
-#define GSN_MLP_PARAMS 709
-/* Network state, device buffers owned by the caller: d_params float [709]
- * master weights laid out W1 [32][16] row-major, b1 [32], W2 [5][32]
- * row-major, b2 [5]; d_m, d_v float [709] Adam moments; d_half fp16 [709]
+#define GSN_MLP_PARAMS 741
+/* Network state, device buffers owned by the caller: d_params float [741]
+ * master weights laid out W1 [32][17] row-major, b1 [32], W2 [5][32]
+ * row-major, b2 [5]; d_m, d_v float [741] Adam moments; d_half fp16 [741]
  * inference copy; step: Adam steps taken (advanced by gsn_mlp_train_step). */
 typedef struct {
     float* d_params;
@@ -382,19 +382,29 @@ typedef struct {
 #define GSN_FEAT_OK 1            /* features in range: the network's scale applies */
 #define GSN_FEAT_OUT_OF_RANGE 2  /* seen, but a feature left [-3, 3]: the network is not trusted and the
                                     kernel needs the full overshoot rule (gsn_mlp_infer counts it) */
-/* Features of every kernel (device float [16][n], layout feature-major) from
+/* Features of every kernel (device float [17][n], layout feature-major) from
  * blocks holding only the primary view (slot 0), in the reduced coordinates of
- * gsn_local_newton_solve.  With L(x) = log10(x + 1e-30) / 10 clipped to [-3, 3]:
+ * gsn_local_newton_solve, and the residual the neighbouring views left at the
+ * kernel.  With L(x) = log10(x + 1e-30) / 10 clipped to [-3, 3]:
  * 0, 1 L(|lambda|) of the reduced position Hessian's larger / smaller
  * eigenvalue; 2 sign of the smaller; 3, 4 L(|H_theta|), sign; 5, 6, 7 the same
  * for the reduced scaling Hessian; 8 L(|H_sigma + h_B|); 9 L(sum of |s| of the
  * primary's colour Hessian diagonal); 10 L(primary coverage); 11-14 L(|g|) of
- * the reduced position, rotation, scaling and opacity gradients; 15 L(opacity).
+ * the reduced position, rotation, scaling and opacity gradients; 15 L(opacity);
+ * 16 L(d_resid[k]), the neighbouring-view residual cached by
+ * gsn_neighbour_residual (d_resid may be NULL: 0).
  * d_ok (device u8 [n]) receives GSN_FEAT_HIDDEN, GSN_FEAT_OK or GSN_FEAT_OUT_OF_RANGE.
  * Errors: GSN_E_SHAPE. */
 gsn_status gsn_step_features(gsn_ctx* ctx, const gsn_gaussians* g, const gsn_camera* primary,
-                             const gsn_blocks* blocks, const gsn_solve_opts* opts, float* d_feat,
-                             uint8_t* d_ok);
+                             const gsn_blocks* blocks, const gsn_solve_opts* opts, const float* d_resid,
+                             float* d_feat, uint8_t* d_ok);
+/* The residual the neighbouring views (the secondary targets of Sec. 4.3) leave at each kernel,
+ * from blocks that hold them (a sweep that runs the full rule): for every kernel the primary
+ * sees and at least one secondary view covers, d_resid[k] = sum over the secondary slots v >= 1
+ * that cover it of |gamma_v| / (|gamma_0| + 1e-30), gamma_v the view's colour gradient (3
+ * channels, Euclidean norm); other kernels keep their value (the cache of their last visit).
+ * d_resid: device float [n].  Errors: GSN_E_SHAPE (n_views < 2), GSN_E_INVALID. */
+gsn_status gsn_neighbour_residual(gsn_ctx* ctx, const gsn_blocks* blocks, float* d_resid);
 /* Labels from the primary-only steps (prim) and the full-rule steps (aug) of
  * the same sweep: d_label, d_mask device float [5][n]; the mask is 1 where the
  * solve stepped the kernel (decisions >= -1), its features were in range
@@ -416,9 +426,9 @@ gsn_status gsn_mlp_reset(gsn_ctx* ctx, gsn_mlp* mlp);
 gsn_status gsn_mlp_infer(gsn_ctx* ctx, const gsn_mlp* mlp, int32_t n, const float* d_feat,
                          const uint8_t* d_ok, float* d_alpha, uint32_t* d_out_of_range);
 /* One Adam step on the mean squared error over the entries with mask 1
- * (features [16][n], labels and mask [5][n]); writes the loss before the step
+ * (features [17][n], labels and mask [5][n]); writes the loss before the step
  * to d_loss (device double, may be NULL) and the gradient to d_grad (device
- * float [709], may be NULL).  Gradient partials are summed in a fixed order:
+ * float [741], may be NULL).  Gradient partials are summed in a fixed order:
  * results are deterministic.  Errors: GSN_E_INVALID (n < 0, null buffers). */
 gsn_status gsn_mlp_train_step(gsn_ctx* ctx, gsn_mlp* mlp, int32_t n, const float* d_feat, const float* d_label,
                               const float* d_mask, const gsn_adam_opts* adam, double* d_loss, float* d_grad);

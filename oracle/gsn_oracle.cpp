@@ -1163,8 +1163,9 @@ int orc_solve(int n, int K, const double* pos, const double* rot, const double* 
     return 0;
 }
 
-// Features of the learned step scale (one 16-vector per kernel) from the summed blocks of
-// the primary view alone, in the reduced coordinates of the solve.  With
+// Features of the learned step scale (one 17-vector per kernel) from the summed blocks of
+// the primary view alone, in the reduced coordinates of the solve, and the cached
+// neighbouring-view residual.  With
 // L(x) = log10(x + 1e-30) / 10:
 //   0, 1  L(|lambda|) of the larger / smaller eigenvalue of the reduced position Hessian,
 //   2     sign of its smaller eigenvalue (+1 when >= 0),
@@ -1175,11 +1176,14 @@ int orc_solve(int n, int K, const double* pos, const double* rot, const double* 
 //   9     L(sum over channels of |s|, the primary view's colour Hessian diagonal),
 //   10    L(primary coverage w),
 //   11-14 L(|g|) of the reduced position, rotation, scaling and opacity gradients,
-//   15    L(opacity).
-// ok[k] = 1 when the kernel is visible in the primary view and every L argument lies in
-// [1e-30, 1e30] (so that no feature leaves [-3, 3]).
+//   15    L(opacity),
+//   16    L(resid[k]) (resid may be null: 0), the neighbouring-view residual of the kernel's
+//         last full-rule sweep.
+// ok[k] = 0 when the kernel is not visible in the primary view, else 1 when every L argument lies
+// in [1e-30, 1e30] (so that no feature leaves [-3, 3]) and 2 when one does not.
 int orc_features(int n, int K, const double* pos, const double* rot, const double* scale, const double* opac,
-                 const double* cam, const double* o, int V, const double* blocks, double* feat, uint8_t* ok) {
+                 const double* cam, const double* o, int V, const double* blocks, const double* resid, double* feat,
+                 uint8_t* ok) {
     const Cam c = load_cam(cam);
     const int NB = S_COUNT_BASE + V * S_VIEW;
     const double kappa = o[O_SMOOTH] != 0.0 ? 0.0 : o[O_KAPPA];
@@ -1188,8 +1192,8 @@ int orc_features(int n, int K, const double* pos, const double* rot, const doubl
 #pragma omp parallel for schedule(static)
     for (int k = 0; k < n; ++k) {
         const double* B = blocks + (size_t)k * NB;
-        double* f = feat + (size_t)k * 16;
-        std::fill(f, f + 16, 0.0);
+        double* f = feat + (size_t)k * 17;
+        std::fill(f, f + 17, 0.0);
         ok[k] = 0;
         if (!(B[38] > 0.0)) continue;
         double p[3], q[4], s[3];
@@ -1229,6 +1233,7 @@ int orc_features(int n, int K, const double* pos, const double* rot, const doubl
         f[13] = L(std::sqrt(R.gs[0] * R.gs[0] + R.gs[1] * R.gs[1]));
         f[14] = L(std::fabs(R.go));
         f[15] = L(opac[k]);
+        f[16] = L(resid ? resid[k] : 0.0);
         ok[k] = in_range ? 1 : 2;  // 0: not seen by the primary, 1: features in range, 2: seen, out of range
     }
     return 0;

@@ -14,12 +14,14 @@ primary-only step the full rule would keep:
   alpha_eff = <Delta_aug, Delta_prim> / |Delta_prim|^2, clipped to [0, 1.5]: the
   length of the full-rule step projected on the primary-only step, in units of
   the primary-only step;
-* features: 16 per kernel from the primary view's blocks alone (``orc_features``);
-* network: 16 -> 32 (ReLU) -> 5, output 1.5 sigmoid, one scale per group
+* features: 16 per kernel from the primary view's blocks alone, and the residual the
+  neighbouring views left at the kernel in its last full-rule sweep (``orc_features``,
+  ``neighbour_residual``);
+* network: 17 -> 32 (ReLU) -> 5, output 1.5 sigmoid, one scale per group
   (position, rotation, scaling, opacity, colour);
 * training: mean squared error over the labelled (kernel, group) entries, Adam.
 
-Parameter vector layout (709 values): W1 [32][16] row-major, b1 [32],
+Parameter vector layout (741 values): W1 [32][17] row-major, b1 [32],
 W2 [5][32] row-major, b2 [5].
 """
 from __future__ import annotations
@@ -30,7 +32,7 @@ import numpy as np
 
 from oracle import oracle as O
 
-N_IN, N_HID, N_OUT = 16, 32, 5
+N_IN, N_HID, N_OUT = 17, 32, 5
 N_PARAMS = N_HID * N_IN + N_HID + N_OUT * N_HID + N_OUT
 ALPHA_MAX = 1.5
 # step-vector columns of each group (position 3, rotation angle 1, scaling 3, opacity 1, colour 3K)
@@ -42,15 +44,41 @@ MIN_STEP_SQ = 1e-30
 FEAT_HIDDEN, FEAT_OK, FEAT_OUT_OF_RANGE = 0, 1, 2
 
 
-def features(g, cam, o, summed, V):
-    """Per-kernel features [n][16] and status codes [n] (FEAT_*) from the summed blocks."""
+def features(g, cam, o, summed, V, resid=None):
+    """Per-kernel features [n][17] and status codes [n] (FEAT_*) from the summed blocks and the
+    cached neighbouring-view residuals resid [n] (None: 0)."""
     g64 = O.G64.of(g)
     feat = np.zeros((g64.n, N_IN))
     ok = np.zeros(g64.n, np.uint8)
+    r = None if resid is None else np.ascontiguousarray(resid, np.float64)
     O.lib().orc_features(ctypes.c_int(g64.n), ctypes.c_int(g64.K), O._p(g64.pos), O._p(g64.rot),
                          O._p(g64.scale), O._p(g64.opac), O._p(O.cam_vec(cam)), O._p(o), ctypes.c_int(V),
-                         O._p(np.ascontiguousarray(summed, np.float64)), O._p(feat), O._p(ok))
+                         O._p(np.ascontiguousarray(summed, np.float64)), O._p(r) if r is not None else None,
+                         O._p(feat), O._p(ok))
     return feat, ok
+
+
+def neighbour_residual(summed, V, prev):
+    """The residual the neighbouring (secondary) views leave at each kernel, from the summed blocks
+    of a full-rule sweep: for kernels the primary sees and some secondary view v >= 1 covers,
+    sum over those views of |gamma_v| / (|gamma_0| + 1e-30) (gamma_v: the view's colour gradient);
+    other kernels keep prev."""
+    S = np.asarray(summed, np.float64)
+    out = np.array(prev, np.float64, copy=True)
+    base = O.NB_BASE
+
+    def gnorm(v):
+        return np.sqrt((S[:, base + O.NB_VIEW * v:base + O.NB_VIEW * v + 3] ** 2).sum(1))
+
+    sec = np.zeros(S.shape[0])
+    seen = np.zeros(S.shape[0], bool)
+    for v in range(1, V):
+        cov = S[:, base + O.NB_VIEW * v + 9] > 0
+        sec[cov] += gnorm(v)[cov]
+        seen |= cov
+    upd = seen & (S[:, 38] > 0)
+    out[upd] = sec[upd] / (gnorm(0)[upd] + 1e-30)
+    return out
 
 
 def unpack(params):

@@ -192,8 +192,8 @@ gsn_status gsn_profile_enable(gsn_ctx* ctx, int32_t on) {
     }
     ctx->recs.clear();
     if (on && !ctx->d_counts)
-        HIP_TRY(ctx, hipMalloc((void**)&ctx->d_counts, GSN_COUNT_N * sizeof(unsigned long long)));
-    if (ctx->d_counts) launch_fill_u32(reinterpret_cast<uint32_t*>(ctx->d_counts), 0u, 2 * GSN_COUNT_N, ctx->stream);
+        HIP_TRY(ctx, hipMalloc((void**)&ctx->d_counts, GSN_PROF_WORDS * sizeof(unsigned long long)));
+    if (ctx->d_counts) launch_fill_u32(reinterpret_cast<uint32_t*>(ctx->d_counts), 0u, 2 * GSN_PROF_WORDS, ctx->stream);
     HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
     ctx->prof = on != 0;
     return GSN_OK;
@@ -216,8 +216,12 @@ gsn_status gsn_profile_read(gsn_ctx* ctx, double* h_ms, int64_t* h_launches, int
         if (h_launches) h_launches[i] = nl[i];
     }
     if (h_counts) {
-        unsigned long long c[GSN_COUNT_N] = {0};
-        if (ctx->d_counts) HIP_TRY(ctx, hipMemcpy(c, ctx->d_counts, sizeof c, hipMemcpyDeviceToHost));
+        std::vector<unsigned long long> c(GSN_PROF_WORDS, 0ull);
+        if (ctx->d_counts)
+            HIP_TRY(ctx, hipMemcpy(c.data(), ctx->d_counts, c.size() * sizeof(unsigned long long), hipMemcpyDeviceToHost));
+        for (int r = 0; r < GSN_SOLVE_SPREAD; ++r)
+            for (int e = 0; e < GSN_SOLVE_EVENTS; ++e)
+                c[GSN_COUNT_SOLVE_ESCALATED + e] += c[GSN_COUNT_N + (size_t)r * GSN_SOLVE_EVENTS + e];
         for (int i = 0; i < GSN_COUNT_N; ++i) h_counts[i] = (int64_t)c[i];
     }
     return GSN_OK;
@@ -286,7 +290,7 @@ static hipError_t frame_buffers(gsn_frame* f, int n, int W, int H, size_t pairs)
     const size_t npx = (size_t)W * H;
     const size_t tiles = (size_t)((W + GSN_TILE - 1) / GSN_TILE) * ((H + GSN_TILE - 1) / GSN_TILE);
     DevBuf* per_kernel4[] = {&f->depth_key, &f->ntiles, &f->ids_a, &f->ids_b, &f->keys_a, &f->keys_b, &f->pair_off};
-    hipError_t e = buf_reserve(f->rec, nn * 3 * sizeof(float4));
+    hipError_t e = buf_reserve(f->rec, nn * 4 * sizeof(float4));
     if (e == hipSuccess) e = buf_reserve(f->rect, nn * sizeof(uint2));
     for (DevBuf* b : per_kernel4)
         if (e == hipSuccess) e = buf_reserve(*b, nn * 4);
@@ -301,7 +305,7 @@ static hipError_t frame_buffers(gsn_frame* f, int n, int W, int H, size_t pairs)
     if (e == hipSuccess) e = buf_reserve(f->img64, 3 * npx * 8);
     if (e == hipSuccess) e = buf_reserve(f->Tfin, npx * 4);
     if (e == hipSuccess) e = buf_reserve(f->ncontrib, npx * 4);
-    if (e == hipSuccess) e = buf_reserve(f->masks, tiles * GSN_MASK_BATCHES * 2 * 4 * GSN_BLOCK * sizeof(uint64_t));
+    if (e == hipSuccess) e = buf_reserve(f->masks, tiles * GSN_MASK_BATCHES * 4 * GSN_BLOCK * sizeof(uint64_t));
     if (e == hipSuccess) e = buf_reserve(f->dL, 3 * npx * 4);
     if (e == hipSuccess) e = buf_reserve(f->hd, 3 * npx * 4);
     if (e == hipSuccess) e = buf_reserve(f->coef, 24 * npx * 4);
@@ -431,7 +435,7 @@ gsn_status gsn_render(gsn_ctx* ctx, const gsn_gaussians* g, const gsn_camera* ca
         launch_fill_u32(bp<uint32_t>(f->kflag), 0u, (nn + 3) / 4, s);
         launch_emit_pairs(bp<uint32_t>(f->ids_a), bp<uint32_t>(f->offsets), (uint32_t)n, d_pairs, cap,
                           bp<uint2>(f->rect), (uint32_t)f->tiles_x, bp<uint32_t>(f->pk_a), bp<uint32_t>(f->pv_a),
-                          bp<uint32_t>(f->pair_off), bp<uint32_t>(f->chunk_first), s);
+                          bp<uint32_t>(f->pair_off), bp<uint32_t>(f->chunk_first), bp<float4>(f->rec), s);
         int tile_bits = 1;
         while ((1ull << tile_bits) < tiles) ++tile_bits;
         HIP_TRY(ctx, radix_sort_pairs(bp<uint32_t>(f->pk_a), bp<uint32_t>(f->pv_a), bp<uint32_t>(f->pk_b),
@@ -878,7 +882,8 @@ gsn_status gsn_first_order_step(gsn_ctx* ctx, gsn_gaussians* g, const gsn_blocks
 }
 
 gsn_status gsn_step_features(gsn_ctx* ctx, const gsn_gaussians* g, const gsn_camera* primary,
-                             const gsn_blocks* b, const gsn_solve_opts* o, float* d_feat, uint8_t* d_ok) {
+                             const gsn_blocks* b, const gsn_solve_opts* o, const float* d_resid, float* d_feat,
+                             uint8_t* d_ok) {
     if (!ctx || !b || !o) return fail(ctx, GSN_E_INVALID, "null argument");
     gsn_status r = check_gaussians(ctx, g);
     if (r != GSN_OK) return r;
@@ -887,7 +892,17 @@ gsn_status gsn_step_features(gsn_ctx* ctx, const gsn_gaussians* g, const gsn_cam
     if (g->n > 0 && (!b->d_data || !d_feat || !d_ok)) return fail(ctx, GSN_E_INVALID, "null device array");
     if (o->npix_primary <= 0) return fail(ctx, GSN_E_INVALID, "npix_primary must be positive");
     HIP_TRY(ctx, hipSetDevice(ctx->device));
-    launch_features(*g, make_devcam(*primary), o->kappa, *b, *o, d_feat, d_ok, ctx->stream);
+    launch_features(*g, make_devcam(*primary), o->kappa, *b, *o, d_resid, d_feat, d_ok, ctx->stream);
+    HIP_TRY(ctx, hipGetLastError());
+    return GSN_OK;
+}
+
+gsn_status gsn_neighbour_residual(gsn_ctx* ctx, const gsn_blocks* b, float* d_resid) {
+    if (!ctx || !b) return fail(ctx, GSN_E_INVALID, "null argument");
+    if (b->n_views < 2) return fail(ctx, GSN_E_SHAPE, "the blocks hold no secondary view");
+    if (b->n > 0 && (!b->d_data || !d_resid)) return fail(ctx, GSN_E_INVALID, "null device array");
+    HIP_TRY(ctx, hipSetDevice(ctx->device));
+    launch_neighbour_residual(*b, d_resid, ctx->stream);
     HIP_TRY(ctx, hipGetLastError());
     return GSN_OK;
 }
@@ -1106,7 +1121,8 @@ gsn_status gsn_frame_records(gsn_ctx* ctx, const gsn_frame* f, float* d_out) {
     if (!ctx || !f || !d_out) return GSN_E_INVALID;
     if (!f->rendered) return fail(ctx, GSN_E_INVALID, "frame was never rendered");
     HIP_TRY(ctx, hipSetDevice(ctx->device));
-    HIP_TRY(ctx, hipMemcpyAsync(d_out, f->rec.p, (size_t)f->n * 48, hipMemcpyDeviceToDevice, ctx->stream));
+    launch_records_out(bp<float4>(f->rec), f->n, reinterpret_cast<float4*>(d_out), ctx->stream);
+    HIP_TRY(ctx, hipGetLastError());
     return GSN_OK;
 }
 

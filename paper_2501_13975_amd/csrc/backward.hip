@@ -181,8 +181,7 @@ __device__ __forceinline__ void write_partial(float* __restrict__ partial, uint8
 template <bool GN>
 __global__ __launch_bounds__(GSN_BLOCK, 3) void raster_bwd_kernel(
     const uint2* __restrict__ ranges, const uint32_t* __restrict__ order, const uint32_t* __restrict__ ids,
-    const float4* __restrict__ rec, const uint2* __restrict__ rect, const uint32_t* __restrict__ pair_off, uint32_t n,
-    DevCam cam, DevRenderOpts ro,
+    const float4* __restrict__ rec, uint32_t n, DevCam cam, DevRenderOpts ro,
     const double* __restrict__ img64, const uint32_t* __restrict__ ncontrib, const uint64_t* __restrict__ masks,
     const float* __restrict__ dLm, const float* __restrict__ hdm, float* __restrict__ partial,
     uint8_t* __restrict__ flags, uint8_t* __restrict__ kflag, unsigned long long* __restrict__ counts) {
@@ -251,7 +250,8 @@ __global__ __launch_bounds__(GSN_BLOCK, 3) void raster_bwd_kernel(
         if (tid < bcnt) {
             ++n_stage;
             const uint32_t id = ids[base + tid];
-            const float4 a = rec[id], b = rec[n + id], c4 = rec[2 * (size_t)n + id];
+            const float4* rp = rec + 4 * (size_t)id;  // the kernel's 64-byte record: one gather
+            const float4 a = rp[0], b = rp[1], c4 = rp[2], d4 = rp[3];
             r_a[tid] = a;
             r_b[tid] = b;
             r_c[tid] = c4;
@@ -261,9 +261,10 @@ __global__ __launch_bounds__(GSN_BLOCK, 3) void raster_bwd_kernel(
                 if (!box_misses(box, tx0, tx1, ty0 + 4.f * w, ty0 + 4.f * w + 3.f) &&
                     !ellipse_misses(a, b, c4, ro.alpha_min, tx0, tx1, ty0 + 4.f * w, ty0 + 4.f * w + 3.f))
                     bandmask |= 1u << w;
-            const uint2 rc = rect[id];
-            const uint32_t x0 = rc.x & 0xffffu, y0 = rc.x >> 16, x1 = rc.y & 0xffffu;
-            r_slot[tid] = pair_off[id] + ((uint32_t)ty - y0) * (x1 - x0) + ((uint32_t)tx - x0);
+            // the (tile, kernel) slot: the kernel's pair offset plus the tile's row-major place in its rectangle
+            const uint32_t rx = __float_as_uint(d4.x), ry = __float_as_uint(d4.y), off = __float_as_uint(d4.z);
+            const uint32_t x0 = rx & 0xffffu, y0 = rx >> 16, x1 = ry & 0xffffu;
+            r_slot[tid] = off + ((uint32_t)ty - y0) * (x1 - x0) + ((uint32_t)tx - x0);
             r_id[tid] = id;
         }
         uint64_t bal[NW];
@@ -291,13 +292,10 @@ __global__ __launch_bounds__(GSN_BLOCK, 3) void raster_bwd_kernel(
         uint64_t bits[NW] = {0ull, 0ull, 0ull, 0ull};
         const uint32_t batch = (base - rg.x) / GSN_BLOCK;
         if (batch < (uint32_t)GSN_MASK_BATCHES) {
-            // the forward pass's pixel-major words and its per-(entry, wave) ballots
-            const uint64_t* mb = masks + ((size_t)tile * GSN_MASK_BATCHES + batch) * 2 * NW * GSN_BLOCK + tid;
+            // the forward pass's pixel-major words
+            const uint64_t* mb = masks + ((size_t)tile * GSN_MASK_BATCHES + batch) * NW * GSN_BLOCK + tid;
 #pragma unroll
-            for (int w = 0; w < NW; ++w) {
-                bits[w] = mb[(size_t)w * GSN_BLOCK];
-                s_mask[tid][w] = mb[(size_t)(NW + w) * GSN_BLOCK];
-            }
+            for (int w = 0; w < NW; ++w) bits[w] = mb[(size_t)w * GSN_BLOCK];
         } else {
             for (uint32_t i = 0; i < nl; ++i) {
                 const int j = r_list[wave][i];
@@ -311,15 +309,18 @@ __global__ __launch_bounds__(GSN_BLOCK, 3) void raster_bwd_kernel(
                 }
             }
         }
-        if (batch >= (uint32_t)GSN_MASK_BATCHES) {
-            for (uint32_t i = 0; i < nl; ++i) {  // uniform across the wave
-                const int j = r_list[wave][i];
-                uint64_t word = 0;
+        // per (entry, wave): the wave's pixels that composited the entry (the transpose of the pixels'
+        // masks), one ballot per entry that some pixel of the wave composited
 #pragma unroll
-                for (int w = 0; w < NW; ++w)
-                    if ((j >> 6) == w) word = bits[w];
-                const uint64_t m = __ballot((word >> (j & 63)) & 1ull);
-                if (lane == 0) s_mask[j][wave] = m;
+        for (int w = 0; w < NW; ++w) {
+            uint64_t any = bits[w];
+#pragma unroll
+            for (int off = 1; off < 64; off <<= 1) any |= (uint64_t)__shfl_xor((unsigned long long)any, off, 64);
+            while (any) {  // uniform across the wave
+                const int jj = __ffsll((unsigned long long)any) - 1;
+                any &= any - 1;
+                const uint64_t m = __ballot((bits[w] >> jj) & 1ull);
+                if (lane == 0) s_mask[w * 64 + jj][wave] = m;
             }
         }
         __syncthreads();
@@ -569,7 +570,7 @@ __device__ __forceinline__ void load_kparams(const float* __restrict__ pos, cons
     for (int a = 0; a < 4; ++a) kp.q[a] = rot[(size_t)a * n + k];
 #pragma unroll
     for (int a = 0; a < 3; ++a) kp.s[a] = scale[(size_t)a * n + k];
-    const float4 r1 = rec[(size_t)n + k];
+    const float4 r1 = rec[4 * (size_t)k + 1];
     kp.fc = r1.x;
     kp.fs = r1.y;
 }
@@ -670,7 +671,7 @@ void launch_raster_bwd(const gsn_frame& f, const float* dL, const float* hd, boo
     auto kern = gauss_newton ? raster_bwd_kernel<true> : raster_bwd_kernel<false>;
     kern<<<tiles, GSN_BLOCK, 0, s>>>(
         bp<uint2>(f.ranges), bp<uint32_t>(f.bwd_order), bp<uint32_t>(f.pv_a), bp<float4>(f.rec),
-        bp<uint2>(f.rect), bp<uint32_t>(f.pair_off), (uint32_t)f.n, f.cam, f.ro, bp<double>(f.img64),
+        (uint32_t)f.n, f.cam, f.ro, bp<double>(f.img64),
         bp<uint32_t>(f.ncontrib), bp<uint64_t>(f.masks), dL, hd, bp<float>(f.partial), bp<uint8_t>(f.flags),
         bp<uint8_t>(f.kflag), counts);
 }

@@ -37,7 +37,8 @@ struct gsn_frame {
     DevCam cam{};
     DevRenderOpts ro{};
     // per kernel
-    DevBuf rec;         // float4 [3][n]: (mx, my, q1, q2), (c, s, sigma, R), (G, B, mx_lo, my_lo)
+    DevBuf rec;         // float4 [n][4], one 64-byte record per kernel: (mx, my, q1, q2), (c, s, sigma, R),
+                        // (G, B, mx_lo, my_lo), (rect x0 | y0 << 16, rect x1 | y1 << 16, pair offset, 0)
     DevBuf rect;        // uint2 [n]: (x0 | y0 << 16, x1 | y1 << 16)
     DevBuf depth_key;   // u32 [n], 0xffffffff when culled
     DevBuf ntiles;      // u32 [n]
@@ -59,9 +60,9 @@ struct gsn_frame {
     DevBuf img64;       // double [3][H][W], the same colour before rounding
     DevBuf Tfin;        // float [H][W]
     DevBuf ncontrib;    // u32 [H][W]
-    DevBuf masks;       // u64 [tiles][GSN_MASK_BATCHES][2][4][256]: composited (pixel, entry) pairs of each
+    DevBuf masks;       // u64 [tiles][GSN_MASK_BATCHES][4][256]: composited (pixel, entry) pairs of each
                         // staged batch of 256 list entries, per pixel (bit j of word w: entry 64 w + j of
-                        // the batch), then per (wave, entry) (bit l: pixel l of the wave's 16 x 4 band)
+                        // the batch)
     DevBuf dL, hd;      // float [3][H][W] loss maps
     DevBuf coef;        // float [3][8][H][W] SSIM coefficient maps (computed in double, stored rounded)
     DevBuf zsum;        // double [n][GSN_NZ] per-kernel sums of the pair partials
@@ -118,6 +119,11 @@ struct StageTimer {
     ~StageTimer();
 };
 inline unsigned long long* prof_counts(const gsn_ctx* c) { return c->prof ? c->d_counts : nullptr; }
+// The profile counter array holds GSN_COUNT_N counters, then GSN_SOLVE_SPREAD copies of the
+// GSN_SOLVE_EVENTS solve counters (GSN_COUNT_SOLVE_ESCALATED onwards) that gsn_profile_read sums.
+#define GSN_SOLVE_EVENTS 13
+#define GSN_SOLVE_SPREAD 64
+constexpr int GSN_PROF_WORDS = GSN_COUNT_N + GSN_SOLVE_SPREAD * GSN_SOLVE_EVENTS;
 
 // ---- launchers (render.hip)
 void launch_fill_u32(uint32_t* p, uint32_t v, size_t n, hipStream_t s);
@@ -147,7 +153,9 @@ void launch_gather_u32(const uint32_t* src, const uint32_t* idx, uint32_t* dst, 
 // pairs in depth order for the live count *d_pairs (launches sized for cap pairs)
 void launch_emit_pairs(const uint32_t* sorted_ids, const uint32_t* offsets, uint32_t n, const uint32_t* d_pairs,
                        uint32_t cap, const uint2* rect, uint32_t tiles_x, uint32_t* keys, uint32_t* vals,
-                       uint32_t* pair_off, uint32_t* chunk_first, hipStream_t s);
+                       uint32_t* pair_off, uint32_t* chunk_first, float4* rec, hipStream_t s);
+// the projected records [n][4] as the public layout [3][n] (gsn_frame_records)
+void launch_records_out(const float4* rec, int n, float4* out, hipStream_t s);
 size_t emit_chunks(uint32_t pairs);
 size_t radix_hist_bytes(uint32_t n);
 void launch_tile_ranges(const uint32_t* keys, const uint32_t* d_pairs, uint32_t cap, uint2* ranges, hipStream_t s);
@@ -207,7 +215,8 @@ void launch_solve_mixed(const gsn_gaussians& g, const DevCam& cam, float kappa, 
                         const gsn_solve_opts& o, const float* gram, const gsn_steps& st, unsigned long long* nonfinite,
                         unsigned long long* prof, hipStream_t s);
 void launch_features(const gsn_gaussians& g, const DevCam& cam, float kappa, const gsn_blocks& b,
-                     const gsn_solve_opts& o, float* feat, uint8_t* ok, hipStream_t s);
+                     const gsn_solve_opts& o, const float* resid, float* feat, uint8_t* ok, hipStream_t s);
+void launch_neighbour_residual(const gsn_blocks& b, float* resid, hipStream_t s);
 int label_blocks(int n);
 // part: double [2][label_blocks(n)] scratch, used when alpha and err are given (err[0..1] +=)
 void launch_labels(int n, int K, const float* sp, const int32_t* fp, const float* sa, const uint8_t* ok,

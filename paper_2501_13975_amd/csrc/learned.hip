@@ -1,5 +1,5 @@
 // learned.hip -- the learned per-kernel step scale: features, labels, and the
-// 16 -> 32 -> 5 network (inference and Adam training).
+// 17 -> 32 -> 5 network (inference and Adam training).
 //
 // The overshoot control of Sec. 4.3 (eq. tildel) adds the blocks of the |N_t|
 // nearest training views to the primary's.  The learned form replaces those
@@ -8,7 +8,8 @@
 // is trained on sweeps that run the full rule.
 //
 // features_kernel: one thread per kernel, the reduced systems of the solve built
-//   from the primary view's blocks alone (reduced.h), 16 log-scaled summaries.
+//   from the primary view's blocks alone (reduced.h), 16 log-scaled summaries, and
+//   the neighbouring-view residual cached from the kernel's last full-rule sweep.
 // labels_kernel:   alpha_eff = <Delta_aug, Delta_prim> / |Delta_prim|^2 per group.
 // mlp_infer_kernel: one thread per kernel, FP16 weights staged in LDS, FP32
 //   accumulation, alpha = 1.5 sigmoid(W2 relu(W1 f + b1) + b2).
@@ -43,8 +44,8 @@ __global__ __launch_bounds__(128) void features_kernel(const float* __restrict__
                                                         const float* __restrict__ scale,
                                                         const float* __restrict__ opac, int n, DevCam c,
                                                         float kappa, const float* __restrict__ blk,
-                                                        gsn_solve_opts o, float* __restrict__ feat,
-                                                        uint8_t* __restrict__ ok) {
+                                                        gsn_solve_opts o, const float* __restrict__ resid,
+                                                        float* __restrict__ feat, uint8_t* __restrict__ ok) {
     const int k = blockIdx.x * blockDim.x + threadIdx.x;
     if (k >= n) return;
     const size_t N = (size_t)n;
@@ -77,10 +78,34 @@ __global__ __launch_bounds__(128) void features_kernel(const float* __restrict__
         f[13] = feat_log(sqrt(R.gs[0] * R.gs[0] + R.gs[1] * R.gs[1]), in_range);
         f[14] = feat_log(fabs(R.go), in_range);
         f[15] = feat_log((double)opac[k], in_range);
+        f[16] = feat_log(resid ? (double)resid[k] : 0.0, in_range);
     }
 #pragma unroll
     for (int i = 0; i < NI; ++i) feat[(size_t)i * N + k] = f[i];
     ok[k] = !vis ? GSN_FEAT_HIDDEN : in_range ? GSN_FEAT_OK : GSN_FEAT_OUT_OF_RANGE;
+}
+
+// Neighbouring-view residual of every kernel covered by the primary and a secondary view.
+__global__ __launch_bounds__(256) void neighbour_residual_kernel(const float* __restrict__ blk, int n, int V,
+                                                                  float* __restrict__ resid) {
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= n) return;
+    const size_t N = (size_t)n;
+    if (!(blk[29 * N + k] > 0.f)) return;
+    auto gnorm = [&](int v) {
+        const size_t b = GSN_BLK_BASE + (size_t)GSN_BLK_VIEW * v;
+        const double x = blk[b * N + k], y = blk[(b + 1) * N + k], z = blk[(b + 2) * N + k];
+        return sqrt(x * x + y * y + z * z);
+    };
+    double sec = 0.0;
+    bool seen = false;
+    for (int v = 1; v < V; ++v) {
+        if (blk[(GSN_BLK_BASE + (size_t)GSN_BLK_VIEW * v + 9) * N + k] > 0.f) {
+            sec += gnorm(v);
+            seen = true;
+        }
+    }
+    if (seen) resid[k] = (float)(sec / (gnorm(0) + 1e-30));
 }
 
 constexpr int LABEL_BLOCK = 256;
@@ -312,10 +337,15 @@ __global__ void mlp_reset_kernel(const float* __restrict__ wf, float* __restrict
 }  // namespace
 
 void launch_features(const gsn_gaussians& g, const DevCam& cam, float kappa, const gsn_blocks& b,
-                     const gsn_solve_opts& o, float* feat, uint8_t* ok, hipStream_t s) {
+                     const gsn_solve_opts& o, const float* resid, float* feat, uint8_t* ok, hipStream_t s) {
     if (g.n == 0) return;
     features_kernel<<<(g.n + 127) / 128, 128, 0, s>>>(g.d_pos, g.d_rot, g.d_scale, g.d_opac, g.n, cam, kappa,
-                                                      b.d_data, o, feat, ok);
+                                                      b.d_data, o, resid, feat, ok);
+}
+
+void launch_neighbour_residual(const gsn_blocks& b, float* resid, hipStream_t s) {
+    if (b.n == 0) return;
+    neighbour_residual_kernel<<<(b.n + 255) / 256, 256, 0, s>>>(b.d_data, b.n, b.n_views, resid);
 }
 
 int label_blocks(int n) { return (n + LABEL_BLOCK - 1) / LABEL_BLOCK; }

@@ -139,7 +139,8 @@ __global__ __launch_bounds__(kThreads) void preprocess_kernel(
     }
     depth_key[k] = __float_as_uint(b.tz);
     ntiles[k] = (uint32_t)((b.x1 - b.x0) * (b.y1 - b.y0));
-    rect[k] = make_uint2((uint32_t)b.x0 | ((uint32_t)b.y0 << 16), (uint32_t)b.x1 | ((uint32_t)b.y1 << 16));
+    const uint2 rk = make_uint2((uint32_t)b.x0 | ((uint32_t)b.y0 << 16), (uint32_t)b.x1 | ((uint32_t)b.y1 << 16));
+    rect[k] = rk;
     // Compositing record in the splat's principal frame (see device_common.h), evaluated in
     // double from the float attributes: the mean is kept as a float pair (hi + lo) because the
     // single-precision pixel coordinate of a mean (ulp 1.2e-4 at x = 1920) would shift a thin
@@ -181,9 +182,13 @@ __global__ __launch_bounds__(kThreads) void preprocess_kernel(
         atomicAdd(culled, 1ull);
         return;
     }
-    rec[k] = make_float4(mu_hi, mv_hi, (float)(1.0 / l1), (float)(1.0 / l2));
-    rec[n + k] = make_float4((float)fc, (float)fs, opac[k], col[0]);
-    rec[2 * (size_t)n + k] = make_float4(col[1], col[2], (float)(mu - (double)mu_hi), (float)(mv - (double)mv_hi));
+    // one 64-byte record per kernel: a list entry's record is one gather (the pair offset is filled
+    // in by pair_off_kernel after the depth sort)
+    float4* r = rec + 4 * (size_t)k;
+    r[0] = make_float4(mu_hi, mv_hi, (float)(1.0 / l1), (float)(1.0 / l2));
+    r[1] = make_float4((float)fc, (float)fs, opac[k], col[0]);
+    r[2] = make_float4(col[1], col[2], (float)(mu - (double)mu_hi), (float)(mv - (double)mv_hi));
+    r[3] = make_float4(__uint_as_float(rk.x), __uint_as_float(rk.y), 0.f, 0.f);
 }
 
 // ---------------------------------------------------------------------------
@@ -497,6 +502,13 @@ __global__ void copy_u32_dev_kernel(uint32_t* __restrict__ dst, const uint32_t* 
     for (; i < n; i += stride) dst[i] = src[i];
 }
 
+__global__ void records_out_kernel(const float4* __restrict__ rec, int n, float4* __restrict__ out) {
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= n) return;
+#pragma unroll
+    for (int j = 0; j < 3; ++j) out[(size_t)j * n + k] = rec[4 * (size_t)k + j];
+}
+
 __global__ void gather_u32_kernel(const uint32_t* __restrict__ src, const uint32_t* __restrict__ idx,
                                   uint32_t* __restrict__ dst, uint32_t n) {
     const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -512,15 +524,18 @@ constexpr int kEmitChunk = 2048;
 // One thread per depth rank: the kernel's pair offset by id, and for every chunk whose first slot
 // falls in the rank's range, that rank (the ranges partition the slots, so each chunk's entry is
 // written once).
-// pairs: the live pair count (0 after a capacity overflow: then no chunk is emitted).
+// pairs: the live pair count (0 after a capacity overflow: then no chunk is emitted).  The offset
+// is also stored in the kernel's record (word 14), next to its tile rectangle.
 __global__ void pair_off_kernel(const uint32_t* __restrict__ sorted_ids, const uint32_t* __restrict__ offsets,
                                 uint32_t n, const uint32_t* __restrict__ d_pairs, uint32_t* __restrict__ pair_off,
-                                uint32_t* __restrict__ chunk_first) {
+                                uint32_t* __restrict__ chunk_first, uint32_t* __restrict__ rec_words) {
     const uint32_t r = blockIdx.x * blockDim.x + threadIdx.x;
     if (r >= n) return;
     const uint32_t pairs = *d_pairs;
     const uint32_t o0 = offsets[r], o1 = min(r + 1 < n ? offsets[r + 1] : pairs, pairs);
-    pair_off[sorted_ids[r]] = o0;
+    const uint32_t id = sorted_ids[r];
+    pair_off[id] = o0;
+    rec_words[16 * (size_t)id + 14] = o0;
     for (uint32_t c = (o0 + kEmitChunk - 1) / kEmitChunk; (size_t)c * kEmitChunk < o1; ++c) chunk_first[c] = r;
 }
 
@@ -651,7 +666,6 @@ __global__ __launch_bounds__(GSN_BLOCK, 6) void raster_fwd_kernel(
     __shared__ float4 s_c[GSN_BLOCK];
     __shared__ uint8_t s_list[NW][GSN_BLOCK];
     __shared__ uint32_t s_cnt[NW][NW];  // [band][loader wave]
-    __shared__ uint64_t s_em[NW][GSN_BLOCK];  // [wave][entry]: the wave's pixels that composited the entry
     const int tile = (int)order[blockIdx.x];
     const int tx = tile % cam.tiles_x, ty = tile / cam.tiles_x;
     const int px = tx * GSN_TILE + (threadIdx.x % GSN_TILE);
@@ -673,25 +687,23 @@ __global__ __launch_bounds__(GSN_BLOCK, 6) void raster_fwd_kernel(
     float4 na = make_float4(0.f, 0.f, 0.f, 0.f), nb = na, nc = na;
     bool nvalid = rg.x + threadIdx.x < rg.y;
     if (nvalid) {
-        const uint32_t id = ids[rg.x + threadIdx.x];
-        na = rec[id];
-        nb = rec[n + id];
-        nc = rec[2 * (size_t)n + id];
+        const float4* r = rec + 4 * (size_t)ids[rg.x + threadIdx.x];
+        na = r[0];
+        nb = r[1];
+        nc = r[2];
     }
     for (uint32_t base = rg.x; base < rg.y; base += GSN_BLOCK) {
         if (__syncthreads_count(done) == GSN_BLOCK) break;
-#pragma unroll
-        for (int w = 0; w < NW; ++w) s_em[w][threadIdx.x] = 0ull;
         const float4 a = na, b = nb, c4 = nc;
         const bool valid = nvalid;
         {
             const uint32_t e2 = base + GSN_BLOCK + threadIdx.x;
             nvalid = e2 < rg.y;
             if (nvalid) {
-                const uint32_t id = ids[e2];
-                na = rec[id];
-                nb = rec[n + id];
-                nc = rec[2 * (size_t)n + id];
+                const float4* r = rec + 4 * (size_t)ids[e2];
+                na = r[0];
+                nb = r[1];
+                nc = r[2];
             }
         }
         uint32_t bandmask = 0;
@@ -741,10 +753,6 @@ __global__ __launch_bounds__(GSN_BLOCK, 6) void raster_fwd_kernel(
                 done = true;
                 comp = false;
             }
-            // the wave's lanes still walking the list all hold entry j: one ballot is the entry's
-            // pixel mask for this band, written by the first of them
-            const uint64_t m = __ballot(comp);
-            if (lane == (int)__builtin_amdgcn_readfirstlane(lane)) s_em[wave][j] = m;
             if (comp) {
                 const double w = (double)(ev.alpha * T);
                 C0 += w * (double)b.w;
@@ -759,13 +767,10 @@ __global__ __launch_bounds__(GSN_BLOCK, 6) void raster_fwd_kernel(
         }
         const uint32_t batch = (base - rg.x) / GSN_BLOCK;
         if (masks && batch < (uint32_t)GSN_MASK_BATCHES) {
-            // pixel-major words [w][pixel], then entry-major words [wave][entry]
-            uint64_t* mb = masks + ((size_t)tile * GSN_MASK_BATCHES + batch) * 2 * NW * GSN_BLOCK + threadIdx.x;
+            // pixel-major words [w][pixel] (the backward pass rebuilds the per-(entry, wave) words from them)
+            uint64_t* mb = masks + ((size_t)tile * GSN_MASK_BATCHES + batch) * NW * GSN_BLOCK + threadIdx.x;
 #pragma unroll
             for (int w = 0; w < NW; ++w) mb[(size_t)w * GSN_BLOCK] = bits[w];
-            __syncthreads();
-#pragma unroll
-            for (int w = 0; w < NW; ++w) mb[(size_t)(NW + w) * GSN_BLOCK] = s_em[w][threadIdx.x];
         }
     }
     {
@@ -924,10 +929,11 @@ size_t radix_hist_bytes(uint32_t n) {
 
 void launch_emit_pairs(const uint32_t* sorted_ids, const uint32_t* offsets, uint32_t n, const uint32_t* d_pairs,
                        uint32_t cap, const uint2* rect, uint32_t tiles_x, uint32_t* keys, uint32_t* vals,
-                       uint32_t* pair_off, uint32_t* chunk_first, hipStream_t s) {
+                       uint32_t* pair_off, uint32_t* chunk_first, float4* rec, hipStream_t s) {
     if (n == 0) return;
     pair_off_kernel<<<(n + kThreads - 1) / kThreads, kThreads, 0, s>>>(sorted_ids, offsets, n, d_pairs, pair_off,
-                                                                       chunk_first);
+                                                                       chunk_first,
+                                                                       reinterpret_cast<uint32_t*>(rec));
     if (cap)
         emit_pairs_kernel<<<(uint32_t)emit_chunks(cap), kThreads, 0, s>>>(sorted_ids, offsets, n, d_pairs, rect,
                                                                         tiles_x, keys, vals, chunk_first);
@@ -945,6 +951,10 @@ void launch_pair_capacity(uint32_t* d_pairs, uint32_t cap, unsigned long long* s
 void launch_fill_u32_dev(uint32_t* p, uint32_t v, const uint32_t* d_count, uint32_t per_word, size_t cap,
                          hipStream_t s) {
     if (cap) fill_u32_dev_kernel<<<grid_for(cap), kThreads, 0, s>>>(p, v, d_count, per_word, cap);
+}
+
+void launch_records_out(const float4* rec, int n, float4* out, hipStream_t s) {
+    if (n > 0) records_out_kernel<<<(n + kThreads - 1) / kThreads, kThreads, 0, s>>>(rec, n, out);
 }
 
 void launch_copy_u32(uint32_t* dst, const uint32_t* src, size_t n, hipStream_t s) {

@@ -91,17 +91,11 @@ __device__ bool clamp_norm(int n, double* x, double radius) {
 // skipped (zero step, decisions -3).  Bits 0-12 are counted while profiling (GSN_COUNT_SOLVE_*),
 // bit 13 always (GSN_STAT_SKIPPED_NONFINITE).
 constexpr int EV_ESC = 0, EV_FALLBACK = 4, EV_CLAMP = 8, EV_SOLVED = 12, EV_NONFINITE = 13;
-constexpr int EV_PROFILED = 13;  // bits counted while profiling
+constexpr int EV_PROFILED = GSN_SOLVE_EVENTS;  // bits counted while profiling
+static_assert(GSN_COUNT_SOLVE_ESCALATED + GSN_SOLVE_EVENTS == GSN_COUNT_SOLVED + 1,
+              "solve event bits 0-12 map onto the counters GSN_COUNT_SOLVE_ESCALATED .. GSN_COUNT_SOLVED");
 __device__ __forceinline__ uint32_t decision_events(int group, int j) {
     return (j > 0 ? 1u << (EV_ESC + group) : 0u) | (j == -1 ? 1u << (EV_FALLBACK + group) : 0u);
-}
-
-// True when every block entry the solve of kernel k reads (base rows and the rows of the V view
-// slots) is finite.
-__device__ __forceinline__ bool blocks_finite(const float* __restrict__ blk, size_t N, int k, int V) {
-    float z = 0.f;  // stays 0 while every entry is finite: x * 0 is NaN for NaN and infinite x
-    for (int r = 0; r < GSN_BLK_BASE + GSN_BLK_VIEW * V; ++r) z += blk[(size_t)r * N + k] * 0.f;
-    return z == 0.f;
 }
 
 // Zero step and decisions -3 for a kernel skipped because of non-finite values.
@@ -128,8 +122,11 @@ __device__ __forceinline__ void count_solve_events(uint32_t ev, unsigned long lo
         if (__lane_id() == 0 && m) atomicAdd(&cnt[b], (uint32_t)__popcll(m));
     }
     __syncthreads();
+    // the workgroups add into GSN_SOLVE_SPREAD copies of the counters (summed by gsn_profile_read),
+    // so that thousands of workgroups do not serialise on thirteen addresses
+    unsigned long long* dst = prof + GSN_COUNT_N + (size_t)(blockIdx.x % GSN_SOLVE_SPREAD) * EV_PROFILED;
     if (threadIdx.x < EV_PROFILED && cnt[threadIdx.x])
-        atomicAdd(&prof[GSN_COUNT_SOLVE_ESCALATED + threadIdx.x], (unsigned long long)cnt[threadIdx.x]);
+        atomicAdd(&dst[threadIdx.x], (unsigned long long)cnt[threadIdx.x]);
 }
 
 // Cholesky solve of an m x m SPD system (m <= VM) held in a VM x VM register array (double).
@@ -303,18 +300,20 @@ __device__ __forceinline__ uint32_t solve_one(int k, const float* __restrict__ p
                                               float* __restrict__ st, int32_t* __restrict__ fl) {
     const size_t N = (size_t)n;
     const int NS = GSN_STEP_BASE + 3 * K;
-    auto B = [&](int row) { return (double)blk[(size_t)row * N + k]; };
-    if (!(B(29) > 0.0)) {
+    if (!(blk[29 * N + k] > 0.f)) {
         for (int r = 0; r < NS; ++r) st[(size_t)r * N + k] = 0.f;
         for (int r = 0; r < 5; ++r) fl[(size_t)r * N + k] = -2;
         return 0u;
     }
-    if (!blocks_finite(blk, N, k, V)) {
-        skip_nonfinite(st, fl, N, k, NS);
-        return 1u << EV_NONFINITE;
-    }
+    // chk stays 0 while every block entry the solve reads and every step component is finite
+    // (x * 0 is NaN exactly for NaN and infinite x)
+    double chk = 0.0;
+    auto B = [&](int row) {
+        const double v = (double)blk[(size_t)row * N + k];
+        chk += v * 0.0;
+        return v;
+    };
     uint32_t ev = 1u << EV_SOLVED;
-    double chk = 0.0;  // stays 0 while every step component is finite
     const double abs_scale = 1.0 / (3.0 * (double)o.npix_primary);
     double s[3];
     for (int a = 0; a < 3; ++a) s[a] = scale[a * N + k];
@@ -575,18 +574,19 @@ __device__ __forceinline__ uint32_t solve_one_mixed(int k, const float* __restri
                                                     unsigned long long* __restrict__ n_fp64) {
     const size_t N = (size_t)n;
     const int NS = GSN_STEP_BASE + 3 * K;
-    auto Bf = [&](int row) { return blk[(size_t)row * N + k]; };
-    if (!(Bf(29) > 0.f)) {
+    if (!(blk[29 * N + k] > 0.f)) {
         for (int r = 0; r < NS; ++r) st[(size_t)r * N + k] = 0.f;
         for (int r = 0; r < 5; ++r) fl[(size_t)r * N + k] = -2;
         return 0u;
     }
-    if (!blocks_finite(blk, N, k, V)) {
-        skip_nonfinite(st, fl, N, k, NS);
-        return 1u << EV_NONFINITE;
-    }
+    // chk stays 0 while every block entry the solve reads and every step component is finite
+    float chk = 0.f;
+    auto Bf = [&](int row) {
+        const float v = blk[(size_t)row * N + k];
+        chk += v * 0.f;
+        return v;
+    };
     uint32_t ev = 1u << EV_SOLVED;
-    float chk = 0.f;  // stays 0 while every step component is finite
     const float abs_scale = 1.0f / (3.0f * (float)o.npix_primary);
     float s[3];
     for (int a = 0; a < 3; ++a) s[a] = scale[a * N + k];

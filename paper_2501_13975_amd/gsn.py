@@ -48,7 +48,8 @@ def lib():
             "gsn_local_newton_solve_noalloc": [P, P, P, P, P, P],
             "gsn_apply_step": [P, P, P, P, P, ctypes.c_uint32],
             "gsn_first_order_step": [P, P, P, P, P, P, ctypes.c_uint32],
-            "gsn_step_features": [P, P, P, P, P, P, P],
+            "gsn_step_features": [P, P, P, P, P, P, P, P],
+            "gsn_neighbour_residual": [P, P, P],
             "gsn_solve_batched": [P, P, ctypes.c_int32],
             "gsn_sh_gram": [P, P, ctypes.c_int32, P],
             "gsn_solve_tune": [P, P, ctypes.c_int32, P, P],
@@ -349,11 +350,17 @@ class Context:
         self._check(lib().gsn_solve_graph_create(self.h, arr, len(items), ctypes.byref(h)))
         return SolveGraph(self, h)
 
-    def step_features(self, g, primary: CCamera, blocks: "Blocks", so: CSolveOpts, feat, ok):
-        """feat: device float [16, n]; ok: device uint8 [n]."""
+    def step_features(self, g, primary: CCamera, blocks: "Blocks", so: CSolveOpts, feat, ok, resid=None):
+        """feat: device float [17, n]; ok: device uint8 [n]; resid: device float [n] (the cached
+        neighbouring-view residuals) or None."""
         cg, cb = g.c(), blocks.c()
         self._check(lib().gsn_step_features(self.h, ctypes.byref(cg), ctypes.byref(primary), ctypes.byref(cb),
-                                            ctypes.byref(so), _ptr(feat), _ptr(ok)))
+                                            ctypes.byref(so), _ptr(resid), _ptr(feat), _ptr(ok)))
+
+    def neighbour_residual(self, blocks: "Blocks", resid):
+        """gsn_neighbour_residual: updates the cache resid (device float [n]) from full-rule blocks."""
+        cb = blocks.c()
+        self._check(lib().gsn_neighbour_residual(self.h, ctypes.byref(cb), _ptr(resid)))
 
     def step_labels(self, prim: "Steps", aug: "Steps", label, mask, ok=None, alpha=None, err=None):
         """label, mask: device float [5, n]; ok: device uint8 [n] feature status (or None); alpha: the
@@ -435,7 +442,7 @@ class Context:
         self._check(lib().gsn_downsample2x(self.h, _ptr(src), int(W), int(H), _ptr(dst)))
 
 
-GSN_MLP_PARAMS = 709
+GSN_MLP_IN, GSN_MLP_PARAMS = 17, 741
 
 
 class CMlp(ctypes.Structure):

@@ -151,25 +151,6 @@ class LocalNewtonTrainer:
                                   state=self.fo_state, beta1=beta1, beta2=beta2, eps=eps, group_mask=group_mask)
 
     # ------------------------------------------------------------ learned form
-    def enable_learned(self, params, every=4, lr=1e-3):
-        n = self.g.n
-        self.mlp = gsn.MLP(params, self.dev)
-        self.ctx.mlp_reset(self.mlp)
-        self.every = int(every)
-        self.lr = float(lr)
-        self.feat = torch.zeros(16, max(n, 1), dtype=torch.float32, device=self.dev)
-        self.ok = torch.zeros(max(n, 1), dtype=torch.uint8, device=self.dev)
-        self.alpha = torch.zeros(5, max(n, 1), dtype=torch.float32, device=self.dev)
-        self.label = torch.zeros(5, max(n, 1), dtype=torch.float32, device=self.dev)
-        self.mask = torch.zeros(5, max(n, 1), dtype=torch.float32, device=self.dev)
-        self.steps_prim = gsn.Steps(n, self.g.sh_degree, self.dev)
-        self.mlp_loss = torch.zeros(1, dtype=torch.float64, device=self.dev)
-        # over the full-rule sweeps: sum of |alpha_mlp - alpha_eff| and number of labelled entries
-        self.err = torch.zeros(2, dtype=torch.float64, device=self.dev)
-        # kernels whose features left the trained range on the current sweep
-        self.out_of_range = torch.zeros(1, dtype=torch.int32, device=self.dev)
-        self.fallback_sweeps = 0
-
     def _accumulate_primary(self, t):
         self.ctx.blocks_zero(self.blocks)
         fr = self.frames[0]
@@ -182,6 +163,64 @@ class LocalNewtonTrainer:
             self.ctx.render(self.g, self.chalf[j], self.ro, fr)
             self.ctx.accumulate_hessian(self.g, fr, self.half_targets[j], self.lo, slot, self.blocks, self.loss[slot])
 
+    def _learned_buffers(self):
+        n = self.g.n
+        if getattr(self, "feat", None) is not None:
+            return
+        self.feat = torch.zeros(gsn.GSN_MLP_IN, max(n, 1), dtype=torch.float32, device=self.dev)
+        # neighbouring-view residual of each kernel, cached from its last full-rule sweep (a feature)
+        self.resid = torch.zeros(max(n, 1), dtype=torch.float32, device=self.dev)
+        self.ok = torch.zeros(max(n, 1), dtype=torch.uint8, device=self.dev)
+        self.alpha = torch.zeros(5, max(n, 1), dtype=torch.float32, device=self.dev)
+        self.label = torch.zeros(5, max(n, 1), dtype=torch.float32, device=self.dev)
+        self.mask = torch.zeros(5, max(n, 1), dtype=torch.float32, device=self.dev)
+        self.steps_prim = gsn.Steps(n, self.g.sh_degree, self.dev)
+        # over the full-rule sweeps: sum of |alpha_mlp - alpha_eff| and number of labelled entries
+        self.err = torch.zeros(2, dtype=torch.float64, device=self.dev)
+
+    def enable_learned(self, params, every=4, lr=1e-3, alpha_mode="mlp", alpha_const=1.0, mlp=None):
+        """Learned form.  alpha_mode "mlp": the network's per-kernel scales; the controls "one" (the
+        primary-only Newton step unscaled) and "const" (every kernel and group scaled by alpha_const)
+        keep the same schedule of full-rule sweeps.  mlp: a network (gsn.MLP) to start from, e.g. one
+        pre-trained on logged plain sweeps; else one from params."""
+        self._learned_buffers()
+        if mlp is None:
+            mlp = gsn.MLP(params, self.dev)
+            self.ctx.mlp_reset(mlp)
+        self.mlp = mlp
+        self.every = int(every)
+        self.lr = float(lr)
+        self.alpha_mode = alpha_mode
+        self.alpha_const = float(alpha_const)
+        self.mlp_loss = torch.zeros(1, dtype=torch.float64, device=self.dev)
+        # kernels whose features left the trained range on the current sweep
+        self.out_of_range = torch.zeros(1, dtype=torch.int32, device=self.dev)
+        self.fallback_sweeps = 0
+
+    def log_sweep(self, t, log, group_mask=31, max_rows=50000, seed=0):
+        """A plain (full-rule) sweep on image t that also logs, for the learned form, the features of
+        the primary-only blocks and the labels alpha_eff comparing the primary-only and full-rule
+        steps: appends (features [17, m], labels [5, m], mask [5, m]) of at most max_rows labelled
+        kernels (a seeded random subset) to `log`, then applies the full-rule step."""
+        self._learned_buffers()
+        so = self.solve_opts(t)
+        n = self.g.n
+        self._accumulate_primary(t)
+        self.ctx.local_newton_solve(self.g, self.ccams[t], self.blocks, so, self.steps_prim)
+        self.ctx.step_features(self.g, self.ccams[t], self.blocks, so, self.feat[:, :n], self.ok[:n],
+                               resid=self.resid[:n])
+        self._accumulate_secondaries(t)
+        if self.n_secondary:
+            self.ctx.neighbour_residual(self.blocks, self.resid[:n])
+        self.ctx.local_newton_solve(self.g, self.ccams[t], self.blocks, so, self.steps)
+        self.ctx.step_labels(self.steps_prim, self.steps, self.label[:, :n], self.mask[:, :n], ok=self.ok[:n])
+        rows = torch.nonzero(self.mask[:, :n].amax(0) > 0).flatten()
+        if rows.numel() > max_rows:
+            gen = torch.Generator(device=self.dev).manual_seed(int(seed))
+            rows = rows[torch.randperm(rows.numel(), generator=gen, device=self.dev)[:max_rows]]
+        log.append((self.feat[:, rows].clone(), self.label[:, rows].clone(), self.mask[:, rows].clone()))
+        self.ctx.apply_step(self.g, self.steps, so, group_mask)
+
     def sweep_learned(self, t, i, group_mask=31, check_range=True):
         """Sweep i of the learned form on training image t.  Every `every`-th sweep runs the full
         rule; so does a learned sweep on which a kernel's features leave the trained range (the
@@ -192,24 +231,33 @@ class LocalNewtonTrainer:
         self._accumulate_primary(t)
         full = i % self.every == 0
         self.ctx.local_newton_solve(self.g, self.ccams[t], self.blocks, so, self.steps)
-        self.ctx.step_features(self.g, self.ccams[t], self.blocks, so, self.feat[:, :n], self.ok[:n])
+        self.ctx.step_features(self.g, self.ccams[t], self.blocks, so, self.feat[:, :n], self.ok[:n],
+                               resid=self.resid[:n])
         self.out_of_range.zero_()
         self.ctx.mlp_infer(self.mlp, self.feat[:, :n], self.ok[:n], self.alpha[:, :n], self.out_of_range)
         if not full and check_range and int(self.out_of_range.item()) > 0:
             full = True
             self.fallback_sweeps += 1
         if not full:
-            self.ctx.apply_step(self.g, self.steps, so, group_mask, scale=self.alpha[:, :n])
+            if self.alpha_mode == "one":
+                self.ctx.apply_step(self.g, self.steps, so, group_mask)
+            else:
+                if self.alpha_mode == "const":
+                    self.alpha.fill_(self.alpha_const)
+                self.ctx.apply_step(self.g, self.steps, so, group_mask, scale=self.alpha[:, :n])
             return
         # full rule: the secondaries' blocks join the primary's; label and train, then apply the full step
         self.steps, self.steps_prim = self.steps_prim, self.steps
         self._accumulate_secondaries(t)
+        if self.n_secondary:
+            self.ctx.neighbour_residual(self.blocks, self.resid[:n])
         self.ctx.local_newton_solve(self.g, self.ccams[t], self.blocks, so, self.steps)
         self.ctx.step_labels(self.steps_prim, self.steps, self.label[:, :n], self.mask[:, :n], ok=self.ok[:n],
                              alpha=self.alpha[:, :n], err=self.err)
         self.ctx.mlp_train_step(self.mlp, self.feat[:, :n], self.label[:, :n], self.mask[:, :n], lr=self.lr,
                                 loss=self.mlp_loss)
         self.ctx.apply_step(self.g, self.steps, so, group_mask)
+
 
     def learned_error(self):
         """Mean |alpha_mlp - alpha_eff| over the labelled entries of the full-rule sweeps so far."""
@@ -222,3 +270,28 @@ class LocalNewtonTrainer:
         for f in self.frames:
             f.close()
         self.ctx.close()
+
+
+def pretrain(ctx, mlp, logs, epochs=5, batch=8192, lr=1e-2, seed=0):
+    """Trains the step-scale network on logged plain sweeps (log_sweep): Adam steps of the library
+    on shuffled mini-batches of the logged (features, labels, mask) rows.  Returns the mean loss
+    of each epoch."""
+    F = torch.cat([x[0] for x in logs], 1)
+    Lb = torch.cat([x[1] for x in logs], 1)
+    M = torch.cat([x[2] for x in logs], 1)
+    m = F.shape[1]
+    gen = torch.Generator(device=F.device).manual_seed(int(seed))
+    loss = torch.zeros(1, dtype=torch.float64, device=F.device)
+    curve = []
+    for _ in range(epochs):
+        perm = torch.randperm(m, generator=gen, device=F.device)
+        tot = torch.zeros(1, dtype=torch.float64, device=F.device)
+        nb = 0
+        for b0 in range(0, m, batch):
+            idx = perm[b0:b0 + batch]
+            ctx.mlp_train_step(mlp, F[:, idx].contiguous(), Lb[:, idx].contiguous(), M[:, idx].contiguous(), lr=lr,
+                               loss=loss)
+            tot += loss
+            nb += 1
+        curve.append(float((tot / max(nb, 1)).cpu()))
+    return curve

@@ -1,14 +1,14 @@
 """Seeded initial weights of the step-scale network (random inputs shared by the
 library and the oracle; no method arithmetic).
 
-Layout (709 values): W1 [32][16] row-major, b1 [32], W2 [5][32] row-major, b2 [5].
+Layout (741 values): W1 [32][17] row-major, b1 [32], W2 [5][32] row-major, b2 [5].
 He-normal first layer, small second layer, zero biases.
 """
 from __future__ import annotations
 
 import numpy as np
 
-N_IN, N_HID, N_OUT = 16, 32, 5
+N_IN, N_HID, N_OUT = 17, 32, 5
 
 
 def init_params(seed: int = 0) -> np.ndarray:

@@ -50,20 +50,32 @@ def test_features_parity(gsn, ctx, sweep_case):
     cfg, t, res = sweep_case
     g, cam, o = cfg.init, cfg.cams[t], res["opts"]
     S1 = O.sum_blocks(res["per_view"][:1]).astype(np.float32).astype(np.float64)
-    want, ok_want = L.features(g, cam, o, S1, 1)
     dg = gsn.DeviceGaussians.from_host(g)
     b = _gpu_blocks(gsn, S1, 1, ctx.device)
     n = g.n
-    feat = torch.zeros(16, n, device=ctx.device)
+    feat = torch.zeros(17, n, device=ctx.device)
     ok = torch.zeros(n, dtype=torch.uint8, device=ctx.device)
     so = gsn.solve_opts(cam.width * cam.height)
-    ctx.step_features(dg, gsn.camera(cam), b, so, feat, ok)
+    # the cached residual of a full-rule sweep (all four views), by the library and by the oracle
+    V = len(res["per_view"])
+    Sfull = O.sum_blocks(res["per_view"]).astype(np.float32).astype(np.float64)
+    prev = np.random.default_rng(1).uniform(0.0, 2.0, n).astype(np.float32)
+    r_want = L.neighbour_residual(Sfull, V, prev.astype(np.float64))
+    r_dev = torch.tensor(prev, device=ctx.device)
+    ctx.neighbour_residual(_gpu_blocks(gsn, Sfull, V, ctx.device), r_dev)
+    r_got = r_dev.cpu().numpy().astype(np.float64)
+    upd = r_want != prev
+    assert upd.sum() > 500
+    assert np.array_equal(r_got[~upd], prev[~upd].astype(np.float64))
+    assert np.max(np.abs(r_got[upd] - r_want[upd]) / np.maximum(r_want[upd], 1e-30)) < 1e-5
+    want, ok_want = L.features(g, cam, o, S1, 1, resid=r_got)
+    ctx.step_features(dg, gsn.camera(cam), b, so, feat, ok, resid=r_dev)
     got = feat.cpu().numpy().T.astype(np.float64)
     okg = ok.cpu().numpy()
     vis = S1[:, 38] > 0
     assert vis.sum() > 1000
     # magnitudes: 1e-5 in feature units is a relative error of 2.3e-4 in the summarised quantity
-    for col in (0, 3, 5, 8, 9, 10, 11, 12, 13, 14, 15):
+    for col in (0, 3, 5, 8, 9, 10, 11, 12, 13, 14, 15, 16):
         assert np.max(np.abs(got[vis, col] - want[vis, col])) < 1e-5, col
     # smaller eigenvalues and signs where the smaller eigenvalue is determined at float precision
     for lo, hi, sg in ((1, 0, 2), (6, 5, 7)):
@@ -157,10 +169,10 @@ def test_mlp_train_steps_parity(gsn, ctx):
     dl = torch.tensor(lab.T.copy(), device=ctx.device)
     dm = torch.tensor(msk.T.copy(), device=ctx.device)
     loss = torch.zeros(1, dtype=torch.float64, device=ctx.device)
-    grad = torch.zeros(709, device=ctx.device)
+    grad = torch.zeros(gsn.GSN_MLP_PARAMS, device=ctx.device)
     p = p0.astype(np.float64)
-    m = np.zeros(709)
-    v = np.zeros(709)
+    m = np.zeros(L.N_PARAMS)
+    v = np.zeros(L.N_PARAMS)
     lr = 1e-2
     for step in range(1, 4):
         # the oracle continues from the library's float32 state, so each step is compared alone
@@ -215,4 +227,43 @@ def test_learned_form_runs(gsn, ctx):
     assert e is not None and np.isfinite(e)
     for x in (dg.pos, dg.rot, dg.scale, dg.opac, dg.sh):
         assert torch.isfinite(x).all()
+    tr.close()
+
+
+def test_trained_network_predicts_the_overshoot_rule(gsn, ctx):
+    """What the network gains over the method without it: trained on (features, alpha_eff) rows that
+    plain full-rule sweeps log, it predicts the scale the overshoot rule applies to the primary-only
+    step on held-out views better than the primary-only step itself (alpha = 1) and better than the
+    best constant (the logged mean label of each group)."""
+    from paper_2501_13975_amd.train import LocalNewtonTrainer, pretrain
+    cfg = make_config("c1", n=6000, width=200, height=150, n_views=12)
+    tg = [torch.tensor(O.render(cfg.gt, c, O.opts()).img.astype(np.float32), device=ctx.device) for c in cfg.cams]
+    dg = gsn.DeviceGaussians.from_host(cfg.init)
+    tr = LocalNewtonTrainer(dg, cfg.cams, tg, 3, solve_kw={"step_frac": 0.3})
+    train_log, held = [], []
+    for i, t in enumerate(range(8)):
+        tr.log_sweep(t, train_log, seed=i)
+    for t in range(8, 12):
+        tr.log_sweep(t, held, seed=100 + t)
+    mlp = gsn.MLP(init_params(0), ctx.device)
+    ctx.mlp_reset(mlp)
+    curve = pretrain(ctx, mlp, train_log, epochs=40, batch=4096, lr=1e-2)
+    print(f"\n[gain] pretraining loss per epoch: first {curve[0]:.4f} last {curve[-1]:.4f}", flush=True)
+    assert curve[-1] < curve[0]
+    F = torch.cat([x[0] for x in held], 1).contiguous()
+    Lb = torch.cat([x[1] for x in held], 1).cpu().numpy()
+    M = torch.cat([x[2] for x in held], 1).cpu().numpy()
+    m = F.shape[1]
+    assert m > 1000
+    alpha = torch.zeros(5, m, device=ctx.device)
+    ctx.mlp_infer(mlp, F, torch.ones(m, dtype=torch.uint8, device=ctx.device), alpha)
+    a = alpha.cpu().numpy()
+    Lt = torch.cat([x[1] for x in train_log], 1).cpu().numpy()
+    Mt = torch.cat([x[2] for x in train_log], 1).cpu().numpy()
+    mean = (Lt * Mt).sum(1) / Mt.sum(1)
+    err = lambda pred: float((np.abs(pred - Lb) * M).sum() / M.sum())  # noqa: E731
+    e_mlp, e_one, e_mean = err(a), err(np.ones_like(Lb)), err(np.broadcast_to(mean[:, None], Lb.shape))
+    print(f"[gain] held-out mean |alpha - alpha_eff|: network {e_mlp:.4f}, alpha=1 {e_one:.4f}, "
+          f"mean label {e_mean:.4f} ({int(M.sum())} entries)", flush=True)
+    assert e_mlp < e_one and e_mlp < e_mean
     tr.close()

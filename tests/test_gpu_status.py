@@ -96,7 +96,11 @@ def test_nonfinite_blocks_are_skipped_and_counted(gsn, case):
     tr.ctx.sync_status()
     vis = np.nonzero(rf[0] >= -1)[0]
     assert vis.size > 1000
-    hit = vis[[3, 50, 400]]
+    cov1 = tr.blocks.view()[30 + 10 * 1 + 9].cpu().numpy()
+    seen1 = vis[cov1[vis] > 0]  # kernels the first secondary view also covers (its rows are read)
+    assert seen1.size > 100
+    hit = np.array([vis[3], vis[50], seen1[seen1.size // 2]])
+    assert np.unique(hit).size == 3
     bv = tr.blocks.view()
     with torch.no_grad():
         bv[4, int(hit[0])] = float("nan")       # H_p entry

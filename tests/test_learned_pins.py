@@ -18,12 +18,12 @@ def _data(n=64, seed=3):
 
 
 def test_param_count():
-    assert L.N_PARAMS == 709 and init_params().size == 709
+    assert L.N_PARAMS == 32 * 17 + 32 + 5 * 32 + 5 == 741 and init_params().size == 741
 
 
 def test_loss_gradient_matches_central_differences():
     F, lab, msk = _data()
-    p = init_params(5).astype(np.float64) + 0.3 * np.random.default_rng(0).standard_normal(709)
+    p = init_params(5).astype(np.float64) + 0.3 * np.random.default_rng(0).standard_normal(L.N_PARAMS)
     _, g = L.loss_grad(p, F, lab, msk)
     h = 1e-6
     fd = np.zeros_like(p)
@@ -46,17 +46,17 @@ def test_output_range_and_zero_network():
     F, _, _ = _data()
     a = L.forward(init_params(1), F * 50.0)
     assert np.all(a > 0.0) and np.all(a < 1.5)
-    assert np.allclose(L.forward(np.zeros(709), F), 0.75)
+    assert np.allclose(L.forward(np.zeros(L.N_PARAMS), F), 0.75)
 
 
 def test_adam_closed_form_with_constant_gradient():
     # with a constant gradient the bias-corrected moments are g and g^2 at every step:
     # each update is -lr g / (|g| + eps)
     rng = np.random.default_rng(4)
-    g = rng.standard_normal(709)
-    p = rng.standard_normal(709)
-    m = np.zeros(709)
-    v = np.zeros(709)
+    g = rng.standard_normal(L.N_PARAMS)
+    p = rng.standard_normal(L.N_PARAMS)
+    m = np.zeros(L.N_PARAMS)
+    v = np.zeros(L.N_PARAMS)
     p0 = p.copy()
     for t in range(1, 6):
         p, m, v = L.adam(p, m, v, t, g, lr=1e-2)
@@ -67,8 +67,8 @@ def test_training_reduces_loss():
     F, _, msk = _data(256)
     target = L.forward(init_params(9).astype(np.float64) * 2.0, F)
     p = init_params(0).astype(np.float64)
-    m = np.zeros(709)
-    v = np.zeros(709)
+    m = np.zeros(L.N_PARAMS)
+    v = np.zeros(L.N_PARAMS)
     l0 = L.loss_grad(p, F, target, msk)[0]
     for t in range(1, 301):
         _, gr = L.loss_grad(p, F, target, msk)
@@ -125,6 +125,31 @@ def test_features_of_isotropic_blocks():
     al = 1e-2 / (3.0 * 120 * 90)
     assert np.allclose(F[:, 8], Lg(np.abs(2e-3 + al * (1 / sig ** 2 + 1 / (1 - sig) ** 2))))
     assert np.all(ok == 1)
+    # the cached neighbouring-view residual enters as feature 16 (0 without a cache)
+    assert np.all(F[:, 16] == -3.0)
+    resid = np.linspace(1e-3, 10.0, n)
+    F2, _ = L.features(g, cam, o, S, V, resid=resid)
+    assert np.allclose(F2[:, 16], Lg(resid)) and np.array_equal(F2[:, :16], F[:, :16])
+    # a feature out of [-3, 3] marks the kernel out of range (code 2); unseen kernels are 0
+    F3, ok3 = L.features(g, cam, o, S, V, resid=np.full(n, 1e40))
+    assert np.all(ok3 == 2) and np.all(F3[:, 16] == 3.0)
     S[:, 38] = 0.0
     _, ok0 = L.features(g, cam, o, S, V)
     assert np.all(ok0 == 0)
+
+
+def test_neighbour_residual_of_constructed_views():
+    # three view slots: the residual is the secondaries' colour-gradient norms over the primary's
+    n, V = 5, 3
+    S = np.zeros((n, 39 + 10 * V))
+    S[:, 38] = [1.0, 1.0, 1.0, 0.0, 1.0]  # kernel 3: not seen by the primary
+    g0 = np.array([[3.0, 4.0, 0.0]] * n)  # |gamma_0| = 5
+    S[:, 39:42] = g0
+    S[:, 39 + 9] = S[:, 38]
+    S[:, 49:52] = [[0.0, 0.0, 2.0]] * n  # view 1: |gamma| = 2
+    S[:, 49 + 9] = [1.0, 0.0, 1.0, 1.0, 0.0]
+    S[:, 59:62] = [[1.0, 2.0, 2.0]] * n  # view 2: |gamma| = 3
+    S[:, 59 + 9] = [1.0, 0.0, 0.0, 1.0, 0.0]
+    prev = np.full(n, 7.0)
+    r = L.neighbour_residual(S, V, prev)
+    assert np.allclose(r, [(2 + 3) / 5, 7.0, 2 / 5, 7.0, 7.0], rtol=1e-14)
