@@ -30,6 +30,8 @@ METRIC = "Newton sweeps/s, 1M Gaussians @1080p: plain FP32 vs mixed+learned at e
 # The unpacked rate, 78.6 TFLOP/s (also the FP64 vector peak), is reported beside it: this library
 # is built without packed FP32 instructions, so that is the rate its FP32 code can reach.
 PEAK_HBM_GBS = 8000.0
+# every kernel's steps times its overlap share (gsn_solve_opts.overlap_scale; --no-overlap turns it off)
+OVERLAP = 1
 PEAK_ALU_TFLOPS = 157.3
 PEAK_ALU_UNPACKED_TFLOPS = 78.6
 
@@ -96,7 +98,7 @@ def _trainer(cfg, targets, dev, learned_every=0, step_frac=1.0, n_secondary=None
     from paper_2501_13975_amd.train import LocalNewtonTrainer
     from synth.mlp_init import init_params
     g = gsn.DeviceGaussians.from_host(cfg.init, dev)
-    kw = {"step_frac": step_frac, "precision": 1 if learned_every else 0}
+    kw = {"step_frac": step_frac, "precision": 1 if learned_every else 0, "overlap": OVERLAP}
     K = cfg.n_secondary if n_secondary is None else n_secondary
     tr = LocalNewtonTrainer(g, cfg.cams, targets, n_secondary=K, solve_kw=kw, gauss_newton=gauss_newton)
     if learned_every:
@@ -202,56 +204,147 @@ def _psnr(tr, targets, dev):
     return float(torch.stack(vals).mean().cpu())
 
 
-def _equal_psnr(cfg, targets, dev, epochs, every, mask, step_frac, checks_per_epoch=5):
-    """Plain form for `epochs` epochs sets the target PSNR; the learned form runs until it reaches
-    it (PSNR checked after every fifth of an epoch, at most 3x as many epochs).  Times cover the
-    sweeps only."""
+def _curve(tr, nv, max_epochs, checks, step, targets, dev, target=None, first_epoch=0):
+    """Sweeps epoch by epoch in the seeded view order, the mean PSNR over all views checked after
+    every 1/checks of an epoch.  Returns [(sweeps, seconds of sweeps, psnr)], stopping at the first
+    check at or above target when one is given."""
     import numpy as np
     import torch
 
     from synth.scenes import view_order
+    out, spent, i = [], 0.0, 0
+    for e in range(first_epoch, first_epoch + max_epochs):
+        order = view_order(nv, e)
+        bounds = np.linspace(0, nv, checks + 1).astype(int)
+        for c in range(checks):
+            torch.cuda.synchronize(dev)
+            t0 = time.perf_counter()
+            for t in order[bounds[c]:bounds[c + 1]]:
+                step(int(t), i)
+                i += 1
+            torch.cuda.synchronize(dev)
+            spent += time.perf_counter() - t0
+            out.append((i, spent, _psnr(tr, targets, dev)))
+            if target is not None and out[-1][2] >= target:
+                return out
+    return out
+
+
+def _first_crossing(curve, target):
+    for sweeps, secs, p in curve:
+        if p >= target:
+            return sweeps, secs
+    return None, None
+
+
+def _logs(cfg, targets, dev, sweeps, mask, step_frac, seed=0):
+    """(features, labels, mask) rows logged by plain full-rule sweeps (the learned form's training
+    data), `sweeps` sweeps from the initial state in the seeded view order."""
+    from synth.scenes import view_order
+    tr = _trainer(cfg, targets, dev, 0, step_frac)
+    log = []
+    order = view_order(len(cfg.cams), 0)
+    for i in range(sweeps):
+        tr.log_sweep(int(order[i % len(order)]), log, mask, max_rows=20000, seed=seed + i)
+    tr.close()
+    return log
+
+
+def _pretrained(logs, dev, epochs=20):
+    """A step-scale network trained by the library's Adam kernels on logged plain sweeps."""
+    import torch
+
+    from paper_2501_13975_amd import gsn
+    from paper_2501_13975_amd.train import pretrain
+    from synth.mlp_init import init_params
+    ctx = gsn.Context(dev)
+    mlp = gsn.MLP(init_params(0), dev)
+    ctx.mlp_reset(mlp)
+    curve = pretrain(ctx, mlp, logs, epochs=epochs, batch=8192, lr=1e-2)
+    torch.cuda.synchronize(dev)
+    ctx.close()
+    Lb = torch.cat([x[1] for x in logs], 1)
+    M = torch.cat([x[2] for x in logs], 1)
+    mean = ((Lb * M).sum(1) / M.sum(1).clamp(min=1)).cpu().numpy()
+    return mlp.params.cpu().numpy(), curve, mean
+
+
+def _equal_psnr(cfg, targets, dev, epochs, every, mask, step_frac, params, label_mean, checks=5):
+    """Plain form for `epochs` epochs sets the target PSNR (its value after the last epoch); every form
+    is checked after each 1/checks of an epoch and timed to its first check at or above the target
+    (sweeps only).  The learned form starts from the pre-trained network; at the learned form's sweep
+    count the controls alpha = 1 (the primary-only step) and alpha = the mean logged label run the
+    same schedule, to show what the network adds."""
+    import numpy as np
+
+    from paper_2501_13975_amd import gsn
     nv = len(cfg.cams)
     out = {"epochs_plain": epochs, "learned_every": every, "group_mask": mask, "step_frac": step_frac,
-           "psnr_checks_per_epoch": checks_per_epoch}
-    for form in ("plain", "learned"):
-        tr = _trainer(cfg, targets, dev, every if form == "learned" else 0, step_frac)
-        out.setdefault("initial_psnr", round(_psnr(tr, targets, dev), 4))
-        spent, psnr, i = 0.0, None, 0
-        target = out.get("target_psnr")
-        max_e = epochs if form == "plain" else 3 * epochs
-        done = False
-        for e in range(max_e):
-            order = view_order(nv, e)
-            bounds = np.linspace(0, nv, checks_per_epoch + 1).astype(int)
-            for c in range(checks_per_epoch):
-                torch.cuda.synchronize(dev)
-                t0 = time.perf_counter()
-                for t in order[bounds[c]:bounds[c + 1]]:
-                    _sweep(tr, int(t), i, form == "learned", mask)
-                    i += 1
-                torch.cuda.synchronize(dev)
-                spent += time.perf_counter() - t0
-                if form == "learned" or c == checks_per_epoch - 1:
-                    psnr = _psnr(tr, targets, dev)
-                if form == "learned" and psnr >= target:
-                    done = True
-                    break
-            log(f"[bench] {form} epoch {e + 1}: PSNR {psnr:.3f} dB, {spent:.2f}s of sweeps")
-            if done:
-                break
-        if form == "plain":
-            out["target_psnr"] = round(psnr, 4)
-            out["plain_seconds"] = round(spent, 3)
-            out["plain_sweeps"] = i
+           "psnr_checks_per_epoch": checks}
+    tr = _trainer(cfg, targets, dev, 0, step_frac, reserve=True)
+    out["initial_psnr"] = round(_psnr(tr, targets, dev), 4)
+    pc = _curve(tr, nv, epochs, checks, lambda t, i: tr.sweep(t, mask), targets, dev)
+    tr.close()
+    target = pc[-1][2]
+    ps, psec = _first_crossing(pc, target)
+    out.update(target_psnr=round(target, 4), plain_curve=[round(x[2], 3) for x in pc], plain_sweeps=ps,
+               plain_seconds=round(psec, 3))
+    log(f"[bench] plain: target {target:.3f} dB after {pc[-1][0]} sweeps; first reached after {ps} ({psec:.2f}s)")
+    runs = {}
+    for mode in ("mlp", "one", "const"):
+        tr = _trainer(cfg, targets, dev, 0, step_frac, reserve=True)
+        tr.enable_learned(None, every=every, lr=1e-2, alpha_mode=mode, alpha_const=float(np.mean(label_mean)),
+                          mlp=_mlp_from(params, dev, tr))
+        step = lambda t, i: tr.sweep_learned(t, i, mask)  # noqa: E731
+        if mode == "mlp":
+            lc = _curve(tr, nv, 3 * epochs, checks, step, targets, dev, target=target)
+            ls, lsec = _first_crossing(lc, target)
+            runs[mode] = {"curve": [round(x[2], 3) for x in lc], "sweeps": lc[-1][0], "seconds": round(lc[-1][1], 3),
+                          "psnr": round(lc[-1][2], 4), "reached_target": ls is not None,
+                          "mean_abs_alpha_error": tr.learned_error(), "fallback_sweeps": tr.fallback_sweeps}
+            budget = lc[-1][0]
         else:
-            out["learned_psnr"] = round(psnr, 4)
-            out["learned_seconds"] = round(spent, 3)
-            out["learned_sweeps"] = i
-            out["learned_reached_target"] = bool(psnr >= target)
-            out["mean_abs_alpha_error"] = tr.learned_error()
-            out["speedup_at_equal_psnr"] = (round(out["plain_seconds"] / spent, 3)
-                                            if psnr >= target else None)
+            # the same number of sweeps as the network's run, same schedule of full-rule sweeps
+            from synth.scenes import view_order
+            i = 0
+            for e in range(3 * epochs):
+                for t in view_order(nv, e):
+                    if i >= budget:
+                        break
+                    tr.sweep_learned(int(t), i, mask)
+                    i += 1
+            runs[mode] = {"sweeps": i, "psnr": round(_psnr(tr, targets, dev), 4)}
         tr.close()
+        log(f"[bench] learned form, alpha {mode}: {runs[mode]}")
+    out["learned"] = runs["mlp"]
+    out["controls_at_equal_sweeps"] = {"alpha_one": runs["one"], "alpha_mean_label": runs["const"],
+                                       "alpha_mean_label_value": [round(float(x), 4) for x in label_mean]}
+    out["speedup_at_equal_psnr"] = (round(psec / runs["mlp"]["seconds"], 3) if runs["mlp"]["reached_target"]
+                                    else None)
+    return out
+
+
+def _mlp_from(params, dev, tr):
+    """A fresh network state (zero Adam moments) with the given master weights."""
+    from paper_2501_13975_amd import gsn
+    m = gsn.MLP(params, dev)
+    tr.ctx.mlp_reset(m)
+    return m
+
+
+def _c4_leg(dev, every, mask, step_frac, params, label_mean, epochs=1):
+    """The largest configuration: 3M kernels, 300 cameras at 1920x1080 (3 half-resolution
+    secondaries), plain form against the learned form started from the network pre-trained on
+    logged plain sweeps of the smaller scenes, timed to equal PSNR."""
+    from synth.scenes import make_config
+    t0 = time.time()
+    cfg = make_config("c4")
+    targets = _targets(cfg, dev)
+    log(f"[bench] c4: {cfg.n} kernels, {len(cfg.cams)} cameras ready ({time.time() - t0:.1f}s)")
+    out = _equal_psnr(cfg, targets, dev, epochs, every, mask, step_frac, params, label_mean)
+    out["workload"] = (f"{cfg.n} Gaussians SH3, {len(cfg.cams)} cameras at {cfg.width}x{cfg.height}, "
+                       f"{cfg.n_secondary} half-resolution secondaries")
+    del targets
     return out
 
 
@@ -366,56 +459,48 @@ def _order_leg(dev, epochs, step_frac):
 ADAM_LR = (1.6e-4, 1e-3, 1e-4, 1.25e-2, 2.5e-3)
 
 
-def _first_order_leg(dev, newton_epochs, max_epochs, mask, step_frac):
+def _first_order_leg(dev, newton_epochs, max_epochs, mask, step_frac, checks=5):
     """Newton sweeps against Adam iterations on the same gradients, 100k-kernel scene (Sec. 1
     and Sec. 5 claim far fewer Newton iterations than first-order ones).  The Newton form
-    (jacobi, 3 secondaries) trains `newton_epochs` epochs and sets the target PSNR; Adam (the
-    primary view's gradient, one image per iteration) runs with the learning rates ADAM_LR
-    scaled by 0.3, 1 and 3 until it reaches the target or `max_epochs` epochs."""
-    import torch
-
-    from synth.scenes import make_config, view_order
+    (jacobi, 3 secondaries) trains `newton_epochs` epochs and sets the target PSNR (its value after
+    the last epoch); Adam (the primary view's gradient, one image per iteration) runs with the
+    learning rates ADAM_LR scaled by 0.3, 1 and 3 until it reaches the target or `max_epochs`
+    epochs.  Every form is checked after each 1/checks of an epoch; iterations and seconds are taken
+    at the first check at or above the target."""
+    from synth.scenes import make_config
     cfg = make_config("c1")
     targets = _targets(cfg, dev)
     nv = len(cfg.cams)
     out = {"workload": f"{cfg.n} Gaussians SH3, {nv} cameras at {cfg.width}x{cfg.height}",
-           "group_mask": mask, "newton_step_frac": step_frac, "adam_lr": list(ADAM_LR)}
+           "group_mask": mask, "newton_step_frac": step_frac, "adam_lr": list(ADAM_LR), "psnr_checks_per_epoch": checks}
     tr = _trainer(cfg, targets, dev, 0, step_frac)
     out["psnr_initial"] = round(_psnr(tr, targets, dev), 4)
-    spent = 0.0
-    for e in range(newton_epochs):
-        torch.cuda.synchronize(dev)
-        t0 = time.perf_counter()
-        for t in view_order(nv, e):
-            tr.sweep(int(t), mask)
-        torch.cuda.synchronize(dev)
-        spent += time.perf_counter() - t0
-    target = _psnr(tr, targets, dev)
+    nc = _curve(tr, nv, newton_epochs, checks, lambda t, i: tr.sweep(t, mask), targets, dev)
     tr.close()
-    out["newton"] = {"sweeps": newton_epochs * nv, "psnr": round(target, 4), "seconds": round(spent, 3)}
+    target = nc[-1][2]
+    ns, nsec = _first_crossing(nc, target)
+    out["newton"] = {"curve": [round(x[2], 4) for x in nc], "psnr": round(target, 4), "sweeps_to_target": ns,
+                     "seconds_to_target": round(nsec, 4)}
     runs = {}
     for f in (0.3, 1.0, 3.0):
         lr = [x * f for x in ADAM_LR]
         tr = _trainer(cfg, targets, dev, 0, 1.0, n_secondary=0)
-        spent, curve, reached = 0.0, [], None
-        for e in range(max_epochs):
-            torch.cuda.synchronize(dev)
-            t0 = time.perf_counter()
-            for t in view_order(nv, e):
-                tr.sweep_first_order(int(t), lr, adam=True, group_mask=mask)
-            torch.cuda.synchronize(dev)
-            spent += time.perf_counter() - t0
-            p = _psnr(tr, targets, dev)
-            curve.append(round(p, 4))
-            if p >= target:
-                reached = (e + 1) * nv
-                break
+        ac = _curve(tr, nv, max_epochs, checks,
+                    lambda t, i: tr.sweep_first_order(t, lr, adam=True, group_mask=mask), targets, dev, target=target)
         tr.close()
-        runs[f"lr_x{f:g}"] = {"psnr_per_epoch": curve, "iterations_to_target": reached, "seconds": round(spent, 3)}
+        its, secs = _first_crossing(ac, target)
+        runs[f"lr_x{f:g}"] = {"curve": [round(x[2], 4) for x in ac], "iterations_to_target": its,
+                              "seconds_to_target": None if secs is None else round(secs, 4),
+                              "best_psnr": round(max(x[2] for x in ac), 4)}
         log(f"[bench] adam lr x{f:g}: {runs[f'lr_x{f:g}']}")
     out["adam"] = runs
-    best = [r["iterations_to_target"] for r in runs.values() if r["iterations_to_target"]]
-    out["iterations_ratio"] = round(min(best) / out["newton"]["sweeps"], 3) if best else None
+    best = [r for r in runs.values() if r["iterations_to_target"]]
+    if best:
+        b = min(best, key=lambda r: r["iterations_to_target"])
+        out["iterations_ratio"] = round(b["iterations_to_target"] / ns, 3)
+        out["seconds_ratio"] = round(min(r["seconds_to_target"] for r in best) / nsec, 3)
+    else:
+        out["iterations_ratio"] = out["seconds_ratio"] = None
     log(f"[bench] first-order vs Newton: {out}")
     return out
 
@@ -545,12 +630,30 @@ def gpu_run(args):
     if args.batched_leg:
         batched = _batched_solve_leg(dev)
         log(f"[bench] batched solve: {batched}")
-    quality = None
+    quality = c4 = pre = None
     if args.quality_epochs > 0 and args.learned_every:
+        # the network learns from (features, alpha_eff) rows that plain sweeps log on the 100k scene and
+        # on this workload, before any timed run
+        from synth.scenes import make_config as _mk
+        c1 = _mk("c1")
+        t1 = _targets(c1, dev)
+        logs = _logs(c1, t1, dev, len(c1.cams), args.quality_mask, args.quality_step_frac)
+        del t1
+        logs += _logs(cfg, targets, dev, args.log_sweeps, args.quality_mask, args.quality_step_frac, seed=1000)
+        params, pcurve, label_mean = _pretrained(logs, dev)
+        pre = {"rows": int(sum(x[0].shape[1] for x in logs)), "loss_per_epoch": [round(x, 5) for x in pcurve],
+               "sources": f"{len(c1.cams)} plain sweeps of the 100k scene, {args.log_sweeps} of this workload",
+               "mean_label": [round(float(x), 4) for x in label_mean]}
+        log(f"[bench] pre-trained the step-scale network: {pre}")
+        del logs
         quality = _equal_psnr(cfg, targets, dev, args.quality_epochs, args.learned_every, args.quality_mask,
-                              args.quality_step_frac)
+                              args.quality_step_frac, params, label_mean)
+        if args.c4_epochs > 0:
+            del targets
+            c4 = _c4_leg(dev, args.learned_every, args.quality_mask, args.quality_step_frac, params, label_mean,
+                         args.c4_epochs)
     return (elapsed, stages, counts, cfg, learned, quality, batched, variants, overshoot, order_exp, first_order, dist,
-            curve, graph, status)
+            curve, graph, status, c4, pre)
 
 
 def _measured_traffic(kernel):
@@ -721,10 +824,17 @@ def main():
                     help="fraction of every Newton step applied in the timed sweeps: the full step is computed, "
                          "and a small fraction keeps the scene near its initial state so that every timed sweep "
                          "sees the same workload")
-    ap.add_argument("--quality-mask", type=int, default=12,
+    ap.add_argument("--c4-epochs", type=int, default=1,
+                    help="epochs of the plain form on the 3M-kernel, 300-camera workload that set its equal-PSNR "
+                         "target; 0 skips")
+    ap.add_argument("--log-sweeps", type=int, default=20,
+                    help="plain sweeps of this workload logged for the network's pre-training")
+    ap.add_argument("--no-overlap", action="store_true",
+                    help="the paper's plain steps: no overlap-share scaling of the simultaneous kernel steps")
+    ap.add_argument("--quality-mask", type=int, default=31,
                     help="attribute groups trained in the equal-PSNR leg (bits: 1 position, 2 rotation, 4 scaling, "
                          "8 opacity, 16 colour)")
-    ap.add_argument("--quality-step-frac", type=float, default=0.3)
+    ap.add_argument("--quality-step-frac", type=float, default=1.0)
     ap.add_argument("--no-batched-leg", dest="batched_leg", action="store_false",
                     help="skip timing the batched solve of the eight 20k-800k scenes")
     ap.add_argument("--no-graph-leg", dest="graph_leg", action="store_false",
@@ -735,7 +845,7 @@ def main():
                     help="epochs of the |N_t| / Gauss-Newton overshoot comparison on the 100k scene; 0 skips")
     ap.add_argument("--order-epochs", type=int, default=1,
                     help="epochs of the jacobi / series-order comparison on the 100k scene; 0 skips")
-    ap.add_argument("--order-step-frac", type=float, default=0.1,
+    ap.add_argument("--order-step-frac", type=float, default=1.0,
                     help="step fraction of the order comparison (it trains every group)")
     ap.add_argument("--curve-epochs", type=int, default=10,
                     help="epochs of the plain-form PSNR curve on the 100k scene; 0 skips")
@@ -746,6 +856,8 @@ def main():
                     help="only copy 1 GiB on the device three times and exit (the calibration run of the HBM "
                          "traffic counters)")
     args = ap.parse_args()
+    global OVERLAP
+    OVERLAP = 0 if args.no_overlap else 1
     if args.copy_probe:
         copy_probe()
         return
@@ -754,7 +866,7 @@ def main():
               file=sys.stderr)
         sys.exit(2)
     (elapsed, stages, counts, cfg, learned, quality, batched, variants, overshoot, order_exp,
-     first_order, dist, curve, graph, status) = gpu_run(args)
+     first_order, dist, curve, graph, status, c4, pre) = gpu_run(args)
     ms_per_step = elapsed * 1e3 / args.steps
     value = args.steps / elapsed
     pixels = cfg.width * cfg.height + cfg.n_secondary * (cfg.width // 2) * (cfg.height // 2)
@@ -787,6 +899,8 @@ def main():
         "cpu_baseline": cpu,
         "learned": learned,
         "equal_psnr": quality,
+        "learned_pretraining": pre,
+        "c4_equal_psnr": c4,
         "batched_solve": batched,
         "variants": variants,
         "overshoot": overshoot,

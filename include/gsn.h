@@ -132,18 +132,28 @@ typedef struct {
      * again for position or rotation systems whose pivots pass their tests by less than a
      * factor of 10 (counted as GSN_COUNT_FP64_SOLVES while profiling). */
     int32_t precision;
+    /* 0: every kernel takes the paper's Newton step (times step_frac).  1: each kernel's steps are
+     * also multiplied by its overlap share omega = sum (alpha T)^2 / sum alpha T over its pixels in
+     * all views of the blocks (in (0, 1]; 1 for a kernel alone on its pixels).  The steps of all
+     * kernels are taken at once, each computed with the others held fixed (the blocks are the
+     * diagonal of the full Hessian); where kernels overlap, their steps add up in the shared pixels
+     * and overshoot.  omega is at most the Gershgorin ratio H_kk / sum_j |H_kj| of the colour system
+     * (sum_j alpha_j T_j = 1 - T_final <= 1 at every pixel), which bounds that overshoot. */
+    int32_t overlap_scale;
 } gsn_solve_opts;
 
 /* Per-kernel gradient/Hessian blocks, summed over the views added so far.
  * d_data is a device array of gsn_blocks_floats(n, n_views) floats laid out
- * [GSN_BLK_BASE + GSN_BLK_VIEW * n_views][n]:
+ * [GSN_BLK_BASE + GSN_BLK_VIEW * n_views + 1][n]:
  *   rows 0..2 g_p, 3..8 H_p (xx xy xz yy yz zz); rows 9..11 g_omega and 12..17
  *   H_omega for the rotation, parametrised by the left rotation vector omega
  *   (q <- exp(omega/2) q, so the paper's rotation angle about r_k is omega =
  *   theta r_k); 18..20 g_s, 21..26 H_s; 27 g_sigma, 28 H_sigma; 29 coverage of
  *   the primary target (sum of alpha T); then per view slot v at 30 + 10 v:
  *   gamma (dL/dc~, 3), s (sum h (alpha T)^2, 3), view direction r (3),
- *   coverage (1). */
+ *   coverage (1); and last, row 30 + 10 n_views: the sum over the views added
+ *   of sum (alpha T)^2 over the kernel's pixels (with the view coverages, the
+ *   kernel's overlap share, gsn_solve_opts.overlap_scale). */
 #define GSN_BLK_BASE 30
 #define GSN_BLK_VIEW 10
 typedef struct {
@@ -435,7 +445,8 @@ gsn_status gsn_mlp_train_step(gsn_ctx* ctx, gsn_mlp* mlp, int32_t n, const float
 
 /* ---------------------------------------------------------------- helpers */
 
-/* Number of floats of a blocks array for n kernels and n_views view slots. */
+/* Number of floats of a blocks array for n kernels and n_views view slots:
+ * (GSN_BLK_BASE + GSN_BLK_VIEW * n_views + 1) * n. */
 int64_t gsn_blocks_floats(int32_t n, int32_t n_views);
 /* Zeroes a blocks array (asynchronously, with a fill kernel). */
 gsn_status gsn_blocks_zero(gsn_ctx* ctx, gsn_blocks* blocks);
@@ -479,12 +490,12 @@ gsn_status gsn_frame_info(gsn_ctx* ctx, const gsn_frame* frame, int64_t* h_pairs
 gsn_status gsn_frame_lists(gsn_ctx* ctx, const gsn_frame* frame, uint32_t* d_ranges, uint32_t* d_ids,
                            uint32_t* d_depth_bits, int32_t* d_rect, uint32_t* d_ncontrib);
 /* Per-kernel projected-space statistics of the last gsn_accumulate_hessian on
- * this frame that ran with keep_zstats (float [44][n]), in each kernel's
+ * this frame that ran with keep_zstats (float [48][n]), in each kernel's
  * principal frame (pi' = V^T pi, Q' = V^T Q V, V from gsn_frame_records):
  * gradient w.r.t. (pi'_1, pi'_2, Q'_11, Q'_12, Q'_22) (5), sigma (1), c~ (3);
  * Hessian block over (pi', Q') (15, upper triangle), its cross block with c~
  * (5 x 3), the c~ diagonal (3), the sigma-sigma entry (1) and the coverage
- * sum alpha T (1). */
+ * sum alpha T (1), then the sum of (alpha T)^2 (1) and 3 zeros. */
 gsn_status gsn_frame_zstats(gsn_ctx* ctx, const gsn_frame* frame, float* d_out);
 /* Copy of the projected kernels of the last render (float [12][n]): image
  * position, high word (2), conic in the principal frame q1 = 1/lambda1,

@@ -65,6 +65,7 @@ enum Opt {
     O_STEP_FRAC,     // every group's Newton step is multiplied by step_frac before the trust radii
     O_DAMP_SH,       // colour damping mu = damp_sh * mean diag(G) + damp_abs / (3 |I|)
     O_GAUSS_NEWTON,  // 1 = local Gauss-Newton blocks: H = sum_ch h_ch J_ch J_ch^T (no dL_ch d2c_ch term)
+    O_OVERLAP,       // 1 = every kernel's steps scaled by its overlap share omega = sum (alpha T)^2 / sum alpha T
     O_COUNT
 };
 
@@ -684,7 +685,7 @@ extern "C" {
 // Number of doubles per kernel written by orc_blocks.
 enum {
     B_GP = 0, B_HP = 3, B_GW = 12, B_HW = 15, B_GS = 24, B_HS = 27, B_GO = 36, B_HO = 37,
-    B_W = 38, B_GAM = 39, B_SC = 42, B_R = 45, B_COUNT = 48
+    B_W = 38, B_GAM = 39, B_SC = 42, B_R = 45, B_W2 = 48, B_COUNT = 49
 };
 int orc_block_count() { return B_COUNT; }
 
@@ -696,7 +697,8 @@ int orc_block_count() { return B_COUNT; }
 // plus the colour statistics that determine the SH blocks: per channel
 // gamma = dL/dc~ and s = sum_pix h (alpha T)^2 (so that the SH gradient is
 // gamma Y(r) and the SH Hessian s Y(r) Y(r)^T, colour being linear in the
-// coefficients), the view direction r and the coverage w = sum_pix alpha T.
+// coefficients), the view direction r, the coverage w = sum_pix alpha T and the sum of its
+// squares sum_pix (alpha T)^2 (the overlap share of the kernel is their ratio).
 // dL, hd: per-pixel loss derivative maps of this view ([3][H][W]).
 // rect: from orc_project32 (standard mode).  out: [nsel][B_COUNT], row-major blocks.
 int orc_blocks(int n, int K, const double* pos, const double* rot, const double* scale,
@@ -773,6 +775,7 @@ int orc_blocks(int n, int K, const double* pos, const double* rot, const double*
                                   B[B_SC + ch] += hh[ch] * (alpha * T) * (alpha * T);
                               }
                               B[B_W] += alpha * T;
+                              B[B_W2] += (alpha * T) * (alpha * T);
                           });
     }
     return 0;
@@ -1064,7 +1067,8 @@ int orc_solve(int n, int K, const double* pos, const double* rot, const double* 
               const double* cam, const double* o, int V, const double* blocks, double* steps, int32_t* dec,
               double* cond) {
     const Cam c = load_cam(cam);
-    const int NB = S_COUNT_BASE + V * S_VIEW, NS = 11 + 3 * K;
+    // the summed blocks: base, V view slots, then the sum over views of sum_pix (alpha T)^2
+    const int NB = S_COUNT_BASE + V * S_VIEW + 1, NS = 11 + 3 * K;
     const double kappa = o[O_SMOOTH] != 0.0 ? 0.0 : o[O_KAPPA];
     const double abs_scale = 1.0 / (3.0 * o[O_NPIX_PRIMARY]);
 #pragma omp parallel for schedule(static)
@@ -1083,6 +1087,19 @@ int orc_solve(int n, int K, const double* pos, const double* rot, const double* 
         for (int a = 0; a < 4; ++a) q[a] = rot[(size_t)a * n + k];
         for (int a = 0; a < 3; ++a) s[a] = scale[(size_t)a * n + k];
         const double sig = opac[k];
+        // step fraction of this kernel: step_frac, times its overlap share when asked for.  Every kernel's
+        // Newton step assumes the other kernels fixed; where several composite into the same pixels their
+        // steps add up there.  The share omega = sum (alpha T)^2 / sum alpha T over the kernel's pixels in
+        // all views is at most its Gershgorin ratio H_kk / sum_j |H_kj| for the colour system (sum_j
+        // alpha_j T_j = 1 - T_final <= 1 at every pixel), so the scaled simultaneous steps cannot
+        // overshoot that quadratic.
+        double frac = o[O_STEP_FRAC];
+        if (o[O_OVERLAP] != 0.0) {
+            double cov = 0.0;
+            for (int v = 0; v < V; ++v) cov += B[S_COUNT_BASE + v * S_VIEW + 9];
+            const double w2 = B[S_COUNT_BASE + V * S_VIEW];
+            frac *= cov > 0.0 ? std::min(1.0, std::max(0.0, w2 / cov)) : 0.0;
+        }
         Reduced R;
         reduce_systems(B, p, q, s, sig, c, kappa, o, abs_scale, R);
         for (int a = 0; a < 3; ++a) st[ST_AXIS + a] = R.r[a];
@@ -1090,7 +1107,7 @@ int orc_solve(int n, int K, const double* pos, const double* rot, const double* 
         {
             double H2[4] = {R.Hp[0], R.Hp[1], R.Hp[2], R.Hp[3]}, dv[2];
             dk[0] = damped_solve(2, H2, R.gp, o, dv, &cnd[0]);
-            for (int a = 0; a < 2; ++a) dv[a] *= o[O_STEP_FRAC];
+            for (int a = 0; a < 2; ++a) dv[a] *= frac;
             clamp_norm(2, dv, o[O_TRUST_POS] * std::max(s[0], std::max(s[1], s[2])));
             for (int a = 0; a < 3; ++a) st[ST_DPOS + a] = R.ux[a] * dv[0] + R.uy[a] * dv[1];
         }
@@ -1098,7 +1115,7 @@ int orc_solve(int n, int K, const double* pos, const double* rot, const double* 
         {
             double th;
             dk[1] = damped_solve(1, &R.Ht, &R.gt, o, &th, &cnd[1]);
-            th *= o[O_STEP_FRAC];
+            th *= frac;
             clamp_norm(1, &th, o[O_TRUST_ROT]);
             st[ST_DTH] = th;
         }
@@ -1106,7 +1123,7 @@ int orc_solve(int n, int K, const double* pos, const double* rot, const double* 
         {
             double av[2];
             dk[2] = damped_solve(2, R.Hs, R.gs, o, av, &cnd[2]);
-            for (int a = 0; a < 2; ++a) av[a] *= o[O_STEP_FRAC];
+            for (int a = 0; a < 2; ++a) av[a] *= frac;
             // the rows of T are unit but not orthogonal, so the clamp acts on Delta s itself
             double dsv[3];
             for (int a = 0; a < 3; ++a) dsv[a] = R.T2[0][a] * av[0] + R.T2[1][a] * av[1];
@@ -1117,7 +1134,7 @@ int orc_solve(int n, int K, const double* pos, const double* rot, const double* 
         {
             double ds;
             dk[3] = damped_solve(1, &R.Ho, &R.go, o, &ds, &cnd[3]);
-            st[ST_DO] = o[O_STEP_FRAC] * ds;
+            st[ST_DO] = frac * ds;
         }
         // Colour: per channel, G = sum_v s~_v b_v b_v^T, g = sum_v gamma_v b_v, b_v = Y(r_v).
         {
@@ -1151,7 +1168,7 @@ int orc_solve(int n, int K, const double* pos, const double* rot, const double* 
                 double x[16], b[16];
                 for (int i = 0; i < K; ++i) b[i] = -gg[i];
                 if (cholesky_solve(K, G, b, 0.0, x)) {
-                    for (int i = 0; i < K; ++i) x[i] *= o[O_STEP_FRAC];
+                    for (int i = 0; i < K; ++i) x[i] *= frac;
                     clamp_norm(K, x, o[O_TRUST_SH]);
                     for (int i = 0; i < K; ++i) st[ST_DSH + ch * K + i] = x[i];
                 }
@@ -1185,7 +1202,7 @@ int orc_features(int n, int K, const double* pos, const double* rot, const doubl
                  const double* cam, const double* o, int V, const double* blocks, const double* resid, double* feat,
                  uint8_t* ok) {
     const Cam c = load_cam(cam);
-    const int NB = S_COUNT_BASE + V * S_VIEW;
+    const int NB = S_COUNT_BASE + V * S_VIEW + 1;
     const double kappa = o[O_SMOOTH] != 0.0 ? 0.0 : o[O_KAPPA];
     const double abs_scale = 1.0 / (3.0 * o[O_NPIX_PRIMARY]);
     (void)K;

@@ -26,14 +26,15 @@ LIB = os.path.join(HERE, "liboracle.so")
 O_NAMES = ["tile", "alpha_min", "alpha_max", "T_min", "kappa", "radius_sigma", "smooth",
            "bg_r", "bg_g", "bg_b", "lambda_ssim", "barrier_beta", "damp_rel", "damp_abs",
            "pivot_min", "max_esc", "sh_floor", "scale_floor", "opac_ftb", "npix_primary", "trust_pos",
-           "trust_rot", "trust_scale", "trust_sh", "opac_eps", "step_frac", "damp_sh", "gauss_newton"]
+           "trust_rot", "trust_scale", "trust_sh", "opac_eps", "step_frac", "damp_sh", "gauss_newton",
+           "overlap"]
 DEFAULTS = dict(tile=16, alpha_min=1.0 / 255.0, alpha_max=0.99, T_min=1e-4, kappa=0.3,
                 radius_sigma=3.0, smooth=0, bg_r=0.0, bg_g=0.0, bg_b=0.0, lambda_ssim=0.2,
                 barrier_beta=1e-2, damp_rel=1e-3, damp_abs=1e-12, pivot_min=1e-3, max_esc=7,
                 sh_floor=1e-3, scale_floor=0.1, opac_ftb=0.995, npix_primary=1.0, trust_pos=2.0,
                 trust_rot=0.5, trust_scale=0.5, trust_sh=1.0, opac_eps=1e-6, step_frac=1.0,
-                damp_sh=1e-3, gauss_newton=0)
-B_COUNT = 48
+                damp_sh=1e-3, gauss_newton=0, overlap=0)
+B_COUNT = 49
 NB_BASE, NB_VIEW = 39, 10
 
 
@@ -225,14 +226,15 @@ def zstats(g, fr: Frame, dL, hd, sel=None):
 
 
 def sum_blocks(per_view):
-    """Combine per-view blocks [V] of [n][48] into the solve layout [n][39 + 10 V].
+    """Combine per-view blocks [V] of [n][49] into the solve layout [n][39 + 10 V + 1].
 
     Position, rotation, scaling and opacity blocks are summed over the views
     (weight 1, Sec. 4.3); the colour statistics stay per view; the coverage
-    of the first (primary) view decides which kernels are trained."""
+    of the first (primary) view decides which kernels are trained; the last
+    column sums sum_pix (alpha T)^2 over the views (the overlap share's numerator)."""
     V = len(per_view)
     n = per_view[0].shape[0]
-    out = np.zeros((n, NB_BASE + NB_VIEW * V))
+    out = np.zeros((n, NB_BASE + NB_VIEW * V + 1))
     for b in per_view:
         out[:, :38] += b[:, :38]
     out[:, 38] = per_view[0][:, 38]
@@ -242,6 +244,7 @@ def sum_blocks(per_view):
         out[:, base + 3:base + 6] = b[:, 42:45]
         out[:, base + 6:base + 9] = b[:, 45:48]
         out[:, base + 9] = b[:, 38]
+    out[:, NB_BASE + NB_VIEW * V] = sum(b[:, 48] for b in per_view)
     return out
 
 

@@ -966,7 +966,7 @@ gsn_status gsn_mlp_train_step(gsn_ctx* ctx, gsn_mlp* mlp, int32_t n, const float
 
 int64_t gsn_blocks_floats(int32_t n, int32_t n_views) {
     if (n < 0 || n_views < 1) return 0;
-    return (int64_t)(GSN_BLK_BASE + GSN_BLK_VIEW * n_views) * n;
+    return (int64_t)(GSN_BLK_BASE + GSN_BLK_VIEW * n_views + 1) * n;
 }
 
 gsn_status gsn_blocks_zero(gsn_ctx* ctx, gsn_blocks* b) {

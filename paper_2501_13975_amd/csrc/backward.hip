@@ -17,7 +17,8 @@
 //     g_w  += A1 sigma G u          g_sigma += A1 G       g_c~ += dL alpha T
 //     H_ww += (A2 sigma^2 G^2 + A1 sigma G) u u^T + A1 sigma G d2f
 //     H_wc~ += sigma G T (h a alpha + dL) u   (per channel)
-//     H_c~c~ += h (alpha T)^2 (diagonal)      H_sigma sigma += A2 G^2    w += alpha T
+//     H_c~c~ += h (alpha T)^2 (diagonal)      H_sigma sigma += A2 G^2    w += alpha T,
+//     w2 += (alpha T)^2 (the kernel's overlap share is w2 / w)
 // (terms in w and sigma vanish where alpha was clamped).  These 44 numbers per
 // kernel are everything the chain rule to position, rotation, scale, opacity
 // and colour needs.
@@ -59,7 +60,8 @@ __device__ __forceinline__ void pair_terms(const float4 a, const float4 b, float
         acc[6 + ch] += dl[ch] * wT;
         acc[39 + ch] += hh[ch] * wT * wT;
     }
-    acc[43] += wT;
+    acc[GSN_ZCOV] += wT;
+    acc[GSN_ZW2] += wT * wT;
     if (clamped) return;
     const float u[5] = {-q1 * dx, -q2 * dy, -0.5f * dx * dx, -dx * dy, -0.5f * dy * dy};
     const float k1 = A1 * sGraw;
@@ -519,7 +521,7 @@ __global__ __launch_bounds__(256) void reduce_pairs_kernel(int n, const uint2* _
     // primary) get a zero coverage, the others are summed one after another by the whole wave
     const int kl = k0 + lane;
     const bool has = kl < n && kflag[kl] != 0 && (!primary_cov || primary_cov[kl] > 0.f);
-    if (kl < n && !has) zsum[(size_t)kl * GSN_NZ + GSN_NZ - 1] = 0.0;
+    if (kl < n && !has) zsum[(size_t)kl * GSN_NZ + GSN_ZCOV] = 0.0;
     // every lane reads its own kernel's slot range up front (one coalesced load instead of a
     // dependent load per kernel); the wave then takes each kernel's range from its lane
     uint32_t my_nt = 0, my_off = 0;
@@ -581,10 +583,10 @@ template <bool GN>
 __global__ __launch_bounds__(128) void chain_pos_kernel(
     const float* __restrict__ pos, const float* __restrict__ rot, const float* __restrict__ scale,
     const float* __restrict__ sh, int n, int K, const double* __restrict__ zsum, const float4* __restrict__ rec,
-    DevCam cam, float kappa, float weight, int slot, float* __restrict__ blk, float* __restrict__ zstats) {
+    DevCam cam, float kappa, float weight, int slot, int V, float* __restrict__ blk, float* __restrict__ zstats) {
     const int k = blockIdx.x * blockDim.x + threadIdx.x;
     if (k >= n) return;
-    if (!(zsum[(size_t)k * GSN_NZ + GSN_NZ - 1] > 0.0)) {  // no pixel of this view composited the kernel
+    if (!(zsum[(size_t)k * GSN_NZ + GSN_ZCOV] > 0.0)) {  // no pixel of this view composited the kernel
         if (zstats) {
 #pragma unroll
             for (int f = 0; f < GSN_NZ; ++f) zstats[(size_t)f * n + k] = 0.f;
@@ -605,7 +607,7 @@ __global__ __launch_bounds__(128) void chain_pos_kernel(
 #pragma unroll
         for (int f = 0; f < GSN_NZ; ++f) zstats[(size_t)f * n + k] = z[f];
     }
-    if (!(z[43] > 0.f)) return;
+    if (!(z[GSN_ZCOV] > 0.f)) return;
     KParams kp;
     load_kparams(pos, rot, scale, rec, n, k, kp);
     const size_t N = (size_t)n;
@@ -619,7 +621,7 @@ __global__ __launch_bounds__(128) void chain_pos_kernel(
     }
     blk[27 * N + k] += weight * z[5];
     blk[28 * N + k] += weight * z[42];
-    if (slot == 0) blk[29 * N + k] = z[43];
+    if (slot == 0) blk[29 * N + k] = z[GSN_ZCOV];
     const size_t vb = GSN_BLK_BASE + (size_t)GSN_BLK_VIEW * slot;
     const float dx = kp.p[0] - cam.o[0], dy = kp.p[1] - cam.o[1], dz = kp.p[2] - cam.o[2];
     const float il = 1.0f / sqrtf(dx * dx + dy * dy + dz * dz);
@@ -631,7 +633,9 @@ __global__ __launch_bounds__(128) void chain_pos_kernel(
     blk[(vb + 6) * N + k] = dx * il;
     blk[(vb + 7) * N + k] = dy * il;
     blk[(vb + 8) * N + k] = dz * il;
-    blk[(vb + 9) * N + k] = z[43];
+    blk[(vb + 9) * N + k] = z[GSN_ZCOV];
+    // the sum over the views of sum (alpha T)^2, after the view slots (the overlap share's numerator)
+    blk[(GSN_BLK_BASE + (size_t)GSN_BLK_VIEW * V) * N + k] += weight * z[GSN_ZW2];
 }
 
 // One thread per kernel: rotation and scale blocks, in double from the double sums of the
@@ -688,7 +692,8 @@ void launch_reduce_chain(const gsn_frame& f, const gsn_gaussians& g, float weigh
     auto pos_k = gauss_newton ? chain_pos_kernel<true> : chain_pos_kernel<false>;
     auto rs_k = gauss_newton ? chain_rs_kernel<true> : chain_rs_kernel<false>;
     pos_k<<<(g.n + 127) / 128, 128, 0, s>>>(g.d_pos, g.d_rot, g.d_scale, g.d_sh, g.n, K, bp<double>(f.zsum),
-                                            bp<float4>(f.rec), f.cam, f.ro.kappa, weight, slot, b.d_data, zstats_out);
+                                            bp<float4>(f.rec), f.cam, f.ro.kappa, weight, slot, b.n_views, b.d_data,
+                                            zstats_out);
     rs_k<<<(g.n + 127) / 128, 128, 0, s>>>(g.d_pos, g.d_rot, g.d_scale, g.n, bp<double>(f.zsum), bp<float4>(f.rec),
                                            f.cam, f.ro.kappa, weight, b.d_data);
 }

@@ -9,7 +9,10 @@
 
 #define GSN_TILE 16
 #define GSN_BLOCK 256          // threads per tile workgroup (16 x 16 pixels, four wave64s)
-#define GSN_NZ 44              // per-kernel projected-space statistics, see backward.hip
+#define GSN_NZ 48              // per-kernel projected-space statistics (44 used, then the sum of
+                               // squared contribution weights, then zero padding), see backward.hip
+#define GSN_ZCOV 43            // index of the coverage sum alpha T among the statistics
+#define GSN_ZW2 44             // index of the sum of (alpha T)^2
 
 // Kernel-space camera (floats) passed by value to kernels.
 struct DevCam {

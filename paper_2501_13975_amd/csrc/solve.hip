@@ -98,6 +98,23 @@ __device__ __forceinline__ uint32_t decision_events(int group, int j) {
     return (j > 0 ? 1u << (EV_ESC + group) : 0u) | (j == -1 ? 1u << (EV_FALLBACK + group) : 0u);
 }
 
+// The fraction of the Newton step kernel k takes: step_frac, times (with overlap_scale) its overlap
+// share omega = sum over its pixels in all views of (alpha T)^2 / sum of alpha T, clipped to [0, 1].
+// All kernels step at once, each computed with the others fixed; where they overlap their steps add
+// up in the shared pixels.  omega <= H_kk / sum_j |H_kj| for the colour system (sum_j alpha_j T_j =
+// 1 - T_final <= 1 at every pixel), a Gershgorin bound on that overshoot.
+template <class T, class RowFn>
+__device__ __forceinline__ T step_fraction(RowFn B, int V, const gsn_solve_opts& o) {
+    T frac = (T)o.step_frac;
+    if (o.overlap_scale) {
+        T cov = (T)0;
+        for (int v = 0; v < V; ++v) cov += (T)B(GSN_BLK_BASE + GSN_BLK_VIEW * v + 9);
+        const T w2 = (T)B(GSN_BLK_BASE + GSN_BLK_VIEW * V);
+        frac *= cov > (T)0 ? fmin((T)1, fmax((T)0, w2 / cov)) : (T)0;
+    }
+    return frac;
+}
+
 // Zero step and decisions -3 for a kernel skipped because of non-finite values.
 __device__ __forceinline__ void skip_nonfinite(float* __restrict__ st, int32_t* __restrict__ fl, size_t N, int k,
                                                int NS) {
@@ -181,9 +198,9 @@ __device__ __forceinline__ bool chol_solve_v(int m, const T A[VM][VM], const T* 
 // Delta = B^T y, which equals the damped coefficient-space solve (B^T S B + mu I) Delta =
 // -B^T gamma for every nv.  The basis rows are re-evaluated instead of stored.
 template <int VM, class RowFn>
-__device__ __forceinline__ bool colour_solve(int K, int V, RowFn B, const gsn_solve_opts& o, double abs_scale,
-                                             float* __restrict__ st, size_t N, int k, int32_t* __restrict__ fl,
-                                             double& chk) {
+__device__ __forceinline__ bool colour_solve(int K, int V, RowFn B, const gsn_solve_opts& o, double frac,
+                                             double abs_scale, float* __restrict__ st, size_t N, int k,
+                                             int32_t* __restrict__ fl, double& chk) {
     int vb[VM];
     int nv = 0;
 #pragma unroll
@@ -275,7 +292,7 @@ __device__ __forceinline__ bool colour_solve(int K, int V, RowFn B, const gsn_so
         double nn = 0.0;
 #pragma unroll
         for (int a = 0; a < 16; ++a) {
-            dsh[ch][a] *= (double)o.step_frac;
+            dsh[ch][a] *= frac;
             nn += dsh[ch][a] * dsh[ch][a];
         }
         nn = sqrt(nn);
@@ -314,6 +331,7 @@ __device__ __forceinline__ uint32_t solve_one(int k, const float* __restrict__ p
         return v;
     };
     uint32_t ev = 1u << EV_SOLVED;
+    const double frac = step_fraction<double>(B, V, o);
     const double abs_scale = 1.0 / (3.0 * (double)o.npix_primary);
     double s[3];
     for (int a = 0; a < 3; ++a) s[a] = scale[a * N + k];
@@ -326,7 +344,7 @@ __device__ __forceinline__ uint32_t solve_one(int k, const float* __restrict__ p
         const int j = damped_small(2, R.Hp, R.gp, o, abs_scale, dv);
         fl[0 * N + k] = j;
         ev |= decision_events(0, j);
-        for (int a = 0; a < 2; ++a) dv[a] *= (double)o.step_frac;
+        for (int a = 0; a < 2; ++a) dv[a] *= frac;
         if (clamp_norm(2, dv, (double)o.trust_pos * fmax(s[0], fmax(s[1], s[2])))) ev |= 1u << (EV_CLAMP + 0);
         for (int a = 0; a < 3; ++a) {
             const double d = R.ux[a] * dv[0] + R.uy[a] * dv[1];
@@ -340,7 +358,7 @@ __device__ __forceinline__ uint32_t solve_one(int k, const float* __restrict__ p
         const int j = damped_small(1, &R.Ht, &R.gt, o, abs_scale, &th);
         fl[1 * N + k] = j;
         ev |= decision_events(1, j);
-        th *= (double)o.step_frac;
+        th *= frac;
         if (clamp_norm(1, &th, (double)o.trust_rot)) ev |= 1u << (EV_CLAMP + 1);
         chk += th * 0.0;
         st[3 * N + k] = (float)th;
@@ -351,7 +369,7 @@ __device__ __forceinline__ uint32_t solve_one(int k, const float* __restrict__ p
         const int j = damped_small(2, R.Hs, R.gs, o, abs_scale, av);
         fl[2 * N + k] = j;
         ev |= decision_events(2, j);
-        for (int a = 0; a < 2; ++a) av[a] *= (double)o.step_frac;
+        for (int a = 0; a < 2; ++a) av[a] *= frac;
         double dsv[3];
         for (int a = 0; a < 3; ++a) dsv[a] = R.T_[0][a] * av[0] + R.T_[1][a] * av[1];
         if (clamp_norm(3, dsv, (double)o.trust_scale * sqrt(s[0] * s[0] + s[1] * s[1] + s[2] * s[2])))
@@ -368,10 +386,10 @@ __device__ __forceinline__ uint32_t solve_one(int k, const float* __restrict__ p
         fl[3 * N + k] = j;
         ev |= decision_events(3, j);
         chk += ds * 0.0;
-        st[10 * N + k] = (float)((double)o.step_frac * ds);
+        st[10 * N + k] = (float)(frac * ds);
     }
     // ---- colour, per channel
-    if (colour_solve<VM>(K, V, B, o, abs_scale, st, N, k, fl, chk)) ev |= 1u << (EV_CLAMP + 3);
+    if (colour_solve<VM>(K, V, B, o, frac, abs_scale, st, N, k, fl, chk)) ev |= 1u << (EV_CLAMP + 3);
     if (!(chk == 0.0)) {
         skip_nonfinite(st, fl, N, k, NS);
         return 1u << EV_NONFINITE;
@@ -469,7 +487,7 @@ __global__ __launch_bounds__(256) void sh_gram_kernel(const float* __restrict__ 
 // Colour step of the mixed form (FP32), from the matrix-core Gram matrices.
 template <class RowFn>
 __device__ __forceinline__ bool colour_solve_mixed(int K, int V, RowFn B, const float* __restrict__ gram,
-                                                   const gsn_solve_opts& o, float abs_scale,
+                                                   const gsn_solve_opts& o, float frac, float abs_scale,
                                                    float* __restrict__ st, size_t N, int k,
                                                    int32_t* __restrict__ fl, const float* __restrict__ blk,
                                                    float& chk) {
@@ -538,7 +556,7 @@ __device__ __forceinline__ bool colour_solve_mixed(int K, int V, RowFn B, const 
         float nn = 0.f;
 #pragma unroll
         for (int a = 0; a < 16; ++a) {
-            dsh[ch][a] *= o.step_frac;
+            dsh[ch][a] *= frac;
             nn += dsh[ch][a] * dsh[ch][a];
         }
         nn = sqrtf(nn);
@@ -587,6 +605,7 @@ __device__ __forceinline__ uint32_t solve_one_mixed(int k, const float* __restri
         return v;
     };
     uint32_t ev = 1u << EV_SOLVED;
+    const float frac = step_fraction<float>(Bf, V, o);
     const float abs_scale = 1.0f / (3.0f * (float)o.npix_primary);
     float s[3];
     for (int a = 0; a < 3; ++a) s[a] = scale[a * N + k];
@@ -622,7 +641,7 @@ __device__ __forceinline__ uint32_t solve_one_mixed(int k, const float* __restri
     }
     fl[0 * N + k] = jp;
     ev |= decision_events(0, jp);
-    for (int a = 0; a < 2; ++a) dv[a] *= o.step_frac;
+    for (int a = 0; a < 2; ++a) dv[a] *= frac;
     if (clamp_norm_f(2, dv, o.trust_pos * fmaxf(s[0], fmaxf(s[1], s[2])))) ev |= 1u << (EV_CLAMP + 0);
     for (int a = 0; a < 3; ++a) {
         const float d = R.ux[a] * dv[0] + R.uy[a] * dv[1];
@@ -631,7 +650,7 @@ __device__ __forceinline__ uint32_t solve_one_mixed(int k, const float* __restri
     }
     fl[1 * N + k] = jr;
     ev |= decision_events(1, jr);
-    th *= o.step_frac;
+    th *= frac;
     if (clamp_norm_f(1, &th, o.trust_rot)) ev |= 1u << (EV_CLAMP + 1);
     chk += th * 0.f;
     st[3 * N + k] = th;
@@ -641,7 +660,7 @@ __device__ __forceinline__ uint32_t solve_one_mixed(int k, const float* __restri
         const int j = damped_small(2, R.Hs, R.gs, o, abs_scale, av);
         fl[2 * N + k] = j;
         ev |= decision_events(2, j);
-        for (int a = 0; a < 2; ++a) av[a] *= o.step_frac;
+        for (int a = 0; a < 2; ++a) av[a] *= frac;
         float dsv[3];
         for (int a = 0; a < 3; ++a) dsv[a] = R.T_[0][a] * av[0] + R.T_[1][a] * av[1];
         if (clamp_norm_f(3, dsv, o.trust_scale * sqrtf(s[0] * s[0] + s[1] * s[1] + s[2] * s[2])))
@@ -657,9 +676,9 @@ __device__ __forceinline__ uint32_t solve_one_mixed(int k, const float* __restri
         fl[3 * N + k] = j;
         ev |= decision_events(3, j);
         chk += ds * 0.f;
-        st[10 * N + k] = o.step_frac * ds;
+        st[10 * N + k] = frac * ds;
     }
-    if (colour_solve_mixed(K, V, Bf, gram, o, abs_scale, st, N, k, fl, blk, chk)) ev |= 1u << (EV_CLAMP + 3);
+    if (colour_solve_mixed(K, V, Bf, gram, o, frac, abs_scale, st, N, k, fl, blk, chk)) ev |= 1u << (EV_CLAMP + 3);
     if (!(chk == 0.f)) {
         skip_nonfinite(st, fl, N, k, NS);
         return 1u << EV_NONFINITE;

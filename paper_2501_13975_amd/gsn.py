@@ -14,7 +14,7 @@ import torch
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libgsn.so")
 
-GSN_BLK_BASE, GSN_BLK_VIEW, GSN_STEP_BASE, GSN_NZ = 30, 10, 11, 44
+GSN_BLK_BASE, GSN_BLK_VIEW, GSN_STEP_BASE, GSN_NZ = 30, 10, 11, 48
 GSN_FEAT_HIDDEN, GSN_FEAT_OK, GSN_FEAT_OUT_OF_RANGE = 0, 1, 2
 STATUS = {0: "GSN_OK", -1: "GSN_E_INVALID", -2: "GSN_E_SHAPE", -3: "GSN_E_CAPACITY", -4: "GSN_E_HIP",
           -5: "GSN_E_NOMEM", -6: "GSN_E_NUMERIC"}
@@ -120,7 +120,7 @@ class CSolveOpts(ctypes.Structure):
                 ("npix_primary", ctypes.c_int32), ("kappa", ctypes.c_float), ("trust_pos", ctypes.c_float),
                 ("trust_rot", ctypes.c_float), ("trust_scale", ctypes.c_float), ("trust_sh", ctypes.c_float),
                 ("opac_eps", ctypes.c_float), ("step_frac", ctypes.c_float), ("damp_sh", ctypes.c_float),
-                ("precision", ctypes.c_int32)]
+                ("precision", ctypes.c_int32), ("overlap_scale", ctypes.c_int32)]
 
 
 class CBlocks(ctypes.Structure):
@@ -143,12 +143,13 @@ def loss_opts(lambda_ssim=0.2, weight=1.0, keep_zstats=False, gauss_newton=False
 
 def solve_opts(npix_primary, kappa=0.3, damp_rel=1e-3, damp_abs=1e-12, pivot_min=1e-3, max_escalations=7,
                barrier_beta=1e-2, sh_floor=1e-3, scale_floor=0.1, opac_ftb=0.995, trust_pos=2.0, trust_rot=0.5,
-               trust_scale=0.5, trust_sh=1.0, opac_eps=1e-6, step_frac=1.0, damp_sh=1e-3, precision=0):
+               trust_scale=0.5, trust_sh=1.0, opac_eps=1e-6, step_frac=1.0, damp_sh=1e-3, precision=0, overlap=0):
     """precision 0: plain form; 1: mixed form (BF16 matrix-core colour Grams, FP32 solves, FP64 for
-    ill-conditioned position and rotation systems)."""
+    ill-conditioned position and rotation systems).  overlap 1: every kernel's steps times its overlap
+    share (gsn_solve_opts.overlap_scale)."""
     return CSolveOpts(damp_rel, damp_abs, pivot_min, max_escalations, barrier_beta, sh_floor, scale_floor,
                       opac_ftb, int(npix_primary), kappa, trust_pos, trust_rot, trust_scale, trust_sh, opac_eps,
-                      step_frac, damp_sh, int(precision))
+                      step_frac, damp_sh, int(precision), int(overlap))
 
 
 def camera(c) -> CCamera:
@@ -509,7 +510,8 @@ class Blocks:
         return CBlocks(_ptr(self.data), self.n, self.n_views)
 
     def view(self):
-        return self.data[:(GSN_BLK_BASE + GSN_BLK_VIEW * self.n_views) * self.n].view(-1, self.n)
+        """Rows [30 + 10 V + 1, n] (see gsn.h: base rows, V view slots, the overlap numerator)."""
+        return self.data[:(GSN_BLK_BASE + GSN_BLK_VIEW * self.n_views + 1) * self.n].view(-1, self.n)
 
 
 class Steps:

@@ -57,9 +57,10 @@ def zstats_gpu_to_full(z):
 
 
 def blocks_gpu_to_oracle_view(blk, slot):
-    """GPU blocks rows [30 + 10 V][n] -> oracle per-view layout [n, 48] for one single-view accumulation."""
+    """GPU blocks rows [30 + 10 V + 1][n] -> oracle per-view layout [n, 49] for one single-view accumulation."""
     n = blk.shape[1]
-    out = np.zeros((n, 48))
+    V = (blk.shape[0] - 31) // 10
+    out = np.zeros((n, 49))
     out[:, 0:3] = blk[0:3].T
     out[:, 3:12] = sym_from_packed(blk[3:9], 3).reshape(n, 9)
     out[:, 12:15] = blk[9:12].T
@@ -73,13 +74,14 @@ def blocks_gpu_to_oracle_view(blk, slot):
     out[:, 39:42] = blk[vb:vb + 3].T
     out[:, 42:45] = blk[vb + 3:vb + 6].T
     out[:, 45:48] = blk[vb + 6:vb + 9].T
+    out[:, 48] = blk[30 + 10 * V]
     return out
 
 
 BLOCK_GROUPS = {
     "g_p": slice(0, 3), "H_p": slice(3, 12), "g_omega": slice(12, 15), "H_omega": slice(15, 24),
     "g_s": slice(24, 27), "H_s": slice(27, 36), "g_sigma": slice(36, 37), "H_sigma": slice(37, 38),
-    "coverage": slice(38, 39), "gamma": slice(39, 42), "s_colour": slice(42, 45),
+    "coverage": slice(38, 39), "gamma": slice(39, 42), "s_colour": slice(42, 45), "w2": slice(48, 49),
 }
 STEP_GROUPS = {"position": slice(0, 3), "rotation": slice(3, 4), "scale": slice(7, 10), "opacity": slice(10, 11)}
 
@@ -204,9 +206,9 @@ def zstats_to_frame(Z, fc, fs):
 
 
 def gpu_blocks_to_summed(gb, V):
-    """GPU blocks rows [30 + 10 V][n] -> the oracle's summed solve layout [n][39 + 10 V]."""
+    """GPU blocks rows [30 + 10 V + 1][n] -> the oracle's summed solve layout [n][39 + 10 V + 1]."""
     n = gb.shape[1]
-    S = np.zeros((n, 39 + 10 * V))
+    S = np.zeros((n, 40 + 10 * V))
     S[:, 0:3] = gb[0:3].T
     S[:, 3:12] = sym_from_packed(gb[3:9], 3).reshape(n, 9)
     S[:, 12:15] = gb[9:12].T
@@ -216,6 +218,7 @@ def gpu_blocks_to_summed(gb, V):
     S[:, 36], S[:, 37], S[:, 38] = gb[27], gb[28], gb[29]
     for v in range(V):
         S[:, 39 + 10 * v:49 + 10 * v] = gb[30 + 10 * v:40 + 10 * v].T
+    S[:, 39 + 10 * V] = gb[30 + 10 * V]
     return S
 
 
@@ -225,9 +228,9 @@ def packed_from_sym(M):
 
 
 def summed_to_gpu_blocks(S, V):
-    """The oracle's summed solve layout [n][39 + 10 V] -> the library's block rows [30 + 10 V][n]."""
+    """The oracle's summed solve layout [n][39 + 10 V + 1] -> the library's block rows [30 + 10 V + 1][n]."""
     n = S.shape[0]
-    gb = np.zeros((30 + 10 * V, n))
+    gb = np.zeros((31 + 10 * V, n))
     gb[0:3] = S[:, 0:3].T
     gb[3:9] = packed_from_sym(S[:, 3:12].reshape(n, 3, 3))
     gb[9:12] = S[:, 12:15].T
@@ -237,6 +240,7 @@ def summed_to_gpu_blocks(S, V):
     gb[27], gb[28], gb[29] = S[:, 36], S[:, 37], S[:, 38]
     for v in range(V):
         gb[30 + 10 * v:40 + 10 * v] = S[:, 39 + 10 * v:49 + 10 * v].T
+    gb[30 + 10 * V] = S[:, 39 + 10 * V]
     return gb
 
 

@@ -36,7 +36,7 @@ def test_host_helpers_without_gpu():
     lib = ctypes.CDLL(LIB)
     lib.gsn_blocks_floats.restype = ctypes.c_int64
     lib.gsn_steps_floats.restype = ctypes.c_int64
-    assert lib.gsn_blocks_floats(1000, 4) == (30 + 40) * 1000
+    assert lib.gsn_blocks_floats(1000, 4) == (30 + 40 + 1) * 1000
     assert lib.gsn_steps_floats(10, 3) == (11 + 48) * 10
     assert lib.gsn_steps_floats(10, 4) == 0
 

@@ -33,7 +33,7 @@ def test_sh_gram_matches_double(gsn, ctx, sh_degree, V):
     rng = np.random.default_rng(10 + V)
     n = 1000 + 13  # several waves of 16 kernels and a ragged tail
     K = (sh_degree + 1) ** 2
-    rows = np.zeros((30 + 10 * V, n), np.float32)
+    rows = np.zeros((31 + 10 * V, n), np.float32)
     dirs = rng.standard_normal((V, n, 3))
     dirs /= np.linalg.norm(dirs, axis=2, keepdims=True)
     cover = rng.random((V, n)) < 0.7

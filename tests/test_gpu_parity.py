@@ -208,14 +208,17 @@ def test_sweep_steps_parity(gsn, ctx, lam, nsec, gn):
     errs["solver_decisions"] = float(same[vis].mean())
     for name, sl in groups:
         errs["solver_" + name] = rel_inf(st_s[sl].T[same], want_s[same, sl])
-    # the same with a step fraction and with the default colour trust radius
-    for tag, field, val in (("frac", "step_frac", 0.3), ("trust", "trust_sh", 1.0)):
+    # the overlap numerator row end to end (the sum over the views of sum (alpha T)^2)
+    errs["overlap_row"] = rel_inf(gb[30 + 10 * V][keep], res["summed"][keep, 39 + 10 * V])
+    # the same with a step fraction, with the default colour trust radius and with the overlap share
+    for tag, field, ofield, val in (("frac", "step_frac", "step_frac", 0.3), ("trust", "trust_sh", "trust_sh", 1.0),
+                                    ("overlap", "overlap_scale", "overlap", 1)):
         so_f = tr.solve_opts(t)
         setattr(so_f, field, val)
         tr.ctx.local_newton_solve(tr.g, tr.ccams[t], tr.blocks, so_f, tr.steps)
         st_f, fl_f = (x.cpu().numpy() for x in tr.steps.view())
         o_f = o_same.copy()
-        o_f[O.O_NAMES.index(field)] = val
+        o_f[O.O_NAMES.index(ofield)] = val
         want_f, dec_f = O.solve(g, cfg.cams[t], o_f, S32, V)
         same_f = np.all(fl_f[:4].T == dec_f[:, :4], axis=1) & vis
         for name, sl in groups:
@@ -229,10 +232,15 @@ def test_sweep_steps_parity(gsn, ctx, lam, nsec, gn):
                             sens=sens)
     _report(f"sweep-steps lam={lam} |N_t|={nsec} gn={gn}", errs)
     assert errs["decision_agreement"] > 0.99 and errs["solver_decisions"] > 0.999
+    assert errs["overlap_row"] < TOL_GRAD
     for name, _ in groups:
         assert errs["solver_" + name] < 1e-5, ("solver", name, errs["solver_" + name])
         assert errs["solver_frac_" + name] < 1e-5, ("solver, step fraction", name, errs["solver_frac_" + name])
         assert errs["solver_trust_" + name] < 1e-5, ("solver, colour radius", name, errs["solver_trust_" + name])
+        # scaled by the overlap share the largest steps are rarely trust-clamped, so the relative measure is
+        # set by ill-conditioned unclamped steps: the Newton-step bar (1e-4) applies
+        assert errs["solver_overlap_" + name] < TOL_STEP, ("solver, overlap share", name,
+                                                         errs["solver_overlap_" + name])
         assert errs[name] < TOL_STEP, (name, errs[name])
         assert errs["determined_" + name] > 0.5 * errs["visible"], ("too few determined steps", name)
     # (3) apply: the oracle's steps (float32, as the library stores them) applied by both sides

@@ -101,7 +101,7 @@ def test_features_of_isotropic_blocks():
     g, cam = cfg.init, cfg.cams[0]
     o = O.opts(npix_primary=120 * 90)
     n, V = g.n, 1
-    S = np.zeros((n, 39 + 10 * V))
+    S = np.zeros((n, 40 + 10 * V))
     a, h = 3.0e-3, -2.0e-5
     S[:, 3:12] = (a * np.eye(3)).ravel()
     S[:, 15:24] = (h * np.eye(3)).ravel()
@@ -141,7 +141,7 @@ def test_features_of_isotropic_blocks():
 def test_neighbour_residual_of_constructed_views():
     # three view slots: the residual is the secondaries' colour-gradient norms over the primary's
     n, V = 5, 3
-    S = np.zeros((n, 39 + 10 * V))
+    S = np.zeros((n, 40 + 10 * V))
     S[:, 38] = [1.0, 1.0, 1.0, 0.0, 1.0]  # kernel 3: not seen by the primary
     g0 = np.array([[3.0, 4.0, 0.0]] * n)  # |gamma_0| = 5
     S[:, 39:42] = g0

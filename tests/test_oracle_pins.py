@@ -750,6 +750,68 @@ def test_step_fraction_scales_every_group_before_the_trust_radii():
     assert np.array_equal(sh[:, 4:7], res["steps"][:, 4:7])  # the rotation axis is not a step
 
 
+def test_overlap_sums_match_python_brute_force():
+    """Coverage sum alpha T and the overlap numerator sum (alpha T)^2 of every kernel, against plain
+    Python loops over the depth-sorted kernels at every pixel (smooth mode: eq. 3dgs exactly)."""
+    g = tiny_scene(7, K=4, seed=31, scale=0.5)
+    cam = tiny_cam(20, 16)
+    o = smooth_opts(0.0)
+    tgt = O.render(tiny_scene(7, K=4, seed=32), cam, o).img
+    B, _, _, _ = oracle_blocks(g, cam, tgt, o)
+    rec, ok = O.project64(g, cam, kappa=0.0)
+    order = np.argsort(rec[:, 11], kind="stable")
+    w1, w2 = np.zeros(g.n), np.zeros(g.n)
+    for y in range(cam.height):
+        for x in range(cam.width):
+            T = 1.0
+            for k in order:
+                dx, dy = rec[k, 0] - x, rec[k, 1] - y
+                a = g.opac[k] * math.exp(-0.5 * (rec[k, 5] * dx * dx + 2 * rec[k, 6] * dx * dy + rec[k, 7] * dy * dy))
+                w1[k] += a * T
+                w2[k] += (a * T) ** 2
+                T *= 1 - a
+    assert np.allclose(B[:, 38], w1, rtol=1e-12) and np.allclose(B[:, 48], w2, rtol=1e-12)
+    assert np.all(w2 <= w1)
+
+
+def test_overlap_share_scales_every_group_before_the_trust_radii():
+    g, cams, tgts, _ = _solve_case()
+    free = dict(npix_primary=32 * 28, trust_pos=1e30, trust_rot=1e30, trust_scale=1e30, trust_sh=1e30)
+    res = O.sweep(g, cams, tgts, 0, np.array([[1], [0]]), O.opts(**free))
+    S = res["summed"]
+    so, do = O.solve(g, cams[0], O.opts(overlap=1, **free), S, 2)
+    assert np.array_equal(do, res["dec"])
+    cov = S[:, 39 + 9] + S[:, 49 + 9]
+    omega = np.where(cov > 0, np.clip(S[:, 59] / np.where(cov > 0, cov, 1.0), 0.0, 1.0), 0.0)
+    seen = res["dec"][:, 0] != -2
+    assert seen.sum() >= 3 and np.all(omega[seen] > 0) and np.all(omega[seen] < 1)
+    cols = np.r_[0:4, 7:11 + 48]
+    assert np.allclose(so[:, cols], omega[:, None] * res["steps"][:, cols], rtol=1e-12, atol=1e-300)
+    assert np.array_equal(so[:, 4:7], res["steps"][:, 4:7])
+
+
+def test_overlap_share_makes_simultaneous_colour_steps_descend():
+    """With L2 the loss is quadratic in the kernels' view-dependent colours, with Hessian
+    H_kj = sum_p w_kp w_jp / (3|I|) >= 0.  Scaled by omega_k <= H_kk / sum_j H_kj (sum_j w_jp = 1 - T_p),
+    the simultaneous per-kernel Newton steps cannot raise the loss (diag(row sums) - H is PSD), while the
+    unscaled steps of many overlapping kernels overshoot."""
+    g = tiny_scene(40, K=1, seed=41, scale=0.45)
+    g.opac[:] = 0.35
+    cam = tiny_cam(32, 28)
+    truth = g.copy()
+    truth.sh = truth.sh + np.random.default_rng(42).normal(0.0, 0.6, truth.sh.shape)
+    o0 = smooth_opts(0.0, npix_primary=32 * 28, trust_sh=1e30, damp_sh=1e-9)
+    tgt = O.render(truth, cam, o0).img
+    L0 = loss_value(g, cam, tgt, o0)
+    after = {}
+    for ov in (0, 1):
+        o = smooth_opts(0.0, npix_primary=32 * 28, trust_sh=1e30, damp_sh=1e-9, overlap=ov)
+        res = O.sweep(g, [cam], [tgt], 0, None, o, mask=16)
+        after[ov] = loss_value(res["new"], cam, tgt, o)
+    assert after[1] < L0
+    assert after[0] > L0 > after[1]
+
+
 def test_scale_row_space_matches_eigenvalue_derivative():
     """T = d lambda/d s (Scaling solve): the step's first-order change of the primary's eigenvalues."""
     g, cams, tgts, o = _solve_case()

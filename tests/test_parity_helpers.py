@@ -10,7 +10,7 @@ from oracle import oracle as O
 def test_block_layout_round_trip():
     rng = np.random.default_rng(0)
     n, V = 7, 4
-    S = rng.standard_normal((n, 39 + 10 * V))
+    S = rng.standard_normal((n, 40 + 10 * V))
     for off in (3, 15, 27):  # the three 3x3 blocks are symmetric
         M = S[:, off:off + 9].reshape(n, 3, 3)
         S[:, off:off + 9] = (M + M.transpose(0, 2, 1)).reshape(n, 9)
