@@ -132,9 +132,10 @@ typedef struct {
      * again for position or rotation systems whose pivots pass their tests by less than a
      * factor of 10 (counted as GSN_COUNT_FP64_SOLVES while profiling). */
     int32_t precision;
-    /* 0: every kernel takes the paper's Newton step (times step_frac).  1: each kernel's steps are
-     * also multiplied by its overlap share omega = sum (alpha T)^2 / sum alpha T over its pixels in
-     * all views of the blocks (in (0, 1]; 1 for a kernel alone on its pixels).  The steps of all
+    /* 0: every kernel takes the paper's Newton step (times step_frac).  1: each kernel's steps,
+     * after the trust radii, are multiplied by its overlap share omega = sum (alpha T)^2 / sum
+     * alpha T over its pixels in all views of the blocks (in (0, 1]; 1 for a kernel alone on its
+     * pixels).  The steps of all
      * kernels are taken at once, each computed with the others held fixed (the blocks are the
      * diagonal of the full Hessian); where kernels overlap, their steps add up in the shared pixels
      * and overshoot.  omega is at most the Gershgorin ratio H_kk / sum_j |H_kj| of the colour system

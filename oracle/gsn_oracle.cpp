@@ -1087,18 +1087,18 @@ int orc_solve(int n, int K, const double* pos, const double* rot, const double* 
         for (int a = 0; a < 4; ++a) q[a] = rot[(size_t)a * n + k];
         for (int a = 0; a < 3; ++a) s[a] = scale[(size_t)a * n + k];
         const double sig = opac[k];
-        // step fraction of this kernel: step_frac, times its overlap share when asked for.  Every kernel's
-        // Newton step assumes the other kernels fixed; where several composite into the same pixels their
-        // steps add up there.  The share omega = sum (alpha T)^2 / sum alpha T over the kernel's pixels in
-        // all views is at most its Gershgorin ratio H_kk / sum_j |H_kj| for the colour system (sum_j
-        // alpha_j T_j = 1 - T_final <= 1 at every pixel), so the scaled simultaneous steps cannot
-        // overshoot that quadratic.
-        double frac = o[O_STEP_FRAC];
+        const double frac = o[O_STEP_FRAC];
+        // overlap share (when asked for): every kernel's Newton step holds the other kernels fixed;
+        // where several composite into the same pixels their steps add up there.  The share
+        // omega = sum (alpha T)^2 / sum alpha T over the kernel's pixels in all views is at most its
+        // Gershgorin ratio H_kk / sum_j |H_kj| for the colour system (sum_j alpha_j T_j = 1 - T_final
+        // <= 1 at every pixel).  It multiplies the kernel's steps after the trust radii.
+        double omega = 1.0;
         if (o[O_OVERLAP] != 0.0) {
             double cov = 0.0;
             for (int v = 0; v < V; ++v) cov += B[S_COUNT_BASE + v * S_VIEW + 9];
             const double w2 = B[S_COUNT_BASE + V * S_VIEW];
-            frac *= cov > 0.0 ? std::min(1.0, std::max(0.0, w2 / cov)) : 0.0;
+            omega = cov > 0.0 ? std::min(1.0, std::max(0.0, w2 / cov)) : 0.0;
         }
         Reduced R;
         reduce_systems(B, p, q, s, sig, c, kappa, o, abs_scale, R);
@@ -1109,7 +1109,7 @@ int orc_solve(int n, int K, const double* pos, const double* rot, const double* 
             dk[0] = damped_solve(2, H2, R.gp, o, dv, &cnd[0]);
             for (int a = 0; a < 2; ++a) dv[a] *= frac;
             clamp_norm(2, dv, o[O_TRUST_POS] * std::max(s[0], std::max(s[1], s[2])));
-            for (int a = 0; a < 3; ++a) st[ST_DPOS + a] = R.ux[a] * dv[0] + R.uy[a] * dv[1];
+            for (int a = 0; a < 3; ++a) st[ST_DPOS + a] = omega * (R.ux[a] * dv[0] + R.uy[a] * dv[1]);
         }
         // rotation: q(theta) = dq(theta) * q with dq = [cos(theta/2), sin(theta/2) r]
         {
@@ -1117,7 +1117,7 @@ int orc_solve(int n, int K, const double* pos, const double* rot, const double* 
             dk[1] = damped_solve(1, &R.Ht, &R.gt, o, &th, &cnd[1]);
             th *= frac;
             clamp_norm(1, &th, o[O_TRUST_ROT]);
-            st[ST_DTH] = th;
+            st[ST_DTH] = omega * th;
         }
         // scaling: Delta s = T^T a
         {
@@ -1128,13 +1128,13 @@ int orc_solve(int n, int K, const double* pos, const double* rot, const double* 
             double dsv[3];
             for (int a = 0; a < 3; ++a) dsv[a] = R.T2[0][a] * av[0] + R.T2[1][a] * av[1];
             clamp_norm(3, dsv, o[O_TRUST_SCALE] * std::sqrt(s[0] * s[0] + s[1] * s[1] + s[2] * s[2]));
-            for (int a = 0; a < 3; ++a) st[ST_DS + a] = dsv[a];
+            for (int a = 0; a < 3; ++a) st[ST_DS + a] = omega * dsv[a];
         }
         // opacity with the log barrier
         {
             double ds;
             dk[3] = damped_solve(1, &R.Ho, &R.go, o, &ds, &cnd[3]);
-            st[ST_DO] = frac * ds;
+            st[ST_DO] = omega * (frac * ds);
         }
         // Colour: per channel, G = sum_v s~_v b_v b_v^T, g = sum_v gamma_v b_v, b_v = Y(r_v).
         {
@@ -1170,7 +1170,7 @@ int orc_solve(int n, int K, const double* pos, const double* rot, const double* 
                 if (cholesky_solve(K, G, b, 0.0, x)) {
                     for (int i = 0; i < K; ++i) x[i] *= frac;
                     clamp_norm(K, x, o[O_TRUST_SH]);
-                    for (int i = 0; i < K; ++i) st[ST_DSH + ch * K + i] = x[i];
+                    for (int i = 0; i < K; ++i) st[ST_DSH + ch * K + i] = omega * x[i];
                 }
             }
         }

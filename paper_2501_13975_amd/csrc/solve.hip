@@ -98,21 +98,19 @@ __device__ __forceinline__ uint32_t decision_events(int group, int j) {
     return (j > 0 ? 1u << (EV_ESC + group) : 0u) | (j == -1 ? 1u << (EV_FALLBACK + group) : 0u);
 }
 
-// The fraction of the Newton step kernel k takes: step_frac, times (with overlap_scale) its overlap
-// share omega = sum over its pixels in all views of (alpha T)^2 / sum of alpha T, clipped to [0, 1].
-// All kernels step at once, each computed with the others fixed; where they overlap their steps add
-// up in the shared pixels.  omega <= H_kk / sum_j |H_kj| for the colour system (sum_j alpha_j T_j =
-// 1 - T_final <= 1 at every pixel), a Gershgorin bound on that overshoot.
+// The overlap share of kernel k (with overlap_scale; else 1): omega = sum over its pixels in all
+// views of (alpha T)^2 / sum of alpha T, clipped to [0, 1].  All kernels step at once, each step
+// computed with the others fixed; where they overlap their steps add up in the shared pixels.
+// omega <= H_kk / sum_j |H_kj| for the colour system (sum_j alpha_j T_j = 1 - T_final <= 1 at every
+// pixel), a Gershgorin bound on that overshoot.  It multiplies the kernel's steps after the trust
+// radii, so that overlapping kernels together move about as far as one kernel's radius allows.
 template <class T, class RowFn>
-__device__ __forceinline__ T step_fraction(RowFn B, int V, const gsn_solve_opts& o) {
-    T frac = (T)o.step_frac;
-    if (o.overlap_scale) {
-        T cov = (T)0;
-        for (int v = 0; v < V; ++v) cov += (T)B(GSN_BLK_BASE + GSN_BLK_VIEW * v + 9);
-        const T w2 = (T)B(GSN_BLK_BASE + GSN_BLK_VIEW * V);
-        frac *= cov > (T)0 ? fmin((T)1, fmax((T)0, w2 / cov)) : (T)0;
-    }
-    return frac;
+__device__ __forceinline__ T overlap_share(RowFn B, int V, const gsn_solve_opts& o) {
+    if (!o.overlap_scale) return (T)1;
+    T cov = (T)0;
+    for (int v = 0; v < V; ++v) cov += (T)B(GSN_BLK_BASE + GSN_BLK_VIEW * v + 9);
+    const T w2 = (T)B(GSN_BLK_BASE + GSN_BLK_VIEW * V);
+    return cov > (T)0 ? fmin((T)1, fmax((T)0, w2 / cov)) : (T)0;
 }
 
 // Zero step and decisions -3 for a kernel skipped because of non-finite values.
@@ -199,8 +197,8 @@ __device__ __forceinline__ bool chol_solve_v(int m, const T A[VM][VM], const T* 
 // -B^T gamma for every nv.  The basis rows are re-evaluated instead of stored.
 template <int VM, class RowFn>
 __device__ __forceinline__ bool colour_solve(int K, int V, RowFn B, const gsn_solve_opts& o, double frac,
-                                             double abs_scale, float* __restrict__ st, size_t N, int k,
-                                             int32_t* __restrict__ fl, double& chk) {
+                                             double omega, double abs_scale, float* __restrict__ st, size_t N,
+                                             int k, int32_t* __restrict__ fl, double& chk) {
     int vb[VM];
     int nv = 0;
 #pragma unroll
@@ -299,7 +297,7 @@ __device__ __forceinline__ bool colour_solve(int K, int V, RowFn B, const gsn_so
         chk += nn * 0.0;
         const bool cut = nn > (double)o.trust_sh && nn > 0.0;
         clamped = clamped || cut;
-        const double f = cut ? (double)o.trust_sh / nn : 1.0;
+        const double f = omega * (cut ? (double)o.trust_sh / nn : 1.0);
 #pragma unroll
         for (int a = 0; a < 16; ++a)
             if (a < K) st[(GSN_STEP_BASE + ch * K + a) * N + k] = (float)(dsh[ch][a] * f);
@@ -331,7 +329,7 @@ __device__ __forceinline__ uint32_t solve_one(int k, const float* __restrict__ p
         return v;
     };
     uint32_t ev = 1u << EV_SOLVED;
-    const double frac = step_fraction<double>(B, V, o);
+    const double frac = (double)o.step_frac, omega = overlap_share<double>(B, V, o);
     const double abs_scale = 1.0 / (3.0 * (double)o.npix_primary);
     double s[3];
     for (int a = 0; a < 3; ++a) s[a] = scale[a * N + k];
@@ -347,7 +345,7 @@ __device__ __forceinline__ uint32_t solve_one(int k, const float* __restrict__ p
         for (int a = 0; a < 2; ++a) dv[a] *= frac;
         if (clamp_norm(2, dv, (double)o.trust_pos * fmax(s[0], fmax(s[1], s[2])))) ev |= 1u << (EV_CLAMP + 0);
         for (int a = 0; a < 3; ++a) {
-            const double d = R.ux[a] * dv[0] + R.uy[a] * dv[1];
+            const double d = omega * (R.ux[a] * dv[0] + R.uy[a] * dv[1]);
             chk += d * 0.0;
             st[(size_t)a * N + k] = (float)d;
         }
@@ -361,7 +359,7 @@ __device__ __forceinline__ uint32_t solve_one(int k, const float* __restrict__ p
         th *= frac;
         if (clamp_norm(1, &th, (double)o.trust_rot)) ev |= 1u << (EV_CLAMP + 1);
         chk += th * 0.0;
-        st[3 * N + k] = (float)th;
+        st[3 * N + k] = (float)(omega * th);
     }
     // ---- scaling in the row space of d lambda / d s: Delta s = T^T a
     {
@@ -376,7 +374,7 @@ __device__ __forceinline__ uint32_t solve_one(int k, const float* __restrict__ p
             ev |= 1u << (EV_CLAMP + 2);
         for (int a = 0; a < 3; ++a) {
             chk += dsv[a] * 0.0;
-            st[(7 + a) * N + k] = (float)dsv[a];
+            st[(7 + a) * N + k] = (float)(omega * dsv[a]);
         }
     }
     // ---- opacity with the log barrier
@@ -386,10 +384,10 @@ __device__ __forceinline__ uint32_t solve_one(int k, const float* __restrict__ p
         fl[3 * N + k] = j;
         ev |= decision_events(3, j);
         chk += ds * 0.0;
-        st[10 * N + k] = (float)(frac * ds);
+        st[10 * N + k] = (float)(omega * (frac * ds));
     }
     // ---- colour, per channel
-    if (colour_solve<VM>(K, V, B, o, frac, abs_scale, st, N, k, fl, chk)) ev |= 1u << (EV_CLAMP + 3);
+    if (colour_solve<VM>(K, V, B, o, frac, omega, abs_scale, st, N, k, fl, chk)) ev |= 1u << (EV_CLAMP + 3);
     if (!(chk == 0.0)) {
         skip_nonfinite(st, fl, N, k, NS);
         return 1u << EV_NONFINITE;
@@ -487,7 +485,7 @@ __global__ __launch_bounds__(256) void sh_gram_kernel(const float* __restrict__ 
 // Colour step of the mixed form (FP32), from the matrix-core Gram matrices.
 template <class RowFn>
 __device__ __forceinline__ bool colour_solve_mixed(int K, int V, RowFn B, const float* __restrict__ gram,
-                                                   const gsn_solve_opts& o, float frac, float abs_scale,
+                                                   const gsn_solve_opts& o, float frac, float omega, float abs_scale,
                                                    float* __restrict__ st, size_t N, int k,
                                                    int32_t* __restrict__ fl, const float* __restrict__ blk,
                                                    float& chk) {
@@ -563,7 +561,7 @@ __device__ __forceinline__ bool colour_solve_mixed(int K, int V, RowFn B, const 
         chk += nn * 0.f;
         const bool cut = nn > o.trust_sh && nn > 0.f;
         clamped = clamped || cut;
-        const float f = cut ? o.trust_sh / nn : 1.f;
+        const float f = omega * (cut ? o.trust_sh / nn : 1.f);
 #pragma unroll
         for (int a = 0; a < 16; ++a)
             if (a < K) st[(GSN_STEP_BASE + ch * K + a) * N + k] = dsh[ch][a] * f;
@@ -605,7 +603,7 @@ __device__ __forceinline__ uint32_t solve_one_mixed(int k, const float* __restri
         return v;
     };
     uint32_t ev = 1u << EV_SOLVED;
-    const float frac = step_fraction<float>(Bf, V, o);
+    const float frac = o.step_frac, omega = overlap_share<float>(Bf, V, o);
     const float abs_scale = 1.0f / (3.0f * (float)o.npix_primary);
     float s[3];
     for (int a = 0; a < 3; ++a) s[a] = scale[a * N + k];
@@ -644,7 +642,7 @@ __device__ __forceinline__ uint32_t solve_one_mixed(int k, const float* __restri
     for (int a = 0; a < 2; ++a) dv[a] *= frac;
     if (clamp_norm_f(2, dv, o.trust_pos * fmaxf(s[0], fmaxf(s[1], s[2])))) ev |= 1u << (EV_CLAMP + 0);
     for (int a = 0; a < 3; ++a) {
-        const float d = R.ux[a] * dv[0] + R.uy[a] * dv[1];
+        const float d = omega * (R.ux[a] * dv[0] + R.uy[a] * dv[1]);
         chk += d * 0.f;
         st[(size_t)a * N + k] = d;
     }
@@ -653,7 +651,7 @@ __device__ __forceinline__ uint32_t solve_one_mixed(int k, const float* __restri
     th *= frac;
     if (clamp_norm_f(1, &th, o.trust_rot)) ev |= 1u << (EV_CLAMP + 1);
     chk += th * 0.f;
-    st[3 * N + k] = th;
+    st[3 * N + k] = omega * th;
     // ---- scaling and opacity in FP32
     {
         float av[2];
@@ -667,7 +665,7 @@ __device__ __forceinline__ uint32_t solve_one_mixed(int k, const float* __restri
             ev |= 1u << (EV_CLAMP + 2);
         for (int a = 0; a < 3; ++a) {
             chk += dsv[a] * 0.f;
-            st[(7 + a) * N + k] = dsv[a];
+            st[(7 + a) * N + k] = omega * dsv[a];
         }
     }
     {
@@ -676,9 +674,10 @@ __device__ __forceinline__ uint32_t solve_one_mixed(int k, const float* __restri
         fl[3 * N + k] = j;
         ev |= decision_events(3, j);
         chk += ds * 0.f;
-        st[10 * N + k] = frac * ds;
+        st[10 * N + k] = omega * (frac * ds);
     }
-    if (colour_solve_mixed(K, V, Bf, gram, o, frac, abs_scale, st, N, k, fl, blk, chk)) ev |= 1u << (EV_CLAMP + 3);
+    if (colour_solve_mixed(K, V, Bf, gram, o, frac, omega, abs_scale, st, N, k, fl, blk, chk))
+        ev |= 1u << (EV_CLAMP + 3);
     if (!(chk == 0.f)) {
         skip_nonfinite(st, fl, N, k, NS);
         return 1u << EV_NONFINITE;

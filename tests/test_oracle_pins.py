@@ -774,7 +774,7 @@ def test_overlap_sums_match_python_brute_force():
     assert np.all(w2 <= w1)
 
 
-def test_overlap_share_scales_every_group_before_the_trust_radii():
+def test_overlap_share_scales_every_group_after_the_trust_radii():
     g, cams, tgts, _ = _solve_case()
     free = dict(npix_primary=32 * 28, trust_pos=1e30, trust_rot=1e30, trust_scale=1e30, trust_sh=1e30)
     res = O.sweep(g, cams, tgts, 0, np.array([[1], [0]]), O.opts(**free))
@@ -788,6 +788,12 @@ def test_overlap_share_scales_every_group_before_the_trust_radii():
     cols = np.r_[0:4, 7:11 + 48]
     assert np.allclose(so[:, cols], omega[:, None] * res["steps"][:, cols], rtol=1e-12, atol=1e-300)
     assert np.array_equal(so[:, 4:7], res["steps"][:, 4:7])
+    # with the trust radii binding, the share scales the clamped steps (overlapping kernels together
+    # stay within about one kernel's radius)
+    tight = dict(npix_primary=32 * 28, trust_pos=1e-3, trust_rot=1e-3, trust_scale=1e-3, trust_sh=1e-3)
+    st_t, _ = O.solve(g, cams[0], O.opts(**tight), S, 2)
+    so_t, _ = O.solve(g, cams[0], O.opts(overlap=1, **tight), S, 2)
+    assert np.allclose(so_t[:, cols], omega[:, None] * st_t[:, cols], rtol=1e-12, atol=1e-300)
 
 
 def test_overlap_share_makes_simultaneous_colour_steps_descend():
