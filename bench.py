@@ -89,16 +89,18 @@ def _targets(cfg, dev):
 
 
 def _trainer(cfg, targets, dev, learned_every=0, step_frac=1.0, n_secondary=None, gauss_newton=False,
-             reserve=False):
+             reserve=False, precision=None):
     """The plain form (FP64 small solves), or with learned_every the mixed + learned form (BF16
-    matrix-core colour Grams, FP32 solves with FP64 for flagged systems, learned step scale).
+    matrix-core colour Grams, FP32 solves with FP64 for flagged systems, single-precision render and
+    accumulation, learned step scale); precision=1 without learned_every is the mixed form alone.
     n_secondary overrides the workload's |N_t|; gauss_newton selects the local Gauss-Newton blocks;
     reserve sizes every frame once, so that sweeps never wait for the device."""
     from paper_2501_13975_amd import gsn
     from paper_2501_13975_amd.train import LocalNewtonTrainer
     from synth.mlp_init import init_params
     g = gsn.DeviceGaussians.from_host(cfg.init, dev)
-    kw = {"step_frac": step_frac, "precision": 1 if learned_every else 0, "overlap": OVERLAP}
+    prec = (1 if learned_every else 0) if precision is None else precision
+    kw = {"step_frac": step_frac, "precision": prec, "overlap": OVERLAP}
     K = cfg.n_secondary if n_secondary is None else n_secondary
     tr = LocalNewtonTrainer(g, cfg.cams, targets, n_secondary=K, solve_kw=kw, gauss_newton=gauss_newton)
     if learned_every:
@@ -602,6 +604,14 @@ def gpu_run(args):
     graph = _graph_rate(cfg, targets, dev, order, args.warmup, args.steps, args.step_frac) if args.graph_leg else None
     log(f"[bench] plain: {args.steps} sweeps in {elapsed:.3f}s; stage ms: "
         + ", ".join(f"{k}={v[0]:.1f}" for k, v in stages.items()))
+    # the mixed precision form alone (full rule every sweep), then with the learned step scale
+    tr = _trainer(cfg, targets, dev, 0, args.step_frac, reserve=True, precision=1)
+    el_m, st_m, _ = _rate_and_profile(tr, order, args.warmup, args.steps, False, dev)
+    tr.close()
+    mixed = {"value": round(args.steps / el_m, 4), "unit": "sweeps/s", "ms_per_step": round(el_m * 1e3 / args.steps, 3),
+             "stage_ms_per_step": {k: round(v[0] / args.steps, 3) for k, v in st_m.items()}}
+    log(f"[bench] mixed: {args.steps / el_m:.2f} sweeps/s; stage ms: "
+        + ", ".join(f"{k}={v[0]:.1f}" for k, v in st_m.items()))
     learned = None
     if args.learned_every:
         tr = _trainer(cfg, targets, dev, args.learned_every, args.step_frac, reserve=True)
@@ -652,8 +662,9 @@ def gpu_run(args):
             del targets
             c4 = _c4_leg(dev, args.learned_every, args.quality_mask, args.quality_step_frac, params, label_mean,
                          args.c4_epochs)
-    return (elapsed, stages, counts, cfg, learned, quality, batched, variants, overshoot, order_exp, first_order, dist,
-            curve, graph, status, c4, pre)
+    return dict(elapsed=elapsed, stages=stages, counts=counts, cfg=cfg, mixed=mixed, learned=learned, quality=quality,
+                batched=batched, variants=variants, overshoot=overshoot, order_exp=order_exp,
+                first_order=first_order, dist=dist, curve=curve, graph=graph, status=status, c4=c4, pre=pre)
 
 
 def _measured_traffic(kernel):
@@ -865,8 +876,8 @@ def main():
         print("bench.py measures one GPU: the training step runs on a single MI355X; run with --gpus 1",
               file=sys.stderr)
         sys.exit(2)
-    (elapsed, stages, counts, cfg, learned, quality, batched, variants, overshoot, order_exp,
-     first_order, dist, curve, graph, status, c4, pre) = gpu_run(args)
+    r = gpu_run(args)
+    elapsed, stages, counts, cfg, status = r["elapsed"], r["stages"], r["counts"], r["cfg"], r["status"]
     ms_per_step = elapsed * 1e3 / args.steps
     value = args.steps / elapsed
     pixels = cfg.width * cfg.height + cfg.n_secondary * (cfg.width // 2) * (cfg.height // 2)
@@ -888,25 +899,26 @@ def main():
                    "gaussians": cfg.n, "width": cfg.width, "height": cfg.height, "cameras": len(cfg.cams),
                    "secondaries": cfg.n_secondary, "form": "plain", "step_frac": args.step_frac},
         "gaussians_updated_per_s": round(value * cfg.n, 1),
-        "sweep_ms_distribution": dist,
+        "sweep_ms_distribution": r["dist"],
         "stage_ms_per_step": {k: round(v[0] / args.steps, 3) for k, v in stages.items()},
         "counts_per_step": {k: int(v / args.steps) for k, v in counts.items()},
         "roofline": rl,
         "sweep_hbm": srl,
         "solve_rules": solve_rules({k: v / args.steps for k, v in counts.items()}),
         "device_status": {k: v for k, v in status.items() if k != "message"},
-        "reserved_graph": graph,
+        "reserved_graph": r["graph"],
         "cpu_baseline": cpu,
-        "learned": learned,
-        "equal_psnr": quality,
-        "learned_pretraining": pre,
-        "c4_equal_psnr": c4,
-        "batched_solve": batched,
-        "variants": variants,
-        "overshoot": overshoot,
-        "schedule_order": order_exp,
-        "first_order": first_order,
-        "psnr_curve": curve,
+        "mixed": r["mixed"],
+        "learned": r["learned"],
+        "equal_psnr": r["quality"],
+        "learned_pretraining": r["pre"],
+        "c4_equal_psnr": r["c4"],
+        "batched_solve": r["batched"],
+        "variants": r["variants"],
+        "overshoot": r["overshoot"],
+        "schedule_order": r["order_exp"],
+        "first_order": r["first_order"],
+        "psnr_curve": r["curve"],
     }
     print(json.dumps(out), flush=True)
 

@@ -81,6 +81,10 @@ typedef struct {
     int32_t tile;
     float alpha_min, alpha_max, T_min, kappa, radius_sigma;
     float bg[3];
+    /* 0: the colour sums along each ray in double (the backward pass takes the colour behind each
+     * splat as the final minus the partial colour); 1: single precision (no double image is kept;
+     * that difference then loses enough to move position and rotation steps by ~1e-4 relative). */
+    int32_t precision;
 } gsn_render_opts;
 
 /* Loss options (Sec. 4.2): L = L2 + lambda_ssim * L_S, with an 11x11 Gaussian
@@ -99,6 +103,10 @@ typedef struct {
     int32_t keep_zstats; /* nonzero: keep this view's per-kernel projected-space
                             statistics in the frame for gsn_frame_zstats */
     int32_t gauss_newton;
+    /* 0: SSIM window sums and correlations, the per-kernel sums of the statistics and the rotation
+     * and scale chain rule in double; 1: mixed form, all of these in single precision.  The SSIM
+     * quotient-rule coefficients and the loss value are computed in double in both forms. */
+    int32_t precision;
 } gsn_loss_opts;
 
 /* Solve options.  Damping: Cholesky of H + mu_j I, mu_j = mu0 10^j for
@@ -205,11 +213,12 @@ gsn_status gsn_frame_destroy(gsn_ctx* ctx, gsn_frame* frame);
  * The tile rectangles and depth keys are computed in single precision with
  * a fixed operation order and no contraction.  d_rgb_out [3][H][W] and
  * d_T_out [H][W] receive copies of the image and final transmittance when
- * not NULL.  Kernels with a NaN or infinite attribute, or whose colour in this
+ * not NULL (opts->precision selects the colour sums' precision for this frame and
+ * its gsn_accumulate_hessian).  Kernels with a NaN or infinite attribute, or whose colour in this
  * view is not finite, are culled (not drawn) and counted (GSN_STAT_CULLED_NONFINITE).
  * A frame in reserved mode (gsn_frame_reserve) is rendered without any allocation
  * or host wait.  Errors: GSN_E_INVALID (null handle or arrays, tile != 16,
- * sh_degree outside 0..3), GSN_E_SHAPE (n < 0, image size <= 0),
+ * sh_degree outside 0..3, precision not 0 or 1), GSN_E_SHAPE (n < 0, image size <= 0),
  * GSN_E_CAPACITY (reserved frame smaller than n or the image). */
 gsn_status gsn_render(gsn_ctx* ctx, const gsn_gaussians* g, const gsn_camera* cam,
                       const gsn_render_opts* opts, gsn_frame* frame, float* d_rgb_out,

@@ -357,7 +357,7 @@ gsn_status gsn_render(gsn_ctx* ctx, const gsn_gaussians* g, const gsn_camera* ca
     if ((st = check_camera(ctx, cam)) != GSN_OK) return st;
     if (opts->tile != GSN_TILE) return fail(ctx, GSN_E_INVALID, "tile must be %d", GSN_TILE);
     if (!(opts->alpha_max > 0.f && opts->alpha_max < 1.f) || !(opts->alpha_min >= 0.f) || !(opts->T_min >= 0.f) ||
-        !(opts->kappa >= 0.f) || !(opts->radius_sigma > 0.f))
+        !(opts->kappa >= 0.f) || !(opts->radius_sigma > 0.f) || (opts->precision != 0 && opts->precision != 1))
         return fail(ctx, GSN_E_INVALID, "render option out of range");
     const bool reserved = f->cap_pairs > 0;
     if (reserved && (g->n > f->cap_n || (int64_t)cam->width * cam->height > (int64_t)f->cap_W * f->cap_H ||
@@ -371,6 +371,7 @@ gsn_status gsn_render(gsn_ctx* ctx, const gsn_gaussians* g, const gsn_camera* ca
     hipStream_t s = ctx->stream;
     const int n = g->n;
     f->rendered = false;
+    f->fp32 = opts->precision == 1;
     f->n = n;
     f->K = (g->sh_degree + 1) * (g->sh_degree + 1);
     f->cam = make_devcam(*cam);
@@ -448,7 +449,7 @@ gsn_status gsn_render(gsn_ctx* ctx, const gsn_gaussians* g, const gsn_camera* ca
         // 5. front-to-back compositing
         StageTimer st_(ctx, GSN_STAGE_RASTER_FWD);
         launch_raster_fwd(bp<uint2>(f->ranges), bp<uint32_t>(f->tile_order), bp<uint32_t>(f->pv_a),
-                          bp<float4>(f->rec), (uint32_t)n, f->cam, f->ro, bp<float>(f->img), bp<double>(f->img64),
+                          bp<float4>(f->rec), (uint32_t)n, f->cam, f->ro, f->fp32, bp<float>(f->img), bp<double>(f->img64),
                           bp<float>(f->Tfin), bp<uint32_t>(f->ncontrib), bp<uint64_t>(f->masks),
                           bp<uint32_t>(f->tile_len), prof_counts(ctx), s);
         // the backward pass takes the tiles with the longest composited prefixes first
@@ -474,6 +475,7 @@ gsn_status gsn_accumulate_hessian(gsn_ctx* ctx, const gsn_gaussians* g, const gs
     if (view_slot < 0 || view_slot >= b->n_views) return fail(ctx, GSN_E_SHAPE, "view_slot %d outside 0..%d", view_slot, b->n_views - 1);
     if (!b->d_data && b->n > 0) return fail(ctx, GSN_E_INVALID, "blocks data is NULL");
     if (!(opts->lambda_ssim >= 0.f)) return fail(ctx, GSN_E_INVALID, "lambda_ssim must be >= 0");
+    if (opts->precision != 0 && opts->precision != 1) return fail(ctx, GSN_E_INVALID, "precision must be 0 or 1");
     HIP_TRY(ctx, hipSetDevice(ctx->device));
     hipStream_t s = ctx->stream;
     const size_t npx = (size_t)f->W * f->H;
@@ -485,7 +487,8 @@ gsn_status gsn_accumulate_hessian(gsn_ctx* ctx, const gsn_gaussians* g, const gs
     {
         StageTimer st_(ctx, GSN_STAGE_LOSS);
         int np_out = 0;
-        launch_loss_maps(bp<float>(f->img), d_target, f->W, f->H, opts->lambda_ssim, bp<float>(f->coef),
+        launch_loss_maps(bp<float>(f->img), d_target, f->W, f->H, opts->lambda_ssim, opts->precision == 1,
+                         bp<float>(f->coef),
                          bp<float>(f->dL), bp<float>(f->hd), bp<double>(f->loss_part), &np_out, s);
         if (d_loss_out) launch_loss_reduce(bp<double>(f->loss_part), np_out, f->W, f->H, d_loss_out, s);
         HIP_TRY(ctx, hipGetLastError());
@@ -503,7 +506,7 @@ gsn_status gsn_accumulate_hessian(gsn_ctx* ctx, const gsn_gaussians* g, const gs
     }
     {
         StageTimer st_(ctx, GSN_STAGE_CHAIN);
-        launch_reduce_chain(*f, *g, opts->weight, view_slot, opts->gauss_newton != 0, *b, zs, s);
+        launch_reduce_chain(*f, *g, opts->weight, view_slot, opts->gauss_newton != 0, opts->precision == 1, *b, zs, s);
     }
     HIP_TRY(ctx, hipGetLastError());
     return GSN_OK;

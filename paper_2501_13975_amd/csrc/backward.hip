@@ -179,12 +179,14 @@ __device__ __forceinline__ void write_partial(float* __restrict__ partial, uint8
 //      out to waves from a block-wide counter)
 //      and the tile's partial sum is written at the (tile, kernel) pair's slot.
 //      Only contributing pairs do the 44-term work.
-// GN: local Gauss-Newton statistics (no loss-gradient times image-curvature terms).
-template <bool GN>
+// GN: local Gauss-Newton statistics (no loss-gradient times image-curvature terms).  CT: the type of
+// the colour sums along the ray (double; float in the mixed form, from the single-precision image).
+template <bool GN, class CT>
 __global__ __launch_bounds__(GSN_BLOCK, 3) void raster_bwd_kernel(
     const uint2* __restrict__ ranges, const uint32_t* __restrict__ order, const uint32_t* __restrict__ ids,
     const float4* __restrict__ rec, uint32_t n, DevCam cam, DevRenderOpts ro,
-    const double* __restrict__ img64, const uint32_t* __restrict__ ncontrib, const uint64_t* __restrict__ masks,
+    const double* __restrict__ img64, const float* __restrict__ img, const uint32_t* __restrict__ ncontrib,
+    const uint64_t* __restrict__ masks,
     const float* __restrict__ dLm, const float* __restrict__ hdm, float* __restrict__ partial,
     uint8_t* __restrict__ flags, uint8_t* __restrict__ kflag, unsigned long long* __restrict__ counts) {
     constexpr int NW = GSN_BLOCK / 64;
@@ -215,7 +217,7 @@ __global__ __launch_bounds__(GSN_BLOCK, 3) void raster_bwd_kernel(
     const uint64_t lt_mask = lane == 0 ? 0ull : (~0ull >> (64 - lane));
     const uint2 rg = ranges[tile];
     const size_t np = (size_t)cam.W * cam.H, pi = (size_t)py * cam.W + px;
-    double cf[3] = {0, 0, 0};
+    CT cf[3] = {CT(0), CT(0), CT(0)};
     uint32_t nc = 0;
     {
         float dlv[3], hv[3];
@@ -223,7 +225,7 @@ __global__ __launch_bounds__(GSN_BLOCK, 3) void raster_bwd_kernel(
         for (int ch = 0; ch < 3; ++ch) {
             dlv[ch] = inside ? dLm[ch * np + pi] : 0.f;
             hv[ch] = inside ? hdm[ch * np + pi] : 0.f;
-            if (inside) cf[ch] = img64[ch * np + pi];
+            if (inside) cf[ch] = img64 ? (CT)img64[ch * np + pi] : (CT)img[ch * np + pi];
         }
         s_lm0[tid] = make_float4(dlv[0], dlv[1], dlv[2], hv[0]);
         s_lm1[tid] = make_float2(hv[1], hv[2]);
@@ -240,7 +242,7 @@ __global__ __launch_bounds__(GSN_BLOCK, 3) void raster_bwd_kernel(
     __syncthreads();
     const uint32_t end = rg.x + s_max;
     float T = 1.f;
-    double Ca0 = 0.0, Ca1 = 0.0, Ca2 = 0.0;
+    CT Ca0 = CT(0), Ca1 = CT(0), Ca2 = CT(0);
     const float fpx = (float)px, fpy = (float)py;
     uint32_t n_eval = 0, n_act = 0, n_part = 0, n_stage = 0;
     for (uint32_t base = rg.x; base < end; base += GSN_BLOCK) {
@@ -383,10 +385,10 @@ __global__ __launch_bounds__(GSN_BLOCK, 3) void raster_bwd_kernel(
                     const float4 b = r_b[j], cc = r_c[j];
                     const SplatEval ev = eval_splat(r_a[j], b, cc, fpx, fpy, ro.alpha_max);
                     const float al = ev.alpha, wT = al * T;
-                    const double wd = (double)wT;
-                    Ca0 += wd * (double)b.w;
-                    Ca1 += wd * (double)cc.x;
-                    Ca2 += wd * (double)cc.y;
+                    const CT wd = (CT)wT;
+                    Ca0 += wd * (CT)b.w;
+                    Ca1 += wd * (CT)cc.x;
+                    Ca2 += wd * (CT)cc.y;
                     // hardware reciprocal (within 1 ulp; the library's divisions are otherwise correctly
                     // rounded): only the pair terms use it, no decision depends on it
                     const float inv = __builtin_amdgcn_rcpf(1.0f - al);
@@ -507,6 +509,7 @@ __global__ __launch_bounds__(GSN_BLOCK, 3) void raster_bwd_kernel(
 // the backward pass wrote, in slot order and in double (deterministic, coalesced 176-byte reads
 // per slot).  A wave per kernel would spend most of the launch starting waves that only read
 // a clear flag.
+template <class Acc>
 __global__ __launch_bounds__(256) void reduce_pairs_kernel(int n, const uint2* __restrict__ rect,
                                                            const uint32_t* __restrict__ pair_off,
                                                            const float* __restrict__ partial,
@@ -537,7 +540,7 @@ __global__ __launch_bounds__(256) void reduce_pairs_kernel(int n, const uint2* _
         const int k = k0 + li;
         const uint32_t nt = (uint32_t)__shfl((int)my_nt, li, 64);
         const uint32_t off = (uint32_t)__shfl((int)my_off, li, 64);
-        double acc = 0.0;
+        Acc acc = Acc(0);
         for (uint32_t base = 0; base < nt; base += 64) {
             const bool fl = base + lane < nt && flags[off + base + lane] != 0;
             uint64_t m = __ballot(fl);
@@ -556,10 +559,10 @@ __global__ __launch_bounds__(256) void reduce_pairs_kernel(int n, const uint2* _
                 }
 #pragma unroll
                 for (int t = 0; t < 8; ++t)
-                    if (t < cntv) acc += (double)v[t];
+                    if (t < cntv) acc += (Acc)v[t];
             }
         }
-        if (lane < GSN_NZ) zsum[(size_t)k * GSN_NZ + lane] = acc;
+        if (lane < GSN_NZ) zsum[(size_t)k * GSN_NZ + lane] = (double)acc;
     }
 }
 
@@ -639,8 +642,8 @@ __global__ __launch_bounds__(128) void chain_pos_kernel(
 }
 
 // One thread per kernel: rotation and scale blocks, in double from the double sums of the
-// conic statistics (both Hessians cancel strongly for thin splats).
-template <bool GN>
+// conic statistics (both Hessians cancel strongly for thin splats); Re = float in the mixed form.
+template <bool GN, class Re>
 __global__ __launch_bounds__(128) void chain_rs_kernel(
     const float* __restrict__ pos, const float* __restrict__ rot, const float* __restrict__ scale, int n,
     const double* __restrict__ zsum, const float4* __restrict__ rec, DevCam cam, float kappa, float weight,
@@ -648,23 +651,23 @@ __global__ __launch_bounds__(128) void chain_rs_kernel(
     const int k = blockIdx.x * blockDim.x + threadIdx.x;
     if (k >= n) return;
     const double* zk = zsum + (size_t)k * GSN_NZ;
-    if (!(zk[43] > 0.0)) return;
-    double gq[3], Hq[3][3];
+    if (!(zk[GSN_ZCOV] > 0.0)) return;
+    Re gq[3], Hq[3][3];
     q_stats(zk, gq, Hq);
     KParams kp;
     load_kparams(pos, rot, scale, rec, n, k, kp);
     const size_t N = (size_t)n;
-    double g[3], H[6];
+    Re g[3], H[6];
     chain_rotation(kp, cam, kappa, gq, Hq, GN, g, H);
 #pragma unroll
-    for (int a = 0; a < 3; ++a) blk[(9 + a) * N + k] += (float)(weight * g[a]);
+    for (int a = 0; a < 3; ++a) blk[(9 + a) * N + k] += (float)((Re)weight * g[a]);
 #pragma unroll
-    for (int a = 0; a < 6; ++a) blk[(12 + a) * N + k] += (float)(weight * H[a]);
+    for (int a = 0; a < 6; ++a) blk[(12 + a) * N + k] += (float)((Re)weight * H[a]);
     chain_scale(kp, cam, kappa, gq, Hq, GN, g, H);
 #pragma unroll
-    for (int a = 0; a < 3; ++a) blk[(18 + a) * N + k] += (float)(weight * g[a]);
+    for (int a = 0; a < 3; ++a) blk[(18 + a) * N + k] += (float)((Re)weight * g[a]);
 #pragma unroll
-    for (int a = 0; a < 6; ++a) blk[(21 + a) * N + k] += (float)(weight * H[a]);
+    for (int a = 0; a < 6; ++a) blk[(21 + a) * N + k] += (float)((Re)weight * H[a]);
 }
 
 }  // namespace
@@ -672,25 +675,27 @@ __global__ __launch_bounds__(128) void chain_rs_kernel(
 void launch_raster_bwd(const gsn_frame& f, const float* dL, const float* hd, bool gauss_newton,
                        unsigned long long* counts, hipStream_t s) {
     const int tiles = f.tiles_x * f.tiles_y;
-    auto kern = gauss_newton ? raster_bwd_kernel<true> : raster_bwd_kernel<false>;
+    // the colour sums of the frame's render: double, or float in the mixed form
+    auto kern = gauss_newton ? (f.fp32 ? raster_bwd_kernel<true, float> : raster_bwd_kernel<true, double>)
+                             : (f.fp32 ? raster_bwd_kernel<false, float> : raster_bwd_kernel<false, double>);
     kern<<<tiles, GSN_BLOCK, 0, s>>>(
         bp<uint2>(f.ranges), bp<uint32_t>(f.bwd_order), bp<uint32_t>(f.pv_a), bp<float4>(f.rec),
-        (uint32_t)f.n, f.cam, f.ro, bp<double>(f.img64),
+        (uint32_t)f.n, f.cam, f.ro, f.fp32 ? nullptr : bp<double>(f.img64), bp<float>(f.img),
         bp<uint32_t>(f.ncontrib), bp<uint64_t>(f.masks), dL, hd, bp<float>(f.partial), bp<uint8_t>(f.flags),
         bp<uint8_t>(f.kflag), counts);
 }
 
 void launch_reduce_chain(const gsn_frame& f, const gsn_gaussians& g, float weight, int slot, bool gauss_newton,
-                         const gsn_blocks& b, float* zstats_out, hipStream_t s) {
+                         bool fp32, const gsn_blocks& b, float* zstats_out, hipStream_t s) {
     if (g.n == 0) return;
     const int K = (g.sh_degree + 1) * (g.sh_degree + 1);
-    reduce_pairs_kernel<<<(g.n + 255) / 256, 256, 0, s>>>(g.n, bp<uint2>(f.rect), bp<uint32_t>(f.pair_off),
-                                                      bp<float>(f.partial), bp<uint8_t>(f.flags),
-                                                      bp<uint8_t>(f.kflag),
-                                                      slot > 0 ? b.d_data + (size_t)29 * g.n : nullptr,
-                                                      bp<double>(f.zsum));
+    auto red_k = fp32 ? reduce_pairs_kernel<float> : reduce_pairs_kernel<double>;
+    red_k<<<(g.n + 255) / 256, 256, 0, s>>>(g.n, bp<uint2>(f.rect), bp<uint32_t>(f.pair_off), bp<float>(f.partial),
+                                            bp<uint8_t>(f.flags), bp<uint8_t>(f.kflag),
+                                            slot > 0 ? b.d_data + (size_t)29 * g.n : nullptr, bp<double>(f.zsum));
     auto pos_k = gauss_newton ? chain_pos_kernel<true> : chain_pos_kernel<false>;
-    auto rs_k = gauss_newton ? chain_rs_kernel<true> : chain_rs_kernel<false>;
+    auto rs_k = gauss_newton ? (fp32 ? chain_rs_kernel<true, float> : chain_rs_kernel<true, double>)
+                             : (fp32 ? chain_rs_kernel<false, float> : chain_rs_kernel<false, double>);
     pos_k<<<(g.n + 127) / 128, 128, 0, s>>>(g.d_pos, g.d_rot, g.d_scale, g.d_sh, g.n, K, bp<double>(f.zsum),
                                             bp<float4>(f.rec), f.cam, f.ro.kappa, weight, slot, b.n_views, b.d_data,
                                             zstats_out);

@@ -6,8 +6,9 @@
 // (eq. local_hessian_gradient applied to the projected quantities z), using
 // second-order jets for z(y).  Sigma = A A^T + kappa I with A = J_persp W R S
 // (Appendix A.3).  Position runs in single precision; scale and rotation run in
-// double precision, because the inverse Q = Sigma^{-1} of thin splats amplifies
-// rounding by the squared condition number of Sigma.
+// double precision in the plain form, because the inverse Q = Sigma^{-1} of thin
+// splats amplifies rounding by the squared condition number of Sigma (the mixed
+// form runs them in single precision: templates on the working type Re).
 #pragma once
 #include "device_common.h"
 
@@ -172,21 +173,22 @@ GSN_HD inline void chain_position(const KParams& kp, const float* shk, size_t st
 
 // Statistics of Q' = (Q'_11, Q'_12, Q'_22): entries 2..4 of the (pi', Q') block, kept in the
 // double precision of the per-kernel sums (the rotation and scale Hessians cancel strongly).
-GSN_HD inline void q_stats(const double* __restrict__ z, double gz[3], double Hz[3][3]) {
+template <class Re>
+GSN_HD inline void q_stats(const double* __restrict__ z, Re gz[3], Re Hz[3][3]) {
     const int pk[3][3] = {{9 + 9, 9 + 10, 9 + 11}, {9 + 10, 9 + 12, 9 + 13}, {9 + 11, 9 + 13, 9 + 14}};
 #pragma unroll
     for (int i = 0; i < 3; ++i) {
-        gz[i] = z[2 + i];
+        gz[i] = (Re)z[2 + i];
 #pragma unroll
-        for (int j = 0; j < 3; ++j) Hz[i][j] = z[pk[i][j]];
+        for (int j = 0; j < 3; ++j) Hz[i][j] = (Re)z[pk[i][j]];
     }
 }
 
 // The six quantities of Sigma = A A^T + kappa I that the conic needs are bilinear in A,
 // F(A) = B_f(A, A): the entries sxx, syy, sxy of A A^T and the three 2x2 minors of A
 // (Cauchy-Binet).  B_f(X, Y) for f = 0..5:
-template <int F>
-GSN_HD inline double conic_bilinear(const double X[2][3], const double Y[2][3]) {
+template <int F, class Re>
+GSN_HD inline Re conic_bilinear(const Re X[2][3], const Re Y[2][3]) {
     if (F == 0) return X[0][0] * Y[0][0] + X[0][1] * Y[0][1] + X[0][2] * Y[0][2];
     if (F == 1) return X[1][0] * Y[1][0] + X[1][1] * Y[1][1] + X[1][2] * Y[1][2];
     if (F == 2) return X[0][0] * Y[1][0] + X[0][1] * Y[1][1] + X[0][2] * Y[1][2];
@@ -198,9 +200,9 @@ GSN_HD inline double conic_bilinear(const double X[2][3], const double Y[2][3]) 
 // Second-order jet of F_f(A(y)) at y = 0 from A0 = A(0), D[i] = dA/dy_i and (if the map is
 // not linear) E(i, j) = d2A/dy_i dy_j:
 //   dF = B(D_i, A0) + B(A0, D_i),  d2F = B(D_i, D_j) + B(D_j, D_i) + B(E_ij, A0) + B(A0, E_ij).
-template <int F, class EFn>
-GSN_HD inline FJet<3, double> bilinear_jet(const double A0[2][3], const double D[3][2][3], EFn E, bool quadratic) {
-    FJet<3, double> r;
+template <int F, class Re, class EFn>
+GSN_HD inline FJet<3, Re> bilinear_jet(const Re A0[2][3], const Re D[3][2][3], EFn E, bool quadratic) {
+    FJet<3, Re> r;
     r.v = conic_bilinear<F>(A0, A0);
 #pragma unroll
     for (int i = 0; i < 3; ++i) r.g[i] = conic_bilinear<F>(D[i], A0) + conic_bilinear<F>(A0, D[i]);
@@ -209,9 +211,9 @@ GSN_HD inline FJet<3, double> bilinear_jet(const double A0[2][3], const double D
     for (int i = 0; i < 3; ++i)
 #pragma unroll
         for (int j = i; j < 3; ++j, ++idx) {
-            double h = conic_bilinear<F>(D[i], D[j]) + conic_bilinear<F>(D[j], D[i]);
+            Re h = conic_bilinear<F>(D[i], D[j]) + conic_bilinear<F>(D[j], D[i]);
             if (quadratic) {
-                double Eij[2][3];
+                Re Eij[2][3];
                 E(i, j, Eij);
                 h += conic_bilinear<F>(Eij, A0) + conic_bilinear<F>(A0, Eij);
             }
@@ -222,13 +224,13 @@ GSN_HD inline FJet<3, double> bilinear_jet(const double A0[2][3], const double D
 
 // Jets of the conic Q = Sigma^{-1} = (syy, -sxy, sxx) / det, det = sum of squared minors +
 // kappa (sxx0 + syy0) + kappa^2 (the form of conic_from_A), with only scalar jets live.
-template <class EFn>
-GSN_HD inline void conic_jets(const double A0[2][3], const double D[3][2][3], EFn E, bool quadratic, double kappa,
-                              FJet<3, double> Q[3]) {
-    typedef FJet<3, double> J;
+template <class Re, class EFn>
+GSN_HD inline void conic_jets(const Re A0[2][3], const Re D[3][2][3], EFn E, bool quadratic, Re kappa,
+                              FJet<3, Re> Q[3]) {
+    typedef FJet<3, Re> J;
     const J sxx0 = bilinear_jet<0>(A0, D, E, quadratic);
     const J syy0 = bilinear_jet<1>(A0, D, E, quadratic);
-    J det = kappa * (sxx0 + syy0) + kappa * kappa;
+    J det = kappa * (sxx0 + syy0) + kappa * kappa;  // all in Re
     {
         const J m = bilinear_jet<3>(A0, D, E, quadratic);
         det = det + m * m;
@@ -249,37 +251,38 @@ GSN_HD inline void conic_jets(const double A0[2][3], const double D[3][2][3], EF
 }
 
 // M' (rows of the perspective Jacobian times the camera rotation, in the splat's principal
-// frame) and R(q) for one kernel, in double.
-GSN_HD inline void frame_M_R(const KParams& kp, const DevCam& c, double M[2][3], double Rq[3][3]) {
-    double tf[3];
+// frame) and R(q) for one kernel, in the working precision Re.
+template <class Re>
+GSN_HD inline void frame_M_R(const KParams& kp, const DevCam& c, Re M[2][3], Re Rq[3][3]) {
+    Re tf[3];
 #pragma unroll
     for (int i = 0; i < 3; ++i)
-        tf[i] = (double)c.R[3 * i] * kp.p[0] + (double)c.R[3 * i + 1] * kp.p[1] + (double)c.R[3 * i + 2] * kp.p[2] +
-                c.t[i];
-    double iz;
-    persp_M<double>(tf, c, M, iz);
+        tf[i] = (Re)c.R[3 * i] * kp.p[0] + (Re)c.R[3 * i + 1] * kp.p[1] + (Re)c.R[3 * i + 2] * kp.p[2] + c.t[i];
+    Re iz;
+    persp_M<Re>(tf, c, M, iz);
     to_frame(M, kp.fc, kp.fs);
-    quat_rot<double>(kp.q, Rq);
+    quat_rot<Re>(kp.q, Rq);
 }
 
 // Scale: A = M' R diag(s) is linear in s, dA/ds_a has the single column a of M' R.
-GSN_HD inline void chain_scale(const KParams& kp, const DevCam& c, float kappa, const double gz[3],
-                               const double Hz[3][3], bool gn, double* g, double* H) {
-    double M[2][3], Rq[3][3];
+template <class Re>
+GSN_HD inline void chain_scale(const KParams& kp, const DevCam& c, float kappa, const Re gz[3],
+                               const Re Hz[3][3], bool gn, Re* g, Re* H) {
+    Re M[2][3], Rq[3][3];
     frame_M_R(kp, c, M, Rq);
-    double A0[2][3], D[3][2][3];
+    Re A0[2][3], D[3][2][3];
 #pragma unroll
     for (int a = 0; a < 3; ++a)
 #pragma unroll
         for (int i = 0; i < 2; ++i) {
-            const double mr = M[i][0] * Rq[0][a] + M[i][1] * Rq[1][a] + M[i][2] * Rq[2][a];
+            const Re mr = M[i][0] * Rq[0][a] + M[i][1] * Rq[1][a] + M[i][2] * Rq[2][a];
             A0[i][a] = mr * kp.s[a];
 #pragma unroll
-            for (int b = 0; b < 3; ++b) D[b][i][a] = b == a ? mr : 0.0;
+            for (int b = 0; b < 3; ++b) D[b][i][a] = b == a ? mr : Re(0);
         }
-    FJet<3, double> Q[3];
-    conic_jets(A0, D, [](int, int, double[2][3]) {}, false, (double)kappa, Q);
-    chain_accumulate<3, 3, double>(Q, gz, Hz, gn, g, H);
+    FJet<3, Re> Q[3];
+    conic_jets(A0, D, [](int, int, Re[2][3]) {}, false, (Re)kappa, Q);
+    chain_accumulate<3, 3, Re>(Q, gz, Hz, gn, g, H);
 }
 
 // Rotation in the tangent space of left rotations: R(omega) = exp([omega]_x) R0, i.e.
@@ -287,16 +290,17 @@ GSN_HD inline void chain_scale(const KParams& kp, const DevCam& c, float kappa, 
 //   dA/domega_i = M' [e_i]_x B0,
 //   d2A/domega_i domega_j = (1/2) (M' e_j)(e_i^T B0) + (1/2) (M' e_i)(e_j^T B0) - delta_ij M' B0
 // (from [e_i]_x [e_j]_x = e_j e_i^T - delta_ij I).
-GSN_HD inline void chain_rotation(const KParams& kp, const DevCam& c, float kappa, const double gz[3],
-                                  const double Hz[3][3], bool gn, double* g, double* H) {
-    double M[2][3], Rq[3][3];
+template <class Re>
+GSN_HD inline void chain_rotation(const KParams& kp, const DevCam& c, float kappa, const Re gz[3],
+                                  const Re Hz[3][3], bool gn, Re* g, Re* H) {
+    Re M[2][3], Rq[3][3];
     frame_M_R(kp, c, M, Rq);
-    double B0[3][3];
+    Re B0[3][3];
 #pragma unroll
     for (int r = 0; r < 3; ++r)
 #pragma unroll
         for (int a = 0; a < 3; ++a) B0[r][a] = Rq[r][a] * kp.s[a];
-    double A0[2][3], D[3][2][3];
+    Re A0[2][3], D[3][2][3];
 #pragma unroll
     for (int i = 0; i < 2; ++i)
 #pragma unroll
@@ -306,21 +310,21 @@ GSN_HD inline void chain_rotation(const KParams& kp, const DevCam& c, float kapp
 #pragma unroll
         for (int a = 0; a < 3; ++a) {
             // column a of [e_k]_x B0 = e_k x B0[:, a]
-            const double b0 = B0[0][a], b1 = B0[1][a], b2 = B0[2][a];
-            const double cx = k == 0 ? 0.0 : (k == 1 ? b2 : -b1);
-            const double cy = k == 0 ? -b2 : (k == 1 ? 0.0 : b0);
-            const double cz = k == 0 ? b1 : (k == 1 ? -b0 : 0.0);
+            const Re b0 = B0[0][a], b1 = B0[1][a], b2 = B0[2][a];
+            const Re cx = k == 0 ? Re(0) : (k == 1 ? b2 : -b1);
+            const Re cy = k == 0 ? -b2 : (k == 1 ? Re(0) : b0);
+            const Re cz = k == 0 ? b1 : (k == 1 ? -b0 : Re(0));
 #pragma unroll
             for (int i = 0; i < 2; ++i) D[k][i][a] = M[i][0] * cx + M[i][1] * cy + M[i][2] * cz;
         }
-    auto E = [&](int i, int j, double out[2][3]) {
+    auto E = [&](int i, int j, Re out[2][3]) {
 #pragma unroll
         for (int r = 0; r < 2; ++r)
 #pragma unroll
             for (int a = 0; a < 3; ++a)
-                out[r][a] = 0.5 * (M[r][j] * B0[i][a] + M[r][i] * B0[j][a]) - (i == j ? A0[r][a] : 0.0);
+                out[r][a] = Re(0.5) * (M[r][j] * B0[i][a] + M[r][i] * B0[j][a]) - (i == j ? A0[r][a] : Re(0));
     };
-    FJet<3, double> Q[3];
-    conic_jets(A0, D, E, true, (double)kappa, Q);
-    chain_accumulate<3, 3, double>(Q, gz, Hz, gn, g, H);
+    FJet<3, Re> Q[3];
+    conic_jets(A0, D, E, true, (Re)kappa, Q);
+    chain_accumulate<3, 3, Re>(Q, gz, Hz, gn, g, H);
 }

@@ -34,6 +34,8 @@ struct gsn_frame {
     // growing mode (buffers sized from the pair count read back after the depth sort)
     int64_t cap_pairs = 0;
     int cap_n = 0, cap_W = 0, cap_H = 0;
+    // mixed form: the colour sums along each ray in single precision (no double image)
+    bool fp32 = false;
     DevCam cam{};
     DevRenderOpts ro{};
     // per kernel
@@ -163,21 +165,21 @@ void launch_tile_ranges(const uint32_t* keys, const uint32_t* d_pairs, uint32_t 
 // list lengths of ranges when lens is null, else lens
 void launch_tile_order(const uint2* ranges, const uint32_t* lens, int tiles, uint32_t* order, hipStream_t s);
 void launch_raster_fwd(const uint2* ranges, const uint32_t* order, const uint32_t* ids, const float4* rec, uint32_t n, const DevCam& cam,
-                       const DevRenderOpts& ro, float* img, double* img64, float* Tfin, uint32_t* ncontrib,
+                       const DevRenderOpts& ro, bool fp32, float* img, double* img64, float* Tfin, uint32_t* ncontrib,
                        uint64_t* masks, uint32_t* tile_len, unsigned long long* counts, hipStream_t s);
 void launch_downsample2x(const float* src, int W, int H, float* dst, hipStream_t s);
 void launch_scene_center(const float* pos, int n, double* out, hipStream_t s);
 
 // ---- launchers (loss.hip)
-void launch_loss_maps(const float* img, const float* tgt, int W, int H, float lambda, float* coef, float* dL,
-                      float* hd, double* part, int* nparts, hipStream_t s);
+void launch_loss_maps(const float* img, const float* tgt, int W, int H, float lambda, bool fp32, float* coef,
+                      float* dL, float* hd, double* part, int* nparts, hipStream_t s);
 void launch_loss_reduce(const double* part, int nparts, int W, int H, double* out, hipStream_t s);
 
 // ---- launchers (backward.hip)
 void launch_raster_bwd(const gsn_frame& f, const float* dL, const float* hd, bool gauss_newton,
                        unsigned long long* counts, hipStream_t s);
 void launch_reduce_chain(const gsn_frame& f, const gsn_gaussians& g, float weight, int slot, bool gauss_newton,
-                         const gsn_blocks& b, float* zstats_out, hipStream_t s);
+                         bool fp32, const gsn_blocks& b, float* zstats_out, hipStream_t s);
 
 // ---- launchers (solve.hip)
 // nonfinite: device counter of kernels skipped for non-finite blocks or steps (always counted);

@@ -30,8 +30,10 @@ namespace {
 constexpr int T = 16, HALO = 5, R = T + 2 * HALO;  // 26
 constexpr double kC1 = 0.01 * 0.01, kC2 = 0.03 * 0.03;
 
-__device__ __forceinline__ void window_weights(double* g, double* g2) {
-    // normalised 1D Gaussian, sigma 1.5; the 2D window is the outer product
+template <class Re>
+__device__ __forceinline__ void window_weights(Re* g, Re* g2) {
+    // normalised 1D Gaussian, sigma 1.5; the 2D window is the outer product (weights evaluated in
+    // double, then rounded to the working type)
     if (threadIdx.x < 11) {
         double s = 0.0, v[11];
         for (int i = 0; i < 11; ++i) {
@@ -39,17 +41,18 @@ __device__ __forceinline__ void window_weights(double* g, double* g2) {
             s += v[i];
         }
         const double gi = v[threadIdx.x] / s;
-        g[threadIdx.x] = gi;
-        g2[threadIdx.x] = gi * gi;
+        g[threadIdx.x] = (Re)gi;
+        g2[threadIdx.x] = (Re)(gi * gi);
     }
 }
 
+template <class Re>
 __global__ __launch_bounds__(256) void ssim_coef_kernel(const float* __restrict__ img, const float* __restrict__ tgt,
                                                          int W, int H, float* __restrict__ coef,
                                                          double* __restrict__ part) {
-    __shared__ double g[11], g2[11];
-    __shared__ double sc[R][R], st[R][R];
-    __shared__ double hs[5][R][T];
+    __shared__ Re g[11], g2[11];
+    __shared__ Re sc[R][R], st[R][R];
+    __shared__ Re hs[5][R][T];
     const int ch = blockIdx.z;
     const int x0 = blockIdx.x * T - HALO, y0 = blockIdx.y * T - HALO;
     const size_t np = (size_t)W * H;
@@ -59,16 +62,16 @@ __global__ __launch_bounds__(256) void ssim_coef_kernel(const float* __restrict_
     for (int i = threadIdx.x; i < R * R; i += 256) {
         const int yy = i / R, xx = i % R, x = x0 + xx, y = y0 + yy;
         const bool in = x >= 0 && y >= 0 && x < W && y < H;
-        sc[yy][xx] = in ? (double)I[(size_t)y * W + x] : 0.0;
-        st[yy][xx] = in ? (double)Tg[(size_t)y * W + x] : 0.0;
+        sc[yy][xx] = in ? (Re)I[(size_t)y * W + x] : Re(0.0);
+        st[yy][xx] = in ? (Re)Tg[(size_t)y * W + x] : Re(0.0);
     }
     __syncthreads();
     for (int i = threadIdx.x; i < R * T; i += 256) {
         const int yy = i / T, xx = i % T;
-        double a = 0, b = 0, c = 0, d = 0, e = 0;
+        Re a = 0, b = 0, c = 0, d = 0, e = 0;
 #pragma unroll
         for (int k = 0; k < 11; ++k) {
-            const double u = sc[yy][xx + k], v = st[yy][xx + k], w = g[k];
+            const Re u = sc[yy][xx + k], v = st[yy][xx + k], w = g[k];
             a += w * u;
             b += w * v;
             c += w * u * u;
@@ -84,18 +87,20 @@ __global__ __launch_bounds__(256) void ssim_coef_kernel(const float* __restrict_
     __syncthreads();
     const int lx = threadIdx.x % T, ly = threadIdx.x / T;
     const int x = blockIdx.x * T + lx, y = blockIdx.y * T + ly;
-    double l2 = 0.0, ls = 0.0;
+    double l2 = 0.0, ls = 0.0;  // loss partials in double in both forms
     if (x < W && y < H) {
-        double m[5] = {0, 0, 0, 0, 0};
+        Re m[5] = {0, 0, 0, 0, 0};
 #pragma unroll
         for (int k = 0; k < 11; ++k)
 #pragma unroll
             for (int q = 0; q < 5; ++q) m[q] += g[k] * hs[q][ly + k][lx];
+        // the quotient-rule coefficients in double in both forms: their terms in 1/f2 and 1/f3 cancel
+        // to a small fraction of their size in flat regions, which single precision does not resolve
         const double mu = m[0], mut = m[1];
         const double f0 = 2.0 * mu * mut + kC1;
-        const double f1 = 2.0 * (m[4] - mu * mut) + kC2;
+        const double f1 = 2.0 * ((double)m[4] - mu * mut) + kC2;
         const double f2 = mu * mu + mut * mut + kC1;
-        const double f3 = (m[2] - mu * mu) + (m[3] - mut * mut) + kC2;
+        const double f3 = ((double)m[2] - mu * mu) + ((double)m[3] - mut * mut) + kC2;
         const double F = (f0 * f1) / (f2 * f3);
         const double i0 = 1.0 / f0, i1 = 1.0 / f1, i2 = 1.0 / f2, i3 = 1.0 / f3;
         const double a0 = 2.0 * mut * i0 - 2.0 * mut * i1 - 2.0 * mu * i2 + 2.0 * mu * i3;
@@ -118,7 +123,7 @@ __global__ __launch_bounds__(256) void ssim_coef_kernel(const float* __restrict_
         cf[7 * np + pi] = (float)(F * btc);
         const double r = (double)sc[ly + HALO][lx + HALO] - (double)st[ly + HALO][lx + HALO];
         l2 = r * r;
-        ls = 1.0 - F;
+        ls = 1.0 - (double)F;
     }
     // deterministic block reduction in double: a butterfly within each wave, then the four wave
     // sums in wave order
@@ -148,12 +153,13 @@ __global__ __launch_bounds__(256) void ssim_coef_kernel(const float* __restrict_
 // tiles, and the small LDS footprint keeps several workgroups per CU.
 constexpr int T2 = 32, R2 = T2 + 2 * HALO;  // 42
 
+template <class Re>
 __global__ __launch_bounds__(256) void ssim_grad_kernel(const float* __restrict__ img, const float* __restrict__ tgt,
                                                          int W, int H, float lambda, const float* __restrict__ coef,
                                                          float* __restrict__ dL, float* __restrict__ hd) {
-    __shared__ double g[11], g2[11];
-    __shared__ double sm[R2][R2];
-    __shared__ double hs[R2][T2];
+    __shared__ Re g[11], g2[11];
+    __shared__ Re sm[R2][R2];
+    __shared__ Re hs[R2][T2];
     const int ch = blockIdx.z;
     const int x0 = blockIdx.x * T2 - HALO, y0 = blockIdx.y * T2 - HALO;
     const size_t np = (size_t)W * H;
@@ -162,15 +168,15 @@ __global__ __launch_bounds__(256) void ssim_grad_kernel(const float* __restrict_
     const int lx = threadIdx.x % T2, ly0 = 4 * (threadIdx.x / T2);  // rows ly0 .. ly0 + 3
     // d1 = v0 + t v1 - c v2 and d2 = v3 + t v4 + c v5 + c^2 v6 + c t v7 - v2 are linear in the
     // correlations v_q, so each map's correlation is folded in as soon as it is taken
-    double cv[4], tv[4], d1[4], d2[4];
+    Re cv[4], tv[4], d1[4], d2[4];
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
         const int x = blockIdx.x * T2 + lx, y = blockIdx.y * T2 + ly0 + r;
         const bool in = x < W && y < H;
         const size_t pi = in ? (size_t)y * W + x : 0;
-        cv[r] = in ? (double)img[ch * np + pi] : 0.0;
-        tv[r] = in ? (double)tgt[ch * np + pi] : 0.0;
-        d1[r] = d2[r] = 0.0;
+        cv[r] = in ? (Re)img[ch * np + pi] : Re(0.0);
+        tv[r] = in ? (Re)tgt[ch * np + pi] : Re(0.0);
+        d1[r] = d2[r] = Re(0.0);
     }
     // the halo tile of map q + 1 is loaded into registers while map q is correlated
     constexpr int NLD = (R2 * R2 + 255) / 256;  // 7 elements per thread
@@ -190,20 +196,20 @@ __global__ __launch_bounds__(256) void ssim_grad_kernel(const float* __restrict_
 #pragma unroll
         for (int j = 0; j < NLD; ++j) {
             const int i = threadIdx.x + 256 * j;
-            if (i < R2 * R2) sm[i / R2][i % R2] = (double)pre[j];
+            if (i < R2 * R2) sm[i / R2][i % R2] = (Re)pre[j];
         }
         __syncthreads();
         if (q + 1 < 8) load_map(q + 1);
-        const double* wq = q < 3 ? g : g2;
+        const Re* wq = q < 3 ? g : g2;
         // horizontal: strips of four outputs share their 14 inputs
         for (int i = threadIdx.x; i < R2 * (T2 / 4); i += 256) {
             const int yy = i / (T2 / 4), xs = 4 * (i % (T2 / 4));
-            double in14[14];
+            Re in14[14];
 #pragma unroll
             for (int k = 0; k < 14; ++k) in14[k] = sm[yy][xs + k];
 #pragma unroll
             for (int o = 0; o < 4; ++o) {
-                double a = 0.0;
+                Re a = Re(0.0);
 #pragma unroll
                 for (int k = 0; k < 11; ++k) a += wq[k] * in14[o + k];
                 hs[yy][xs + o] = a;
@@ -211,29 +217,29 @@ __global__ __launch_bounds__(256) void ssim_grad_kernel(const float* __restrict_
         }
         __syncthreads();
         // vertical: the thread's four rows share their 14 inputs
-        double col[14];
+        Re col[14];
 #pragma unroll
         for (int k = 0; k < 14; ++k) col[k] = hs[ly0 + k][lx];
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
-            double a = 0.0;
+            Re a = Re(0.0);
 #pragma unroll
             for (int k = 0; k < 11; ++k) a += wq[k] * col[r + k];
-            const double c = cv[r], t = tv[r];
-            const double k1 = q == 0 ? 1.0 : q == 1 ? t : q == 2 ? -c : 0.0;
-            const double k2 = q < 2 ? 0.0 : q == 2 ? -1.0 : q == 3 ? 1.0 : q == 4 ? t : q == 5 ? c : q == 6 ? c * c : c * t;
+            const Re c = cv[r], t = tv[r];
+            const Re k1 = q == 0 ? Re(1.0) : q == 1 ? t : q == 2 ? -c : Re(0.0);
+            const Re k2 = q < 2 ? Re(0.0) : q == 2 ? -Re(1.0) : q == 3 ? Re(1.0) : q == 4 ? t : q == 5 ? c : q == 6 ? c * c : c * t;
             d1[r] += k1 * a;
             d2[r] += k2 * a;
         }
     }
-    const double norm = 1.0 / (3.0 * (double)np);
+    const Re norm = Re(1.0) / (Re(3.0) * (Re)np);
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
         const int x = blockIdx.x * T2 + lx, y = blockIdx.y * T2 + ly0 + r;
         if (x >= W || y >= H) continue;
         const size_t pi = (size_t)y * W + x;
-        dL[ch * np + pi] = (float)((cv[r] - tv[r]) * norm - (double)lambda * norm * d1[r]);
-        hd[ch * np + pi] = (float)(norm - (double)lambda * norm * d2[r]);
+        dL[ch * np + pi] = (float)((cv[r] - tv[r]) * norm - (Re)lambda * norm * d1[r]);
+        hd[ch * np + pi] = (float)(norm - (Re)lambda * norm * d2[r]);
     }
 }
 
@@ -262,13 +268,18 @@ __global__ void loss_reduce_kernel(const double* __restrict__ part, int nparts, 
 
 }  // namespace
 
-void launch_loss_maps(const float* img, const float* tgt, int W, int H, float lambda, float* coef, float* dL,
-                      float* hd, double* part, int* nparts, hipStream_t s) {
+void launch_loss_maps(const float* img, const float* tgt, int W, int H, float lambda, bool fp32, float* coef,
+                      float* dL, float* hd, double* part, int* nparts, hipStream_t s) {
     dim3 grid((W + T - 1) / T, (H + T - 1) / T, 3);
     *nparts = (int)(grid.x * grid.y * grid.z);
-    ssim_coef_kernel<<<grid, 256, 0, s>>>(img, tgt, W, H, coef, part);
     dim3 grid2((W + T2 - 1) / T2, (H + T2 - 1) / T2, 3);
-    ssim_grad_kernel<<<grid2, 256, 0, s>>>(img, tgt, W, H, lambda, coef, dL, hd);
+    if (fp32) {
+        ssim_coef_kernel<float><<<grid, 256, 0, s>>>(img, tgt, W, H, coef, part);
+        ssim_grad_kernel<float><<<grid2, 256, 0, s>>>(img, tgt, W, H, lambda, coef, dL, hd);
+    } else {
+        ssim_coef_kernel<double><<<grid, 256, 0, s>>>(img, tgt, W, H, coef, part);
+        ssim_grad_kernel<double><<<grid2, 256, 0, s>>>(img, tgt, W, H, lambda, coef, dL, hd);
+    }
 }
 
 void launch_loss_reduce(const double* part, int nparts, int W, int H, double* out, hipStream_t s) {

@@ -654,7 +654,9 @@ __global__ __launch_bounds__(1024) void tile_order_kernel(const uint2* __restric
 // gets the ordered list of the batch's entries whose alpha-support box meets its
 // band, so a wave only steps through entries that can composite in it.
 // ---------------------------------------------------------------------------
-// Six waves per SIMD (at most 80 VGPRs, no spills; six workgroups' LDS fit in a CU).
+// Six waves per SIMD (at most 80 VGPRs, no spills; six workgroups' LDS fit in a CU).  CT: the type
+// of the colour sums (double; float in the mixed form, which then writes no double image).
+template <class CT>
 __global__ __launch_bounds__(GSN_BLOCK, 6) void raster_fwd_kernel(
     const uint2* __restrict__ ranges, const uint32_t* __restrict__ order, const uint32_t* __restrict__ ids, const float4* __restrict__ rec, uint32_t n,
     DevCam cam, DevRenderOpts ro, float* __restrict__ img, double* __restrict__ img64, float* __restrict__ Tfin,
@@ -676,9 +678,9 @@ __global__ __launch_bounds__(GSN_BLOCK, 6) void raster_fwd_kernel(
     const uint64_t lt_mask = lane == 0 ? 0ull : (~0ull >> (64 - lane));
     const float tx0 = (float)(tx * GSN_TILE), tx1 = tx0 + (float)(GSN_TILE - 1);
     const float ty0 = (float)(ty * GSN_TILE);
-    // colour accumulated in double: the backward pass subtracts partial sums from it
+    // colour accumulated in CT: the backward pass subtracts partial sums from it
     float T = 1.0f;
-    double C0 = 0.0, C1 = 0.0, C2 = 0.0;
+    CT C0 = CT(0), C1 = CT(0), C2 = CT(0);
     uint32_t last = 0;
     bool done = !inside;
     const float fpx = (float)px, fpy = (float)py;
@@ -754,10 +756,10 @@ __global__ __launch_bounds__(GSN_BLOCK, 6) void raster_fwd_kernel(
                 comp = false;
             }
             if (comp) {
-                const double w = (double)(ev.alpha * T);
-                C0 += w * (double)b.w;
-                C1 += w * (double)cc.x;
-                C2 += w * (double)cc.y;
+                const CT w = (CT)(ev.alpha * T);
+                C0 += w * (CT)b.w;
+                C1 += w * (CT)cc.x;
+                C2 += w * (CT)cc.y;
                 T = Tn;
                 last = base + j + 1 - rg.x;
 #pragma unroll
@@ -799,14 +801,15 @@ __global__ __launch_bounds__(GSN_BLOCK, 6) void raster_fwd_kernel(
     }
     if (inside) {
         const size_t np = (size_t)cam.W * cam.H, pi = (size_t)py * cam.W + px;
-        const double c0 = C0 + (double)(T * ro.bg[0]), c1 = C1 + (double)(T * ro.bg[1]),
-                     c2 = C2 + (double)(T * ro.bg[2]);
+        const CT c0 = C0 + (CT)(T * ro.bg[0]), c1 = C1 + (CT)(T * ro.bg[1]), c2 = C2 + (CT)(T * ro.bg[2]);
         img[pi] = (float)c0;
         img[np + pi] = (float)c1;
         img[2 * np + pi] = (float)c2;
-        img64[pi] = c0;
-        img64[np + pi] = c1;
-        img64[2 * np + pi] = c2;
+        if (img64) {
+            img64[pi] = (double)c0;
+            img64[np + pi] = (double)c1;
+            img64[2 * np + pi] = (double)c2;
+        }
         Tfin[pi] = T;
         ncontrib[pi] = last;
     }
@@ -966,11 +969,15 @@ void launch_tile_order(const uint2* ranges, const uint32_t* lens, int tiles, uin
 }
 
 void launch_raster_fwd(const uint2* ranges, const uint32_t* order, const uint32_t* ids, const float4* rec, uint32_t n, const DevCam& cam,
-                       const DevRenderOpts& ro, float* img, double* img64, float* Tfin, uint32_t* ncontrib,
+                       const DevRenderOpts& ro, bool fp32, float* img, double* img64, float* Tfin, uint32_t* ncontrib,
                        uint64_t* masks, uint32_t* tile_len, unsigned long long* counts, hipStream_t s) {
     const int tiles = cam.tiles_x * cam.tiles_y;
-    raster_fwd_kernel<<<tiles, GSN_BLOCK, 0, s>>>(ranges, order, ids, rec, n, cam, ro, img, img64, Tfin, ncontrib, masks,
-                                                  tile_len, counts);
+    if (fp32)
+        raster_fwd_kernel<float><<<tiles, GSN_BLOCK, 0, s>>>(ranges, order, ids, rec, n, cam, ro, img, nullptr, Tfin,
+                                                             ncontrib, masks, tile_len, counts);
+    else
+        raster_fwd_kernel<double><<<tiles, GSN_BLOCK, 0, s>>>(ranges, order, ids, rec, n, cam, ro, img, img64, Tfin,
+                                                              ncontrib, masks, tile_len, counts);
 }
 
 void launch_downsample2x(const float* src, int W, int H, float* dst, hipStream_t s) {

@@ -105,12 +105,12 @@ class CCamera(ctypes.Structure):
 class CRenderOpts(ctypes.Structure):
     _fields_ = [("tile", ctypes.c_int32), ("alpha_min", ctypes.c_float), ("alpha_max", ctypes.c_float),
                 ("T_min", ctypes.c_float), ("kappa", ctypes.c_float), ("radius_sigma", ctypes.c_float),
-                ("bg", ctypes.c_float * 3)]
+                ("bg", ctypes.c_float * 3), ("precision", ctypes.c_int32)]
 
 
 class CLossOpts(ctypes.Structure):
     _fields_ = [("lambda_ssim", ctypes.c_float), ("weight", ctypes.c_float), ("keep_zstats", ctypes.c_int32),
-                ("gauss_newton", ctypes.c_int32)]
+                ("gauss_newton", ctypes.c_int32), ("precision", ctypes.c_int32)]
 
 
 class CSolveOpts(ctypes.Structure):
@@ -133,12 +133,15 @@ class CSteps(ctypes.Structure):
 
 
 def render_opts(alpha_min=1.0 / 255.0, alpha_max=0.99, T_min=1e-4, kappa=0.3, radius_sigma=3.0,
-                bg=(0.0, 0.0, 0.0)):
-    return CRenderOpts(16, alpha_min, alpha_max, T_min, kappa, radius_sigma, (ctypes.c_float * 3)(*bg))
+                bg=(0.0, 0.0, 0.0), precision=0):
+    """precision 1: the mixed form's single-precision colour sums."""
+    return CRenderOpts(16, alpha_min, alpha_max, T_min, kappa, radius_sigma, (ctypes.c_float * 3)(*bg),
+                       int(precision))
 
 
-def loss_opts(lambda_ssim=0.2, weight=1.0, keep_zstats=False, gauss_newton=False):
-    return CLossOpts(lambda_ssim, weight, int(keep_zstats), int(gauss_newton))
+def loss_opts(lambda_ssim=0.2, weight=1.0, keep_zstats=False, gauss_newton=False, precision=0):
+    """precision 1: the mixed form's single-precision SSIM maps, statistic sums and rotation/scale chain."""
+    return CLossOpts(lambda_ssim, weight, int(keep_zstats), int(gauss_newton), int(precision))
 
 
 def solve_opts(npix_primary, kappa=0.3, damp_rel=1e-3, damp_abs=1e-12, pivot_min=1e-3, max_escalations=7,

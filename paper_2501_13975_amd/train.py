@@ -38,9 +38,12 @@ class LocalNewtonTrainer:
         self.chalf = [gsn.camera_half(c) for c in self.ccams]
         self.targets = targets
         self.n_secondary = int(n_secondary) if len(self.cams) > 1 else 0
-        self.ro = render_opts or gsn.render_opts()
-        self.lo = gsn.loss_opts(lambda_ssim, 1.0, keep_zstats, gauss_newton)
         self.solve_kw = dict(solve_kw or {})
+        # the mixed form (solve precision 1) also accumulates in single precision; its colour sums along
+        # each ray stay in double (in single precision they move the position and rotation steps by ~1e-4)
+        mixed = int(self.solve_kw.get("precision", 0) == 1)
+        self.ro = render_opts or gsn.render_opts()
+        self.lo = gsn.loss_opts(lambda_ssim, 1.0, keep_zstats, gauss_newton, precision=mixed)
         V = 1 + self.n_secondary
         self.blocks = gsn.Blocks(gauss.n, V, self.dev)
         self.steps = gsn.Steps(gauss.n, gauss.sh_degree, self.dev)

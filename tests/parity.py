@@ -86,17 +86,17 @@ BLOCK_GROUPS = {
 STEP_GROUPS = {"position": slice(0, 3), "rotation": slice(3, 4), "scale": slice(7, 10), "opacity": slice(10, 11)}
 
 
-def gpu_view(ctx, gsn, dg, cam, target_t, lam, blocks, slot, keep=True, gn=False):
+def gpu_view(ctx, gsn, dg, cam, target_t, lam, blocks, slot, keep=True, gn=False, precision=0, render_precision=0):
     """Render + accumulate one view on the GPU; returns numpy copies of every stage."""
     import torch
     fr = ctx.frame()
     ccam = cam if isinstance(cam, gsn.CCamera) else gsn.camera(cam)
-    ro = gsn.render_opts()
+    ro = gsn.render_opts(precision=render_precision)
     rgb = torch.zeros(3, cam.height, cam.width, dtype=torch.float32, device=ctx.device)
     T = torch.zeros(cam.height, cam.width, dtype=torch.float32, device=ctx.device)
     ctx.render(dg, ccam, ro, fr, rgb, T)
     loss = torch.zeros(2, dtype=torch.float64, device=ctx.device)
-    ctx.accumulate_hessian(dg, fr, target_t, gsn.loss_opts(lam, 1.0, keep, gn), slot, blocks, loss)
+    ctx.accumulate_hessian(dg, fr, target_t, gsn.loss_opts(lam, 1.0, keep, gn, precision), slot, blocks, loss)
     torch.cuda.synchronize()
     ranges, ids, depth, rect, nc = fr.lists(dg.n, cam.width * cam.height)
     dL, h = fr.loss_maps(cam.height, cam.width)
@@ -119,6 +119,46 @@ def oracle_view(g, cam, target, lam, o=None, gn=False):
     B = O.blocks(g, fr, dL, hd)
     Z = O.zstats(g, fr, dL, hd)
     return dict(fr=fr, parts=parts, dL=dL, hd=hd, blocks=B, z=Z)
+
+
+def view_errors(g, cam, gv, ov, blk):
+    """Per-stage relative errors of one GPU view (gpu_view, its single-view blocks) against the oracle's
+    (oracle_view), on the pixels and kernels whose decisions are unambiguous; returns (errors, kept kernels)."""
+    mask = pixel_mask(ov)
+    errs = {"ambiguous_px": int((~mask).sum())}
+    fr = ov["fr"]
+    errs["img"] = rel_inf(gv["img"][:, mask], fr.img[:, mask])
+    errs["T"] = rel_inf(gv["T"][mask], fr.Tfinal[mask])
+    errs["ncontrib_mismatch"] = int((gv["ncontrib"][mask] != fr.ncontrib[mask]).sum())
+    errs["loss_L2"] = abs(gv["loss"][0] - ov["parts"][0]) / abs(ov["parts"][0])
+    errs["loss_S"] = abs(gv["loss"][1] - ov["parts"][1]) / abs(ov["parts"][1])
+    # loss maps beyond the SSIM reach of the ambiguous pixels (their windows carry an ambiguous
+    # pixel's legitimate difference into the neighbours' derivatives)
+    reach = ssim_reach(mask)
+    errs["dL"] = rel_inf(gv["dL"][:, ~reach], ov["dL"][:, ~reach])
+    errs["h"] = rel_inf(gv["h"][:, ~reach], ov["hd"][:, ~reach])
+    # kernels composited at an ambiguous pixel or within its reach are excluded from the
+    # per-kernel comparisons
+    bad = near_threshold_kernels(fr, g.n) | kernels_in_reach(fr, reach, g.n)
+    errs["excluded_kernels"] = int(bad.sum())
+    keep = ~bad
+    gz, Hz, wz = zstats_gpu_to_full(gv["z"])
+    # the oracle's statistics in each kernel's principal frame, taken from the oracle's own projection
+    fc, fs = oracle_frames(g, cam)
+    Zo = zstats_to_frame(ov["z"], fc, fs)
+    errs["z_g"] = rel_inf(gz[keep], Zo[keep, :9])
+    # the library keeps the (pi, Q, c~) block and the sigma-sigma entry: the sigma cross terms
+    # are not needed by any attribute group (no attribute moves both sigma and pi, Q or c~)
+    used = np.zeros((9, 9), bool)
+    used[:5, :5] = used[:5, 6:] = used[6:, :5] = True
+    used[5, 5] = True
+    used[[6, 7, 8], [6, 7, 8]] = True
+    errs["z_H"] = rel_inf(Hz[keep][:, used], Zo[keep, 9:90].reshape(-1, 9, 9)[:, used])
+    errs["z_w"] = rel_inf(wz[keep], Zo[keep, 90])
+    Bg = blocks_gpu_to_oracle_view(blk, 0)
+    for name, sl in BLOCK_GROUPS.items():
+        errs[name] = rel_inf(Bg[keep][:, sl], ov["blocks"][keep][:, sl])
+    return errs, keep
 
 
 def compare_binning(gv, ov, n):

@@ -7,10 +7,21 @@ import pytest
 
 from oracle import oracle as O
 from synth.scenes import make_config
-from tests.parity import STEP_GROUPS, rel_inf, summed_to_gpu_blocks
+from tests.parity import BLOCK_GROUPS, STEP_GROUPS, rel_inf, summed_to_gpu_blocks
 
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
+
+# Bars of the mixed form against the FP64 oracle (relative infinity norm per tensor, attribute group
+# or step group).  Its single-precision accumulation keeps every stage of one view within the plain
+# form's 1e-5 (measured up to 6e-6) and the determined steps within the Newton-step bar 1e-4
+# (measured up to 2.5e-5).  Single-precision colour sums keep the view's stages within 1e-5 too,
+# but the backward pass takes each splat's colour behind it as the difference of the final and the
+# partial colour, and that cancellation moves the determined position and rotation steps by up to
+# 1.5e-4 of their largest: bounded at 1e-3, and not part of the mixed form.
+MIXED_VIEW_TOL = 1e-5
+MIXED_STEP_TOL = 1e-4
+FP32_COLOUR_STEP_TOL = 1e-3
 
 
 @pytest.fixture(scope="module")
@@ -95,3 +106,74 @@ def test_mixed_solve_error_against_oracle(gsn, ctx):
     for name in STEP_GROUPS:
         assert errs[name] < 1e-4, (name, errs[name])
     assert errs["colour_rel_p50"] < 1e-4 and errs["colour_rel_p99"] < 1e-3
+
+
+def test_mixed_view_stages_against_oracle(gsn, ctx):
+    """The mixed form's single-precision accumulation (SSIM window sums, per-kernel statistic sums,
+    rotation and scale chain) against the FP64 oracle, beside the plain form's errors on the same
+    view; the single-precision colour sums of the render are measured too."""
+    from tests.parity import gpu_view, oracle_view, view_errors
+    cfg = make_config("c1", n=6000, width=250, height=190, n_views=6)
+    cam = cfg.cams[2]
+    g = cfg.init
+    tgt = O.render(cfg.gt, cam, O.opts()).img.astype(np.float32)
+    ov = oracle_view(g, cam, tgt, 0.2)
+    dg = gsn.DeviceGaussians.from_host(g)
+    out = {}
+    for name, prec, rprec in (("plain", 0, 0), ("mixed", 1, 0), ("fp32 colour", 1, 1)):
+        blocks = gsn.Blocks(g.n, 1, ctx.device)
+        ctx.blocks_zero(blocks)
+        gv = gpu_view(ctx, gsn, dg, cam, torch.tensor(tgt, device=ctx.device), 0.2, blocks, 0, precision=prec,
+                      render_precision=rprec)
+        out[name], _ = view_errors(g, cam, gv, ov, blocks.view().cpu().numpy())
+    print("\n[view stages, plain | mixed | mixed with fp32 colour sums] " + " ".join(
+        f"{k}={out['plain'][k]:.2e}|{out['mixed'][k]:.2e}|{out['fp32 colour'][k]:.2e}" for k in out["plain"]),
+        flush=True)
+    for name in ("mixed", "fp32 colour"):
+        e = out[name]
+        assert e["ncontrib_mismatch"] == 0
+        for k in ("img", "T", "loss_L2", "loss_S", "dL", "h", "z_g", "z_H", "z_w") + tuple(BLOCK_GROUPS):
+            assert e[k] < MIXED_VIEW_TOL, (name, k, e[k])
+
+
+def test_mixed_sweep_steps_against_oracle(gsn, ctx):
+    """A whole mixed-form sweep (double colour sums, single-precision accumulation, BF16 colour
+    Gram, FP32 solve) against the oracle's FP64 sweep, and the same with single-precision colour
+    sums: the steps of the kernels whose step is determined to 1e-5 of the blocks, per group."""
+    from paper_2501_13975_amd.train import LocalNewtonTrainer
+    from tests.parity import near_threshold_kernels, step_sensitivity
+    cfg = make_config("c1", n=4000, width=200, height=150, n_views=8)
+    tg = [O.render(cfg.gt, c, O.opts()).img.astype(np.float32) for c in cfg.cams]
+    g, t, nsec = cfg.init, 3, 3
+    knn = O.camera_knn(cfg.cams, g, nsec)
+    o = O.opts(lambda_ssim=0.2, trust_sh=1e30)
+    res = O.sweep(g, cfg.cams, tg, t, knn, o)
+    bad = np.zeros(g.n, bool)
+    for v in [t] + list(knn[t]):
+        bad |= near_threshold_kernels(O.render(g, cfg.cams[v], o, g32=g), g.n)
+    sens = step_sensitivity(g, cfg.cams[t], res["opts"], res["summed"], 4)
+    dg = gsn.DeviceGaussians.from_host(g)
+    K = (g.sh_degree + 1) ** 2
+    groups = list(STEP_GROUPS.items()) + [("colour", slice(11, 11 + 3 * K))]
+    vis = res["dec"][:, 0] != -2
+    errs = {}
+    for form, prec, rprec in (("plain", 0, 0), ("mixed", 1, 0), ("fp32colour", 1, 1)):
+        tr = LocalNewtonTrainer(dg, cfg.cams, [torch.tensor(x, device=ctx.device) for x in tg], nsec, 0.2,
+                                solve_kw={"trust_sh": 1e30, "precision": prec})
+        tr.ro = gsn.render_opts(precision=rprec)
+        tr.accumulate(t)
+        tr.ctx.local_newton_solve(tr.g, tr.ccams[t], tr.blocks, tr.solve_opts(t), tr.steps)
+        st, fl = (x.cpu().numpy() for x in tr.steps.view())
+        tr.close()
+        agree = np.all(fl[:4].T == res["dec"][:, :4], axis=1)
+        errs[f"{form}_agree"] = float(agree[vis].mean())
+        keep = agree & vis & ~bad
+        for i, (name, sl) in enumerate(groups):
+            ok = keep & (sens[:, i] <= 1e-5)
+            errs[f"{form}_{name}"] = rel_inf(st[sl].T[ok], res["steps"][ok, sl])
+    print("\n[sweep steps] " + " ".join(f"{k}={v:.2e}" for k, v in errs.items()), flush=True)
+    for form in ("mixed", "fp32colour"):
+        assert errs[f"{form}_agree"] > 0.99
+    for name, _ in groups:
+        assert errs[f"mixed_{name}"] < MIXED_STEP_TOL, (name, errs[f"mixed_{name}"])
+        assert errs[f"fp32colour_{name}"] < FP32_COLOUR_STEP_TOL, (name, errs[f"fp32colour_{name}"])

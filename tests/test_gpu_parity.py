@@ -17,11 +17,9 @@ import pytest
 from oracle import oracle as O
 from synth.scenes import make_config
 from tests.parity import (BLOCK_GROUPS, STEP_GROUPS, TOL_GRAD, TOL_IMAGE, TOL_STEP, blocks_gpu_to_oracle_view,
-                          compare_binning, gpu_view, kernels_in_reach, near_threshold_kernels, oracle_frames,
-                          oracle_view, pixel_mask, ssim_reach,
-                          summed_to_gpu_blocks,
-                          rel_inf, step_sensitivity,
-                          zstats_gpu_to_full, zstats_to_frame)
+                          compare_binning, gpu_view, near_threshold_kernels, oracle_frames, oracle_view,
+                          summed_to_gpu_blocks, rel_inf,
+                          step_sensitivity, view_errors, zstats_gpu_to_full, zstats_to_frame)
 
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
@@ -53,41 +51,10 @@ def _check_view(gsn, ctx, g, cam, tgt, lam, label, gn=False):
     gv = gpu_view(ctx, gsn, dg, cam, torch.tensor(tgt, device=ctx.device), lam, blocks, 0, gn=gn)
     ov = oracle_view(g, cam, tgt, lam, gn=gn)
     ntiles = compare_binning(gv, ov, g.n)
-    mask = pixel_mask(ov)
-    errs = {"tiles": ntiles, "pairs": gv["pairs"], "ambiguous_px": int((~mask).sum())}
-    fr = ov["fr"]
-    errs["img"] = rel_inf(gv["img"][:, mask], fr.img[:, mask])
-    errs["T"] = rel_inf(gv["T"][mask], fr.Tfinal[mask])
-    errs["ncontrib_mismatch"] = int((gv["ncontrib"][mask] != fr.ncontrib[mask]).sum())
-    errs["loss_L2"] = abs(gv["loss"][0] - ov["parts"][0]) / abs(ov["parts"][0])
-    errs["loss_S"] = abs(gv["loss"][1] - ov["parts"][1]) / abs(ov["parts"][1])
-    # loss maps beyond the SSIM reach of the ambiguous pixels (their windows carry an ambiguous
-    # pixel's legitimate difference into the neighbours' derivatives)
-    reach = ssim_reach(mask)
-    errs["dL"] = rel_inf(gv["dL"][:, ~reach], ov["dL"][:, ~reach])
-    errs["h"] = rel_inf(gv["h"][:, ~reach], ov["hd"][:, ~reach])
-    # kernels composited at an ambiguous pixel or within its reach are excluded from the
-    # per-kernel comparisons
-    bad = near_threshold_kernels(fr, g.n) | kernels_in_reach(fr, reach, g.n)
-    errs["excluded_kernels"] = int(bad.sum())
-    keep = ~bad
-    gz, Hz, wz = zstats_gpu_to_full(gv["z"])
-    # the oracle's statistics in each kernel's principal frame, taken from the oracle's own projection
-    fc, fs = oracle_frames(g, cam)
-    Zo = zstats_to_frame(ov["z"], fc, fs)
-    errs["z_g"] = rel_inf(gz[keep], Zo[keep, :9])
-    # the library keeps the (pi, Q, c~) block and the sigma-sigma entry: the sigma cross terms
-    # are not needed by any attribute group (no attribute moves both sigma and pi, Q or c~)
-    used = np.zeros((9, 9), bool)
-    used[:5, :5] = used[:5, 6:] = used[6:, :5] = True
-    used[5, 5] = True
-    used[[6, 7, 8], [6, 7, 8]] = True
-    errs["z_H"] = rel_inf(Hz[keep][:, used], Zo[keep, 9:90].reshape(-1, 9, 9)[:, used])
-    errs["z_w"] = rel_inf(wz[keep], Zo[keep, 90])
     blk = blocks.view().cpu().numpy()
-    Bg = blocks_gpu_to_oracle_view(blk, 0)
-    for name, sl in BLOCK_GROUPS.items():
-        errs[name] = rel_inf(Bg[keep][:, sl], ov["blocks"][keep][:, sl])
+    errs, keep = view_errors(g, cam, gv, ov, blk)
+    errs = {"tiles": ntiles, "pairs": gv["pairs"], **errs}
+    fr = ov["fr"]
     _report(label, errs)
     dump = os.environ.get("GSN_DUMP_DIR")
     if dump:
