@@ -241,6 +241,27 @@ gsn_status gsn_accumulate_hessian(gsn_ctx* ctx, const gsn_gaussians* g, const gs
                                   const float* d_target, const gsn_loss_opts* opts,
                                   int32_t view_slot, gsn_blocks* blocks, double* d_loss_out);
 
+/* The views of one sweep (Sec. 4.3: the primary target and its secondary targets) rendered and
+ * accumulated together: for i = 0..n_views-1, gsn_render of cams[i] into frames[i] followed by
+ * gsn_accumulate_hessian of d_targets[i] into slot first_slot + i, with results identical bit
+ * for bit to those calls made one after another.  The views' work is spread over four streams of
+ * the library's own (default priority), forked from the context's stream and joined back into it
+ * before the call returns, so that a view's projection, sort, rasters and loss maps overlap the
+ * others'; each view's additions into the rows summed over the views wait for the previous
+ * view's, and a secondary slot's per-kernel sums wait for the primary's coverage row when slot 0
+ * is among the views.  With the profiler on (gsn_profile_enable) the views run one after another
+ * on the context's stream.  The frames must be distinct; reserved frames (gsn_frame_reserve)
+ * keep the call free of host waits and let it be captured (gsn_capture_begin).
+ * cams [n_views], frames [n_views], d_targets [n_views] (device [3][H][W] each, at each camera's
+ * size) are caller-owned; d_loss_out (device double [n_views][2], may be NULL) receives (L2, L_S)
+ * per view.  Errors: those of gsn_render and gsn_accumulate_hessian (the views before the
+ * failing one have been issued), GSN_E_SHAPE (n_views < 1 or above 9, slots outside the blocks'
+ * 0..n_views-1), GSN_E_INVALID (null arrays or entries, a frame given twice), GSN_E_HIP. */
+gsn_status gsn_accumulate_views(gsn_ctx* ctx, const gsn_gaussians* g, int32_t n_views, int32_t first_slot,
+                                const gsn_camera* cams, gsn_frame* const* frames,
+                                const float* const* d_targets, const gsn_render_opts* ropts,
+                                const gsn_loss_opts* lopts, gsn_blocks* blocks, double* d_loss_out);
+
 /* Solves every kernel's local Newton systems (eq. local_newton) in the
  * paper's reduced coordinates relative to the primary camera: position in
  * the plane normal to the view direction r_k, rotation angle about r_k,

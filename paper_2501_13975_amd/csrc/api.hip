@@ -131,6 +131,20 @@ gsn_status check_camera(gsn_ctx* ctx, const gsn_camera* c) {
 
 extern "C" {
 
+// The streams and events of gsn_accumulate_views (those created so far).
+static void destroy_side(gsn_ctx* c) {
+    for (int i = 0; i < gsn_ctx::kSide; ++i) {
+        if (c->side[i]) {
+            (void)hipStreamSynchronize(c->side[i]);
+            (void)hipStreamDestroy(c->side[i]);
+        }
+        if (c->ev_join[i]) (void)hipEventDestroy(c->ev_join[i]);
+    }
+    for (int i = 0; i < gsn_ctx::kMaxViews; ++i)
+        if (c->ev_chain[i]) (void)hipEventDestroy(c->ev_chain[i]);
+    if (c->ev_fork) (void)hipEventDestroy(c->ev_fork);
+}
+
 gsn_status gsn_create(gsn_ctx** out, int32_t device, void* hip_stream) {
     if (!out) return GSN_E_INVALID;
     *out = nullptr;
@@ -147,6 +161,14 @@ gsn_status gsn_create(gsn_ctx** out, int32_t device, void* hip_stream) {
     hipError_t e = hipGetDevice(&cur);
     if (e == hipSuccess) e = hipSetDevice(device);
     if (e == hipSuccess) e = hipMalloc((void**)&c->d_stats, GSN_STAT_N * sizeof(unsigned long long));
+    // default-priority, non-blocking streams for gsn_accumulate_views, and their events
+    for (int i = 0; i < gsn_ctx::kSide && e == hipSuccess; ++i) {
+        e = hipStreamCreateWithFlags(&c->side[i], hipStreamNonBlocking);
+        if (e == hipSuccess) e = hipEventCreateWithFlags(&c->ev_join[i], hipEventDisableTiming);
+    }
+    for (int i = 0; i < gsn_ctx::kMaxViews && e == hipSuccess; ++i)
+        e = hipEventCreateWithFlags(&c->ev_chain[i], hipEventDisableTiming);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming);
     if (e == hipSuccess) {
         launch_fill_u32(reinterpret_cast<uint32_t*>(c->d_stats), 0u, 2 * GSN_STAT_N, c->stream);
         e = hipStreamSynchronize(c->stream);
@@ -154,6 +176,7 @@ gsn_status gsn_create(gsn_ctx** out, int32_t device, void* hip_stream) {
     (void)hipSetDevice(cur);
     if (e != hipSuccess) {
         if (c->d_stats) (void)hipFree(c->d_stats);
+        destroy_side(c);
         delete c;
         return e == hipErrorOutOfMemory ? GSN_E_NOMEM : GSN_E_HIP;
     }
@@ -173,6 +196,7 @@ gsn_status gsn_destroy(gsn_ctx* ctx) {
     if (ctx->d_counts) (void)hipFree(ctx->d_counts);
     if (ctx->d_stats) (void)hipFree(ctx->d_stats);
     if (ctx->cap_stream) (void)hipStreamDestroy(ctx->cap_stream);
+    destroy_side(ctx);
     buf_free(ctx->mlp_part);
     buf_free(ctx->mlp_stat);
     buf_free(ctx->label_part);
@@ -463,8 +487,12 @@ gsn_status gsn_render(gsn_ctx* ctx, const gsn_gaussians* g, const gsn_camera* ca
     return GSN_OK;
 }
 
-gsn_status gsn_accumulate_hessian(gsn_ctx* ctx, const gsn_gaussians* g, const gsn_frame* fc, const float* d_target,
-                                  const gsn_loss_opts* opts, int32_t view_slot, gsn_blocks* b, double* d_loss_out) {
+// gsn_accumulate_hessian on the context's current stream.  When not null, wait_reduce is waited for
+// before the view's per-kernel sums (a secondary slot reads the primary coverage row), wait_chain
+// before its additions into the blocks, and done_chain is recorded after them.
+static gsn_status accumulate_impl(gsn_ctx* ctx, const gsn_gaussians* g, const gsn_frame* fc, const float* d_target,
+                                  const gsn_loss_opts* opts, int32_t view_slot, gsn_blocks* b, double* d_loss_out,
+                                  hipEvent_t wait_reduce, hipEvent_t wait_chain, hipEvent_t done_chain) {
     if (!ctx || !fc || !opts || !b || !d_target) return fail(ctx, GSN_E_INVALID, "null argument");
     gsn_frame* f = const_cast<gsn_frame*>(fc);
     gsn_status st = check_gaussians(ctx, g);
@@ -506,10 +534,71 @@ gsn_status gsn_accumulate_hessian(gsn_ctx* ctx, const gsn_gaussians* g, const gs
     }
     {
         StageTimer st_(ctx, GSN_STAGE_CHAIN);
-        launch_reduce_chain(*f, *g, opts->weight, view_slot, opts->gauss_newton != 0, opts->precision == 1, *b, zs, s);
+        if (wait_reduce) HIP_TRY(ctx, hipStreamWaitEvent(s, wait_reduce, 0));
+        launch_reduce_pairs(*f, *g, view_slot, opts->precision == 1, *b, s);
+        if (wait_chain && wait_chain != wait_reduce) HIP_TRY(ctx, hipStreamWaitEvent(s, wait_chain, 0));
+        launch_chain(*f, *g, opts->weight, view_slot, opts->gauss_newton != 0, opts->precision == 1, *b, zs, s);
+        if (done_chain) HIP_TRY(ctx, hipEventRecord(done_chain, s));
     }
     HIP_TRY(ctx, hipGetLastError());
     return GSN_OK;
+}
+
+gsn_status gsn_accumulate_hessian(gsn_ctx* ctx, const gsn_gaussians* g, const gsn_frame* fc, const float* d_target,
+                                  const gsn_loss_opts* opts, int32_t view_slot, gsn_blocks* b, double* d_loss_out) {
+    return accumulate_impl(ctx, g, fc, d_target, opts, view_slot, b, d_loss_out, nullptr, nullptr, nullptr);
+}
+
+gsn_status gsn_accumulate_views(gsn_ctx* ctx, const gsn_gaussians* g, int32_t n_views, int32_t first_slot,
+                                const gsn_camera* cams, gsn_frame* const* frames, const float* const* d_targets,
+                                const gsn_render_opts* ro, const gsn_loss_opts* lo, gsn_blocks* b,
+                                double* d_loss_out) {
+    if (!ctx || !cams || !frames || !d_targets || !ro || !lo || !b) return fail(ctx, GSN_E_INVALID, "null argument");
+    if (n_views < 1 || first_slot < 0 || first_slot + n_views > b->n_views || n_views > gsn_ctx::kMaxViews)
+        return fail(ctx, GSN_E_SHAPE, "views %d..%d outside the blocks' slots 0..%d", first_slot,
+                    first_slot + n_views - 1, b->n_views - 1);
+    for (int i = 0; i < n_views; ++i) {
+        if (!frames[i] || !d_targets[i]) return fail(ctx, GSN_E_INVALID, "view %d: null frame or target", i);
+        for (int j = 0; j < i; ++j)
+            if (frames[j] == frames[i]) return fail(ctx, GSN_E_INVALID, "views %d and %d share a frame", j, i);
+        gsn_status r = check_camera(ctx, &cams[i]);
+        if (r != GSN_OK) return r;
+    }
+    HIP_TRY(ctx, hipSetDevice(ctx->device));
+    double* loss = d_loss_out;
+    if (ctx->prof || n_views == 1) {  // one stream: the stage timers bracket each stage alone
+        for (int i = 0; i < n_views; ++i) {
+            gsn_status r = gsn_render(ctx, g, &cams[i], ro, frames[i], nullptr, nullptr);
+            if (r == GSN_OK)
+                r = accumulate_impl(ctx, g, frames[i], d_targets[i], lo, first_slot + i, b, loss ? loss + 2 * i : nullptr,
+                                    nullptr, nullptr, nullptr);
+            if (r != GSN_OK) return r;
+        }
+        return GSN_OK;
+    }
+    hipStream_t home = ctx->stream;
+    const int used = std::min(n_views, gsn_ctx::kSide);
+    HIP_TRY(ctx, hipEventRecord(ctx->ev_fork, home));
+    for (int k = 0; k < used; ++k) HIP_TRY(ctx, hipStreamWaitEvent(ctx->side[k], ctx->ev_fork, 0));
+    gsn_status r = GSN_OK;
+    for (int i = 0; i < n_views && r == GSN_OK; ++i) {
+        ctx->stream = ctx->side[i % gsn_ctx::kSide];
+        r = gsn_render(ctx, g, &cams[i], ro, frames[i], nullptr, nullptr);
+        // the primary's sums and additions come first; each later view adds after the one before it
+        hipEvent_t wait_reduce = (first_slot == 0 && i > 0) ? ctx->ev_chain[0] : nullptr;
+        hipEvent_t wait_chain = i > 0 ? ctx->ev_chain[i - 1] : nullptr;
+        if (r == GSN_OK)
+            r = accumulate_impl(ctx, g, frames[i], d_targets[i], lo, first_slot + i, b, loss ? loss + 2 * i : nullptr,
+                                wait_reduce, wait_chain, ctx->ev_chain[i]);
+    }
+    // join every stream that took work, also after a failure, so that later calls stay ordered
+    ctx->stream = home;
+    for (int k = 0; k < used; ++k) {
+        const hipError_t e1 = hipEventRecord(ctx->ev_join[k], ctx->side[k]);
+        const hipError_t e2 = e1 == hipSuccess ? hipStreamWaitEvent(home, ctx->ev_join[k], 0) : e1;
+        if (e2 != hipSuccess && r == GSN_OK) r = fail(ctx, GSN_E_HIP, "joining the view streams: %s", hipGetErrorString(e2));
+    }
+    return r;
 }
 
 // Argument checks shared by both solve entry points.

@@ -685,14 +685,19 @@ void launch_raster_bwd(const gsn_frame& f, const float* dL, const float* hd, boo
         bp<uint8_t>(f.kflag), counts);
 }
 
-void launch_reduce_chain(const gsn_frame& f, const gsn_gaussians& g, float weight, int slot, bool gauss_newton,
-                         bool fp32, const gsn_blocks& b, float* zstats_out, hipStream_t s) {
+void launch_reduce_pairs(const gsn_frame& f, const gsn_gaussians& g, int slot, bool fp32, const gsn_blocks& b,
+                         hipStream_t s) {
     if (g.n == 0) return;
-    const int K = (g.sh_degree + 1) * (g.sh_degree + 1);
     auto red_k = fp32 ? reduce_pairs_kernel<float> : reduce_pairs_kernel<double>;
     red_k<<<(g.n + 255) / 256, 256, 0, s>>>(g.n, bp<uint2>(f.rect), bp<uint32_t>(f.pair_off), bp<float>(f.partial),
                                             bp<uint8_t>(f.flags), bp<uint8_t>(f.kflag),
                                             slot > 0 ? b.d_data + (size_t)29 * g.n : nullptr, bp<double>(f.zsum));
+}
+
+void launch_chain(const gsn_frame& f, const gsn_gaussians& g, float weight, int slot, bool gauss_newton, bool fp32,
+                  const gsn_blocks& b, float* zstats_out, hipStream_t s) {
+    if (g.n == 0) return;
+    const int K = (g.sh_degree + 1) * (g.sh_degree + 1);
     auto pos_k = gauss_newton ? chain_pos_kernel<true> : chain_pos_kernel<false>;
     auto rs_k = gauss_newton ? (fp32 ? chain_rs_kernel<true, float> : chain_rs_kernel<true, double>)
                              : (fp32 ? chain_rs_kernel<false, float> : chain_rs_kernel<false, double>);

@@ -104,6 +104,11 @@ struct gsn_ctx {
     // the library's own stream, in place of the caller's
     bool capturing = false, capture_failed = false;
     hipStream_t cap_stream = nullptr, user_stream = nullptr;
+    // gsn_accumulate_views: the library's own streams the views are spread over (forked from and
+    // joined back into the context's stream), and the events that order them
+    static constexpr int kSide = 4, kMaxViews = 9;
+    hipStream_t side[kSide] = {};
+    hipEvent_t ev_fork = nullptr, ev_join[kSide] = {}, ev_chain[kMaxViews] = {};
 };
 
 struct gsn_graph {
@@ -178,8 +183,12 @@ void launch_loss_reduce(const double* part, int nparts, int W, int H, double* ou
 // ---- launchers (backward.hip)
 void launch_raster_bwd(const gsn_frame& f, const float* dL, const float* hd, bool gauss_newton,
                        unsigned long long* counts, hipStream_t s);
-void launch_reduce_chain(const gsn_frame& f, const gsn_gaussians& g, float weight, int slot, bool gauss_newton,
-                         bool fp32, const gsn_blocks& b, float* zstats_out, hipStream_t s);
+// per-kernel sums of a view's (tile, kernel) partials (a secondary slot reads the primary coverage row)
+void launch_reduce_pairs(const gsn_frame& f, const gsn_gaussians& g, int slot, bool fp32, const gsn_blocks& b,
+                         hipStream_t s);
+// the chain rule from those sums into the blocks (adds to the rows summed over the views)
+void launch_chain(const gsn_frame& f, const gsn_gaussians& g, float weight, int slot, bool gauss_newton, bool fp32,
+                  const gsn_blocks& b, float* zstats_out, hipStream_t s);
 
 // ---- launchers (solve.hip)
 // nonfinite: device counter of kernels skipped for non-finite blocks or steps (always counted);

@@ -44,6 +44,7 @@ def lib():
             "gsn_frame_create": [P, ctypes.POINTER(P)], "gsn_frame_destroy": [P, P],
             "gsn_render": [P, P, P, P, P, P, P],
             "gsn_accumulate_hessian": [P, P, P, P, P, ctypes.c_int32, P, P],
+            "gsn_accumulate_views": [P, P, ctypes.c_int32, ctypes.c_int32, P, P, P, P, P, P, P],
             "gsn_local_newton_solve": [P, P, P, P, P, P],
             "gsn_local_newton_solve_noalloc": [P, P, P, P, P, P],
             "gsn_apply_step": [P, P, P, P, P, ctypes.c_uint32],
@@ -294,6 +295,24 @@ class Context:
         self._check(lib().gsn_accumulate_hessian(self.h, ctypes.byref(cg), frame.h, _ptr(target),
                                                  ctypes.byref(lo), int(view_slot), ctypes.byref(cb),
                                                  _ptr(loss_out)))
+
+    def accumulate_views(self, g, cams, frames, targets, ro: CRenderOpts, lo: CLossOpts, blocks: "Blocks",
+                         loss_out=None, first_slot=0):
+        """Render + accumulate of several views (view i into slot first_slot + i) with their work
+        overlapped on the library's streams; loss_out: float64 [n_views][2] on the device, or None."""
+        n = len(cams)
+        if not (len(frames) == len(targets) == n):
+            raise ValueError("cams, frames and targets differ in length")
+        if loss_out is not None and (loss_out.dtype != torch.float64 or not loss_out.is_contiguous()
+                                     or loss_out.numel() < 2 * n):
+            raise ValueError("loss_out must be a contiguous float64 tensor of at least [n_views][2]")
+        cg, cb = g.c(), blocks.c()
+        ccams = (CCamera * n)(*cams)
+        hfr = (ctypes.c_void_p * n)(*[f.h.value for f in frames])
+        htg = (ctypes.c_void_p * n)(*[t.data_ptr() for t in targets])
+        self._check(lib().gsn_accumulate_views(self.h, ctypes.byref(cg), n, int(first_slot), ccams, hfr, htg,
+                                               ctypes.byref(ro), ctypes.byref(lo), ctypes.byref(cb),
+                                               _ptr(loss_out)))
 
     def local_newton_solve(self, g, primary: CCamera, blocks: "Blocks", so: CSolveOpts, steps: "Steps"):
         cg, cb, cs = g.c(), blocks.c(), steps.c()

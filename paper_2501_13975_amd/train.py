@@ -116,13 +116,10 @@ class LocalNewtonTrainer:
     def accumulate(self, t):
         """Primary and secondary renders and block accumulation for training image t."""
         self.ctx.blocks_zero(self.blocks)
-        views = [(self.ccams[t], self.targets[t])]
-        for j in self.knn[t]:
-            views.append((self.chalf[j], self.half_targets[j]))
-        for slot, (cam, tgt) in enumerate(views):
-            fr = self.frames[slot]
-            self.ctx.render(self.g, cam, self.ro, fr)
-            self.ctx.accumulate_hessian(self.g, fr, tgt, self.lo, slot, self.blocks, self.loss[slot])
+        cams = [self.ccams[t]] + [self.chalf[j] for j in self.knn[t]]
+        tgts = [self.targets[t]] + [self.half_targets[j] for j in self.knn[t]]
+        self.ctx.accumulate_views(self.g, cams, self.frames[:len(cams)], tgts, self.ro, self.lo, self.blocks,
+                                  self.loss)
 
     def sweep(self, t, group_mask=31):
         """Jacobi schedule: every group linearised at the same state, one render and
@@ -161,10 +158,10 @@ class LocalNewtonTrainer:
         self.ctx.accumulate_hessian(self.g, fr, self.targets[t], self.lo, 0, self.blocks, self.loss[0])
 
     def _accumulate_secondaries(self, t):
-        for slot, j in enumerate(self.knn[t], start=1):
-            fr = self.frames[slot]
-            self.ctx.render(self.g, self.chalf[j], self.ro, fr)
-            self.ctx.accumulate_hessian(self.g, fr, self.half_targets[j], self.lo, slot, self.blocks, self.loss[slot])
+        if len(self.knn[t]):
+            self.ctx.accumulate_views(self.g, [self.chalf[j] for j in self.knn[t]], self.frames[1:1 + len(self.knn[t])],
+                                      [self.half_targets[j] for j in self.knn[t]], self.ro, self.lo, self.blocks,
+                                      self.loss[1:], first_slot=1)
 
     def _learned_buffers(self):
         n = self.g.n

@@ -199,6 +199,10 @@ def test_sweep_steps_parity(gsn, ctx, lam, nsec, gn):
                             sens=sens)
     _report(f"sweep-steps lam={lam} |N_t|={nsec} gn={gn}", errs)
     assert errs["decision_agreement"] > 0.99 and errs["solver_decisions"] > 0.999
+    # kernels composited at a pixel whose threshold decision is ambiguous are left out of the end-to-end
+    # comparison (17% of the visible ones in this scene with three secondaries; none without): a ceiling
+    # keeps that share from growing unnoticed
+    assert errs["excluded_near_threshold"] <= 0.2 * errs["visible"], errs["excluded_near_threshold"]
     assert errs["overlap_row"] < TOL_GRAD
     for name, _ in groups:
         assert errs["solver_" + name] < 1e-5, ("solver", name, errs["solver_" + name])
