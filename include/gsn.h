@@ -254,8 +254,8 @@ gsn_status gsn_accumulate_hessian(gsn_ctx* ctx, const gsn_gaussians* g, const gs
  * keep the call free of host waits and let it be captured (gsn_capture_begin).
  * cams [n_views], frames [n_views], d_targets [n_views] (device [3][H][W] each, at each camera's
  * size) are caller-owned; d_loss_out (device double [n_views][2], may be NULL) receives (L2, L_S)
- * per view.  Errors: those of gsn_render and gsn_accumulate_hessian (the views before the
- * failing one have been issued), GSN_E_SHAPE (n_views < 1 or above 9, slots outside the blocks'
+ * per view.  Errors: those of gsn_render and gsn_accumulate_hessian (part of the other views'
+ * work may have been issued; the blocks are then incomplete), GSN_E_SHAPE (n_views < 1 or above 9, slots outside the blocks'
  * 0..n_views-1), GSN_E_INVALID (null arrays or entries, a frame given twice), GSN_E_HIP. */
 gsn_status gsn_accumulate_views(gsn_ctx* ctx, const gsn_gaussians* g, int32_t n_views, int32_t first_slot,
                                 const gsn_camera* cams, gsn_frame* const* frames,

@@ -298,9 +298,10 @@ gsn_status gsn_frame_destroy(gsn_ctx* ctx, gsn_frame* f) {
     (void)hipSetDevice(ctx->device);
     (void)hipStreamSynchronize(ctx->stream);
     DevBuf* all[] = {&f->rec, &f->rect, &f->depth_key, &f->ntiles, &f->ids_a, &f->ids_b, &f->keys_a, &f->keys_b,
-                     &f->offsets, &f->pair_off, &f->pk_a, &f->pv_a, &f->pk_b, &f->pv_b, &f->partial, &f->flags, &f->kflag,
+                     &f->offsets, &f->pair_off, &f->nsup, &f->moffs, &f->pk_a, &f->pv_a, &f->pk_b, &f->pv_b, &f->sranges,
+                     &f->seg_base, &f->seg_counts, &f->seg_offs, &f->partial, &f->flags, &f->kflag,
                      &f->ranges, &f->img, &f->img64, &f->Tfin, &f->ncontrib, &f->dL, &f->hd, &f->coef, &f->zsum, &f->zstats,
-                     &f->loss_part, &f->hist, &f->scan_tmp, &f->total, &f->masks, &f->chunk_first, &f->tile_order, &f->tile_len, &f->bwd_order};
+                     &f->loss_part, &f->hist, &f->scan_tmp, &f->total, &f->masks, &f->tile_order, &f->tile_len, &f->bwd_order};
     for (DevBuf* b : all) buf_free(*b);
     if (f->h_total) (void)hipHostFree(f->h_total);
     delete f;
@@ -313,7 +314,8 @@ static hipError_t frame_buffers(gsn_frame* f, int n, int W, int H, size_t pairs)
     const size_t nn = (size_t)std::max(n, 1);
     const size_t npx = (size_t)W * H;
     const size_t tiles = (size_t)((W + GSN_TILE - 1) / GSN_TILE) * ((H + GSN_TILE - 1) / GSN_TILE);
-    DevBuf* per_kernel4[] = {&f->depth_key, &f->ntiles, &f->ids_a, &f->ids_b, &f->keys_a, &f->keys_b, &f->pair_off};
+    DevBuf* per_kernel4[] = {&f->depth_key, &f->ntiles, &f->ids_a, &f->ids_b, &f->keys_a, &f->keys_b, &f->pair_off,
+                             &f->nsup, &f->moffs};
     hipError_t e = buf_reserve(f->rec, nn * 4 * sizeof(float4));
     if (e == hipSuccess) e = buf_reserve(f->rect, nn * sizeof(uint2));
     for (DevBuf* b : per_kernel4)
@@ -325,6 +327,10 @@ static hipError_t frame_buffers(gsn_frame* f, int n, int W, int H, size_t pairs)
     DevBuf* per_tile4[] = {&f->tile_order, &f->tile_len, &f->bwd_order};
     for (DevBuf* b : per_tile4)
         if (e == hipSuccess) e = buf_reserve(*b, tiles * 4);
+    const int tx = (W + GSN_TILE - 1) / GSN_TILE, ty = (H + GSN_TILE - 1) / GSN_TILE;
+    const size_t n_super = super_tiles(tx, ty);
+    if (e == hipSuccess) e = buf_reserve(f->sranges, n_super * sizeof(uint2));
+    if (e == hipSuccess) e = buf_reserve(f->seg_base, (n_super + 1) * 4);
     if (e == hipSuccess) e = buf_reserve(f->img, 3 * npx * 4);
     if (e == hipSuccess) e = buf_reserve(f->img64, 3 * npx * 8);
     if (e == hipSuccess) e = buf_reserve(f->Tfin, npx * 4);
@@ -334,19 +340,22 @@ static hipError_t frame_buffers(gsn_frame* f, int n, int W, int H, size_t pairs)
     if (e == hipSuccess) e = buf_reserve(f->hd, 3 * npx * 4);
     if (e == hipSuccess) e = buf_reserve(f->coef, 24 * npx * 4);
     if (e == hipSuccess) e = buf_reserve(f->loss_part, (size_t)2 * 3 * tiles * sizeof(double));
-    if (e == hipSuccess) e = buf_reserve(f->total, 16);
+    if (e == hipSuccess) e = buf_reserve(f->total, 32);
     const size_t pp = std::max<size_t>(pairs, 1);
     // the histogram size is not monotone in the key count (the tile grows past 4M keys): cover
     // every count up to nn
     const size_t hist = std::max({radix_hist_bytes((uint32_t)nn), radix_hist_bytes((uint32_t)std::min<size_t>(nn, 1u << 22)),
                                   radix_hist_bytes((uint32_t)pp), radix_hist_bytes((uint32_t)std::min<size_t>(pp, 1u << 22))});
     if (e == hipSuccess) e = buf_reserve(f->hist, hist);
-    if (e == hipSuccess) e = buf_reserve(f->scan_tmp, scan_tmp_bytes((uint32_t)nn));
+    if (e == hipSuccess) e = buf_reserve(f->scan_tmp, scan_tmp_bytes((uint32_t)std::max(nn, tiles)));
     if (pairs == 0 || e != hipSuccess) return e;
     DevBuf* per_pair4[] = {&f->pk_a, &f->pv_a, &f->pk_b, &f->pv_b};
     for (DevBuf* b : per_pair4)
         if (e == hipSuccess) e = buf_reserve(*b, pp * 4);
-    if (e == hipSuccess) e = buf_reserve(f->chunk_first, emit_chunks((uint32_t)pp) * 4 + 4);
+    const size_t words = segment_words(pp, tx, ty);
+    if (e == hipSuccess) e = buf_reserve(f->seg_counts, words * 4);
+    if (e == hipSuccess) e = buf_reserve(f->seg_offs, words * 4);
+    if (e == hipSuccess) e = buf_reserve(f->scan_tmp, scan_tmp_bytes((uint32_t)std::max({nn, tiles, words})));
     if (e == hipSuccess) e = buf_reserve(f->partial, pp * GSN_NZ * 4);
     if (e == hipSuccess) e = buf_reserve(f->flags, (pp + 3) / 4 * 4);
     return e;
@@ -458,21 +467,20 @@ gsn_status gsn_render(gsn_ctx* ctx, const gsn_gaussians* g, const gsn_camera* ca
         // depends only on this render, not on the loss)
         launch_fill_u32_dev(bp<uint32_t>(f->flags), 0u, d_pairs, 4, ((size_t)cap + 3) / 4, s);
         launch_fill_u32(bp<uint32_t>(f->kflag), 0u, (nn + 3) / 4, s);
-        launch_emit_pairs(bp<uint32_t>(f->ids_a), bp<uint32_t>(f->offsets), (uint32_t)n, d_pairs, cap,
-                          bp<uint2>(f->rect), (uint32_t)f->tiles_x, bp<uint32_t>(f->pk_a), bp<uint32_t>(f->pv_a),
-                          bp<uint32_t>(f->pair_off), bp<uint32_t>(f->chunk_first), bp<float4>(f->rec), s);
-        int tile_bits = 1;
-        while ((1ull << tile_bits) < tiles) ++tile_bits;
-        HIP_TRY(ctx, radix_sort_pairs(bp<uint32_t>(f->pk_a), bp<uint32_t>(f->pv_a), bp<uint32_t>(f->pk_b),
-                                      bp<uint32_t>(f->pv_b), cap, d_pairs, 0, tile_bits, f->hist, s));
-        launch_fill_u32(bp<uint32_t>(f->ranges), 0u, 2 * tiles, s);
-        launch_tile_ranges(bp<uint32_t>(f->pk_a), d_pairs, cap, bp<uint2>(f->ranges), s);
+        launch_pair_off(bp<uint32_t>(f->ids_a), bp<uint32_t>(f->offsets), (uint32_t)n, bp<uint32_t>(f->pair_off),
+                        bp<float4>(f->rec), s);
+        const TileListBufs tb{bp<uint32_t>(f->nsup),       bp<uint32_t>(f->moffs),    bp<uint32_t>(f->pk_a),
+                              bp<uint32_t>(f->pv_a),       bp<uint32_t>(f->pk_b),     bp<uint32_t>(f->pv_b),
+                              bp<uint2>(f->sranges),       bp<uint32_t>(f->seg_base), bp<uint32_t>(f->seg_counts),
+                              bp<uint32_t>(f->seg_offs),   bp<uint2>(f->ranges)};
+        HIP_TRY(ctx, build_tile_lists(bp<uint32_t>(f->ids_a), bp<uint2>(f->rect), (uint32_t)n, d_total, cap, f->tiles_x,
+                                      f->tiles_y, tb, f->hist, f->scan_tmp, &f->list_ids, s));
         launch_tile_order(bp<uint2>(f->ranges), nullptr, (int)tiles, bp<uint32_t>(f->tile_order), s);
     }
     {
         // 5. front-to-back compositing
         StageTimer st_(ctx, GSN_STAGE_RASTER_FWD);
-        launch_raster_fwd(bp<uint2>(f->ranges), bp<uint32_t>(f->tile_order), bp<uint32_t>(f->pv_a),
+        launch_raster_fwd(bp<uint2>(f->ranges), bp<uint32_t>(f->tile_order), f->list_ids,
                           bp<float4>(f->rec), (uint32_t)n, f->cam, f->ro, f->fp32, bp<float>(f->img), bp<double>(f->img64),
                           bp<float>(f->Tfin), bp<uint32_t>(f->ncontrib), bp<uint64_t>(f->masks),
                           bp<uint32_t>(f->tile_len), prof_counts(ctx), s);
@@ -581,15 +589,18 @@ gsn_status gsn_accumulate_views(gsn_ctx* ctx, const gsn_gaussians* g, int32_t n_
     HIP_TRY(ctx, hipEventRecord(ctx->ev_fork, home));
     for (int k = 0; k < used; ++k) HIP_TRY(ctx, hipStreamWaitEvent(ctx->side[k], ctx->ev_fork, 0));
     gsn_status r = GSN_OK;
+    // every view's render is issued before any accumulation, so that every stream has work early
     for (int i = 0; i < n_views && r == GSN_OK; ++i) {
         ctx->stream = ctx->side[i % gsn_ctx::kSide];
         r = gsn_render(ctx, g, &cams[i], ro, frames[i], nullptr, nullptr);
+    }
+    for (int i = 0; i < n_views && r == GSN_OK; ++i) {
+        ctx->stream = ctx->side[i % gsn_ctx::kSide];
         // the primary's sums and additions come first; each later view adds after the one before it
         hipEvent_t wait_reduce = (first_slot == 0 && i > 0) ? ctx->ev_chain[0] : nullptr;
         hipEvent_t wait_chain = i > 0 ? ctx->ev_chain[i - 1] : nullptr;
-        if (r == GSN_OK)
-            r = accumulate_impl(ctx, g, frames[i], d_targets[i], lo, first_slot + i, b, loss ? loss + 2 * i : nullptr,
-                                wait_reduce, wait_chain, ctx->ev_chain[i]);
+        r = accumulate_impl(ctx, g, frames[i], d_targets[i], lo, first_slot + i, b, loss ? loss + 2 * i : nullptr,
+                            wait_reduce, wait_chain, ctx->ev_chain[i]);
     }
     // join every stream that took work, also after a failure, so that later calls stay ordered
     ctx->stream = home;
@@ -1172,7 +1183,7 @@ gsn_status gsn_frame_lists(gsn_ctx* ctx, const gsn_frame* f, uint32_t* d_ranges,
         gsn_status r = frame_pairs(ctx, f, &pairs);
         if (r != GSN_OK) return r;
     }
-    if (d_ids && pairs) HIP_TRY(ctx, hipMemcpyAsync(d_ids, f->pv_a.p, (size_t)pairs * 4, hipMemcpyDeviceToDevice, s));
+    if (d_ids && pairs) HIP_TRY(ctx, hipMemcpyAsync(d_ids, f->list_ids, (size_t)pairs * 4, hipMemcpyDeviceToDevice, s));
     if (d_ncontrib) HIP_TRY(ctx, hipMemcpyAsync(d_ncontrib, f->ncontrib.p, npx * 4, hipMemcpyDeviceToDevice, s));
     if ((d_depth_bits || d_rect) && f->n > 0) {
         // depth keys were sorted in place; recompute the per-kernel view from the rect/keys copies

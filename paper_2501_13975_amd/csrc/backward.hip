@@ -679,7 +679,7 @@ void launch_raster_bwd(const gsn_frame& f, const float* dL, const float* hd, boo
     auto kern = gauss_newton ? (f.fp32 ? raster_bwd_kernel<true, float> : raster_bwd_kernel<true, double>)
                              : (f.fp32 ? raster_bwd_kernel<false, float> : raster_bwd_kernel<false, double>);
     kern<<<tiles, GSN_BLOCK, 0, s>>>(
-        bp<uint2>(f.ranges), bp<uint32_t>(f.bwd_order), bp<uint32_t>(f.pv_a), bp<float4>(f.rec),
+        bp<uint2>(f.ranges), bp<uint32_t>(f.bwd_order), f.list_ids, bp<float4>(f.rec),
         (uint32_t)f.n, f.cam, f.ro, f.fp32 ? nullptr : bp<double>(f.img64), bp<float>(f.img),
         bp<uint32_t>(f.ncontrib), bp<uint64_t>(f.masks), dL, hd, bp<float>(f.partial), bp<uint8_t>(f.flags),
         bp<uint8_t>(f.kflag), counts);

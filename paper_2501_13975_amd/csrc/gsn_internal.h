@@ -47,9 +47,15 @@ struct gsn_frame {
     DevBuf ids_a, ids_b, keys_a, keys_b;  // u32 [n] sort ping-pong
     DevBuf offsets;     // u32 [n + 1] pair offset by depth rank
     DevBuf pair_off;    // u32 [n] pair offset by kernel id
-    DevBuf chunk_first; // u32 [pairs / 2048 + 1] depth rank owning the first slot of each emission chunk
-    // per pair
-    DevBuf pk_a, pv_a, pk_b, pv_b;  // u32 [pairs] (tile, id) ping-pong
+    DevBuf nsup, moffs; // u32 [n] super-tile memberships by depth rank, and their offsets
+    // per pair: the super-tile memberships (key, id) and their sort buffers; the tile lists are
+    // written into the values buffer the sorted memberships do not occupy (list_ids)
+    DevBuf pk_a, pv_a, pk_b, pv_b;
+    uint32_t* list_ids = nullptr;  // u32 [pairs]: kernel ids of the tile lists, ranges index it
+    // per super-tile / segment
+    DevBuf sranges;     // uint2 [super-tiles]: member range
+    DevBuf seg_base;    // u32 [super-tiles + 1]: first segment
+    DevBuf seg_counts, seg_offs;  // u32 [segments x 64]: entries per (segment, tile), and their places in the lists
     DevBuf partial;     // float [pairs][GSN_NZ]
     DevBuf flags;       // u8 [pairs], partial written
     DevBuf kflag;       // u8 [n], some partial of the kernel written
@@ -70,7 +76,8 @@ struct gsn_frame {
     DevBuf zsum;        // double [n][GSN_NZ] per-kernel sums of the pair partials
     DevBuf zstats;      // float [GSN_NZ][n], optional debug copy
     DevBuf loss_part;   // double [2][nblocks]
-    // sort / scan scratch; total: u32 [0] scanned pair total, [1] live pair count of the render
+    // sort / scan scratch; total: u32 [0] scanned pair total, [1] live pair count of the render,
+    // [2] scanned membership total, [3] live membership count, [4] scanned tile-list total
     DevBuf hist, scan_tmp, total;
     uint32_t* h_total = nullptr;  // pinned host word
 };
@@ -142,8 +149,10 @@ void launch_preprocess(const gsn_gaussians& g, const DevCam& cam, const DevRende
 // stable LSD radix sort of (key, val) pairs on bits [bit_lo, bit_hi); result lands in (k0, v0).  The
 // launches are sized for n keys; with d_n, only the first min(*d_n, n) keys (read on the device) are
 // sorted.  hist must hold radix_hist_bytes(n) bytes.
+// With k_res and v_res the result is left where the passes put it and returned there (no copy back).
 hipError_t radix_sort_pairs(uint32_t* k0, uint32_t* v0, uint32_t* k1, uint32_t* v1, uint32_t n, const uint32_t* d_n,
-                            int bit_lo, int bit_hi, DevBuf& hist, hipStream_t s);
+                            int bit_lo, int bit_hi, DevBuf& hist, hipStream_t s, uint32_t** k_res = nullptr,
+                            uint32_t** v_res = nullptr);
 void launch_copy_u32(uint32_t* dst, const uint32_t* src, size_t n, hipStream_t s);
 // d_pairs[1] = d_pairs[0] when it is at most cap, else 0 with the overflow recorded in stats
 void launch_pair_capacity(uint32_t* d_pairs, uint32_t cap, unsigned long long* stats, unsigned long long* prof,
@@ -157,15 +166,30 @@ size_t scan_tmp_bytes(uint32_t n);
 hipError_t exclusive_scan_u32(const uint32_t* in, uint32_t* out, uint32_t n, uint32_t* d_total,
                               DevBuf& scan_tmp, hipStream_t s);
 void launch_gather_u32(const uint32_t* src, const uint32_t* idx, uint32_t* dst, uint32_t n, hipStream_t s);
-// pairs in depth order for the live count *d_pairs (launches sized for cap pairs)
-void launch_emit_pairs(const uint32_t* sorted_ids, const uint32_t* offsets, uint32_t n, const uint32_t* d_pairs,
-                       uint32_t cap, const uint2* rect, uint32_t tiles_x, uint32_t* keys, uint32_t* vals,
-                       uint32_t* pair_off, uint32_t* chunk_first, float4* rec, hipStream_t s);
+// each kernel's (tile, kernel) slot offset by id, also into its record
+void launch_pair_off(const uint32_t* sorted_ids, const uint32_t* offsets, uint32_t n, uint32_t* pair_off, float4* rec,
+                     hipStream_t s);
+// buffers of the two-level tile binning
+struct TileListBufs {
+    uint32_t *nsup, *moffs;           // [n]
+    uint32_t *mk, *mv, *mk2, *mv2;    // [cap pairs]
+    uint2* sranges;                   // [super-tiles]
+    uint32_t* seg_base;               // [super-tiles + 1]
+    uint32_t *counts, *offs;          // [segment_words]
+    uint2* ranges;                    // [tiles]
+};
+uint32_t super_tiles(int tiles_x, int tiles_y);
+// words of the per-(segment, tile) count and offset arrays for cap_pairs pairs
+size_t segment_words(size_t cap_pairs, int tiles_x, int tiles_y);
+// per-tile lists of the kernels whose tile rectangle covers each tile, in depth order (sorted_ids),
+// for the live pair count d_total[1] (launches sized for cap pairs); *ids_out receives the list
+// buffer (one of mv, mv2) that ranges index
+hipError_t build_tile_lists(const uint32_t* sorted_ids, const uint2* rect, uint32_t n, uint32_t* d_total, uint32_t cap,
+                            int tiles_x, int tiles_y, const TileListBufs& bufs, DevBuf& hist, DevBuf& scan_tmp,
+                            uint32_t** ids_out, hipStream_t s);
 // the projected records [n][4] as the public layout [3][n] (gsn_frame_records)
 void launch_records_out(const float4* rec, int n, float4* out, hipStream_t s);
-size_t emit_chunks(uint32_t pairs);
 size_t radix_hist_bytes(uint32_t n);
-void launch_tile_ranges(const uint32_t* keys, const uint32_t* d_pairs, uint32_t cap, uint2* ranges, hipStream_t s);
 // tiles ordered by a length, longest first (coarse: four buckets per octave, any order within one): the
 // list lengths of ranges when lens is null, else lens
 void launch_tile_order(const uint2* ranges, const uint32_t* lens, int tiles, uint32_t* order, hipStream_t s);

@@ -517,98 +517,207 @@ __global__ void gather_u32_kernel(const uint32_t* __restrict__ src, const uint32
 
 // One thread per depth rank: writes the kernel's (tile, id) pairs, row-major
 // over its rectangle, at its scanned offset.
-// Each kernel's slot range: pair_off[id] = offsets[depth rank].
-// Pairs in depth order are emitted by contiguous chunks of kEmitChunk pair slots per workgroup.
-constexpr int kEmitChunk = 2048;
-
-// One thread per depth rank: the kernel's pair offset by id, and for every chunk whose first slot
-// falls in the rank's range, that rank (the ranges partition the slots, so each chunk's entry is
-// written once).
-// pairs: the live pair count (0 after a capacity overflow: then no chunk is emitted).  The offset
-// is also stored in the kernel's record (word 14), next to its tile rectangle.
+// Each kernel's slot range: pair_off[id] = offsets[depth rank], kernel r (depth rank) owning the
+// slots [offsets[r], offsets[r] + ntiles) of its (tile, kernel) pairs in row-major tile order.  The
+// offset is also stored in the kernel's record (word 14), next to its tile rectangle.
 __global__ void pair_off_kernel(const uint32_t* __restrict__ sorted_ids, const uint32_t* __restrict__ offsets,
-                                uint32_t n, const uint32_t* __restrict__ d_pairs, uint32_t* __restrict__ pair_off,
-                                uint32_t* __restrict__ chunk_first, uint32_t* __restrict__ rec_words) {
+                                uint32_t n, uint32_t* __restrict__ pair_off, uint32_t* __restrict__ rec_words) {
     const uint32_t r = blockIdx.x * blockDim.x + threadIdx.x;
     if (r >= n) return;
-    const uint32_t pairs = *d_pairs;
-    const uint32_t o0 = offsets[r], o1 = min(r + 1 < n ? offsets[r + 1] : pairs, pairs);
-    const uint32_t id = sorted_ids[r];
+    const uint32_t id = sorted_ids[r], o0 = offsets[r];
     pair_off[id] = o0;
     rec_words[16 * (size_t)id + 14] = o0;
-    for (uint32_t c = (o0 + kEmitChunk - 1) / kEmitChunk; (size_t)c * kEmitChunk < o1; ++c) chunk_first[c] = r;
 }
 
-// The workgroup stages the (few) kernels whose ranges meet its chunk, so that the writes are
-// coalesced, and each thread finds the kernel of its slot by binary search over their offsets.
-// Kernel r (depth rank) owns slots [offsets[r], offsets[r] + ntiles) in row-major tile order.
+// ---------------------------------------------------------------------------
+// Per-tile lists by two-level binning.  The tiles are grouped into super-tiles of kSuper x kSuper
+// tiles.  (1) Each kernel, in depth order, emits one membership (super-tile, kernel) per super-tile
+// its tile rectangle meets, and a stable radix partition by super-tile leaves each super-tile's
+// members in depth order (a few memberships per kernel, against tens of (tile, kernel) pairs).
+// (2) A super-tile's members are cut into segments of kSegment, one wave each.  The wave counts
+// its entries per tile (lane j holds tile j's count), and one exclusive scan over the counts laid
+// out super-tile by super-tile, tile by tile within it and segment by segment within a tile, gives
+// every segment's place in every tile's list.  The wave then writes its entries in member order: for
+// each tile a ballot over the wave ranks the members that cover it, so each list comes out in depth
+// order, identical to a stable partition of all pairs by tile, and its run is written coalesced.
+// The lists are stored super-tile after super-tile; ranges index them.
+// ---------------------------------------------------------------------------
+constexpr int kSuper = 8, kSuperTiles = kSuper * kSuper;
+constexpr int kSegment = 512;
 
-// The grid covers the pair capacity; chunks past the live pair count return at once.
-__global__ __launch_bounds__(kThreads) void emit_pairs_kernel(const uint32_t* __restrict__ sorted_ids,
-                                                               const uint32_t* __restrict__ offsets, uint32_t n,
-                                                               const uint32_t* __restrict__ d_pairs,
-                                                               const uint2* __restrict__ rect,
-                                                               uint32_t tiles_x, uint32_t* __restrict__ keys,
-                                                               uint32_t* __restrict__ vals,
-                                                               const uint32_t* __restrict__ chunk_first) {
-    __shared__ uint32_t s_off[kEmitChunk], s_id[kEmitChunk];
-    __shared__ uint2 s_rect[kEmitChunk];
-    __shared__ uint32_t s_r0, s_cnt;
-    const uint32_t pairs = *d_pairs;
-    const uint32_t p0 = blockIdx.x * (uint32_t)kEmitChunk;
-    if (p0 >= pairs) return;  // uniform across the workgroup
-    const uint32_t p1 = min(pairs, p0 + (uint32_t)kEmitChunk);
-    if (threadIdx.x == 0) {
-        // first and last ranks whose ranges meet [p0, p1): the rank owning p0, and the rank owning
-        // the next chunk's first slot unless its range starts there (visible kernels have at least
-        // one pair each, so at most kEmitChunk ranks meet a chunk)
-        const uint32_t r0 = chunk_first[blockIdx.x];
-        uint32_t r1;
-        if (p1 < pairs) {
-            r1 = chunk_first[blockIdx.x + 1];
-            if (offsets[r1] >= p1) --r1;
-        } else {
-            uint32_t lo = r0, hi = n - 1;  // last rank whose range starts at or before p1 - 1
-            while (lo < hi) {
-                const uint32_t mid = (lo + hi + 1) >> 1;
-                if (offsets[mid] <= p1 - 1) lo = mid; else hi = mid - 1;
+__device__ __forceinline__ void rect_bounds(uint2 rc, uint32_t& x0, uint32_t& y0, uint32_t& x1, uint32_t& y1) {
+    x0 = rc.x & 0xffffu;
+    y0 = rc.x >> 16;
+    x1 = rc.y & 0xffffu;
+    y1 = rc.y >> 16;
+}
+
+// nsup[r]: the number of super-tiles the tile rectangle of depth rank r meets (0 for an empty one).
+__global__ void super_count_kernel(const uint32_t* __restrict__ sorted_ids, const uint2* __restrict__ rect,
+                                   uint32_t n, uint32_t* __restrict__ nsup) {
+    const uint32_t r = blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= n) return;
+    uint32_t x0, y0, x1, y1;
+    rect_bounds(rect[sorted_ids[r]], x0, y0, x1, y1);
+    nsup[r] = (x1 > x0 && y1 > y0) ? ((x1 - 1) / kSuper - x0 / kSuper + 1) * ((y1 - 1) / kSuper - y0 / kSuper + 1) : 0u;
+}
+
+// The live membership count: the scanned total, or 0 when the render's pairs did not fit (d_total[1]
+// is then 0 while d_total[0] is not).  Memberships never outnumber pairs (each meets at least one
+// tile), so a live count fits the pair buffers.  One thread.
+__global__ void member_live_kernel(uint32_t* __restrict__ d_total) {
+    d_total[3] = (d_total[1] == 0u && d_total[0] != 0u) ? 0u : d_total[2];
+}
+
+// Memberships of depth rank r at moffs[r]: keys = super-tile id (row-major), values = kernel id.
+__global__ void super_emit_kernel(const uint32_t* __restrict__ sorted_ids, const uint2* __restrict__ rect,
+                                  const uint32_t* __restrict__ moffs, uint32_t n, const uint32_t* __restrict__ d_total,
+                                  uint32_t sup_x, uint32_t* __restrict__ keys, uint32_t* __restrict__ vals) {
+    const uint32_t r = blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= n || d_total[3] == 0u) return;
+    const uint32_t id = sorted_ids[r];
+    uint32_t x0, y0, x1, y1;
+    rect_bounds(rect[id], x0, y0, x1, y1);
+    if (x1 <= x0 || y1 <= y0) return;
+    uint32_t m = moffs[r];
+    for (uint32_t sy = y0 / kSuper; sy <= (y1 - 1) / kSuper; ++sy)
+        for (uint32_t sx = x0 / kSuper; sx <= (x1 - 1) / kSuper; ++sx) {
+            keys[m] = sy * sup_x + sx;
+            vals[m] = id;
+            ++m;
+        }
+}
+
+// seg_base[st]: the first segment of super-tile st (exclusive scan of ceil(members / kSegment)),
+// seg_base[n_super] the number of segments.  One workgroup of kThreads.
+__global__ __launch_bounds__(kThreads) void segment_scan_kernel(const uint2* __restrict__ sranges, uint32_t n_super,
+                                                                 uint32_t* __restrict__ seg_base) {
+    uint32_t carry = 0;
+    for (uint32_t b0 = 0; b0 < n_super; b0 += kThreads) {  // uniform across the workgroup
+        const uint32_t st = b0 + threadIdx.x;
+        uint32_t c = 0;
+        if (st < n_super) {
+            const uint2 sr = sranges[st];
+            c = (sr.y - sr.x + kSegment - 1) / kSegment;
+        }
+        uint32_t tot;
+        const uint32_t off = block_excl_scan(c, &tot);
+        if (st < n_super) seg_base[st] = carry + off;
+        carry += tot;
+    }
+    if (threadIdx.x == 0) seg_base[n_super] = carry;
+}
+
+// Segment b's super-tile (the last st with seg_base[st] <= b), its member range and the segments
+// [b0, b1) of that super-tile.  False past the last segment.
+__device__ __forceinline__ bool segment_of(uint32_t b, const uint32_t* __restrict__ seg_base, uint32_t n_super,
+                                           const uint2* __restrict__ sranges, uint32_t& st, uint32_t& m0,
+                                           uint32_t& m1, uint32_t& b0, uint32_t& b1) {
+    if (b >= seg_base[n_super]) return false;
+    uint32_t lo = 0, hi = n_super - 1;
+    while (lo < hi) {
+        const uint32_t mid = (lo + hi + 1) >> 1;
+        if (seg_base[mid] <= b) lo = mid; else hi = mid - 1;
+    }
+    st = lo;
+    b0 = seg_base[st];
+    b1 = seg_base[st + 1];
+    const uint2 sr = sranges[st];
+    m0 = sr.x + (b - b0) * (uint32_t)kSegment;
+    m1 = min(sr.y, m0 + (uint32_t)kSegment);
+    return true;
+}
+
+// Place of (segment b, local tile j) in the count and offset arrays: the super-tile's block starts at
+// kSuperTiles * b0 and holds its tiles one after another, each with its segments in order.
+__device__ __forceinline__ size_t count_index(uint32_t b, uint32_t j, uint32_t b0, uint32_t b1) {
+    return (size_t)kSuperTiles * b0 + (size_t)j * (b1 - b0) + (b - b0);
+}
+
+// The rectangle of a member, clipped to super-tile st and in its local tile coordinates [0, kSuper).
+__device__ __forceinline__ void local_rect(uint2 rc, uint32_t st, uint32_t sup_x, uint32_t& lx0, uint32_t& ly0,
+                                           uint32_t& lx1, uint32_t& ly1) {
+    uint32_t x0, y0, x1, y1;
+    rect_bounds(rc, x0, y0, x1, y1);
+    const uint32_t ox = (st % sup_x) * kSuper, oy = (st / sup_x) * kSuper;
+    lx0 = max(x0, ox) - ox;
+    ly0 = max(y0, oy) - oy;
+    lx1 = min(x1, ox + kSuper) - ox;
+    ly1 = min(y1, oy + kSuper) - oy;
+}
+
+// One wave per segment: counts of its entries per local tile (COUNT), or its entries written into the
+// tile lists at the scanned offsets, in member order (!COUNT).  Waves of a workgroup are independent.
+template <bool COUNT>
+__global__ __launch_bounds__(kThreads) void segment_tiles_kernel(const uint32_t* __restrict__ mvals,
+                                                                  const uint2* __restrict__ sranges,
+                                                                  const uint32_t* __restrict__ seg_base,
+                                                                  uint32_t n_super, const uint2* __restrict__ rect,
+                                                                  uint32_t sup_x, uint32_t* __restrict__ counts,
+                                                                  const uint32_t* __restrict__ offs,
+                                                                  uint32_t* __restrict__ ids) {
+    const int lane = __lane_id();
+    const uint32_t b = blockIdx.x * (kThreads / 64) + threadIdx.x / 64;
+    uint32_t st, m0, m1, b0, b1;
+    if (!segment_of(b, seg_base, n_super, sranges, st, m0, m1, b0, b1)) return;  // uniform across the wave
+    const uint64_t lt_mask = lane == 0 ? 0ull : (~0ull >> (64 - lane));
+    const size_t ci = count_index(b, (uint32_t)lane, b0, b1);
+    uint32_t run = COUNT ? 0u : offs[ci];  // lane j: tile j's count, or its next place in the list
+    for (uint32_t base = m0; base < m1; base += 64) {  // uniform across the wave
+        const uint32_t m = base + (uint32_t)lane;
+        uint32_t id = 0, lx0 = 0, ly0 = 0, lx1 = 0, ly1 = 0;
+        if (m < m1) {
+            id = mvals[m];
+            local_rect(rect[id], st, sup_x, lx0, ly0, lx1, ly1);
+        }
+        for (uint32_t ly = 0; ly < (uint32_t)kSuper; ++ly) {
+            const bool row = ly >= ly0 && ly < ly1;
+            if (__ballot(row) == 0ull) continue;  // no member of this batch covers the row
+#pragma unroll
+            for (uint32_t lx = 0; lx < (uint32_t)kSuper; ++lx) {
+                const uint32_t j = ly * kSuper + lx;
+                const bool c = row && lx >= lx0 && lx < lx1;
+                const uint64_t bal = __ballot(c);
+                if (!COUNT) {
+                    // tile j's next place, read from lane j (j is uniform across the wave)
+                    const uint32_t at = (uint32_t)__builtin_amdgcn_readlane((int)run, (int)j);
+                    if (c) ids[at + (uint32_t)__popcll(bal & lt_mask)] = id;
+                }
+                if ((uint32_t)lane == j) run += (uint32_t)__popcll(bal);
             }
-            r1 = lo;
         }
-        s_r0 = r0;
-        s_cnt = r1 - r0 + 1;
     }
-    __syncthreads();
-    const uint32_t r0 = s_r0, cnt = s_cnt;
-    for (uint32_t j = threadIdx.x; j < cnt; j += blockDim.x) {
-        const uint32_t id = sorted_ids[r0 + j];
-        s_off[j] = offsets[r0 + j];
-        s_id[j] = id;
-        s_rect[j] = rect[id];
-    }
-    __syncthreads();
-    for (uint32_t p = p0 + threadIdx.x; p < p1; p += blockDim.x) {
-        uint32_t lo = 0, hi = cnt - 1;
-        while (lo < hi) {
-            const uint32_t mid = (lo + hi + 1) >> 1;
-            if (s_off[mid] <= p) lo = mid; else hi = mid - 1;
-        }
-        const uint2 rc = s_rect[lo];
-        const uint32_t x0 = rc.x & 0xffffu, y0 = rc.x >> 16, x1 = rc.y & 0xffffu;
-        const uint32_t w = x1 - x0, i = p - s_off[lo];
-        keys[p] = (y0 + i / w) * tiles_x + x0 + i % w;
-        vals[p] = s_id[lo];
-    }
+    if (COUNT) counts[ci] = run;
 }
 
-__global__ void tile_ranges_kernel(const uint32_t* __restrict__ keys, const uint32_t* __restrict__ d_pairs,
-                                   uint2* __restrict__ ranges) {
-    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
-    const uint32_t pairs = *d_pairs;
-    if (i >= pairs) return;
-    const uint32_t k = keys[i];
-    if (i == 0 || keys[i - 1] != k) ranges[k].x = i;
-    if (i == pairs - 1 || keys[i + 1] != k) ranges[k].y = i + 1;
+// Per tile: its range in the lists (the offset of its super-tile's first segment, and the last
+// segment's offset plus count); (0, 0) for a tile whose super-tile has no members.
+__global__ void tile_list_ranges_kernel(const uint32_t* __restrict__ seg_base, uint32_t tiles_x, uint32_t tiles,
+                                        uint32_t sup_x, const uint32_t* __restrict__ counts,
+                                        const uint32_t* __restrict__ offs, uint2* __restrict__ ranges) {
+    const uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= tiles) return;
+    const uint32_t tx = t % tiles_x, ty = t / tiles_x;
+    const uint32_t st = (ty / kSuper) * sup_x + tx / kSuper, j = (ty % kSuper) * kSuper + tx % kSuper;
+    const uint32_t b0 = seg_base[st], b1 = seg_base[st + 1];
+    if (b1 == b0) {
+        ranges[t] = make_uint2(0u, 0u);
+        return;
+    }
+    const size_t first = count_index(b0, j, b0, b1), last = count_index(b1 - 1, j, b0, b1);
+    ranges[t] = make_uint2(offs[first], offs[last] + counts[last]);
+}
+
+// [start, end) of each key's run in sorted keys (live count *d_count; grid-stride, so the grid need
+// not cover the capacity).
+__global__ void key_ranges_kernel(const uint32_t* __restrict__ keys, const uint32_t* __restrict__ d_count,
+                                  uint2* __restrict__ ranges) {
+    const uint32_t count = *d_count;
+    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < count; i += gridDim.x * blockDim.x) {
+        const uint32_t k = keys[i];
+        if (i == 0 || keys[i - 1] != k) ranges[k].x = i;
+        if (i == count - 1 || keys[i + 1] != k) ranges[k].y = i + 1;
+    }
 }
 
 // One workgroup: tiles bucketed by list length (four buckets per octave) and written out longest
@@ -884,7 +993,7 @@ hipError_t exclusive_scan_u32(const uint32_t* in, uint32_t* out, uint32_t n, uin
 }
 
 hipError_t radix_sort_pairs(uint32_t* k0, uint32_t* v0, uint32_t* k1, uint32_t* v1, uint32_t n, const uint32_t* d_n,
-                            int bit_lo, int bit_hi, DevBuf& hist, hipStream_t s) {
+                            int bit_lo, int bit_hi, DevBuf& hist, hipStream_t s, uint32_t** k_res, uint32_t** v_res) {
     if (n == 0) return hipSuccess;
     const uint32_t tile = radix_tile(n), nb = (n + tile - 1) / tile;
     const bool small = n <= kRsSmallN;
@@ -905,6 +1014,11 @@ hipError_t radix_sort_pairs(uint32_t* k0, uint32_t* v0, uint32_t* k1, uint32_t* 
         uint32_t* t = ka; ka = kb; kb = t;
         t = va; va = vb; vb = t;
     }
+    if (k_res && v_res) {  // the caller takes the result where the passes left it
+        *k_res = ka;
+        *v_res = va;
+        return hipGetLastError();
+    }
     if (passes & 1) {
         // the result is in the second buffers: copy the live keys back with kernels (no copy nodes when a
         // caller captures the stream)
@@ -923,28 +1037,71 @@ void launch_gather_u32(const uint32_t* src, const uint32_t* idx, uint32_t* dst, 
     if (n) gather_u32_kernel<<<(n + kThreads - 1) / kThreads, kThreads, 0, s>>>(src, idx, dst, n);
 }
 
-size_t emit_chunks(uint32_t pairs) { return ((size_t)pairs + kEmitChunk - 1) / kEmitChunk; }
-
 size_t radix_hist_bytes(uint32_t n) {
     const size_t nb = ((size_t)n + radix_tile(n) - 1) / radix_tile(n);
     return ((size_t)256 * nb * 2 + 256) * 4;
 }
 
-void launch_emit_pairs(const uint32_t* sorted_ids, const uint32_t* offsets, uint32_t n, const uint32_t* d_pairs,
-                       uint32_t cap, const uint2* rect, uint32_t tiles_x, uint32_t* keys, uint32_t* vals,
-                       uint32_t* pair_off, uint32_t* chunk_first, float4* rec, hipStream_t s) {
-    if (n == 0) return;
-    pair_off_kernel<<<(n + kThreads - 1) / kThreads, kThreads, 0, s>>>(sorted_ids, offsets, n, d_pairs, pair_off,
-                                                                       chunk_first,
-                                                                       reinterpret_cast<uint32_t*>(rec));
-    if (cap)
-        emit_pairs_kernel<<<(uint32_t)emit_chunks(cap), kThreads, 0, s>>>(sorted_ids, offsets, n, d_pairs, rect,
-                                                                        tiles_x, keys, vals, chunk_first);
+void launch_pair_off(const uint32_t* sorted_ids, const uint32_t* offsets, uint32_t n, uint32_t* pair_off, float4* rec,
+                     hipStream_t s) {
+    if (n)
+        pair_off_kernel<<<(n + kThreads - 1) / kThreads, kThreads, 0, s>>>(sorted_ids, offsets, n, pair_off,
+                                                                           reinterpret_cast<uint32_t*>(rec));
 }
 
-void launch_tile_ranges(const uint32_t* keys, const uint32_t* d_pairs, uint32_t cap, uint2* ranges, hipStream_t s) {
-    if (cap) tile_ranges_kernel<<<(cap + kThreads - 1) / kThreads, kThreads, 0, s>>>(keys, d_pairs, ranges);
+uint32_t super_tiles_x(int tiles_x) { return (uint32_t)((tiles_x + kSuper - 1) / kSuper); }
+uint32_t super_tiles(int tiles_x, int tiles_y) { return super_tiles_x(tiles_x) * (uint32_t)((tiles_y + kSuper - 1) / kSuper); }
+// segments are at most ceil(members / kSegment) per super-tile, members at most pairs
+size_t max_segments(size_t cap_pairs, int tiles_x, int tiles_y) {
+    return (cap_pairs + kSegment - 1) / kSegment + super_tiles(tiles_x, tiles_y);
 }
+size_t segment_words(size_t cap_pairs, int tiles_x, int tiles_y) {
+    return max_segments(cap_pairs, tiles_x, tiles_y) * kSuperTiles;
+}
+
+hipError_t build_tile_lists(const uint32_t* sorted_ids, const uint2* rect, uint32_t n, uint32_t* d_total, uint32_t cap,
+                            int tiles_x, int tiles_y, const TileListBufs& bb, DevBuf& hist, DevBuf& scan_tmp,
+                            uint32_t** ids_out, hipStream_t s) {
+    const uint32_t tiles = (uint32_t)tiles_x * (uint32_t)tiles_y;
+    const uint32_t sup_x = super_tiles_x(tiles_x), n_super = super_tiles(tiles_x, tiles_y);
+    const uint32_t ng = (n + kThreads - 1) / kThreads;
+    if (n == 0 || cap == 0) {
+        launch_fill_u32(reinterpret_cast<uint32_t*>(bb.ranges), 0u, 2 * (size_t)tiles, s);
+        *ids_out = bb.mv;
+        return hipGetLastError();
+    }
+    // (1) memberships in depth order, partitioned by super-tile
+    launch_fill_u32(reinterpret_cast<uint32_t*>(bb.sranges), 0u, 2 * (size_t)n_super, s);
+    super_count_kernel<<<ng, kThreads, 0, s>>>(sorted_ids, rect, n, bb.nsup);
+    hipError_t e = exclusive_scan_u32(bb.nsup, bb.moffs, n, d_total + 2, scan_tmp, s);
+    if (e != hipSuccess) return e;
+    member_live_kernel<<<1, 1, 0, s>>>(d_total);
+    super_emit_kernel<<<ng, kThreads, 0, s>>>(sorted_ids, rect, bb.moffs, n, d_total, sup_x, bb.mk, bb.mv);
+    int bits = 1;
+    while ((1u << bits) < n_super) ++bits;
+    uint32_t *mk = bb.mk, *mv = bb.mv;
+    e = radix_sort_pairs(bb.mk, bb.mv, bb.mk2, bb.mv2, cap, d_total + 3, 0, bits, hist, s, &mk, &mv);
+    if (e != hipSuccess) return e;
+    key_ranges_kernel<<<grid_for(cap, kThreads, 4096), kThreads, 0, s>>>(mk, d_total + 3, bb.sranges);
+    // the tile lists go to whichever values buffer the sorted members do not occupy
+    *ids_out = mv == bb.mv ? bb.mv2 : bb.mv;
+    // (2) segments: counts per tile, one scan, then the lists
+    segment_scan_kernel<<<1, kThreads, 0, s>>>(bb.sranges, n_super, bb.seg_base);
+    const size_t words = segment_words(cap, tiles_x, tiles_y);
+    const uint32_t nwg = (uint32_t)((max_segments(cap, tiles_x, tiles_y) + kThreads / 64 - 1) / (kThreads / 64));
+    segment_tiles_kernel<true><<<nwg, kThreads, 0, s>>>(mv, bb.sranges, bb.seg_base, n_super, rect, sup_x, bb.counts,
+                                                         nullptr, nullptr);
+    // the scan runs over the capacity: entries past the live segments are never read
+    e = exclusive_scan_u32(bb.counts, bb.offs, (uint32_t)words, d_total + 4, scan_tmp, s);
+    if (e != hipSuccess) return e;
+    tile_list_ranges_kernel<<<(tiles + kThreads - 1) / kThreads, kThreads, 0, s>>>(bb.seg_base, (uint32_t)tiles_x,
+                                                                                   tiles, sup_x, bb.counts, bb.offs,
+                                                                                   bb.ranges);
+    segment_tiles_kernel<false><<<nwg, kThreads, 0, s>>>(mv, bb.sranges, bb.seg_base, n_super, rect, sup_x, nullptr,
+                                                          bb.offs, *ids_out);
+    return hipGetLastError();
+}
+
 
 void launch_pair_capacity(uint32_t* d_pairs, uint32_t cap, unsigned long long* stats, unsigned long long* prof,
                           hipStream_t s) {
