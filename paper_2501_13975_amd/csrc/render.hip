@@ -569,7 +569,20 @@ __global__ void member_live_kernel(uint32_t* __restrict__ d_total) {
     d_total[3] = (d_total[1] == 0u && d_total[0] != 0u) ? 0u : d_total[2];
 }
 
-// Memberships of depth rank r at moffs[r]: keys = super-tile id (row-major), values = kernel id.
+// A membership's key: the super-tile id (row-major) in the low 16 bits, which the partition sorts
+// on, and above them the kernel's rectangle clipped to the super-tile in its local tile coordinates
+// (lx0, ly0, lx1 - 1, ly1 - 1, 3 bits each), so that the segment passes need no gather by kernel id.
+__device__ __forceinline__ uint32_t member_key(uint32_t st, uint32_t lx0, uint32_t ly0, uint32_t lx1, uint32_t ly1) {
+    return st | (lx0 << 16) | (ly0 << 19) | ((lx1 - 1) << 22) | ((ly1 - 1) << 25);
+}
+__device__ __forceinline__ void member_rect(uint32_t key, uint32_t& lx0, uint32_t& ly0, uint32_t& lx1, uint32_t& ly1) {
+    lx0 = (key >> 16) & 7u;
+    ly0 = (key >> 19) & 7u;
+    lx1 = ((key >> 22) & 7u) + 1;
+    ly1 = ((key >> 25) & 7u) + 1;
+}
+
+// Memberships of depth rank r at moffs[r]: keys as member_key, values = kernel id.
 __global__ void super_emit_kernel(const uint32_t* __restrict__ sorted_ids, const uint2* __restrict__ rect,
                                   const uint32_t* __restrict__ moffs, uint32_t n, const uint32_t* __restrict__ d_total,
                                   uint32_t sup_x, uint32_t* __restrict__ keys, uint32_t* __restrict__ vals) {
@@ -582,7 +595,9 @@ __global__ void super_emit_kernel(const uint32_t* __restrict__ sorted_ids, const
     uint32_t m = moffs[r];
     for (uint32_t sy = y0 / kSuper; sy <= (y1 - 1) / kSuper; ++sy)
         for (uint32_t sx = x0 / kSuper; sx <= (x1 - 1) / kSuper; ++sx) {
-            keys[m] = sy * sup_x + sx;
+            const uint32_t ox = sx * kSuper, oy = sy * kSuper;
+            keys[m] = member_key(sy * sup_x + sx, max(x0, ox) - ox, max(y0, oy) - oy, min(x1, ox + kSuper) - ox,
+                                 min(y1, oy + kSuper) - oy);
             vals[m] = id;
             ++m;
         }
@@ -634,26 +649,14 @@ __device__ __forceinline__ size_t count_index(uint32_t b, uint32_t j, uint32_t b
     return (size_t)kSuperTiles * b0 + (size_t)j * (b1 - b0) + (b - b0);
 }
 
-// The rectangle of a member, clipped to super-tile st and in its local tile coordinates [0, kSuper).
-__device__ __forceinline__ void local_rect(uint2 rc, uint32_t st, uint32_t sup_x, uint32_t& lx0, uint32_t& ly0,
-                                           uint32_t& lx1, uint32_t& ly1) {
-    uint32_t x0, y0, x1, y1;
-    rect_bounds(rc, x0, y0, x1, y1);
-    const uint32_t ox = (st % sup_x) * kSuper, oy = (st / sup_x) * kSuper;
-    lx0 = max(x0, ox) - ox;
-    ly0 = max(y0, oy) - oy;
-    lx1 = min(x1, ox + kSuper) - ox;
-    ly1 = min(y1, oy + kSuper) - oy;
-}
-
 // One wave per segment: counts of its entries per local tile (COUNT), or its entries written into the
 // tile lists at the scanned offsets, in member order (!COUNT).  Waves of a workgroup are independent.
 template <bool COUNT>
-__global__ __launch_bounds__(kThreads) void segment_tiles_kernel(const uint32_t* __restrict__ mvals,
+__global__ __launch_bounds__(kThreads) void segment_tiles_kernel(const uint32_t* __restrict__ mkeys,
+                                                                  const uint32_t* __restrict__ mvals,
                                                                   const uint2* __restrict__ sranges,
                                                                   const uint32_t* __restrict__ seg_base,
-                                                                  uint32_t n_super, const uint2* __restrict__ rect,
-                                                                  uint32_t sup_x, uint32_t* __restrict__ counts,
+                                                                  uint32_t n_super, uint32_t* __restrict__ counts,
                                                                   const uint32_t* __restrict__ offs,
                                                                   uint32_t* __restrict__ ids) {
     const int lane = __lane_id();
@@ -667,8 +670,8 @@ __global__ __launch_bounds__(kThreads) void segment_tiles_kernel(const uint32_t*
         const uint32_t m = base + (uint32_t)lane;
         uint32_t id = 0, lx0 = 0, ly0 = 0, lx1 = 0, ly1 = 0;
         if (m < m1) {
-            id = mvals[m];
-            local_rect(rect[id], st, sup_x, lx0, ly0, lx1, ly1);
+            if (!COUNT) id = mvals[m];
+            member_rect(mkeys[m], lx0, ly0, lx1, ly1);
         }
         for (uint32_t ly = 0; ly < (uint32_t)kSuper; ++ly) {
             const bool row = ly >= ly0 && ly < ly1;
@@ -708,15 +711,15 @@ __global__ void tile_list_ranges_kernel(const uint32_t* __restrict__ seg_base, u
     ranges[t] = make_uint2(offs[first], offs[last] + counts[last]);
 }
 
-// [start, end) of each key's run in sorted keys (live count *d_count; grid-stride, so the grid need
-// not cover the capacity).
+// [start, end) of each key's run in keys sorted on their bits `mask` (live count *d_count; grid-stride,
+// so the grid need not cover the capacity).
 __global__ void key_ranges_kernel(const uint32_t* __restrict__ keys, const uint32_t* __restrict__ d_count,
-                                  uint2* __restrict__ ranges) {
+                                  uint32_t mask, uint2* __restrict__ ranges) {
     const uint32_t count = *d_count;
     for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < count; i += gridDim.x * blockDim.x) {
-        const uint32_t k = keys[i];
-        if (i == 0 || keys[i - 1] != k) ranges[k].x = i;
-        if (i == count - 1 || keys[i + 1] != k) ranges[k].y = i + 1;
+        const uint32_t k = keys[i] & mask;
+        if (i == 0 || (keys[i - 1] & mask) != k) ranges[k].x = i;
+        if (i == count - 1 || (keys[i + 1] & mask) != k) ranges[k].y = i + 1;
     }
 }
 
@@ -1078,27 +1081,28 @@ hipError_t build_tile_lists(const uint32_t* sorted_ids, const uint2* rect, uint3
     member_live_kernel<<<1, 1, 0, s>>>(d_total);
     super_emit_kernel<<<ng, kThreads, 0, s>>>(sorted_ids, rect, bb.moffs, n, d_total, sup_x, bb.mk, bb.mv);
     int bits = 1;
+    // at most 16: the image limits (at most 2^28 pixels, 65535 tiles a side) keep n_super below 2^15
     while ((1u << bits) < n_super) ++bits;
     uint32_t *mk = bb.mk, *mv = bb.mv;
     e = radix_sort_pairs(bb.mk, bb.mv, bb.mk2, bb.mv2, cap, d_total + 3, 0, bits, hist, s, &mk, &mv);
     if (e != hipSuccess) return e;
-    key_ranges_kernel<<<grid_for(cap, kThreads, 4096), kThreads, 0, s>>>(mk, d_total + 3, bb.sranges);
+    key_ranges_kernel<<<grid_for(cap, kThreads, 4096), kThreads, 0, s>>>(mk, d_total + 3, 0xffffu, bb.sranges);
     // the tile lists go to whichever values buffer the sorted members do not occupy
     *ids_out = mv == bb.mv ? bb.mv2 : bb.mv;
     // (2) segments: counts per tile, one scan, then the lists
     segment_scan_kernel<<<1, kThreads, 0, s>>>(bb.sranges, n_super, bb.seg_base);
     const size_t words = segment_words(cap, tiles_x, tiles_y);
     const uint32_t nwg = (uint32_t)((max_segments(cap, tiles_x, tiles_y) + kThreads / 64 - 1) / (kThreads / 64));
-    segment_tiles_kernel<true><<<nwg, kThreads, 0, s>>>(mv, bb.sranges, bb.seg_base, n_super, rect, sup_x, bb.counts,
-                                                         nullptr, nullptr);
+    segment_tiles_kernel<true><<<nwg, kThreads, 0, s>>>(mk, mv, bb.sranges, bb.seg_base, n_super, bb.counts, nullptr,
+                                                         nullptr);
     // the scan runs over the capacity: entries past the live segments are never read
     e = exclusive_scan_u32(bb.counts, bb.offs, (uint32_t)words, d_total + 4, scan_tmp, s);
     if (e != hipSuccess) return e;
     tile_list_ranges_kernel<<<(tiles + kThreads - 1) / kThreads, kThreads, 0, s>>>(bb.seg_base, (uint32_t)tiles_x,
                                                                                    tiles, sup_x, bb.counts, bb.offs,
                                                                                    bb.ranges);
-    segment_tiles_kernel<false><<<nwg, kThreads, 0, s>>>(mv, bb.sranges, bb.seg_base, n_super, rect, sup_x, nullptr,
-                                                          bb.offs, *ids_out);
+    segment_tiles_kernel<false><<<nwg, kThreads, 0, s>>>(mk, mv, bb.sranges, bb.seg_base, n_super, nullptr, bb.offs,
+                                                          *ids_out);
     return hipGetLastError();
 }
 
