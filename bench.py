@@ -117,7 +117,7 @@ def _sweep(tr, t, i, learned, mask=31):
         tr.sweep(t, mask)
 
 
-def _timed(tr, order, warmup, steps, learned, dev, profile=True):
+def _timed(tr, order, warmup, steps, learned, dev, profile=True, wave_steps=False):
     """Times `steps` sweeps after `warmup` untimed ones (the host clock around a synchronised
     loop).  With profile, the library also times every stage with HIP events and counts its work
     (a few microseconds per stage): the stage times and counters are returned."""
@@ -126,7 +126,7 @@ def _timed(tr, order, warmup, steps, learned, dev, profile=True):
         _sweep(tr, int(order[i]), i, learned)
     torch.cuda.synchronize(dev)
     if profile:
-        tr.ctx.profile_enable(True)
+        tr.ctx.profile_enable(True, steps=wave_steps)
     torch.cuda.synchronize(dev)
     start = time.perf_counter()
     for i in range(steps):
@@ -599,6 +599,8 @@ def gpu_run(args):
     prof_el, stages, counts = _timed(tr, order[args.warmup + args.steps:], 0, args.steps, False, dev)
     log(f"[bench] plain: {args.steps / elapsed:.2f} sweeps/s; profiled {args.steps / prof_el:.2f} sweeps/s")
     dist = _sweep_times(tr, order, args.warmup + 2 * args.steps, 30, False, dev)
+    # the raster passes' lane use, from a few more sweeps that also count their wave steps
+    _, _, lane_counts = _timed(tr, order[args.warmup + 2 * args.steps + 30:], 0, 8, False, dev, wave_steps=True)
     status = tr.check_status()
     tr.close()
     graph = _graph_rate(cfg, targets, dev, order, args.warmup, args.steps, args.step_frac) if args.graph_leg else None
@@ -662,7 +664,7 @@ def gpu_run(args):
             del targets
             c4 = _c4_leg(dev, args.learned_every, args.quality_mask, args.quality_step_frac, params, label_mean,
                          args.c4_epochs)
-    return dict(elapsed=elapsed, stages=stages, counts=counts, cfg=cfg, mixed=mixed, learned=learned, quality=quality,
+    return dict(elapsed=elapsed, stages=stages, counts=counts, lane_counts=lane_counts, cfg=cfg, mixed=mixed, learned=learned, quality=quality,
                 batched=batched, variants=variants, overshoot=overshoot, order_exp=order_exp,
                 first_order=first_order, dist=dist, curve=curve, graph=graph, status=status, c4=c4, pre=pre)
 
@@ -759,6 +761,14 @@ def roofline(stages, counts, steps, pixels_per_step, n, views):
     out.update(bound="hbm", achieved=round(achieved, 1), peak=PEAK_HBM_GBS, unit="GB/s",
                frac=round(achieved / PEAK_HBM_GBS, 5), traffic=None)
     return out
+
+
+def lane_use(c):
+    """Share of a wave's 64 lanes at work in the raster passes' per-pixel loops: per-pixel steps
+    over 64 x the waves' steps (counted in sweeps profiled at level 2)."""
+    return {"fwd": round(c["fwd_evals"] / max(64 * c["fwd_wave_steps"], 1), 3),
+            "bwd": round((c["bwd_active"] + c["bwd_evals"]) / max(64 * c["bwd_wave_steps"], 1), 3),
+            "sweeps": 8}
 
 
 def solve_rules(counts):
@@ -902,6 +912,8 @@ def main():
         "sweep_ms_distribution": r["dist"],
         "stage_ms_per_step": {k: round(v[0] / args.steps, 3) for k, v in stages.items()},
         "counts_per_step": {k: int(v / args.steps) for k, v in counts.items()},
+        # share of a wave's 64 lanes at work in the raster passes' per-pixel loops
+        "raster_lane_use": lane_use(r["lane_counts"]),
         "roofline": rl,
         "sweep_hbm": srl,
         "solve_rules": solve_rules({k: v / args.steps for k, v in counts.items()}),

@@ -609,12 +609,19 @@ typedef enum {
     GSN_COUNT_SOLVED = 20,          /* kernels solved (visible in the primary, finite blocks and steps) */
     GSN_COUNT_OPAC_BOUND = 21,      /* gsn_apply_step: opacity steps cut by the fraction-to-boundary rule
                                        or the bounds [opac_eps, 1 - opac_eps] */
-    GSN_COUNT_N = 22
+    /* Wave steps of the raster passes' per-pixel loops (one per entry a wave's pixels visit
+     * together): against the per-pixel counts above they give the share of lanes at work.
+     * Counted only at profiling level 2 (gsn_profile_enable), whose raster passes take longer. */
+    GSN_COUNT_FWD_WAVE_STEPS = 22,  /* forward: entries of the band lists the wave walked */
+    GSN_COUNT_BWD_WAVE_STEPS = 23,  /* backward: composited entries the wave walked, and entries evaluated
+                                       again past the recorded batches */
+    GSN_COUNT_N = 24
 } gsn_counter;
 
-/* Turns stage timing on or off and clears what was accumulated.  While on,
- * every stage is bracketed by HIP events on the context's stream (a few
- * microseconds of overhead per stage) and the raster passes count their work. */
+/* Turns stage timing on (on = 1, or 2 to count the raster passes' wave steps too) or off (0)
+ * and clears what was accumulated.  While on, every stage is bracketed by HIP events on the
+ * context's stream (a few microseconds of overhead per stage) and the raster passes count their
+ * work. */
 gsn_status gsn_profile_enable(gsn_ctx* ctx, int32_t on);
 /* Synchronises the stream and returns, per stage, the summed event time in
  * milliseconds (h_ms[GSN_STAGE_COUNT]) and the number of timed launches

@@ -220,6 +220,7 @@ gsn_status gsn_profile_enable(gsn_ctx* ctx, int32_t on) {
     if (ctx->d_counts) launch_fill_u32(reinterpret_cast<uint32_t*>(ctx->d_counts), 0u, 2 * GSN_PROF_WORDS, ctx->stream);
     HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
     ctx->prof = on != 0;
+    ctx->prof_steps = on == 2;
     return GSN_OK;
 }
 
@@ -483,7 +484,7 @@ gsn_status gsn_render(gsn_ctx* ctx, const gsn_gaussians* g, const gsn_camera* ca
         launch_raster_fwd(bp<uint2>(f->ranges), bp<uint32_t>(f->tile_order), f->list_ids,
                           bp<float4>(f->rec), (uint32_t)n, f->cam, f->ro, f->fp32, bp<float>(f->img), bp<double>(f->img64),
                           bp<float>(f->Tfin), bp<uint32_t>(f->ncontrib), bp<uint64_t>(f->masks),
-                          bp<uint32_t>(f->tile_len), prof_counts(ctx), s);
+                          bp<uint32_t>(f->tile_len), prof_counts(ctx), ctx->prof_steps, s);
         // the backward pass takes the tiles with the longest composited prefixes first
         launch_tile_order(nullptr, bp<uint32_t>(f->tile_len), (int)tiles, bp<uint32_t>(f->bwd_order), s);
         HIP_TRY(ctx, hipGetLastError());
@@ -538,7 +539,8 @@ static gsn_status accumulate_impl(gsn_ctx* ctx, const gsn_gaussians* g, const gs
     {
         StageTimer st_(ctx, GSN_STAGE_RASTER_BWD);
         if (f->pairs != 0)  // reserved frames (pairs = -1) always launch: empty lists end at once
-            launch_raster_bwd(*f, bp<float>(f->dL), bp<float>(f->hd), opts->gauss_newton != 0, prof_counts(ctx), s);
+            launch_raster_bwd(*f, bp<float>(f->dL), bp<float>(f->hd), opts->gauss_newton != 0, prof_counts(ctx),
+                              ctx->prof && ctx->prof_steps, s);
     }
     {
         StageTimer st_(ctx, GSN_STAGE_CHAIN);

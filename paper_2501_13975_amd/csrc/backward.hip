@@ -181,7 +181,13 @@ __device__ __forceinline__ void write_partial(float* __restrict__ partial, uint8
 //      Only contributing pairs do the 44-term work.
 // GN: local Gauss-Newton statistics (no loss-gradient times image-curvature terms).  CT: the type of
 // the colour sums along the ray (double; float in the mixed form, from the single-precision image).
-template <bool GN, class CT>
+__device__ __forceinline__ uint32_t wave_max(uint32_t v) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v = max(v, (uint32_t)__shfl_xor((int)v, off, 64));
+    return v;
+}
+
+template <bool GN, class CT, bool STEPS>
 __global__ __launch_bounds__(GSN_BLOCK, 3) void raster_bwd_kernel(
     const uint2* __restrict__ ranges, const uint32_t* __restrict__ order, const uint32_t* __restrict__ ids,
     const float4* __restrict__ rec, uint32_t n, DevCam cam, DevRenderOpts ro,
@@ -244,7 +250,7 @@ __global__ __launch_bounds__(GSN_BLOCK, 3) void raster_bwd_kernel(
     float T = 1.f;
     CT Ca0 = CT(0), Ca1 = CT(0), Ca2 = CT(0);
     const float fpx = (float)px, fpy = (float)py;
-    uint32_t n_eval = 0, n_act = 0, n_part = 0, n_stage = 0;
+    uint32_t n_eval = 0, n_act = 0, n_part = 0, n_stage = 0, n_steps = 0;  // n_steps: the wave's, in every lane
     for (uint32_t base = rg.x; base < end; base += GSN_BLOCK) {
         const int bcnt = (int)min((uint32_t)GSN_BLOCK, end - base);
         // stage the batch: one entry per thread, its slot and its band mask
@@ -301,7 +307,8 @@ __global__ __launch_bounds__(GSN_BLOCK, 3) void raster_bwd_kernel(
 #pragma unroll
             for (int w = 0; w < NW; ++w) bits[w] = mb[(size_t)w * GSN_BLOCK];
         } else {
-            for (uint32_t i = 0; i < nl; ++i) {
+            uint32_t i = 0;
+            for (; i < nl; ++i) {
                 const int j = r_list[wave][i];
                 if (base + j - rg.x >= nc) break;
                 ++n_eval;
@@ -312,6 +319,7 @@ __global__ __launch_bounds__(GSN_BLOCK, 3) void raster_bwd_kernel(
                         if ((j >> 6) == w) bits[w] |= 1ull << (j & 63);
                 }
             }
+            if (STEPS) n_steps += wave_max(i < nl ? i + 1 : i);  // the breaking step counts
         }
         // per (entry, wave): the wave's pixels that composited the entry (the transpose of the pixels'
         // masks), one ballot per entry that some pixel of the wave composited
@@ -378,6 +386,7 @@ __global__ __launch_bounds__(GSN_BLOCK, 3) void raster_bwd_kernel(
                 uint64_t rem = bits[w];
                 if (r0 > wlo) rem &= ~0ull << (r0 - wlo);
                 if (r1 < whi) rem &= (1ull << (r1 - wlo)) - 1ull;
+                if (STEPS) n_steps += wave_max((uint32_t)__popcll(rem));
                 while (rem) {
                     const int j = wlo + __ffsll((unsigned long long)rem) - 1;
                     rem &= rem - 1;
@@ -485,19 +494,21 @@ __global__ __launch_bounds__(GSN_BLOCK, 3) void raster_bwd_kernel(
         }
     }
     if (counts) {
-        __shared__ unsigned long long s_cnt[4];
-        if (tid == 0) s_cnt[0] = s_cnt[1] = s_cnt[2] = s_cnt[3] = 0;
+        __shared__ unsigned long long s_cnt[5];
+        if (tid < 5) s_cnt[tid] = 0;
         __syncthreads();
         atomicAdd(&s_cnt[0], (unsigned long long)n_eval);
         atomicAdd(&s_cnt[1], (unsigned long long)n_act);
         atomicAdd(&s_cnt[2], (unsigned long long)n_part);
         atomicAdd(&s_cnt[3], (unsigned long long)n_stage);
+        if (STEPS && lane == 0) atomicAdd(&s_cnt[4], (unsigned long long)n_steps);
         __syncthreads();
         if (tid == 0) {
             atomicAdd(&counts[GSN_COUNT_BWD_EVALS], s_cnt[0]);
             atomicAdd(&counts[GSN_COUNT_BWD_ACTIVE], s_cnt[1]);
             atomicAdd(&counts[GSN_COUNT_PARTIALS], s_cnt[2]);
             atomicAdd(&counts[GSN_COUNT_BWD_STAGED], s_cnt[3]);
+            atomicAdd(&counts[GSN_COUNT_BWD_WAVE_STEPS], s_cnt[4]);
         }
     }
 }
@@ -672,12 +683,17 @@ __global__ __launch_bounds__(128) void chain_rs_kernel(
 
 }  // namespace
 
+template <bool STEPS>
+static auto bwd_variant(bool gauss_newton, bool fp32) {
+    return gauss_newton ? (fp32 ? raster_bwd_kernel<true, float, STEPS> : raster_bwd_kernel<true, double, STEPS>)
+                        : (fp32 ? raster_bwd_kernel<false, float, STEPS> : raster_bwd_kernel<false, double, STEPS>);
+}
+
 void launch_raster_bwd(const gsn_frame& f, const float* dL, const float* hd, bool gauss_newton,
-                       unsigned long long* counts, hipStream_t s) {
+                       unsigned long long* counts, bool steps, hipStream_t s) {
     const int tiles = f.tiles_x * f.tiles_y;
     // the colour sums of the frame's render: double, or float in the mixed form
-    auto kern = gauss_newton ? (f.fp32 ? raster_bwd_kernel<true, float> : raster_bwd_kernel<true, double>)
-                             : (f.fp32 ? raster_bwd_kernel<false, float> : raster_bwd_kernel<false, double>);
+    auto kern = steps && counts ? bwd_variant<true>(gauss_newton, f.fp32) : bwd_variant<false>(gauss_newton, f.fp32);
     kern<<<tiles, GSN_BLOCK, 0, s>>>(
         bp<uint2>(f.ranges), bp<uint32_t>(f.bwd_order), f.list_ids, bp<float4>(f.rec),
         (uint32_t)f.n, f.cam, f.ro, f.fp32 ? nullptr : bp<double>(f.img64), bp<float>(f.img),

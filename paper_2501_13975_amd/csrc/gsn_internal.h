@@ -93,6 +93,7 @@ struct gsn_ctx {
     std::string err;
     // measurement (gsn_profile_enable)
     bool prof = false;
+    bool prof_steps = false;  // level 2: the raster passes also count their wave steps
     std::vector<ProfRec> recs;
     std::vector<hipEvent_t> pool;
     unsigned long long* d_counts = nullptr;  // GSN_COUNT_N device counters
@@ -195,7 +196,7 @@ size_t radix_hist_bytes(uint32_t n);
 void launch_tile_order(const uint2* ranges, const uint32_t* lens, int tiles, uint32_t* order, hipStream_t s);
 void launch_raster_fwd(const uint2* ranges, const uint32_t* order, const uint32_t* ids, const float4* rec, uint32_t n, const DevCam& cam,
                        const DevRenderOpts& ro, bool fp32, float* img, double* img64, float* Tfin, uint32_t* ncontrib,
-                       uint64_t* masks, uint32_t* tile_len, unsigned long long* counts, hipStream_t s);
+                       uint64_t* masks, uint32_t* tile_len, unsigned long long* counts, bool steps, hipStream_t s);
 void launch_downsample2x(const float* src, int W, int H, float* dst, hipStream_t s);
 void launch_scene_center(const float* pos, int n, double* out, hipStream_t s);
 
@@ -206,7 +207,7 @@ void launch_loss_reduce(const double* part, int nparts, int W, int H, double* ou
 
 // ---- launchers (backward.hip)
 void launch_raster_bwd(const gsn_frame& f, const float* dL, const float* hd, bool gauss_newton,
-                       unsigned long long* counts, hipStream_t s);
+                       unsigned long long* counts, bool steps, hipStream_t s);
 // per-kernel sums of a view's (tile, kernel) partials (a secondary slot reads the primary coverage row)
 void launch_reduce_pairs(const gsn_frame& f, const gsn_gaussians& g, int slot, bool fp32, const gsn_blocks& b,
                          hipStream_t s);

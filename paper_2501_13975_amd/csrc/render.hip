@@ -768,7 +768,7 @@ __global__ __launch_bounds__(1024) void tile_order_kernel(const uint2* __restric
 // ---------------------------------------------------------------------------
 // Six waves per SIMD (at most 80 VGPRs, no spills; six workgroups' LDS fit in a CU).  CT: the type
 // of the colour sums (double; float in the mixed form, which then writes no double image).
-template <class CT>
+template <class CT, bool STEPS>
 __global__ __launch_bounds__(GSN_BLOCK, 6) void raster_fwd_kernel(
     const uint2* __restrict__ ranges, const uint32_t* __restrict__ order, const uint32_t* __restrict__ ids, const float4* __restrict__ rec, uint32_t n,
     DevCam cam, DevRenderOpts ro, float* __restrict__ img, double* __restrict__ img64, float* __restrict__ Tfin,
@@ -797,6 +797,7 @@ __global__ __launch_bounds__(GSN_BLOCK, 6) void raster_fwd_kernel(
     bool done = !inside;
     const float fpx = (float)px, fpy = (float)py;
     uint32_t evals = 0, staged = 0;
+    uint32_t wsteps = 0;  // the wave's steps: the longest walk over its lanes, batch after batch
     // each thread's entry of the next batch is loaded while the current batch is composited
     float4 na = make_float4(0.f, 0.f, 0.f, 0.f), nb = na, nc = na;
     bool nvalid = rg.x + threadIdx.x < rg.y;
@@ -856,7 +857,8 @@ __global__ __launch_bounds__(GSN_BLOCK, 6) void raster_fwd_kernel(
         uint64_t bits[NW];
 #pragma unroll
         for (int w = 0; w < NW; ++w) bits[w] = 0ull;
-        for (uint32_t i = 0; i < nl && !done; ++i) {
+        uint32_t i = 0;
+        for (; i < nl && !done; ++i) {
             const int j = s_list[wave][i];
             const float4 a = s_a[j], b = s_b[j], cc = s_c[j];
             const SplatEval ev = eval_splat(a, b, cc, fpx, fpy, ro.alpha_max);
@@ -879,6 +881,12 @@ __global__ __launch_bounds__(GSN_BLOCK, 6) void raster_fwd_kernel(
                     if ((j >> 6) == q) bits[q] |= 1ull << (j & 63);
             }
         }
+        if (STEPS) {  // the wave walks as far as its longest lane
+            uint32_t m = i;
+#pragma unroll
+            for (int off = 32; off > 0; off >>= 1) m = max(m, (uint32_t)__shfl_xor((int)m, off, 64));
+            wsteps += m;
+        }
         const uint32_t batch = (base - rg.x) / GSN_BLOCK;
         if (masks && batch < (uint32_t)GSN_MASK_BATCHES) {
             // pixel-major words [w][pixel] (the backward pass rebuilds the per-(entry, wave) words from them)
@@ -900,15 +908,17 @@ __global__ __launch_bounds__(GSN_BLOCK, 6) void raster_fwd_kernel(
         if (threadIdx.x == 0) tile_len[tile] = s_len;
     }
     if (counts) {
-        __shared__ unsigned long long s_evals, s_staged;
-        if (threadIdx.x == 0) s_evals = s_staged = 0;
+        __shared__ unsigned long long s_evals, s_staged, s_steps;
+        if (threadIdx.x == 0) s_evals = s_staged = s_steps = 0;
         __syncthreads();
         atomicAdd(&s_evals, (unsigned long long)evals);
         atomicAdd(&s_staged, (unsigned long long)staged);
+        if (STEPS && lane == 0) atomicAdd(&s_steps, (unsigned long long)wsteps);
         __syncthreads();
         if (threadIdx.x == 0) {
             atomicAdd(&counts[GSN_COUNT_FWD_EVALS], s_evals);
             atomicAdd(&counts[GSN_COUNT_FWD_STAGED], s_staged);
+            atomicAdd(&counts[GSN_COUNT_FWD_WAVE_STEPS], s_steps);
         }
     }
     if (inside) {
@@ -1131,14 +1141,13 @@ void launch_tile_order(const uint2* ranges, const uint32_t* lens, int tiles, uin
 
 void launch_raster_fwd(const uint2* ranges, const uint32_t* order, const uint32_t* ids, const float4* rec, uint32_t n, const DevCam& cam,
                        const DevRenderOpts& ro, bool fp32, float* img, double* img64, float* Tfin, uint32_t* ncontrib,
-                       uint64_t* masks, uint32_t* tile_len, unsigned long long* counts, hipStream_t s) {
+                       uint64_t* masks, uint32_t* tile_len, unsigned long long* counts, bool steps, hipStream_t s) {
     const int tiles = cam.tiles_x * cam.tiles_y;
-    if (fp32)
-        raster_fwd_kernel<float><<<tiles, GSN_BLOCK, 0, s>>>(ranges, order, ids, rec, n, cam, ro, img, nullptr, Tfin,
-                                                             ncontrib, masks, tile_len, counts);
-    else
-        raster_fwd_kernel<double><<<tiles, GSN_BLOCK, 0, s>>>(ranges, order, ids, rec, n, cam, ro, img, img64, Tfin,
-                                                              ncontrib, masks, tile_len, counts);
+    steps = steps && counts;
+    auto kern = fp32 ? (steps ? raster_fwd_kernel<float, true> : raster_fwd_kernel<float, false>)
+                     : (steps ? raster_fwd_kernel<double, true> : raster_fwd_kernel<double, false>);
+    kern<<<tiles, GSN_BLOCK, 0, s>>>(ranges, order, ids, rec, n, cam, ro, img, fp32 ? nullptr : img64, Tfin, ncontrib,
+                                     masks, tile_len, counts);
 }
 
 void launch_downsample2x(const float* src, int W, int H, float* dst, hipStream_t s) {

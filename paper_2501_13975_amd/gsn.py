@@ -414,7 +414,7 @@ class Context:
                  "bwd_staged")
                 + tuple(f"escalated_{g}" for g in GROUPS4) + tuple(f"fallback_{g}" for g in GROUPS4)
                 + tuple(f"clamped_{g}" for g in ("position", "rotation", "scaling", "colour"))
-                + ("solved", "opacity_bound"))
+                + ("solved", "opacity_bound", "fwd_wave_steps", "bwd_wave_steps"))
 
     def sync_status(self):
         """gsn_sync_status: (status code, {counter: value}, message); synchronises the stream and clears
@@ -438,8 +438,9 @@ class Context:
         self._check(st)
         return SolveGraph(self, h)
 
-    def profile_enable(self, on=True):
-        self._check(lib().gsn_profile_enable(self.h, int(bool(on))))
+    def profile_enable(self, on=True, steps=False):
+        """steps: also count the raster passes' wave steps (profiling level 2, slower rasters)."""
+        self._check(lib().gsn_profile_enable(self.h, (2 if steps else 1) if on else 0))
 
     def profile_read(self):
         """{stage: (ms, launches)}, {counter: value}; synchronises the stream."""
