@@ -775,6 +775,7 @@ __global__ __launch_bounds__(GSN_BLOCK, 6) void raster_fwd_kernel(
     uint32_t* __restrict__ ncontrib, uint64_t* __restrict__ masks, uint32_t* __restrict__ tile_len,
     unsigned long long* __restrict__ counts) {
     constexpr int NW = GSN_BLOCK / 64;
+    static_assert(NW == 4, "the composited-entry words below assume four waves");
     __shared__ float4 s_a[GSN_BLOCK];
     __shared__ float4 s_b[GSN_BLOCK];
     __shared__ float4 s_c[GSN_BLOCK];
@@ -859,7 +860,8 @@ __global__ __launch_bounds__(GSN_BLOCK, 6) void raster_fwd_kernel(
         for (int w = 0; w < NW; ++w) bits[w] = 0ull;
         uint32_t i = 0;
         for (; i < nl && !done; ++i) {
-            const int j = s_list[wave][i];
+            // the wave's lanes walk its band list together: the entry is the same in every lane
+            const int j = __builtin_amdgcn_readfirstlane((int)s_list[wave][i]);
             const float4 a = s_a[j], b = s_b[j], cc = s_c[j];
             const SplatEval ev = eval_splat(a, b, cc, fpx, fpy, ro.alpha_max);
             ++evals;
@@ -876,9 +878,11 @@ __global__ __launch_bounds__(GSN_BLOCK, 6) void raster_fwd_kernel(
                 C2 += w * (CT)cc.y;
                 T = Tn;
                 last = base + j + 1 - rg.x;
+                // word and bit are uniform across the wave: the selects are scalar, the ors plain
+                const uint64_t bit = 1ull << (j & 63);
+                const int q = j >> 6;
 #pragma unroll
-                for (int q = 0; q < NW; ++q)
-                    if ((j >> 6) == q) bits[q] |= 1ull << (j & 63);
+                for (int w = 0; w < NW; ++w) bits[w] |= q == w ? bit : 0ull;
             }
         }
         if (STEPS) {  // the wave walks as far as its longest lane
