@@ -244,10 +244,10 @@ gsn_status gsn_accumulate_hessian(gsn_ctx* ctx, const gsn_gaussians* g, const gs
 /* The views of one sweep (Sec. 4.3: the primary target and its secondary targets) rendered and
  * accumulated together: for i = 0..n_views-1, gsn_render of cams[i] into frames[i] followed by
  * gsn_accumulate_hessian of d_targets[i] into slot first_slot + i, with results identical bit
- * for bit to those calls made one after another.  The views' work is spread over four streams of
- * the library's own (default priority), forked from the context's stream and joined back into it
- * before the call returns, so that a view's projection, sort, rasters and loss maps overlap the
- * others'; each view's additions into the rows summed over the views wait for the previous
+ * for bit to those calls made one after another.  The views take in turn the context's stream and
+ * three streams of the library's own (default priority), forked from the context's stream and
+ * joined back into it before the call returns, so that a view's projection, sort, rasters and loss
+ * maps overlap the others'; each view's additions into the rows summed over the views wait for the previous
  * view's, and a secondary slot's per-kernel sums wait for the primary's coverage row when slot 0
  * is among the views.  With the profiler on (gsn_profile_enable) the views run one after another
  * on the context's stream.  The frames must be distinct; reserved frames (gsn_frame_reserve)

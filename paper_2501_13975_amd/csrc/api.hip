@@ -301,7 +301,8 @@ gsn_status gsn_frame_destroy(gsn_ctx* ctx, gsn_frame* f) {
     DevBuf* all[] = {&f->rec, &f->rect, &f->depth_key, &f->ntiles, &f->ids_a, &f->ids_b, &f->keys_a, &f->keys_b,
                      &f->offsets, &f->pair_off, &f->nsup, &f->moffs, &f->pk_a, &f->pv_a, &f->pk_b, &f->pv_b, &f->sranges,
                      &f->seg_base, &f->seg_counts, &f->seg_offs, &f->partial, &f->flags, &f->kflag,
-                     &f->ranges, &f->img, &f->img64, &f->Tfin, &f->ncontrib, &f->dL, &f->hd, &f->coef, &f->zsum, &f->zstats,
+                     &f->ranges, &f->img, &f->img64, &f->Tfin, &f->ncontrib, &f->dL, &f->hd, &f->coef, &f->zsum,
+                     &f->sumrows, &f->contrib, &f->zstats,
                      &f->loss_part, &f->hist, &f->scan_tmp, &f->total, &f->masks, &f->tile_order, &f->tile_len, &f->bwd_order};
     for (DevBuf* b : all) buf_free(*b);
     if (f->h_total) (void)hipHostFree(f->h_total);
@@ -324,6 +325,8 @@ static hipError_t frame_buffers(gsn_frame* f, int n, int W, int H, size_t pairs)
     if (e == hipSuccess) e = buf_reserve(f->offsets, (nn + 1) * 4);
     if (e == hipSuccess) e = buf_reserve(f->kflag, (nn + 3) / 4 * 4);
     if (e == hipSuccess) e = buf_reserve(f->zsum, nn * GSN_NZ * 8);
+    if (e == hipSuccess) e = buf_reserve(f->sumrows, nn * (kSumOverlap + 1) * 4);
+    if (e == hipSuccess) e = buf_reserve(f->contrib, (nn + 3) / 4 * 4);
     if (e == hipSuccess) e = buf_reserve(f->ranges, tiles * sizeof(uint2));
     DevBuf* per_tile4[] = {&f->tile_order, &f->tile_len, &f->bwd_order};
     for (DevBuf* b : per_tile4)
@@ -497,11 +500,12 @@ gsn_status gsn_render(gsn_ctx* ctx, const gsn_gaussians* g, const gsn_camera* ca
 }
 
 // gsn_accumulate_hessian on the context's current stream.  When not null, wait_reduce is waited for
-// before the view's per-kernel sums (a secondary slot reads the primary coverage row), wait_chain
-// before its additions into the blocks, and done_chain is recorded after them.
+// before the view's per-kernel sums (a secondary slot reads the primary coverage row) and done_reduce
+// is recorded after them; with sum_now the view's shares of the rows summed over the views are added
+// to the blocks at once (else the caller adds them, gsn_accumulate_views after all its views).
 static gsn_status accumulate_impl(gsn_ctx* ctx, const gsn_gaussians* g, const gsn_frame* fc, const float* d_target,
                                   const gsn_loss_opts* opts, int32_t view_slot, gsn_blocks* b, double* d_loss_out,
-                                  hipEvent_t wait_reduce, hipEvent_t wait_chain, hipEvent_t done_chain) {
+                                  hipEvent_t wait_reduce, hipEvent_t done_reduce, bool sum_now) {
     if (!ctx || !fc || !opts || !b || !d_target) return fail(ctx, GSN_E_INVALID, "null argument");
     gsn_frame* f = const_cast<gsn_frame*>(fc);
     gsn_status st = check_gaussians(ctx, g);
@@ -531,6 +535,8 @@ static gsn_status accumulate_impl(gsn_ctx* ctx, const gsn_gaussians* g, const gs
         HIP_TRY(ctx, hipGetLastError());
     }
     HIP_TRY(ctx, buf_reserve(f->zsum, (size_t)std::max(f->n, 1) * GSN_NZ * 8));
+    HIP_TRY(ctx, buf_reserve(f->sumrows, (size_t)std::max(f->n, 1) * (kSumOverlap + 1) * 4));
+    HIP_TRY(ctx, buf_reserve(f->contrib, ((size_t)std::max(f->n, 1) + 3) / 4 * 4));
     float* zs = nullptr;
     if (opts->keep_zstats) {
         HIP_TRY(ctx, buf_reserve(f->zstats, (size_t)std::max(f->n, 1) * GSN_NZ * 4));
@@ -546,9 +552,15 @@ static gsn_status accumulate_impl(gsn_ctx* ctx, const gsn_gaussians* g, const gs
         StageTimer st_(ctx, GSN_STAGE_CHAIN);
         if (wait_reduce) HIP_TRY(ctx, hipStreamWaitEvent(s, wait_reduce, 0));
         launch_reduce_pairs(*f, *g, view_slot, opts->precision == 1, *b, s);
-        if (wait_chain && wait_chain != wait_reduce) HIP_TRY(ctx, hipStreamWaitEvent(s, wait_chain, 0));
+        if (done_reduce) HIP_TRY(ctx, hipEventRecord(done_reduce, s));
         launch_chain(*f, *g, opts->weight, view_slot, opts->gauss_newton != 0, opts->precision == 1, *b, zs, s);
-        if (done_chain) HIP_TRY(ctx, hipEventRecord(done_chain, s));
+        if (sum_now) {
+            SumViews sv{};
+            sv.count = 1;
+            sv.rows[0] = bp<float>(f->sumrows);
+            sv.contrib[0] = bp<uint8_t>(f->contrib);
+            launch_sum_views(*b, sv, s);
+        }
     }
     HIP_TRY(ctx, hipGetLastError());
     return GSN_OK;
@@ -556,7 +568,7 @@ static gsn_status accumulate_impl(gsn_ctx* ctx, const gsn_gaussians* g, const gs
 
 gsn_status gsn_accumulate_hessian(gsn_ctx* ctx, const gsn_gaussians* g, const gsn_frame* fc, const float* d_target,
                                   const gsn_loss_opts* opts, int32_t view_slot, gsn_blocks* b, double* d_loss_out) {
-    return accumulate_impl(ctx, g, fc, d_target, opts, view_slot, b, d_loss_out, nullptr, nullptr, nullptr);
+    return accumulate_impl(ctx, g, fc, d_target, opts, view_slot, b, d_loss_out, nullptr, nullptr, true);
 }
 
 gsn_status gsn_accumulate_views(gsn_ctx* ctx, const gsn_gaussians* g, int32_t n_views, int32_t first_slot,
@@ -581,28 +593,30 @@ gsn_status gsn_accumulate_views(gsn_ctx* ctx, const gsn_gaussians* g, int32_t n_
             gsn_status r = gsn_render(ctx, g, &cams[i], ro, frames[i], nullptr, nullptr);
             if (r == GSN_OK)
                 r = accumulate_impl(ctx, g, frames[i], d_targets[i], lo, first_slot + i, b, loss ? loss + 2 * i : nullptr,
-                                    nullptr, nullptr, nullptr);
+                                    nullptr, nullptr, true);
             if (r != GSN_OK) return r;
         }
         return GSN_OK;
     }
     hipStream_t home = ctx->stream;
-    const int used = std::min(n_views, gsn_ctx::kSide);
+    // view i goes to stream i % 4: the context's stream, then the side streams
+    auto stream_of = [&](int i) { return i % (gsn_ctx::kSide + 1) == 0 ? home : ctx->side[i % (gsn_ctx::kSide + 1) - 1]; };
+    const int used = std::min(n_views - 1, gsn_ctx::kSide);
     HIP_TRY(ctx, hipEventRecord(ctx->ev_fork, home));
     for (int k = 0; k < used; ++k) HIP_TRY(ctx, hipStreamWaitEvent(ctx->side[k], ctx->ev_fork, 0));
     gsn_status r = GSN_OK;
     // every view's render is issued before any accumulation, so that every stream has work early
     for (int i = 0; i < n_views && r == GSN_OK; ++i) {
-        ctx->stream = ctx->side[i % gsn_ctx::kSide];
+        ctx->stream = stream_of(i);
         r = gsn_render(ctx, g, &cams[i], ro, frames[i], nullptr, nullptr);
     }
     for (int i = 0; i < n_views && r == GSN_OK; ++i) {
-        ctx->stream = ctx->side[i % gsn_ctx::kSide];
-        // the primary's sums and additions come first; each later view adds after the one before it
+        ctx->stream = stream_of(i);
+        // a secondary view's sums wait for the primary's coverage row when the primary is among the views
         hipEvent_t wait_reduce = (first_slot == 0 && i > 0) ? ctx->ev_chain[0] : nullptr;
-        hipEvent_t wait_chain = i > 0 ? ctx->ev_chain[i - 1] : nullptr;
+        hipEvent_t done_reduce = (first_slot == 0 && i == 0) ? ctx->ev_chain[0] : nullptr;
         r = accumulate_impl(ctx, g, frames[i], d_targets[i], lo, first_slot + i, b, loss ? loss + 2 * i : nullptr,
-                            wait_reduce, wait_chain, ctx->ev_chain[i]);
+                            wait_reduce, done_reduce, false);
     }
     // join every stream that took work, also after a failure, so that later calls stay ordered
     ctx->stream = home;
@@ -610,6 +624,19 @@ gsn_status gsn_accumulate_views(gsn_ctx* ctx, const gsn_gaussians* g, int32_t n_
         const hipError_t e1 = hipEventRecord(ctx->ev_join[k], ctx->side[k]);
         const hipError_t e2 = e1 == hipSuccess ? hipStreamWaitEvent(home, ctx->ev_join[k], 0) : e1;
         if (e2 != hipSuccess && r == GSN_OK) r = fail(ctx, GSN_E_HIP, "joining the view streams: %s", hipGetErrorString(e2));
+    }
+    if (r == GSN_OK) {
+        // the views' shares of the summed rows, added in view order: the additions of the same calls
+        // made one after another
+        SumViews sv{};
+        sv.count = n_views;
+        for (int i = 0; i < n_views; ++i) {
+            sv.rows[i] = bp<float>(frames[i]->sumrows);
+            sv.contrib[i] = bp<uint8_t>(frames[i]->contrib);
+        }
+        StageTimer st_(ctx, GSN_STAGE_CHAIN);
+        launch_sum_views(*b, sv, home);
+        HIP_TRY(ctx, hipGetLastError());
     }
     return r;
 }

@@ -527,6 +527,7 @@ __global__ __launch_bounds__(256) void reduce_pairs_kernel(int n, const uint2* _
                                                            const uint8_t* __restrict__ flags,
                                                            const uint8_t* __restrict__ kflag,
                                                            const float* __restrict__ primary_cov,
+                                                           float* __restrict__ cov_out,
                                                            double* __restrict__ zsum) {
     const int lane = __lane_id();
     const int k0 = (blockIdx.x * (blockDim.x / 64) + threadIdx.x / 64) * 64;
@@ -574,6 +575,8 @@ __global__ __launch_bounds__(256) void reduce_pairs_kernel(int n, const uint2* _
             }
         }
         if (lane < GSN_NZ) zsum[(size_t)k * GSN_NZ + lane] = (double)acc;
+        // the primary view's coverage row of the blocks, which the secondary views' sums read
+        if (cov_out && lane == GSN_ZCOV) cov_out[k] = (float)(double)acc;
     }
 }
 
@@ -597,10 +600,14 @@ template <bool GN>
 __global__ __launch_bounds__(128) void chain_pos_kernel(
     const float* __restrict__ pos, const float* __restrict__ rot, const float* __restrict__ scale,
     const float* __restrict__ sh, int n, int K, const double* __restrict__ zsum, const float4* __restrict__ rec,
-    DevCam cam, float kappa, float weight, int slot, int V, float* __restrict__ blk, float* __restrict__ zstats) {
+    DevCam cam, float kappa, float weight, int slot, float* __restrict__ blk, float* __restrict__ sr,
+    uint8_t* __restrict__ contrib, float* __restrict__ zstats) {
     const int k = blockIdx.x * blockDim.x + threadIdx.x;
     if (k >= n) return;
-    if (!(zsum[(size_t)k * GSN_NZ + GSN_ZCOV] > 0.0)) {  // no pixel of this view composited the kernel
+    const double cov = zsum[(size_t)k * GSN_NZ + GSN_ZCOV];
+    const bool adds = cov > 0.0 && (float)cov > 0.f;
+    contrib[k] = adds ? 1 : 0;
+    if (!(cov > 0.0)) {  // no pixel of this view composited the kernel
         if (zstats) {
 #pragma unroll
             for (int f = 0; f < GSN_NZ; ++f) zstats[(size_t)f * n + k] = 0.f;
@@ -621,7 +628,7 @@ __global__ __launch_bounds__(128) void chain_pos_kernel(
 #pragma unroll
         for (int f = 0; f < GSN_NZ; ++f) zstats[(size_t)f * n + k] = z[f];
     }
-    if (!(z[GSN_ZCOV] > 0.f)) return;
+    if (!adds) return;
     KParams kp;
     load_kparams(pos, rot, scale, rec, n, k, kp);
     const size_t N = (size_t)n;
@@ -629,13 +636,12 @@ __global__ __launch_bounds__(128) void chain_pos_kernel(
         float g[3], H[6];
         chain_position(kp, sh + k, N, K, cam, kappa, z, GN, g, H);
 #pragma unroll
-        for (int a = 0; a < 3; ++a) blk[a * N + k] += weight * g[a];
+        for (int a = 0; a < 3; ++a) sr[a * N + k] = weight * g[a];
 #pragma unroll
-        for (int a = 0; a < 6; ++a) blk[(3 + a) * N + k] += weight * H[a];
+        for (int a = 0; a < 6; ++a) sr[(3 + a) * N + k] = weight * H[a];
     }
-    blk[27 * N + k] += weight * z[5];
-    blk[28 * N + k] += weight * z[42];
-    if (slot == 0) blk[29 * N + k] = z[GSN_ZCOV];
+    sr[27 * N + k] = weight * z[5];
+    sr[28 * N + k] = weight * z[42];
     const size_t vb = GSN_BLK_BASE + (size_t)GSN_BLK_VIEW * slot;
     const float dx = kp.p[0] - cam.o[0], dy = kp.p[1] - cam.o[1], dz = kp.p[2] - cam.o[2];
     const float il = 1.0f / sqrtf(dx * dx + dy * dy + dz * dz);
@@ -648,8 +654,8 @@ __global__ __launch_bounds__(128) void chain_pos_kernel(
     blk[(vb + 7) * N + k] = dy * il;
     blk[(vb + 8) * N + k] = dz * il;
     blk[(vb + 9) * N + k] = z[GSN_ZCOV];
-    // the sum over the views of sum (alpha T)^2, after the view slots (the overlap share's numerator)
-    blk[(GSN_BLK_BASE + (size_t)GSN_BLK_VIEW * V) * N + k] += weight * z[GSN_ZW2];
+    // this view's share of the sum over the views of sum (alpha T)^2 (the overlap share's numerator)
+    sr[(size_t)kSumOverlap * N + k] = weight * z[GSN_ZW2];
 }
 
 // One thread per kernel: rotation and scale blocks, in double from the double sums of the
@@ -658,11 +664,11 @@ template <bool GN, class Re>
 __global__ __launch_bounds__(128) void chain_rs_kernel(
     const float* __restrict__ pos, const float* __restrict__ rot, const float* __restrict__ scale, int n,
     const double* __restrict__ zsum, const float4* __restrict__ rec, DevCam cam, float kappa, float weight,
-    float* __restrict__ blk) {
+    float* __restrict__ sr) {
     const int k = blockIdx.x * blockDim.x + threadIdx.x;
     if (k >= n) return;
     const double* zk = zsum + (size_t)k * GSN_NZ;
-    if (!(zk[GSN_ZCOV] > 0.0)) return;
+    if (!(zk[GSN_ZCOV] > 0.0 && (float)zk[GSN_ZCOV] > 0.f)) return;  // the gate of chain_pos_kernel
     Re gq[3], Hq[3][3];
     q_stats(zk, gq, Hq);
     KParams kp;
@@ -671,14 +677,34 @@ __global__ __launch_bounds__(128) void chain_rs_kernel(
     Re g[3], H[6];
     chain_rotation(kp, cam, kappa, gq, Hq, GN, g, H);
 #pragma unroll
-    for (int a = 0; a < 3; ++a) blk[(9 + a) * N + k] += (float)((Re)weight * g[a]);
+    for (int a = 0; a < 3; ++a) sr[(9 + a) * N + k] = (float)((Re)weight * g[a]);
 #pragma unroll
-    for (int a = 0; a < 6; ++a) blk[(12 + a) * N + k] += (float)((Re)weight * H[a]);
+    for (int a = 0; a < 6; ++a) sr[(12 + a) * N + k] = (float)((Re)weight * H[a]);
     chain_scale(kp, cam, kappa, gq, Hq, GN, g, H);
 #pragma unroll
-    for (int a = 0; a < 3; ++a) blk[(18 + a) * N + k] += (float)((Re)weight * g[a]);
+    for (int a = 0; a < 3; ++a) sr[(18 + a) * N + k] = (float)((Re)weight * g[a]);
 #pragma unroll
-    for (int a = 0; a < 6; ++a) blk[(21 + a) * N + k] += (float)((Re)weight * H[a]);
+    for (int a = 0; a < 6; ++a) sr[(21 + a) * N + k] = (float)((Re)weight * H[a]);
+}
+
+// Adds the views' shares of the rows summed over the views (position, rotation, scaling, opacity,
+// the overlap numerator) to the blocks, view after view in the order given, for the kernels each view
+// reached: the same additions, in the same order, whether the views were accumulated one call at a
+// time or together.
+__global__ void sum_views_kernel(float* __restrict__ blk, int n, int V, SumViews sv) {
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= n) return;
+    const size_t N = (size_t)n;
+    bool any = false;
+    for (int v = 0; v < sv.count; ++v) any |= sv.contrib[v][k] != 0;
+    if (!any) return;
+    for (int r = 0; r <= kSumOverlap; ++r) {
+        const size_t row = r < kSumOverlap ? (size_t)r : (size_t)GSN_BLK_BASE + (size_t)GSN_BLK_VIEW * V;
+        float a = blk[row * N + k];
+        for (int v = 0; v < sv.count; ++v)
+            if (sv.contrib[v][k]) a += sv.rows[v][(size_t)r * N + k];
+        blk[row * N + k] = a;
+    }
 }
 
 }  // namespace
@@ -705,9 +731,14 @@ void launch_reduce_pairs(const gsn_frame& f, const gsn_gaussians& g, int slot, b
                          hipStream_t s) {
     if (g.n == 0) return;
     auto red_k = fp32 ? reduce_pairs_kernel<float> : reduce_pairs_kernel<double>;
+    float* cov = b.d_data + (size_t)29 * g.n;
     red_k<<<(g.n + 255) / 256, 256, 0, s>>>(g.n, bp<uint2>(f.rect), bp<uint32_t>(f.pair_off), bp<float>(f.partial),
-                                            bp<uint8_t>(f.flags), bp<uint8_t>(f.kflag),
-                                            slot > 0 ? b.d_data + (size_t)29 * g.n : nullptr, bp<double>(f.zsum));
+                                            bp<uint8_t>(f.flags), bp<uint8_t>(f.kflag), slot > 0 ? cov : nullptr,
+                                            slot == 0 ? cov : nullptr, bp<double>(f.zsum));
+}
+
+void launch_sum_views(const gsn_blocks& b, const SumViews& sv, hipStream_t s) {
+    if (b.n > 0 && sv.count > 0) sum_views_kernel<<<(b.n + 255) / 256, 256, 0, s>>>(b.d_data, b.n, b.n_views, sv);
 }
 
 void launch_chain(const gsn_frame& f, const gsn_gaussians& g, float weight, int slot, bool gauss_newton, bool fp32,
@@ -718,8 +749,8 @@ void launch_chain(const gsn_frame& f, const gsn_gaussians& g, float weight, int 
     auto rs_k = gauss_newton ? (fp32 ? chain_rs_kernel<true, float> : chain_rs_kernel<true, double>)
                              : (fp32 ? chain_rs_kernel<false, float> : chain_rs_kernel<false, double>);
     pos_k<<<(g.n + 127) / 128, 128, 0, s>>>(g.d_pos, g.d_rot, g.d_scale, g.d_sh, g.n, K, bp<double>(f.zsum),
-                                            bp<float4>(f.rec), f.cam, f.ro.kappa, weight, slot, b.n_views, b.d_data,
-                                            zstats_out);
+                                            bp<float4>(f.rec), f.cam, f.ro.kappa, weight, slot, b.d_data,
+                                            bp<float>(f.sumrows), bp<uint8_t>(f.contrib), zstats_out);
     rs_k<<<(g.n + 127) / 128, 128, 0, s>>>(g.d_pos, g.d_rot, g.d_scale, g.n, bp<double>(f.zsum), bp<float4>(f.rec),
-                                           f.cam, f.ro.kappa, weight, b.d_data);
+                                           f.cam, f.ro.kappa, weight, bp<float>(f.sumrows));
 }

@@ -74,6 +74,8 @@ struct gsn_frame {
     DevBuf dL, hd;      // float [3][H][W] loss maps
     DevBuf coef;        // float [3][8][H][W] SSIM coefficient maps (computed in double, stored rounded)
     DevBuf zsum;        // double [n][GSN_NZ] per-kernel sums of the pair partials
+    DevBuf sumrows;     // float [kSumOverlap + 1][n]: this view's shares of the rows summed over the views
+    DevBuf contrib;     // u8 [n]: the kernel has shares in sumrows (the view reached it)
     DevBuf zstats;      // float [GSN_NZ][n], optional debug copy
     DevBuf loss_part;   // double [2][nblocks]
     // sort / scan scratch; total: u32 [0] scanned pair total, [1] live pair count of the render,
@@ -112,9 +114,10 @@ struct gsn_ctx {
     // the library's own stream, in place of the caller's
     bool capturing = false, capture_failed = false;
     hipStream_t cap_stream = nullptr, user_stream = nullptr;
-    // gsn_accumulate_views: the library's own streams the views are spread over (forked from and
-    // joined back into the context's stream), and the events that order them
-    static constexpr int kSide = 4, kMaxViews = 9;
+    // gsn_accumulate_views: the context's stream and three of the library's own take the views in
+    // turn (the side streams forked from and joined back into the context's stream; four streams in
+    // all, as many as the device gives a process hardware queues), and the events that order them
+    static constexpr int kSide = 3, kMaxViews = 9;
     hipStream_t side[kSide] = {};
     hipEvent_t ev_fork = nullptr, ev_join[kSide] = {}, ev_chain[kMaxViews] = {};
 };
@@ -208,7 +211,18 @@ void launch_loss_reduce(const double* part, int nparts, int W, int H, double* ou
 // ---- launchers (backward.hip)
 void launch_raster_bwd(const gsn_frame& f, const float* dL, const float* hd, bool gauss_newton,
                        unsigned long long* counts, bool steps, hipStream_t s);
-// per-kernel sums of a view's (tile, kernel) partials (a secondary slot reads the primary coverage row)
+// Rows of the blocks summed over the views: 0..28 (position, rotation, scaling, opacity), then the
+// overlap numerator (row kSumOverlap of a frame's sumrows, row GSN_BLK_BASE + GSN_BLK_VIEW V of the blocks).
+constexpr int kSumOverlap = 29;
+struct SumViews {
+    int count;
+    const float* rows[9];
+    const uint8_t* contrib[9];
+};
+// adds the views' shares (sumrows of each frame, in the order given) to the blocks
+void launch_sum_views(const gsn_blocks& b, const SumViews& sv, hipStream_t s);
+// per-kernel sums of a view's (tile, kernel) partials (a secondary slot reads the primary coverage row,
+// the primary's writes it)
 void launch_reduce_pairs(const gsn_frame& f, const gsn_gaussians& g, int slot, bool fp32, const gsn_blocks& b,
                          hipStream_t s);
 // the chain rule from those sums into the blocks (adds to the rows summed over the views)
