@@ -695,16 +695,26 @@ __global__ void sum_views_kernel(float* __restrict__ blk, int n, int V, SumViews
     const int k = blockIdx.x * blockDim.x + threadIdx.x;
     if (k >= n) return;
     const size_t N = (size_t)n;
-    bool any = false;
-    for (int v = 0; v < sv.count; ++v) any |= sv.contrib[v][k] != 0;
-    if (!any) return;
-    for (int r = 0; r <= kSumOverlap; ++r) {
-        const size_t row = r < kSumOverlap ? (size_t)r : (size_t)GSN_BLK_BASE + (size_t)GSN_BLK_VIEW * V;
-        float a = blk[row * N + k];
-        for (int v = 0; v < sv.count; ++v)
-            if (sv.contrib[v][k]) a += sv.rows[v][(size_t)r * N + k];
-        blk[row * N + k] = a;
+    uint32_t mask = 0;
+    for (int v = 0; v < sv.count; ++v) mask |= (sv.contrib[v][k] != 0 ? 1u : 0u) << v;
+    if (!mask) return;
+    // every row is loaded before any store (the views' rows and the blocks are separate arrays)
+    constexpr int NR = kSumOverlap + 1;
+    const size_t over = (size_t)GSN_BLK_BASE + (size_t)GSN_BLK_VIEW * V;
+    float a[NR];
+#pragma unroll
+    for (int r = 0; r < NR; ++r) a[r] = blk[(r < kSumOverlap ? (size_t)r : over) * N + k];
+    for (int v = 0; v < sv.count; ++v) {
+        if (!((mask >> v) & 1u)) continue;
+        const float* __restrict__ src = sv.rows[v];
+        float t[NR];
+#pragma unroll
+        for (int r = 0; r < NR; ++r) t[r] = src[(size_t)r * N + k];
+#pragma unroll
+        for (int r = 0; r < NR; ++r) a[r] += t[r];
     }
+#pragma unroll
+    for (int r = 0; r < NR; ++r) blk[(r < kSumOverlap ? (size_t)r : over) * N + k] = a[r];
 }
 
 }  // namespace
