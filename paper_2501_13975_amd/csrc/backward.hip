@@ -41,6 +41,8 @@ namespace {
 constexpr int PMAX = 896;   // composited (pixel, entry) pairs staged per round
 constexpr int BIG = 64;     // entries with more pairs are summed by LG lanes, others by SG
 constexpr int SG = 8, LG = 32;
+// statistics a pair adds to (0 .. GSN_ZW2); the rest of the GSN_NZ words are padding, kept zero
+constexpr int kLiveZ = GSN_ZW2 + 1;
 
 // Contribution of one active (pixel, splat) pair to the 44 statistics (see the header comment).
 template <bool GN>
@@ -462,7 +464,7 @@ __global__ __launch_bounds__(GSN_BLOCK, 3) void raster_bwd_kernel(
                                                ro.alpha_max, acc);
                         }
 #pragma unroll
-                        for (int f = 0; f < GSN_NZ; ++f) acc[f] = group_sum<LG>(acc[f]);
+                        for (int f = 0; f < kLiveZ; ++f) acc[f] = group_sum<LG>(acc[f]);
                         if (k < nlarge && r == group_writer<LG>()) {
                             write_partial(partial, flags, r_slot[e], acc);
                             kflag[r_id[e]] = 1;
@@ -480,7 +482,7 @@ __global__ __launch_bounds__(GSN_BLOCK, 3) void raster_bwd_kernel(
                                                ro.alpha_max, acc);
                         }
 #pragma unroll
-                        for (int f = 0; f < GSN_NZ; ++f) acc[f] = group_sum<SG>(acc[f]);
+                        for (int f = 0; f < kLiveZ; ++f) acc[f] = group_sum<SG>(acc[f]);
                         if (k < nsmall && r == group_writer<SG>()) {
                             write_partial(partial, flags, r_slot[e], acc);
                             kflag[r_id[e]] = 1;
