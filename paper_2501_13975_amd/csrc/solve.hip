@@ -701,7 +701,7 @@ __global__ __launch_bounds__(128) void solve_mixed_kernel(const float* __restric
 }
 
 template <int VM>
-__global__ __launch_bounds__(128) void solve_kernel(const float* __restrict__ pos, const float* __restrict__ rot,
+__global__ __launch_bounds__(128, 3) void solve_kernel(const float* __restrict__ pos, const float* __restrict__ rot,
                                                      const float* __restrict__ scale, const float* __restrict__ opac,
                                                      int n, int K, DevCam c, float kappa,
                                                      const float* __restrict__ blk, int V, gsn_solve_opts o,
