@@ -302,7 +302,7 @@ gsn_status gsn_frame_destroy(gsn_ctx* ctx, gsn_frame* f) {
                      &f->offsets, &f->pair_off, &f->nsup, &f->moffs, &f->pk_a, &f->pv_a, &f->pk_b, &f->pv_b, &f->sranges,
                      &f->seg_base, &f->seg_counts, &f->seg_offs, &f->partial, &f->flags, &f->kflag,
                      &f->ranges, &f->img, &f->img64, &f->Tfin, &f->ncontrib, &f->dL, &f->hd, &f->coef, &f->zsum,
-                     &f->sumrows, &f->contrib, &f->zstats,
+                     &f->zsum_f, &f->sumrows, &f->contrib, &f->zstats,
                      &f->loss_part, &f->hist, &f->scan_tmp, &f->total, &f->masks, &f->tile_order, &f->tile_len, &f->bwd_order};
     for (DevBuf* b : all) buf_free(*b);
     if (f->h_total) (void)hipHostFree(f->h_total);
@@ -324,7 +324,8 @@ static hipError_t frame_buffers(gsn_frame* f, int n, int W, int H, size_t pairs)
         if (e == hipSuccess) e = buf_reserve(*b, nn * 4);
     if (e == hipSuccess) e = buf_reserve(f->offsets, (nn + 1) * 4);
     if (e == hipSuccess) e = buf_reserve(f->kflag, (nn + 3) / 4 * 4);
-    if (e == hipSuccess) e = buf_reserve(f->zsum, nn * GSN_NZ * 8);
+    if (e == hipSuccess) e = buf_reserve(f->zsum_f, nn * GSN_NZ * 4);
+    if (e == hipSuccess) e = buf_reserve(f->zsum, nn * 10 * 8);
     if (e == hipSuccess) e = buf_reserve(f->sumrows, nn * (kSumOverlap + 1) * 4);
     if (e == hipSuccess) e = buf_reserve(f->contrib, (nn + 3) / 4 * 4);
     if (e == hipSuccess) e = buf_reserve(f->ranges, tiles * sizeof(uint2));
@@ -534,7 +535,8 @@ static gsn_status accumulate_impl(gsn_ctx* ctx, const gsn_gaussians* g, const gs
         if (d_loss_out) launch_loss_reduce(bp<double>(f->loss_part), np_out, f->W, f->H, d_loss_out, s);
         HIP_TRY(ctx, hipGetLastError());
     }
-    HIP_TRY(ctx, buf_reserve(f->zsum, (size_t)std::max(f->n, 1) * GSN_NZ * 8));
+    HIP_TRY(ctx, buf_reserve(f->zsum_f, (size_t)std::max(f->n, 1) * GSN_NZ * 4));
+    HIP_TRY(ctx, buf_reserve(f->zsum, (size_t)std::max(f->n, 1) * 10 * 8));
     HIP_TRY(ctx, buf_reserve(f->sumrows, (size_t)std::max(f->n, 1) * (kSumOverlap + 1) * 4));
     HIP_TRY(ctx, buf_reserve(f->contrib, ((size_t)std::max(f->n, 1) + 3) / 4 * 4));
     float* zs = nullptr;

@@ -43,6 +43,12 @@ constexpr int BIG = 64;     // entries with more pairs are summed by LG lanes, o
 constexpr int SG = 8, LG = 32;
 // statistics a pair adds to (0 .. GSN_ZW2); the rest of the GSN_NZ words are padding, kept zero
 constexpr int kLiveZ = GSN_ZW2 + 1;
+// The per-kernel sums the rotation and scale chain rule reads, kept in double: the conic gradient
+// (statistics 2..4), its Hessian (18..23, packed upper triangle) and the coverage.
+constexpr int kZq = 10, kZqCov = 9;
+__device__ __forceinline__ int zq_slot(int f) {
+    return (f >= 2 && f <= 4) ? f - 2 : (f >= 18 && f <= 23) ? f - 15 : f == GSN_ZCOV ? kZqCov : -1;
+}
 
 // Contribution of one active (pixel, splat) pair to the 44 statistics (see the header comment).
 template <bool GN>
@@ -530,7 +536,7 @@ __global__ __launch_bounds__(256) void reduce_pairs_kernel(int n, const uint2* _
                                                            const uint8_t* __restrict__ kflag,
                                                            const float* __restrict__ primary_cov,
                                                            float* __restrict__ cov_out,
-                                                           double* __restrict__ zsum) {
+                                                           float* __restrict__ zf, double* __restrict__ zq) {
     const int lane = __lane_id();
     const int k0 = (blockIdx.x * (blockDim.x / 64) + threadIdx.x / 64) * 64;
     if (k0 >= n) return;
@@ -538,7 +544,10 @@ __global__ __launch_bounds__(256) void reduce_pairs_kernel(int n, const uint2* _
     // primary) get a zero coverage, the others are summed one after another by the whole wave
     const int kl = k0 + lane;
     const bool has = kl < n && kflag[kl] != 0 && (!primary_cov || primary_cov[kl] > 0.f);
-    if (kl < n && !has) zsum[(size_t)kl * GSN_NZ + GSN_ZCOV] = 0.0;
+    if (kl < n && !has) {
+        zf[(size_t)kl * GSN_NZ + GSN_ZCOV] = 0.f;
+        zq[(size_t)kl * kZq + kZqCov] = 0.0;
+    }
     // every lane reads its own kernel's slot range up front (one coalesced load instead of a
     // dependent load per kernel); the wave then takes each kernel's range from its lane
     uint32_t my_nt = 0, my_off = 0;
@@ -576,7 +585,11 @@ __global__ __launch_bounds__(256) void reduce_pairs_kernel(int n, const uint2* _
                     if (t < cntv) acc += (Acc)v[t];
             }
         }
-        if (lane < GSN_NZ) zsum[(size_t)k * GSN_NZ + lane] = (double)acc;
+        // every statistic in single precision (192 contiguous bytes), and in double those the rotation and
+        // scale chain rule reads (the plain form's conic statistics and coverage)
+        if (lane < GSN_NZ) zf[(size_t)k * GSN_NZ + lane] = (float)(double)acc;
+        const int q = zq_slot(lane);
+        if (q >= 0) zq[(size_t)k * kZq + q] = (double)acc;
         // the primary view's coverage row of the blocks, which the secondary views' sums read
         if (cov_out && lane == GSN_ZCOV) cov_out[k] = (float)(double)acc;
     }
@@ -601,12 +614,13 @@ __device__ __forceinline__ void load_kparams(const float* __restrict__ pos, cons
 template <bool GN>
 __global__ __launch_bounds__(128) void chain_pos_kernel(
     const float* __restrict__ pos, const float* __restrict__ rot, const float* __restrict__ scale,
-    const float* __restrict__ sh, int n, int K, const double* __restrict__ zsum, const float4* __restrict__ rec,
+    const float* __restrict__ sh, int n, int K, const float* __restrict__ zf, const double* __restrict__ zq,
+    const float4* __restrict__ rec,
     DevCam cam, float kappa, float weight, int slot, float* __restrict__ blk, float* __restrict__ sr,
     uint8_t* __restrict__ contrib, float* __restrict__ zstats) {
     const int k = blockIdx.x * blockDim.x + threadIdx.x;
     if (k >= n) return;
-    const double cov = zsum[(size_t)k * GSN_NZ + GSN_ZCOV];
+    const double cov = zq[(size_t)k * kZq + kZqCov];
     const bool adds = cov > 0.0 && (float)cov > 0.f;
     contrib[k] = adds ? 1 : 0;
     if (!(cov > 0.0)) {  // no pixel of this view composited the kernel
@@ -618,12 +632,14 @@ __global__ __launch_bounds__(128) void chain_pos_kernel(
     }
     float z[GSN_NZ];
     {
-        const double2* zp = reinterpret_cast<const double2*>(zsum + (size_t)k * GSN_NZ);
+        const float4* zp = reinterpret_cast<const float4*>(zf + (size_t)k * GSN_NZ);
 #pragma unroll
-        for (int f = 0; f < GSN_NZ / 2; ++f) {
-            const double2 v = zp[f];
-            z[2 * f] = (float)v.x;
-            z[2 * f + 1] = (float)v.y;
+        for (int f = 0; f < GSN_NZ / 4; ++f) {
+            const float4 v = zp[f];
+            z[4 * f] = v.x;
+            z[4 * f + 1] = v.y;
+            z[4 * f + 2] = v.z;
+            z[4 * f + 3] = v.w;
         }
     }
     if (zstats) {
@@ -665,14 +681,14 @@ __global__ __launch_bounds__(128) void chain_pos_kernel(
 template <bool GN, class Re>
 __global__ __launch_bounds__(128) void chain_rs_kernel(
     const float* __restrict__ pos, const float* __restrict__ rot, const float* __restrict__ scale, int n,
-    const double* __restrict__ zsum, const float4* __restrict__ rec, DevCam cam, float kappa, float weight,
+    const double* __restrict__ zq, const float4* __restrict__ rec, DevCam cam, float kappa, float weight,
     float* __restrict__ sr) {
     const int k = blockIdx.x * blockDim.x + threadIdx.x;
     if (k >= n) return;
-    const double* zk = zsum + (size_t)k * GSN_NZ;
-    if (!(zk[GSN_ZCOV] > 0.0 && (float)zk[GSN_ZCOV] > 0.f)) return;  // the gate of chain_pos_kernel
+    const double* zk = zq + (size_t)k * kZq;
+    if (!(zk[kZqCov] > 0.0 && (float)zk[kZqCov] > 0.f)) return;  // the gate of chain_pos_kernel
     Re gq[3], Hq[3][3];
-    q_stats(zk, gq, Hq);
+    q_stats_packed(zk, gq, Hq);
     KParams kp;
     load_kparams(pos, rot, scale, rec, n, k, kp);
     const size_t N = (size_t)n;
@@ -746,7 +762,7 @@ void launch_reduce_pairs(const gsn_frame& f, const gsn_gaussians& g, int slot, b
     float* cov = b.d_data + (size_t)29 * g.n;
     red_k<<<(g.n + 255) / 256, 256, 0, s>>>(g.n, bp<uint2>(f.rect), bp<uint32_t>(f.pair_off), bp<float>(f.partial),
                                             bp<uint8_t>(f.flags), bp<uint8_t>(f.kflag), slot > 0 ? cov : nullptr,
-                                            slot == 0 ? cov : nullptr, bp<double>(f.zsum));
+                                            slot == 0 ? cov : nullptr, bp<float>(f.zsum_f), bp<double>(f.zsum));
 }
 
 void launch_sum_views(const gsn_blocks& b, const SumViews& sv, hipStream_t s) {
@@ -760,7 +776,8 @@ void launch_chain(const gsn_frame& f, const gsn_gaussians& g, float weight, int 
     auto pos_k = gauss_newton ? chain_pos_kernel<true> : chain_pos_kernel<false>;
     auto rs_k = gauss_newton ? (fp32 ? chain_rs_kernel<true, float> : chain_rs_kernel<true, double>)
                              : (fp32 ? chain_rs_kernel<false, float> : chain_rs_kernel<false, double>);
-    pos_k<<<(g.n + 127) / 128, 128, 0, s>>>(g.d_pos, g.d_rot, g.d_scale, g.d_sh, g.n, K, bp<double>(f.zsum),
+    pos_k<<<(g.n + 127) / 128, 128, 0, s>>>(g.d_pos, g.d_rot, g.d_scale, g.d_sh, g.n, K, bp<float>(f.zsum_f),
+                                            bp<double>(f.zsum),
                                             bp<float4>(f.rec), f.cam, f.ro.kappa, weight, slot, b.d_data,
                                             bp<float>(f.sumrows), bp<uint8_t>(f.contrib), zstats_out);
     rs_k<<<(g.n + 127) / 128, 128, 0, s>>>(g.d_pos, g.d_rot, g.d_scale, g.n, bp<double>(f.zsum), bp<float4>(f.rec),

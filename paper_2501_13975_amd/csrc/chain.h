@@ -184,6 +184,18 @@ GSN_HD inline void q_stats(const double* __restrict__ z, Re gz[3], Re Hz[3][3]) 
     }
 }
 
+// The same from the packed copy: zq[0..2] = statistics 2..4, zq[3..8] = statistics 18..23.
+template <class Re>
+GSN_HD inline void q_stats_packed(const double* __restrict__ zq, Re gz[3], Re Hz[3][3]) {
+    const int pk[3][3] = {{3, 4, 5}, {4, 6, 7}, {5, 7, 8}};
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+        gz[i] = (Re)zq[i];
+#pragma unroll
+        for (int j = 0; j < 3; ++j) Hz[i][j] = (Re)zq[pk[i][j]];
+    }
+}
+
 // The six quantities of Sigma = A A^T + kappa I that the conic needs are bilinear in A,
 // F(A) = B_f(A, A): the entries sxx, syy, sxy of A A^T and the three 2x2 minors of A
 // (Cauchy-Binet).  B_f(X, Y) for f = 0..5:

@@ -73,7 +73,8 @@ struct gsn_frame {
                         // the batch)
     DevBuf dL, hd;      // float [3][H][W] loss maps
     DevBuf coef;        // float [3][8][H][W] SSIM coefficient maps (computed in double, stored rounded)
-    DevBuf zsum;        // double [n][GSN_NZ] per-kernel sums of the pair partials
+    DevBuf zsum_f;      // float [n][GSN_NZ] per-kernel sums of the pair partials
+    DevBuf zsum;        // double [n][10]: of those, the ones the rotation and scale chain rule reads
     DevBuf sumrows;     // float [kSumOverlap + 1][n]: this view's shares of the rows summed over the views
     DevBuf contrib;     // u8 [n]: the kernel has shares in sumrows (the view reached it)
     DevBuf zstats;      // float [GSN_NZ][n], optional debug copy
