@@ -1050,7 +1050,7 @@ gsn_status gsn_step_labels(gsn_ctx* ctx, const gsn_steps* prim, const gsn_steps*
         return fail(ctx, GSN_E_INVALID, "null device array");
     HIP_TRY(ctx, hipSetDevice(ctx->device));
     const int K = (prim->sh_degree + 1) * (prim->sh_degree + 1);
-    if (d_alpha && d_err) HIP_TRY(ctx, buf_reserve(ctx->label_part, (size_t)2 * std::max(label_blocks(prim->n), 1) * 8));
+    if (d_alpha && d_err) HIP_TRY(ctx, buf_reserve(ctx->label_part, label_part_words(prim->n) * 8));
     launch_labels(prim->n, K, prim->d_data, prim->d_flags, aug->d_data, d_ok, d_alpha, d_label, d_mask,
                   bp<double>(ctx->label_part), d_err, ctx->stream);
     HIP_TRY(ctx, hipGetLastError());
@@ -1090,7 +1090,7 @@ gsn_status gsn_mlp_train_step(gsn_ctx* ctx, gsn_mlp* mlp, int32_t n, const float
     HIP_TRY(ctx, hipSetDevice(ctx->device));
     const int nb = std::max(mlp_grad_blocks(n), 1);
     HIP_TRY(ctx, buf_reserve(ctx->mlp_part, (size_t)nb * GSN_MLP_PARAMS * 4));
-    HIP_TRY(ctx, buf_reserve(ctx->mlp_stat, (size_t)nb * 2 * 8));
+    HIP_TRY(ctx, buf_reserve(ctx->mlp_stat, mlp_stat_words(n) * 8));
     mlp->step += 1;
     launch_mlp_train(*mlp, n, d_feat, d_label, d_mask, bp<float>(ctx->mlp_part), bp<double>(ctx->mlp_stat), *a,
                      d_grad, d_loss, ctx->stream);

@@ -269,6 +269,9 @@ void launch_features(const gsn_gaussians& g, const DevCam& cam, float kappa, con
                      const gsn_solve_opts& o, const float* resid, float* feat, uint8_t* ok, hipStream_t s);
 void launch_neighbour_residual(const gsn_blocks& b, float* resid, hipStream_t s);
 int label_blocks(int n);
+// words (double) of the label and training scratch: the per-block partials and their slice sums
+size_t label_part_words(int n);
+size_t mlp_stat_words(int n);
 // part: double [2][label_blocks(n)] scratch, used when alpha and err are given (err[0..1] +=)
 void launch_labels(int n, int K, const float* sp, const int32_t* fp, const float* sa, const uint8_t* ok,
                    const float* alpha, float* label, float* mask, double* part, double* err, hipStream_t s);

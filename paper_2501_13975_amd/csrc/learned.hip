@@ -163,12 +163,35 @@ __global__ __launch_bounds__(LABEL_BLOCK) void labels_kernel(int n, int K, const
     }
 }
 
-// out[0] += sum of part[2 b], out[1] += sum of part[2 b + 1], in block order (one thread per sum).
-__global__ void label_error_sum_kernel(const double* __restrict__ part, int nblocks, double* __restrict__ out) {
+// Deterministic sums of the rows of a [rows][cols] array of per-block partials: the rows are cut into
+// kSlices contiguous ranges, and out[s][c] = the sum over range s of in[r][c] in a fixed order (each of
+// the workgroup's four waves takes every fourth row, the waves' sums are added in wave order); the
+// consumer adds the kSlices slice sums in order.  Grid (ceil(cols / 64), kSlices), 256 threads.  One
+// thread per column summing thousands of partials one after another was latency-bound (6 ms for the
+// network's gradient at 1M kernels).
+constexpr int kSlices = 64;
+template <class T>
+__global__ __launch_bounds__(256) void column_slices_kernel(const T* __restrict__ in, int rows, int cols,
+                                                             double* __restrict__ out) {
+    __shared__ double s_w[4][64];
+    const int lane = __lane_id(), w = threadIdx.x / 64;
+    const int c = blockIdx.x * 64 + lane;
+    const int chunk = (rows + kSlices - 1) / kSlices;
+    const int r0 = blockIdx.y * chunk, r1 = min(rows, r0 + chunk);
+    double a = 0.0;
+    if (c < cols)
+        for (int r = r0 + w; r < r1; r += 4) a += (double)in[(size_t)r * cols + c];
+    s_w[w][lane] = a;
+    __syncthreads();
+    if (w == 0 && c < cols) out[(size_t)blockIdx.y * cols + c] = ((s_w[0][lane] + s_w[1][lane]) + s_w[2][lane]) + s_w[3][lane];
+}
+
+// out[0] += the sum of the label errors, out[1] += that of the mask, from the slice sums of part.
+__global__ void label_error_sum_kernel(const double* __restrict__ slices, double* __restrict__ out) {
     const int t = threadIdx.x;
     if (t >= 2) return;
     double a = 0.0;
-    for (int b = 0; b < nblocks; ++b) a += part[2 * b + t];
+    for (int sl = 0; sl < kSlices; ++sl) a += slices[2 * sl + t];
     out[t] += a;
 }
 
@@ -292,16 +315,16 @@ __global__ __launch_bounds__(GRAD_SAMPLES) void mlp_grad_kernel(const float* __r
 // Adam step (step number t) and refreshes the FP16 copy; writes the loss before the step.
 __global__ __launch_bounds__(256) void mlp_adam_kernel(float* __restrict__ wf, float* __restrict__ m,
                                                         float* __restrict__ v, __half* __restrict__ wh,
-                                                        const float* __restrict__ part,
-                                                        const double* __restrict__ stat, int nblocks, int t,
+                                                        const double* __restrict__ grad_slices,
+                                                        const double* __restrict__ stat_slices, int t,
                                                         float lr, float b1, float b2, float eps,
                                                         float* __restrict__ grad_out, double* __restrict__ loss) {
     __shared__ double s_cnt, s_loss;
     if (threadIdx.x == 0) {
         double a = 0.0, c = 0.0;
-        for (int b = 0; b < nblocks; ++b) {
-            a += stat[2 * b];
-            c += stat[2 * b + 1];
+        for (int sl = 0; sl < kSlices; ++sl) {
+            a += stat_slices[2 * sl];
+            c += stat_slices[2 * sl + 1];
         }
         s_cnt = fmax(c, 1.0);
         s_loss = a;
@@ -312,7 +335,7 @@ __global__ __launch_bounds__(256) void mlp_adam_kernel(float* __restrict__ wf, f
     const double c1 = 1.0 - pow((double)b1, (double)t), c2 = 1.0 - pow((double)b2, (double)t);
     for (int p = threadIdx.x; p < NP; p += blockDim.x) {
         double gsum = 0.0;
-        for (int b = 0; b < nblocks; ++b) gsum += (double)part[(size_t)b * NP + p];
+        for (int sl = 0; sl < kSlices; ++sl) gsum += grad_slices[(size_t)sl * NP + p];
         const float g = (float)(gsum / cnt);
         if (grad_out) grad_out[p] = g;
         const float mm = b1 * m[p] + (1.f - b1) * g;
@@ -355,7 +378,16 @@ void launch_labels(int n, int K, const float* sp, const int32_t* fp, const float
     if (n == 0) return;
     const int nb = label_blocks(n);
     labels_kernel<<<nb, LABEL_BLOCK, 0, s>>>(n, K, sp, fp, sa, ok, alpha, label, mask, alpha && err ? part : nullptr);
-    if (alpha && err) label_error_sum_kernel<<<1, 64, 0, s>>>(part, nb, err);
+    if (alpha && err) {
+        double* slices = part + 2 * (size_t)nb;
+        column_slices_kernel<double><<<dim3(1, kSlices), 256, 0, s>>>(part, nb, 2, slices);
+        label_error_sum_kernel<<<1, 64, 0, s>>>(slices, err);
+    }
+}
+
+size_t label_part_words(int n) { return 2 * (size_t)std::max(label_blocks(n), 1) + 2 * (size_t)kSlices; }
+size_t mlp_stat_words(int n) {
+    return 2 * (size_t)std::max(mlp_grad_blocks(n), 1) + (size_t)kSlices * (GSN_MLP_PARAMS + 2);
 }
 
 void launch_mlp_infer(const uint16_t* wh, int n, const float* feat, const uint8_t* ok, float* out,
@@ -371,8 +403,14 @@ void launch_mlp_train(gsn_mlp& mlp, int n, const float* feat, const float* label
                       double* stat, const gsn_adam_opts& a, float* grad_out, double* loss, hipStream_t s) {
     const int nb = std::max(mlp_grad_blocks(n), 1);
     if (n > 0) mlp_grad_kernel<<<nb, GRAD_SAMPLES, 0, s>>>(mlp.d_params, n, feat, label, mask, part, stat);
-    mlp_adam_kernel<<<1, 256, 0, s>>>(mlp.d_params, mlp.d_m, mlp.d_v, reinterpret_cast<__half*>(mlp.d_half), part,
-                                      stat, n > 0 ? nb : 0, mlp.step, a.lr, a.beta1, a.beta2, a.eps, grad_out, loss);
+    // stat holds [nb][2] partials, then the slice sums of the gradient [kSlices][NP] and of stat [kSlices][2]
+    double* gslices = stat + 2 * (size_t)nb;
+    double* sslices = gslices + (size_t)kSlices * NP;
+    const int rows = n > 0 ? nb : 0;
+    column_slices_kernel<float><<<dim3((NP + 63) / 64, kSlices), 256, 0, s>>>(part, rows, NP, gslices);
+    column_slices_kernel<double><<<dim3(1, kSlices), 256, 0, s>>>(stat, rows, 2, sslices);
+    mlp_adam_kernel<<<1, 256, 0, s>>>(mlp.d_params, mlp.d_m, mlp.d_v, reinterpret_cast<__half*>(mlp.d_half), gslices,
+                                      sslices, mlp.step, a.lr, a.beta1, a.beta2, a.eps, grad_out, loss);
 }
 
 void launch_mlp_reset(gsn_mlp& mlp, hipStream_t s) {

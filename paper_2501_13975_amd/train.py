@@ -193,8 +193,12 @@ class LocalNewtonTrainer:
         self.alpha_mode = alpha_mode
         self.alpha_const = float(alpha_const)
         self.mlp_loss = torch.zeros(1, dtype=torch.float64, device=self.dev)
-        # kernels whose features left the trained range on the current sweep
+        # kernels whose features left the trained range on the current sweep, and the counts of the
+        # last learned sweeps on their way to the host (pinned words and the events that mark them)
         self.out_of_range = torch.zeros(1, dtype=torch.int32, device=self.dev)
+        self._oor_words = [torch.zeros(1, dtype=torch.int32, pin_memory=True) for _ in range(3)]
+        self._oor_pending = []
+        self._oor_next = 0
         self.fallback_sweeps = 0
 
     def log_sweep(self, t, log, group_mask=31, max_rows=50000, seed=0):
@@ -223,21 +227,32 @@ class LocalNewtonTrainer:
 
     def sweep_learned(self, t, i, group_mask=31, check_range=True):
         """Sweep i of the learned form on training image t.  Every `every`-th sweep runs the full
-        rule; so does a learned sweep on which a kernel's features leave the trained range (the
-        overshoot rule is the fallback of the network; with check_range the count is read back,
-        one host wait per learned sweep)."""
+        rule.  The overshoot rule is also the network's fallback: kernels whose features leave the
+        trained range get no step on a learned sweep (alpha 0), and with check_range the learned sweep
+        two after it runs the full rule (the count travels to the host without a wait: by then the
+        device has long finished the sweep that counted it)."""
         so = self.solve_opts(t)
         n = self.g.n
-        self._accumulate_primary(t)
         full = i % self.every == 0
+        if check_range and len(self._oor_pending) >= 2:
+            ev, word = self._oor_pending.pop(0)
+            ev.synchronize()
+            if int(word[0]) > 0 and not full:
+                full = True
+                self.fallback_sweeps += 1
+        self._accumulate_primary(t)
         self.ctx.local_newton_solve(self.g, self.ccams[t], self.blocks, so, self.steps)
         self.ctx.step_features(self.g, self.ccams[t], self.blocks, so, self.feat[:, :n], self.ok[:n],
                                resid=self.resid[:n])
         self.out_of_range.zero_()
         self.ctx.mlp_infer(self.mlp, self.feat[:, :n], self.ok[:n], self.alpha[:, :n], self.out_of_range)
-        if not full and check_range and int(self.out_of_range.item()) > 0:
-            full = True
-            self.fallback_sweeps += 1
+        if check_range and not full:
+            word = self._oor_words[self._oor_next]
+            self._oor_next = (self._oor_next + 1) % len(self._oor_words)
+            word.copy_(self.out_of_range, non_blocking=True)
+            ev = torch.cuda.Event()
+            ev.record()
+            self._oor_pending.append((ev, word))
         if not full:
             if self.alpha_mode == "one":
                 self.ctx.apply_step(self.g, self.steps, so, group_mask)
