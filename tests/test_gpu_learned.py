@@ -230,6 +230,37 @@ def test_learned_form_runs(gsn, ctx):
     tr.close()
 
 
+def test_out_of_range_features_bring_the_full_rule_two_sweeps_later(gsn, ctx):
+    """The fallback of the learned form: a learned sweep whose inference counts kernels with features
+    out of the trained range (forced here by adding to the library's count after the real inference)
+    makes the learned sweep two after it run the full rule (it trains the network), and only that one."""
+    from paper_2501_13975_amd.train import LocalNewtonTrainer
+    cfg = make_config("c1", n=3000, width=160, height=120, n_views=6)
+    tg = [torch.tensor(O.render(cfg.gt, c, O.opts()).img.astype(np.float32), device=ctx.device) for c in cfg.cams]
+    dg = gsn.DeviceGaussians.from_host(cfg.init)
+    tr = LocalNewtonTrainer(dg, cfg.cams, tg, 3)
+    tr.enable_learned(init_params(0), every=100, lr=1e-2)
+    infer = tr.ctx.mlp_infer
+    forced = {"sweep": None, "i": 0}
+
+    def mlp_infer(*args, **kw):
+        infer(*args, **kw)
+        if forced["i"] == forced["sweep"]:
+            tr.out_of_range.add_(1)  # on the device, after the library's count
+
+    tr.ctx.mlp_infer = mlp_infer
+    steps = []
+    for i in range(1, 8):  # sweep 0 would be a scheduled full-rule sweep
+        forced["i"] = i
+        forced["sweep"] = 2
+        tr.sweep_learned(i % len(cfg.cams), i)
+        steps.append(tr.mlp.step)
+    # the network trains only on full-rule sweeps: the one at i = 4, two after the counted i = 2
+    assert steps == [0, 0, 0, 1, 1, 1, 1], steps
+    assert tr.fallback_sweeps == 1
+    tr.close()
+
+
 def test_trained_network_predicts_the_overshoot_rule(gsn, ctx):
     """What the network gains over the method without it: trained on (features, alpha_eff) rows that
     plain full-rule sweeps log, it predicts the scale the overshoot rule applies to the primary-only
