@@ -766,8 +766,11 @@ def roofline(stages, counts, steps, pixels_per_step, n, views):
 def lane_use(c):
     """Share of a wave's 64 lanes at work in the raster passes' per-pixel loops: per-pixel steps
     over 64 x the waves' steps (counted in sweeps profiled at level 2)."""
+    cyc = [c[f"bwd_cycles_{p}"] for p in ("stage", "scan", "walk", "sums")]
+    tot = max(sum(cyc), 1)
     return {"fwd": round(c["fwd_evals"] / max(64 * c["fwd_wave_steps"], 1), 3),
             "bwd": round((c["bwd_active"] + c["bwd_evals"]) / max(64 * c["bwd_wave_steps"], 1), 3),
+            "bwd_wave_time_share": {p: round(x / tot, 3) for p, x in zip(("stage", "scan", "walk", "sums"), cyc)},
             "sweeps": 8}
 
 

@@ -615,7 +615,10 @@ typedef enum {
     GSN_COUNT_FWD_WAVE_STEPS = 22,  /* forward: entries of the band lists the wave walked */
     GSN_COUNT_BWD_WAVE_STEPS = 23,  /* backward: composited entries the wave walked, and entries evaluated
                                        again past the recorded batches */
-    GSN_COUNT_N = 24
+    /* Shader-clock cycles the backward raster's waves spent (level 2): + 0 staging the batch and its
+     * composited-entry masks, + 1 the slot scan, + 2 the per-pixel walk, + 3 the per-entry sums. */
+    GSN_COUNT_BWD_CYCLES = 24,
+    GSN_COUNT_N = 28
 } gsn_counter;
 
 /* Turns stage timing on (on = 1, or 2 to count the raster passes' wave steps too) or off (0)

@@ -259,6 +259,16 @@ __global__ __launch_bounds__(GSN_BLOCK, 3) void raster_bwd_kernel(
     CT Ca0 = CT(0), Ca1 = CT(0), Ca2 = CT(0);
     const float fpx = (float)px, fpy = (float)py;
     uint32_t n_eval = 0, n_act = 0, n_part = 0, n_stage = 0, n_steps = 0;  // n_steps: the wave's, in every lane
+    // level-2 profiling: the wave's shader-clock cycles in staging and masks (a), the slot scan (b), the
+    // per-pixel walk (c) and the per-entry sums (d)
+    unsigned long long cyc[4] = {0ull, 0ull, 0ull, 0ull}, t_mark = STEPS ? clock64() : 0ull;
+    auto lap = [&](int ph) {
+        if (STEPS) {
+            const unsigned long long now = clock64();
+            cyc[ph] += now - t_mark;
+            t_mark = now;
+        }
+    };
     for (uint32_t base = rg.x; base < end; base += GSN_BLOCK) {
         const int bcnt = (int)min((uint32_t)GSN_BLOCK, end - base);
         // stage the batch: one entry per thread, its slot and its band mask
@@ -344,6 +354,7 @@ __global__ __launch_bounds__(GSN_BLOCK, 3) void raster_bwd_kernel(
             }
         }
         __syncthreads();
+        lap(0);
         // (b) slots: block-wide exclusive scan of the batch's pair counts in (entry, wave) order, once per
         // batch; a round's slots are offsets from the scan at its first entry.  Thread t owns the four
         // cells of entry t.
@@ -386,6 +397,7 @@ __global__ __launch_bounds__(GSN_BLOCK, 3) void raster_bwd_kernel(
                 if (s_off[mid * NW] - rbase <= (uint32_t)PMAX) lo = mid; else hi = mid - 1;
             }
             const int r1 = lo;
+            lap(1);
             // (c) front to back over the pixel's composited entries r0..r1-1
 #pragma unroll
             for (int w = 0; w < NW; ++w) {
@@ -418,6 +430,7 @@ __global__ __launch_bounds__(GSN_BLOCK, 3) void raster_bwd_kernel(
                     T *= (1.0f - al);
                 }
             }
+            lap(2);
             // (d) per-entry sums.  Entries of the round with 1..BIG pairs go to groups of SG lanes, larger
             // ones to groups of LG; a group sums its entry's pairs lane-strided and then across its lanes
             // with DPP row operations, so every sum is taken in one fixed order.  Waves take the work
@@ -499,12 +512,15 @@ __global__ __launch_bounds__(GSN_BLOCK, 3) void raster_bwd_kernel(
             }
             r0 = r1;
             __syncthreads();
+            lap(3);
         }
     }
     if (counts) {
-        __shared__ unsigned long long s_cnt[5];
-        if (tid < 5) s_cnt[tid] = 0;
+        __shared__ unsigned long long s_cnt[9];
+        if (tid < 9) s_cnt[tid] = 0;
         __syncthreads();
+        if (STEPS && lane == 0)
+            for (int ph = 0; ph < 4; ++ph) atomicAdd(&s_cnt[5 + ph], cyc[ph]);
         atomicAdd(&s_cnt[0], (unsigned long long)n_eval);
         atomicAdd(&s_cnt[1], (unsigned long long)n_act);
         atomicAdd(&s_cnt[2], (unsigned long long)n_part);
@@ -517,6 +533,8 @@ __global__ __launch_bounds__(GSN_BLOCK, 3) void raster_bwd_kernel(
             atomicAdd(&counts[GSN_COUNT_PARTIALS], s_cnt[2]);
             atomicAdd(&counts[GSN_COUNT_BWD_STAGED], s_cnt[3]);
             atomicAdd(&counts[GSN_COUNT_BWD_WAVE_STEPS], s_cnt[4]);
+            if (STEPS)
+                for (int ph = 0; ph < 4; ++ph) atomicAdd(&counts[GSN_COUNT_BWD_CYCLES + ph], s_cnt[5 + ph]);
         }
     }
 }

@@ -414,7 +414,8 @@ class Context:
                  "bwd_staged")
                 + tuple(f"escalated_{g}" for g in GROUPS4) + tuple(f"fallback_{g}" for g in GROUPS4)
                 + tuple(f"clamped_{g}" for g in ("position", "rotation", "scaling", "colour"))
-                + ("solved", "opacity_bound", "fwd_wave_steps", "bwd_wave_steps"))
+                + ("solved", "opacity_bound", "fwd_wave_steps", "bwd_wave_steps")
+                + tuple(f"bwd_cycles_{p}" for p in ("stage", "scan", "walk", "sums")))
 
     def sync_status(self):
         """gsn_sync_status: (status code, {counter: value}, message); synchronises the stream and clears
