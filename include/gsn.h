@@ -149,6 +149,10 @@ typedef struct {
      * and overshoot.  omega is at most the Gershgorin ratio H_kk / sum_j |H_kj| of the colour system
      * (sum_j alpha_j T_j = 1 - T_final <= 1 at every pixel), which bounds that overshoot. */
     int32_t overlap_scale;
+    /* 0: the colour solve and the overlap share take every view slot of the blocks; k > 0: only the
+     * first k (with k = 1, the primary-only step of a sweep whose secondary views are already in the
+     * blocks' slots but whose shares of the summed rows are not yet added, gsn_add_view_shares). */
+    int32_t view_limit;
 } gsn_solve_opts;
 
 /* Per-kernel gradient/Hessian blocks, summed over the views added so far.
@@ -254,13 +258,26 @@ gsn_status gsn_accumulate_hessian(gsn_ctx* ctx, const gsn_gaussians* g, const gs
  * keep the call free of host waits and let it be captured (gsn_capture_begin).
  * cams [n_views], frames [n_views], d_targets [n_views] (device [3][H][W] each, at each camera's
  * size) are caller-owned; d_loss_out (device double [n_views][2], may be NULL) receives (L2, L_S)
- * per view.  Errors: those of gsn_render and gsn_accumulate_hessian (part of the other views'
+ * per view.  add_shares = 0 leaves the views' shares of the rows summed over the views in the
+ * frames, for gsn_add_view_shares (the slot rows and the primary's coverage row are written in both
+ * cases).  Errors: those of gsn_render and gsn_accumulate_hessian (part of the other views'
  * work may have been issued; the blocks are then incomplete), GSN_E_SHAPE (n_views < 1 or above 9, slots outside the blocks'
  * 0..n_views-1), GSN_E_INVALID (null arrays or entries, a frame given twice), GSN_E_HIP. */
 gsn_status gsn_accumulate_views(gsn_ctx* ctx, const gsn_gaussians* g, int32_t n_views, int32_t first_slot,
                                 const gsn_camera* cams, gsn_frame* const* frames,
                                 const float* const* d_targets, const gsn_render_opts* ropts,
-                                const gsn_loss_opts* lopts, gsn_blocks* blocks, double* d_loss_out);
+                                const gsn_loss_opts* lopts, gsn_blocks* blocks, double* d_loss_out,
+                                int32_t add_shares);
+
+/* The views' shares of the rows summed over the views (position, rotation, scaling, opacity and the
+ * overlap numerator; each frame keeps its view's shares from its accumulation) added to `blocks` in
+ * the order of frames[]: with gsn_accumulate_views(..., add_shares = 0) a caller adds the primary's
+ * share, solves the primary-only step (gsn_solve_opts.view_limit = 1), then adds the secondaries'
+ * (the learned form's full-rule sweep, Sec. 4.3), with the blocks of one gsn_accumulate_views call
+ * at the end.  frames [n_views] must hold views accumulated into these blocks since they were last
+ * rendered.  Errors: GSN_E_INVALID (null handles, a frame with no accumulated view of this size),
+ * GSN_E_SHAPE (n_views outside 0..9). */
+gsn_status gsn_add_view_shares(gsn_ctx* ctx, gsn_blocks* blocks, int32_t n_views, gsn_frame* const* frames);
 
 /* Solves every kernel's local Newton systems (eq. local_newton) in the
  * paper's reduced coordinates relative to the primary camera: position in

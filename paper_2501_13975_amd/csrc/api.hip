@@ -573,10 +573,30 @@ gsn_status gsn_accumulate_hessian(gsn_ctx* ctx, const gsn_gaussians* g, const gs
     return accumulate_impl(ctx, g, fc, d_target, opts, view_slot, b, d_loss_out, nullptr, nullptr, true);
 }
 
+gsn_status gsn_add_view_shares(gsn_ctx* ctx, gsn_blocks* b, int32_t n_views, gsn_frame* const* frames) {
+    if (!ctx || !b || !frames) return fail(ctx, GSN_E_INVALID, "null argument");
+    if (n_views < 0 || n_views > gsn_ctx::kMaxViews) return fail(ctx, GSN_E_SHAPE, "n_views %d not in 0..9", n_views);
+    SumViews sv{};
+    sv.count = n_views;
+    for (int i = 0; i < n_views; ++i) {
+        const gsn_frame* f = frames[i];
+        if (!f || !f->rendered || f->n != b->n || f->sumrows.bytes < (size_t)b->n * (kSumOverlap + 1) * 4 ||
+            f->contrib.bytes < (size_t)b->n)
+            return fail(ctx, GSN_E_INVALID, "frame %d holds no accumulated view of these blocks", i);
+        sv.rows[i] = bp<float>(f->sumrows);
+        sv.contrib[i] = bp<uint8_t>(f->contrib);
+    }
+    HIP_TRY(ctx, hipSetDevice(ctx->device));
+    StageTimer st_(ctx, GSN_STAGE_CHAIN);
+    launch_sum_views(*b, sv, ctx->stream);
+    HIP_TRY(ctx, hipGetLastError());
+    return GSN_OK;
+}
+
 gsn_status gsn_accumulate_views(gsn_ctx* ctx, const gsn_gaussians* g, int32_t n_views, int32_t first_slot,
                                 const gsn_camera* cams, gsn_frame* const* frames, const float* const* d_targets,
                                 const gsn_render_opts* ro, const gsn_loss_opts* lo, gsn_blocks* b,
-                                double* d_loss_out) {
+                                double* d_loss_out, int32_t add_shares) {
     if (!ctx || !cams || !frames || !d_targets || !ro || !lo || !b) return fail(ctx, GSN_E_INVALID, "null argument");
     if (n_views < 1 || first_slot < 0 || first_slot + n_views > b->n_views || n_views > gsn_ctx::kMaxViews)
         return fail(ctx, GSN_E_SHAPE, "views %d..%d outside the blocks' slots 0..%d", first_slot,
@@ -595,7 +615,7 @@ gsn_status gsn_accumulate_views(gsn_ctx* ctx, const gsn_gaussians* g, int32_t n_
             gsn_status r = gsn_render(ctx, g, &cams[i], ro, frames[i], nullptr, nullptr);
             if (r == GSN_OK)
                 r = accumulate_impl(ctx, g, frames[i], d_targets[i], lo, first_slot + i, b, loss ? loss + 2 * i : nullptr,
-                                    nullptr, nullptr, true);
+                                    nullptr, nullptr, add_shares != 0);
             if (r != GSN_OK) return r;
         }
         return GSN_OK;
@@ -627,7 +647,7 @@ gsn_status gsn_accumulate_views(gsn_ctx* ctx, const gsn_gaussians* g, int32_t n_
         const hipError_t e2 = e1 == hipSuccess ? hipStreamWaitEvent(home, ctx->ev_join[k], 0) : e1;
         if (e2 != hipSuccess && r == GSN_OK) r = fail(ctx, GSN_E_HIP, "joining the view streams: %s", hipGetErrorString(e2));
     }
-    if (r == GSN_OK) {
+    if (r == GSN_OK && add_shares) {
         // the views' shares of the summed rows, added in view order: the additions of the same calls
         // made one after another
         SumViews sv{};
@@ -658,6 +678,7 @@ static gsn_status check_solve_args(gsn_ctx* ctx, const gsn_gaussians* g, const g
         return fail(ctx, GSN_E_INVALID, "solve option out of range");
     if (o->precision != 0 && o->precision != 1) return fail(ctx, GSN_E_INVALID, "precision must be 0 or 1");
     if (o->precision == 1 && b->n_views > 4) return fail(ctx, GSN_E_SHAPE, "the mixed form takes at most 4 views");
+    if (o->view_limit < 0) return fail(ctx, GSN_E_INVALID, "view_limit must be >= 0");
     return GSN_OK;
 }
 
@@ -671,7 +692,7 @@ gsn_status gsn_local_newton_solve(gsn_ctx* ctx, const gsn_gaussians* g, const gs
     unsigned long long* nonfinite = ctx->d_stats + GSN_STAT_SKIPPED_NONFINITE;
     if (o->precision == 1) {
         const int K = (g->sh_degree + 1) * (g->sh_degree + 1);
-        launch_sh_gram(b->d_data, g->n, K, b->n_views, bp<float>(ctx->gram), ctx->stream);
+        launch_sh_gram(b->d_data, g->n, K, solve_view_slots(b->n_views, *o), bp<float>(ctx->gram), ctx->stream);
         launch_solve_mixed(*g, make_devcam(*primary), o->kappa, *b, *o, bp<float>(ctx->gram), *st, nonfinite,
                            prof_counts(ctx), ctx->stream);
     } else {
@@ -694,7 +715,7 @@ gsn_status gsn_local_newton_solve_noalloc(gsn_ctx* ctx, const gsn_gaussians* g, 
     unsigned long long* nonfinite = ctx->d_stats + GSN_STAT_SKIPPED_NONFINITE;
     if (o->precision == 1) {
         const int K = (g->sh_degree + 1) * (g->sh_degree + 1);
-        launch_sh_gram(b->d_data, g->n, K, b->n_views, ctx->noalloc_gram, ctx->stream);
+        launch_sh_gram(b->d_data, g->n, K, solve_view_slots(b->n_views, *o), ctx->noalloc_gram, ctx->stream);
         launch_solve_mixed(*g, make_devcam(*primary), o->kappa, *b, *o, ctx->noalloc_gram, *st, nonfinite,
                            prof_counts(ctx), ctx->stream);
     } else {

@@ -256,6 +256,8 @@ struct SolveScene {
 };
 void launch_solve_batched(const SolveScene* d_scenes, int count, long long total, int max_views, int block,
                           int grid, unsigned long long* nonfinite, hipStream_t s);
+// the view slots a solve with options o takes of blocks with V slots
+int solve_view_slots(int V, const gsn_solve_opts& o);
 void launch_sh_gram(const float* blk, int n, int K, int V, float* gram, hipStream_t s);
 // Devices whose no-allocation scratch address is cached.
 #define GSN_MAX_DEVICES 64

@@ -104,13 +104,19 @@ __device__ __forceinline__ uint32_t decision_events(int group, int j) {
 // omega <= H_kk / sum_j |H_kj| for the colour system (sum_j alpha_j T_j = 1 - T_final <= 1 at every
 // pixel), a Gershgorin bound on that overshoot.  It multiplies the kernel's steps after the trust
 // radii, so that overlapping kernels together move about as far as one kernel's radius allows.
+// Vc: the view slots taken (the first Vc of the blocks' V), see view_slots.
 template <class T, class RowFn>
-__device__ __forceinline__ T overlap_share(RowFn B, int V, const gsn_solve_opts& o) {
+__device__ __forceinline__ T overlap_share(RowFn B, int V, int Vc, const gsn_solve_opts& o) {
     if (!o.overlap_scale) return (T)1;
     T cov = (T)0;
-    for (int v = 0; v < V; ++v) cov += (T)B(GSN_BLK_BASE + GSN_BLK_VIEW * v + 9);
+    for (int v = 0; v < Vc; ++v) cov += (T)B(GSN_BLK_BASE + GSN_BLK_VIEW * v + 9);
     const T w2 = (T)B(GSN_BLK_BASE + GSN_BLK_VIEW * V);
     return cov > (T)0 ? fmin((T)1, fmax((T)0, w2 / cov)) : (T)0;
+}
+
+// The view slots a solve takes: all V of the blocks, or the first o.view_limit of them.
+__host__ __device__ __forceinline__ int view_slots(int V, const gsn_solve_opts& o) {
+    return o.view_limit > 0 && o.view_limit < V ? o.view_limit : V;
 }
 
 // Zero step and decisions -3 for a kernel skipped because of non-finite values.
@@ -329,7 +335,8 @@ __device__ __forceinline__ uint32_t solve_one(int k, const float* __restrict__ p
         return v;
     };
     uint32_t ev = 1u << EV_SOLVED;
-    const double frac = (double)o.step_frac, omega = overlap_share<double>(B, V, o);
+    const int Vc = view_slots(V, o);
+    const double frac = (double)o.step_frac, omega = overlap_share<double>(B, V, Vc, o);
     const double abs_scale = 1.0 / (3.0 * (double)o.npix_primary);
     double s[3];
     for (int a = 0; a < 3; ++a) s[a] = scale[a * N + k];
@@ -387,7 +394,7 @@ __device__ __forceinline__ uint32_t solve_one(int k, const float* __restrict__ p
         st[10 * N + k] = (float)(omega * (frac * ds));
     }
     // ---- colour, per channel
-    if (colour_solve<VM>(K, V, B, o, frac, omega, abs_scale, st, N, k, fl, chk)) ev |= 1u << (EV_CLAMP + 3);
+    if (colour_solve<VM>(K, Vc, B, o, frac, omega, abs_scale, st, N, k, fl, chk)) ev |= 1u << (EV_CLAMP + 3);
     if (!(chk == 0.0)) {
         skip_nonfinite(st, fl, N, k, NS);
         return 1u << EV_NONFINITE;
@@ -603,7 +610,8 @@ __device__ __forceinline__ uint32_t solve_one_mixed(int k, const float* __restri
         return v;
     };
     uint32_t ev = 1u << EV_SOLVED;
-    const float frac = o.step_frac, omega = overlap_share<float>(Bf, V, o);
+    const int Vc = view_slots(V, o);
+    const float frac = o.step_frac, omega = overlap_share<float>(Bf, V, Vc, o);
     const float abs_scale = 1.0f / (3.0f * (float)o.npix_primary);
     float s[3];
     for (int a = 0; a < 3; ++a) s[a] = scale[a * N + k];
@@ -676,7 +684,7 @@ __device__ __forceinline__ uint32_t solve_one_mixed(int k, const float* __restri
         chk += ds * 0.f;
         st[10 * N + k] = omega * (frac * ds);
     }
-    if (colour_solve_mixed(K, V, Bf, gram, o, frac, omega, abs_scale, st, N, k, fl, blk, chk))
+    if (colour_solve_mixed(K, Vc, Bf, gram, o, frac, omega, abs_scale, st, N, k, fl, blk, chk))
         ev |= 1u << (EV_CLAMP + 3);
     if (!(chk == 0.f)) {
         skip_nonfinite(st, fl, N, k, NS);
@@ -847,6 +855,8 @@ static void launch_batched_block(const SolveScene* d_scenes, int count, long lon
     else
         solve_batched_kernel<9, BLOCK><<<grid, BLOCK, 0, s>>>(d_scenes, count, total, nonfinite);
 }
+
+int solve_view_slots(int V, const gsn_solve_opts& o) { return view_slots(V, o); }
 
 void launch_sh_gram(const float* blk, int n, int K, int V, float* gram, hipStream_t s) {
     if (n == 0) return;

@@ -44,7 +44,8 @@ def lib():
             "gsn_frame_create": [P, ctypes.POINTER(P)], "gsn_frame_destroy": [P, P],
             "gsn_render": [P, P, P, P, P, P, P],
             "gsn_accumulate_hessian": [P, P, P, P, P, ctypes.c_int32, P, P],
-            "gsn_accumulate_views": [P, P, ctypes.c_int32, ctypes.c_int32, P, P, P, P, P, P, P],
+            "gsn_accumulate_views": [P, P, ctypes.c_int32, ctypes.c_int32, P, P, P, P, P, P, P, ctypes.c_int32],
+            "gsn_add_view_shares": [P, P, ctypes.c_int32, P],
             "gsn_local_newton_solve": [P, P, P, P, P, P],
             "gsn_local_newton_solve_noalloc": [P, P, P, P, P, P],
             "gsn_apply_step": [P, P, P, P, P, ctypes.c_uint32],
@@ -121,7 +122,7 @@ class CSolveOpts(ctypes.Structure):
                 ("npix_primary", ctypes.c_int32), ("kappa", ctypes.c_float), ("trust_pos", ctypes.c_float),
                 ("trust_rot", ctypes.c_float), ("trust_scale", ctypes.c_float), ("trust_sh", ctypes.c_float),
                 ("opac_eps", ctypes.c_float), ("step_frac", ctypes.c_float), ("damp_sh", ctypes.c_float),
-                ("precision", ctypes.c_int32), ("overlap_scale", ctypes.c_int32)]
+                ("precision", ctypes.c_int32), ("overlap_scale", ctypes.c_int32), ("view_limit", ctypes.c_int32)]
 
 
 class CBlocks(ctypes.Structure):
@@ -147,13 +148,14 @@ def loss_opts(lambda_ssim=0.2, weight=1.0, keep_zstats=False, gauss_newton=False
 
 def solve_opts(npix_primary, kappa=0.3, damp_rel=1e-3, damp_abs=1e-12, pivot_min=1e-3, max_escalations=7,
                barrier_beta=1e-2, sh_floor=1e-3, scale_floor=0.1, opac_ftb=0.995, trust_pos=2.0, trust_rot=0.5,
-               trust_scale=0.5, trust_sh=1.0, opac_eps=1e-6, step_frac=1.0, damp_sh=1e-3, precision=0, overlap=0):
+               trust_scale=0.5, trust_sh=1.0, opac_eps=1e-6, step_frac=1.0, damp_sh=1e-3, precision=0, overlap=0,
+               view_limit=0):
     """precision 0: plain form; 1: mixed form (BF16 matrix-core colour Grams, FP32 solves, FP64 for
     ill-conditioned position and rotation systems).  overlap 1: every kernel's steps times its overlap
-    share (gsn_solve_opts.overlap_scale)."""
+    share (gsn_solve_opts.overlap_scale).  view_limit k > 0: only the first k view slots."""
     return CSolveOpts(damp_rel, damp_abs, pivot_min, max_escalations, barrier_beta, sh_floor, scale_floor,
                       opac_ftb, int(npix_primary), kappa, trust_pos, trust_rot, trust_scale, trust_sh, opac_eps,
-                      step_frac, damp_sh, int(precision), int(overlap))
+                      step_frac, damp_sh, int(precision), int(overlap), int(view_limit))
 
 
 def camera(c) -> CCamera:
@@ -297,9 +299,10 @@ class Context:
                                                  _ptr(loss_out)))
 
     def accumulate_views(self, g, cams, frames, targets, ro: CRenderOpts, lo: CLossOpts, blocks: "Blocks",
-                         loss_out=None, first_slot=0):
+                         loss_out=None, first_slot=0, add_shares=True):
         """Render + accumulate of several views (view i into slot first_slot + i) with their work
-        overlapped on the library's streams; loss_out: float64 [n_views][2] on the device, or None."""
+        overlapped on the library's streams; loss_out: float64 [n_views][2] on the device, or None.
+        add_shares False: the views' shares of the summed rows stay in the frames (add_view_shares)."""
         n = len(cams)
         if not (len(frames) == len(targets) == n):
             raise ValueError("cams, frames and targets differ in length")
@@ -312,7 +315,13 @@ class Context:
         htg = (ctypes.c_void_p * n)(*[t.data_ptr() for t in targets])
         self._check(lib().gsn_accumulate_views(self.h, ctypes.byref(cg), n, int(first_slot), ccams, hfr, htg,
                                                ctypes.byref(ro), ctypes.byref(lo), ctypes.byref(cb),
-                                               _ptr(loss_out)))
+                                               _ptr(loss_out), int(bool(add_shares))))
+
+    def add_view_shares(self, blocks: "Blocks", frames):
+        """Adds the frames' shares of the summed rows to the blocks, in the order given."""
+        cb = blocks.c()
+        hfr = (ctypes.c_void_p * len(frames))(*[f.h.value for f in frames])
+        self._check(lib().gsn_add_view_shares(self.h, ctypes.byref(cb), len(frames), hfr))
 
     def local_newton_solve(self, g, primary: CCamera, blocks: "Blocks", so: CSolveOpts, steps: "Steps"):
         cg, cb, cs = g.c(), blocks.c(), steps.c()

@@ -157,11 +157,20 @@ class LocalNewtonTrainer:
         self.ctx.render(self.g, self.ccams[t], self.ro, fr)
         self.ctx.accumulate_hessian(self.g, fr, self.targets[t], self.lo, 0, self.blocks, self.loss[0])
 
-    def _accumulate_secondaries(self, t):
-        if len(self.knn[t]):
-            self.ctx.accumulate_views(self.g, [self.chalf[j] for j in self.knn[t]], self.frames[1:1 + len(self.knn[t])],
-                                      [self.half_targets[j] for j in self.knn[t]], self.ro, self.lo, self.blocks,
-                                      self.loss[1:], first_slot=1)
+    def _accumulate_held(self, t):
+        """All views of image t accumulated with their shares of the summed rows left in the frames."""
+        self.ctx.blocks_zero(self.blocks)
+        cams = [self.ccams[t]] + [self.chalf[j] for j in self.knn[t]]
+        tgts = [self.targets[t]] + [self.half_targets[j] for j in self.knn[t]]
+        self.ctx.accumulate_views(self.g, cams, self.frames[:len(cams)], tgts, self.ro, self.lo, self.blocks,
+                                  self.loss, add_shares=False)
+
+    @staticmethod
+    def _primary_only(so):
+        """The solve options taking the primary's view slot alone (the secondaries' slots may be filled)."""
+        sp = gsn.CSolveOpts.from_buffer_copy(so)
+        sp.view_limit = 1
+        return sp
 
     def _learned_buffers(self):
         n = self.g.n
@@ -209,11 +218,12 @@ class LocalNewtonTrainer:
         self._learned_buffers()
         so = self.solve_opts(t)
         n = self.g.n
-        self._accumulate_primary(t)
-        self.ctx.local_newton_solve(self.g, self.ccams[t], self.blocks, so, self.steps_prim)
+        self._accumulate_held(t)
+        self.ctx.add_view_shares(self.blocks, self.frames[:1])
+        self.ctx.local_newton_solve(self.g, self.ccams[t], self.blocks, self._primary_only(so), self.steps_prim)
         self.ctx.step_features(self.g, self.ccams[t], self.blocks, so, self.feat[:, :n], self.ok[:n],
                                resid=self.resid[:n])
-        self._accumulate_secondaries(t)
+        self.ctx.add_view_shares(self.blocks, self.frames[1:1 + len(self.knn[t])])
         if self.n_secondary:
             self.ctx.neighbour_residual(self.blocks, self.resid[:n])
         self.ctx.local_newton_solve(self.g, self.ccams[t], self.blocks, so, self.steps)
@@ -240,8 +250,15 @@ class LocalNewtonTrainer:
             if int(word[0]) > 0 and not full:
                 full = True
                 self.fallback_sweeps += 1
-        self._accumulate_primary(t)
-        self.ctx.local_newton_solve(self.g, self.ccams[t], self.blocks, so, self.steps)
+        if full:
+            # every view rendered and accumulated at once, the secondaries' shares of the summed rows
+            # held back: the blocks then hold the primary's system, as after _accumulate_primary
+            self._accumulate_held(t)
+            self.ctx.add_view_shares(self.blocks, self.frames[:1])
+            self.ctx.local_newton_solve(self.g, self.ccams[t], self.blocks, self._primary_only(so), self.steps_prim)
+        else:
+            self._accumulate_primary(t)
+            self.ctx.local_newton_solve(self.g, self.ccams[t], self.blocks, so, self.steps)
         self.ctx.step_features(self.g, self.ccams[t], self.blocks, so, self.feat[:, :n], self.ok[:n],
                                resid=self.resid[:n])
         self.out_of_range.zero_()
@@ -262,8 +279,7 @@ class LocalNewtonTrainer:
                 self.ctx.apply_step(self.g, self.steps, so, group_mask, scale=self.alpha[:, :n])
             return
         # full rule: the secondaries' blocks join the primary's; label and train, then apply the full step
-        self.steps, self.steps_prim = self.steps_prim, self.steps
-        self._accumulate_secondaries(t)
+        self.ctx.add_view_shares(self.blocks, self.frames[1:1 + len(self.knn[t])])
         if self.n_secondary:
             self.ctx.neighbour_residual(self.blocks, self.resid[:n])
         self.ctx.local_newton_solve(self.g, self.ccams[t], self.blocks, so, self.steps)

@@ -81,6 +81,46 @@ def test_overlapped_views_equal_sequential_calls(gsn, case, nsec, reserve):
     tr.close()
 
 
+@pytest.mark.parametrize("precision", [0, 1])
+def test_held_shares_give_the_primary_system_then_the_sweep(gsn, case, precision):
+    """Views accumulated with their shares of the summed rows held in the frames: after the primary's
+    share the solve on the primary's slot alone equals the solve of the blocks of the primary alone,
+    and after the secondaries' shares the blocks equal those of the sequential calls."""
+    cfg, tg = case
+    tr = _trainer(gsn, cfg, tg, 3, True)
+    for t in (2, 6):
+        print(f"\n[held shares] precision={precision} t={t}", flush=True)
+        b_seq, l_seq = _sequential(tr, t)
+        so = tr.solve_opts(t)
+        so.precision = precision
+        sp = tr._primary_only(so)
+        cams, tgts = _views(tr, t)
+        # the primary alone, its blocks and primary-only step
+        tr.ctx.blocks_zero(tr.blocks)
+        tr.ctx.render(tr.g, cams[0], tr.ro, tr.frames[0])
+        tr.ctx.accumulate_hessian(tr.g, tr.frames[0], tgts[0], tr.lo, 0, tr.blocks, tr.loss[0])
+        tr.ctx.local_newton_solve(tr.g, cams[0], tr.blocks, so, tr.steps)
+        torch.cuda.synchronize()
+        s_prim, f_prim = [x.clone() for x in tr.steps.view()]
+        # every view, shares held; the primary's added, solved on slot 0 alone
+        tr.loss.zero_()
+        tr._accumulate_held(t)
+        tr.ctx.add_view_shares(tr.blocks, tr.frames[:1])
+        tr.ctx.local_newton_solve(tr.g, cams[0], tr.blocks, sp, tr.steps)
+        torch.cuda.synchronize()
+        assert torch.equal(tr.steps.view()[0], s_prim)
+        assert torch.equal(tr.steps.view()[1], f_prim)
+        tr.ctx.add_view_shares(tr.blocks, tr.frames[1:len(cams)])
+        torch.cuda.synchronize()
+        assert torch.equal(tr.blocks.view(), b_seq)
+        assert torch.equal(tr.loss, l_seq)
+    with pytest.raises(gsn.GsnError):  # more frames than the entry takes
+        tr.ctx.add_view_shares(tr.blocks, [tr.frames[0]] * 10)
+    st, stats, msg = tr.ctx.sync_status()
+    assert st == 0 and not any(stats.values()), (st, stats, msg)
+    tr.close()
+
+
 def test_profiled_views_run_in_sequence_with_equal_results(gsn, case):
     cfg, tg = case
     tr = _trainer(gsn, cfg, tg, 3, True)
