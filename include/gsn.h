@@ -319,6 +319,15 @@ gsn_status gsn_local_newton_solve_noalloc(gsn_ctx* ctx, const gsn_gaussians* g, 
 gsn_status gsn_apply_step(gsn_ctx* ctx, gsn_gaussians* g, const gsn_steps* steps,
                           const gsn_solve_opts* opts, const float* d_scale, uint32_t group_mask);
 
+/* gsn_local_newton_solve followed by gsn_apply_step(g, steps, opts, NULL, group_mask) in one
+ * launch: the thread that solves a kernel applies its step at once (a sweep's solve and update,
+ * Sec. 4.2), so the parameters are read and written in the same pass.  steps receive the solved
+ * steps and decisions as with gsn_local_newton_solve; g's parameters end as after the two calls,
+ * bit for bit.  Errors: as gsn_local_newton_solve, and GSN_E_INVALID for group_mask bits above 4. */
+gsn_status gsn_solve_apply(gsn_ctx* ctx, gsn_gaussians* g, const gsn_camera* primary,
+                           const gsn_blocks* blocks, const gsn_solve_opts* opts, gsn_steps* steps,
+                           uint32_t group_mask);
+
 /* First-order baseline on the same gradients (the comparison behind the paper's
  * claims of fewer iterations than first-order training, Sec. 1 and Sec. 5).
  * lr: learning rates of the groups position, rotation (left rotation vector,

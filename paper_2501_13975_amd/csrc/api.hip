@@ -682,6 +682,21 @@ static gsn_status check_solve_args(gsn_ctx* ctx, const gsn_gaussians* g, const g
     return GSN_OK;
 }
 
+// The solve launches of the three solve entry points: gram is the mixed form's Gram scratch (the
+// context's buffer, or the no-allocation array), ap the update fused into the solve (mask 0: none).
+static void launch_solve_any(gsn_ctx* ctx, const gsn_gaussians* g, const gsn_camera* primary, const gsn_blocks* b,
+                             const gsn_solve_opts* o, gsn_steps* st, float* gram, const ApplyTo& ap) {
+    unsigned long long* nonfinite = ctx->d_stats + GSN_STAT_SKIPPED_NONFINITE;
+    if (o->precision == 1) {
+        const int K = (g->sh_degree + 1) * (g->sh_degree + 1);
+        launch_sh_gram(b->d_data, g->n, K, solve_view_slots(b->n_views, *o), gram, ctx->stream);
+        launch_solve_mixed(*g, make_devcam(*primary), o->kappa, *b, *o, gram, *st, nonfinite, prof_counts(ctx), ap,
+                           ctx->stream);
+    } else {
+        launch_solve(*g, make_devcam(*primary), o->kappa, *b, *o, *st, nonfinite, prof_counts(ctx), ap, ctx->stream);
+    }
+}
+
 gsn_status gsn_local_newton_solve(gsn_ctx* ctx, const gsn_gaussians* g, const gsn_camera* primary,
                                   const gsn_blocks* b, const gsn_solve_opts* o, gsn_steps* st) {
     gsn_status r = check_solve_args(ctx, g, primary, b, o, st);
@@ -689,15 +704,27 @@ gsn_status gsn_local_newton_solve(gsn_ctx* ctx, const gsn_gaussians* g, const gs
     HIP_TRY(ctx, hipSetDevice(ctx->device));
     if (o->precision == 1) HIP_TRY(ctx, buf_reserve(ctx->gram, (size_t)std::max(g->n, 1) * 10 * 4));
     StageTimer st_(ctx, GSN_STAGE_SOLVE);
-    unsigned long long* nonfinite = ctx->d_stats + GSN_STAT_SKIPPED_NONFINITE;
-    if (o->precision == 1) {
-        const int K = (g->sh_degree + 1) * (g->sh_degree + 1);
-        launch_sh_gram(b->d_data, g->n, K, solve_view_slots(b->n_views, *o), bp<float>(ctx->gram), ctx->stream);
-        launch_solve_mixed(*g, make_devcam(*primary), o->kappa, *b, *o, bp<float>(ctx->gram), *st, nonfinite,
-                           prof_counts(ctx), ctx->stream);
-    } else {
-        launch_solve(*g, make_devcam(*primary), o->kappa, *b, *o, *st, nonfinite, prof_counts(ctx), ctx->stream);
-    }
+    launch_solve_any(ctx, g, primary, b, o, st, bp<float>(ctx->gram), ApplyTo{});
+    HIP_TRY(ctx, hipGetLastError());
+    return GSN_OK;
+}
+
+gsn_status gsn_solve_apply(gsn_ctx* ctx, gsn_gaussians* g, const gsn_camera* primary, const gsn_blocks* b,
+                           const gsn_solve_opts* o, gsn_steps* st, uint32_t group_mask) {
+    gsn_status r = check_solve_args(ctx, g, primary, b, o, st);
+    if (r != GSN_OK) return r;
+    if (group_mask > 31u) return fail(ctx, GSN_E_INVALID, "group_mask 0x%x has bits beyond the five groups", group_mask);
+    HIP_TRY(ctx, hipSetDevice(ctx->device));
+    if (o->precision == 1) HIP_TRY(ctx, buf_reserve(ctx->gram, (size_t)std::max(g->n, 1) * 10 * 4));
+    StageTimer st_(ctx, GSN_STAGE_SOLVE);
+    ApplyTo ap;
+    ap.pos = g->d_pos;
+    ap.rot = g->d_rot;
+    ap.scale = g->d_scale;
+    ap.opac = g->d_opac;
+    ap.sh = g->d_sh;
+    ap.mask = group_mask;
+    launch_solve_any(ctx, g, primary, b, o, st, bp<float>(ctx->gram), ap);
     HIP_TRY(ctx, hipGetLastError());
     return GSN_OK;
 }
@@ -712,15 +739,7 @@ gsn_status gsn_local_newton_solve_noalloc(gsn_ctx* ctx, const gsn_gaussians* g, 
     if (!ctx->noalloc_gram) return fail(ctx, GSN_E_INVALID, "no scratch address for this device");
     HIP_TRY(ctx, hipSetDevice(ctx->device));
     // no stage timing here: timing may create events; no buffer is reserved or grown
-    unsigned long long* nonfinite = ctx->d_stats + GSN_STAT_SKIPPED_NONFINITE;
-    if (o->precision == 1) {
-        const int K = (g->sh_degree + 1) * (g->sh_degree + 1);
-        launch_sh_gram(b->d_data, g->n, K, solve_view_slots(b->n_views, *o), ctx->noalloc_gram, ctx->stream);
-        launch_solve_mixed(*g, make_devcam(*primary), o->kappa, *b, *o, ctx->noalloc_gram, *st, nonfinite,
-                           prof_counts(ctx), ctx->stream);
-    } else {
-        launch_solve(*g, make_devcam(*primary), o->kappa, *b, *o, *st, nonfinite, prof_counts(ctx), ctx->stream);
-    }
+    launch_solve_any(ctx, g, primary, b, o, st, ctx->noalloc_gram, ApplyTo{});
     HIP_TRY(ctx, hipGetLastError());
     return GSN_OK;
 }

@@ -233,9 +233,19 @@ void launch_chain(const gsn_frame& f, const gsn_gaussians& g, float weight, int 
 // ---- launchers (solve.hip)
 // nonfinite: device counter of kernels skipped for non-finite blocks or steps (always counted);
 // prof: the profile counters (solve events, GSN_COUNT_SOLVE_*), or NULL when not profiling
+// The update a solve launch applies as it goes (mask 0: none; else the parameter groups of mask, as
+// gsn_apply_step with no scales).
+struct ApplyTo {
+    float* pos = nullptr;
+    float* rot = nullptr;
+    float* scale = nullptr;
+    float* opac = nullptr;
+    float* sh = nullptr;
+    uint32_t mask = 0;
+};
 void launch_solve(const gsn_gaussians& g, const DevCam& cam, float kappa, const gsn_blocks& b,
                   const gsn_solve_opts& o, const gsn_steps& st, unsigned long long* nonfinite,
-                  unsigned long long* prof, hipStream_t s);
+                  unsigned long long* prof, const ApplyTo& ap, hipStream_t s);
 void launch_apply(const gsn_gaussians& g, const gsn_steps& st, const gsn_solve_opts& o, const float* scale,
                   uint32_t mask, unsigned long long* prof, hipStream_t s);
 void launch_first_order(const gsn_gaussians& g, const gsn_blocks& b, const gsn_first_order_opts& fo, float c1,
@@ -266,7 +276,7 @@ void launch_sh_gram(const float* blk, int n, int K, int V, float* gram, hipStrea
 hipError_t solve_scratch_address(int device, float** out);
 void launch_solve_mixed(const gsn_gaussians& g, const DevCam& cam, float kappa, const gsn_blocks& b,
                         const gsn_solve_opts& o, const float* gram, const gsn_steps& st, unsigned long long* nonfinite,
-                        unsigned long long* prof, hipStream_t s);
+                        unsigned long long* prof, const ApplyTo& ap, hipStream_t s);
 void launch_features(const gsn_gaussians& g, const DevCam& cam, float kappa, const gsn_blocks& b,
                      const gsn_solve_opts& o, const float* resid, float* feat, uint8_t* ok, hipStream_t s);
 void launch_neighbour_residual(const gsn_blocks& b, float* resid, hipStream_t s);

@@ -240,27 +240,45 @@ __global__ __launch_bounds__(kThreads) void scan_reduce_kernel(const uint32_t* _
     if (threadIdx.x == 0) block_sums[blockIdx.x] = tot;
 }
 
+// The block's tile passes through LDS so that the global loads and stores are coalesced (thread t
+// scans items 8t .. 8t + 7 of the tile, read and written as two 16-byte words).
 __global__ __launch_bounds__(kThreads) void scan_apply_kernel(const uint32_t* __restrict__ in,
                                                                uint32_t* __restrict__ out, uint32_t n,
                                                                const uint32_t* __restrict__ block_off,
                                                                uint32_t* __restrict__ d_total) {
-    const size_t base = (size_t)blockIdx.x * kScanTile + (size_t)threadIdx.x * kScanItems;
-    uint32_t v[kScanItems], s = 0;
+    static_assert(kScanItems == 8, "two 16-byte LDS words per thread");
+    __shared__ uint4 tile4[kScanTile / 4];
+    uint32_t* tile = reinterpret_cast<uint32_t*>(tile4);
+    const size_t base = (size_t)blockIdx.x * kScanTile;
+    const int tid = threadIdx.x;
 #pragma unroll
     for (int i = 0; i < kScanItems; ++i) {
-        const size_t idx = base + i;
-        v[i] = idx < n ? in[idx] : 0u;
-        s += v[i];
+        const size_t idx = base + (size_t)i * kThreads + tid;
+        tile[i * kThreads + tid] = idx < n ? in[idx] : 0u;
     }
+    __syncthreads();
+    const uint4 w0 = tile4[2 * tid], w1 = tile4[2 * tid + 1];
+    const uint32_t v[kScanItems] = {w0.x, w0.y, w0.z, w0.w, w1.x, w1.y, w1.z, w1.w};
+    uint32_t s = 0;
+#pragma unroll
+    for (int i = 0; i < kScanItems; ++i) s += v[i];
     uint32_t tot;
     uint32_t off = block_excl_scan(s, &tot) + (block_off ? block_off[blockIdx.x] : 0u);
+    uint32_t o[kScanItems];
 #pragma unroll
     for (int i = 0; i < kScanItems; ++i) {
-        const size_t idx = base + i;
-        if (idx < n) out[idx] = off;
+        o[i] = off;
         off += v[i];
     }
-    if (d_total && blockIdx.x == gridDim.x - 1 && threadIdx.x == kThreads - 1) *d_total = off;
+    tile4[2 * tid] = make_uint4(o[0], o[1], o[2], o[3]);
+    tile4[2 * tid + 1] = make_uint4(o[4], o[5], o[6], o[7]);
+    if (d_total && blockIdx.x == gridDim.x - 1 && tid == kThreads - 1) *d_total = off;
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < kScanItems; ++i) {
+        const size_t idx = base + (size_t)i * kThreads + tid;
+        if (idx < n) out[idx] = tile[i * kThreads + tid];
+    }
 }
 
 hipError_t scan_rec(const uint32_t* in, uint32_t* out, uint32_t n, uint32_t* d_total, uint32_t* tmp,

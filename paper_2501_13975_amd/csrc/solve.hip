@@ -693,59 +693,6 @@ __device__ __forceinline__ uint32_t solve_one_mixed(int k, const float* __restri
     return ev;
 }
 
-__global__ __launch_bounds__(128) void solve_mixed_kernel(const float* __restrict__ pos, const float* __restrict__ rot,
-                                                           const float* __restrict__ scale,
-                                                           const float* __restrict__ opac, int n, int K, DevCam c,
-                                                           float kappa, const float* __restrict__ blk, int V,
-                                                           gsn_solve_opts o, const float* __restrict__ gram,
-                                                           float* __restrict__ st, int32_t* __restrict__ fl,
-                                                           unsigned long long* __restrict__ n_fp64,
-                                                           unsigned long long* __restrict__ nonfinite,
-                                                           unsigned long long* __restrict__ prof) {
-    const int k = blockIdx.x * blockDim.x + threadIdx.x;
-    uint32_t ev = 0;
-    if (k < n) ev = solve_one_mixed(k, pos, rot, scale, opac, n, K, c, kappa, blk, V, o, gram, st, fl, n_fp64);
-    count_solve_events(ev, nonfinite, prof);
-}
-
-template <int VM>
-__global__ __launch_bounds__(128, 3) void solve_kernel(const float* __restrict__ pos, const float* __restrict__ rot,
-                                                     const float* __restrict__ scale, const float* __restrict__ opac,
-                                                     int n, int K, DevCam c, float kappa,
-                                                     const float* __restrict__ blk, int V, gsn_solve_opts o,
-                                                     float* __restrict__ st, int32_t* __restrict__ fl,
-                                                     unsigned long long* __restrict__ nonfinite,
-                                                     unsigned long long* __restrict__ prof) {
-    const int k = blockIdx.x * blockDim.x + threadIdx.x;
-    uint32_t ev = 0;
-    if (k < n) ev = solve_one<VM>(k, pos, rot, scale, opac, n, K, c, kappa, blk, V, o, st, fl);
-    count_solve_events(ev, nonfinite, prof);
-}
-
-// Several scenes in one persistent launch: the threads of a grid sized to the device walk
-// the concatenated kernel index space (scene s owns [first[s], first[s + 1])) in strides;
-// each kernel's solve is the per-scene solve, so the results are identical.
-template <int VM, int BLOCK>
-__global__ __launch_bounds__(BLOCK, 3) void solve_batched_kernel(const SolveScene* __restrict__ scenes, int count,
-                                                               long long total,
-                                                               unsigned long long* __restrict__ nonfinite) {
-    __shared__ long long s_first[GSN_SOLVE_MAX_SCENES + 1];
-    for (int i = threadIdx.x; i <= count; i += blockDim.x) s_first[i] = i < count ? scenes[i].first : total;
-    __syncthreads();
-    const long long stride = (long long)gridDim.x * blockDim.x;
-    for (long long gi = (long long)blockIdx.x * blockDim.x + threadIdx.x; gi < total; gi += stride) {
-        int lo = 0, hi = count - 1;  // last scene whose first index <= gi
-        while (lo < hi) {
-            const int mid = (lo + hi + 1) >> 1;
-            if (s_first[mid] <= gi) lo = mid; else hi = mid - 1;
-        }
-        const SolveScene& sc = scenes[lo];
-        const uint32_t ev = solve_one<VM>((int)(gi - s_first[lo]), sc.pos, sc.rot, sc.scale, sc.opac, sc.n, sc.K,
-                                          sc.cam, sc.kappa, sc.blk, sc.V, sc.o, sc.st, sc.fl);
-        if ((ev >> EV_NONFINITE) & 1u) atomicAdd(nonfinite, 1ull);
-    }
-}
-
 // The update of kernel k (kernels the solve skipped, decisions -2 or -3, are not passed here).
 __device__ __forceinline__ void apply_one(float* __restrict__ pos, float* __restrict__ rot, float* __restrict__ scale,
                                           float* __restrict__ opac, float* __restrict__ sh, int n, int K,
@@ -782,6 +729,75 @@ __device__ __forceinline__ void apply_one(float* __restrict__ pos, float* __rest
     }
     if (mask & 16u)
         for (int i = 0; i < 3 * K; ++i) sh[i * N + k] += a[4] * st[(GSN_STEP_BASE + i) * N + k];
+}
+
+// A solve with its update fused (ap.mask != 0): the thread that solved kernel k applies the groups
+// of ap.mask of its step at once (as apply_kernel with no scales), reading back its own step and
+// decisions; the opacity bound is counted as apply_kernel counts it.
+__device__ __forceinline__ void fused_apply(const ApplyTo& ap, int n, int K, const float* __restrict__ st,
+                                            const int32_t* __restrict__ fl, const gsn_solve_opts& o, int k,
+                                            unsigned long long* __restrict__ prof) {
+    bool bound = false;
+    if (k < n && fl[k] >= -1) apply_one(ap.pos, ap.rot, ap.scale, ap.opac, ap.sh, n, K, st, nullptr, o, ap.mask, k, bound);
+    if (prof) {  // uniform across the launch
+        const uint64_t m = __ballot(bound);
+        if (__lane_id() == 0 && m) atomicAdd(&prof[GSN_COUNT_OPAC_BOUND], (unsigned long long)__popcll(m));
+    }
+}
+
+// pos, rot, scale and opac are not restrict-qualified here: with a fused update the same arrays are
+// written through ap.
+__global__ __launch_bounds__(128) void solve_mixed_kernel(const float* pos, const float* rot, const float* scale,
+                                                           const float* opac, int n, int K, DevCam c,
+                                                           float kappa, const float* __restrict__ blk, int V,
+                                                           gsn_solve_opts o, const float* __restrict__ gram,
+                                                           float* __restrict__ st, int32_t* __restrict__ fl,
+                                                           unsigned long long* __restrict__ n_fp64,
+                                                           unsigned long long* __restrict__ nonfinite,
+                                                           unsigned long long* __restrict__ prof, ApplyTo ap) {
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    uint32_t ev = 0;
+    if (k < n) ev = solve_one_mixed(k, pos, rot, scale, opac, n, K, c, kappa, blk, V, o, gram, st, fl, n_fp64);
+    count_solve_events(ev, nonfinite, prof);
+    if (ap.mask) fused_apply(ap, n, K, st, fl, o, k, prof);  // uniform across the launch
+}
+
+template <int VM>
+__global__ __launch_bounds__(128, 3) void solve_kernel(const float* pos, const float* rot, const float* scale,
+                                                     const float* opac, int n, int K, DevCam c, float kappa,
+                                                     const float* __restrict__ blk, int V, gsn_solve_opts o,
+                                                     float* __restrict__ st, int32_t* __restrict__ fl,
+                                                     unsigned long long* __restrict__ nonfinite,
+                                                     unsigned long long* __restrict__ prof, ApplyTo ap) {
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    uint32_t ev = 0;
+    if (k < n) ev = solve_one<VM>(k, pos, rot, scale, opac, n, K, c, kappa, blk, V, o, st, fl);
+    count_solve_events(ev, nonfinite, prof);
+    if (ap.mask) fused_apply(ap, n, K, st, fl, o, k, prof);  // uniform across the launch
+}
+
+// Several scenes in one persistent launch: the threads of a grid sized to the device walk
+// the concatenated kernel index space (scene s owns [first[s], first[s + 1])) in strides;
+// each kernel's solve is the per-scene solve, so the results are identical.
+template <int VM, int BLOCK>
+__global__ __launch_bounds__(BLOCK, 3) void solve_batched_kernel(const SolveScene* __restrict__ scenes, int count,
+                                                               long long total,
+                                                               unsigned long long* __restrict__ nonfinite) {
+    __shared__ long long s_first[GSN_SOLVE_MAX_SCENES + 1];
+    for (int i = threadIdx.x; i <= count; i += blockDim.x) s_first[i] = i < count ? scenes[i].first : total;
+    __syncthreads();
+    const long long stride = (long long)gridDim.x * blockDim.x;
+    for (long long gi = (long long)blockIdx.x * blockDim.x + threadIdx.x; gi < total; gi += stride) {
+        int lo = 0, hi = count - 1;  // last scene whose first index <= gi
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (s_first[mid] <= gi) lo = mid; else hi = mid - 1;
+        }
+        const SolveScene& sc = scenes[lo];
+        const uint32_t ev = solve_one<VM>((int)(gi - s_first[lo]), sc.pos, sc.rot, sc.scale, sc.opac, sc.n, sc.K,
+                                          sc.cam, sc.kappa, sc.blk, sc.V, sc.o, sc.st, sc.fl);
+        if ((ev >> EV_NONFINITE) & 1u) atomicAdd(nonfinite, 1ull);
+    }
 }
 
 __global__ __launch_bounds__(256) void apply_kernel(float* __restrict__ pos, float* __restrict__ rot,
@@ -833,18 +849,18 @@ hipError_t solve_scratch_address(int device, float** out) {
 
 void launch_solve(const gsn_gaussians& g, const DevCam& cam, float kappa, const gsn_blocks& b,
                   const gsn_solve_opts& o, const gsn_steps& st, unsigned long long* nonfinite,
-                  unsigned long long* prof, hipStream_t s) {
+                  unsigned long long* prof, const ApplyTo& ap, hipStream_t s) {
     if (g.n == 0) return;
     const int K = (g.sh_degree + 1) * (g.sh_degree + 1);
     // the hot path has a primary and up to three secondaries: a 4-view kernel keeps its arrays in registers
     if (b.n_views <= 4)
         solve_kernel<4><<<(g.n + 127) / 128, 128, 0, s>>>(g.d_pos, g.d_rot, g.d_scale, g.d_opac, g.n, K, cam, kappa,
                                                           b.d_data, b.n_views, o, st.d_data, st.d_flags, nonfinite,
-                                                          prof);
+                                                          prof, ap);
     else
         solve_kernel<9><<<(g.n + 127) / 128, 128, 0, s>>>(g.d_pos, g.d_rot, g.d_scale, g.d_opac, g.n, K, cam, kappa,
                                                           b.d_data, b.n_views, o, st.d_data, st.d_flags, nonfinite,
-                                                          prof);
+                                                          prof, ap);
 }
 
 template <int BLOCK>
@@ -866,13 +882,13 @@ void launch_sh_gram(const float* blk, int n, int K, int V, float* gram, hipStrea
 
 void launch_solve_mixed(const gsn_gaussians& g, const DevCam& cam, float kappa, const gsn_blocks& b,
                         const gsn_solve_opts& o, const float* gram, const gsn_steps& st, unsigned long long* nonfinite,
-                        unsigned long long* prof, hipStream_t s) {
+                        unsigned long long* prof, const ApplyTo& ap, hipStream_t s) {
     if (g.n == 0) return;
     const int K = (g.sh_degree + 1) * (g.sh_degree + 1);
     unsigned long long* n_fp64 = prof ? prof + GSN_COUNT_FP64_SOLVES : nullptr;
     solve_mixed_kernel<<<(g.n + 127) / 128, 128, 0, s>>>(g.d_pos, g.d_rot, g.d_scale, g.d_opac, g.n, K, cam, kappa,
                                                          b.d_data, b.n_views, o, gram, st.d_data, st.d_flags, n_fp64,
-                                                         nonfinite, prof);
+                                                         nonfinite, prof, ap);
 }
 
 void launch_solve_batched(const SolveScene* d_scenes, int count, long long total, int max_views, int block,

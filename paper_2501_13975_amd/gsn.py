@@ -49,6 +49,7 @@ def lib():
             "gsn_local_newton_solve": [P, P, P, P, P, P],
             "gsn_local_newton_solve_noalloc": [P, P, P, P, P, P],
             "gsn_apply_step": [P, P, P, P, P, ctypes.c_uint32],
+            "gsn_solve_apply": [P, P, P, P, P, P, ctypes.c_uint32],
             "gsn_first_order_step": [P, P, P, P, P, P, ctypes.c_uint32],
             "gsn_step_features": [P, P, P, P, P, P, P, P],
             "gsn_neighbour_residual": [P, P, P],
@@ -339,6 +340,12 @@ class Context:
         cg, cs = g.c(), steps.c()
         self._check(lib().gsn_apply_step(self.h, ctypes.byref(cg), ctypes.byref(cs), ctypes.byref(so),
                                          _ptr(scale), int(group_mask)))
+
+    def solve_apply(self, g, primary: CCamera, blocks: "Blocks", so: CSolveOpts, steps: "Steps", group_mask=31):
+        """gsn_solve_apply: the solve and the update of the groups in group_mask in one launch."""
+        cg, cb, cs = g.c(), blocks.c(), steps.c()
+        self._check(lib().gsn_solve_apply(self.h, ctypes.byref(cg), ctypes.byref(primary), ctypes.byref(cb),
+                                          ctypes.byref(so), ctypes.byref(cs), int(group_mask)))
 
     def first_order_step(self, g, blocks: "Blocks", so: CSolveOpts, lr, adam=True, step=1, state=None,
                          beta1=0.9, beta2=0.999, eps=1e-15, group_mask=31):

@@ -125,9 +125,7 @@ class LocalNewtonTrainer:
         """Jacobi schedule: every group linearised at the same state, one render and
         accumulation per view, the steps of the groups in group_mask applied together."""
         self.accumulate(t)
-        so = self.solve_opts(t)
-        self.ctx.local_newton_solve(self.g, self.ccams[t], self.blocks, so, self.steps)
-        self.ctx.apply_step(self.g, self.steps, so, group_mask)
+        self.ctx.solve_apply(self.g, self.ccams[t], self.blocks, self.solve_opts(t), self.steps, group_mask)
 
     def sweep_series(self, t, order=(1, 2, 4, 8, 16)):
         """Series schedule (Sec. 4.2, groups solved one after another: position, rotation,
@@ -282,12 +280,12 @@ class LocalNewtonTrainer:
         self.ctx.add_view_shares(self.blocks, self.frames[1:1 + len(self.knn[t])])
         if self.n_secondary:
             self.ctx.neighbour_residual(self.blocks, self.resid[:n])
-        self.ctx.local_newton_solve(self.g, self.ccams[t], self.blocks, so, self.steps)
+        # the full step applied with its solve (the labels and the training read the steps only)
+        self.ctx.solve_apply(self.g, self.ccams[t], self.blocks, so, self.steps, group_mask)
         self.ctx.step_labels(self.steps_prim, self.steps, self.label[:, :n], self.mask[:, :n], ok=self.ok[:n],
                              alpha=self.alpha[:, :n], err=self.err)
         self.ctx.mlp_train_step(self.mlp, self.feat[:, :n], self.label[:, :n], self.mask[:, :n], lr=self.lr,
                                 loss=self.mlp_loss)
-        self.ctx.apply_step(self.g, self.steps, so, group_mask)
 
 
     def learned_error(self):
