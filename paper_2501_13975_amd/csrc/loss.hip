@@ -243,24 +243,40 @@ __global__ __launch_bounds__(256) void ssim_grad_kernel(const float* __restrict_
     }
 }
 
-__global__ void loss_reduce_kernel(const double* __restrict__ part, int nparts, double npix, double* __restrict__ out) {
-    __shared__ double red[2][256];
-    double a = 0.0, b = 0.0;
-    for (int i = threadIdx.x; i < nparts; i += 256) {
-        a += part[i];
-        b += part[nparts + i];
+// One workgroup of kReduceThreads: each thread sums its strided share of the partials with four
+// independent accumulators (so that its loads are in flight together), then the workgroup adds the
+// threads' sums in a fixed tree; the order depends only on nparts, so the value is deterministic.
+constexpr int kReduceThreads = 1024;
+__global__ __launch_bounds__(kReduceThreads) void loss_reduce_kernel(const double* __restrict__ part, int nparts,
+                                                                      double npix, double* __restrict__ out) {
+    __shared__ double red[2][kReduceThreads];
+    const int t = threadIdx.x;
+    double a[4] = {0.0, 0.0, 0.0, 0.0}, b[4] = {0.0, 0.0, 0.0, 0.0};
+    int i = t;
+    for (; i + 3 * kReduceThreads < nparts; i += 4 * kReduceThreads) {
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            a[u] += part[i + u * kReduceThreads];
+            b[u] += part[nparts + i + u * kReduceThreads];
+        }
     }
-    red[0][threadIdx.x] = a;
-    red[1][threadIdx.x] = b;
+#pragma unroll
+    for (int u = 0; u < 3; ++u)  // at most three left: i + 3 kReduceThreads >= nparts
+        if (i + u * kReduceThreads < nparts) {
+            a[u] += part[i + u * kReduceThreads];
+            b[u] += part[nparts + i + u * kReduceThreads];
+        }
+    red[0][t] = (a[0] + a[1]) + (a[2] + a[3]);
+    red[1][t] = (b[0] + b[1]) + (b[2] + b[3]);
     __syncthreads();
-    for (int s = 128; s > 0; s >>= 1) {
-        if (threadIdx.x < s) {
-            red[0][threadIdx.x] += red[0][threadIdx.x + s];
-            red[1][threadIdx.x] += red[1][threadIdx.x + s];
+    for (int s = kReduceThreads / 2; s > 0; s >>= 1) {
+        if (t < s) {
+            red[0][t] += red[0][t + s];
+            red[1][t] += red[1][t + s];
         }
         __syncthreads();
     }
-    if (threadIdx.x == 0) {
+    if (t == 0) {
         out[0] = red[0][0] / (6.0 * npix);
         out[1] = red[1][0] / (3.0 * npix);
     }
@@ -283,5 +299,5 @@ void launch_loss_maps(const float* img, const float* tgt, int W, int H, float la
 }
 
 void launch_loss_reduce(const double* part, int nparts, int W, int H, double* out, hipStream_t s) {
-    loss_reduce_kernel<<<1, 256, 0, s>>>(part, nparts, (double)W * (double)H, out);
+    loss_reduce_kernel<<<1, kReduceThreads, 0, s>>>(part, nparts, (double)W * (double)H, out);
 }

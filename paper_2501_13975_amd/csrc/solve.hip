@@ -727,8 +727,21 @@ __device__ __forceinline__ void apply_one(float* __restrict__ pos, float* __rest
         bound = put != want;
         opac[k] = put;
     }
-    if (mask & 16u)
-        for (int i = 0; i < 3 * K; ++i) sh[i * N + k] += a[4] * st[(GSN_STEP_BASE + i) * N + k];
+    if (mask & 16u) {
+        // every coefficient's step and value loaded before any is stored (constant indices: the loads
+        // are in flight together, which matters inside the solve's low-occupancy launch)
+        constexpr int kMaxC = 48;  // 3 channels x 16 coefficients at degree 3
+        float dv[kMaxC], sv[kMaxC];
+#pragma unroll
+        for (int i = 0; i < kMaxC; ++i)
+            if (i < 3 * K) {
+                dv[i] = st[(GSN_STEP_BASE + i) * N + k];
+                sv[i] = sh[i * N + k];
+            }
+#pragma unroll
+        for (int i = 0; i < kMaxC; ++i)
+            if (i < 3 * K) sh[i * N + k] = sv[i] + a[4] * dv[i];
+    }
 }
 
 // A solve with its update fused (ap.mask != 0): the thread that solved kernel k applies the groups
