@@ -148,6 +148,58 @@ def _rate_and_profile(tr, order, warmup, steps, learned, dev):
     return el, st, cn
 
 
+def _mixed_vs_plain(cfg, targets, dev, t, step_frac):
+    """One sweep's blocks and steps of the mixed form against the plain form's on the same state
+    (training image t): per group the largest difference relative to the plain form's largest
+    entry, over the kernels the primary sees; steps over the kernels whose five decisions agree
+    (largest, median, 99th and 99.9th percentile over the kernels), and the share of solved kernels
+    whose decisions differ.  The plain form matches the FP64
+    oracle to about 1e-6 (the parity tests), so these are the mixed form's errors to that accuracy."""
+    import torch
+    from paper_2501_13975_amd import gsn
+    res = {}
+    trs = [_trainer(cfg, targets, dev, 0, step_frac, precision=p) for p in (0, 1)]
+    blocks, steps, flags = [], [], []
+    for tr in trs:
+        tr.accumulate(t)
+        tr.ctx.local_newton_solve(tr.g, tr.ccams[t], tr.blocks, tr.solve_opts(t), tr.steps)
+        st, fl = tr.steps.view()
+        blocks.append(tr.blocks.view().clone())
+        steps.append(st.clone())
+        flags.append(fl.clone())
+    for tr in trs:
+        tr.close()
+    torch.cuda.synchronize(dev)
+    seen = blocks[0][29] > 0
+    V = trs[0].blocks.n_views
+    colour = [gsn.GSN_BLK_BASE + gsn.GSN_BLK_VIEW * v + r for v in range(V) for r in range(6)]
+
+    def rel(a, b, rows, cols, quantiles=False):
+        x, y = a[rows][:, cols].double(), b[rows][:, cols].double()
+        den = float(y.abs().max()) if y.numel() else 0.0
+        if den <= 0:
+            return 0.0
+        d = (x - y).abs().amax(0) / den  # per kernel: its largest difference in the group
+        if not quantiles:
+            return round(float(d.max()), 8)
+        q = torch.quantile(d, torch.tensor([0.5, 0.99, 0.999], dtype=d.dtype, device=d.device)).tolist()
+        return {"max": round(float(d.max()), 8), "p50": round(q[0], 10), "p99": round(q[1], 8), "p999": round(q[2], 8)}
+
+    groups = {"position": list(range(0, 9)), "rotation": list(range(9, 18)), "scaling": list(range(18, 27)),
+              "opacity": [27, 28], "colour": colour}
+    res["blocks_rel"] = {k: rel(blocks[1], blocks[0], rows, seen) for k, rows in groups.items()}
+    solved = (flags[0] >= -1).all(0) & (flags[1] >= -1).all(0)
+    same = solved & (flags[0] == flags[1]).all(0)
+    K = steps[0].shape[0] - gsn.GSN_STEP_BASE
+    sgroups = {"position": [0, 1, 2], "rotation": [3], "scaling": [7, 8, 9], "opacity": [10],
+               "colour": list(range(gsn.GSN_STEP_BASE, gsn.GSN_STEP_BASE + K))}
+    res["steps_rel"] = {k: rel(steps[1], steps[0], rows, same, True) for k, rows in sgroups.items()}
+    res["kernels_solved"] = int(solved.sum())
+    res["decisions_differ"] = round(float((solved & ~same).sum()) / max(int(solved.sum()), 1), 6)
+    res["image"] = int(t)
+    return res
+
+
 def _graph_rate(cfg, targets, dev, order, warmup, steps, step_frac):
     """The plain form with reserved frames, each sweep a replay of its image's captured HIP graph
     (captured before timing), against the same sweeps issued one call at a time (also without host
@@ -614,6 +666,8 @@ def gpu_run(args):
              "stage_ms_per_step": {k: round(v[0] / args.steps, 3) for k, v in st_m.items()}}
     log(f"[bench] mixed: {args.steps / el_m:.2f} sweeps/s; stage ms: "
         + ", ".join(f"{k}={v[0]:.1f}" for k, v in st_m.items()))
+    mixed["vs_plain"] = _mixed_vs_plain(cfg, targets, dev, int(order[0]), args.step_frac)
+    log(f"[bench] mixed against plain: {mixed['vs_plain']}")
     learned = None
     if args.learned_every:
         tr = _trainer(cfg, targets, dev, args.learned_every, args.step_frac, reserve=True)
