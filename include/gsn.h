@@ -251,9 +251,10 @@ gsn_status gsn_accumulate_hessian(gsn_ctx* ctx, const gsn_gaussians* g, const gs
  * for bit to those calls made one after another.  The views take in turn the context's stream and
  * three streams of the library's own (default priority), forked from the context's stream and
  * joined back into it before the call returns, so that a view's projection, sort, rasters and loss
- * maps overlap the others'; each view's additions into the rows summed over the views wait for the previous
- * view's, and a secondary slot's per-kernel sums wait for the primary's coverage row when slot 0
- * is among the views.  With the profiler on (gsn_profile_enable) the views run one after another
+ * maps overlap the others'; each view's shares of the rows summed over the views are kept in its
+ * frame and added to the blocks after the join, in view order (the blocks equal those of the calls
+ * made one after another, bit for bit), and a secondary slot's per-kernel sums wait for the
+ * primary's coverage row when slot 0 is among the views.  With the profiler on (gsn_profile_enable) the views run one after another
  * on the context's stream.  The frames must be distinct; reserved frames (gsn_frame_reserve)
  * keep the call free of host waits and let it be captured (gsn_capture_begin).
  * cams [n_views], frames [n_views], d_targets [n_views] (device [3][H][W] each, at each camera's
