@@ -101,3 +101,64 @@ def test_binding_counter_names_follow_the_header():
     assert gsn.STATS[stats["GSN_STAT_PAIRS_NEEDED"]] == "pairs_needed"
     stages = _enum_values("GSN_STAGE_")
     assert len(gsn.Context.STAGES) == stages["GSN_STAGE_COUNT"]
+
+
+# every option and handle struct of include/gsn.h against the binding's ctypes mirror
+_STRUCTS = {
+    "gsn_gaussians": "CGaussians", "gsn_camera": "CCamera", "gsn_render_opts": "CRenderOpts",
+    "gsn_loss_opts": "CLossOpts", "gsn_solve_opts": "CSolveOpts", "gsn_blocks": "CBlocks", "gsn_steps": "CSteps",
+    "gsn_first_order_opts": "CFirstOrderOpts", "gsn_solve_item": "CSolveItem", "gsn_mlp": "CMlp",
+    "gsn_adam_opts": "CAdamOpts",
+}
+
+
+def _c_layouts(tmp_path):
+    """sizeof and the offset of every field of each struct, from a host C program built with gcc."""
+    import shutil
+    import subprocess
+    if shutil.which("gcc") is None:
+        pytest.skip("gcc not found")
+    src = open(HEADER).read()
+    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "gsn.h"', "int main(void) {"]
+    for cname in _STRUCTS:
+        body = re.search(r"typedef struct \{([^{}]*)\}\s*" + cname + r"\s*;", src)
+        assert body, cname
+        text = re.sub(r"/\*.*?\*/", "", body.group(1), flags=re.S)
+        fields = []
+        for decl in text.split(";"):
+            decl = decl.strip()
+            if not decl:
+                continue
+            m = re.match(r"(.*?)\s*([A-Za-z_][A-Za-z0-9_]*)\s*(\[[^\]]*\])?\s*$", decl.split(",")[0])
+            assert m, decl
+            fields.append(m.group(2))
+            for extra in decl.split(",")[1:]:
+                fields.append(re.sub(r"[\s*]|\[.*\]", "", extra))
+        lines.append(f'printf("{cname} %zu", sizeof({cname}));')
+        for f in fields:
+            lines.append(f'printf(" {f}=%zu", offsetof({cname}, {f}));')
+        lines.append('printf("\\n");')
+    lines.append("return 0; }")
+    c = tmp_path / "layout.c"
+    c.write_text("\n".join(lines))
+    exe = tmp_path / "layout"
+    subprocess.check_call(["gcc", "-std=c11", "-I", os.path.dirname(HEADER), str(c), "-o", str(exe)])
+    out = {}
+    for line in subprocess.check_output([str(exe)]).decode().splitlines():
+        parts = line.split()
+        out[parts[0]] = (int(parts[1]), {k: int(v) for k, v in (p.split("=") for p in parts[2:])})
+    return out
+
+
+def test_binding_structs_match_the_header(tmp_path):
+    """The ctypes mirrors in gsn.py have the size and field offsets of the header's structs (checked
+    on the host with gcc), so that no option is marshalled into the wrong field."""
+    from paper_2501_13975_amd import gsn
+    layouts = _c_layouts(tmp_path)
+    for cname, pyname in _STRUCTS.items():
+        size, offs = layouts[cname]
+        cls = getattr(gsn, pyname)
+        assert ctypes.sizeof(cls) == size, (cname, ctypes.sizeof(cls), size)
+        py = {name: getattr(cls, name).offset for name, _ in cls._fields_}
+        assert list(py) == list(offs), (cname, list(py), list(offs))
+        assert py == offs, (cname, py, offs)
