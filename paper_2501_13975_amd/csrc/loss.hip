@@ -15,7 +15,7 @@
 // Summing over the windows that contain a pixel turns each window-centred
 // coefficient map into a correlation with w (three maps) or w^2 (five maps).
 //
-// Pass 1 (one workgroup per 16x16 tile of window centres and channel): moments
+// Pass 1 (one workgroup per 16x16 tile of window centres, its three channels in turn): moments
 // by separable convolution through LDS, then the eight coefficient maps
 // (computed in double and stored in single precision: their rounding moves dL
 // and h by about 5e-8 of the maps' largest values) and the loss partial sums
@@ -53,96 +53,116 @@ __global__ __launch_bounds__(256) void ssim_coef_kernel(const float* __restrict_
     __shared__ Re g[11], g2[11];
     __shared__ Re sc[R][R], st[R][R];
     __shared__ Re hs[5][R][T];
-    const int ch = blockIdx.z;
+    __shared__ double red[2][4];
     const int x0 = blockIdx.x * T - HALO, y0 = blockIdx.y * T - HALO;
     const size_t np = (size_t)W * H;
-    const float* I = img + ch * np;
-    const float* Tg = tgt + ch * np;
     window_weights(g, g2);
-    for (int i = threadIdx.x; i < R * R; i += 256) {
-        const int yy = i / R, xx = i % R, x = x0 + xx, y = y0 + yy;
-        const bool in = x >= 0 && y >= 0 && x < W && y < H;
-        sc[yy][xx] = in ? (Re)I[(size_t)y * W + x] : Re(0.0);
-        st[yy][xx] = in ? (Re)Tg[(size_t)y * W + x] : Re(0.0);
-    }
-    __syncthreads();
-    for (int i = threadIdx.x; i < R * T; i += 256) {
-        const int yy = i / T, xx = i % T;
-        Re a = 0, b = 0, c = 0, d = 0, e = 0;
+    // the three channels one after another: the next channel's halo tiles of image and target are
+    // loaded into registers while the current one is processed
+    constexpr int NLD = (R * R + 255) / 256;  // 3 elements per thread and array
+    float ld_c[NLD], ld_t[NLD];
+    auto load = [&](int c) {
 #pragma unroll
-        for (int k = 0; k < 11; ++k) {
-            const Re u = sc[yy][xx + k], v = st[yy][xx + k], w = g[k];
-            a += w * u;
-            b += w * v;
-            c += w * u * u;
-            d += w * v * v;
-            e += w * u * v;
+        for (int j = 0; j < NLD; ++j) {
+            const int i = threadIdx.x + 256 * j;
+            const int yy = i / R, xx = i % R, x = x0 + xx, y = y0 + yy;
+            const bool in = i < R * R && x >= 0 && y >= 0 && x < W && y < H;
+            const size_t at = in ? (size_t)c * np + (size_t)y * W + x : 0;
+            ld_c[j] = in ? img[at] : 0.f;
+            ld_t[j] = in ? tgt[at] : 0.f;
         }
-        hs[0][yy][xx] = a;
-        hs[1][yy][xx] = b;
-        hs[2][yy][xx] = c;
-        hs[3][yy][xx] = d;
-        hs[4][yy][xx] = e;
-    }
-    __syncthreads();
-    const int lx = threadIdx.x % T, ly = threadIdx.x / T;
-    const int x = blockIdx.x * T + lx, y = blockIdx.y * T + ly;
-    double l2 = 0.0, ls = 0.0;  // loss partials in double in both forms
-    if (x < W && y < H) {
-        Re m[5] = {0, 0, 0, 0, 0};
+    };
+    load(0);
+    for (int ch = 0; ch < 3; ++ch) {
 #pragma unroll
-        for (int k = 0; k < 11; ++k)
+        for (int j = 0; j < NLD; ++j) {
+            const int i = threadIdx.x + 256 * j;
+            if (i < R * R) {
+                sc[i / R][i % R] = (Re)ld_c[j];
+                st[i / R][i % R] = (Re)ld_t[j];
+            }
+        }
+        __syncthreads();
+        if (ch + 1 < 3) load(ch + 1);
+        for (int i = threadIdx.x; i < R * T; i += 256) {
+            const int yy = i / T, xx = i % T;
+            Re a = 0, b = 0, c = 0, d = 0, e = 0;
 #pragma unroll
-            for (int q = 0; q < 5; ++q) m[q] += g[k] * hs[q][ly + k][lx];
-        // the quotient-rule coefficients in double in both forms: their terms in 1/f2 and 1/f3 cancel
-        // to a small fraction of their size in flat regions, which single precision does not resolve
-        const double mu = m[0], mut = m[1];
-        const double f0 = 2.0 * mu * mut + kC1;
-        const double f1 = 2.0 * ((double)m[4] - mu * mut) + kC2;
-        const double f2 = mu * mu + mut * mut + kC1;
-        const double f3 = ((double)m[2] - mu * mu) + ((double)m[3] - mut * mut) + kC2;
-        const double F = (f0 * f1) / (f2 * f3);
-        const double i0 = 1.0 / f0, i1 = 1.0 / f1, i2 = 1.0 / f2, i3 = 1.0 / f3;
-        const double a0 = 2.0 * mut * i0 - 2.0 * mut * i1 - 2.0 * mu * i2 + 2.0 * mu * i3;
-        const double a1 = 2.0 * i1, a2 = 2.0 * i3;
-        const double b0 = a0 * a0 - 4.0 * mut * mut * i0 * i0 - 4.0 * mut * mut * i1 * i1 - 2.0 * i2 +
-                          4.0 * mu * mu * i2 * i2 + 2.0 * i3 + 4.0 * mu * mu * i3 * i3;
-        const double bt = 2.0 * a0 * a1 + 8.0 * mut * i1 * i1;
-        const double bc = -2.0 * a0 * a2 - 8.0 * mu * i3 * i3;
-        const double bcc = 8.0 * i3 * i3;
-        const double btc = -8.0 * i1 * i3;
-        const size_t pi = (size_t)y * W + x;
-        float* cf = coef + (size_t)ch * 8 * np;
-        cf[0 * np + pi] = (float)(F * a0);
-        cf[1 * np + pi] = (float)(F * a1);
-        cf[2 * np + pi] = (float)(F * a2);
-        cf[3 * np + pi] = (float)(F * b0);
-        cf[4 * np + pi] = (float)(F * bt);
-        cf[5 * np + pi] = (float)(F * bc);
-        cf[6 * np + pi] = (float)(F * bcc);
-        cf[7 * np + pi] = (float)(F * btc);
-        const double r = (double)sc[ly + HALO][lx + HALO] - (double)st[ly + HALO][lx + HALO];
-        l2 = r * r;
-        ls = 1.0 - (double)F;
-    }
-    // deterministic block reduction in double: a butterfly within each wave, then the four wave
-    // sums in wave order
-    __shared__ double red[2][4];
+            for (int k = 0; k < 11; ++k) {
+                const Re u = sc[yy][xx + k], v = st[yy][xx + k], w = g[k];
+                a += w * u;
+                b += w * v;
+                c += w * u * u;
+                d += w * v * v;
+                e += w * u * v;
+            }
+            hs[0][yy][xx] = a;
+            hs[1][yy][xx] = b;
+            hs[2][yy][xx] = c;
+            hs[3][yy][xx] = d;
+            hs[4][yy][xx] = e;
+        }
+        __syncthreads();
+        const int lx = threadIdx.x % T, ly = threadIdx.x / T;
+        const int x = blockIdx.x * T + lx, y = blockIdx.y * T + ly;
+        double l2 = 0.0, ls = 0.0;  // loss partials in double in both forms
+        if (x < W && y < H) {
+            Re m[5] = {0, 0, 0, 0, 0};
 #pragma unroll
-    for (int off = 32; off > 0; off >>= 1) {
-        l2 += __shfl_xor(l2, off, 64);
-        ls += __shfl_xor(ls, off, 64);
-    }
-    if (__lane_id() == 0) {
-        red[0][threadIdx.x / 64] = l2;
-        red[1][threadIdx.x / 64] = ls;
-    }
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        const int nb = gridDim.x * gridDim.y * gridDim.z;
-        const int b = (blockIdx.z * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x;
-        part[b] = ((red[0][0] + red[0][1]) + red[0][2]) + red[0][3];
-        part[nb + b] = ((red[1][0] + red[1][1]) + red[1][2]) + red[1][3];
+            for (int k = 0; k < 11; ++k)
+#pragma unroll
+                for (int q = 0; q < 5; ++q) m[q] += g[k] * hs[q][ly + k][lx];
+            // the quotient-rule coefficients in double in both forms: their terms in 1/f2 and 1/f3 cancel
+            // to a small fraction of their size in flat regions, which single precision does not resolve
+            const double mu = m[0], mut = m[1];
+            const double f0 = 2.0 * mu * mut + kC1;
+            const double f1 = 2.0 * ((double)m[4] - mu * mut) + kC2;
+            const double f2 = mu * mu + mut * mut + kC1;
+            const double f3 = ((double)m[2] - mu * mu) + ((double)m[3] - mut * mut) + kC2;
+            const double F = (f0 * f1) / (f2 * f3);
+            const double i0 = 1.0 / f0, i1 = 1.0 / f1, i2 = 1.0 / f2, i3 = 1.0 / f3;
+            const double a0 = 2.0 * mut * i0 - 2.0 * mut * i1 - 2.0 * mu * i2 + 2.0 * mu * i3;
+            const double a1 = 2.0 * i1, a2 = 2.0 * i3;
+            const double b0 = a0 * a0 - 4.0 * mut * mut * i0 * i0 - 4.0 * mut * mut * i1 * i1 - 2.0 * i2 +
+                              4.0 * mu * mu * i2 * i2 + 2.0 * i3 + 4.0 * mu * mu * i3 * i3;
+            const double bt = 2.0 * a0 * a1 + 8.0 * mut * i1 * i1;
+            const double bc = -2.0 * a0 * a2 - 8.0 * mu * i3 * i3;
+            const double bcc = 8.0 * i3 * i3;
+            const double btc = -8.0 * i1 * i3;
+            const size_t pi = (size_t)y * W + x;
+            float* cf = coef + (size_t)ch * 8 * np;
+            cf[0 * np + pi] = (float)(F * a0);
+            cf[1 * np + pi] = (float)(F * a1);
+            cf[2 * np + pi] = (float)(F * a2);
+            cf[3 * np + pi] = (float)(F * b0);
+            cf[4 * np + pi] = (float)(F * bt);
+            cf[5 * np + pi] = (float)(F * bc);
+            cf[6 * np + pi] = (float)(F * bcc);
+            cf[7 * np + pi] = (float)(F * btc);
+            const double r = (double)sc[ly + HALO][lx + HALO] - (double)st[ly + HALO][lx + HALO];
+            l2 = r * r;
+            ls = 1.0 - (double)F;
+        }
+        // deterministic block reduction in double: a butterfly within each wave, then the four wave
+        // sums in wave order
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) {
+            l2 += __shfl_xor(l2, off, 64);
+            ls += __shfl_xor(ls, off, 64);
+        }
+        if (__lane_id() == 0) {
+            red[0][threadIdx.x / 64] = l2;
+            red[1][threadIdx.x / 64] = ls;
+        }
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            // the partials of (channel, tile row, tile column), as one workgroup per tile and channel
+            const int nb = gridDim.x * gridDim.y * 3;
+            const int b = (ch * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x;
+            part[b] = ((red[0][0] + red[0][1]) + red[0][2]) + red[0][3];
+            part[nb + b] = ((red[1][0] + red[1][1]) + red[1][2]) + red[1][3];
+        }
+        __syncthreads();  // the LDS tiles and sums are rewritten for the next channel
     }
 }
 
@@ -286,8 +306,8 @@ __global__ __launch_bounds__(kReduceThreads) void loss_reduce_kernel(const doubl
 
 void launch_loss_maps(const float* img, const float* tgt, int W, int H, float lambda, bool fp32, float* coef,
                       float* dL, float* hd, double* part, int* nparts, hipStream_t s) {
-    dim3 grid((W + T - 1) / T, (H + T - 1) / T, 3);
-    *nparts = (int)(grid.x * grid.y * grid.z);
+    dim3 grid((W + T - 1) / T, (H + T - 1) / T, 1);  // the three channels in each workgroup
+    *nparts = (int)(grid.x * grid.y * 3);
     dim3 grid2((W + T2 - 1) / T2, (H + T2 - 1) / T2, 3);
     if (fp32) {
         ssim_coef_kernel<float><<<grid, 256, 0, s>>>(img, tgt, W, H, coef, part);
