@@ -29,7 +29,7 @@
 // splat's 44 statistics over its pairs (see raster_bwd_kernel); the tile's
 // partial sum is written at the (tile, kernel) pair's slot.  Workgroups take the
 // tiles with the longest composited prefixes (recorded by the forward pass) first.
-// reduce_pairs: a wave per 64 kernels sums each flagged kernel's written pair slots in a fixed order
+// reduce_pairs: a wave per 16 kernels sums each flagged kernel's written pair slots in a fixed order
 // (no atomics: results are deterministic); chain_pos / chain_rs: one thread per
 // kernel applies the chain rule through the projection with second-order jets
 // and adds the attribute blocks (position, opacity, colour / rotation, scale).
@@ -539,13 +539,18 @@ __global__ __launch_bounds__(GSN_BLOCK, 3) void raster_bwd_kernel(
     }
 }
 
-// One wave per 64 consecutive kernels.  Most kernels have no written slot in a view (their
+// One wave per kReduceKernels consecutive kernels.  Most kernels have no written slot in a view (their
 // kernel flag is clear): for them only the coverage entry is written (zero), which the chain
 // kernels test first.  The wave then takes its flagged kernels one after another: the kernel's
 // (tile, kernel) slots are scanned 64 at a time, and lane f < 44 adds statistic f of every slot
 // the backward pass wrote, in slot order and in double (deterministic, coalesced 176-byte reads
 // per slot).  A wave per kernel would spend most of the launch starting waves that only read
 // a clear flag.
+// Kernels per wave of the pair reduction: the kernels a view reaches come in runs (the ids of a
+// surface are contiguous), and a wave sums its flagged kernels one after another, so fewer kernels per
+// wave spread a run's serial load latencies over more waves.
+constexpr int kReduceKernels = 16;
+
 template <class Acc>
 __global__ __launch_bounds__(256) void reduce_pairs_kernel(int n, const uint2* __restrict__ rect,
                                                            const uint32_t* __restrict__ pair_off,
@@ -556,13 +561,14 @@ __global__ __launch_bounds__(256) void reduce_pairs_kernel(int n, const uint2* _
                                                            float* __restrict__ cov_out,
                                                            float* __restrict__ zf, double* __restrict__ zq) {
     const int lane = __lane_id();
-    const int k0 = (blockIdx.x * (blockDim.x / 64) + threadIdx.x / 64) * 64;
+    const int k0 = (blockIdx.x * (blockDim.x / 64) + threadIdx.x / 64) * kReduceKernels;
     if (k0 >= n) return;
-    // the wave's 64 kernels: those without partials (or, for a secondary view, not seen by the
-    // primary) get a zero coverage, the others are summed one after another by the whole wave
+    // the wave's kReduceKernels kernels: those without partials (or, for a secondary view, not seen by
+    // the primary) get a zero coverage, the others are summed one after another by the whole wave
     const int kl = k0 + lane;
-    const bool has = kl < n && kflag[kl] != 0 && (!primary_cov || primary_cov[kl] > 0.f);
-    if (kl < n && !has) {
+    const bool mine = lane < kReduceKernels && kl < n;
+    const bool has = mine && kflag[kl] != 0 && (!primary_cov || primary_cov[kl] > 0.f);
+    if (mine && !has) {
         zf[(size_t)kl * GSN_NZ + GSN_ZCOV] = 0.f;
         zq[(size_t)kl * kZq + kZqCov] = 0.0;
     }
@@ -778,7 +784,7 @@ void launch_reduce_pairs(const gsn_frame& f, const gsn_gaussians& g, int slot, b
     if (g.n == 0) return;
     auto red_k = fp32 ? reduce_pairs_kernel<float> : reduce_pairs_kernel<double>;
     float* cov = b.d_data + (size_t)29 * g.n;
-    red_k<<<(g.n + 255) / 256, 256, 0, s>>>(g.n, bp<uint2>(f.rect), bp<uint32_t>(f.pair_off), bp<float>(f.partial),
+    red_k<<<(g.n + 4 * kReduceKernels - 1) / (4 * kReduceKernels), 256, 0, s>>>(g.n, bp<uint2>(f.rect), bp<uint32_t>(f.pair_off), bp<float>(f.partial),
                                             bp<uint8_t>(f.flags), bp<uint8_t>(f.kflag), slot > 0 ? cov : nullptr,
                                             slot == 0 ? cov : nullptr, bp<float>(f.zsum_f), bp<double>(f.zsum));
 }
